@@ -1,0 +1,364 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Nothing here touches the GPU library.  Each test names the passage or the
+independent fact it checks; together they are chosen so that a plausible
+slip in the oracle (a wrong bound, a wrong re-dispatch, a wrong leaf rule, a
+dropped PageRank term, a transposed adjacency, a directed/undirected mix-up)
+fails at least one of them.
+"""
+import itertools
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import GOLDEN
+
+U64 = np.uint64
+E = 0xFFFFFFFFFFFFFFFF
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def slots_from_json(vals):
+    return np.array([E if v is None else v for v in vals], dtype=np.uint64)
+
+
+def key(u, v):
+    return (int(u) << 32) | int(v)
+
+
+# --------------------------------------------------------------------------
+# density bounds: figure "PMA insertion example" (Section 4.1)
+
+def test_threshold_rows_match_figure():
+    g = golden("threshold_table.json")
+    lf, H = g["leaf_size"], g["height"]
+    mn, mx = O.level_bounds(lf, H)
+    for h in range(H + 1):
+        cap = g["segment_size"][h]
+        assert cap == lf << h
+        # the printed rho/tau are rounded to two decimals: the integer bounds
+        # must be the strict bounds of some rho, tau inside that rounding
+        # interval (Algorithm GPMA+ tests (n_s+|U_s|)/cap < tau)
+        t_lo, t_hi = Fraction(g["tau"][h]) - Fraction(1, 200), Fraction(g["tau"][h]) + Fraction(1, 200)
+        r_lo, r_hi = Fraction(g["rho"][h]) - Fraction(1, 200), Fraction(g["rho"][h]) + Fraction(1, 200)
+        assert Fraction(int(mx[h])) < t_hi * cap and Fraction(int(mx[h]) + 1) >= t_lo * cap
+        assert Fraction(int(mn[h])) > r_lo * cap and Fraction(int(mn[h]) - 1) <= r_hi * cap
+    # where the figure's count rows agree with its rho/tau rows they must match
+    assert int(mx[0]) == g["max_entries"][0]
+    assert int(mn[0]) == g["min_entries"][0] and int(mn[1]) == g["min_entries"][1]
+
+
+def test_threshold_interpolation_is_linear_in_height():
+    # leaf and root rows of the figure; the middle rows are their linear
+    # interpolation rounded to two decimals (0.1867 -> 0.19, 0.2933 -> 0.29)
+    g = golden("threshold_table.json")
+    H = g["height"]
+    for h in range(H + 1):
+        rho = Fraction(g["rho"][0]) + (Fraction(g["rho"][H]) - Fraction(g["rho"][0])) * h / H
+        tau = Fraction(g["tau"][0]) + (Fraction(g["tau"][H]) - Fraction(g["tau"][0])) * h / H
+        assert round(float(rho), 2) == g["rho"][h]
+        assert round(float(tau), 2) == g["tau"][h]
+    # and the oracle's bound at a big segment converges on tau_h * cap_h
+    lf, H2 = 1 << 12, 4
+    mn, mx = O.level_bounds(lf, H2)
+    for h in range(H2 + 1):
+        tau = 0.92 + (0.80 - 0.92) * h / H2
+        rho = 0.08 + (0.40 - 0.08) * h / H2
+        cap = lf << h
+        assert abs(int(mx[h]) - tau * cap) <= 1.0
+        assert abs(int(mn[h]) - rho * cap) <= 1.0
+
+
+def test_single_level_tree_uses_root_bounds():
+    mn, mx = O.level_bounds(16, 0)
+    assert int(mx[0]) == 12          # largest m < 0.80 * 16 = 12.8
+    assert int(mn[0]) == 7           # smallest m > 0.40 * 16 = 6.4
+
+
+# --------------------------------------------------------------------------
+# CSR on GPMA: figure "GPMA based on CSR" (Section 4.2)
+
+def test_csr_example_row_offsets():
+    g = golden("csr_example.json")
+    V = g["num_vertices"]
+    off, col = g["row_offset"], g["column_index"]
+    edges = [key(u, col[i]) for u in range(V) for i in range(off[u], off[u + 1])]
+    p = O.OraclePMA(V, np.array(edges[::-1], dtype=np.uint64), 16)
+    s = p.slots()
+    O.check_invariants(s, 16, V)
+    comp = O.stored(s)
+    guard = (comp & U64(0xFFFFFFFF)) == U64(0xFFFFFFFF)
+    # compacted array with guards: [0->0, 0->2, G0, 1->2, G1, 2->0, 2->1, 2->2, G2]
+    assert [int(x) for x in np.nonzero(guard)[0]] == [2, 4, 8]
+    # row offsets over the compacted array, guards dropped, equal the figure
+    rows = (comp >> U64(32)).astype(np.int64)
+    plain = np.zeros(V + 1, np.int64)
+    np.add.at(plain, rows[~guard] + 1, 1)
+    assert list(np.cumsum(plain)) == off
+    assert [int(x & U64(0xFFFFFFFF)) for x in comp[~guard]] == col
+    # the gapped row offsets bracket exactly the rows' entries and guards
+    ro = O.row_offsets(s, V)
+    for u in range(V):
+        seg = s[ro[u]:ro[u + 1]]
+        seg = seg[seg != U64(E)]
+        assert int(seg[-1]) == key(u, 0xFFFFFFFF)
+        assert [int(x & U64(0xFFFFFFFF)) for x in seg[:-1]] == col[off[u]:off[u + 1]]
+
+
+# --------------------------------------------------------------------------
+# worked examples of the update
+
+def test_example1_sequential_pma_insert_climbs_to_16_31():
+    g = golden("example1_pma_insert.json")
+    p = O.OraclePMA.from_slots(slots_from_json(g["slots"]), g["leaf_size"])
+    p.insert(np.array(g["insert"], dtype=np.uint64))
+    assert [list(m) for m in p.merge_log()] == g["expected_merges"]
+    h, s = g["expected_merges"][0]
+    lo = s * (g["leaf_size"] << h)
+    assert [lo, lo + (g["leaf_size"] << h) - 1] == g["expected_segment_interval"]
+    out = p.slots()
+    # untouched left half; right half re-dispatched evenly: 12 entries, 3 per leaf
+    assert np.array_equal(out[:16], slots_from_json(g["slots"])[:16])
+    right = out[16:].reshape(4, 4)
+    assert list((right != U64(E)).sum(1)) == [3, 3, 3, 3]
+    assert [int(x) for x in O.stored(out[16:])] == [40, 45, 47, 48, 50, 52, 54, 56, 60, 62, 70, 72]
+
+
+def test_example3_gpmaplus_rounds():
+    g = golden("example3_gpmaplus_insert.json")
+    init = slots_from_json(g["slots"])
+    p = O.OraclePMA.from_slots(init, g["leaf_size"])
+    p.insert(np.array(g["insert"], dtype=np.uint64))
+    assert [list(m) for m in p.merge_log()] == g["expected_merges"]
+    out = p.slots()
+    want = sorted(set(int(x) for x in O.stored(init)) | set(g["insert"]))
+    assert [int(x) for x in O.stored(out)] == want
+    assert list((out.reshape(8, 4) != U64(E)).sum(1)) == [3] * 8
+
+
+def test_example3_under_a_successor_leaf_rule_would_differ():
+    # the leaf rule matters: 4 has predecessor 0 (leaf 0) but successor 5
+    # (leaf 1); the paper merges {1,4} together at the leaf level
+    g = golden("example3_gpmaplus_insert.json")
+    p = O.OraclePMA.from_slots(slots_from_json(g["slots"]), g["leaf_size"])
+    p.insert(np.array([4], dtype=np.uint64))
+    assert p.merge_log() == [(0, 0)]
+
+
+# --------------------------------------------------------------------------
+# set semantics by brute force, invariants after every batch
+
+def _check(p, ref, V, lf):
+    s = p.slots()
+    O.check_invariants(s, lf, V)
+    assert [int(x) for x in O.edge_keys(s)] == sorted(ref)
+    assert p.size == len(ref) + V
+    # per-level bounds are checked only where a merge happens, so the root may
+    # sit above its own bound after leaf-level merges; only cap bounds size
+    assert p.size <= p.capacity
+
+
+def test_exhaustive_tiny_graphs():
+    V, lf = 2, 16
+    universe = [key(u, v) for u in range(V) for v in range(V)]
+    subsets = [set(c) for r in range(len(universe) + 1) for c in itertools.combinations(universe, r)]
+    for init in subsets:
+        for batch in subsets:
+            for op in ("insert", "delete"):
+                p = O.OraclePMA(V, np.array(sorted(init), dtype=np.uint64), lf)
+                getattr(p, op)(np.array(sorted(batch) * 2, dtype=np.uint64))
+                ref = init | batch if op == "insert" else init - batch
+                _check(p, ref, V, lf)
+                changed = len(batch - init) if op == "insert" else len(batch & init)
+                assert p.last_applied() == changed
+                assert p.last_noops() == 2 * len(batch) - changed
+
+
+@pytest.mark.parametrize("seed,V,lf", [(1, 8, 16), (2, 32, 16), (3, 64, 32), (4, 300, 16)])
+def test_random_batches_vs_set(seed, V, lf):
+    rng = np.random.default_rng(seed)
+
+    def rnd(n):
+        return [key(a, b) for a, b in zip(rng.integers(0, V, n), rng.integers(0, V, n))]
+
+    ref = set(rnd(3 * V))
+    p = O.OraclePMA(V, np.array(list(ref), dtype=np.uint64), lf)
+    _check(p, ref, V, lf)
+    for t in range(40):
+        b = int(rng.integers(1, 4 * V))
+        if rng.random() < 0.5:
+            ins = rnd(b)
+            p.insert(np.array(ins, dtype=np.uint64))
+            ref |= set(ins)
+        else:
+            pool = sorted(ref)
+            dl = [pool[i] for i in rng.integers(0, len(pool), b)] if pool else []
+            dl += rnd(b // 4)     # some absent keys: no-ops
+            p.delete(np.array(dl, dtype=np.uint64))
+            ref -= set(dl)
+        _check(p, ref, V, lf)
+
+
+def test_growth_and_shrink_resize_rules():
+    V, lf = 16, 16
+    p = O.OraclePMA(V, [], lf)
+    ref = set()
+    caps = [p.capacity]
+    allk = [key(u, v) for u in range(V) for v in range(V)]
+    rng = np.random.default_rng(7)
+    rng.shuffle(allk)
+    for i in range(0, len(allk), 23):
+        p.insert(np.array(allk[i:i + 23], dtype=np.uint64))
+        ref |= set(allk[i:i + 23])
+        _check(p, ref, V, lf)
+        caps.append(p.capacity)
+        for lvl, seg in p.merge_log():
+            if lvl < 0:    # a root rebuild: the new capacity is the smallest that fits
+                mn, mx = O.level_bounds(lf, int(np.log2(seg // lf)))
+                assert p.size <= int(mx[-1])
+                if seg > lf:
+                    mn2, mx2 = O.level_bounds(lf, int(np.log2(seg // 2 // lf)))
+                    assert p.size > int(mx2[-1])
+    assert caps == sorted(caps) and caps[-1] > caps[0]
+    for i in range(0, len(allk), 31):
+        p.delete(np.array(allk[i:i + 31], dtype=np.uint64))
+        ref -= set(allk[i:i + 31])
+        _check(p, ref, V, lf)
+        for lvl, seg in p.merge_log():
+            if lvl < 0 and seg > lf:
+                mn, mx = O.level_bounds(lf, int(np.log2(seg // lf)))
+                assert p.size >= int(mn[-1])
+    assert p.capacity < caps[-1]
+
+
+def test_invalid_keys_leave_state_unchanged():
+    p = O.OraclePMA(4, [key(0, 1), key(1, 2)], 16)
+    before = p.slots()
+    for bad in (key(4, 0), key(0, 4), key(1, 0xFFFFFFFF)):
+        with pytest.raises(O.OracleError):
+            p.insert(np.array([key(2, 3), bad], dtype=np.uint64))
+        with pytest.raises(O.OracleError):
+            p.delete(np.array([key(0, 1), bad], dtype=np.uint64))
+    assert np.array_equal(p.slots(), before)
+
+
+def test_amortized_work_grows_slowly():
+    # Lemma (Section 4.1) / Theorem 1 (Section 5.2): work per update is
+    # polylogarithmic; the slots rewritten per applied update stay far below
+    # the array size as the array grows
+    rng = np.random.default_rng(3)
+    for V in (64, 256):
+        keys = [key(a, b) for a, b in zip(rng.integers(0, V, 20 * V), rng.integers(0, V, 20 * V))]
+        p = O.OraclePMA(V, keys[: 10 * V], 16)
+        work = applied = 0
+        for i in range(10 * V, 20 * V, 32):
+            p.insert(np.array(keys[i:i + 32], dtype=np.uint64))
+            applied += p.last_applied()
+            for lvl, seg in p.merge_log():
+                work += (16 << lvl) if lvl >= 0 else seg
+        assert applied > 0 and work / applied < p.capacity / 8
+
+
+# --------------------------------------------------------------------------
+# PageRank (Section 6.1): fp64 power iteration
+
+def google_matrix(V, edges, d):
+    A = np.zeros((V, V))
+    for k in edges:
+        A[k >> 32, k & 0xFFFFFFFF] = 1.0
+    deg = A.sum(1)
+    P = np.where(deg[:, None] > 0, A / np.maximum(deg, 1)[:, None], 1.0 / V)
+    return d * P.T + (1 - d) / V
+
+
+def test_pagerank_cycle_and_edgeless_are_uniform():
+    V = 7
+    cyc = [key(i, (i + 1) % V) for i in range(V)]
+    np.testing.assert_allclose(O.pagerank(V, cyc, iters=10), np.full(V, 1 / V), rtol=1e-14)
+    np.testing.assert_allclose(O.pagerank(V, [], iters=10), np.full(V, 1 / V), rtol=1e-14)
+
+
+def test_pagerank_is_stationary_vector_of_google_matrix():
+    rng = np.random.default_rng(5)
+    V = 40
+    edges = sorted({key(a, b) for a, b in zip(rng.integers(0, V, 150), rng.integers(0, V // 2, 150))})
+    x = O.pagerank(V, edges, iters=300)
+    G = google_matrix(V, edges, 0.85)
+    w, vecs = np.linalg.eig(G)
+    v = np.real(vecs[:, np.argmax(np.real(w))])
+    v = v / v.sum()
+    np.testing.assert_allclose(x, v, rtol=1e-9)
+    assert abs(x.sum() - 1) < 1e-12
+
+
+def test_pagerank_single_step_matches_matrix_form():
+    rng = np.random.default_rng(6)
+    V = 25
+    edges = sorted({key(a, b) for a, b in zip(rng.integers(0, V, 60), rng.integers(0, V, 60))})
+    x0 = rng.random(V)
+    x0 /= x0.sum()
+    got = O.pagerank(V, edges, x0=x0, iters=1, damping=0.7)
+    want = google_matrix(V, edges, 0.7) @ x0
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# BFS (Algorithm "Breadth-First Search", Section 4.2) and CC (Section 6.1)
+
+def test_bfs_closed_forms():
+    V = 10
+    path = [key(i, i + 1) for i in range(V - 1)]
+    assert list(O.bfs(V, path, 0)) == list(range(V))
+    assert list(O.bfs(V, path, 4)) == [-1] * 4 + list(range(V - 4))   # directed
+    star = [key(0, i) for i in range(1, V)]
+    assert list(O.bfs(V, star, 0)) == [0] + [1] * (V - 1)
+    assert list(O.bfs(V, star, 3)) == [-1, -1, -1, 0] + [-1] * (V - 4)
+
+
+def test_bfs_matches_boolean_matrix_powers():
+    rng = np.random.default_rng(8)
+    V = 30
+    edges = sorted({key(a, b) for a, b in zip(rng.integers(0, V, 45), rng.integers(0, V, 45))})
+    A = np.zeros((V, V), dtype=np.int64)
+    for k in edges:
+        A[k >> 32, k & 0xFFFFFFFF] = 1
+    for src in (0, 3, 17):
+        want = np.full(V, -1)
+        reach = np.zeros(V, dtype=np.int64)
+        reach[src] = 1
+        seen = reach.copy()
+        want[src] = 0
+        for dist in range(1, V):
+            reach = ((reach @ A) > 0).astype(np.int64) & (1 - seen)
+            want[reach > 0] = dist
+            seen |= reach
+        assert list(O.bfs(V, edges, src)) == list(want)
+
+
+def test_cc_closed_forms_and_scipy():
+    V = 12
+    cyc = [key(i, (i + 1) % 4) for i in range(4)] + [key(4 + (i + 1) % 4, 4 + i) for i in range(4)]
+    lab = O.cc(V, cyc)
+    assert list(lab) == [0] * 4 + [4] * 4 + list(range(8, 12))
+    full = [key(u, v) for u in range(V) for v in range(V) if u != v]
+    assert list(O.cc(V, full)) == [0] * V
+    from scipy.sparse import coo_matrix
+    from scipy.sparse.csgraph import connected_components
+    rng = np.random.default_rng(9)
+    V = 200
+    edges = sorted({key(a, b) for a, b in zip(rng.integers(0, V, 150), rng.integers(0, V, 150))})
+    src = np.array([k >> 32 for k in edges])
+    dst = np.array([k & 0xFFFFFFFF for k in edges])
+    M = coo_matrix((np.ones(len(edges)), (src, dst)), shape=(V, V))
+    n, comp = connected_components(M, directed=True, connection="weak")
+    want = np.array([np.min(np.nonzero(comp == comp[v])[0]) for v in range(V)])
+    assert np.array_equal(O.cc(V, edges), want)
+    assert len(set(O.cc(V, edges))) == n
