@@ -1,0 +1,184 @@
+/*
+ * gpma.h -- C ABI of the MI355X (gfx950) GPMA+ dynamic-graph library.
+ *
+ * A directed graph lives on the GPU as a packed memory array (PMA): sorted
+ * 64-bit edge keys src<<32 | dst with bounded gaps, leaf segments of
+ * `leaf_size` slots and an implicit tree of segments over the leaves
+ * (Sha, Li, He, Tan, "Accelerating Dynamic Graph Analytics on GPUs",
+ * Section 4.1).  Each vertex u also owns a guard entry u<<32 | 0xFFFFFFFF
+ * that closes its row, so CSR row offsets stay valid while entries move
+ * (Section 4.2, "CSR as a case study").  Batches of insertions and deletions
+ * are applied by the lock-free, level-by-level GPMA+ update (Section 5.2,
+ * Algorithm "GPMA+ Segment-Oriented Insertion", and its dual for
+ * deletions).  PageRank, BFS and connected components (Section 6.1,
+ * "Applications") read the array in place.
+ *
+ * Conventions for every call:
+ *   - Pointers named *_dev are device pointers (HBM of the current device);
+ *     everything else is host memory.  The caller keeps ownership of every
+ *     buffer it passes; the library keeps no pointer to it after the call
+ *     returns, and reads/writes it only in work ordered on `stream`.
+ *   - Calls are ordered on the caller's `stream`.  They return to the host
+ *     once their work is enqueued, except where noted (each update batch
+ *     synchronises with the host once per tree level it climbs; resizes,
+ *     BFS levels and CC rounds also read small counters back).
+ *   - A handle must be used by one host thread at a time; handles are
+ *     independent.  Return value 0 = GPMA_OK, negative = error.
+ *   - On any error the handle is left exactly as it was before the call.
+ */
+#ifndef GPMA_H
+#define GPMA_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gpma gpma_t;
+
+enum {
+    GPMA_OK = 0,
+    GPMA_EINVAL = -1,   /* bad argument or key; nothing was changed */
+    GPMA_ENOMEM = -2,   /* device allocation failed; nothing was changed */
+    GPMA_EDEVICE = -3,  /* a HIP call failed */
+};
+
+/* empty slot (key 0 is the real edge (0,0), so a gap is all ones) */
+#define GPMA_EMPTY 0xFFFFFFFFFFFFFFFFull
+/* the column of a guard entry ("infinity", Section 4.2) */
+#define GPMA_GUARD_DST 0xFFFFFFFFu
+
+/* Density bounds of the segment tree (Section 4.1, figure "PMA insertion
+ * example"): rho (lower) and tau (upper) at the leaves and at the root, in
+ * per mille, interpolated linearly in the height in between.  An insertion
+ * merges into a segment iff (n_s + |U_s|)/capacity < tau_h, a deletion iff
+ * (n_s - |D_s|)/capacity > rho_h.
+ * Requirements (else GPMA_EINVAL): leaf_size a power of two in [16, 1024]
+ * (0 picks one: the next power of two >= log2 of the capacity, at least 16,
+ * Section 4.1 "leaf segments with O(log N) length"); 0 < rho_leaf <= rho_root
+ * < tau_root <= tau_leaf < 1000; 2*rho_root <= tau_root; and
+ * rho_leaf * leaf_size >= 1000 (no leaf can ever become empty).
+ * Defaults are the figure's: tau .92/.80, rho .08/.40. */
+typedef struct {
+    uint32_t leaf_size;
+    uint32_t tau_leaf_pm, tau_root_pm;
+    uint32_t rho_leaf_pm, rho_root_pm;
+    uint32_t flags;     /* reserved, must be 0 */
+} gpma_params;
+
+/* Per-batch statistics; filled when a non-NULL pointer is passed. */
+typedef struct {
+    uint64_t requested;      /* keys passed in */
+    uint64_t applied;        /* edges actually inserted / deleted */
+    uint64_t noops;          /* repeats, present inserts, absent deletes */
+    int32_t  top_level;      /* highest level with a merge, -1 if none */
+    uint32_t resized;        /* 1 when the root was rebuilt at a new capacity */
+    uint64_t segments_merged[40];  /* per level */
+    uint64_t slots_rewritten;      /* sum of capacities of merged segments */
+} gpma_stats;
+
+/* Fill *p with the defaults above. */
+void gpma_default_params(gpma_params *p);
+
+/* Build the PMA for `num_vertices` vertices (1 <= V <= 2^31) holding the set
+ * of `n` keys at init_keys_dev (unsorted; repeats collapse) plus V guards.
+ * Keys need src < V and dst < V.  The capacity is the smallest leaf_size*2^k
+ * whose root upper bound admits every entry (at most 2^31 slots); entries
+ * are spread evenly over all leaves.  Synchronises with the host once.
+ * *out receives the handle (NULL on error). */
+int gpma_create(gpma_t **out, uint32_t num_vertices, const uint64_t *init_keys_dev,
+                uint64_t n, const gpma_params *params, hipStream_t stream);
+
+/* Free every device buffer of the handle (after `stream`-ordered work on it
+ * has finished: the call synchronises the device). */
+int gpma_destroy(gpma_t *h);
+
+/* Set union with the b keys at keys_dev (Algorithm "GPMA+ Segment-Oriented
+ * Insertion"): sort, locate each key's leaf, then merge level by level; the
+ * root doubles when it cannot absorb what is left.  Keys already present and
+ * repeats are no-ops.  Any key with src >= V or dst >= V makes the whole
+ * batch a no-op and returns GPMA_EINVAL. */
+int gpma_insert_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
+                      hipStream_t stream, gpma_stats *stats);
+
+/* Set difference (the dual of insertion, Section 4.1): a segment absorbs
+ * its deletions iff it stays above its lower bound; the root halves when it
+ * falls below its own.  Absent keys are no-ops; guards cannot be named
+ * (dst must be < V). */
+int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
+                      hipStream_t stream, gpma_stats *stats);
+
+/* PageRank by power iteration (Section 6.1): exactly `iters` steps of
+ *   x'[v] = (1-d)/V + d * ( sum_{u->v} x[u]/outdeg(u) + D/V ),
+ * D = sum of x over vertices without out-edges (self-loops count).
+ * init_dev: V floats, or NULL for the uniform 1/V; out_dev: V floats, may
+ * alias init_dev (warm start from the previous result).  Products and sums
+ * are formed in fp64; each step rounds once to fp32.
+ * GPMA_EINVAL if iters == 0 or damping is not in (0,1). */
+int gpma_pagerank(gpma_t *h, const float *init_dev, float *out_dev, uint32_t iters,
+                  float damping, hipStream_t stream);
+
+/* BFS hop distances from `source` along out-edges (Section 4.2, Algorithm
+ * "Breadth-First Search"; rows are read through the CSR offsets and gaps
+ * and guards are skipped).  dist_dev: V int32, -1 = unreachable.
+ * GPMA_EINVAL if source >= V. */
+int gpma_bfs(gpma_t *h, uint32_t source, int32_t *dist_dev, hipStream_t stream);
+
+/* Connected components with edge direction ignored (Section 6.1); every
+ * vertex gets the smallest vertex id of its component.  label_dev: V uint32. */
+int gpma_cc(gpma_t *h, uint32_t *label_dev, hipStream_t stream);
+
+/* Introspection.  Counts are those after the last completed call. */
+uint64_t gpma_num_edges(const gpma_t *h);     /* guards excluded */
+uint64_t gpma_capacity(const gpma_t *h);      /* slots */
+uint32_t gpma_leaf_size(const gpma_t *h);
+uint32_t gpma_num_vertices(const gpma_t *h);
+
+/* Copy the raw slot array (capacity uint64, gaps = GPMA_EMPTY, guards
+ * included) to out_dev.  GPMA_EINVAL if max < capacity. *cap_out = capacity. */
+int gpma_export_slots(gpma_t *h, uint64_t *out_dev, uint64_t max, uint64_t *cap_out,
+                      hipStream_t stream);
+/* Copy the stored edges in key order (guards dropped).  GPMA_EINVAL if
+ * max < number of edges.  Synchronises; *n_out = number of edges. */
+int gpma_export_keys(gpma_t *h, uint64_t *out_dev, uint64_t max, uint64_t *n_out,
+                     hipStream_t stream);
+/* Per-leaf entry counts (capacity/leaf_size uint16). */
+int gpma_export_leaf_counts(gpma_t *h, uint16_t *out_dev, uint64_t max, hipStream_t stream);
+/* CSR row offsets on the PMA (V+1 uint32): row u spans slots
+ * [off[u], off[u+1]) and ends with its guard; off[0] = 0. */
+int gpma_export_row_offsets(gpma_t *h, uint32_t *out_dev, uint64_t max, hipStream_t stream);
+/* Out-degrees (V uint32), guards excluded. */
+int gpma_export_degrees(gpma_t *h, uint32_t *out_dev, uint64_t max, hipStream_t stream);
+
+/* Wait for all work of the handle.  Returns 0. */
+int gpma_sync(gpma_t *h);
+
+/* Static message for an error code. */
+const char *gpma_strerror(int code);
+
+/* Kernel timing for roofline accounting.  When enabled, the library brackets
+ * every launch of the kernels below with HIP events on the launch stream and
+ * accumulates elapsed time, launch count and algorithmic bytes (what the
+ * method must move; see the per-kernel notes in the implementation).
+ * gpma_profile_read synchronises the events it reads. */
+enum {
+    GPMA_K_SPMV = 0,      /* PageRank push over the slot stream */
+    GPMA_K_LEAF_MERGE,    /* level-0 fused probe/check/merge */
+    GPMA_K_SEG_MERGE,     /* levels >= 1, workgroup tier */
+    GPMA_K_SORT,          /* whole batch radix sort (all passes) */
+    GPMA_K_LOCATE,        /* leaf search */
+    GPMA_K_BFS,           /* frontier expansion */
+    GPMA_K_CC,            /* hooking sweep */
+    GPMA_K_COUNT
+};
+int gpma_profile_enable(gpma_t *h, int enable);
+int gpma_profile_reset(gpma_t *h);
+int gpma_profile_read(gpma_t *h, int kernel, double *ms_total, uint64_t *launches,
+                      double *bytes_total);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPMA_H */

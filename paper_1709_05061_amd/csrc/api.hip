@@ -1,0 +1,804 @@
+// Host side of the GPMA+ library: the C ABI, the handle, the density bounds,
+// the level-by-level driver of the batched update (Section 5.2, Algorithm
+// "GPMA+ Segment-Oriented Insertion" and its dual), root resize, and the
+// analytics drivers.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+
+using namespace gpma_dev;
+using namespace gpma_host;
+
+namespace {
+
+constexpr uint64_t kMaxCap = 1ull << 31;   // row offsets are uint32
+constexpr uint32_t kMaxLeaf = 512;
+
+uint32_t ilog2(uint64_t x) {
+    uint32_t r = 0;
+    while (x > 1) { x >>= 1; r++; }
+    return r;
+}
+uint32_t bit_width(uint64_t x) {
+    uint32_t b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+uint64_t next_pow2(uint64_t x) {
+    uint64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+struct Prof {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+
+}  // namespace
+
+struct gpma {
+    uint32_t V = 0, lf = 0, lf_log2 = 0;
+    uint32_t tau_leaf = 0, tau_root = 0, rho_leaf = 0, rho_root = 0;
+    uint64_t cap = 0, L = 0;
+    uint32_t H = 0;
+    uint64_t n = 0;   // stored entries, guards included
+    uint64_t *slots = nullptr;
+    uint16_t *cnt = nullptr;
+    uint32_t *row_ptr = nullptr;
+    uint32_t *deg = nullptr;
+
+    // batch scratch
+    uint64_t bcap = 0;
+    uint64_t *kA = nullptr, *kB = nullptr, *kC = nullptr, *kD = nullptr;
+    uint32_t *leafA = nullptr, *leafB = nullptr;
+    uint8_t *stA = nullptr, *stB = nullptr;
+    uint32_t *flags = nullptr, *tmp = nullptr;
+    Ctl *ctl = nullptr;       // device
+    Ctl *ctl_h = nullptr;     // pinned host mirror
+
+    // device-tier scratch (grown on demand)
+    uint64_t dt_cap = 0;
+    uint64_t *dtA = nullptr, *dtB = nullptr;
+    uint64_t dt_off_cap = 0;
+    uint32_t *dt_off = nullptr, *dt_tmp = nullptr, *dt_tot = nullptr;
+
+    // analytics scratch
+    double *pr_contrib = nullptr, *pr_y = nullptr, *pr_dang = nullptr;
+    uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *small = nullptr;
+    uint32_t *small_h = nullptr;   // pinned
+
+    Device dev;
+    int prof_on = 0;
+    std::vector<Prof> prof_pending;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[GPMA_K_COUNT] = {};
+    double prof_bytes[GPMA_K_COUNT] = {};
+    uint64_t prof_n[GPMA_K_COUNT] = {};
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(T **p, uint64_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return GPMA_ENOMEM;
+    }
+    return GPMA_OK;
+}
+
+template <typename T>
+void dev_free(T *&p) {
+    if (p) hipFree((void *)p);
+    p = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// density bounds (Section 4.1, figure "PMA insertion example")
+//
+// rho_h and tau_h move linearly with the height h from the leaf values to the
+// root values; a one-leaf tree (H = 0) uses the root values.  With
+// cap_h = lf * 2^h slots, an insertion passes iff (n+u)/cap_h < tau_h, i.e.
+// n+u <= hi = ceil(tau_h*cap_h) - 1, and a deletion iff (n-d)/cap_h > rho_h,
+// i.e. n-d >= lo = floor(rho_h*cap_h) + 1.  Exact in 64-bit integers:
+// tau_h*cap_h = (tau_leaf*(H-h) + tau_root*h) * cap_h / (1000*H).
+void bounds_at(uint32_t lf, uint32_t tl, uint32_t tr, uint32_t rl, uint32_t rr, uint32_t H,
+               uint32_t h, uint64_t *lo, uint64_t *hi) {
+    const uint64_t cap_h = (uint64_t)lf << h;
+    const uint64_t wl = H ? (uint64_t)(H - h) : 0, wr = H ? (uint64_t)h : 1;
+    const uint64_t den = 1000ull * (H ? H : 1);
+    const uint64_t t = ((uint64_t)tl * wl + (uint64_t)tr * wr) * cap_h;
+    const uint64_t r = ((uint64_t)rl * wl + (uint64_t)rr * wr) * cap_h;
+    *hi = (t % den ? t / den + 1 : t / den) - 1;
+    *lo = r / den + 1;
+}
+
+void bounds(const gpma *g, uint32_t H, uint32_t h, uint64_t *lo, uint64_t *hi) {
+    bounds_at(g->lf, g->tau_leaf, g->tau_root, g->rho_leaf, g->rho_root, H, h, lo, hi);
+}
+
+uint64_t root_hi(const gpma *g, uint64_t cap) {
+    uint64_t lo, hi;
+    uint32_t H = ilog2(cap / g->lf);
+    bounds(g, H, H, &lo, &hi);
+    return hi;
+}
+uint64_t root_lo(const gpma *g, uint64_t cap) {
+    uint64_t lo, hi;
+    uint32_t H = ilog2(cap / g->lf);
+    bounds(g, H, H, &lo, &hi);
+    return lo;
+}
+
+bool params_valid(const gpma_params *p, bool allow_auto) {
+    uint32_t lf = p->leaf_size;
+    if (!(allow_auto && lf == 0)) {
+        if (lf < 16 || lf > kMaxLeaf || (lf & (lf - 1))) return false;
+        if ((uint64_t)p->rho_leaf_pm * lf < 1000) return false;
+    }
+    if (!(p->rho_leaf_pm > 0 && p->rho_leaf_pm <= p->rho_root_pm && p->rho_root_pm < p->tau_root_pm &&
+          p->tau_root_pm <= p->tau_leaf_pm && p->tau_leaf_pm < 1000))
+        return false;
+    if (2 * p->rho_root_pm > p->tau_root_pm) return false;
+    if (p->flags) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+
+hipEvent_t ev_get(gpma *g) {
+    if (!g->ev_pool.empty()) {
+        hipEvent_t e = g->ev_pool.back();
+        g->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    hipEventCreate(&e);
+    return e;
+}
+
+struct ProfScope {
+    gpma *g;
+    int kind;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    ProfScope(gpma *g_, int k, hipStream_t s_) : g(g_), kind(k), s(s_) {
+        if (g->prof_on) {
+            a = ev_get(g);
+            hipEventRecord(a, s);
+        }
+    }
+    void done(double bytes) {
+        if (!a) return;
+        hipEvent_t b = ev_get(g);
+        hipEventRecord(b, s);
+        g->prof_pending.push_back(Prof{kind, a, b, bytes});
+        a = nullptr;
+    }
+    ~ProfScope() { done(0.0); }
+};
+
+void prof_collect(gpma *g) {
+    for (auto &p : g->prof_pending) {
+        hipEventSynchronize(p.b);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, p.a, p.b);
+        g->prof_ms[p.kind] += ms;
+        g->prof_bytes[p.kind] += p.bytes;
+        g->prof_n[p.kind] += 1;
+        g->ev_pool.push_back(p.a);
+        g->ev_pool.push_back(p.b);
+    }
+    g->prof_pending.clear();
+}
+
+// ---------------------------------------------------------------------------
+// scratch management
+
+void free_batch(gpma *g) {
+    dev_free(g->kA); dev_free(g->kB); dev_free(g->kC); dev_free(g->kD);
+    dev_free(g->leafA); dev_free(g->leafB); dev_free(g->stA); dev_free(g->stB);
+    dev_free(g->flags); dev_free(g->tmp);
+    g->bcap = 0;
+}
+
+int ensure_batch(gpma *g, uint64_t b) {
+    if (b <= g->bcap) return GPMA_OK;
+    free_batch(g);
+    uint64_t c = next_pow2(std::max<uint64_t>(b, 4096));
+    size_t tw = std::max(radix_tmp_words(c), scan_tmp_words(c + 1));
+    int e = GPMA_OK;
+    e |= dev_alloc(&g->kA, c); e |= dev_alloc(&g->kB, c);
+    e |= dev_alloc(&g->kC, c); e |= dev_alloc(&g->kD, c);
+    e |= dev_alloc(&g->leafA, c); e |= dev_alloc(&g->leafB, c);
+    e |= dev_alloc(&g->stA, c); e |= dev_alloc(&g->stB, c);
+    e |= dev_alloc(&g->flags, c + 1); e |= dev_alloc(&g->tmp, tw);
+    if (e) {
+        free_batch(g);
+        return GPMA_ENOMEM;
+    }
+    g->bcap = c;
+    return GPMA_OK;
+}
+
+int ensure_dt(gpma *g, uint64_t entries, uint64_t leaves) {
+    if (entries > g->dt_cap) {
+        dev_free(g->dtA); dev_free(g->dtB);
+        g->dt_cap = 0;
+        uint64_t c = next_pow2(entries);
+        if (dev_alloc(&g->dtA, c) || dev_alloc(&g->dtB, c)) {
+            dev_free(g->dtA); dev_free(g->dtB);
+            return GPMA_ENOMEM;
+        }
+        g->dt_cap = c;
+    }
+    if (leaves > g->dt_off_cap) {
+        dev_free(g->dt_off); dev_free(g->dt_tmp);
+        g->dt_off_cap = 0;
+        uint64_t c = next_pow2(leaves);
+        if (dev_alloc(&g->dt_off, c) || dev_alloc(&g->dt_tmp, scan_tmp_words(c))) {
+            dev_free(g->dt_off); dev_free(g->dt_tmp);
+            return GPMA_ENOMEM;
+        }
+        g->dt_off_cap = c;
+    }
+    return GPMA_OK;
+}
+
+void read_ctl(gpma *g, hipStream_t s) {
+    hipMemcpyAsync(g->ctl_h, g->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+}
+
+void set_geometry(gpma *g, uint64_t cap) {
+    g->cap = cap;
+    g->L = cap >> g->lf_log2;
+    g->H = ilog2(g->L);
+}
+
+// Exclusive prefix of the leaf counts of leaves [first, first+P) into
+// g->dt_off; returns the segment's entry count (one host sync).
+int segment_offsets(gpma *g, uint64_t first, uint64_t P, uint64_t *ns, hipStream_t s) {
+    int e = ensure_dt(g, 0, P);
+    if (e) return e;
+    launch_leaf_counts_u32(g->cnt, first, P, g->dt_off, s);
+    scan_u32(g->dt_off, g->dt_off, P, g->small, g->dt_tmp, s);
+    hipMemcpyAsync(g->small_h, g->small, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    *ns = g->small_h[0];
+    return GPMA_OK;
+}
+
+// Root rebuild: merge every stored entry with the k remaining updates U and
+// re-dispatch all of them evenly over ncap slots (ncap == cap: in place).
+int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t k, uint64_t n_now,
+                 uint64_t ncap, hipStream_t s) {
+    uint64_t ns = 0;
+    int e = segment_offsets(g, 0, g->L, &ns, s);
+    if (e) return e;
+    if (ns != n_now) return GPMA_EDEVICE;   // host and device disagree: refuse to write
+    uint64_t N = del ? ns - k : ns + k;
+    e = ensure_dt(g, ns + k, 0);
+    if (e) return e;
+    uint64_t *nslots = g->slots;
+    uint16_t *ncnt = g->cnt;
+    if (ncap != g->cap) {
+        if (dev_alloc(&nslots, ncap)) return GPMA_ENOMEM;
+        if (dev_alloc(&ncnt, ncap >> g->lf_log2)) {
+            dev_free(nslots);
+            return GPMA_ENOMEM;
+        }
+    }
+    launch_gather_segment(g->slots, g->cnt, 0, g->L, g->lf, g->dt_off, g->dtA, s);
+    launch_merge_sorted(del, g->dtA, ns, U, k, g->dtB, s);
+    launch_dispatch(g->dtB, N, nslots, ncnt, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
+    launch_mark_done(del, U, status, 0, k, g->deg, g->ctl, ncap, s);
+    if (ncap != g->cap) {
+        hipStreamSynchronize(s);
+        dev_free(g->slots);
+        dev_free(g->cnt);
+        g->slots = nslots;
+        g->cnt = ncnt;
+        set_geometry(g, ncap);
+    }
+    return GPMA_OK;
+}
+
+
+struct LevelArrays {
+    uint64_t *k;
+    uint32_t *l;
+    uint8_t *st;
+    uint32_t *n;   // device count of pending updates
+};
+
+// Host-driven device tier at height h: the remaining updates' leaves come
+// back to the host, are grouped by segment, and every segment is counted,
+// checked and (if it passes) gathered, merged and re-dispatched by kernels.
+int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint64_t rem,
+                      uint64_t lo, uint64_t hi, hipStream_t s) {
+    std::vector<uint32_t> lh(rem);
+    hipMemcpyAsync(lh.data(), c.l, rem * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    const uint64_t P = 1ull << h;
+    for (uint64_t i = 0; i < rem;) {
+        const uint32_t seg = lh[i] >> h;
+        uint64_t j = i;
+        while (j < rem && (lh[j] >> h) == seg) j++;
+        const uint64_t k = j - i, first = (uint64_t)seg << h;
+        uint64_t ns = 0;
+        int e = segment_offsets(g, first, P, &ns, s);
+        if (e) return e;
+        const bool pass = del ? (ns >= k + lo) : (ns + k <= hi);
+        if (pass) {
+            e = ensure_dt(g, ns + k, 0);
+            if (e) return e;
+            launch_gather_segment(g->slots, g->cnt, first, P, g->lf, g->dt_off, g->dtA, s);
+            launch_merge_sorted(del, g->dtA, ns, c.k + i, k, g->dtB, s);
+            launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->cnt, g->row_ptr, first, P, g->lf, s);
+            launch_mark_done(del, c.k, c.st, i, k, g->deg, g->ctl, P << g->lf_log2, s);
+        }
+        i = j;
+    }
+    return GPMA_OK;
+}
+
+int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t s,
+                gpma_stats *st) {
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->requested = b;
+        st->top_level = -1;
+    }
+    if (b == 0) return GPMA_OK;
+    if (!keys || b >= (1ull << 31)) return GPMA_EINVAL;
+    int e = ensure_batch(g, b);
+    if (e) return e;
+
+    // Sort(U) and drop repeats
+    hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
+    launch_validate(keys, b, g->V, g->ctl, s);
+    const uint32_t sb = bit_width(g->V - 1);
+    const uint64_t *sorted;
+    {
+        ProfScope ps(g, GPMA_K_SORT, s);
+        sorted = radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s);
+        ps.done(16.0 * (double)b * (double)((2 * sb + 7) / 8));
+    }
+    uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
+    LevelArrays cur{ukeys, g->leafA, g->stA, &g->ctl->n_in};
+    LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
+    unique_sorted(sorted, b, ukeys, cur.n, g->flags, g->tmp, s);
+
+    // BinarySearchLeafSegments
+    {
+        ProfScope ps(g, GPMA_K_LOCATE, s);
+        launch_locate(cur.k, cur.n, b, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
+        ps.done(16.0 * (double)b);
+    }
+
+    // level 0 (fused with the no-op probe)
+    uint64_t lo, hi;
+    bounds(g, g->H, 0, &lo, &hi);
+    hipEvent_t pa = nullptr, pb = nullptr;
+    if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
+    launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->row_ptr, g->deg,
+                      g->lf, lo, hi, g->ctl, s);
+    if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
+    compact_pending(cur.k, cur.l, cur.st, cur.n, b, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, s);
+    read_ctl(g, s);
+    if (g->ctl_h->err) {
+        if (pa) { g->ev_pool.push_back(pa); g->ev_pool.push_back(pb); }
+        return GPMA_EINVAL;
+    }
+    const uint64_t distinct = g->ctl_h->n_in;
+    uint32_t segs_seen = g->ctl_h->segs;
+    if (pa) g->prof_pending.push_back(Prof{GPMA_K_LEAF_MERGE, pa, pb,
+                                           16.0 * g->lf * segs_seen + 12.0 * (double)distinct});
+    if (st) {
+        st->segments_merged[0] = segs_seen;
+        if (segs_seen) st->top_level = 0;
+    }
+    uint64_t rem = g->ctl_h->lvl[0];
+    std::swap(cur, nxt);
+    nxt.k = (cur.k == g->kC) ? g->kD : g->kC;
+    nxt.l = (cur.l == g->leafB) ? g->leafA : g->leafB;
+    nxt.st = (cur.st == g->stB) ? g->stA : g->stB;
+    nxt.n = (cur.n == &g->ctl->lvl[0]) ? &g->ctl->lvl[1] : &g->ctl->lvl[0];
+
+    // levels 1 .. H-1: ascend with whatever is left
+    for (uint32_t h = 1; h < g->H && rem > 0; h++) {
+        bounds(g, g->H, h, &lo, &hi);
+        if (seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds) {
+            pa = pb = nullptr;
+            if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
+            launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, rem, g->slots, g->cnt, g->row_ptr,
+                             g->deg, g->lf, lo, hi, g->ctl, s);
+            if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
+        } else {
+            pa = pb = nullptr;
+            e = device_tier_level(g, del, h, cur, rem, lo, hi, s);
+            if (e) return e;
+        }
+        compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags,
+                        g->tmp, s);
+        read_ctl(g, s);
+        const uint32_t segs_h = g->ctl_h->segs - segs_seen;
+        segs_seen = g->ctl_h->segs;
+        if (pa) g->prof_pending.push_back(Prof{GPMA_K_SEG_MERGE, pa, pb,
+                                               16.0 * (double)(g->lf << h) * segs_h + 12.0 * (double)rem});
+        if (st) {
+            st->segments_merged[h] = segs_h;
+            if (segs_h) st->top_level = (int32_t)h;
+        }
+        rem = (nxt.n == &g->ctl->lvl[0]) ? g->ctl_h->lvl[0] : g->ctl_h->lvl[1];
+        std::swap(cur, nxt);
+        nxt.k = (cur.k == g->kC) ? g->kD : g->kC;
+        nxt.l = (cur.l == g->leafB) ? g->leafA : g->leafB;
+        nxt.st = (cur.st == g->stB) ? g->stA : g->stB;
+        nxt.n = (cur.n == &g->ctl->lvl[0]) ? &g->ctl->lvl[1] : &g->ctl->lvl[0];
+    }
+
+    // the root: absorb in place when the bound holds, else resize
+    bool resized = false;
+    if (rem > 0) {
+        const uint64_t n_now = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+        uint64_t ncap = g->cap;
+        if (!del) {
+            while (n_now + rem > root_hi(g, ncap)) ncap *= 2;
+        } else {
+            const uint64_t left = n_now - rem;
+            while (ncap > g->lf && left < root_lo(g, ncap) && left <= root_hi(g, ncap / 2)) ncap /= 2;
+        }
+        if (ncap > kMaxCap) return GPMA_ENOMEM;
+        const uint32_t Hold = g->H;
+        const uint64_t cap_old = g->cap;
+        e = rebuild_root(g, del, cur.k, cur.st, rem, n_now, ncap, s);
+        if (e) return e;
+        read_ctl(g, s);
+        resized = g->cap != cap_old;
+        if (st) {
+            st->segments_merged[Hold] += 1;
+            st->top_level = (int32_t)Hold;
+        }
+    }
+    g->n = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+    if (st) {
+        st->applied = g->ctl_h->applied;
+        st->noops = b - g->ctl_h->applied;
+        st->slots_rewritten = g->ctl_h->rewritten;
+        st->resized = resized ? 1 : 0;
+    }
+    return GPMA_OK;
+}
+
+void free_all(gpma *g) {
+    free_batch(g);
+    dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
+    dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
+    dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
+    dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->small);
+    dev_free(g->ctl);
+    if (g->ctl_h) hipHostFree(g->ctl_h);
+    if (g->small_h) hipHostFree(g->small_h);
+    g->ctl_h = nullptr;
+    g->small_h = nullptr;
+    for (auto &p : g->prof_pending) { hipEventDestroy(p.a); hipEventDestroy(p.b); }
+    g->prof_pending.clear();
+    for (auto e : g->ev_pool) hipEventDestroy(e);
+    g->ev_pool.clear();
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+
+extern "C" {
+
+void gpma_default_params(gpma_params *p) {
+    p->leaf_size = 0;
+    p->tau_leaf_pm = 920;
+    p->tau_root_pm = 800;
+    p->rho_leaf_pm = 80;
+    p->rho_root_pm = 400;
+    p->flags = 0;
+}
+
+const char *gpma_strerror(int code) {
+    switch (code) {
+        case GPMA_OK: return "ok";
+        case GPMA_EINVAL: return "invalid argument or key";
+        case GPMA_ENOMEM: return "device memory allocation failed";
+        case GPMA_EDEVICE: return "HIP call failed";
+        default: return "unknown error";
+    }
+}
+
+int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, const gpma_params *params,
+                hipStream_t s) {
+    if (!out) return GPMA_EINVAL;
+    *out = nullptr;
+    gpma_params p;
+    if (params) p = *params; else gpma_default_params(&p);
+    if (!params_valid(&p, true)) return GPMA_EINVAL;
+    if (V == 0 || V > (1u << 31)) return GPMA_EINVAL;
+    if (n && !keys) return GPMA_EINVAL;
+    const uint64_t tot = n + V;
+    if (tot >= kMaxCap) return GPMA_EINVAL;
+
+    gpma *g = new (std::nothrow) gpma();
+    if (!g) return GPMA_ENOMEM;
+    g->V = V;
+    g->tau_leaf = p.tau_leaf_pm; g->tau_root = p.tau_root_pm;
+    g->rho_leaf = p.rho_leaf_pm; g->rho_root = p.rho_root_pm;
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&g->dev.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    hipDeviceGetAttribute(&g->dev.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (g->dev.max_lds > 65536) g->dev.max_lds = 65536;
+    // GPMA_TIER_LDS caps the LDS the workgroup tier may use, so tests can
+    // drive small segments through the device tier
+    if (const char *t = getenv("GPMA_TIER_LDS")) g->dev.max_lds = std::min(g->dev.max_lds, atoi(t));
+
+    int e = GPMA_OK;
+    uint64_t *in = nullptr, *ba = nullptr, *bb = nullptr, *uq = nullptr;
+    uint32_t *fl = nullptr, *tmp = nullptr;
+    e |= dev_alloc(&g->ctl, 1);
+    e |= dev_alloc(&g->small, 4);
+    if (hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc((void **)&g->small_h, 4 * sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
+    e |= dev_alloc(&in, tot); e |= dev_alloc(&ba, tot); e |= dev_alloc(&bb, tot);
+    e |= dev_alloc(&fl, tot + 1);
+    e |= dev_alloc(&tmp, std::max(radix_tmp_words(tot), scan_tmp_words(tot + 1)));
+    if (e) {
+        dev_free(in); dev_free(ba); dev_free(bb); dev_free(fl); dev_free(tmp);
+        free_all(g);
+        delete g;
+        return GPMA_ENOMEM;
+    }
+    hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
+    if (n) {
+        hipMemcpyAsync(in, keys, n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+        launch_validate(keys, n, V, g->ctl, s);
+    }
+    launch_append_guards(in + n, V, s);
+    const uint64_t *sorted = radix_sort_keys(in, tot, bit_width(V - 1), bit_width(V), V, ba, bb, tmp, s);
+    uq = (sorted == ba) ? bb : ba;
+    unique_sorted(sorted, tot, uq, &g->ctl->n_in, fl, tmp, s);
+    read_ctl(g, s);
+    const uint64_t nu = g->ctl_h->n_in;
+    auto cleanup = [&]() { dev_free(in); dev_free(ba); dev_free(bb); dev_free(fl); dev_free(tmp); };
+    if (g->ctl_h->err) {
+        cleanup();
+        free_all(g);
+        delete g;
+        return GPMA_EINVAL;
+    }
+    // capacity: the smallest power of two (at least one leaf) whose root bound
+    // admits every entry; the leaf length then follows it (O(log N), at least 16)
+    uint32_t lf = p.leaf_size;
+    uint64_t cap = 16;
+    g->lf = 16;
+    while (nu > root_hi(g, cap)) cap *= 2;
+    if (lf == 0) {
+        lf = (uint32_t)std::max<uint64_t>(16, next_pow2(ilog2(cap)));
+        while ((uint64_t)g->rho_leaf * lf < 1000) lf *= 2;
+        lf = std::min(lf, kMaxLeaf);
+    }
+    g->lf = lf;
+    g->lf_log2 = ilog2(lf);
+    cap = lf;
+    while (nu > root_hi(g, cap)) cap *= 2;
+    if (cap > kMaxCap) {
+        cleanup();
+        free_all(g);
+        delete g;
+        return GPMA_EINVAL;
+    }
+    set_geometry(g, cap);
+    e |= dev_alloc(&g->slots, cap);
+    e |= dev_alloc(&g->cnt, g->L);
+    e |= dev_alloc(&g->row_ptr, (uint64_t)V + 1);
+    e |= dev_alloc(&g->deg, V);
+    if (e) {
+        cleanup();
+        free_all(g);
+        delete g;
+        return GPMA_ENOMEM;
+    }
+    hipMemsetAsync(g->row_ptr, 0, sizeof(uint32_t), s);
+    launch_dispatch(uq, nu, g->slots, g->cnt, g->row_ptr, 0, g->L, lf, s);
+    launch_degrees_from_sorted(uq, nu, V, fl, g->deg, s);
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        cleanup();
+        free_all(g);
+        delete g;
+        return GPMA_EDEVICE;
+    }
+    cleanup();
+    g->n = nu;
+    *out = g;
+    return GPMA_OK;
+}
+
+int gpma_destroy(gpma_t *g) {
+    if (!g) return GPMA_OK;
+    hipDeviceSynchronize();
+    free_all(g);
+    delete g;
+    return GPMA_OK;
+}
+
+int gpma_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st) {
+    if (!g) return GPMA_EINVAL;
+    return apply_batch(g, keys, b, false, s, st);
+}
+
+int gpma_delete_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st) {
+    if (!g) return GPMA_EINVAL;
+    return apply_batch(g, keys, b, true, s, st);
+}
+
+uint64_t gpma_num_edges(const gpma_t *g) { return g ? g->n - g->V : 0; }
+uint64_t gpma_capacity(const gpma_t *g) { return g ? g->cap : 0; }
+uint32_t gpma_leaf_size(const gpma_t *g) { return g ? g->lf : 0; }
+uint32_t gpma_num_vertices(const gpma_t *g) { return g ? g->V : 0; }
+
+int gpma_export_slots(gpma_t *g, uint64_t *out, uint64_t max, uint64_t *cap_out, hipStream_t s) {
+    if (!g) return GPMA_EINVAL;
+    if (cap_out) *cap_out = g->cap;
+    if (!out || max < g->cap) return GPMA_EINVAL;
+    hipMemcpyAsync(out, g->slots, g->cap * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+    return GPMA_OK;
+}
+
+int gpma_export_keys(gpma_t *g, uint64_t *out, uint64_t max, uint64_t *n_out, hipStream_t s) {
+    if (!g) return GPMA_EINVAL;
+    const uint64_t m = g->n - g->V;
+    if (n_out) *n_out = m;
+    if (!out || max < m) return GPMA_EINVAL;
+    uint32_t *fl = nullptr, *tmp = nullptr;
+    if (dev_alloc(&fl, g->cap + 1) || dev_alloc(&tmp, scan_tmp_words(g->cap))) {
+        dev_free(fl);
+        dev_free(tmp);
+        return GPMA_ENOMEM;
+    }
+    compact_edges(g->slots, g->cap, out, g->small, fl, tmp, s);
+    hipStreamSynchronize(s);
+    dev_free(fl);
+    dev_free(tmp);
+    return GPMA_OK;
+}
+
+int gpma_export_leaf_counts(gpma_t *g, uint16_t *out, uint64_t max, hipStream_t s) {
+    if (!g || !out || max < g->L) return GPMA_EINVAL;
+    hipMemcpyAsync(out, g->cnt, g->L * sizeof(uint16_t), hipMemcpyDeviceToDevice, s);
+    return GPMA_OK;
+}
+
+int gpma_export_row_offsets(gpma_t *g, uint32_t *out, uint64_t max, hipStream_t s) {
+    if (!g || !out || max < (uint64_t)g->V + 1) return GPMA_EINVAL;
+    hipMemcpyAsync(out, g->row_ptr, ((uint64_t)g->V + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    return GPMA_OK;
+}
+
+int gpma_export_degrees(gpma_t *g, uint32_t *out, uint64_t max, hipStream_t s) {
+    if (!g || !out || max < g->V) return GPMA_EINVAL;
+    hipMemcpyAsync(out, g->deg, (uint64_t)g->V * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    return GPMA_OK;
+}
+
+int gpma_sync(gpma_t *g) {
+    (void)g;
+    hipDeviceSynchronize();
+    return GPMA_OK;
+}
+
+int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, float damping,
+                  hipStream_t s) {
+    if (!g || !out || iters == 0 || !(damping > 0.f && damping < 1.f)) return GPMA_EINVAL;
+    if (!g->pr_contrib) {
+        int e = GPMA_OK;
+        e |= dev_alloc(&g->pr_contrib, g->V);
+        e |= dev_alloc(&g->pr_y, g->V);
+        e |= dev_alloc(&g->pr_dang, 1);
+        if (e) {
+            dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
+            return GPMA_ENOMEM;
+        }
+    }
+    const double spmv_bytes = 8.0 * (double)g->n + 16.0 * (double)g->V;
+    for (uint32_t it = 0; it < iters; it++) {
+        const float *x = it == 0 ? init : out;
+        launch_pr_prep(x, g->deg, g->V, x == nullptr, g->pr_contrib, g->pr_y, g->pr_dang, s);
+        {
+            ProfScope ps(g, GPMA_K_SPMV, s);
+            launch_pr_spmv(g->slots, g->cap, g->pr_contrib, g->pr_y, s);
+            ps.done(spmv_bytes);
+        }
+        launch_pr_combine(g->pr_y, g->pr_dang, g->V, (double)damping, out, s);
+    }
+    return GPMA_OK;
+}
+
+int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
+    if (!g || !dist || source >= g->V) return GPMA_EINVAL;
+    if (!g->bfs_q0) {
+        if (dev_alloc(&g->bfs_q0, g->V) || dev_alloc(&g->bfs_q1, g->V)) {
+            dev_free(g->bfs_q0); dev_free(g->bfs_q1);
+            return GPMA_ENOMEM;
+        }
+    }
+    uint32_t *cur = g->bfs_q0, *nxt = g->bfs_q1;
+    launch_bfs_init(dist, g->V, source, cur, g->small, s);
+    uint32_t nfront = 1;
+    for (int32_t level = 0; nfront > 0; level++) {
+        hipMemsetAsync(g->small + 1, 0, sizeof(uint32_t), s);
+        {
+            ProfScope ps(g, GPMA_K_BFS, s);
+            launch_bfs_expand(g->slots, g->row_ptr, cur, nfront, level, dist, nxt, g->small + 1, s);
+        }
+        hipMemcpyAsync(g->small_h, g->small + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        nfront = g->small_h[0];
+        std::swap(cur, nxt);
+    }
+    return GPMA_OK;
+}
+
+int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
+    if (!g || !label) return GPMA_EINVAL;
+    launch_cc_init(label, g->V, s);
+    for (int round = 0;; round++) {
+        hipMemsetAsync(g->small + 2, 0, sizeof(uint32_t), s);
+        {
+            ProfScope ps(g, GPMA_K_CC, s);
+            launch_cc_hook(g->slots, g->cap, label, g->small + 2, s);
+            ps.done(8.0 * (double)g->n + 8.0 * (double)g->V);
+        }
+        launch_cc_compress(label, g->V, s);
+        hipMemcpyAsync(g->small_h + 2, g->small + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        if (!g->small_h[2]) break;
+    }
+    return GPMA_OK;
+}
+
+int gpma_profile_enable(gpma_t *g, int enable) {
+    if (!g) return GPMA_EINVAL;
+    g->prof_on = enable ? 1 : 0;
+    return GPMA_OK;
+}
+
+int gpma_profile_reset(gpma_t *g) {
+    if (!g) return GPMA_EINVAL;
+    prof_collect(g);
+    for (int k = 0; k < GPMA_K_COUNT; k++) {
+        g->prof_ms[k] = 0;
+        g->prof_bytes[k] = 0;
+        g->prof_n[k] = 0;
+    }
+    return GPMA_OK;
+}
+
+int gpma_profile_read(gpma_t *g, int kernel, double *ms, uint64_t *launches, double *bytes) {
+    if (!g || kernel < 0 || kernel >= GPMA_K_COUNT) return GPMA_EINVAL;
+    prof_collect(g);
+    if (ms) *ms = g->prof_ms[kernel];
+    if (launches) *launches = g->prof_n[kernel];
+    if (bytes) *bytes = g->prof_bytes[kernel];
+    return GPMA_OK;
+}
+
+}  // extern "C"

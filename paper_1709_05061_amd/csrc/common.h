@@ -1,0 +1,173 @@
+// Internal declarations shared by the HIP sources of the GPMA+ library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gpma.h"
+
+namespace gpma_dev {
+
+constexpr uint64_t kEmpty = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint32_t kGuardDst = 0xFFFFFFFFu;
+constexpr int kWave = 64;
+
+// status of one update inside a batch
+enum : uint8_t { kPending = 0, kDone = 1, kNoop = 2 };
+
+// Device-side control block of one batch.  The host reads it back once per
+// level (one small copy) to decide whether to climb further.
+struct Ctl {
+    uint32_t err;        // an invalid key was seen: the batch is a no-op
+    uint32_t n_in;       // distinct updates of the batch
+    uint32_t lvl[2];     // pending updates after alternate levels (compactions)
+    uint32_t segs;       // segments merged so far in the batch
+    uint64_t applied;    // updates merged so far in the batch
+    uint64_t noops;      // updates dropped as no-ops
+    int64_t dn;          // change of the stored entry count so far
+    uint64_t rewritten;  // sum of capacities of merged segments
+};
+
+__device__ __forceinline__ bool is_guard(uint64_t k) {
+    return (uint32_t)k == kGuardDst;
+}
+__device__ __forceinline__ uint32_t key_src(uint64_t k) { return (uint32_t)(k >> 32); }
+__device__ __forceinline__ uint32_t key_dst(uint64_t k) { return (uint32_t)k; }
+
+// number of a[0..n) that are < k (a sorted)
+template <typename PtrT>
+__device__ __forceinline__ uint32_t lower_bound_u64(PtrT a, uint32_t n, uint64_t k) {
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename PtrT>
+__device__ __forceinline__ bool contains_u64(PtrT a, uint32_t n, uint64_t k) {
+    uint32_t i = lower_bound_u64(a, n, k);
+    return i < n && a[i] == k;
+}
+
+// Even re-dispatch of N ranked entries over P leaves: leaf j holds ranks
+// [floor(jN/P), floor((j+1)N/P)).  Rank r therefore sits in leaf
+// ceil((r+1)P/N) - 1 at offset r - floor(leaf*N/P).
+__device__ __forceinline__ uint64_t leaf_start(uint64_t j, uint64_t N, uint64_t P) {
+    return (uint64_t)(((unsigned __int128)j * N) / P);
+}
+__device__ __forceinline__ uint64_t rank_leaf(uint64_t r, uint64_t N, uint64_t P) {
+    return (uint64_t)((((unsigned __int128)(r + 1)) * P - 1) / N);
+}
+
+// wave-level ordering of LDS traffic between lanes of one wave
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    uint32_t lane = __lane_id();
+    return lane ? ((~0ull) >> (64 - lane)) : 0ull;
+}
+
+}  // namespace gpma_dev
+
+// ---------------------------------------------------------------------------
+// launchers (host side), implemented in prims.hip / pma.hip / analytics.hip
+
+namespace gpma_host {
+
+struct Device {
+    int max_lds = 65536;   // bytes of LDS one workgroup may allocate
+    int cus = 256;
+};
+
+// ---- primitives (prims.hip)
+// exclusive scan of n uint32 in place-safe (in may equal out); the total is
+// written to *total_dev when non-null.  tmp needs scan_tmp_words(n) words.
+size_t scan_tmp_words(uint64_t n);
+void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev,
+              uint32_t *tmp, hipStream_t s);
+
+// keys-only LSD radix sort of n uint64 keys on the bits of the compressed
+// key (src << dbits) | dst', where dst' = dst, or V for a guard.  Result in
+// *out (one of buf_a/buf_b); `in` is not modified.  tmp: radix_tmp_words(n).
+size_t radix_tmp_words(uint64_t n);
+const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
+                                uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
+                                hipStream_t s);
+
+// unique of a sorted array: out receives the distinct keys, *count_dev their
+// number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).
+void unique_sorted(const uint64_t *in, uint64_t n, uint64_t *out, uint32_t *count_dev,
+                   uint32_t *flags, uint32_t *tmp, hipStream_t s);
+// same, reading n from a device counter (upper bound n_max on the host)
+void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max, uint64_t *out,
+                       uint32_t *count_dev, uint32_t *flags, uint32_t *tmp, hipStream_t s);
+
+// keep (key, leaf) pairs whose status is pending; n from *n_dev (<= n_max);
+// the number kept goes to *count_dev and the kept pairs get status pending.
+void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *status,
+                     const uint32_t *n_dev, uint64_t n_max, uint64_t *keys_out,
+                     uint32_t *leaf_out, uint8_t *status_out, uint32_t *count_dev,
+                     uint32_t *flags, uint32_t *tmp, hipStream_t s);
+
+// stored edges (not empty, not guard) of slots[0..cap) in order
+void compact_edges(const uint64_t *slots, uint64_t cap, uint64_t *out, uint32_t *count_dev,
+                   uint32_t *flags, uint32_t *tmp, hipStream_t s);
+
+// ---- PMA kernels (pma.hip)
+void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, gpma_dev::Ctl *ctl,
+                     hipStream_t s);
+void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s);
+void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max,
+                   const uint64_t *slots, uint64_t L, uint32_t lf, const gpma_dev::Ctl *ctl,
+                   uint32_t *leaf, uint8_t *status, hipStream_t s);
+void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
+                       const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
+                       uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t min0,
+                       uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s);
+// workgroup tier at height h >= 1; needs seg_merge_lds_bytes(lf, h) <= max LDS
+size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h);
+void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
+                      uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
+                      uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t minh,
+                      uint64_t maxh, gpma_dev::Ctl *ctl, hipStream_t s);
+// device tier pieces (one segment at a time; also the root rebuild and bulk load)
+void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, uint64_t first_leaf,
+                           uint64_t P, uint32_t lf, const uint32_t *leaf_off, uint64_t *out,
+                           hipStream_t s);
+void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_t *U, uint64_t k,
+                         uint64_t *out, hipStream_t s);
+void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt,
+                     uint32_t *row_ptr, uint64_t first_leaf, uint64_t P, uint32_t lf,
+                     hipStream_t s);
+void launch_leaf_counts_u32(const uint16_t *cnt, uint64_t first_leaf, uint64_t P, uint32_t *out,
+                            hipStream_t s);
+void launch_mark_done(bool del, const uint64_t *keys, uint8_t *status, uint64_t first,
+                      uint64_t count, uint32_t *deg, gpma_dev::Ctl *ctl, uint64_t cap_seg,
+                      hipStream_t s);
+void launch_degrees_from_sorted(const uint64_t *sorted, uint64_t n, uint32_t V, uint32_t *gpos,
+                                uint32_t *deg, hipStream_t s);
+
+// ---- analytics (analytics.hip)
+void launch_pr_prep(const float *x, const uint32_t *deg, uint32_t V, bool uniform,
+                    double *contrib, double *y, double *dangling, hipStream_t s);
+void launch_pr_spmv(const uint64_t *slots, uint64_t cap, const double *contrib, double *y,
+                    hipStream_t s);
+void launch_pr_combine(const double *y, const double *dangling, uint32_t V, double damping,
+                       float *out, hipStream_t s);
+void launch_bfs_init(int32_t *dist, uint32_t V, uint32_t source, uint32_t *queue,
+                     uint32_t *qcount, hipStream_t s);
+void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uint32_t *front,
+                       uint32_t nfront, int32_t level, int32_t *dist, uint32_t *next,
+                       uint32_t *next_count, hipStream_t s);
+void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s);
+void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t *changed,
+                    hipStream_t s);
+void launch_cc_compress(uint32_t *label, uint32_t V, hipStream_t s);
+
+}  // namespace gpma_host

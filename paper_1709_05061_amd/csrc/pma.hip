@@ -1,0 +1,549 @@
+// PMA kernels of the GPMA+ update (Section 5.2, Algorithm "GPMA+ Segment-
+// Oriented Insertion", and its dual for deletions) for gfx950.
+//
+// Layout (HBM): slots[cap] uint64 sorted keys with gaps (kEmpty); leaf j is
+// slots[j*lf, (j+1)*lf) and always holds a packed prefix of cnt[j] >= 1
+// entries followed by gaps; row_ptr[V+1] uint32 CSR offsets (row u ends with
+// its guard); deg[V] uint32 out-degrees.
+//
+// Tiers of TryInsert+ (Section 5.2 and Appendix A, warp / block / device):
+//   level 0   k_leaf_merge: a group of lf/SPL lanes of one wave per leaf, the
+//             leaf staged through a per-group LDS slice (no workgroup barrier);
+//   level h   k_seg_merge: one workgroup per segment, the segment staged in
+//             LDS (up to what one workgroup may allocate);
+//   above     host-driven device tier: gather -> merge -> dispatch kernels.
+#include "common.h"
+
+using namespace gpma_dev;
+
+namespace {
+
+inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// batch validation: every key needs src < V and dst < V
+
+__global__ void k_validate(const uint64_t *__restrict__ keys, uint64_t n, uint32_t V,
+                           Ctl *__restrict__ ctl) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (i < n) {
+        uint64_t k = keys[i];
+        bad = key_src(k) >= V || key_dst(k) >= V;
+    }
+    if (__ballot(bad) && __lane_id() == 0) atomicOr(&ctl->err, 1u);
+}
+
+__global__ void k_append_guards(uint64_t *__restrict__ dst, uint32_t V) {
+    uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < V) dst[u] = (u << 32) | kGuardDst;
+}
+
+// ---------------------------------------------------------------------------
+// BinarySearchLeafSegments: the leaf of key k is the leaf holding the
+// greatest stored key <= k, leaf 0 when there is none.  No leaf is ever empty,
+// so the first slot of every leaf is its smallest key and those pivots
+// ascend strictly: a plain binary search over slots[j*lf].
+
+__global__ void k_locate(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev,
+                         uint64_t n_max, const uint64_t *__restrict__ slots, uint64_t L,
+                         uint32_t lf_log2, const Ctl *__restrict__ ctl, uint32_t *__restrict__ leaf,
+                         uint8_t *__restrict__ status) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_max || i >= *n_dev || ctl->err) return;
+    uint64_t k = keys[i];
+    uint64_t lo = 0, hi = L;   // count of leaves whose pivot is <= k
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (slots[mid << lf_log2] <= k) lo = mid + 1; else hi = mid;
+    }
+    leaf[i] = (uint32_t)(lo ? lo - 1 : 0);
+    status[i] = kPending;
+}
+
+// ---------------------------------------------------------------------------
+// sub-wave group helpers (G lanes, G a power of two <= 64, group-aligned)
+
+template <int G>
+__device__ __forceinline__ uint32_t group_sum(uint32_t v) {
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, G);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t group_excl_scan(uint32_t v, uint32_t gl) {
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, G);
+        if (gl >= (uint32_t)d) x += y;
+    }
+    return x - v;
+}
+
+// end of the run of equal leaf>>h values starting at i (exclusive), in [i+1, n]
+__device__ __forceinline__ uint32_t run_end(const uint32_t *__restrict__ leaf, uint32_t i,
+                                            uint32_t n, uint32_t s, uint32_t h) {
+    uint32_t lo = i + 1, hi = n;
+    // small runs are the common case: probe a few neighbours first
+    if (lo < hi && (leaf[lo] >> h) != s) return lo;
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if ((leaf[mid] >> h) == s) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Level 0: TryInsert+ / TryDelete+ on leaf segments, fused with the existence
+// probe that turns present inserts and absent deletes into no-ops (the probe
+// reads the same leaf, and at level 0 no other group writes that leaf).
+// Group = G lanes, each holding SPL consecutive slots of the leaf (lf = G*SPL).
+
+template <int G, int SPL, bool DEL>
+__global__ void __launch_bounds__(256)
+k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+             uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+             uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+             uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t min0,
+             uint32_t max0, Ctl *__restrict__ ctl) {
+    constexpr int LF = G * SPL;
+    constexpr int GPB = 256 / G;   // groups per block
+    __shared__ uint64_t s_leaf[GPB][LF];
+    __shared__ uint64_t s_upd[GPB][LF];
+    __shared__ uint64_t s_out[GPB][LF];
+
+    const uint32_t gib = threadIdx.x / G;          // group in block
+    const uint32_t gl = threadIdx.x & (G - 1);     // lane in group
+    const uint64_t gi = (uint64_t)blockIdx.x * GPB + gib;
+    if (gi >= n_max) return;
+    const uint32_t n = *n_dev;
+    if (gi >= n || ctl->err) return;
+    const uint32_t i = (uint32_t)gi;
+    const uint32_t lf_i = leaf[i];
+    if (i > 0 && leaf[i - 1] == lf_i) return;      // not the head of its run
+    const uint32_t e = run_end(leaf, i, n, lf_i, 0);
+    const uint32_t k = e - i;
+
+    uint64_t *lb = s_leaf[gib];
+    uint64_t *ub = s_upd[gib];
+    uint64_t *ob = s_out[gib];
+    const uint64_t base = (uint64_t)lf_i * LF;
+    uint64_t mine[SPL];
+#pragma unroll
+    for (int q = 0; q < SPL; q++) {
+        mine[q] = slots[base + gl * SPL + q];
+        lb[gl * SPL + q] = mine[q];
+    }
+    const uint32_t c = cnt[lf_i];
+    wave_lds_sync();
+
+    // classify the run: applicable updates are compacted (in key order) into ub
+    uint32_t kapp = 0;
+    for (uint32_t r0 = 0; r0 < k; r0 += G) {
+        const uint32_t t = r0 + gl;
+        const bool valid = t < k;
+        const uint64_t key = valid ? keys[i + t] : 0;
+        const bool present = valid && contains_u64(lb, c, key);
+        const bool app = valid && (DEL ? present : !present);
+        const uint32_t pos = kapp + group_excl_scan<G>(app ? 1u : 0u, gl);
+        if (app && pos < LF) ub[pos] = key;
+        if (valid) status[i + t] = app ? kPending : kNoop;
+        kapp += group_sum<G>(app ? 1u : 0u);
+    }
+    if (gl == 0 && k > kapp) atomicAdd((unsigned long long *)&ctl->noops, (unsigned long long)(k - kapp));
+    if (kapp == 0) return;
+    const bool pass = DEL ? (c >= kapp + min0) : (c + kapp <= max0);
+    if (!pass) return;
+    wave_lds_sync();
+
+    // Merge + even re-dispatch: a leaf is one segment of one leaf, so the
+    // merged run is simply packed at the front
+    const uint32_t N = DEL ? c - kapp : c + kapp;
+#pragma unroll
+    for (int q = 0; q < SPL; q++) {
+        const uint32_t x = gl * SPL + q;
+        if (x < c) {
+            const uint64_t a = mine[q];
+            const uint32_t below = lower_bound_u64(ub, kapp, a);
+            if (DEL) {
+                if (!(below < kapp && ub[below] == a)) ob[x - below] = a;
+            } else {
+                ob[x + below] = a;
+            }
+        }
+    }
+    if (!DEL) {
+        for (uint32_t t = gl; t < kapp; t += G) {
+            const uint64_t uk = ub[t];
+            ob[t + lower_bound_u64(lb, c, uk)] = uk;
+        }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < SPL; q++) {
+        const uint32_t p = gl * SPL + q;
+        const uint64_t v = p < N ? ob[p] : kEmpty;
+        slots[base + p] = v;
+        if (p < N && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(base + p + 1);
+    }
+    if (gl == 0) {
+        cnt[lf_i] = (uint16_t)N;
+        atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)kapp);
+        atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(DEL ? -(int64_t)kapp : (int64_t)kapp));
+        atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)LF);
+        atomicAdd(&ctl->segs, 1u);
+    }
+    for (uint32_t t = gl; t < k; t += G) {
+        if (status[i + t] == kPending) {
+            status[i + t] = kDone;
+            atomicAdd(&deg[key_src(keys[i + t])], DEL ? 0xFFFFFFFFu : 1u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level h >= 1, workgroup tier: one workgroup per segment of P = 2^h leaves.
+// CountSegment sums the leaf counts; a passing segment is staged (compacted)
+// in LDS, merged with its updates by rank, and written back evenly.
+
+constexpr int kSegThreads = 256;
+
+__device__ __forceinline__ void block_scan_counts(uint32_t *v, uint32_t P, uint32_t *total,
+                                                  uint32_t *lds_w) {
+    // exclusive scan of v[0..P) in place; P <= a few thousand
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    uint32_t carry = 0;
+    for (uint32_t b0 = 0; b0 < P; b0 += blockDim.x) {
+        uint32_t j = b0 + threadIdx.x;
+        uint32_t x0 = j < P ? v[j] : 0;
+        uint32_t x = x0;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            uint32_t y = __shfl_up(x, d, kWave);
+            if (lane >= d) x += y;
+        }
+        if (lane == kWave - 1) lds_w[wid] = x;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int w = 0; w < nw; w++) {
+                uint32_t t = lds_w[w];
+                lds_w[w] = run;
+                run += t;
+            }
+            lds_w[nw] = run;
+        }
+        __syncthreads();
+        if (j < P) v[j] = carry + lds_w[wid] + x - x0;
+        carry += lds_w[nw];
+        __syncthreads();
+    }
+    *total = carry;
+}
+
+template <bool DEL>
+__global__ void __launch_bounds__(kSegThreads)
+k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+            uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
+            uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+            uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t lf_log2,
+            uint64_t minh, uint64_t maxh, Ctl *__restrict__ ctl) {
+    extern __shared__ uint64_t dyn[];
+    __shared__ uint32_t s_misc[kSegThreads / kWave + 4];
+    const uint32_t n = *n_dev;
+    const uint32_t i = blockIdx.x;
+    if (i >= n || ctl->err) return;
+    const uint32_t s = leaf[i] >> h;
+    if (i > 0 && (leaf[i - 1] >> h) == s) return;
+    const uint32_t e = run_end(leaf, i, n, s, h);
+    const uint32_t k = e - i;
+    const uint32_t lf = 1u << lf_log2;
+    const uint32_t P = 1u << h;
+    const uint64_t cap_h = (uint64_t)P << lf_log2;
+    const uint64_t first_leaf = (uint64_t)s << h;
+    const uint64_t base = first_leaf << lf_log2;
+
+    // LDS: E[cap_h] entries, U[cap_h] updates, off[P] leaf offsets
+    uint64_t *E = dyn;
+    uint64_t *U = dyn + cap_h;
+    uint32_t *off = (uint32_t *)(dyn + 2 * cap_h);
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) off[j] = cnt[first_leaf + j];
+    __syncthreads();
+    uint32_t ns;
+    block_scan_counts(off, P, &ns, s_misc);
+    const bool pass = DEL ? ((uint64_t)ns >= (uint64_t)k + minh) : ((uint64_t)ns + k <= maxh);
+    if (!pass) return;
+
+    for (uint64_t p = threadIdx.x; p < cap_h; p += blockDim.x) {
+        uint32_t j = (uint32_t)(p >> lf_log2), o = (uint32_t)(p & (lf - 1));
+        uint32_t cj = (j + 1 < P ? off[j + 1] : ns) - off[j];
+        if (o < cj) E[off[j] + o] = slots[base + p];
+    }
+    for (uint32_t t = threadIdx.x; t < k; t += blockDim.x) U[t] = keys[i + t];
+    __syncthreads();
+
+    const uint64_t N = DEL ? (uint64_t)ns - k : (uint64_t)ns + k;
+    auto put = [&](uint64_t r, uint64_t v) {
+        uint64_t j = rank_leaf(r, N, P);
+        uint64_t pos = base + (j << lf_log2) + (r - leaf_start(j, N, P));
+        slots[pos] = v;
+        if (is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(pos + 1);
+    };
+    for (uint32_t x = threadIdx.x; x < ns; x += blockDim.x) {
+        const uint64_t a = E[x];
+        const uint32_t below = lower_bound_u64(U, k, a);
+        if (DEL) {
+            if (!(below < k && U[below] == a)) put(x - below, a);
+        } else {
+            put((uint64_t)x + below, a);
+        }
+    }
+    if (!DEL) {
+        for (uint32_t t = threadIdx.x; t < k; t += blockDim.x) {
+            const uint64_t uk = U[t];
+            put((uint64_t)t + lower_bound_u64(E, ns, uk), uk);
+        }
+    }
+    for (uint64_t p = threadIdx.x; p < cap_h; p += blockDim.x) {
+        uint64_t j = p >> lf_log2, o = p & (lf - 1);
+        uint64_t cj = leaf_start(j + 1, N, P) - leaf_start(j, N, P);
+        if (o >= cj) slots[base + p] = kEmpty;
+        if (o == 0) cnt[first_leaf + j] = (uint16_t)cj;
+    }
+    for (uint32_t t = threadIdx.x; t < k; t += blockDim.x) {
+        status[i + t] = kDone;
+        atomicAdd(&deg[key_src(U[t])], DEL ? 0xFFFFFFFFu : 1u);
+    }
+    if (threadIdx.x == 0) {
+        atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)k);
+        atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(DEL ? -(int64_t)k : (int64_t)k));
+        atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)cap_h);
+        atomicAdd(&ctl->segs, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// device tier (large segments, root rebuild, bulk load)
+
+__global__ void k_leaf_counts_u32(const uint16_t *__restrict__ cnt, uint64_t first_leaf, uint64_t P,
+                                  uint32_t *__restrict__ out) {
+    uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < P) out[j] = cnt[first_leaf + j];
+}
+
+// compacted entries of the segment, in order: leaf j's prefix goes to
+// out[leaf_off[j] ..]
+__global__ void k_gather_segment(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
+                                 uint64_t first_leaf, uint64_t P, uint32_t lf_log2,
+                                 const uint32_t *__restrict__ leaf_off, uint64_t *__restrict__ out) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (P << lf_log2)) return;
+    uint64_t j = p >> lf_log2, o = p & ((1u << lf_log2) - 1);
+    if (o < cnt[first_leaf + j]) out[leaf_off[j] + o] = slots[(first_leaf << lf_log2) + p];
+}
+
+// Merge(s, U_s) by rank: every element finds its output rank with one binary
+// search in the other list (both sorted, disjoint for insert; U a subset of
+// A for delete).
+__global__ void k_merge_rank_a(bool del, const uint64_t *__restrict__ A, uint64_t na,
+                               const uint64_t *__restrict__ U, uint64_t k, uint64_t *__restrict__ out) {
+    uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= na) return;
+    uint64_t a = A[x];
+    uint64_t lo = 0, hi = k;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (U[mid] < a) lo = mid + 1; else hi = mid;
+    }
+    if (del) {
+        if (!(lo < k && U[lo] == a)) out[x - lo] = a;
+    } else {
+        out[x + lo] = a;
+    }
+}
+
+__global__ void k_merge_rank_u(const uint64_t *__restrict__ A, uint64_t na,
+                               const uint64_t *__restrict__ U, uint64_t k, uint64_t *__restrict__ out) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= k) return;
+    uint64_t u = U[t];
+    uint64_t lo = 0, hi = na;
+    while (lo < hi) {
+        uint64_t mid = (lo + hi) >> 1;
+        if (A[mid] < u) lo = mid + 1; else hi = mid;
+    }
+    out[t + lo] = u;
+}
+
+// even re-dispatch of M[0..N) over leaves first_leaf .. first_leaf+P-1
+__global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t *__restrict__ slots,
+                           uint16_t *__restrict__ cnt, uint32_t *__restrict__ row_ptr,
+                           uint64_t first_leaf, uint64_t P, uint32_t lf_log2) {
+    uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (P << lf_log2)) return;
+    uint64_t j = p >> lf_log2, o = p & ((1u << lf_log2) - 1);
+    uint64_t st = leaf_start(j, N, P);
+    uint64_t cj = leaf_start(j + 1, N, P) - st;
+    uint64_t pos = (first_leaf << lf_log2) + p;
+    uint64_t v = o < cj ? M[st + o] : kEmpty;
+    slots[pos] = v;
+    if (o == 0) cnt[first_leaf + j] = (uint16_t)cj;
+    if (o < cj && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(pos + 1);
+}
+
+__global__ void k_mark_done(bool del, const uint64_t *__restrict__ keys, uint8_t *__restrict__ status,
+                            uint64_t first, uint64_t count, uint32_t *__restrict__ deg,
+                            Ctl *__restrict__ ctl, uint64_t cap_seg) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) {
+        status[first + t] = kDone;
+        atomicAdd(&deg[key_src(keys[first + t])], del ? 0xFFFFFFFFu : 1u);
+    }
+    if (t == 0) {
+        atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)count);
+        atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(del ? -(int64_t)count : (int64_t)count));
+        atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)cap_seg);
+        atomicAdd(&ctl->segs, 1u);
+    }
+}
+
+// degrees at bulk load: guard positions in the sorted unique array
+__global__ void k_guard_pos(const uint64_t *__restrict__ a, uint64_t n, uint32_t *__restrict__ gpos) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && is_guard(a[i])) gpos[key_src(a[i])] = (uint32_t)i;
+}
+
+__global__ void k_deg_from_gpos(const uint32_t *__restrict__ gpos, uint32_t V, uint32_t *__restrict__ deg) {
+    uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= V) return;
+    int64_t prev = u ? (int64_t)gpos[u - 1] : -1;
+    deg[u] = (uint32_t)((int64_t)gpos[u] - prev - 1);
+}
+
+uint32_t log2_u32(uint32_t x) {
+    uint32_t r = 0;
+    while (x > 1) { x >>= 1; r++; }
+    return r;
+}
+
+}  // namespace
+
+namespace gpma_host {
+
+void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, Ctl *ctl, hipStream_t s) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_validate, dim3((uint32_t)div_up(n, 256)), dim3(256), 0, s, keys, n, V, ctl);
+}
+
+void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s) {
+    hipLaunchKernelGGL(k_append_guards, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, dst, V);
+}
+
+void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
+                   uint64_t L, uint32_t lf, const Ctl *ctl, uint32_t *leaf, uint8_t *status,
+                   hipStream_t s) {
+    if (!n_max) return;
+    hipLaunchKernelGGL(k_locate, dim3((uint32_t)div_up(n_max, 256)), dim3(256), 0, s, keys, n_dev,
+                       n_max, slots, L, log2_u32(lf), ctl, leaf, status);
+}
+
+template <int G, int SPL>
+static void leaf_merge_t(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
+                         const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
+                         uint32_t *row_ptr, uint32_t *deg, uint32_t min0, uint32_t max0, Ctl *ctl,
+                         hipStream_t s) {
+    constexpr int GPB = 256 / G;
+    dim3 grid((uint32_t)div_up(n_max, GPB));
+    if (del)
+        hipLaunchKernelGGL((k_leaf_merge<G, SPL, true>), grid, dim3(256), 0, s, keys, leaf, status,
+                           n_dev, n_max, slots, cnt, row_ptr, deg, min0, max0, ctl);
+    else
+        hipLaunchKernelGGL((k_leaf_merge<G, SPL, false>), grid, dim3(256), 0, s, keys, leaf, status,
+                           n_dev, n_max, slots, cnt, row_ptr, deg, min0, max0, ctl);
+}
+
+void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
+                       const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
+                       uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t min0, uint64_t max0,
+                       Ctl *ctl, hipStream_t s) {
+    if (!n_max) return;
+    uint32_t mn = (uint32_t)min0, mx = (uint32_t)max0;
+    switch (lf) {
+        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+    }
+}
+
+size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h) {
+    uint64_t cap_h = (uint64_t)lf << h;
+    return 2 * cap_h * sizeof(uint64_t) + ((uint64_t)1 << h) * sizeof(uint32_t);
+}
+
+void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
+                      uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
+                      uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t minh,
+                      uint64_t maxh, Ctl *ctl, hipStream_t s) {
+    if (!n_max) return;
+    size_t lds = seg_merge_lds_bytes(lf, h);
+    if (del)
+        hipLaunchKernelGGL(k_seg_merge<true>, dim3((uint32_t)n_max), dim3(kSegThreads), lds, s, h,
+                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,
+                           maxh, ctl);
+    else
+        hipLaunchKernelGGL(k_seg_merge<false>, dim3((uint32_t)n_max), dim3(kSegThreads), lds, s, h,
+                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,
+                           maxh, ctl);
+}
+
+void launch_leaf_counts_u32(const uint16_t *cnt, uint64_t first_leaf, uint64_t P, uint32_t *out,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_leaf_counts_u32, dim3((uint32_t)div_up(P, 256)), dim3(256), 0, s, cnt,
+                       first_leaf, P, out);
+}
+
+void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, uint64_t first_leaf,
+                           uint64_t P, uint32_t lf, const uint32_t *leaf_off, uint64_t *out,
+                           hipStream_t s) {
+    uint64_t total = P * lf;
+    hipLaunchKernelGGL(k_gather_segment, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, slots,
+                       cnt, first_leaf, P, log2_u32(lf), leaf_off, out);
+}
+
+void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_t *U, uint64_t k,
+                         uint64_t *out, hipStream_t s) {
+    if (na)
+        hipLaunchKernelGGL(k_merge_rank_a, dim3((uint32_t)div_up(na, 256)), dim3(256), 0, s, del, A,
+                           na, U, k, out);
+    if (!del && k)
+        hipLaunchKernelGGL(k_merge_rank_u, dim3((uint32_t)div_up(k, 256)), dim3(256), 0, s, A, na, U,
+                           k, out);
+}
+
+void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *row_ptr,
+                     uint64_t first_leaf, uint64_t P, uint32_t lf, hipStream_t s) {
+    uint64_t total = P * lf;
+    hipLaunchKernelGGL(k_dispatch, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, M, N, slots,
+                       cnt, row_ptr, first_leaf, P, log2_u32(lf));
+}
+
+void launch_mark_done(bool del, const uint64_t *keys, uint8_t *status, uint64_t first, uint64_t count,
+                      uint32_t *deg, Ctl *ctl, uint64_t cap_seg, hipStream_t s) {
+    hipLaunchKernelGGL(k_mark_done, dim3((uint32_t)div_up(count ? count : 1, 256)), dim3(256), 0, s,
+                       del, keys, status, first, count, deg, ctl, cap_seg);
+}
+
+void launch_degrees_from_sorted(const uint64_t *sorted, uint64_t n, uint32_t V, uint32_t *gpos,
+                                uint32_t *deg, hipStream_t s) {
+    hipLaunchKernelGGL(k_guard_pos, dim3((uint32_t)div_up(n, 256)), dim3(256), 0, s, sorted, n, gpos);
+    hipLaunchKernelGGL(k_deg_from_gpos, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, gpos, V, deg);
+}
+
+}  // namespace gpma_host

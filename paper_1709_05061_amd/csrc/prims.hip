@@ -1,0 +1,356 @@
+// Data-parallel primitives for the GPMA+ update, written for gfx950 wave64:
+// exclusive scan, keys-only LSD radix sort, unique and stream compaction.
+// The paper builds its update from such primitives (Section 5.2: sort,
+// run-length encoding, exclusive scan); these are our own.
+#include "common.h"
+
+using namespace gpma_dev;
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 2048
+
+constexpr int kSortThreads = 256;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kSortChunks = 16;                          // 64-key chunks per wave
+constexpr int kSortTile = kSortThreads * kSortChunks;    // 4096
+constexpr int kSortWaveSpan = kWave * kSortChunks;       // 1024
+
+inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// exclusive scan of one value per thread over the workgroup; *total gets the
+// workgroup sum.  lds: (blockDim/64 + 1) words.
+__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uint32_t *lds) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) lds[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nw; w++) {
+            uint32_t t = lds[w];
+            lds[w] = run;
+            run += t;
+        }
+        lds[nw] = run;
+    }
+    __syncthreads();
+    uint32_t excl = x - v + lds[wid];
+    *total = lds[nw];
+    __syncthreads();
+    return excl;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_reduce(const uint32_t *__restrict__ in, uint64_t n, uint32_t *__restrict__ tile_sums) {
+    __shared__ uint32_t lds[kScanThreads / kWave + 1];
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + (uint64_t)i * kScanThreads + threadIdx.x;
+        if (idx < n) s += in[idx];
+    }
+    uint32_t tot;
+    block_exclusive_scan(s, &tot, lds);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+// one workgroup: exclusive scan of the tile sums in place, total to *total
+__global__ void __launch_bounds__(1024)
+k_scan_top(uint32_t *__restrict__ sums, uint64_t ntiles, uint32_t *__restrict__ total) {
+    __shared__ uint32_t lds[1024 / kWave + 1];
+    uint32_t carry = 0;
+    for (uint64_t base = 0; base < ntiles; base += blockDim.x) {
+        uint64_t idx = base + threadIdx.x;
+        uint32_t v = idx < ntiles ? sums[idx] : 0;
+        uint32_t tot;
+        uint32_t e = block_exclusive_scan(v, &tot, lds);
+        if (idx < ntiles) sums[idx] = carry + e;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_apply(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, uint64_t n,
+             const uint32_t *__restrict__ tile_offs) {
+    __shared__ uint32_t lds[kScanThreads / kWave + 1];
+    // each thread takes kScanItems consecutive items so the scan order is the
+    // array order
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0;
+        s += v[i];
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot, lds) + tile_offs[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; i++) {
+        uint64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// radix sort
+
+struct DigitMap {
+    uint32_t shift, mask, dbits, V;
+    __device__ __forceinline__ uint32_t operator()(uint64_t k) const {
+        uint64_t src = k >> 32;
+        uint32_t dst = (uint32_t)k;
+        uint64_t d = (dst == kGuardDst) ? (uint64_t)V : (uint64_t)dst;
+        uint64_t ck = (src << dbits) | d;
+        return (uint32_t)(ck >> shift) & mask;
+    }
+};
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, uint32_t ntiles,
+                uint32_t *__restrict__ counts) {
+    __shared__ uint32_t hist[256];
+    for (int i = threadIdx.x; i < 256; i += kSortThreads) hist[i] = 0;
+    __syncthreads();
+    uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+#pragma unroll 4
+    for (int i = 0; i < kSortChunks; i++) {
+        uint64_t idx = base + (uint64_t)i * kSortThreads + threadIdx.x;
+        if (idx < n) atomicAdd(&hist[dm(keys[idx])], 1u);
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads)
+        counts[(uint64_t)d * ntiles + blockIdx.x] = hist[d];
+}
+
+// Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
+// tile and walks them in 64-key chunks; lanes holding the same digit find
+// each other with one ballot per digit bit, so the rank of a key among equal
+// digits is (keys of that digit in earlier chunks) + (lower lanes in this
+// chunk).  Per-wave digit counts are then prefixed across waves.
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_downsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, uint32_t bits,
+                  uint32_t ntiles, const uint32_t *__restrict__ offs,
+                  uint64_t *__restrict__ out) {
+    __shared__ uint32_t wcnt[kSortWaves][256];
+    __shared__ uint32_t goff[256];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int w = threadIdx.x / kWave;
+    for (int i = threadIdx.x; i < kSortWaves * 256; i += kSortThreads) (&wcnt[0][0])[i] = 0;
+    __syncthreads();
+
+    const uint64_t base = (uint64_t)blockIdx.x * kSortTile + (uint64_t)w * kSortWaveSpan;
+    const uint64_t ltmask = lanemask_lt();
+    uint64_t k[kSortChunks];
+    uint32_t rk[kSortChunks];
+#pragma unroll
+    for (int c = 0; c < kSortChunks; c++) {
+        uint64_t idx = base + (uint64_t)c * kWave + lane;
+        bool valid = idx < n;
+        k[c] = valid ? keys[idx] : 0;
+        uint32_t d = dm(k[c]);
+        uint64_t m = __ballot(valid);
+        for (uint32_t b = 0; b < bits; b++) {
+            uint32_t bit = (d >> b) & 1u;
+            uint64_t bb = __ballot(bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t before = wcnt[w][d];
+        rk[c] = before + (uint32_t)__popcll(m & ltmask);
+        wave_lds_sync();
+        if (valid && (uint32_t)(__ffsll((unsigned long long)m) - 1) == (uint32_t)lane)
+            wcnt[w][d] = before + (uint32_t)__popcll(m);
+        wave_lds_sync();
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) {
+        uint32_t run = 0;
+#pragma unroll
+        for (int ww = 0; ww < kSortWaves; ww++) {
+            uint32_t t = wcnt[ww][d];
+            wcnt[ww][d] = run;
+            run += t;
+        }
+        goff[d] = offs[(uint64_t)d * ntiles + blockIdx.x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kSortChunks; c++) {
+        uint64_t idx = base + (uint64_t)c * kWave + lane;
+        if (idx < n) {
+            uint32_t d = dm(k[c]);
+            out[goff[d] + wcnt[w][d] + rk[c]] = k[c];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// flags for compaction
+
+__global__ void k_flag_unique(const uint64_t *__restrict__ a, uint64_t n,
+                              const uint32_t *__restrict__ n_dev, uint32_t *__restrict__ flags) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t lim = n_dev ? *n_dev : n;
+    flags[i] = (i < lim && (i == 0 || a[i] != a[i - 1])) ? 1u : 0u;
+}
+
+__global__ void k_scatter_unique(const uint64_t *__restrict__ a, uint64_t n,
+                                 const uint32_t *__restrict__ n_dev,
+                                 const uint32_t *__restrict__ pos, uint64_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t lim = n_dev ? *n_dev : n;
+    if (i < lim && (i == 0 || a[i] != a[i - 1])) out[pos[i]] = a[i];
+}
+
+__global__ void k_flag_pending(const uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
+                               uint64_t n_max, uint32_t *__restrict__ flags) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_max) return;
+    flags[i] = (i < *n_dev && status[i] == kPending) ? 1u : 0u;
+}
+
+__global__ void k_scatter_pending(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+                                  const uint8_t *__restrict__ status,
+                                  const uint32_t *__restrict__ n_dev, uint64_t n_max,
+                                  const uint32_t *__restrict__ pos, uint64_t *__restrict__ keys_out,
+                                  uint32_t *__restrict__ leaf_out, uint8_t *__restrict__ status_out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_max || i >= *n_dev || status[i] != kPending) return;
+    uint32_t p = pos[i];
+    keys_out[p] = keys[i];
+    leaf_out[p] = leaf[i];
+    status_out[p] = kPending;
+}
+
+__global__ void k_flag_edges(const uint64_t *__restrict__ slots, uint64_t cap,
+                             uint32_t *__restrict__ flags) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    uint64_t k = slots[i];
+    flags[i] = (k != kEmpty && !is_guard(k)) ? 1u : 0u;
+}
+
+__global__ void k_scatter_edges(const uint64_t *__restrict__ slots, uint64_t cap,
+                                const uint32_t *__restrict__ pos, uint64_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    uint64_t k = slots[i];
+    if (k != kEmpty && !is_guard(k)) out[pos[i]] = k;
+}
+
+}  // namespace
+
+namespace gpma_host {
+
+size_t scan_tmp_words(uint64_t n) { return div_up(n ? n : 1, kScanTile) + 1; }
+
+void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev, uint32_t *tmp,
+              hipStream_t s) {
+    if (n == 0) {
+        if (total_dev) hipMemsetAsync(total_dev, 0, sizeof(uint32_t), s);
+        return;
+    }
+    uint64_t ntiles = div_up(n, kScanTile);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, ntiles, total_dev);
+    hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)ntiles), dim3(kScanThreads), 0, s, in, out, n,
+                       tmp);
+}
+
+size_t radix_tmp_words(uint64_t n) {
+    uint64_t ntiles = div_up(n ? n : 1, kSortTile);
+    uint64_t m = 256 * ntiles;
+    return m + scan_tmp_words(m);
+}
+
+static uint32_t bit_width(uint64_t x) {
+    uint32_t b = 0;
+    while (x) { b++; x >>= 1; }
+    return b;
+}
+
+const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
+                                uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
+                                hipStream_t s) {
+    (void)bit_width;
+    uint32_t total = sbits + dbits;
+    if (total == 0) total = 1;
+    uint32_t passes = (total + 7) / 8;
+    uint32_t bits = (total + passes - 1) / passes;
+    uint64_t ntiles = div_up(n ? n : 1, kSortTile);
+    uint64_t m = 256 * ntiles;
+    uint32_t *counts = tmp;
+    uint32_t *stmp = tmp + m;
+    const uint64_t *src = in;
+    uint64_t *dst = buf_a;
+    for (uint32_t p = 0; p < passes; p++) {
+        DigitMap dm{p * bits, (1u << bits) - 1u, dbits, V};
+        uint64_t mm = (uint64_t)(dm.mask + 1) * ntiles;
+        hipLaunchKernelGGL(k_radix_upsweep, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, src, n,
+                           dm, (uint32_t)ntiles, counts);
+        scan_u32(counts, counts, mm, nullptr, stmp, s);
+        hipLaunchKernelGGL(k_radix_downsweep, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, src,
+                           n, dm, bits, (uint32_t)ntiles, counts, dst);
+        src = dst;
+        dst = (dst == buf_a) ? buf_b : buf_a;
+    }
+    return src;
+}
+
+void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max, uint64_t *out,
+                       uint32_t *count_dev, uint32_t *flags, uint32_t *tmp, hipStream_t s) {
+    if (n_max == 0) {
+        hipMemsetAsync(count_dev, 0, sizeof(uint32_t), s);
+        return;
+    }
+    uint32_t g = (uint32_t)div_up(n_max, 256);
+    hipLaunchKernelGGL(k_flag_unique, dim3(g), dim3(256), 0, s, in, n_max, n_dev, flags);
+    scan_u32(flags, flags, n_max, count_dev, tmp, s);
+    hipLaunchKernelGGL(k_scatter_unique, dim3(g), dim3(256), 0, s, in, n_max, n_dev, flags, out);
+}
+
+void unique_sorted(const uint64_t *in, uint64_t n, uint64_t *out, uint32_t *count_dev,
+                   uint32_t *flags, uint32_t *tmp, hipStream_t s) {
+    unique_sorted_dyn(in, nullptr, n, out, count_dev, flags, tmp, s);
+}
+
+void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *status,
+                     const uint32_t *n_dev, uint64_t n_max, uint64_t *keys_out, uint32_t *leaf_out,
+                     uint8_t *status_out, uint32_t *count_dev, uint32_t *flags, uint32_t *tmp,
+                     hipStream_t s) {
+    if (n_max == 0) {
+        hipMemsetAsync(count_dev, 0, sizeof(uint32_t), s);
+        return;
+    }
+    uint32_t g = (uint32_t)div_up(n_max, 256);
+    hipLaunchKernelGGL(k_flag_pending, dim3(g), dim3(256), 0, s, status, n_dev, n_max, flags);
+    scan_u32(flags, flags, n_max, count_dev, tmp, s);
+    hipLaunchKernelGGL(k_scatter_pending, dim3(g), dim3(256), 0, s, keys, leaf, status, n_dev, n_max,
+                       flags, keys_out, leaf_out, status_out);
+}
+
+void compact_edges(const uint64_t *slots, uint64_t cap, uint64_t *out, uint32_t *count_dev,
+                   uint32_t *flags, uint32_t *tmp, hipStream_t s) {
+    uint32_t g = (uint32_t)div_up(cap, 256);
+    hipLaunchKernelGGL(k_flag_edges, dim3(g), dim3(256), 0, s, slots, cap, flags);
+    scan_u32(flags, flags, cap, count_dev, tmp, s);
+    hipLaunchKernelGGL(k_scatter_edges, dim3(g), dim3(256), 0, s, slots, cap, flags, out);
+}
+
+}  // namespace gpma_host

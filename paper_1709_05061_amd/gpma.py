@@ -1,0 +1,319 @@
+"""ctypes binding of libgpma.so (the C ABI in include/gpma.h).
+
+Argument marshalling only: every step of the update and of the analytics
+runs in the HIP library.  Device buffers are torch tensors on the current
+HIP device; streams are torch streams.  There is no CPU fallback: importing
+works anywhere, but the first call raises if the library is not built or no
+GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgpma.so")
+
+GPMA_OK, GPMA_EINVAL, GPMA_ENOMEM, GPMA_EDEVICE = 0, -1, -2, -3
+EMPTY = 0xFFFFFFFFFFFFFFFF
+GUARD_DST = 0xFFFFFFFF
+
+# kernel ids for the profiling calls
+K_SPMV, K_LEAF_MERGE, K_SEG_MERGE, K_SORT, K_LOCATE, K_BFS, K_CC = range(7)
+KERNEL_NAMES = ["spmv", "leaf_merge", "seg_merge", "sort", "locate", "bfs_expand", "cc_hook"]
+
+
+class gpma_params(C.Structure):
+    _fields_ = [("leaf_size", C.c_uint32), ("tau_leaf_pm", C.c_uint32), ("tau_root_pm", C.c_uint32),
+                ("rho_leaf_pm", C.c_uint32), ("rho_root_pm", C.c_uint32), ("flags", C.c_uint32)]
+
+
+class gpma_stats(C.Structure):
+    _fields_ = [("requested", C.c_uint64), ("applied", C.c_uint64), ("noops", C.c_uint64),
+                ("top_level", C.c_int32), ("resized", C.c_uint32),
+                ("segments_merged", C.c_uint64 * 40), ("slots_rewritten", C.c_uint64)]
+
+
+class GpmaError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s failed: %s (%d)" % (what, strerror(code), code))
+        self.code = code
+
+
+_lib = None
+
+
+def load_library() -> C.CDLL:
+    """Load libgpma.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libgpma.so is not built (run __graft_entry__.build() or "
+                           "python paper_1709_05061_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, u32, u64, i32, f32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_float
+    pu64 = C.POINTER(u64)
+    sig = {
+        "gpma_default_params": (None, [C.POINTER(gpma_params)]),
+        "gpma_create": (C.c_int, [C.POINTER(vp), u32, vp, u64, C.POINTER(gpma_params), vp]),
+        "gpma_destroy": (C.c_int, [vp]),
+        "gpma_insert_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
+        "gpma_delete_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
+        "gpma_pagerank": (C.c_int, [vp, vp, vp, u32, f32, vp]),
+        "gpma_bfs": (C.c_int, [vp, u32, vp, vp]),
+        "gpma_cc": (C.c_int, [vp, vp, vp]),
+        "gpma_num_edges": (u64, [vp]),
+        "gpma_capacity": (u64, [vp]),
+        "gpma_leaf_size": (u32, [vp]),
+        "gpma_num_vertices": (u32, [vp]),
+        "gpma_export_slots": (C.c_int, [vp, vp, u64, pu64, vp]),
+        "gpma_export_keys": (C.c_int, [vp, vp, u64, pu64, vp]),
+        "gpma_export_leaf_counts": (C.c_int, [vp, vp, u64, vp]),
+        "gpma_export_row_offsets": (C.c_int, [vp, vp, u64, vp]),
+        "gpma_export_degrees": (C.c_int, [vp, vp, u64, vp]),
+        "gpma_sync": (C.c_int, [vp]),
+        "gpma_strerror": (C.c_char_p, [C.c_int]),
+        "gpma_profile_enable": (C.c_int, [vp, C.c_int]),
+        "gpma_profile_reset": (C.c_int, [vp]),
+        "gpma_profile_read": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), pu64,
+                                        C.POINTER(C.c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols() -> List[str]:
+    return ["gpma_default_params", "gpma_create", "gpma_destroy", "gpma_insert_batch",
+            "gpma_delete_batch", "gpma_pagerank", "gpma_bfs", "gpma_cc", "gpma_num_edges",
+            "gpma_capacity", "gpma_leaf_size", "gpma_num_vertices", "gpma_export_slots",
+            "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_row_offsets",
+            "gpma_export_degrees", "gpma_sync", "gpma_strerror", "gpma_profile_enable",
+            "gpma_profile_reset", "gpma_profile_read"]
+
+
+def strerror(code: int) -> str:
+    try:
+        return load_library().gpma_strerror(code).decode()
+    except Exception:  # pragma: no cover
+        return "error"
+
+
+def _stream(stream=None) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_u64(t: torch.Tensor) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("keys must be a device tensor")
+    if t.dtype not in (torch.int64, torch.uint64):
+        raise ValueError("keys must be 64-bit integers")
+    return t.contiguous()
+
+
+def _check(code: int, what: str):
+    if code != GPMA_OK:
+        raise GpmaError(code, what)
+
+
+# --------------------------------------------------------------------------
+# thin wrappers with the C names
+
+def gpma_default_params() -> gpma_params:
+    p = gpma_params()
+    load_library().gpma_default_params(C.byref(p))
+    return p
+
+
+def gpma_create(num_vertices: int, init_keys: torch.Tensor, params: Optional[gpma_params] = None,
+                stream=None) -> C.c_void_p:
+    lib = load_library()
+    h = C.c_void_p()
+    k = _dev_u64(init_keys)
+    rc = lib.gpma_create(C.byref(h), num_vertices, C.c_void_p(k.data_ptr()), k.numel(),
+                         C.byref(params) if params is not None else None, _stream(stream))
+    _check(rc, "gpma_create")
+    return h
+
+
+def gpma_destroy(h) -> None:
+    load_library().gpma_destroy(h)
+
+
+def gpma_insert_batch(h, keys: torch.Tensor, stream=None, stats: bool = False):
+    k = _dev_u64(keys)
+    st = gpma_stats() if stats else None
+    rc = load_library().gpma_insert_batch(h, C.c_void_p(k.data_ptr()), k.numel(), _stream(stream),
+                                          C.byref(st) if st is not None else None)
+    _check(rc, "gpma_insert_batch")
+    return st
+
+
+def gpma_delete_batch(h, keys: torch.Tensor, stream=None, stats: bool = False):
+    k = _dev_u64(keys)
+    st = gpma_stats() if stats else None
+    rc = load_library().gpma_delete_batch(h, C.c_void_p(k.data_ptr()), k.numel(), _stream(stream),
+                                          C.byref(st) if st is not None else None)
+    _check(rc, "gpma_delete_batch")
+    return st
+
+
+def gpma_pagerank(h, init: Optional[torch.Tensor], out: torch.Tensor, iters: int = 10,
+                  damping: float = 0.85, stream=None) -> torch.Tensor:
+    assert out.is_cuda and out.dtype == torch.float32 and out.is_contiguous()
+    ip = None
+    if init is not None:
+        assert init.is_cuda and init.dtype == torch.float32 and init.is_contiguous()
+        ip = C.c_void_p(init.data_ptr())
+    rc = load_library().gpma_pagerank(h, ip, C.c_void_p(out.data_ptr()), iters, damping, _stream(stream))
+    _check(rc, "gpma_pagerank")
+    return out
+
+
+def gpma_bfs(h, source: int, dist: torch.Tensor, stream=None) -> torch.Tensor:
+    assert dist.is_cuda and dist.dtype == torch.int32 and dist.is_contiguous()
+    _check(load_library().gpma_bfs(h, source, C.c_void_p(dist.data_ptr()), _stream(stream)), "gpma_bfs")
+    return dist
+
+
+def gpma_cc(h, label: torch.Tensor, stream=None) -> torch.Tensor:
+    assert label.is_cuda and label.dtype == torch.int32 and label.is_contiguous()
+    _check(load_library().gpma_cc(h, C.c_void_p(label.data_ptr()), _stream(stream)), "gpma_cc")
+    return label
+
+
+# --------------------------------------------------------------------------
+# convenience object
+
+@dataclass
+class BatchStats:
+    requested: int
+    applied: int
+    noops: int
+    top_level: int
+    resized: bool
+    segments_merged: List[int] = field(default_factory=list)
+    slots_rewritten: int = 0
+
+    @classmethod
+    def of(cls, st: gpma_stats) -> "BatchStats":
+        segs = list(st.segments_merged)
+        while segs and segs[-1] == 0:
+            segs.pop()
+        return cls(st.requested, st.applied, st.noops, st.top_level, bool(st.resized), segs,
+                   st.slots_rewritten)
+
+
+class GPMA:
+    """A GPU PMA holding a dynamic directed graph (one handle of the C ABI)."""
+
+    def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
+                 tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, stream=None):
+        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, 0)
+        self._lib = load_library()
+        self.V = num_vertices
+        self.h = gpma_create(num_vertices, init_keys, p, stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            gpma_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- updates
+    def insert(self, keys: torch.Tensor, stream=None, stats=False):
+        st = gpma_insert_batch(self.h, keys, stream, stats)
+        return BatchStats.of(st) if stats else None
+
+    def delete(self, keys: torch.Tensor, stream=None, stats=False):
+        st = gpma_delete_batch(self.h, keys, stream, stats)
+        return BatchStats.of(st) if stats else None
+
+    # --- analytics
+    def pagerank(self, init: Optional[torch.Tensor] = None, iters: int = 10, damping: float = 0.85,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.V, dtype=torch.float32, device="cuda")
+        return gpma_pagerank(self.h, init, out, iters, damping, stream)
+
+    def bfs(self, source: int, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.V, dtype=torch.int32, device="cuda")
+        return gpma_bfs(self.h, source, out, stream)
+
+    def cc(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.V, dtype=torch.int32, device="cuda")
+        return gpma_cc(self.h, out, stream)
+
+    # --- introspection
+    @property
+    def num_edges(self) -> int:
+        return int(self._lib.gpma_num_edges(self.h))
+
+    @property
+    def capacity(self) -> int:
+        return int(self._lib.gpma_capacity(self.h))
+
+    @property
+    def leaf_size(self) -> int:
+        return int(self._lib.gpma_leaf_size(self.h))
+
+    def slots(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.capacity, dtype=torch.int64, device="cuda")
+        cap = C.c_uint64()
+        _check(self._lib.gpma_export_slots(self.h, C.c_void_p(out.data_ptr()), out.numel(),
+                                           C.byref(cap), _stream(stream)), "gpma_export_slots")
+        return out
+
+    def keys(self, stream=None) -> torch.Tensor:
+        out = torch.empty(max(self.num_edges, 1), dtype=torch.int64, device="cuda")
+        n = C.c_uint64()
+        _check(self._lib.gpma_export_keys(self.h, C.c_void_p(out.data_ptr()), out.numel(),
+                                          C.byref(n), _stream(stream)), "gpma_export_keys")
+        return out[: n.value]
+
+    def leaf_counts(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.capacity // self.leaf_size, dtype=torch.int16, device="cuda")
+        _check(self._lib.gpma_export_leaf_counts(self.h, C.c_void_p(out.data_ptr()), out.numel(),
+                                                 _stream(stream)), "gpma_export_leaf_counts")
+        return out
+
+    def row_offsets(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.V + 1, dtype=torch.int32, device="cuda")
+        _check(self._lib.gpma_export_row_offsets(self.h, C.c_void_p(out.data_ptr()), out.numel(),
+                                                 _stream(stream)), "gpma_export_row_offsets")
+        return out
+
+    def degrees(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.V, dtype=torch.int32, device="cuda")
+        _check(self._lib.gpma_export_degrees(self.h, C.c_void_p(out.data_ptr()), out.numel(),
+                                             _stream(stream)), "gpma_export_degrees")
+        return out
+
+    # --- profiling
+    def profile(self, enable: bool = True):
+        self._lib.gpma_profile_enable(self.h, 1 if enable else 0)
+
+    def profile_reset(self):
+        self._lib.gpma_profile_reset(self.h)
+
+    def profile_read(self, kernel: int):
+        ms, n, by = C.c_double(), C.c_uint64(), C.c_double()
+        self._lib.gpma_profile_read(self.h, kernel, C.byref(ms), C.byref(n), C.byref(by))
+        return ms.value, n.value, by.value

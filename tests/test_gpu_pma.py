@@ -1,0 +1,280 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Layout parity is slot for slot: the GPU's raw slot array, leaf counts, CSR
+row offsets and degrees must equal what the sequential oracle produces from
+the same seeded inputs.  BFS and CC must match exactly; PageRank within
+1e-6 max relative error (each of the 10 fp32 roundings adds at most 2^-24
+relative error to positive terms, so 10 steps stay below 6e-7).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+PR_RTOL = 1e-6
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(keys) -> torch.Tensor:
+    if isinstance(keys, torch.Tensor):
+        return keys.to("cuda")
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(keys, dtype=np.uint64)).view(np.int64)).cuda()
+
+
+def npu64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def check_state(g, ref, V):
+    slots = npu64(g.slots())
+    want = ref.slots()
+    assert g.capacity == ref.capacity
+    if not np.array_equal(slots, want):
+        bad = np.nonzero(slots != want)[0]
+        raise AssertionError("slots differ at %d positions, first %s: gpu %x oracle %x"
+                             % (bad.size, bad[:5], slots[bad[0]], want[bad[0]]))
+    lf = g.leaf_size
+    assert np.array_equal(g.leaf_counts().cpu().numpy().astype(np.int64), O.leaf_counts(want, lf))
+    assert np.array_equal(g.row_offsets().cpu().numpy().astype(np.int64), O.row_offsets(want, V))
+    edges = O.edge_keys(want)
+    assert np.array_equal(g.degrees().cpu().numpy().astype(np.int64), O.out_degrees(edges, V))
+    assert g.num_edges == edges.size
+    return edges
+
+
+def make(V, init, lf, **kw):
+    from paper_1709_05061_amd import GPMA
+    init_np = np.asarray(init.numpy() if isinstance(init, torch.Tensor) else init).view(np.uint64) \
+        if len(init) else np.zeros(0, np.uint64)
+    g = GPMA(V, dev(init_np), leaf_size=lf, **kw)
+    ref = O.OraclePMA(V, init_np, lf, **kw)
+    return g, ref
+
+
+@pytest.mark.parametrize("V,n,lf,seed", [(3, 0, 16, 0), (100, 0, 16, 1), (1000, 5000, 16, 2),
+                                         (1 << 14, 1 << 17, 32, 3), (5000, 40000, 64, 4),
+                                         (777, 3000, 128, 5)])
+def test_create_matches_oracle(V, n, lf, seed):
+    say("create", V, n, lf, seed)
+    init = synth.random_batch(V, n, seed)
+    g, ref = make(V, init, lf)
+    check_state(g, ref, V)
+    g.close()
+
+
+def test_create_csr_example_and_auto_leaf():
+    from paper_1709_05061_amd import GPMA
+    keys = [(0 << 32) | 0, (0 << 32) | 2, (1 << 32) | 2, (2 << 32) | 0, (2 << 32) | 1, (2 << 32) | 2]
+    g = GPMA(3, dev(keys))
+    assert g.leaf_size == 16
+    ref = O.OraclePMA(3, np.array(keys, np.uint64), 16)
+    check_state(g, ref, 3)
+    ro = g.row_offsets().cpu().numpy()
+    assert ro[0] == 0 and list(npu64(g.keys())) == sorted(keys)
+    g.close()
+
+
+def run_stream(g, ref, V, batches, pr_every=0, check_every=1):
+    """batches: list of (op, numpy uint64 keys)."""
+    x = None
+    for t, (op, keys) in enumerate(batches):
+        st = getattr(g, op)(dev(keys), stats=True)
+        getattr(ref, op)(keys)
+        assert st.applied == ref.last_applied(), (t, op, st, ref.last_applied())
+        if t % check_every == 0 or t == len(batches) - 1:
+            edges = check_state(g, ref, V)
+            if pr_every and t % pr_every == 0:
+                x = g.pagerank(init=x, iters=10)
+                want = O.pagerank(V, edges, x0=None if t == 0 else xin, iters=10)
+                rel = np.max(np.abs(x.cpu().numpy() - want) / want)
+                assert rel < PR_RTOL, (t, rel)
+            xin = None if x is None else x.cpu().numpy().astype(np.float64)
+
+
+def test_sliding_window_er_2e14():
+    """Uniform random graph, 2^14 vertices, 2^17 initial edges, 32 slides of
+    2^10 deletes (oldest) + 2^10 inserts; PageRank after every slide."""
+    V, W, b, S = 1 << 14, 1 << 17, 1 << 10, 32
+    st = synth.er_stream(V, W, b, S, seed=1)
+    g, ref = make(V, st.initial(), 32)
+    check_state(g, ref, V)
+    x = None
+    for t in range(S):
+        say("slide", t)
+        d, i = st.slide(t, b)
+        sd = g.delete(dev(d), stats=True)
+        ref.delete(npu64(d))
+        assert sd.applied == b and ref.last_applied() == b
+        si = g.insert(dev(i), stats=True)
+        ref.insert(npu64(i))
+        assert si.applied == b
+        edges = check_state(g, ref, V)
+        xin = None if x is None else x.cpu().numpy().astype(np.float64)
+        x = g.pagerank(init=x, iters=10, out=None)
+        want = O.pagerank(V, edges, x0=xin, iters=10)
+        rel = np.max(np.abs(x.cpu().numpy() - want) / want)
+        assert rel < PR_RTOL, (t, rel)
+    g.close()
+
+
+@pytest.mark.parametrize("tier_lds", [None, "0"])
+def test_growth_and_shrink_climbs_levels(tier_lds, monkeypatch):
+    """Small graph grown well past several doublings and shrunk back: every
+    level of the tree and the root resize are exercised; with tier_lds=0 the
+    levels above the leaves run through the device tier."""
+    if tier_lds is not None:
+        monkeypatch.setenv("GPMA_TIER_LDS", tier_lds)
+    V, lf = 64, 16
+    rng = np.random.default_rng(3)
+    allk = np.array([(u << 32) | v for u in range(V) for v in range(V)], dtype=np.uint64)
+    rng.shuffle(allk)
+    g, ref = make(V, allk[:40], lf)
+    batches = []
+    pos = 40
+    for sz in [1, 3, 17, 64, 200, 333, 500, 800, 999, 1]:
+        kk = allk[pos:pos + sz]
+        pos += sz
+        extra = allk[:5]                      # present keys: no-ops
+        batches.append(("insert", np.concatenate([kk, kk[:2], extra])))
+    live = allk[:pos]
+    for sz in [700, 900, 1000, 500, 300, 100, 10, 3]:
+        idx = rng.choice(live.size, min(sz, live.size), replace=False)
+        kk = live[idx]
+        live = np.delete(live, idx)
+        batches.append(("delete", np.concatenate([kk, kk[:3]])))
+    say("growth/shrink", tier_lds, len(batches))
+    run_stream(g, ref, V, batches, pr_every=3)
+    g.close()
+
+
+def test_sorted_stream_is_adversarial_but_exact():
+    """Sorted arrivals all land at the right end of the array (the worst case
+    for segment cascades)."""
+    V, lf = 256, 16
+    allk = np.array([(u << 32) | v for u in range(V) for v in range(0, V, 3)], dtype=np.uint64)
+    g, ref = make(V, allk[:500], lf)
+    batches = [("insert", allk[p:p + 400]) for p in range(500, allk.size, 400)]
+    batches += [("delete", allk[p:p + 700]) for p in range(0, allk.size, 700)]
+    run_stream(g, ref, V, batches)
+    g.close()
+
+
+@pytest.mark.parametrize("lf", [16, 32, 64, 128, 256, 512])
+def test_leaf_sizes(lf):
+    V = 2000
+    st = synth.er_stream(V, 30000, 3000, 4, seed=lf)
+    g, ref = make(V, st.initial(), lf)
+    batches = []
+    for t in range(4):
+        d, i = st.slide(t, 3000)
+        batches += [("delete", npu64(d)), ("insert", npu64(i))]
+    batches.append(("insert", npu64(synth.random_batch(V, 5000, 99))))
+    run_stream(g, ref, V, batches)
+    g.close()
+
+
+def test_rmat_stream_batch_sizes():
+    """R-MAT (a=.57, b=c=.19) scale 14, edge factor 16; slides of 2^6..2^12."""
+    st = synth.rmat_stream(14, 16, seed=2)
+    V = st.V
+    g, ref = make(V, st.initial(), 32)
+    check_state(g, ref, V)
+    t0 = 0
+    for lb in (6, 8, 10, 12):
+        b = 1 << lb
+        for _ in range(2):
+            d, i = st.order[t0:t0 + b], st.order[st.window + t0: st.window + t0 + b]
+            t0 += b
+            say("rmat slide b=", b)
+            run_stream(g, ref, V, [("delete", npu64(d)), ("insert", npu64(i))])
+    g.close()
+
+
+def test_invalid_batch_changes_nothing():
+    from paper_1709_05061_amd import GpmaError
+    V = 50
+    g, ref = make(V, synth.random_batch(V, 300, 1), 16)
+    before = npu64(g.slots())
+    for bad in ((V << 32) | 1, (1 << 32) | V, (3 << 32) | 0xFFFFFFFF):
+        for op in ("insert", "delete"):
+            with pytest.raises(GpmaError) as ei:
+                getattr(g, op)(dev([(1 << 32) | 2, bad]))
+            assert ei.value.code == -1
+    assert np.array_equal(npu64(g.slots()), before)
+    check_state(g, ref, V)
+    g.close()
+
+
+def test_empty_repeated_and_noop_batches():
+    V = 40
+    init = npu64(synth.random_batch(V, 200, 4))
+    g, ref = make(V, init, 16)
+    st = g.insert(dev(np.zeros(0, np.uint64)), stats=True)
+    assert st.applied == 0
+    present = np.unique(init)[:30]
+    st = g.insert(dev(np.concatenate([present, present])), stats=True)
+    assert st.applied == 0 and st.noops == 60
+    absent = np.array([(39 << 32) | v for v in range(40)], np.uint64)
+    absent = absent[~np.isin(absent, init)]
+    st = g.delete(dev(absent), stats=True)
+    assert st.applied == 0
+    run_stream(g, ref, V, [("insert", np.repeat(absent[:5], 7)), ("delete", np.repeat(absent[:5], 3))])
+    g.close()
+
+
+@pytest.mark.parametrize("kind", ["er", "rmat"])
+def test_analytics_match_oracle(kind):
+    if kind == "er":
+        V = 3000
+        edges_t = synth.er_edges(V, 9000, seed=5)
+    else:
+        u = synth.rmat_unique(12, 16 << 12, seed=6)
+        V, edges_t = 1 << 12, u
+    e = np.unique(npu64(edges_t))
+    g, _ = make(V, e, 32)
+    for src in (0, 1, V // 2, V - 1):
+        assert np.array_equal(g.bfs(src).cpu().numpy(), O.bfs(V, e, src)), src
+    assert np.array_equal(g.cc().cpu().numpy().astype(np.uint32), O.cc(V, e))
+    x = g.pagerank(iters=10).cpu().numpy()
+    want = O.pagerank(V, e, iters=10)
+    assert np.max(np.abs(x - want) / want) < PR_RTOL
+    # warm start from a non-uniform fp32 vector; out aliases init
+    x0 = torch.rand(V, device="cuda", dtype=torch.float32) + 0.1
+    x0 /= x0.sum()
+    xin = x0.cpu().numpy().astype(np.float64)
+    g.pagerank(init=x0, iters=7, damping=0.7, out=x0)
+    want = O.pagerank(V, e, x0=xin, iters=7, damping=0.7)
+    assert np.max(np.abs(x0.cpu().numpy() - want) / want) < PR_RTOL
+    g.close()
+
+
+def test_analytics_closed_forms():
+    from paper_1709_05061_amd import GPMA
+    V = 1000
+    path = [(i << 32) | (i + 1) for i in range(V - 1)]
+    g = GPMA(V, dev(path), leaf_size=16)
+    assert list(g.bfs(0).cpu().numpy()) == list(range(V))
+    assert list(g.cc().cpu().numpy()) == [0] * V
+    x = g.pagerank(iters=10).cpu().numpy()
+    assert abs(x.sum() - 1) < 1e-5
+    g.close()
+    cyc = [(i << 32) | ((i + 1) % V) for i in range(V)]
+    g = GPMA(V, dev(cyc), leaf_size=16)
+    np.testing.assert_allclose(g.pagerank(iters=10).cpu().numpy(), 1.0 / V, rtol=1e-6)
+    g.close()
+    g = GPMA(V, dev(np.zeros(0, np.uint64)), leaf_size=16)
+    np.testing.assert_allclose(g.pagerank(iters=3).cpu().numpy(), 1.0 / V, rtol=1e-6)
+    assert list(g.bfs(5).cpu().numpy()) == [-1] * 5 + [0] + [-1] * (V - 6)
+    assert list(g.cc().cpu().numpy()) == list(range(V))
+    g.close()
