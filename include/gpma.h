@@ -65,8 +65,15 @@ typedef struct {
     uint32_t leaf_size;
     uint32_t tau_leaf_pm, tau_root_pm;
     uint32_t rho_leaf_pm, rho_root_pm;
-    uint32_t flags;     /* reserved, must be 0 */
+    uint32_t flags;     /* GPMA_FLAG_* below; other bits must be 0 */
 } gpma_params;
+
+/* Keep a second, dst-major PMA (keys dst<<32 | src, one guard per vertex)
+ * updated by the same GPMA+ batches.  It holds every vertex's in-edges as a
+ * contiguous row, so PageRank pulls (a segmented reduction, no per-edge
+ * atomics) instead of pushing.  Costs a second update per batch and a second
+ * array.  Not in the paper (its SpMV reads a CSR copy); a design addition. */
+#define GPMA_FLAG_MIRROR 1u
 
 /* Per-batch statistics; filled when a non-NULL pointer is passed. */
 typedef struct {
@@ -129,6 +136,11 @@ int gpma_bfs(gpma_t *h, uint32_t source, int32_t *dist_dev, hipStream_t stream);
 /* Connected components with edge direction ignored (Section 6.1); every
  * vertex gets the smallest vertex id of its component.  label_dev: V uint32. */
 int gpma_cc(gpma_t *h, uint32_t *label_dev, hipStream_t stream);
+
+/* The mirror of a handle created with GPMA_FLAG_MIRROR, else NULL.  A
+ * borrowed handle for the read-only calls below (export, introspection); it
+ * must not be updated or destroyed directly. */
+gpma_t *gpma_get_mirror(gpma_t *h);
 
 /* Introspection.  Counts are those after the last completed call. */
 uint64_t gpma_num_edges(const gpma_t *h);     /* guards excluded */

@@ -38,17 +38,88 @@ k_pr_prep(const float *__restrict__ x, const uint32_t *__restrict__ deg, uint32_
     }
 }
 
-// Push y[dst] += contrib[src] for every stored edge.  The slot stream is read
-// once, coalesced; src is non-decreasing along it, so contrib[src] reads hit
-// cache; the scatter into y goes through fp64 atomics.
+// Push y[dst] += contrib[src] for every stored edge of a src-major array.
+// Lane pairs of slots walk the array; a leaf's gap tail is never loaded (its
+// leaf count says where the packed prefix ends).  src is non-decreasing along
+// the stream, so contrib[src] reads hit cache; y takes one fp64 atomic per edge.
 __global__ void __launch_bounds__(256)
-k_pr_spmv(const uint64_t *__restrict__ slots, uint64_t cap, const double *__restrict__ contrib,
-          double *__restrict__ y) {
+k_pr_push(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint64_t cap,
+          uint32_t lf_log2, const double *__restrict__ contrib, double *__restrict__ y) {
+    const uint64_t lfm = (1ull << lf_log2) - 1;
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x * 2;
     for (uint64_t p = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; p < cap; p += stride) {
-        const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(slots + p);
-        if (kk.x != kEmpty && !is_guard(kk.x)) unsafeAtomicAdd(&y[key_dst(kk.x)], contrib[key_src(kk.x)]);
-        if (kk.y != kEmpty && !is_guard(kk.y)) unsafeAtomicAdd(&y[key_dst(kk.y)], contrib[key_src(kk.y)]);
+        const uint32_t c = cnt[p >> lf_log2];
+        const uint32_t o = (uint32_t)(p & lfm);
+        if (o >= c) continue;
+        uint64_t k0, k1 = kEmpty;
+        if (o + 1 < c) {
+            const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(slots + p);
+            k0 = kk.x;
+            k1 = kk.y;
+        } else {
+            k0 = slots[p];
+        }
+        if (!is_guard(k0)) unsafeAtomicAdd(&y[key_dst(k0)], contrib[key_src(k0)]);
+        if (k1 != kEmpty && !is_guard(k1)) unsafeAtomicAdd(&y[key_dst(k1)], contrib[key_src(k1)]);
+    }
+}
+
+// Pull over the dst-major mirror: entry v<<32|u adds contrib[u] to y[v].  A
+// wave takes 128 consecutive slots (2 per lane).  Along the array the row v is
+// non-decreasing; a gap takes the row of its leaf's last entry, so the wave
+// sees runs of equal rows.  A segmented inclusive scan over the lanes sums each
+// run; a run wholly inside the wave is a complete row and is stored, a run
+// touching either end of the wave may continue in a neighbour and is added
+// atomically (y is zeroed beforehand).  At most two atomics per wave.
+__global__ void __launch_bounds__(256)
+k_pr_pull(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint64_t cap,
+          uint32_t lf_log2, const double *__restrict__ contrib, double *__restrict__ y) {
+    const uint32_t lane = __lane_id();
+    const uint64_t lfm = (1ull << lf_log2) - 1;
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    for (uint64_t base = wave * 2 * kWave; base < cap; base += nwaves * 2 * kWave) {
+        const uint64_t p = base + 2 * lane;
+        uint32_t r0 = kNone, r1 = kNone;
+        double a = 0.0, b = 0.0;
+        if (p < cap) {
+            const uint64_t leaf = p >> lf_log2;
+            const uint32_t c = cnt[leaf];
+            const uint32_t o = (uint32_t)(p & lfm);
+            uint64_t k0 = kEmpty, k1 = kEmpty;
+            if (o + 1 < c) {
+                const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(slots + p);
+                k0 = kk.x;
+                k1 = kk.y;
+            } else if (o < c) {
+                k0 = slots[p];
+            }
+            uint64_t last = 0;
+            if (o + 1 >= c) last = slots[(leaf << lf_log2) + c - 1];
+            r0 = (uint32_t)((o < c ? k0 : last) >> 32);
+            r1 = (uint32_t)((o + 1 < c ? k1 : last) >> 32);
+            if (o < c && !is_guard(k0)) a = contrib[key_dst(k0)];
+            if (o + 1 < c && !is_guard(k1)) b = contrib[key_dst(k1)];
+        }
+        double sc = (r0 == r1) ? a + b : b;   // running sum of the lane's tail run
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const double ys = __shfl_up(sc, d, kWave);
+            const uint32_t yr = __shfl_up(r1, d, kWave);
+            if (lane >= (uint32_t)d && yr == r1) sc += ys;
+        }
+        const double prev_s = __shfl_up(sc, 1, kWave);
+        const uint32_t prev_r = __shfl_up(r1, 1, kWave);
+        const uint32_t next_r0 = __shfl_down(r0, 1, kWave);
+        const uint32_t first_row = __shfl(r0, 0, kWave);
+        if (r0 != r1 && r0 != kNone) {
+            const double va = a + ((lane > 0 && prev_r == r0) ? prev_s : 0.0);
+            if (r0 == first_row) unsafeAtomicAdd(&y[r0], va); else y[r0] = va;
+        }
+        if (r1 != kNone && (lane == kWave - 1 || next_r0 != r1)) {
+            if (r1 == first_row || lane == kWave - 1) unsafeAtomicAdd(&y[r1], sc); else y[r1] = sc;
+        }
     }
 }
 
@@ -74,38 +145,69 @@ __global__ void k_bfs_init(int32_t *__restrict__ dist, uint32_t V, uint32_t sour
     }
 }
 
-// One wave per frontier vertex walks its row [row_ptr[u], row_ptr[u+1]),
-// skipping gaps and the guard (the IsEntryExist test of Algorithm "GPU-based
-// BFS Neighbour Gathering").  New vertices are claimed with a CAS on dist and
-// appended with one atomic per wave.
+// Frontier expansion, load-balanced over slots rather than vertices: the
+// frontier's rows [row_ptr[u], row_ptr[u+1]) are laid end to end (offs is
+// the exclusive scan of their lengths, *total their sum) and every thread
+// takes kBfsItems consecutive slots of that concatenation, so a hub's long
+// row is spread over many threads.  Gaps and guards are skipped (the
+// IsEntryExist test of Algorithm "GPU-based BFS Neighbour Gathering").  New
+// vertices are claimed with a CAS on dist and appended with one atomic per
+// wave.
+constexpr int kBfsItems = 8;
+
+__global__ void k_bfs_row_len(const uint32_t *__restrict__ row_ptr, const uint32_t *__restrict__ front,
+                              uint32_t nfront, uint32_t *__restrict__ len) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nfront) {
+        uint32_t u = front[i];
+        len[i] = row_ptr[u + 1] - row_ptr[u];
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_bfs_expand(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr,
-             const uint32_t *__restrict__ front, uint32_t nfront, int32_t level,
-             int32_t *__restrict__ dist, uint32_t *__restrict__ next, uint32_t *__restrict__ next_count) {
-    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+             const uint32_t *__restrict__ front, const uint32_t *__restrict__ offs, uint32_t nfront,
+             const uint32_t *__restrict__ total, int32_t level, int32_t *__restrict__ dist,
+             uint32_t *__restrict__ next, uint32_t *__restrict__ next_count) {
+    const uint32_t T = *total;
     const uint32_t lane = __lane_id();
-    if (wave >= nfront) return;
-    const uint32_t u = front[wave];
-    const uint32_t beg = row_ptr[u], end = row_ptr[u + 1];
-    for (uint32_t p0 = beg; p0 < end; p0 += kWave) {
-        uint32_t p = p0 + lane;
-        bool claim = false;
-        uint32_t v = 0;
-        if (p < end) {
-            uint64_t k = slots[p];
-            if (k != kEmpty && !is_guard(k)) {
-                v = key_dst(k);
-                if (__hip_atomic_load(&dist[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0)
-                    claim = atomicCAS(&dist[v], -1, level + 1) == -1;
-            }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x * kBfsItems;
+    for (uint64_t t0 = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) * kBfsItems; t0 < T + 0ull;
+         t0 += stride) {
+        // frontier entry holding slot t0: the last i with offs[i] <= t0
+        uint32_t lo = 0, hi = nfront;
+        while (hi - lo > 1) {
+            uint32_t mid = (lo + hi) >> 1;
+            if (offs[mid] <= t0) lo = mid; else hi = mid;
         }
-        uint64_t m = __ballot(claim);
-        if (m) {
-            uint32_t leader = __ffsll((unsigned long long)m) - 1;
-            uint32_t base = 0;
-            if (lane == leader) base = atomicAdd(next_count, (uint32_t)__popcll(m));
-            base = __shfl(base, leader, kWave);
-            if (claim) next[base + __popcll(m & lanemask_lt())] = v;
+        uint32_t i = lo;
+        uint32_t rend = (i + 1 < nfront) ? offs[i + 1] : T;
+        uint32_t rbase = row_ptr[front[i]] - offs[i];
+        for (int q = 0; q < kBfsItems; q++) {
+            const uint64_t t = t0 + q;
+            bool claim = false;
+            uint32_t v = 0;
+            if (t < T) {
+                while (t >= rend) {   // next non-empty row (rows have at least a guard)
+                    i++;
+                    rend = (i + 1 < nfront) ? offs[i + 1] : T;
+                    rbase = row_ptr[front[i]] - offs[i];
+                }
+                const uint64_t k = slots[rbase + t];
+                if (k != kEmpty && !is_guard(k)) {
+                    v = key_dst(k);
+                    if (__hip_atomic_load(&dist[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0)
+                        claim = atomicCAS(&dist[v], -1, level + 1) == -1;
+                }
+            }
+            const uint64_t m = __ballot(claim);
+            if (m) {
+                const uint32_t leader = __ffsll((unsigned long long)m) - 1;
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(next_count, (uint32_t)__popcll(m));
+                base = __shfl(base, leader, kWave);
+                if (claim) next[base + __popcll(m & lanemask_lt())] = v;
+            }
         }
     }
 }
@@ -170,9 +272,28 @@ void launch_pr_prep(const float *x, const uint32_t *deg, uint32_t V, bool unifor
                        uniform ? 1 : 0, contrib, y, dangling);
 }
 
-void launch_pr_spmv(const uint64_t *slots, uint64_t cap, const double *contrib, double *y,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_pr_spmv, dim3(grid_for_stream(cap, 2)), dim3(256), 0, s, slots, cap, contrib, y);
+void launch_pr_push(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, uint32_t lf_log2,
+                    const double *contrib, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_pr_push, dim3(grid_for_stream(cap, 2)), dim3(256), 0, s, slots, cnt, cap,
+                       lf_log2, contrib, y);
+}
+
+void launch_pr_pull(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, uint32_t lf_log2,
+                    const double *contrib, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_pr_pull, dim3(grid_for_stream(cap, 2)), dim3(256), 0, s, slots, cnt, cap,
+                       lf_log2, contrib, y);
+}
+
+__global__ void k_transpose_keys(const uint64_t *__restrict__ in, uint64_t n, uint64_t *__restrict__ out) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        uint64_t k = in[i];
+        out[i] = (k << 32) | (k >> 32);
+    }
+}
+
+void launch_transpose_keys(const uint64_t *in, uint64_t n, uint64_t *out, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_transpose_keys, dim3((uint32_t)div_up(n, 256)), dim3(256), 0, s, in, n, out);
 }
 
 void launch_pr_combine(const double *y, const double *dangling, uint32_t V, double damping, float *out,
@@ -187,12 +308,17 @@ void launch_bfs_init(int32_t *dist, uint32_t V, uint32_t source, uint32_t *queue
                        queue, qcount);
 }
 
+void launch_bfs_row_len(const uint32_t *row_ptr, const uint32_t *front, uint32_t nfront, uint32_t *len,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_row_len, dim3((uint32_t)div_up(nfront, 256)), dim3(256), 0, s, row_ptr,
+                       front, nfront, len);
+}
+
 void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uint32_t *front,
-                       uint32_t nfront, int32_t level, int32_t *dist, uint32_t *next,
-                       uint32_t *next_count, hipStream_t s) {
-    uint64_t threads = (uint64_t)nfront * kWave;
-    hipLaunchKernelGGL(k_bfs_expand, dim3((uint32_t)div_up(threads, 256)), dim3(256), 0, s, slots,
-                       row_ptr, front, nfront, level, dist, next, next_count);
+                       const uint32_t *offs, uint32_t nfront, const uint32_t *total, uint64_t max_total,
+                       int32_t level, int32_t *dist, uint32_t *next, uint32_t *next_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for_stream(max_total, kBfsItems)), dim3(256), 0, s, slots,
+                       row_ptr, front, offs, nfront, total, level, dist, next, next_count);
 }
 
 void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s) {

@@ -68,9 +68,15 @@ struct gpma {
     uint64_t dt_off_cap = 0;
     uint32_t *dt_off = nullptr, *dt_tmp = nullptr, *dt_tot = nullptr;
 
+    // dst-major mirror (keys dst<<32|src), kept in step with every batch
+    gpma *mir = nullptr;
+    uint64_t *tkeys = nullptr;
+    uint64_t tkeys_cap = 0;
+
     // analytics scratch
     double *pr_contrib = nullptr, *pr_y = nullptr, *pr_dang = nullptr;
-    uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *small = nullptr;
+    uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *bfs_off = nullptr, *bfs_tmp = nullptr;
+    uint32_t *small = nullptr;
     uint32_t *small_h = nullptr;   // pinned
 
     Device dev;
@@ -149,7 +155,7 @@ bool params_valid(const gpma_params *p, bool allow_auto) {
           p->tau_root_pm <= p->tau_leaf_pm && p->tau_leaf_pm < 1000))
         return false;
     if (2 * p->rho_root_pm > p->tau_root_pm) return false;
-    if (p->flags) return false;
+    if (p->flags & ~(uint32_t)GPMA_FLAG_MIRROR) return false;
     return true;
 }
 
@@ -302,7 +308,7 @@ int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t
     launch_gather_segment(g->slots, g->cnt, 0, g->L, g->lf, g->dt_off, g->dtA, s);
     launch_merge_sorted(del, g->dtA, ns, U, k, g->dtB, s);
     launch_dispatch(g->dtB, N, nslots, ncnt, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
-    launch_mark_done(del, U, status, 0, k, g->deg, g->ctl, ncap, s);
+    launch_mark_done(del, U, status, 0, k, g->deg, g->ctl, ncap, true, s);
     if (ncap != g->cap) {
         hipStreamSynchronize(s);
         dev_free(g->slots);
@@ -346,7 +352,7 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
             launch_gather_segment(g->slots, g->cnt, first, P, g->lf, g->dt_off, g->dtA, s);
             launch_merge_sorted(del, g->dtA, ns, c.k + i, k, g->dtB, s);
             launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->cnt, g->row_ptr, first, P, g->lf, s);
-            launch_mark_done(del, c.k, c.st, i, k, g->deg, g->ctl, P << g->lf_log2, s);
+            launch_mark_done(del, c.k, c.st, i, k, g->deg, g->ctl, P << g->lf_log2, false, s);
         }
         i = j;
     }
@@ -395,7 +401,8 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->row_ptr, g->deg,
                       g->lf, lo, hi, g->ctl, s);
     if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
-    compact_pending(cur.k, cur.l, cur.st, cur.n, b, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, s);
+    compact_pending(cur.k, cur.l, cur.st, cur.n, b, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del,
+                    g->lf, g->ctl, s);
     read_ctl(g, s);
     if (g->ctl_h->err) {
         if (pa) { g->ev_pool.push_back(pa); g->ev_pool.push_back(pb); }
@@ -431,7 +438,7 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
             if (e) return e;
         }
         compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags,
-                        g->tmp, s);
+                        g->tmp, del, (uint64_t)g->lf << h, g->ctl, s);
         read_ctl(g, s);
         const uint32_t segs_h = g->ctl_h->segs - segs_seen;
         segs_seen = g->ctl_h->segs;
@@ -484,10 +491,12 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
 
 void free_all(gpma *g) {
     free_batch(g);
+    dev_free(g->tkeys);
     dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
-    dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->small);
+    dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
+    dev_free(g->small);
     dev_free(g->ctl);
     if (g->ctl_h) hipHostFree(g->ctl_h);
     if (g->small_h) hipHostFree(g->small_h);
@@ -555,7 +564,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     uint64_t *in = nullptr, *ba = nullptr, *bb = nullptr, *uq = nullptr;
     uint32_t *fl = nullptr, *tmp = nullptr;
     e |= dev_alloc(&g->ctl, 1);
-    e |= dev_alloc(&g->small, 4);
+    e |= dev_alloc(&g->small, 8);
     if (hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (hipHostMalloc((void **)&g->small_h, 4 * sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
     e |= dev_alloc(&in, tot); e |= dev_alloc(&ba, tot); e |= dev_alloc(&bb, tot);
@@ -628,6 +637,25 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     }
     cleanup();
     g->n = nu;
+    if (p.flags & GPMA_FLAG_MIRROR) {
+        gpma_params mp = p;
+        mp.flags = 0;
+        mp.leaf_size = g->lf;
+        uint64_t *tk = nullptr;
+        if (n && dev_alloc(&tk, n)) {
+            free_all(g);
+            delete g;
+            return GPMA_ENOMEM;
+        }
+        launch_transpose_keys(keys, n, tk, s);
+        int e2 = gpma_create(&g->mir, V, tk, n, &mp, s);
+        dev_free(tk);
+        if (e2) {
+            free_all(g);
+            delete g;
+            return e2;
+        }
+    }
     *out = g;
     return GPMA_OK;
 }
@@ -635,20 +663,41 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
 int gpma_destroy(gpma_t *g) {
     if (!g) return GPMA_OK;
     hipDeviceSynchronize();
+    if (g->mir) gpma_destroy(g->mir);
+    g->mir = nullptr;
     free_all(g);
     delete g;
     return GPMA_OK;
 }
 
-int gpma_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st) {
+static int apply_with_mirror(gpma_t *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t s,
+                             gpma_stats *st) {
     if (!g) return GPMA_EINVAL;
-    return apply_batch(g, keys, b, false, s, st);
+    int e = apply_batch(g, keys, b, del, s, st);
+    if (e || !g->mir || b == 0) return e;
+    if (b > g->tkeys_cap) {
+        dev_free(g->tkeys);
+        g->tkeys_cap = 0;
+        if (dev_alloc(&g->tkeys, next_pow2(b))) return GPMA_ENOMEM;
+        g->tkeys_cap = next_pow2(b);
+    }
+    launch_transpose_keys(keys, b, g->tkeys, s);
+    e = apply_batch(g->mir, g->tkeys, b, del, s, nullptr);
+    if (e) return e;
+    // both arrays hold the same edge set
+    if (g->mir->n != g->n) return GPMA_EDEVICE;
+    return GPMA_OK;
+}
+
+int gpma_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st) {
+    return apply_with_mirror(g, keys, b, false, s, st);
 }
 
 int gpma_delete_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st) {
-    if (!g) return GPMA_EINVAL;
-    return apply_batch(g, keys, b, true, s, st);
+    return apply_with_mirror(g, keys, b, true, s, st);
 }
+
+gpma_t *gpma_get_mirror(gpma_t *g) { return g ? g->mir : nullptr; }
 
 uint64_t gpma_num_edges(const gpma_t *g) { return g ? g->n - g->V : 0; }
 uint64_t gpma_capacity(const gpma_t *g) { return g ? g->cap : 0; }
@@ -718,13 +767,19 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
             return GPMA_ENOMEM;
         }
     }
+    // algorithmic bytes of one SpMV: every stored entry once, the contribution
+    // vector and the accumulator once each
     const double spmv_bytes = 8.0 * (double)g->n + 16.0 * (double)g->V;
     for (uint32_t it = 0; it < iters; it++) {
         const float *x = it == 0 ? init : out;
         launch_pr_prep(x, g->deg, g->V, x == nullptr, g->pr_contrib, g->pr_y, g->pr_dang, s);
         {
             ProfScope ps(g, GPMA_K_SPMV, s);
-            launch_pr_spmv(g->slots, g->cap, g->pr_contrib, g->pr_y, s);
+            if (g->mir)
+                launch_pr_pull(g->mir->slots, g->mir->cnt, g->mir->cap, g->mir->lf_log2, g->pr_contrib,
+                               g->pr_y, s);
+            else
+                launch_pr_push(g->slots, g->cnt, g->cap, g->lf_log2, g->pr_contrib, g->pr_y, s);
             ps.done(spmv_bytes);
         }
         launch_pr_combine(g->pr_y, g->pr_dang, g->V, (double)damping, out, s);
@@ -735,8 +790,13 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
 int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
     if (!g || !dist || source >= g->V) return GPMA_EINVAL;
     if (!g->bfs_q0) {
-        if (dev_alloc(&g->bfs_q0, g->V) || dev_alloc(&g->bfs_q1, g->V)) {
-            dev_free(g->bfs_q0); dev_free(g->bfs_q1);
+        int e = GPMA_OK;
+        e |= dev_alloc(&g->bfs_q0, g->V);
+        e |= dev_alloc(&g->bfs_q1, g->V);
+        e |= dev_alloc(&g->bfs_off, g->V);
+        e |= dev_alloc(&g->bfs_tmp, scan_tmp_words(g->V));
+        if (e) {
+            dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
             return GPMA_ENOMEM;
         }
     }
@@ -747,7 +807,11 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
         hipMemsetAsync(g->small + 1, 0, sizeof(uint32_t), s);
         {
             ProfScope ps(g, GPMA_K_BFS, s);
-            launch_bfs_expand(g->slots, g->row_ptr, cur, nfront, level, dist, nxt, g->small + 1, s);
+            // rows of the frontier end to end: lengths, their scan, the expansion
+            launch_bfs_row_len(g->row_ptr, cur, nfront, g->bfs_off, s);
+            scan_u32(g->bfs_off, g->bfs_off, nfront, g->small + 3, g->bfs_tmp, s);
+            launch_bfs_expand(g->slots, g->row_ptr, cur, g->bfs_off, nfront, g->small + 3, g->cap, level,
+                              dist, nxt, g->small + 1, s);
         }
         hipMemcpyAsync(g->small_h, g->small + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);

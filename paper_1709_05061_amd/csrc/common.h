@@ -12,8 +12,9 @@ constexpr uint64_t kEmpty = 0xFFFFFFFFFFFFFFFFull;
 constexpr uint32_t kGuardDst = 0xFFFFFFFFu;
 constexpr int kWave = 64;
 
-// status of one update inside a batch
-enum : uint8_t { kPending = 0, kDone = 1, kNoop = 2 };
+// status of one update inside a batch; kHead marks the first update of a
+// segment that merged (the compaction pass counts merged segments with it)
+enum : uint8_t { kPending = 0, kDone = 1, kNoop = 2, kStateMask = 0x7F, kHead = 0x80 };
 
 // Device-side control block of one batch.  The host reads it back once per
 // level (one small copy) to decide whether to climb further.
@@ -110,10 +111,14 @@ void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max
 
 // keep (key, leaf) pairs whose status is pending; n from *n_dev (<= n_max);
 // the number kept goes to *count_dev and the kept pairs get status pending.
+// Also accumulates the level's statistics into ctl (one atomic per block):
+// applied / dn (+-merged updates), noops, merged segments and their slots
+// (cap_h each).
 void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *status,
                      const uint32_t *n_dev, uint64_t n_max, uint64_t *keys_out,
                      uint32_t *leaf_out, uint8_t *status_out, uint32_t *count_dev,
-                     uint32_t *flags, uint32_t *tmp, hipStream_t s);
+                     uint32_t *flags, uint32_t *tmp, bool del, uint64_t cap_h,
+                     gpma_dev::Ctl *ctl, hipStream_t s);
 
 // stored edges (not empty, not guard) of slots[0..cap) in order
 void compact_edges(const uint64_t *slots, uint64_t cap, uint64_t *out, uint32_t *count_dev,
@@ -147,24 +152,32 @@ void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *c
                      hipStream_t s);
 void launch_leaf_counts_u32(const uint16_t *cnt, uint64_t first_leaf, uint64_t P, uint32_t *out,
                             hipStream_t s);
+// count=true: also add to ctl (used by the root rebuild, after which no
+// compaction pass runs)
 void launch_mark_done(bool del, const uint64_t *keys, uint8_t *status, uint64_t first,
                       uint64_t count, uint32_t *deg, gpma_dev::Ctl *ctl, uint64_t cap_seg,
-                      hipStream_t s);
+                      bool count_stats, hipStream_t s);
 void launch_degrees_from_sorted(const uint64_t *sorted, uint64_t n, uint32_t V, uint32_t *gpos,
                                 uint32_t *deg, hipStream_t s);
 
 // ---- analytics (analytics.hip)
 void launch_pr_prep(const float *x, const uint32_t *deg, uint32_t V, bool uniform,
                     double *contrib, double *y, double *dangling, hipStream_t s);
-void launch_pr_spmv(const uint64_t *slots, uint64_t cap, const double *contrib, double *y,
-                    hipStream_t s);
+void launch_pr_push(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, uint32_t lf_log2,
+                    const double *contrib, double *y, hipStream_t s);
+void launch_pr_pull(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, uint32_t lf_log2,
+                    const double *contrib, double *y, hipStream_t s);
+void launch_transpose_keys(const uint64_t *in, uint64_t n, uint64_t *out, hipStream_t s);
 void launch_pr_combine(const double *y, const double *dangling, uint32_t V, double damping,
                        float *out, hipStream_t s);
 void launch_bfs_init(int32_t *dist, uint32_t V, uint32_t source, uint32_t *queue,
                      uint32_t *qcount, hipStream_t s);
+void launch_bfs_row_len(const uint32_t *row_ptr, const uint32_t *front, uint32_t nfront, uint32_t *len,
+                        hipStream_t s);
 void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uint32_t *front,
-                       uint32_t nfront, int32_t level, int32_t *dist, uint32_t *next,
-                       uint32_t *next_count, hipStream_t s);
+                       const uint32_t *offs, uint32_t nfront, const uint32_t *total, uint64_t max_total,
+                       int32_t level, int32_t *dist, uint32_t *next, uint32_t *next_count,
+                       hipStream_t s);
 void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s);
 void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t *changed,
                     hipStream_t s);

@@ -152,7 +152,6 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
         if (valid) status[i + t] = app ? kPending : kNoop;
         kapp += group_sum<G>(app ? 1u : 0u);
     }
-    if (gl == 0 && k > kapp) atomicAdd((unsigned long long *)&ctl->noops, (unsigned long long)(k - kapp));
     if (kapp == 0) return;
     const bool pass = DEL ? (c >= kapp + min0) : (c + kapp <= max0);
     if (!pass) return;
@@ -188,18 +187,15 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
         slots[base + p] = v;
         if (p < N && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(base + p + 1);
     }
-    if (gl == 0) {
-        cnt[lf_i] = (uint16_t)N;
-        atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)kapp);
-        atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(DEL ? -(int64_t)kapp : (int64_t)kapp));
-        atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)LF);
-        atomicAdd(&ctl->segs, 1u);
-    }
+    if (gl == 0) cnt[lf_i] = (uint16_t)N;
+    // statuses of the run were written by the same lanes in the classify loop
     for (uint32_t t = gl; t < k; t += G) {
-        if (status[i + t] == kPending) {
-            status[i + t] = kDone;
+        uint8_t st = status[i + t];
+        if (st == kPending) {
+            st = kDone;
             atomicAdd(&deg[key_src(keys[i + t])], DEL ? 0xFFFFFFFFu : 1u);
         }
+        status[i + t] = t == 0 ? (uint8_t)(st | kHead) : st;
     }
 }
 
@@ -315,14 +311,8 @@ k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__res
         if (o == 0) cnt[first_leaf + j] = (uint16_t)cj;
     }
     for (uint32_t t = threadIdx.x; t < k; t += blockDim.x) {
-        status[i + t] = kDone;
+        status[i + t] = t == 0 ? (uint8_t)(kDone | kHead) : (uint8_t)kDone;
         atomicAdd(&deg[key_src(U[t])], DEL ? 0xFFFFFFFFu : 1u);
-    }
-    if (threadIdx.x == 0) {
-        atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)k);
-        atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(DEL ? -(int64_t)k : (int64_t)k));
-        atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)cap_h);
-        atomicAdd(&ctl->segs, 1u);
     }
 }
 
@@ -397,13 +387,13 @@ __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t 
 
 __global__ void k_mark_done(bool del, const uint64_t *__restrict__ keys, uint8_t *__restrict__ status,
                             uint64_t first, uint64_t count, uint32_t *__restrict__ deg,
-                            Ctl *__restrict__ ctl, uint64_t cap_seg) {
+                            Ctl *__restrict__ ctl, uint64_t cap_seg, int count_stats) {
     uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) {
-        status[first + t] = kDone;
+        status[first + t] = t == 0 ? (uint8_t)(kDone | kHead) : (uint8_t)kDone;
         atomicAdd(&deg[key_src(keys[first + t])], del ? 0xFFFFFFFFu : 1u);
     }
-    if (t == 0) {
+    if (t == 0 && count_stats) {
         atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)count);
         atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(del ? -(int64_t)count : (int64_t)count));
         atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)cap_seg);
@@ -535,9 +525,9 @@ void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *c
 }
 
 void launch_mark_done(bool del, const uint64_t *keys, uint8_t *status, uint64_t first, uint64_t count,
-                      uint32_t *deg, Ctl *ctl, uint64_t cap_seg, hipStream_t s) {
+                      uint32_t *deg, Ctl *ctl, uint64_t cap_seg, bool count_stats, hipStream_t s) {
     hipLaunchKernelGGL(k_mark_done, dim3((uint32_t)div_up(count ? count : 1, 256)), dim3(256), 0, s,
-                       del, keys, status, first, count, deg, ctl, cap_seg);
+                       del, keys, status, first, count, deg, ctl, cap_seg, count_stats ? 1 : 0);
 }
 
 void launch_degrees_from_sorted(const uint64_t *sorted, uint64_t n, uint32_t V, uint32_t *gpos,

@@ -218,11 +218,47 @@ __global__ void k_scatter_unique(const uint64_t *__restrict__ a, uint64_t n,
     if (i < lim && (i == 0 || a[i] != a[i - 1])) out[pos[i]] = a[i];
 }
 
-__global__ void k_flag_pending(const uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
-                               uint64_t n_max, uint32_t *__restrict__ flags) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_max) return;
-    flags[i] = (i < *n_dev && status[i] == kPending) ? 1u : 0u;
+__global__ void __launch_bounds__(256)
+k_flag_pending(const uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
+               uint64_t n_max, uint32_t *__restrict__ flags, int del, uint64_t cap_h,
+               Ctl *__restrict__ ctl) {
+    __shared__ uint32_t red[3][256 / kWave];
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t done = 0, noop = 0, head = 0;
+    if (i < n_max) {
+        uint32_t f = 0;
+        if (i < *n_dev) {
+            const uint8_t st = status[i];
+            const uint8_t state = st & kStateMask;
+            f = state == kPending;
+            done = state == kDone;
+            noop = state == kNoop;
+            head = (st & kHead) ? 1u : 0u;
+        }
+        flags[i] = f;
+    }
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        done += __shfl_xor(done, d, kWave);
+        noop += __shfl_xor(noop, d, kWave);
+        head += __shfl_xor(head, d, kWave);
+    }
+    const int w = threadIdx.x / kWave;
+    if (__lane_id() == 0) { red[0][w] = done; red[1][w] = noop; red[2][w] = head; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t a = 0, b = 0, c = 0;
+        for (int k = 0; k < 256 / kWave; k++) { a += red[0][k]; b += red[1][k]; c += red[2][k]; }
+        if (a) {
+            atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)a);
+            atomicAdd((unsigned long long *)&ctl->dn, (unsigned long long)(del ? -(int64_t)a : (int64_t)a));
+        }
+        if (b) atomicAdd((unsigned long long *)&ctl->noops, (unsigned long long)b);
+        if (c) {
+            atomicAdd(&ctl->segs, c);
+            atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)(c * cap_h));
+        }
+    }
 }
 
 __global__ void k_scatter_pending(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
@@ -231,7 +267,7 @@ __global__ void k_scatter_pending(const uint64_t *__restrict__ keys, const uint3
                                   const uint32_t *__restrict__ pos, uint64_t *__restrict__ keys_out,
                                   uint32_t *__restrict__ leaf_out, uint8_t *__restrict__ status_out) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_max || i >= *n_dev || status[i] != kPending) return;
+    if (i >= n_max || i >= *n_dev || (status[i] & kStateMask) != kPending) return;
     uint32_t p = pos[i];
     keys_out[p] = keys[i];
     leaf_out[p] = leaf[i];
@@ -333,13 +369,14 @@ void unique_sorted(const uint64_t *in, uint64_t n, uint64_t *out, uint32_t *coun
 void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *status,
                      const uint32_t *n_dev, uint64_t n_max, uint64_t *keys_out, uint32_t *leaf_out,
                      uint8_t *status_out, uint32_t *count_dev, uint32_t *flags, uint32_t *tmp,
-                     hipStream_t s) {
+                     bool del, uint64_t cap_h, Ctl *ctl, hipStream_t s) {
     if (n_max == 0) {
         hipMemsetAsync(count_dev, 0, sizeof(uint32_t), s);
         return;
     }
     uint32_t g = (uint32_t)div_up(n_max, 256);
-    hipLaunchKernelGGL(k_flag_pending, dim3(g), dim3(256), 0, s, status, n_dev, n_max, flags);
+    hipLaunchKernelGGL(k_flag_pending, dim3(g), dim3(256), 0, s, status, n_dev, n_max, flags,
+                       del ? 1 : 0, cap_h, ctl);
     scan_u32(flags, flags, n_max, count_dev, tmp, s);
     hipLaunchKernelGGL(k_scatter_pending, dim3(g), dim3(256), 0, s, keys, leaf, status, n_dev, n_max,
                        flags, keys_out, leaf_out, status_out);

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgpma.so")
 
 GPMA_OK, GPMA_EINVAL, GPMA_ENOMEM, GPMA_EDEVICE = 0, -1, -2, -3
+GPMA_FLAG_MIRROR = 1
 EMPTY = 0xFFFFFFFFFFFFFFFF
 GUARD_DST = 0xFFFFFFFF
 
@@ -77,6 +78,7 @@ def load_library() -> C.CDLL:
         "gpma_export_row_offsets": (C.c_int, [vp, vp, u64, vp]),
         "gpma_export_degrees": (C.c_int, [vp, vp, u64, vp]),
         "gpma_sync": (C.c_int, [vp]),
+        "gpma_get_mirror": (vp, [vp]),
         "gpma_strerror": (C.c_char_p, [C.c_int]),
         "gpma_profile_enable": (C.c_int, [vp, C.c_int]),
         "gpma_profile_reset": (C.c_int, [vp]),
@@ -96,7 +98,7 @@ def exported_symbols() -> List[str]:
             "gpma_delete_batch", "gpma_pagerank", "gpma_bfs", "gpma_cc", "gpma_num_edges",
             "gpma_capacity", "gpma_leaf_size", "gpma_num_vertices", "gpma_export_slots",
             "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_row_offsets",
-            "gpma_export_degrees", "gpma_sync", "gpma_strerror", "gpma_profile_enable",
+            "gpma_export_degrees", "gpma_sync", "gpma_get_mirror", "gpma_strerror", "gpma_profile_enable",
             "gpma_profile_reset", "gpma_profile_read"]
 
 
@@ -214,52 +216,13 @@ class BatchStats:
                    st.slots_rewritten)
 
 
-class GPMA:
-    """A GPU PMA holding a dynamic directed graph (one handle of the C ABI)."""
+class _HandleView:
+    """Read-only calls on a handle (exports, introspection)."""
 
-    def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
-                 tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, stream=None):
-        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, 0)
+    def __init__(self, h, V: int):
         self._lib = load_library()
-        self.V = num_vertices
-        self.h = gpma_create(num_vertices, init_keys, p, stream)
-
-    def close(self):
-        if getattr(self, "h", None):
-            gpma_destroy(self.h)
-            self.h = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
-
-    # --- updates
-    def insert(self, keys: torch.Tensor, stream=None, stats=False):
-        st = gpma_insert_batch(self.h, keys, stream, stats)
-        return BatchStats.of(st) if stats else None
-
-    def delete(self, keys: torch.Tensor, stream=None, stats=False):
-        st = gpma_delete_batch(self.h, keys, stream, stats)
-        return BatchStats.of(st) if stats else None
-
-    # --- analytics
-    def pagerank(self, init: Optional[torch.Tensor] = None, iters: int = 10, damping: float = 0.85,
-                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        if out is None:
-            out = torch.empty(self.V, dtype=torch.float32, device="cuda")
-        return gpma_pagerank(self.h, init, out, iters, damping, stream)
-
-    def bfs(self, source: int, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        if out is None:
-            out = torch.empty(self.V, dtype=torch.int32, device="cuda")
-        return gpma_bfs(self.h, source, out, stream)
-
-    def cc(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        if out is None:
-            out = torch.empty(self.V, dtype=torch.int32, device="cuda")
-        return gpma_cc(self.h, out, stream)
+        self.h = h
+        self.V = V
 
     # --- introspection
     @property
@@ -305,6 +268,61 @@ class GPMA:
         _check(self._lib.gpma_export_degrees(self.h, C.c_void_p(out.data_ptr()), out.numel(),
                                              _stream(stream)), "gpma_export_degrees")
         return out
+
+
+
+class GPMA(_HandleView):
+    """A GPU PMA holding a dynamic directed graph (one handle of the C ABI).
+    mirror=True also keeps the dst-major mirror (GPMA_FLAG_MIRROR)."""
+
+    def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
+                 tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, mirror: bool = False,
+                 stream=None):
+        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root,
+                        GPMA_FLAG_MIRROR if mirror else 0)
+        super().__init__(gpma_create(num_vertices, init_keys, p, stream), num_vertices)
+
+    def close(self):
+        if getattr(self, "h", None):
+            gpma_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def mirror(self):
+        """The dst-major mirror as a read-only view (None without one)."""
+        m = self._lib.gpma_get_mirror(self.h)
+        return _HandleView(C.c_void_p(m), self.V) if m else None
+
+    # --- updates
+    def insert(self, keys: torch.Tensor, stream=None, stats=False):
+        st = gpma_insert_batch(self.h, keys, stream, stats)
+        return BatchStats.of(st) if stats else None
+
+    def delete(self, keys: torch.Tensor, stream=None, stats=False):
+        st = gpma_delete_batch(self.h, keys, stream, stats)
+        return BatchStats.of(st) if stats else None
+
+    # --- analytics
+    def pagerank(self, init: Optional[torch.Tensor] = None, iters: int = 10, damping: float = 0.85,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.V, dtype=torch.float32, device="cuda")
+        return gpma_pagerank(self.h, init, out, iters, damping, stream)
+
+    def bfs(self, source: int, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.V, dtype=torch.int32, device="cuda")
+        return gpma_bfs(self.h, source, out, stream)
+
+    def cc(self, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.V, dtype=torch.int32, device="cuda")
+        return gpma_cc(self.h, out, stream)
 
     # --- profiling
     def profile(self, enable: bool = True):

@@ -278,3 +278,62 @@ def test_analytics_closed_forms():
     assert list(g.bfs(5).cpu().numpy()) == [-1] * 5 + [0] + [-1] * (V - 6)
     assert list(g.cc().cpu().numpy()) == list(range(V))
     g.close()
+
+
+def transpose(keys: np.ndarray) -> np.ndarray:
+    k = np.asarray(keys, dtype=np.uint64)
+    return (k << np.uint64(32)) | (k >> np.uint64(32))
+
+
+@pytest.mark.parametrize("kind", ["er", "growth"])
+def test_mirror_tracks_every_batch(kind):
+    """The dst-major mirror equals an oracle PMA fed the transposed batches;
+    PageRank pulled over it matches the fp64 oracle."""
+    from paper_1709_05061_amd import GPMA
+    if kind == "er":
+        V, lf = 1 << 12, 32
+        st = synth.er_stream(V, 1 << 15, 1 << 9, 6, seed=21)
+        init = npu64(st.initial())
+        batches = []
+        for t in range(6):
+            d, i = st.slide(t, 1 << 9)
+            batches += [("delete", npu64(d)), ("insert", npu64(i))]
+    else:
+        V, lf = 48, 16
+        rng = np.random.default_rng(8)
+        allk = np.array([(u << 32) | v for u in range(V) for v in range(V)], dtype=np.uint64)
+        rng.shuffle(allk)
+        init = allk[:30]
+        batches = [("insert", allk[30:400]), ("insert", allk[400:1500]), ("delete", allk[:1200]),
+                   ("delete", allk[1200:1490])]
+    g = GPMA(V, dev(init), leaf_size=lf, mirror=True)
+    ref = O.OraclePMA(V, init, lf)
+    mref = O.OraclePMA(V, transpose(init), lf)
+    m = g.mirror()
+    for t, (op, keys) in enumerate(batches):
+        say("mirror", kind, t, op)
+        getattr(g, op)(dev(keys))
+        getattr(ref, op)(keys)
+        getattr(mref, op)(transpose(keys))
+        edges = check_state(g, ref, V)
+        assert np.array_equal(npu64(m.slots()), mref.slots())
+        assert np.array_equal(m.row_offsets().cpu().numpy().astype(np.int64), O.row_offsets(mref.slots(), V))
+        x = g.pagerank(iters=10).cpu().numpy()
+        want = O.pagerank(V, edges, iters=10)
+        assert np.max(np.abs(x - want) / want) < PR_RTOL
+    g.close()
+
+
+def test_pull_and_push_pagerank_agree_on_rmat():
+    from paper_1709_05061_amd import GPMA
+    u = np.unique(npu64(synth.rmat_unique(13, 16 << 13, seed=9)))
+    V = 1 << 13
+    a = GPMA(V, dev(u), mirror=True)
+    b = GPMA(V, dev(u), mirror=False)
+    xa = a.pagerank(iters=10).cpu().numpy()
+    xb = b.pagerank(iters=10).cpu().numpy()
+    want = O.pagerank(V, u, iters=10)
+    assert np.max(np.abs(xa - want) / want) < PR_RTOL
+    assert np.max(np.abs(xb - want) / want) < PR_RTOL
+    a.close()
+    b.close()
