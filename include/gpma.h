@@ -174,7 +174,8 @@ const char *gpma_strerror(int code);
  * every launch of the kernels below with HIP events on the launch stream and
  * accumulates elapsed time, launch count and algorithmic bytes (what the
  * method must move; see the per-kernel notes in the implementation).
- * gpma_profile_read synchronises the events it reads. */
+ * gpma_profile_read synchronises the events it reads; with a mirror, the
+ * mirror's launches are included. */
 enum {
     GPMA_K_SPMV = 0,      /* PageRank push over the slot stream */
     GPMA_K_LEAF_MERGE,    /* level-0 fused probe/check/merge */

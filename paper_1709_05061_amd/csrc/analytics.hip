@@ -165,7 +165,7 @@ __global__ void k_bfs_row_len(const uint32_t *__restrict__ row_ptr, const uint32
 }
 
 __global__ void __launch_bounds__(256)
-k_bfs_expand(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr,
+k_bfs_expand(const uint64_t *__restrict__ slots, uint64_t cap, const uint32_t *__restrict__ row_ptr,
              const uint32_t *__restrict__ front, const uint32_t *__restrict__ offs, uint32_t nfront,
              const uint32_t *__restrict__ total, int32_t level, int32_t *__restrict__ dist,
              uint32_t *__restrict__ next, uint32_t *__restrict__ next_count) {
@@ -181,8 +181,11 @@ k_bfs_expand(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ ro
             if (offs[mid] <= t0) lo = mid; else hi = mid;
         }
         uint32_t i = lo;
+        // slot of concatenation index t in row i: row_ptr[front[i]] + (t - offs[i]),
+        // kept in 64 bits (row starts can precede their concatenation offset)
         uint32_t rend = (i + 1 < nfront) ? offs[i + 1] : T;
-        uint32_t rbase = row_ptr[front[i]] - offs[i];
+        uint64_t rstart = row_ptr[front[i]];
+        uint64_t roff = offs[i];
         for (int q = 0; q < kBfsItems; q++) {
             const uint64_t t = t0 + q;
             bool claim = false;
@@ -191,9 +194,11 @@ k_bfs_expand(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ ro
                 while (t >= rend) {   // next non-empty row (rows have at least a guard)
                     i++;
                     rend = (i + 1 < nfront) ? offs[i + 1] : T;
-                    rbase = row_ptr[front[i]] - offs[i];
+                    rstart = row_ptr[front[i]];
+                    roff = offs[i];
                 }
-                const uint64_t k = slots[rbase + t];
+                const uint64_t p = rstart + (t - roff);
+                const uint64_t k = p < cap ? slots[p] : kEmpty;
                 if (k != kEmpty && !is_guard(k)) {
                     v = key_dst(k);
                     if (__hip_atomic_load(&dist[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0)
@@ -318,7 +323,7 @@ void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uin
                        const uint32_t *offs, uint32_t nfront, const uint32_t *total, uint64_t max_total,
                        int32_t level, int32_t *dist, uint32_t *next, uint32_t *next_count, hipStream_t s) {
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for_stream(max_total, kBfsItems)), dim3(256), 0, s, slots,
-                       row_ptr, front, offs, nfront, total, level, dist, next, next_count);
+                       max_total, row_ptr, front, offs, nfront, total, level, dist, next, next_count);
 }
 
 void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s) {

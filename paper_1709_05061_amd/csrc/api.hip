@@ -842,11 +842,13 @@ int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
 int gpma_profile_enable(gpma_t *g, int enable) {
     if (!g) return GPMA_EINVAL;
     g->prof_on = enable ? 1 : 0;
+    if (g->mir) g->mir->prof_on = g->prof_on;
     return GPMA_OK;
 }
 
 int gpma_profile_reset(gpma_t *g) {
     if (!g) return GPMA_EINVAL;
+    if (g->mir) gpma_profile_reset(g->mir);
     prof_collect(g);
     for (int k = 0; k < GPMA_K_COUNT; k++) {
         g->prof_ms[k] = 0;
@@ -859,9 +861,17 @@ int gpma_profile_reset(gpma_t *g) {
 int gpma_profile_read(gpma_t *g, int kernel, double *ms, uint64_t *launches, double *bytes) {
     if (!g || kernel < 0 || kernel >= GPMA_K_COUNT) return GPMA_EINVAL;
     prof_collect(g);
-    if (ms) *ms = g->prof_ms[kernel];
-    if (launches) *launches = g->prof_n[kernel];
-    if (bytes) *bytes = g->prof_bytes[kernel];
+    double m = g->prof_ms[kernel], by = g->prof_bytes[kernel];
+    uint64_t n = g->prof_n[kernel];
+    if (g->mir) {   // the mirror's update kernels count with the handle's
+        prof_collect(g->mir);
+        m += g->mir->prof_ms[kernel];
+        by += g->mir->prof_bytes[kernel];
+        n += g->mir->prof_n[kernel];
+    }
+    if (ms) *ms = m;
+    if (launches) *launches = n;
+    if (bytes) *bytes = by;
     return GPMA_OK;
 }
 
