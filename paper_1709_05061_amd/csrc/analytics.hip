@@ -3,6 +3,8 @@
 //   PageRank: matrix-based; push over the sorted slot stream, fp64 sums.
 //   BFS:      vertex-centric; rows via the CSR offsets, wave per frontier row.
 //   CC:       edge-centric; hooking over the slot stream + pointer jumping.
+#include <algorithm>
+
 #include "common.h"
 
 using namespace gpma_dev;
@@ -11,6 +13,16 @@ namespace {
 
 inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
+// slot streams are read once per pass: non-temporal loads keep them from
+// evicting the vectors the pass gathers from (contributions, labels, dist)
+__device__ __forceinline__ uint64_t ld_stream(const uint64_t *p) {
+    return __builtin_nontemporal_load(p);
+}
+__device__ __forceinline__ void ld_stream2(const uint64_t *p, uint64_t &a, uint64_t &b) {
+    a = __builtin_nontemporal_load(p);
+    b = __builtin_nontemporal_load(p + 1);
+}
+
 // ---------------------------------------------------------------------------
 // PageRank: x'[v] = (1-d)/V + d * (sum_{u->v} x[u]/outdeg(u) + D/V)
 
@@ -18,20 +30,20 @@ __global__ void __launch_bounds__(256)
 k_pr_prep(const float *__restrict__ x, const uint32_t *__restrict__ deg, uint32_t V, int uniform,
           double *__restrict__ contrib, double *__restrict__ y, double *__restrict__ dangling) {
     __shared__ double part[256 / kWave];
-    uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     double dm = 0.0;
-    if (v < V) {
-        double xv = uniform ? 1.0 / (double)V : (double)x[v];
-        uint32_t dv = deg[v];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < V; v += stride) {
+        const double xv = uniform ? 1.0 / (double)V : (double)x[v];
+        const uint32_t dv = deg[v];
         contrib[v] = dv ? xv / (double)dv : 0.0;
-        if (!dv) dm = xv;
+        if (!dv) dm += xv;
         y[v] = 0.0;
     }
 #pragma unroll
     for (int d = kWave / 2; d >= 1; d >>= 1) dm += __shfl_xor(dm, d, kWave);
     if (__lane_id() == 0) part[threadIdx.x / kWave] = dm;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) {   // one atomic per block; the grid is bounded
         double t = 0.0;
         for (int w = 0; w < 256 / kWave; w++) t += part[w];
         if (t != 0.0) unsafeAtomicAdd(dangling, t);
@@ -52,13 +64,8 @@ k_pr_push(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, 
         const uint32_t o = (uint32_t)(p & lfm);
         if (o >= c) continue;
         uint64_t k0, k1 = kEmpty;
-        if (o + 1 < c) {
-            const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(slots + p);
-            k0 = kk.x;
-            k1 = kk.y;
-        } else {
-            k0 = slots[p];
-        }
+        if (o + 1 < c) ld_stream2(slots + p, k0, k1);
+        else k0 = ld_stream(slots + p);
         if (!is_guard(k0)) unsafeAtomicAdd(&y[key_dst(k0)], contrib[key_src(k0)]);
         if (k1 != kEmpty && !is_guard(k1)) unsafeAtomicAdd(&y[key_dst(k1)], contrib[key_src(k1)]);
     }
@@ -71,55 +78,77 @@ k_pr_push(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, 
 // run; a run wholly inside the wave is a complete row and is stored, a run
 // touching either end of the wave may continue in a neighbour and is added
 // atomically (y is zeroed beforehand).  At most two atomics per wave.
+struct PullLane {
+    uint32_t r0, r1;   // rows of the lane's two slots (kNone past the end)
+    double a, b;       // their contributions (0 for gaps and guards)
+};
+
+__device__ __forceinline__ PullLane pull_load(const uint64_t *__restrict__ slots,
+                                              const uint16_t *__restrict__ cnt, uint64_t cap,
+                                              uint32_t lf_log2, const double *__restrict__ contrib,
+                                              uint64_t p) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    PullLane L{kNone, kNone, 0.0, 0.0};
+    if (p >= cap) return L;
+    const uint64_t lfm = (1ull << lf_log2) - 1;
+    const uint64_t leaf = p >> lf_log2;
+    const uint32_t c = cnt[leaf];
+    const uint32_t o = (uint32_t)(p & lfm);
+    uint64_t k0 = kEmpty, k1 = kEmpty;
+    if (o + 1 < c) ld_stream2(slots + p, k0, k1);
+    else if (o < c) k0 = ld_stream(slots + p);
+    uint64_t last = 0;
+    if (o + 1 >= c) last = slots[(leaf << lf_log2) + c - 1];
+    L.r0 = (uint32_t)((o < c ? k0 : last) >> 32);
+    L.r1 = (uint32_t)((o + 1 < c ? k1 : last) >> 32);
+    if (o < c && !is_guard(k0)) L.a = contrib[key_dst(k0)];
+    if (o + 1 < c && !is_guard(k1)) L.b = contrib[key_dst(k1)];
+    return L;
+}
+
+__device__ __forceinline__ void pull_reduce(const PullLane &L, uint32_t lane, double *__restrict__ y) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;
+    double sc = (L.r0 == L.r1) ? L.a + L.b : L.b;   // running sum of the lane's tail run
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const double ys = __shfl_up(sc, d, kWave);
+        const uint32_t yr = __shfl_up(L.r1, d, kWave);
+        if (lane >= (uint32_t)d && yr == L.r1) sc += ys;
+    }
+    const double prev_s = __shfl_up(sc, 1, kWave);
+    const uint32_t prev_r = __shfl_up(L.r1, 1, kWave);
+    const uint32_t next_r0 = __shfl_down(L.r0, 1, kWave);
+    const uint32_t first_row = __shfl(L.r0, 0, kWave);
+    if (L.r0 != L.r1 && L.r0 != kNone) {
+        const double va = L.a + ((lane > 0 && prev_r == L.r0) ? prev_s : 0.0);
+        if (L.r0 == first_row) unsafeAtomicAdd(&y[L.r0], va); else y[L.r0] = va;
+    }
+    if (L.r1 != kNone && (lane == kWave - 1 || next_r0 != L.r1)) {
+        if (L.r1 == first_row || lane == kWave - 1) unsafeAtomicAdd(&y[L.r1], sc); else y[L.r1] = sc;
+    }
+}
+
+// Pull over the dst-major mirror: entry v<<32|u adds contrib[u] to y[v].  A
+// wave takes chunks of 128 consecutive slots (2 per lane), two chunks at a
+// time so each lane has four contribution gathers in flight.  Along the
+// array the row v is non-decreasing; a gap takes the row of its leaf's last
+// entry, so a chunk holds runs of equal rows.  A segmented inclusive scan
+// over the lanes sums each run; a run wholly inside the chunk is a complete
+// row and is stored, a run touching either end of the chunk may continue in
+// a neighbour and is added atomically (y is zeroed beforehand).  At most two
+// atomics per chunk.
 __global__ void __launch_bounds__(256)
 k_pr_pull(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint64_t cap,
           uint32_t lf_log2, const double *__restrict__ contrib, double *__restrict__ y) {
     const uint32_t lane = __lane_id();
-    const uint64_t lfm = (1ull << lf_log2) - 1;
     const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
     const uint64_t nwaves = (uint64_t)gridDim.x * blockDim.x / kWave;
-    constexpr uint32_t kNone = 0xFFFFFFFFu;
-    for (uint64_t base = wave * 2 * kWave; base < cap; base += nwaves * 2 * kWave) {
-        const uint64_t p = base + 2 * lane;
-        uint32_t r0 = kNone, r1 = kNone;
-        double a = 0.0, b = 0.0;
-        if (p < cap) {
-            const uint64_t leaf = p >> lf_log2;
-            const uint32_t c = cnt[leaf];
-            const uint32_t o = (uint32_t)(p & lfm);
-            uint64_t k0 = kEmpty, k1 = kEmpty;
-            if (o + 1 < c) {
-                const ulonglong2 kk = *reinterpret_cast<const ulonglong2 *>(slots + p);
-                k0 = kk.x;
-                k1 = kk.y;
-            } else if (o < c) {
-                k0 = slots[p];
-            }
-            uint64_t last = 0;
-            if (o + 1 >= c) last = slots[(leaf << lf_log2) + c - 1];
-            r0 = (uint32_t)((o < c ? k0 : last) >> 32);
-            r1 = (uint32_t)((o + 1 < c ? k1 : last) >> 32);
-            if (o < c && !is_guard(k0)) a = contrib[key_dst(k0)];
-            if (o + 1 < c && !is_guard(k1)) b = contrib[key_dst(k1)];
-        }
-        double sc = (r0 == r1) ? a + b : b;   // running sum of the lane's tail run
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const double ys = __shfl_up(sc, d, kWave);
-            const uint32_t yr = __shfl_up(r1, d, kWave);
-            if (lane >= (uint32_t)d && yr == r1) sc += ys;
-        }
-        const double prev_s = __shfl_up(sc, 1, kWave);
-        const uint32_t prev_r = __shfl_up(r1, 1, kWave);
-        const uint32_t next_r0 = __shfl_down(r0, 1, kWave);
-        const uint32_t first_row = __shfl(r0, 0, kWave);
-        if (r0 != r1 && r0 != kNone) {
-            const double va = a + ((lane > 0 && prev_r == r0) ? prev_s : 0.0);
-            if (r0 == first_row) unsafeAtomicAdd(&y[r0], va); else y[r0] = va;
-        }
-        if (r1 != kNone && (lane == kWave - 1 || next_r0 != r1)) {
-            if (r1 == first_row || lane == kWave - 1) unsafeAtomicAdd(&y[r1], sc); else y[r1] = sc;
-        }
+    constexpr uint64_t kChunk = 2 * kWave;
+    for (uint64_t base = wave * 2 * kChunk; base < cap; base += nwaves * 2 * kChunk) {
+        const PullLane A = pull_load(slots, cnt, cap, lf_log2, contrib, base + 2 * lane);
+        const PullLane B = pull_load(slots, cnt, cap, lf_log2, contrib, base + kChunk + 2 * lane);
+        pull_reduce(A, lane, y);
+        pull_reduce(B, lane, y);
     }
 }
 
@@ -217,6 +246,47 @@ k_bfs_expand(const uint64_t *__restrict__ slots, uint64_t cap, const uint32_t *_
     }
 }
 
+// Bottom-up step over the dst-major mirror, whose row v lists the in-edges
+// of v: a thread per vertex; an unvisited v scans its in-edges and stops at
+// the first u on the current level, then joins the next level.  Only the
+// thread of v writes dist[v], so no CAS is needed; a u claimed during this
+// step has dist[u] = level+1 and is correctly not taken as a parent.  Used
+// for large frontiers (most unvisited vertices then find a parent within a
+// few in-edges).
+__global__ void __launch_bounds__(256)
+k_bfs_bottom_up(const uint64_t *__restrict__ mslots, const uint32_t *__restrict__ mrow, uint32_t V,
+                int32_t level, int32_t *__restrict__ dist, uint32_t *__restrict__ next,
+                uint32_t *__restrict__ next_count) {
+    const uint32_t lane = __lane_id();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t v0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v0 < V + 0ull; v0 += stride) {
+        const uint32_t v = (uint32_t)v0;
+        bool claim = false;
+        if (dist[v] < 0) {
+            const uint32_t end = mrow[v + 1];
+            for (uint32_t p = mrow[v]; p < end; p++) {
+                const uint64_t k = mslots[p];
+                if (k == kEmpty) continue;
+                if (is_guard(k)) break;
+                const uint32_t u = (uint32_t)k;
+                if (__hip_atomic_load(&dist[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == level) {
+                    claim = true;
+                    break;
+                }
+            }
+            if (claim) __hip_atomic_store(&dist[v], level + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        const uint64_t m = __ballot(claim);
+        if (m) {
+            const uint32_t leader = __ffsll((unsigned long long)m) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(next_count, (uint32_t)__popcll(m));
+            base = __shfl(base, leader, kWave);
+            if (claim) next[base + __popcll(m & lanemask_lt())] = v;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // CC: parent pointers only ever decrease (atomicMin of a root onto a smaller
 // root), so every tree's root is its smallest vertex and find() terminates.
@@ -240,7 +310,7 @@ k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uin
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     bool any = false;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
-        uint64_t k = slots[p];
+        uint64_t k = ld_stream(slots + p);
         if (k == kEmpty || is_guard(k)) continue;
         uint32_t a = cc_find(label, key_src(k));
         uint32_t b = cc_find(label, key_dst(k));
@@ -273,8 +343,9 @@ namespace gpma_host {
 void launch_pr_prep(const float *x, const uint32_t *deg, uint32_t V, bool uniform, double *contrib,
                     double *y, double *dangling, hipStream_t s) {
     hipMemsetAsync(dangling, 0, sizeof(double), s);
-    hipLaunchKernelGGL(k_pr_prep, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, x, deg, V,
-                       uniform ? 1 : 0, contrib, y, dangling);
+    const uint32_t blocks = (uint32_t)std::min<uint64_t>(div_up(V, 256), 1024);
+    hipLaunchKernelGGL(k_pr_prep, dim3(blocks), dim3(256), 0, s, x, deg, V, uniform ? 1 : 0, contrib,
+                       y, dangling);
 }
 
 void launch_pr_push(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, uint32_t lf_log2,
@@ -285,7 +356,7 @@ void launch_pr_push(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, ui
 
 void launch_pr_pull(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, uint32_t lf_log2,
                     const double *contrib, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_pr_pull, dim3(grid_for_stream(cap, 2)), dim3(256), 0, s, slots, cnt, cap,
+    hipLaunchKernelGGL(k_pr_pull, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cnt, cap,
                        lf_log2, contrib, y);
 }
 
@@ -324,6 +395,12 @@ void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uin
                        int32_t level, int32_t *dist, uint32_t *next, uint32_t *next_count, hipStream_t s) {
     hipLaunchKernelGGL(k_bfs_expand, dim3(grid_for_stream(max_total, kBfsItems)), dim3(256), 0, s, slots,
                        max_total, row_ptr, front, offs, nfront, total, level, dist, next, next_count);
+}
+
+void launch_bfs_bottom_up(const uint64_t *mslots, const uint32_t *mrow, uint32_t V, int32_t level,
+                          int32_t *dist, uint32_t *next, uint32_t *next_count, hipStream_t s) {
+    hipLaunchKernelGGL(k_bfs_bottom_up, dim3(grid_for_stream(V, 1)), dim3(256), 0, s, mslots, mrow, V,
+                       level, dist, next, next_count);
 }
 
 void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s) {

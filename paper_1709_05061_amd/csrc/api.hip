@@ -807,11 +807,16 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
         hipMemsetAsync(g->small + 1, 0, sizeof(uint32_t), s);
         {
             ProfScope ps(g, GPMA_K_BFS, s);
-            // rows of the frontier end to end: lengths, their scan, the expansion
-            launch_bfs_row_len(g->row_ptr, cur, nfront, g->bfs_off, s);
-            scan_u32(g->bfs_off, g->bfs_off, nfront, g->small + 3, g->bfs_tmp, s);
-            launch_bfs_expand(g->slots, g->row_ptr, cur, g->bfs_off, nfront, g->small + 3, g->cap, level,
-                              dist, nxt, g->small + 1, s);
+            if (g->mir && (uint64_t)nfront * 64 >= g->V) {
+                // large frontier: bottom-up over the in-edges (mirror)
+                launch_bfs_bottom_up(g->mir->slots, g->mir->row_ptr, g->V, level, dist, nxt, g->small + 1, s);
+            } else {
+                // rows of the frontier end to end: lengths, their scan, the expansion
+                launch_bfs_row_len(g->row_ptr, cur, nfront, g->bfs_off, s);
+                scan_u32(g->bfs_off, g->bfs_off, nfront, g->small + 3, g->bfs_tmp, s);
+                launch_bfs_expand(g->slots, g->row_ptr, cur, g->bfs_off, nfront, g->small + 3, g->cap,
+                                  level, dist, nxt, g->small + 1, s);
+            }
         }
         hipMemcpyAsync(g->small_h, g->small + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
         hipStreamSynchronize(s);

@@ -97,9 +97,10 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev
 // key (src << dbits) | dst', where dst' = dst, or V for a guard.  Result in
 // *out (one of buf_a/buf_b); `in` is not modified.  tmp: radix_tmp_words(n).
 size_t radix_tmp_words(uint64_t n);
+// n_dev (optional): the actual count, on the device (<= n, which sizes grids)
 const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
                                 uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
-                                hipStream_t s);
+                                hipStream_t s, const uint32_t *n_dev = nullptr);
 
 // unique of a sorted array: out receives the distinct keys, *count_dev their
 // number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).
@@ -126,7 +127,7 @@ void compact_edges(const uint64_t *slots, uint64_t cap, uint64_t *out, uint32_t 
 
 // ---- PMA kernels (pma.hip)
 void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, gpma_dev::Ctl *ctl,
-                     hipStream_t s);
+                     hipStream_t s, const uint32_t *n_dev = nullptr);
 void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s);
 void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max,
                    const uint64_t *slots, uint64_t L, uint32_t lf, const gpma_dev::Ctl *ctl,
@@ -178,6 +179,8 @@ void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uin
                        const uint32_t *offs, uint32_t nfront, const uint32_t *total, uint64_t max_total,
                        int32_t level, int32_t *dist, uint32_t *next, uint32_t *next_count,
                        hipStream_t s);
+void launch_bfs_bottom_up(const uint64_t *mslots, const uint32_t *mrow, uint32_t V, int32_t level,
+                          int32_t *dist, uint32_t *next, uint32_t *next_count, hipStream_t s);
 void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s);
 void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t *changed,
                     hipStream_t s);

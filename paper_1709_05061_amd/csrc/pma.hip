@@ -23,9 +23,10 @@ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------------------
 // batch validation: every key needs src < V and dst < V
 
-__global__ void k_validate(const uint64_t *__restrict__ keys, uint64_t n, uint32_t V,
-                           Ctl *__restrict__ ctl) {
+__global__ void k_validate(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t *__restrict__ n_dev,
+                           uint32_t V, Ctl *__restrict__ ctl) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n_dev && *n_dev < n) n = *n_dev;
     bool bad = false;
     if (i < n) {
         uint64_t k = keys[i];
@@ -241,18 +242,16 @@ __device__ __forceinline__ void block_scan_counts(uint32_t *v, uint32_t P, uint3
     *total = carry;
 }
 
+// One segment of the workgroup tier (head update i).  Block-uniform control
+// flow: every early return is taken by the whole workgroup.
 template <bool DEL>
-__global__ void __launch_bounds__(kSegThreads)
-k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
-            uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
-            uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
-            uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t lf_log2,
-            uint64_t minh, uint64_t maxh, Ctl *__restrict__ ctl) {
-    extern __shared__ uint64_t dyn[];
-    __shared__ uint32_t s_misc[kSegThreads / kWave + 4];
-    const uint32_t n = *n_dev;
-    const uint32_t i = blockIdx.x;
-    if (i >= n || ctl->err) return;
+__device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h,
+                                              const uint64_t *__restrict__ keys,
+                                              const uint32_t *__restrict__ leaf,
+                                              uint8_t *__restrict__ status, uint64_t *__restrict__ slots,
+                                              uint16_t *__restrict__ cnt, uint32_t *__restrict__ row_ptr,
+                                              uint32_t *__restrict__ deg, uint32_t lf_log2, uint64_t minh,
+                                              uint64_t maxh, uint64_t *dyn, uint32_t *s_misc) {
     const uint32_t s = leaf[i] >> h;
     if (i > 0 && (leaf[i - 1] >> h) == s) return;
     const uint32_t e = run_end(leaf, i, n, s, h);
@@ -314,6 +313,22 @@ k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__res
         status[i + t] = t == 0 ? (uint8_t)(kDone | kHead) : (uint8_t)kDone;
         atomicAdd(&deg[key_src(U[t])], DEL ? 0xFFFFFFFFu : 1u);
     }
+}
+
+template <bool DEL>
+__global__ void __launch_bounds__(kSegThreads)
+k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+            uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
+            uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+            uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t lf_log2,
+            uint64_t minh, uint64_t maxh, Ctl *__restrict__ ctl) {
+    extern __shared__ uint64_t dyn[];
+    __shared__ uint32_t s_misc[kSegThreads / kWave + 4];
+    const uint32_t n = *n_dev;
+    if (ctl->err) return;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) seg_merge_one<DEL>(i, n, h, keys, leaf, status, slots,
+                                                                           cnt, row_ptr, deg, lf_log2, minh,
+                                                                           maxh, dyn, s_misc);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,9 +439,10 @@ uint32_t log2_u32(uint32_t x) {
 
 namespace gpma_host {
 
-void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, Ctl *ctl, hipStream_t s) {
+void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, Ctl *ctl, hipStream_t s,
+                     const uint32_t *n_dev) {
     if (!n) return;
-    hipLaunchKernelGGL(k_validate, dim3((uint32_t)div_up(n, 256)), dim3(256), 0, s, keys, n, V, ctl);
+    hipLaunchKernelGGL(k_validate, dim3((uint32_t)div_up(n, 256)), dim3(256), 0, s, keys, n, n_dev, V, ctl);
 }
 
 void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s) {
@@ -483,12 +499,13 @@ void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t
                       uint64_t maxh, Ctl *ctl, hipStream_t s) {
     if (!n_max) return;
     size_t lds = seg_merge_lds_bytes(lf, h);
+    const uint32_t grid = (uint32_t)(n_max < 4096 ? n_max : 4096);
     if (del)
-        hipLaunchKernelGGL(k_seg_merge<true>, dim3((uint32_t)n_max), dim3(kSegThreads), lds, s, h,
+        hipLaunchKernelGGL(k_seg_merge<true>, dim3(grid), dim3(kSegThreads), lds, s, h,
                            keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,
                            maxh, ctl);
     else
-        hipLaunchKernelGGL(k_seg_merge<false>, dim3((uint32_t)n_max), dim3(kSegThreads), lds, s, h,
+        hipLaunchKernelGGL(k_seg_merge<false>, dim3(grid), dim3(kSegThreads), lds, s, h,
                            keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,
                            maxh, ctl);
 }

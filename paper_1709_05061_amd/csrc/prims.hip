@@ -14,9 +14,13 @@ constexpr int kScanTile = kScanThreads * kScanItems;   // 2048
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kSortChunks = 16;                          // 64-key chunks per wave
-constexpr int kSortTile = kSortThreads * kSortChunks;    // 4096
-constexpr int kSortWaveSpan = kWave * kSortChunks;       // 1024
+// 64-key chunks per wave: 16 (4096-key tiles) for large inputs, 4 (1024-key
+// tiles) for batches, so a 2^16-key batch still spreads over 64 workgroups
+constexpr int kChunksLarge = 16;
+constexpr int kChunksSmall = 4;
+constexpr uint64_t kSmallSortMax = 1ull << 20;
+constexpr uint64_t kFuseTiles = 64;
+constexpr uint64_t kScanSingleMax = 1ull << 16;
 
 inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
@@ -81,6 +85,26 @@ k_scan_top(uint32_t *__restrict__ sums, uint64_t ntiles, uint32_t *__restrict__ 
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// small inputs: one workgroup, each thread owns a contiguous run of items
+__global__ void __launch_bounds__(1024)
+k_scan_single(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, uint64_t n,
+              uint32_t *__restrict__ total) {
+    __shared__ uint32_t lds[1024 / kWave + 1];
+    const uint64_t per = (n + blockDim.x - 1) / blockDim.x;
+    const uint64_t b = (uint64_t)threadIdx.x * per;
+    const uint64_t e = b + per < n ? b + per : n;
+    uint32_t s = 0;
+    for (uint64_t i = b; i < e; i++) s += in[i];
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(s, &tot, lds);
+    for (uint64_t i = b; i < e; i++) {
+        const uint32_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_apply(const uint32_t *__restrict__ in, uint32_t *__restrict__ out, uint64_t n,
              const uint32_t *__restrict__ tile_offs) {
@@ -120,15 +144,18 @@ struct DigitMap {
     }
 };
 
+template <int CH>
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, uint32_t ntiles,
-                uint32_t *__restrict__ counts) {
+k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t *__restrict__ n_dev,
+                DigitMap dm, uint32_t ntiles, uint32_t *__restrict__ counts) {
+    constexpr int kSortTile = kSortThreads * CH;
+    if (n_dev && *n_dev < n) n = *n_dev;
     __shared__ uint32_t hist[256];
     for (int i = threadIdx.x; i < 256; i += kSortThreads) hist[i] = 0;
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * kSortTile;
 #pragma unroll 4
-    for (int i = 0; i < kSortChunks; i++) {
+    for (int i = 0; i < CH; i++) {
         uint64_t idx = base + (uint64_t)i * kSortThreads + threadIdx.x;
         if (idx < n) atomicAdd(&hist[dm(keys[idx])], 1u);
     }
@@ -142,10 +169,15 @@ k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, uint
 // each other with one ballot per digit bit, so the rank of a key among equal
 // digits is (keys of that digit in earlier chunks) + (lower lanes in this
 // chunk).  Per-wave digit counts are then prefixed across waves.
+template <int CH>
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_downsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, uint32_t bits,
-                  uint32_t ntiles, const uint32_t *__restrict__ offs,
-                  uint64_t *__restrict__ out) {
+k_radix_downsweep(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t *__restrict__ n_dev,
+                  DigitMap dm, uint32_t bits, uint32_t ntiles, const uint32_t *__restrict__ offs,
+                  int fuse_offsets, uint64_t *__restrict__ out) {
+    if (n_dev && *n_dev < n) n = *n_dev;
+    constexpr int kSortChunks = CH;
+    constexpr int kSortTile = kSortThreads * CH;
+    constexpr int kSortWaveSpan = kWave * CH;
     __shared__ uint32_t wcnt[kSortWaves][256];
     __shared__ uint32_t goff[256];
     const int lane = threadIdx.x & (kWave - 1);
@@ -177,6 +209,32 @@ k_radix_downsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, ui
         wave_lds_sync();
     }
     __syncthreads();
+    if (fuse_offsets) {
+        // few tiles: derive this tile's digit offsets from the raw counts
+        // (digits below d over all tiles, plus digit d in earlier tiles)
+        __shared__ uint32_t dtot[257];
+        for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) {
+            uint32_t tot = 0, before = 0;
+            for (uint32_t t = 0; t < ntiles; t++) {
+                uint32_t c = offs[(uint64_t)d * ntiles + t];
+                tot += c;
+                if (t < blockIdx.x) before += c;
+            }
+            dtot[d] = tot;
+            goff[d] = before;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (uint32_t d = 0; d <= dm.mask; d++) {
+                uint32_t t = dtot[d];
+                dtot[d] = run;
+                run += t;
+            }
+        }
+        __syncthreads();
+        for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) goff[d] += dtot[d];
+    }
     for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) {
         uint32_t run = 0;
 #pragma unroll
@@ -185,7 +243,7 @@ k_radix_downsweep(const uint64_t *__restrict__ keys, uint64_t n, DigitMap dm, ui
             wcnt[ww][d] = run;
             run += t;
         }
-        goff[d] = offs[(uint64_t)d * ntiles + blockIdx.x];
+        if (!fuse_offsets) goff[d] = offs[(uint64_t)d * ntiles + blockIdx.x];
     }
     __syncthreads();
 #pragma unroll
@@ -223,17 +281,18 @@ k_flag_pending(const uint8_t *__restrict__ status, const uint32_t *__restrict__ 
                uint64_t n_max, uint32_t *__restrict__ flags, int del, uint64_t cap_h,
                Ctl *__restrict__ ctl) {
     __shared__ uint32_t red[3][256 / kWave];
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = *n_dev;
     uint32_t done = 0, noop = 0, head = 0;
-    if (i < n_max) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_max; i += stride) {
         uint32_t f = 0;
-        if (i < *n_dev) {
+        if (i < n) {
             const uint8_t st = status[i];
             const uint8_t state = st & kStateMask;
             f = state == kPending;
-            done = state == kDone;
-            noop = state == kNoop;
-            head = (st & kHead) ? 1u : 0u;
+            done += state == kDone;
+            noop += state == kNoop;
+            head += (st & kHead) ? 1u : 0u;
         }
         flags[i] = f;
     }
@@ -302,6 +361,10 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev
         if (total_dev) hipMemsetAsync(total_dev, 0, sizeof(uint32_t), s);
         return;
     }
+    if (n <= kScanSingleMax) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev);
+        return;
+    }
     uint64_t ntiles = div_up(n, kScanTile);
     hipLaunchKernelGGL(k_scan_reduce, dim3((uint32_t)ntiles), dim3(kScanThreads), 0, s, in, n, tmp);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, ntiles, total_dev);
@@ -309,8 +372,12 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev
                        tmp);
 }
 
+static uint64_t sort_tile(uint64_t n) {
+    return (uint64_t)kSortThreads * (n <= kSmallSortMax ? kChunksSmall : kChunksLarge);
+}
+
 size_t radix_tmp_words(uint64_t n) {
-    uint64_t ntiles = div_up(n ? n : 1, kSortTile);
+    uint64_t ntiles = div_up(n ? n : 1, sort_tile(n));
     uint64_t m = 256 * ntiles;
     return m + scan_tmp_words(m);
 }
@@ -323,13 +390,14 @@ static uint32_t bit_width(uint64_t x) {
 
 const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
                                 uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
-                                hipStream_t s) {
+                                hipStream_t s, const uint32_t *n_dev) {
     (void)bit_width;
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
     uint32_t passes = (total + 7) / 8;
     uint32_t bits = (total + passes - 1) / passes;
-    uint64_t ntiles = div_up(n ? n : 1, kSortTile);
+    const bool small = n <= kSmallSortMax;
+    uint64_t ntiles = div_up(n ? n : 1, sort_tile(n));
     uint64_t m = 256 * ntiles;
     uint32_t *counts = tmp;
     uint32_t *stmp = tmp + m;
@@ -338,11 +406,21 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
     for (uint32_t p = 0; p < passes; p++) {
         DigitMap dm{p * bits, (1u << bits) - 1u, dbits, V};
         uint64_t mm = (uint64_t)(dm.mask + 1) * ntiles;
-        hipLaunchKernelGGL(k_radix_upsweep, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, src, n,
-                           dm, (uint32_t)ntiles, counts);
-        scan_u32(counts, counts, mm, nullptr, stmp, s);
-        hipLaunchKernelGGL(k_radix_downsweep, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, src,
-                           n, dm, bits, (uint32_t)ntiles, counts, dst);
+        // up to kFuseTiles tiles the downsweep derives its offsets itself
+        const int fuse = ntiles <= kFuseTiles;
+        if (small) {
+            hipLaunchKernelGGL(k_radix_upsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
+                               s, src, n, n_dev, dm, (uint32_t)ntiles, counts);
+            if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
+            hipLaunchKernelGGL(k_radix_downsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads),
+                               0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
+        } else {
+            hipLaunchKernelGGL(k_radix_upsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
+                               s, src, n, n_dev, dm, (uint32_t)ntiles, counts);
+            if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
+            hipLaunchKernelGGL(k_radix_downsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads),
+                               0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
+        }
         src = dst;
         dst = (dst == buf_a) ? buf_b : buf_a;
     }
@@ -375,7 +453,8 @@ void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *
         return;
     }
     uint32_t g = (uint32_t)div_up(n_max, 256);
-    hipLaunchKernelGGL(k_flag_pending, dim3(g), dim3(256), 0, s, status, n_dev, n_max, flags,
+    const uint32_t gf = g < 64 ? g : 64;   // few blocks: one stats atomic each
+    hipLaunchKernelGGL(k_flag_pending, dim3(gf), dim3(256), 0, s, status, n_dev, n_max, flags,
                        del ? 1 : 0, cap_h, ctl);
     scan_u32(flags, flags, n_max, count_dev, tmp, s);
     hipLaunchKernelGGL(k_scatter_pending, dim3(g), dim3(256), 0, s, keys, leaf, status, n_dev, n_max,

@@ -53,11 +53,11 @@ def check_state(g, ref, V):
     return edges
 
 
-def make(V, init, lf, **kw):
+def make(V, init, lf, mirror=False, **kw):
     from paper_1709_05061_amd import GPMA
     init_np = np.asarray(init.numpy() if isinstance(init, torch.Tensor) else init).view(np.uint64) \
         if len(init) else np.zeros(0, np.uint64)
-    g = GPMA(V, dev(init_np), leaf_size=lf, **kw)
+    g = GPMA(V, dev(init_np), leaf_size=lf, mirror=mirror, **kw)
     ref = O.OraclePMA(V, init_np, lf, **kw)
     return g, ref
 
@@ -233,8 +233,11 @@ def test_empty_repeated_and_noop_batches():
     g.close()
 
 
+@pytest.mark.parametrize("mirror", [False, True])
 @pytest.mark.parametrize("kind", ["er", "rmat"])
-def test_analytics_match_oracle(kind):
+def test_analytics_match_oracle(kind, mirror):
+    """BFS (top-down; with the mirror also bottom-up on large frontiers), CC
+    and PageRank (push; with the mirror pull) against the oracle."""
     if kind == "er":
         V = 3000
         edges_t = synth.er_edges(V, 9000, seed=5)
@@ -242,7 +245,7 @@ def test_analytics_match_oracle(kind):
         u = synth.rmat_unique(12, 16 << 12, seed=6)
         V, edges_t = 1 << 12, u
     e = np.unique(npu64(edges_t))
-    g, _ = make(V, e, 32)
+    g, _ = make(V, e, 32, mirror=mirror)
     for src in (0, 1, V // 2, V - 1):
         assert np.array_equal(g.bfs(src).cpu().numpy(), O.bfs(V, e, src)), src
     assert np.array_equal(g.cc().cpu().numpy().astype(np.uint32), O.cc(V, e))
