@@ -117,6 +117,24 @@ int gpma_insert_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
 int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
                       hipStream_t stream, gpma_stats *stats);
 
+/* Fused batching: apply `count` batches in order (ops[i] = 0 insert, 1
+ * delete; keys_dev[i] device pointers with sizes[i] keys; the three arrays
+ * are host arrays).  The result is the one of the same sequence of
+ * gpma_insert_batch / gpma_delete_batch calls, slot for slot.  Each batch
+ * replays a HIP graph captured once per (size class, operation) that runs
+ * the whole batch with device-side control up to the highest level the
+ * workgroup tier covers; the host synchronises once per call, plus once for
+ * each batch that climbs above those levels (its remaining levels and the
+ * root are then completed on the host-driven path).  Not in the paper; the
+ * answer to its observation that GPMA+ pays for many kernel calls on small
+ * batches.  On an invalid key in batch i, batches before i stay applied,
+ * batch i and later are not, and GPMA_EINVAL is returned; *completed (if
+ * non-NULL) receives the number of batches applied.  `total` (if non-NULL)
+ * receives summed statistics (per-level counts are not filled). */
+int gpma_apply_batches(gpma_t *h, uint32_t count, const uint8_t *ops, const uint64_t *const *keys_dev,
+                       const uint64_t *sizes, hipStream_t stream, gpma_stats *total,
+                       uint32_t *completed);
+
 /* PageRank by power iteration (Section 6.1): exactly `iters` steps of
  *   x'[v] = (1-d)/V + d * ( sum_{u->v} x[u]/outdeg(u) + D/V ),
  * D = sum of x over vertices without out-edges (self-loops count).

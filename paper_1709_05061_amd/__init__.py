@@ -7,4 +7,4 @@ include/gpma.h); this package is its ctypes binding.
 """
 from .gpma import (GPMA, BatchStats, GpmaError, gpma_bfs, gpma_cc, gpma_create,  # noqa: F401
                    gpma_default_params, gpma_delete_batch, gpma_destroy, gpma_insert_batch,
-                   gpma_pagerank, load_library, LIB_PATH)
+                   gpma_pagerank, gpma_apply_batches, load_library, LIB_PATH)

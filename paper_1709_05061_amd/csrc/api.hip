@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "common.h"
+#include "fused.h"
 
 using namespace gpma_dev;
 using namespace gpma_host;
@@ -78,6 +79,30 @@ struct gpma {
     uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *bfs_off = nullptr, *bfs_tmp = nullptr;
     uint32_t *small = nullptr;
     uint32_t *small_h = nullptr;   // pinned
+
+    // fused batching: cached graphs (valid while geom_version is unchanged)
+    struct GraphEntry {
+        hipGraphExec_t exec;
+        uint64_t cls;
+        bool del;
+        uint32_t version;
+        uint64_t *fin_k;
+        uint32_t *fin_l;
+        uint8_t *fin_st;
+        uint32_t *fin_n;
+        uint32_t h_top;
+    };
+    std::vector<GraphEntry> graphs;
+    uint32_t geom_version = 1;
+    hipStream_t cap_stream = nullptr;
+    uint64_t *kS = nullptr;              // staging of the batch being replayed
+    FusedState *fs = nullptr;            // device
+    uint32_t *stop = nullptr;            // device; the mirror uses its primary's
+    uint32_t *cur_n = nullptr;           // device: size of the batch being replayed
+    BatchDesc *desc = nullptr;           // device table of the current chunk
+    BatchOut *outs = nullptr;            // device per-batch results
+    FusedState *fs_h = nullptr;          // pinned mirror of *fs
+    uint32_t *stop_h = nullptr;          // pinned
 
     Device dev;
     int prof_on = 0;
@@ -211,7 +236,15 @@ void prof_collect(gpma *g) {
 // ---------------------------------------------------------------------------
 // scratch management
 
+void drop_graphs(gpma *g) {
+    for (auto &e : g->graphs) hipGraphExecDestroy(e.exec);
+    g->graphs.clear();
+    g->geom_version++;
+}
+
 void free_batch(gpma *g) {
+    drop_graphs(g);
+    dev_free(g->kS);
     dev_free(g->kA); dev_free(g->kB); dev_free(g->kC); dev_free(g->kD);
     dev_free(g->leafA); dev_free(g->leafB); dev_free(g->stA); dev_free(g->stB);
     dev_free(g->flags); dev_free(g->tmp);
@@ -224,6 +257,7 @@ int ensure_batch(gpma *g, uint64_t b) {
     uint64_t c = next_pow2(std::max<uint64_t>(b, 4096));
     size_t tw = std::max(radix_tmp_words(c), scan_tmp_words(c + 1));
     int e = GPMA_OK;
+    e |= dev_alloc(&g->kS, c);
     e |= dev_alloc(&g->kA, c); e |= dev_alloc(&g->kB, c);
     e |= dev_alloc(&g->kC, c); e |= dev_alloc(&g->kD, c);
     e |= dev_alloc(&g->leafA, c); e |= dev_alloc(&g->leafB, c);
@@ -266,7 +300,10 @@ void read_ctl(gpma *g, hipStream_t s) {
     hipStreamSynchronize(s);
 }
 
+void drop_graphs(gpma *g);
+
 void set_geometry(gpma *g, uint64_t cap) {
+    if (g->cap != cap) drop_graphs(g);   // captured graphs hold the old arrays
     g->cap = cap;
     g->L = cap >> g->lf_log2;
     g->H = ilog2(g->L);
@@ -359,6 +396,87 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
     return GPMA_OK;
 }
 
+// Levels h_start .. H-1 and the root for the updates still pending in `cur`
+// (rem of them; g->ctl holds the batch's counters so far).  Shared by the
+// plain path and by the completion of a fused batch that stopped.
+int finish_levels(gpma *g, bool del, LevelArrays cur, uint64_t rem, uint32_t h_start, uint32_t segs_seen,
+                  gpma_stats *st, hipStream_t s) {
+    int e = GPMA_OK;
+    uint64_t lo, hi;
+    hipEvent_t pa = nullptr, pb = nullptr;
+    LevelArrays nxt;
+    auto other = [&](const LevelArrays &c) {
+        LevelArrays o;
+        o.k = (c.k == g->kC) ? g->kD : g->kC;
+        o.l = (c.l == g->leafB) ? g->leafA : g->leafB;
+        o.st = (c.st == g->stB) ? g->stA : g->stB;
+        o.n = (c.n == &g->ctl->lvl[0]) ? &g->ctl->lvl[1] : &g->ctl->lvl[0];
+        return o;
+    };
+    nxt = other(cur);
+
+    // levels h_start .. H-1: ascend with whatever is left
+    for (uint32_t h = h_start; h < g->H && rem > 0; h++) {
+        bounds(g, g->H, h, &lo, &hi);
+        if (seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds) {
+            pa = pb = nullptr;
+            if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
+            launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, rem, g->slots, g->cnt, g->row_ptr,
+                             g->deg, g->lf, lo, hi, g->ctl, s);
+            if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
+        } else {
+            pa = pb = nullptr;
+            e = device_tier_level(g, del, h, cur, rem, lo, hi, s);
+            if (e) return e;
+        }
+        compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags,
+                        g->tmp, del, (uint64_t)g->lf << h, g->ctl, s);
+        read_ctl(g, s);
+        const uint32_t segs_h = g->ctl_h->segs - segs_seen;
+        segs_seen = g->ctl_h->segs;
+        if (pa) g->prof_pending.push_back(Prof{GPMA_K_SEG_MERGE, pa, pb,
+                                               16.0 * (double)(g->lf << h) * segs_h + 12.0 * (double)rem});
+        if (st) {
+            st->segments_merged[h] += segs_h;
+            if (segs_h) st->top_level = (int32_t)h;
+        }
+        rem = (nxt.n == &g->ctl->lvl[0]) ? g->ctl_h->lvl[0] : g->ctl_h->lvl[1];
+        cur = nxt;
+        nxt = other(cur);
+    }
+
+    // the root: absorb in place when the bound holds, else resize
+    bool resized = false;
+    if (rem > 0) {
+        const uint64_t n_now = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+        uint64_t ncap = g->cap;
+        if (!del) {
+            while (n_now + rem > root_hi(g, ncap)) ncap *= 2;
+        } else {
+            const uint64_t left = n_now - rem;
+            while (ncap > g->lf && left < root_lo(g, ncap) && left <= root_hi(g, ncap / 2)) ncap /= 2;
+        }
+        if (ncap > kMaxCap) return GPMA_ENOMEM;
+        const uint32_t Hold = g->H;
+        const uint64_t cap_old = g->cap;
+        e = rebuild_root(g, del, cur.k, cur.st, rem, n_now, ncap, s);
+        if (e) return e;
+        read_ctl(g, s);
+        resized = g->cap != cap_old;
+        if (st) {
+            st->segments_merged[Hold] += 1;
+            st->top_level = (int32_t)Hold;
+        }
+    }
+    g->n = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+    if (st) {
+        st->applied += g->ctl_h->applied;
+        st->slots_rewritten += g->ctl_h->rewritten;
+        st->resized |= resized ? 1 : 0;
+    }
+    return GPMA_OK;
+}
+
 int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t s,
                 gpma_stats *st) {
     if (st) {
@@ -418,80 +536,21 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     }
     uint64_t rem = g->ctl_h->lvl[0];
     std::swap(cur, nxt);
-    nxt.k = (cur.k == g->kC) ? g->kD : g->kC;
-    nxt.l = (cur.l == g->leafB) ? g->leafA : g->leafB;
-    nxt.st = (cur.st == g->stB) ? g->stA : g->stB;
-    nxt.n = (cur.n == &g->ctl->lvl[0]) ? &g->ctl->lvl[1] : &g->ctl->lvl[0];
-
-    // levels 1 .. H-1: ascend with whatever is left
-    for (uint32_t h = 1; h < g->H && rem > 0; h++) {
-        bounds(g, g->H, h, &lo, &hi);
-        if (seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds) {
-            pa = pb = nullptr;
-            if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
-            launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, rem, g->slots, g->cnt, g->row_ptr,
-                             g->deg, g->lf, lo, hi, g->ctl, s);
-            if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
-        } else {
-            pa = pb = nullptr;
-            e = device_tier_level(g, del, h, cur, rem, lo, hi, s);
-            if (e) return e;
-        }
-        compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags,
-                        g->tmp, del, (uint64_t)g->lf << h, g->ctl, s);
-        read_ctl(g, s);
-        const uint32_t segs_h = g->ctl_h->segs - segs_seen;
-        segs_seen = g->ctl_h->segs;
-        if (pa) g->prof_pending.push_back(Prof{GPMA_K_SEG_MERGE, pa, pb,
-                                               16.0 * (double)(g->lf << h) * segs_h + 12.0 * (double)rem});
-        if (st) {
-            st->segments_merged[h] = segs_h;
-            if (segs_h) st->top_level = (int32_t)h;
-        }
-        rem = (nxt.n == &g->ctl->lvl[0]) ? g->ctl_h->lvl[0] : g->ctl_h->lvl[1];
-        std::swap(cur, nxt);
-        nxt.k = (cur.k == g->kC) ? g->kD : g->kC;
-        nxt.l = (cur.l == g->leafB) ? g->leafA : g->leafB;
-        nxt.st = (cur.st == g->stB) ? g->stA : g->stB;
-        nxt.n = (cur.n == &g->ctl->lvl[0]) ? &g->ctl->lvl[1] : &g->ctl->lvl[0];
-    }
-
-    // the root: absorb in place when the bound holds, else resize
-    bool resized = false;
-    if (rem > 0) {
-        const uint64_t n_now = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
-        uint64_t ncap = g->cap;
-        if (!del) {
-            while (n_now + rem > root_hi(g, ncap)) ncap *= 2;
-        } else {
-            const uint64_t left = n_now - rem;
-            while (ncap > g->lf && left < root_lo(g, ncap) && left <= root_hi(g, ncap / 2)) ncap /= 2;
-        }
-        if (ncap > kMaxCap) return GPMA_ENOMEM;
-        const uint32_t Hold = g->H;
-        const uint64_t cap_old = g->cap;
-        e = rebuild_root(g, del, cur.k, cur.st, rem, n_now, ncap, s);
-        if (e) return e;
-        read_ctl(g, s);
-        resized = g->cap != cap_old;
-        if (st) {
-            st->segments_merged[Hold] += 1;
-            st->top_level = (int32_t)Hold;
-        }
-    }
-    g->n = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
-    if (st) {
-        st->applied = g->ctl_h->applied;
-        st->noops = b - g->ctl_h->applied;
-        st->slots_rewritten = g->ctl_h->rewritten;
-        st->resized = resized ? 1 : 0;
-    }
-    return GPMA_OK;
+    e = finish_levels(g, del, cur, rem, 1, segs_seen, st, s);
+    if (st) st->noops = b - st->applied;
+    return e;
 }
 
 void free_all(gpma *g) {
     free_batch(g);
     dev_free(g->tkeys);
+    dev_free(g->fs); dev_free(g->stop); dev_free(g->cur_n); dev_free(g->desc); dev_free(g->outs);
+    if (g->fs_h) hipHostFree(g->fs_h);
+    if (g->stop_h) hipHostFree(g->stop_h);
+    g->fs_h = nullptr;
+    g->stop_h = nullptr;
+    if (g->cap_stream) hipStreamDestroy(g->cap_stream);
+    g->cap_stream = nullptr;
     dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
@@ -506,6 +565,219 @@ void free_all(gpma *g) {
     g->prof_pending.clear();
     for (auto e : g->ev_pool) hipEventDestroy(e);
     g->ev_pool.clear();
+}
+
+// ---------------------------------------------------------------------------
+// fused batching (host side)
+
+constexpr uint32_t kFusedChunk = 4096;   // batches per descriptor table
+
+uint64_t batch_class(uint64_t b) { return next_pow2(std::max<uint64_t>(b, 1024)); }
+
+int ensure_fused(gpma *g) {
+    if (g->fs) return GPMA_OK;
+    int e = GPMA_OK;
+    e |= dev_alloc(&g->fs, 1);
+    e |= dev_alloc(&g->stop, 1);
+    e |= dev_alloc(&g->cur_n, 1);
+    e |= dev_alloc(&g->desc, kFusedChunk);
+    e |= dev_alloc(&g->outs, kFusedChunk);
+    if (hipHostMalloc((void **)&g->fs_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc((void **)&g->stop_h, sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (!e && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
+    return e;
+}
+
+// Enqueue one batch of a fused sequence with device-side control only (no
+// host reads), for batches of at most `cls` keys: fetch, validate, sort,
+// unique, locate, level 0, then levels 1..h_top of the workgroup tier, then
+// finish.  Returns where the pending updates end up.
+void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc, uint32_t *stop,
+                          bool transpose, hipStream_t s, gpma::GraphEntry *ge) {
+    launch_fetch(desc, g->fs, stop, g->kS, g->cur_n, g->ctl, transpose, cls, s);
+    launch_validate(g->kS, cls, g->V, g->ctl, s, g->cur_n);
+    const uint32_t sb = bit_width(g->V - 1);
+    const uint64_t *sorted = radix_sort_keys(g->kS, cls, sb, sb, g->V, g->kA, g->kB, g->tmp, s, g->cur_n);
+    uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
+    LevelArrays cur{ukeys, g->leafA, g->stA, &g->ctl->n_in};
+    LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
+    unique_sorted_dyn(sorted, g->cur_n, cls, ukeys, cur.n, g->flags, g->tmp, s);
+    launch_locate(cur.k, cur.n, cls, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
+    uint64_t lo, hi;
+    bounds(g, g->H, 0, &lo, &hi);
+    launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf, lo,
+                      hi, g->ctl, s);
+    compact_pending(cur.k, cur.l, cur.st, cur.n, cls, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del, g->lf,
+                    g->ctl, s);
+    auto other = [&](const LevelArrays &c) {
+        LevelArrays o;
+        o.k = (c.k == g->kC) ? g->kD : g->kC;
+        o.l = (c.l == g->leafB) ? g->leafA : g->leafB;
+        o.st = (c.st == g->stB) ? g->stA : g->stB;
+        o.n = (c.n == &g->ctl->lvl[0]) ? &g->ctl->lvl[1] : &g->ctl->lvl[0];
+        return o;
+    };
+    cur = nxt;
+    nxt = other(cur);
+    uint32_t h_top = 0;
+    for (uint32_t h = 1; h < g->H && seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds; h++) {
+        bounds(g, g->H, h, &lo, &hi);
+        launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf,
+                         lo, hi, g->ctl, s);
+        compact_pending(cur.k, cur.l, cur.st, cur.n, cls, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del,
+                        (uint64_t)g->lf << h, g->ctl, s);
+        cur = nxt;
+        nxt = other(cur);
+        h_top = h;
+    }
+    launch_finish(g->fs, stop, g->ctl, cur.n, g->outs, s);
+    ge->fin_k = cur.k;
+    ge->fin_l = cur.l;
+    ge->fin_st = cur.st;
+    ge->fin_n = cur.n;
+    ge->h_top = h_top;
+}
+
+gpma::GraphEntry *get_graph(gpma *g, uint64_t cls, bool del, const BatchDesc *desc, uint32_t *stop,
+                            bool transpose) {
+    for (auto &e : g->graphs)
+        if (e.cls == cls && e.del == del && e.version == g->geom_version) return &e;
+    gpma::GraphEntry ge{};
+    ge.cls = cls;
+    ge.del = del;
+    ge.version = g->geom_version;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    enqueue_device_batch(g, del, cls, desc, stop, transpose, g->cap_stream, &ge);
+    if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
+    hipError_t r = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (r != hipSuccess) return nullptr;
+    g->graphs.push_back(ge);
+    return &g->graphs.back();
+}
+
+void read_fused(gpma *g, hipStream_t s) {
+    hipMemcpyAsync(g->fs_h, g->fs, sizeof(FusedState), hipMemcpyDeviceToHost, s);
+}
+
+void reset_fused(gpma *g, uint32_t batch, hipStream_t s) {
+    FusedState z{};
+    z.batch = batch;
+    hipMemcpyAsync(g->fs, &z, sizeof(uint32_t) * 4, hipMemcpyHostToDevice, s);
+    hipStreamSynchronize(s);
+}
+
+// Complete the stopped batch of handle g: restore its control block and run
+// the host-driven levels above the graph's, then the root.
+int complete_stopped(gpma *g, bool del, hipStream_t s, gpma_stats *st) {
+    const gpma::GraphEntry *ge = nullptr;
+    // the entry that ran is any with the batch's class/op; its final arrays
+    // depend only on H and the tier limit, identical across classes
+    for (auto &e : g->graphs)
+        if (e.del == del && e.version == g->geom_version) { ge = &e; break; }
+    if (!ge) return GPMA_EDEVICE;
+    hipMemcpyAsync(g->ctl, &g->fs->snap, sizeof(Ctl), hipMemcpyDeviceToDevice, s);
+    read_ctl(g, s);
+    if (g->ctl_h->err) return GPMA_EINVAL;
+    const uint64_t rem = (ge->fin_n == &g->ctl->lvl[0]) ? g->ctl_h->lvl[0] : g->ctl_h->lvl[1];
+    LevelArrays cur{ge->fin_k, ge->fin_l, ge->fin_st, ge->fin_n};
+    return finish_levels(g, del, cur, rem, ge->h_top + 1, g->ctl_h->segs, st, s);
+}
+
+int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys, const uint64_t *sizes,
+                hipStream_t s, gpma_stats *total, uint32_t *done_out);
+
+}  // namespace
+
+namespace {
+
+// Sum the results of batches [from, to) of handle g into g->n and *total.
+void account(gpma *g, uint32_t from, uint32_t to, hipStream_t s, gpma_stats *total) {
+    if (to <= from) return;
+    std::vector<BatchOut> o(to - from);
+    hipMemcpyAsync(o.data(), g->outs + from, o.size() * sizeof(BatchOut), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    for (auto &x : o) {
+        g->n = (uint64_t)((int64_t)g->n + x.dn);
+        if (total) {
+            total->applied += x.applied;
+            total->noops += x.noops;
+            total->slots_rewritten += x.rewritten;
+        }
+    }
+}
+
+int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys, const uint64_t *sizes,
+                hipStream_t s, gpma_stats *total, uint32_t *done_out) {
+    gpma *m = g->mir;
+    std::vector<BatchDesc> hd(count);
+    for (uint32_t i = 0; i < count; i++) hd[i] = BatchDesc{keys[i], sizes[i]};
+    hipMemcpyAsync(g->desc, hd.data(), count * sizeof(BatchDesc), hipMemcpyHostToDevice, s);
+    hipMemsetAsync(g->stop, 0, sizeof(uint32_t), s);
+    reset_fused(g, 0, s);
+    if (m) reset_fused(m, 0, s);
+    uint32_t next = 0;
+    while (next < count) {
+        for (uint32_t i = next; i < count; i++) {
+            const uint64_t cls = batch_class(sizes[i]);
+            gpma::GraphEntry *ge = get_graph(g, cls, ops[i] != 0, g->desc, g->stop, false);
+            if (!ge) return GPMA_EDEVICE;
+            if (hipGraphLaunch(ge->exec, s) != hipSuccess) return GPMA_EDEVICE;
+            if (m) {
+                gpma::GraphEntry *gm = get_graph(m, cls, ops[i] != 0, g->desc, g->stop, true);
+                if (!gm) return GPMA_EDEVICE;
+                if (hipGraphLaunch(gm->exec, s) != hipSuccess) return GPMA_EDEVICE;
+            }
+        }
+        read_fused(g, s);
+        if (m) read_fused(m, s);
+        hipMemcpyAsync(g->stop_h, g->stop, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
+        const uint32_t bg = g->fs_h->batch, bm = m ? m->fs_h->batch : bg;
+        const bool hg = g->fs_h->halted != 0, hm = m ? m->fs_h->halted != 0 : false;
+        account(g, next, bg, s, total);
+        if (m) account(m, next, bm, s, nullptr);
+        if (!*g->stop_h) {
+            next = count;
+            break;
+        }
+        // one handle stopped at batch b with updates left above the graph's levels
+        const uint32_t b = hg ? bg : bm;
+        const bool del = ops[b] != 0;
+        int e = GPMA_OK;
+        if (hg) {
+            e = complete_stopped(g, del, s, total);
+            if (e) {
+                *done_out = b;
+                return e;
+            }
+            if (total) total->noops += g->ctl_h->noops;
+            if (m) {
+                if (sizes[b] > g->tkeys_cap) {
+                    dev_free(g->tkeys);
+                    g->tkeys_cap = 0;
+                    if (dev_alloc(&g->tkeys, next_pow2(sizes[b]))) return GPMA_ENOMEM;
+                    g->tkeys_cap = next_pow2(sizes[b]);
+                }
+                launch_transpose_keys(keys[b], sizes[b], g->tkeys, s);
+                e = apply_batch(m, g->tkeys, sizes[b], del, s, nullptr);
+            }
+        } else {
+            e = complete_stopped(m, del, s, nullptr);
+        }
+        if (e) {
+            *done_out = b;
+            return e;
+        }
+        hipMemsetAsync(g->stop, 0, sizeof(uint32_t), s);
+        reset_fused(g, b + 1, s);
+        if (m) reset_fused(m, b + 1, s);
+        next = b + 1;
+    }
+    if (m && m->n != g->n) return GPMA_EDEVICE;
+    *done_out = count;
+    return GPMA_OK;
 }
 
 }  // namespace
@@ -698,6 +970,38 @@ int gpma_delete_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s
 }
 
 gpma_t *gpma_get_mirror(gpma_t *g) { return g ? g->mir : nullptr; }
+
+int gpma_apply_batches(gpma_t *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys,
+                       const uint64_t *sizes, hipStream_t s, gpma_stats *total, uint32_t *completed) {
+    if (completed) *completed = 0;
+    if (total) {
+        memset(total, 0, sizeof(*total));
+        total->top_level = -1;
+    }
+    if (!g || (count && (!ops || !keys || !sizes))) return GPMA_EINVAL;
+    uint64_t cmax = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        if (ops[i] > 1 || sizes[i] >= (1ull << 31) || (sizes[i] && !keys[i])) return GPMA_EINVAL;
+        cmax = std::max(cmax, batch_class(sizes[i]));
+        if (total) total->requested += sizes[i];
+    }
+    if (count == 0) return GPMA_OK;
+    int e = ensure_batch(g, cmax);
+    if (!e) e = ensure_fused(g);
+    if (!e && g->mir) e = ensure_batch(g->mir, cmax);
+    if (!e && g->mir) e = ensure_fused(g->mir);
+    if (e) return e;
+    uint32_t done = 0;
+    for (uint32_t c0 = 0; c0 < count; c0 += kFusedChunk) {
+        const uint32_t n = std::min(kFusedChunk, count - c0);
+        uint32_t d = 0;
+        e = apply_chunk(g, n, ops + c0, keys + c0, sizes + c0, s, total, &d);
+        done += d;
+        if (e) break;
+    }
+    if (completed) *completed = done;
+    return e;
+}
 
 uint64_t gpma_num_edges(const gpma_t *g) { return g ? g->n - g->V : 0; }
 uint64_t gpma_capacity(const gpma_t *g) { return g ? g->cap : 0; }

@@ -79,6 +79,8 @@ def load_library() -> C.CDLL:
         "gpma_export_degrees": (C.c_int, [vp, vp, u64, vp]),
         "gpma_sync": (C.c_int, [vp]),
         "gpma_get_mirror": (vp, [vp]),
+        "gpma_apply_batches": (C.c_int, [vp, u32, C.POINTER(C.c_uint8), C.POINTER(vp), C.POINTER(u64), vp,
+                                         C.POINTER(gpma_stats), C.POINTER(u32)]),
         "gpma_strerror": (C.c_char_p, [C.c_int]),
         "gpma_profile_enable": (C.c_int, [vp, C.c_int]),
         "gpma_profile_reset": (C.c_int, [vp]),
@@ -98,7 +100,8 @@ def exported_symbols() -> List[str]:
             "gpma_delete_batch", "gpma_pagerank", "gpma_bfs", "gpma_cc", "gpma_num_edges",
             "gpma_capacity", "gpma_leaf_size", "gpma_num_vertices", "gpma_export_slots",
             "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_row_offsets",
-            "gpma_export_degrees", "gpma_sync", "gpma_get_mirror", "gpma_strerror", "gpma_profile_enable",
+            "gpma_export_degrees", "gpma_sync", "gpma_get_mirror", "gpma_apply_batches", "gpma_strerror",
+            "gpma_profile_enable",
             "gpma_profile_reset", "gpma_profile_read"]
 
 
@@ -168,6 +171,22 @@ def gpma_delete_batch(h, keys: torch.Tensor, stream=None, stats: bool = False):
                                           C.byref(st) if st is not None else None)
     _check(rc, "gpma_delete_batch")
     return st
+
+
+def gpma_apply_batches(h, ops, batches, stream=None):
+    """Fused batching: ops[i] in {0 insert, 1 delete}, batches[i] device key
+    tensors.  Returns (stats, completed)."""
+    n = len(batches)
+    ks = [_dev_u64(b) for b in batches]
+    ops_arr = (C.c_uint8 * max(n, 1))(*[int(o) for o in ops])
+    ptrs = (C.c_void_p * max(n, 1))(*[k.data_ptr() for k in ks])
+    sizes = (C.c_uint64 * max(n, 1))(*[k.numel() for k in ks])
+    st = gpma_stats()
+    done = C.c_uint32()
+    rc = load_library().gpma_apply_batches(h, n, ops_arr, ptrs, sizes, _stream(stream), C.byref(st),
+                                           C.byref(done))
+    _check(rc, "gpma_apply_batches")
+    return st, done.value
 
 
 def gpma_pagerank(h, init: Optional[torch.Tensor], out: torch.Tensor, iters: int = 10,
@@ -306,6 +325,11 @@ class GPMA(_HandleView):
     def delete(self, keys: torch.Tensor, stream=None, stats=False):
         st = gpma_delete_batch(self.h, keys, stream, stats)
         return BatchStats.of(st) if stats else None
+
+    def apply_batches(self, ops, batches, stream=None) -> BatchStats:
+        """Fused batching of a sequence of insert (0) / delete (1) batches."""
+        st, _ = gpma_apply_batches(self.h, ops, batches, stream)
+        return BatchStats.of(st)
 
     # --- analytics
     def pagerank(self, init: Optional[torch.Tensor] = None, iters: int = 10, damping: float = 0.85,

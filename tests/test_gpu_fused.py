@@ -1,0 +1,140 @@
+"""Fused batching (HIP-graph replay of uneven batch sequences) equals the
+plain per-batch path slot for slot, including batches that climb above the
+captured levels and resize the root, graphs replayed many times with eager
+plain batches in between, and the mirror."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def dev(keys):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(keys, dtype=np.uint64)).view(np.int64)).cuda()
+
+
+def npu64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def make_sequence(V, live, n, seed):
+    """n uneven batches (sizes log-uniform 2^3..2^12): inserts of random keys,
+    deletes of live keys plus absent ones; one sorted run and one large
+    insert that forces a resize."""
+    rng = np.random.default_rng(seed)
+    live = set(int(x) for x in live)
+    ops, bs = [], []
+    for t in range(n):
+        size = int(2 ** rng.uniform(3, 12))
+        if t == n // 3:      # sorted run into one corner: climbs levels
+            u = int(rng.integers(0, V))
+            keys = np.array([(u << 32) | v for v in range(V)][:size], np.uint64)
+            op = 0
+        elif t == 2 * n // 3:    # large insert: the root doubles
+            keys = np.array([(int(a) << 32) | int(b) for a, b in
+                             zip(rng.integers(0, V, 4 * len(live) + 64), rng.integers(0, V, 4 * len(live) + 64))],
+                            np.uint64)
+            op = 0
+        elif rng.random() < 0.5 or len(live) < 2 * size:
+            keys = np.array([(int(a) << 32) | int(b) for a, b in
+                             zip(rng.integers(0, V, size), rng.integers(0, V, size))], np.uint64)
+            op = 0
+        else:
+            pool = np.array(sorted(live), np.uint64)
+            keys = np.concatenate([pool[rng.choice(pool.size, size, replace=False)],
+                                   np.array([(int(V - 1) << 32) | int(rng.integers(0, V))], np.uint64)])
+            op = 1
+        keys = np.concatenate([keys, keys[: max(1, keys.size // 10)]])   # repeats
+        if op == 0:
+            live |= set(int(x) for x in keys)
+        else:
+            live -= set(int(x) for x in keys)
+        ops.append(op)
+        bs.append(keys)
+    return ops, bs
+
+
+@pytest.mark.parametrize("mirror", [False, True])
+def test_fused_equals_plain(mirror):
+    from paper_1709_05061_amd import GPMA
+    V, lf = 512, 16
+    init = np.unique(npu64(synth.random_batch(V, 6000, 3)))
+    ops, bs = make_sequence(V, init, 36, seed=5)
+    plain = GPMA(V, dev(init), leaf_size=lf, mirror=mirror)
+    fused = GPMA(V, dev(init), leaf_size=lf, mirror=mirror)
+    ref = O.OraclePMA(V, init, lf)
+    cuts = [0, 5, 6, 20, 36]
+    for c in range(len(cuts) - 1):
+        lo, hi = cuts[c], cuts[c + 1]
+        say("fused call", lo, hi, "mirror", mirror)
+        for i in range(lo, hi):
+            (plain.delete if ops[i] else plain.insert)(dev(bs[i]))
+            (ref.delete if ops[i] else ref.insert)(bs[i])
+        st = fused.apply_batches(ops[lo:hi], [dev(b) for b in bs[lo:hi]])
+        assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
+        assert np.array_equal(npu64(fused.slots()), ref.slots())
+        assert fused.num_edges == plain.num_edges
+        assert np.array_equal(fused.degrees().cpu().numpy(), plain.degrees().cpu().numpy())
+        assert np.array_equal(fused.row_offsets().cpu().numpy(), plain.row_offsets().cpu().numpy())
+        if mirror:
+            assert np.array_equal(npu64(fused.mirror().slots()), npu64(plain.mirror().slots()))
+        # an eager plain batch between graph replays, on both handles
+        extra = npu64(synth.random_batch(V, 37, 100 + c))
+        plain.insert(dev(extra))
+        fused.insert(dev(extra))
+        ref.insert(extra)
+        assert np.array_equal(npu64(fused.slots()), npu64(plain.slots()))
+    plain.close()
+    fused.close()
+
+
+def test_fused_replays_many_batches_same_class():
+    """Many replays of the same cached graphs (one size class)."""
+    from paper_1709_05061_amd import GPMA
+    V = 1 << 12
+    st = synth.er_stream(V, 1 << 15, 700, 24, seed=9)
+    plain = GPMA(V, st.initial().cuda(), leaf_size=32)
+    fused = GPMA(V, st.initial().cuda(), leaf_size=32)
+    ops, bs = [], []
+    for t in range(24):
+        d, i = st.slide(t, 700)
+        d, i = d.cuda(), i.cuda()
+        ops += [1, 0]
+        bs += [d, i]
+        plain.delete(d)
+        plain.insert(i)
+    for rep in range(3):
+        lo, hi = 16 * rep, 16 * (rep + 1)
+        s = fused.apply_batches(ops[lo:hi], bs[lo:hi])
+        assert s.applied == 700 * (hi - lo)
+    assert np.array_equal(npu64(fused.slots()), npu64(plain.slots()))
+    plain.close()
+    fused.close()
+
+
+def test_fused_invalid_key_stops_at_that_batch():
+    from paper_1709_05061_amd import GPMA, GpmaError
+    from paper_1709_05061_amd.gpma import gpma_apply_batches
+    V = 300
+    init = np.unique(npu64(synth.random_batch(V, 2000, 1)))
+    g = GPMA(V, dev(init), leaf_size=16)
+    ref = O.OraclePMA(V, init, 16)
+    good = [npu64(synth.random_batch(V, 50, 10 + i)) for i in range(4)]
+    bad = np.array([(V << 32) | 1], np.uint64)
+    seq = [good[0], good[1], bad, good[2]]
+    with pytest.raises(GpmaError) as ei:
+        gpma_apply_batches(g.h, [0, 0, 0, 0], [dev(b) for b in seq])
+    assert ei.value.code == -1
+    ref.insert(good[0])
+    ref.insert(good[1])
+    assert np.array_equal(npu64(g.slots()), ref.slots())
+    g.close()
