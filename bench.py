@@ -82,6 +82,93 @@ def cpu_baseline(batch: int, slides: int, scale: int = 20):
     }
 
 
+def uneven_section(args):
+    """The fused-batching workload: a power-law social graph (1.6M vertices,
+    30M edges, out-degree exponent 2.1), window = first half, then `n` slides
+    of uneven size (log-uniform 2^6..2^18 each way), leaf size autotuned;
+    fused vs plain update throughput at identical output."""
+    import torch
+
+    import synth
+    from paper_1709_05061_amd import GPMA
+    from paper_1709_05061_amd.autotune import autotune_leaf_size
+    V, m = 1_600_000, 30_000_000
+    e = synth.powerlaw_edges(V, m, seed=args.seed + 20, device="cuda")
+    st = synth.Stream(V, e, e.numel() // 2)
+    sizes = synth.loguniform_sizes(args.uneven_slides, 6, 18, args.seed + 21)
+    ops, bs, pos = [], [], 0
+    for b in sizes:
+        ops += [1, 0]
+        bs += [st.order[pos:pos + b], st.order[st.window + pos: st.window + pos + b]]
+        pos += b
+    tune = autotune_leaf_size(V, st.initial(), ops[:64], bs[:64], mirror=False, cache_path=None)
+    lf = tune["leaf_size"]
+    plain = GPMA(V, st.initial(), leaf_size=lf)
+    fused = GPMA(V, st.initial(), leaf_size=lf)
+    fused.apply_batches(ops[:2], bs[:2])          # captures the first graphs
+    plain.delete(bs[0])
+    plain.insert(bs[1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for o, b in zip(ops[2:], bs[2:]):
+        (plain.delete if o else plain.insert)(b)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sf = fused.apply_batches(ops[2:], bs[2:])
+    torch.cuda.synchronize()
+    t_fused = time.perf_counter() - t0
+    same = bool(torch.equal(plain.slots(), fused.slots()))
+    n_upd = sum(int(b.numel()) for b in bs[2:])
+    out = {"workload": "power-law graph V=1.6M, 30M edges, out-degree exponent 2.1, window 15M; "
+                       "%d slides of log-uniform 2^6..2^18 deletes + inserts" % (len(sizes) - 1),
+           "leaf_size": lf, "autotune_ms": tune["ms"], "updates": n_upd,
+           "plain_updates_per_s": n_upd / t_plain, "fused_updates_per_s": n_upd / t_fused,
+           "fused_speedup": t_plain / t_fused, "identical_output": same, "applied": sf.applied}
+    plain.close()
+    fused.close()
+    return out
+
+
+def service_section(args):
+    """Streaming service on R-MAT scale 22 (window = first half of the
+    distinct edges): Poisson edge arrivals at each rate for `service_s`
+    seconds, continuous batching, BFS and 10-iteration PageRank queries at a
+    Poisson rate, query slots admitted by an HBM budget."""
+    import torch
+
+    import synth
+    from paper_1709_05061_amd.service import GraphService
+    st = synth.rmat_stream(22, 16, seed=args.seed + 30, device="cuda")
+    V = st.V
+    out = {"workload": "R-MAT scale 22 edge factor 16, window %d edges; Poisson arrivals %gs per rate; "
+                       "BFS + PageRank(10) queries at %g/s; HBM budget %d GiB"
+                       % (st.window, args.service_s, args.query_rate, args.service_budget_gib),
+           "rates": {}}
+    pos = st.window
+    for k, rate in enumerate((1e5, 1e6, 1e7)):
+        n = int(rate * args.service_s)
+        n = min(n, st.order.numel() - pos)
+        arrivals = st.order[pos:pos + n]
+        times = synth.poisson_times(n, rate, seed=args.seed + 31 + k)
+        nq = max(4, int(args.query_rate * args.service_s))
+        qt = synth.poisson_times(nq, args.query_rate, seed=args.seed + 41 + k).tolist()
+        kinds = ["bfs" if i % 2 == 0 else "pagerank" for i in range(nq)]
+        srcs = synth.uniform_below(torch.arange(nq), args.seed + 51 + k, V).tolist()
+        qargs = [srcs[i] if kinds[i] == "bfs" else 10 for i in range(nq)]
+        window = st.order[pos - st.window:pos]
+        svc = GraphService(V, window, mirror=True, hbm_budget_bytes=args.service_budget_gib << 30,
+                           max_batch=1 << 18, max_slots=4)
+        rep = svc.run(times, arrivals, qt, kinds, qargs, time_limit_s=60)
+        out["rates"]["%g" % rate] = rep.summary()
+        log("service at %g edges/s: %s" % (rate, rep.summary()))
+        svc.close()
+        del svc
+        torch.cuda.empty_cache()
+        pos += n
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +182,15 @@ def main():
     ap.add_argument("--no-analytics", action="store_true")
     ap.add_argument("--no-mirror", action="store_true",
                     help="no dst-major mirror: PageRank pushes with fp64 atomics")
+    ap.add_argument("--plain", action="store_true", help="time the plain per-batch path as value")
+    ap.add_argument("--no-compare", action="store_true", help="skip the plain-path comparison run")
+    ap.add_argument("--uneven-slides", type=int, default=128)
+    ap.add_argument("--no-uneven", action="store_true")
+    ap.add_argument("--no-service", action="store_true")
+    ap.add_argument("--service-s", type=float, default=1.0)
+    ap.add_argument("--query-rate", type=float, default=40.0)
+    ap.add_argument("--service-budget-gib", type=int, default=16)
+    ap.add_argument("--no-learned", action="store_true", help="binary-search locate in the main path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slides", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
@@ -126,11 +222,50 @@ def main():
     torch.cuda.synchronize()
     log("generated R-MAT s%d: window %d edges, %d fresh arrivals in %.1fs"
         % (args.scale, st.window, st.order.numel() - st.window, time.time() - t0))
+    mirror = not args.no_mirror
+    fused_mode = not args.plain
     t0 = time.time()
-    g = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=not args.no_mirror)
+    learned = not args.no_learned
+    g = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror, learned=learned)
     torch.cuda.synchronize()
     log("created PMA: %d edges, capacity %d slots, leaf %d in %.1fs"
         % (g.num_edges, g.capacity, g.leaf_size, time.time() - t0))
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(stream)
+        return e
+
+    def update(h, t, fused):
+        d, i = st.slide(t, b)
+        if fused:
+            s = h.apply_batches([1, 0], [d, i])
+            return s.applied, int(s.resized)
+        sd = h.delete(d, stats=True)
+        si = h.insert(i, stats=True)
+        return sd.applied + si.applied, int(sd.resized) + int(si.resized)
+
+    # the other update path on a second handle, same slides: throughput and
+    # identical output
+    other = None
+    other_ups = None
+    if not args.no_compare:
+        # the baseline path: plain per-batch calls, binary-search locate
+        other = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror)
+        for t in range(args.warmup):
+            update(other, t, not fused_mode)
+        ms = []
+        n_o = 0
+        for t in range(args.warmup, args.warmup + args.steps):
+            e0 = ev()
+            a, _ = update(other, t, not fused_mode)
+            e1 = ev()
+            n_o += a
+            ms.append((e0, e1))
+        torch.cuda.synchronize()
+        other_ups = n_o / (sum(a.elapsed_time(c) for a, c in ms) / 1e3)
+        log("%s path: %.3g updates/s" % ("plain" if fused_mode else "fused", other_ups))
 
     # BFS sources: vertices with out-edges, drawn with the seeded generator
     deg = g.degrees()
@@ -138,20 +273,11 @@ def main():
     pick = synth.uniform_below(torch.arange(args.warmup + args.steps, device="cuda"), args.seed + 7,
                                cand.numel())
     sources = cand[pick].tolist()
-
-    stream = torch.cuda.current_stream()
     x = torch.full((V,), 1.0 / V, dtype=torch.float32, device="cuda")
 
-    def ev():
-        e = torch.cuda.Event(enable_timing=True)
-        e.record(stream)
-        return e
-
-    def step(t, timed):
-        d, i = st.slide(t, b)
+    def step(t):
         e0 = ev()
-        sd = g.delete(d, stats=True)
-        si = g.insert(i, stats=True)
+        a, r = update(g, t, fused_mode)
         e1 = ev()
         marks = [e0, e1]
         if not args.no_analytics:
@@ -161,10 +287,10 @@ def main():
             marks.append(ev())
             g.cc()
             marks.append(ev())
-        return sd, si, marks
+        return a, r, marks
 
     for t in range(args.warmup):
-        step(t, False)
+        step(t)
     torch.cuda.synchronize()
     g.profile_reset()
     g.profile(True)
@@ -174,9 +300,9 @@ def main():
     torch.cuda.synchronize()
     tw0 = time.perf_counter()
     for t in range(args.warmup, args.warmup + args.steps):
-        sd, si, marks = step(t, True)
-        applied += sd.applied + si.applied
-        resized += int(sd.resized) + int(si.resized)
+        a, r, marks = step(t)
+        applied += a
+        resized += r
         recs.append(marks)
     torch.cuda.synchronize()
     wall = time.perf_counter() - tw0
@@ -190,14 +316,21 @@ def main():
         phases["cc"] = sum(m[3].elapsed_time(m[4]) for m in recs) / len(recs)
     updates_per_s = applied / (sum(upd_ms) / 1e3)
 
+    identical = None
+    if other is not None:
+        identical = bool(torch.equal(g.slots(), other.slots()))
+        if mirror:
+            identical = identical and bool(torch.equal(g.mirror().slots(), other.mirror().slots()))
+        other.close()
+        del other
+
     kernels = {}
     for kid, name in enumerate(G.KERNEL_NAMES):
         ms, n, by = g.profile_read(kid)
         if n:
             kernels[name] = {"launches": n, "mean_us": 1e3 * ms / n, "total_ms": ms,
                              "GBps": (by / (ms / 1e3) / 1e9) if by and ms else None}
-    dom = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
-    dom_name, dom_k = dom
+    dom_name, dom_k = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
     achieved = dom_k["GBps"]
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
@@ -221,20 +354,37 @@ def main():
                                % (args.scale, args.edge_factor, b, b, args.pr_iters),
                    "scale": args.scale, "edge_factor": args.edge_factor, "batch": b,
                    "window_edges": int(st.window), "capacity": g.capacity, "leaf_size": g.leaf_size,
-                   "mirror": not args.no_mirror},
+                   "mirror": mirror, "update_path": "fused" if fused_mode else "plain",
+                   "learned_locator": learned},
         "phases_ms": phases,
         "update_ms_p50": pctl(upd_ms, 50),
         "update_ms_p99": pctl(upd_ms, 99),
         "applied_per_step": applied / args.steps,
         "resizes": resized,
+        ("plain_updates_per_s" if fused_mode else "fused_updates_per_s"): other_ups,
+        "fused_speedup": (updates_per_s / other_ups if fused_mode else other_ups / updates_per_s)
+        if other_ups else None,
+        "identical_output": identical,
         "spmv_GBps": spmv["GBps"] if spmv else None,
         "spmv_frac": (spmv["GBps"] / HBM_PEAK_GBPS) if spmv and spmv["GBps"] else None,
         "kernels": kernels,
         "roofline": roofline,
     }
+    if learned:
+        out["locator"] = g.locator_info()
     g.close()
     del st
     torch.cuda.empty_cache()
+    if not args.no_service:
+        log("streaming service (R-MAT scale 22)")
+        out["service"] = service_section(args)
+        r7 = out["service"]["rates"].get("1e+07") or {}
+        out["stream_latency_ms_p99"] = r7.get("edge_latency_ms_p99")
+        torch.cuda.empty_cache()
+    if not args.no_uneven:
+        log("uneven-batch workload (power-law graph)")
+        out["uneven"] = uneven_section(args)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(b, args.cpu_slides)

@@ -75,6 +75,16 @@ typedef struct {
  * array.  Not in the paper (its SpMV reads a CSR copy); a design addition. */
 #define GPMA_FLAG_MIRROR 1u
 
+/* Learned segment locator: a 2 -> 32 -> 1 MLP over (src/V, dst/V) with a
+ * skip term predicts each update's leaf (layer 2 on MFMA, bf16 weights, fp32
+ * accumulation); an exact search inside the measured error window corrects
+ * it, checked against the window's bracketing pivots, with the full binary
+ * search as fallback, so the leaf (and every later result) is identical to
+ * the binary-search locate of Algorithm "GPMA+ Segment-Oriented
+ * Insertion".  Refitted after every rebuild of the array, every 64 batches,
+ * or when more than 1/16 of a batch's lookups fall back.  A design addition. */
+#define GPMA_FLAG_LEARNED_LOCATOR 2u
+
 /* Per-batch statistics; filled when a non-NULL pointer is passed. */
 typedef struct {
     uint64_t requested;      /* keys passed in */
@@ -154,6 +164,33 @@ int gpma_bfs(gpma_t *h, uint32_t source, int32_t *dist_dev, hipStream_t stream);
 /* Connected components with edge direction ignored (Section 6.1); every
  * vertex gets the smallest vertex id of its component.  label_dev: V uint32. */
 int gpma_cc(gpma_t *h, uint32_t *label_dev, hipStream_t stream);
+
+/* Snapshots for concurrent analytics (the streaming service): a read-only
+ * handle holding device copies of the arrays the analytics read (slots, leaf
+ * counts, row offsets, degrees, and the mirror's), taken in `stream` order,
+ * i.e. of the graph as left by the work enqueued on `stream` before it.
+ * gpma_pagerank / gpma_bfs / gpma_cc / exports work on it (one host thread and
+ * one stream per snapshot at a time); updates return GPMA_EINVAL.  Free with
+ * gpma_destroy.  gpma_snapshot_refresh copies a newer state into an existing
+ * snapshot (reallocating only if the capacity changed).  Not in the paper: it
+ * lets queries on version v overlap the updates that make version v+1. */
+int gpma_snapshot(gpma_t *h, gpma_t **snap_out, hipStream_t stream);
+int gpma_snapshot_refresh(gpma_t *h, gpma_t *snap, hipStream_t stream);
+/* Device bytes of the arrays a snapshot copies (the budget unit of a query). */
+uint64_t gpma_device_bytes(const gpma_t *h);
+
+/* The leaf of each of n keys (BinarySearchLeafSegments: the leaf holding the
+ * greatest stored key <= k, leaf 0 if none), through the learned locator when
+ * the handle has one.  Keys need src < V, dst < V (else GPMA_EINVAL).
+ * leaf_out_dev: n uint32.  Synchronises. */
+int gpma_locate(gpma_t *h, const uint64_t *keys_dev, uint64_t n, uint32_t *leaf_out_dev,
+                hipStream_t stream);
+/* Refit the learned locator now (GPMA_EINVAL without one). */
+int gpma_locator_refit(gpma_t *h, hipStream_t stream);
+/* Learned-locator state: current error window (leaves; all ones when the
+ * model is unusable), lookups and fallbacks so far, number of fits. */
+int gpma_locator_info(const gpma_t *h, uint32_t *eps, uint64_t *lookups, uint64_t *misses,
+                      uint64_t *fits);
 
 /* The mirror of a handle created with GPMA_FLAG_MIRROR, else NULL.  A
  * borrowed handle for the read-only calls below (export, introspection); it

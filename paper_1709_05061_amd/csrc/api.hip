@@ -3,6 +3,7 @@
 // "GPMA+ Segment-Oriented Insertion" and its dual), root resize, and the
 // analytics drivers.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -10,6 +11,7 @@
 
 #include "common.h"
 #include "fused.h"
+#include "locator.h"
 
 using namespace gpma_dev;
 using namespace gpma_host;
@@ -103,6 +105,21 @@ struct gpma {
     BatchOut *outs = nullptr;            // device per-batch results
     FusedState *fs_h = nullptr;          // pinned mirror of *fs
     uint32_t *stop_h = nullptr;          // pinned
+    FusedState *reset_h = nullptr;       // pinned source of state resets
+    BatchDesc *desc_h = nullptr;         // pinned staging of the descriptor table
+    BatchOut *outs_h = nullptr;          // pinned copy of the per-batch results
+
+    bool readonly = false;   // a snapshot: analytics and exports only
+
+    // learned segment locator
+    bool learned = false;
+    LocModel *loc = nullptr;       // device
+    LocModel loc_h{};              // host copy
+    double *loc_gram = nullptr;    // device fp64 normal equations
+    uint32_t *loc_err = nullptr;   // device
+    uint32_t batches_since_fit = 0;
+    uint64_t loc_lookups = 0, loc_misses = 0, loc_fits = 0;
+    uint64_t acc_lookups = 0, acc_misses = 0;   // fused batches since the last check
 
     Device dev;
     int prof_on = 0;
@@ -180,7 +197,7 @@ bool params_valid(const gpma_params *p, bool allow_auto) {
           p->tau_root_pm <= p->tau_leaf_pm && p->tau_leaf_pm < 1000))
         return false;
     if (2 * p->rho_root_pm > p->tau_root_pm) return false;
-    if (p->flags & ~(uint32_t)GPMA_FLAG_MIRROR) return false;
+    if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR)) return false;
     return true;
 }
 
@@ -396,6 +413,134 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
     return GPMA_OK;
 }
 
+
+// ---------------------------------------------------------------------------
+// learned locator: fit and dispatch
+
+void do_locate(gpma *g, const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, uint32_t *leaf,
+               uint8_t *status, hipStream_t s) {
+    if (g->learned && g->loc)
+        launch_locate_learned(keys, n_dev, n_max, g->slots, g->L, g->lf_log2, g->loc, g->ctl, leaf, status,
+                              &g->ctl->misses, s);
+    else
+        launch_locate(keys, n_dev, n_max, g->slots, g->L, g->lf, g->ctl, leaf, status, s);
+}
+
+// Cholesky solve of the (ridge-regularised) n x n normal equations
+bool solve_spd(std::vector<double> &A, std::vector<double> &b, int n) {
+    double tr = 0;
+    for (int i = 0; i < n; i++) tr += A[i * n + i];
+    const double ridge = 1e-12 * (tr / n) + 1e-300;
+    for (int i = 0; i < n; i++) A[i * n + i] += ridge;
+    for (int j = 0; j < n; j++) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; k++) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0)) return false;
+        d = std::sqrt(d);
+        A[j * n + j] = d;
+        for (int i = j + 1; i < n; i++) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; k++) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / d;
+        }
+    }
+    for (int i = 0; i < n; i++) {       // L y = b
+        double v = b[i];
+        for (int k = 0; k < i; k++) v -= A[i * n + k] * b[k];
+        b[i] = v / A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; i--) {  // L^T w = y
+        double v = b[i];
+        for (int k = i + 1; k < n; k++) v -= A[k * n + i] * b[k];
+        b[i] = v / A[i * n + i];
+    }
+    return true;
+}
+
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Fit the model to the current leaf pivots: knots at pivot quantiles, layer 2
+// by least squares on (up to) 2^16 sampled pivots, then the error bound over
+// every pivot with the device inference code.
+int locator_fit(gpma *g, hipStream_t s) {
+    if (!g->loc) {
+        int e = GPMA_OK;
+        e |= dev_alloc(&g->loc, 1);
+        e |= dev_alloc(&g->loc_gram, loc_gram_words());
+        e |= dev_alloc(&g->loc_err, 1);
+        if (e) return GPMA_ENOMEM;
+    }
+    const uint64_t L = g->L;
+    const uint64_t S = std::min<uint64_t>(L, 1u << 16), stride = L / S;
+    // knots: x of 32 evenly spaced pivots
+    uint64_t piv[32];
+    const uint64_t step = L >= 32 ? L / 32 : 1;
+    const uint64_t np = std::min<uint64_t>(32, L);
+    hipMemcpy2DAsync(piv, sizeof(uint64_t), g->slots, (step << g->lf_log2) * sizeof(uint64_t), sizeof(uint64_t),
+                     np, hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    LocModel m{};
+    m.V = g->V;
+    m.inv_v = 1.0f / (float)g->V;
+    m.inv_v1 = 1.0f / (float)((double)g->V + 1.0);
+    m.L = (uint32_t)L;
+    for (int u = 0; u < 31; u++) {
+        const uint64_t k = piv[std::min<uint64_t>((uint64_t)u * np / 31, np - 1)];
+        m.w1x[u] = 1.0f;
+        m.w1y[u] = 0.0f;
+        m.b1[u] = -(float)(k >> 32) * m.inv_v;
+    }
+    m.w1x[31] = 0.0f;
+    m.w1y[31] = 1.0f;
+    m.b1[31] = 0.0f;
+    hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
+    hipMemsetAsync(g->loc_gram, 0, loc_gram_words() * sizeof(double), s);
+    launch_loc_gram(g->slots, L, g->lf_log2, stride, S, g->loc, g->loc_gram, s);
+    std::vector<double> gram(loc_gram_words());
+    hipMemcpyAsync(gram.data(), g->loc_gram, gram.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    const int F = 33;
+    std::vector<double> A(gram.begin(), gram.begin() + F * F), b(gram.begin() + F * F, gram.end());
+    if (!solve_spd(A, b, F)) {
+        g->loc_h = m;   // invalid: every lookup falls back
+        return GPMA_OK;
+    }
+    for (int u = 0; u < 32; u++) m.w2[u] = host_bf16((float)b[u]);
+    m.b2 = (float)b[32];
+    m.eps = 0;
+    m.valid = 0;
+    hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
+    hipMemsetAsync(g->loc_err, 0, sizeof(uint32_t), s);
+    launch_loc_eval(g->slots, L, g->lf_log2, g->loc, g->loc_err, s);
+    uint32_t err = 0;
+    hipMemcpyAsync(&err, g->loc_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    hipStreamSynchronize(s);
+    m.eps = err + 1;   // keys between pivots may sit one leaf further
+    m.valid = 1;
+    hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
+    hipStreamSynchronize(s);
+    g->loc_h = m;
+    g->batches_since_fit = 0;
+    g->loc_fits++;
+    return GPMA_OK;
+}
+
+// after a batch: count lookups and misses; refit when the array was rebuilt,
+// every 64 batches, or when more than 1/16 of the lookups missed
+int locator_after_batch(gpma *g, uint64_t lookups, uint64_t misses, bool rebuilt, hipStream_t s) {
+    if (!g->learned) return GPMA_OK;
+    g->loc_lookups += lookups;
+    g->loc_misses += misses;
+    g->batches_since_fit++;
+    if (rebuilt || g->loc_h.L != g->L || g->batches_since_fit >= 64 || misses * 16 > lookups)
+        return locator_fit(g, s);
+    return GPMA_OK;
+}
+
 // Levels h_start .. H-1 and the root for the updates still pending in `cur`
 // (rem of them; g->ctl holds the batch's counters so far).  Shared by the
 // plain path and by the completion of a fused batch that stopped.
@@ -507,7 +652,7 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     // BinarySearchLeafSegments
     {
         ProfScope ps(g, GPMA_K_LOCATE, s);
-        launch_locate(cur.k, cur.n, b, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
+        do_locate(g, cur.k, cur.n, b, cur.l, cur.st, s);
         ps.done(16.0 * (double)b);
     }
 
@@ -536,19 +681,29 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     }
     uint64_t rem = g->ctl_h->lvl[0];
     std::swap(cur, nxt);
+    const uint64_t cap_before = g->cap;
+    const uint32_t misses = g->ctl_h->misses;
     e = finish_levels(g, del, cur, rem, 1, segs_seen, st, s);
     if (st) st->noops = b - st->applied;
+    if (!e) e = locator_after_batch(g, distinct, misses, g->cap != cap_before, s);
     return e;
 }
 
 void free_all(gpma *g) {
     free_batch(g);
+    dev_free(g->loc); dev_free(g->loc_gram); dev_free(g->loc_err);
     dev_free(g->tkeys);
     dev_free(g->fs); dev_free(g->stop); dev_free(g->cur_n); dev_free(g->desc); dev_free(g->outs);
     if (g->fs_h) hipHostFree(g->fs_h);
     if (g->stop_h) hipHostFree(g->stop_h);
+    if (g->reset_h) hipHostFree(g->reset_h);
+    if (g->desc_h) hipHostFree(g->desc_h);
+    if (g->outs_h) hipHostFree(g->outs_h);
     g->fs_h = nullptr;
     g->stop_h = nullptr;
+    g->reset_h = nullptr;
+    g->desc_h = nullptr;
+    g->outs_h = nullptr;
     if (g->cap_stream) hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
     dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
@@ -571,6 +726,9 @@ void free_all(gpma *g) {
 // fused batching (host side)
 
 constexpr uint32_t kFusedChunk = 4096;   // batches per descriptor table
+// levels above the leaves that a batch graph covers; a batch with updates
+// left above them stops the replay and finishes on the host-driven path
+constexpr uint32_t kFusedLevels = 2;
 
 uint64_t batch_class(uint64_t b) { return next_pow2(std::max<uint64_t>(b, 1024)); }
 
@@ -584,6 +742,9 @@ int ensure_fused(gpma *g) {
     e |= dev_alloc(&g->outs, kFusedChunk);
     if (hipHostMalloc((void **)&g->fs_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (hipHostMalloc((void **)&g->stop_h, sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc((void **)&g->reset_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc((void **)&g->desc_h, kFusedChunk * sizeof(BatchDesc), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc((void **)&g->outs_h, kFusedChunk * sizeof(BatchOut), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (!e && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
     return e;
 }
@@ -602,7 +763,7 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     LevelArrays cur{ukeys, g->leafA, g->stA, &g->ctl->n_in};
     LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
     unique_sorted_dyn(sorted, g->cur_n, cls, ukeys, cur.n, g->flags, g->tmp, s);
-    launch_locate(cur.k, cur.n, cls, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
+    do_locate(g, cur.k, cur.n, cls, cur.l, cur.st, s);
     uint64_t lo, hi;
     bounds(g, g->H, 0, &lo, &hi);
     launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf, lo,
@@ -620,7 +781,8 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     cur = nxt;
     nxt = other(cur);
     uint32_t h_top = 0;
-    for (uint32_t h = 1; h < g->H && seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds; h++) {
+    for (uint32_t h = 1; h <= kFusedLevels && h < g->H && seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds;
+         h++) {
         bounds(g, g->H, h, &lo, &hi);
         launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf,
                          lo, hi, g->ctl, s);
@@ -662,10 +824,11 @@ void read_fused(gpma *g, hipStream_t s) {
 }
 
 void reset_fused(gpma *g, uint32_t batch, hipStream_t s) {
-    FusedState z{};
-    z.batch = batch;
-    hipMemcpyAsync(g->fs, &z, sizeof(uint32_t) * 4, hipMemcpyHostToDevice, s);
-    hipStreamSynchronize(s);
+    // the pinned source is rewritten only after the stream has drained the
+    // previous copy (every caller synchronises between resets)
+    memset(g->reset_h, 0, sizeof(uint32_t) * 4);
+    g->reset_h->batch = batch;
+    hipMemcpyAsync(g->fs, g->reset_h, sizeof(uint32_t) * 4, hipMemcpyHostToDevice, s);
 }
 
 // Complete the stopped batch of handle g: restore its control block and run
@@ -692,14 +855,14 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
 
 namespace {
 
-// Sum the results of batches [from, to) of handle g into g->n and *total.
-void account(gpma *g, uint32_t from, uint32_t to, hipStream_t s, gpma_stats *total) {
-    if (to <= from) return;
-    std::vector<BatchOut> o(to - from);
-    hipMemcpyAsync(o.data(), g->outs + from, o.size() * sizeof(BatchOut), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    for (auto &x : o) {
+// Sum the results of batches [from, to) of handle g (already copied to the
+// pinned outs_h) into g->n and *total.
+void account(gpma *g, uint32_t from, uint32_t to, gpma_stats *total) {
+    for (uint32_t b = from; b < to; b++) {
+        const BatchOut &x = g->outs_h[b];
         g->n = (uint64_t)((int64_t)g->n + x.dn);
+        g->acc_lookups += x.lookups;
+        g->acc_misses += x.misses;
         if (total) {
             total->applied += x.applied;
             total->noops += x.noops;
@@ -711,9 +874,10 @@ void account(gpma *g, uint32_t from, uint32_t to, hipStream_t s, gpma_stats *tot
 int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys, const uint64_t *sizes,
                 hipStream_t s, gpma_stats *total, uint32_t *done_out) {
     gpma *m = g->mir;
-    std::vector<BatchDesc> hd(count);
-    for (uint32_t i = 0; i < count; i++) hd[i] = BatchDesc{keys[i], sizes[i]};
-    hipMemcpyAsync(g->desc, hd.data(), count * sizeof(BatchDesc), hipMemcpyHostToDevice, s);
+    // the previous call ended with a synchronisation, so the pinned staging
+    // buffers are free to rewrite
+    for (uint32_t i = 0; i < count; i++) g->desc_h[i] = BatchDesc{keys[i], sizes[i]};
+    hipMemcpyAsync(g->desc, g->desc_h, count * sizeof(BatchDesc), hipMemcpyHostToDevice, s);
     hipMemsetAsync(g->stop, 0, sizeof(uint32_t), s);
     reset_fused(g, 0, s);
     if (m) reset_fused(m, 0, s);
@@ -733,11 +897,16 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
         read_fused(g, s);
         if (m) read_fused(m, s);
         hipMemcpyAsync(g->stop_h, g->stop, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        hipMemcpyAsync(g->outs_h + next, g->outs + next, (count - next) * sizeof(BatchOut),
+                       hipMemcpyDeviceToHost, s);
+        if (m)
+            hipMemcpyAsync(m->outs_h + next, m->outs + next, (count - next) * sizeof(BatchOut),
+                           hipMemcpyDeviceToHost, s);
         if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
         const uint32_t bg = g->fs_h->batch, bm = m ? m->fs_h->batch : bg;
         const bool hg = g->fs_h->halted != 0, hm = m ? m->fs_h->halted != 0 : false;
-        account(g, next, bg, s, total);
-        if (m) account(m, next, bm, s, nullptr);
+        account(g, next, bg, total);
+        if (m) account(m, next, bm, nullptr);
         if (!*g->stop_h) {
             next = count;
             break;
@@ -771,11 +940,22 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             return e;
         }
         hipMemsetAsync(g->stop, 0, sizeof(uint32_t), s);
+        if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;   // frees reset_h
         reset_fused(g, b + 1, s);
         if (m) reset_fused(m, b + 1, s);
         next = b + 1;
     }
     if (m && m->n != g->n) return GPMA_EDEVICE;
+    for (gpma *h : {g, m}) {
+        if (!h) continue;
+        const uint64_t lk = h->acc_lookups, ms = h->acc_misses;
+        h->acc_lookups = h->acc_misses = 0;
+        if (h->learned) {
+            h->batches_since_fit += count > 0 ? count - 1 : 0;   // locator_after_batch adds one
+            int e = locator_after_batch(h, lk, ms, h->loc_h.L != h->L, s);
+            if (e) return e;
+        }
+    }
     *done_out = count;
     return GPMA_OK;
 }
@@ -784,6 +964,87 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
 
 // ===========================================================================
 // C ABI
+
+// Snapshots: a read-only copy of the arrays the analytics read (slots, leaf
+// counts, row offsets, degrees; the mirror's too), taken in stream order.
+static int snapshot_alloc(gpma *src, gpma *c) {
+    c->V = src->V; c->lf = src->lf; c->lf_log2 = src->lf_log2;
+    c->tau_leaf = src->tau_leaf; c->tau_root = src->tau_root;
+    c->rho_leaf = src->rho_leaf; c->rho_root = src->rho_root;
+    c->cap = src->cap; c->L = src->L; c->H = src->H; c->n = src->n;
+    c->dev = src->dev;
+    c->readonly = true;
+    int e = GPMA_OK;
+    e |= dev_alloc(&c->slots, src->cap);
+    e |= dev_alloc(&c->cnt, src->L);
+    e |= dev_alloc(&c->row_ptr, (uint64_t)src->V + 1);
+    e |= dev_alloc(&c->deg, src->V);
+    if (!c->ctl) e |= dev_alloc(&c->ctl, 1);
+    if (!c->small) e |= dev_alloc(&c->small, 8);
+    if (!c->ctl_h && hipHostMalloc((void **)&c->ctl_h, sizeof(Ctl), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (!c->small_h && hipHostMalloc((void **)&c->small_h, 4 * sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
+    return e;
+}
+
+static void snapshot_copy(gpma *src, gpma *c, hipStream_t s) {
+    hipMemcpyAsync(c->slots, src->slots, src->cap * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(c->cnt, src->cnt, src->L * sizeof(uint16_t), hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(c->row_ptr, src->row_ptr, ((uint64_t)src->V + 1) * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    hipMemcpyAsync(c->deg, src->deg, (uint64_t)src->V * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    c->n = src->n;
+}
+
+static int snapshot_refresh_one(gpma *src, gpma *c, hipStream_t s) {
+    if (c->cap != src->cap || c->V != src->V) {
+        hipStreamSynchronize(s);
+        dev_free(c->slots); dev_free(c->cnt); dev_free(c->row_ptr); dev_free(c->deg);
+        int e = snapshot_alloc(src, c);
+        if (e) return e;
+    }
+    snapshot_copy(src, c, s);
+    return GPMA_OK;
+}
+
+extern "C" int gpma_snapshot_refresh(gpma_t *src, gpma_t *snap, hipStream_t s);
+
+extern "C" int gpma_snapshot(gpma_t *src, gpma_t **out, hipStream_t s) {
+    if (!out) return GPMA_EINVAL;
+    *out = nullptr;
+    if (!src || src->readonly) return GPMA_EINVAL;
+    gpma *c = new (std::nothrow) gpma();
+    if (!c) return GPMA_ENOMEM;
+    int e = snapshot_alloc(src, c);
+    if (!e && src->mir) {
+        c->mir = new (std::nothrow) gpma();
+        e = c->mir ? snapshot_alloc(src->mir, c->mir) : GPMA_ENOMEM;
+    }
+    if (e) {
+        if (c->mir) { free_all(c->mir); delete c->mir; }
+        free_all(c);
+        delete c;
+        return e;
+    }
+    snapshot_copy(src, c, s);
+    if (src->mir) snapshot_copy(src->mir, c->mir, s);
+    *out = c;
+    return GPMA_OK;
+}
+
+extern "C" int gpma_snapshot_refresh(gpma_t *src, gpma_t *snap, hipStream_t s) {
+    if (!src || !snap || src->readonly || !snap->readonly) return GPMA_EINVAL;
+    if (!src->mir != !snap->mir) return GPMA_EINVAL;
+    int e = snapshot_refresh_one(src, snap, s);
+    if (!e && src->mir) e = snapshot_refresh_one(src->mir, snap->mir, s);
+    return e;
+}
+
+extern "C" uint64_t gpma_device_bytes(const gpma_t *g) {
+    if (!g) return 0;
+    uint64_t b = g->cap * 8 + g->L * 2 + ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4;
+    if (g->mir) b += gpma_device_bytes(g->mir);
+    return b;
+}
+
 
 extern "C" {
 
@@ -899,6 +1160,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
         return GPMA_ENOMEM;
     }
     hipMemsetAsync(g->row_ptr, 0, sizeof(uint32_t), s);
+    g->learned = (p.flags & GPMA_FLAG_LEARNED_LOCATOR) != 0;
     launch_dispatch(uq, nu, g->slots, g->cnt, g->row_ptr, 0, g->L, lf, s);
     launch_degrees_from_sorted(uq, nu, V, fl, g->deg, s);
     if (hipStreamSynchronize(s) != hipSuccess) {
@@ -909,9 +1171,14 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     }
     cleanup();
     g->n = nu;
+    if (g->learned && locator_fit(g, s)) {
+        free_all(g);
+        delete g;
+        return GPMA_ENOMEM;
+    }
     if (p.flags & GPMA_FLAG_MIRROR) {
         gpma_params mp = p;
-        mp.flags = 0;
+        mp.flags = p.flags & GPMA_FLAG_LEARNED_LOCATOR;
         mp.leaf_size = g->lf;
         uint64_t *tk = nullptr;
         if (n && dev_alloc(&tk, n)) {
@@ -944,7 +1211,7 @@ int gpma_destroy(gpma_t *g) {
 
 static int apply_with_mirror(gpma_t *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t s,
                              gpma_stats *st) {
-    if (!g) return GPMA_EINVAL;
+    if (!g || g->readonly) return GPMA_EINVAL;
     int e = apply_batch(g, keys, b, del, s, st);
     if (e || !g->mir || b == 0) return e;
     if (b > g->tkeys_cap) {
@@ -971,6 +1238,39 @@ int gpma_delete_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s
 
 gpma_t *gpma_get_mirror(gpma_t *g) { return g ? g->mir : nullptr; }
 
+int gpma_locate(gpma_t *g, const uint64_t *keys, uint64_t n, uint32_t *leaf_out, hipStream_t s) {
+    if (!g || g->readonly || (n && (!keys || !leaf_out)) || n >= (1ull << 31)) return GPMA_EINVAL;
+    if (!n) return GPMA_OK;
+    int e = ensure_batch(g, n);
+    if (e) return e;
+    hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
+    launch_validate(keys, n, g->V, g->ctl, s);
+    g->small_h[0] = (uint32_t)n;
+    hipMemcpyAsync(&g->ctl->n_in, g->small_h, sizeof(uint32_t), hipMemcpyHostToDevice, s);
+    do_locate(g, keys, &g->ctl->n_in, n, leaf_out, g->stA, s);
+    read_ctl(g, s);
+    if (g->ctl_h->err) return GPMA_EINVAL;
+    if (g->learned) {
+        g->loc_lookups += n;
+        g->loc_misses += g->ctl_h->misses;
+    }
+    return GPMA_OK;
+}
+
+int gpma_locator_refit(gpma_t *g, hipStream_t s) {
+    if (!g || !g->learned) return GPMA_EINVAL;
+    return locator_fit(g, s);
+}
+
+int gpma_locator_info(const gpma_t *g, uint32_t *eps, uint64_t *lookups, uint64_t *misses, uint64_t *fits) {
+    if (!g || !g->learned) return GPMA_EINVAL;
+    if (eps) *eps = g->loc_h.valid ? g->loc_h.eps : 0xFFFFFFFFu;
+    if (lookups) *lookups = g->loc_lookups;
+    if (misses) *misses = g->loc_misses;
+    if (fits) *fits = g->loc_fits;
+    return GPMA_OK;
+}
+
 int gpma_apply_batches(gpma_t *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys,
                        const uint64_t *sizes, hipStream_t s, gpma_stats *total, uint32_t *completed) {
     if (completed) *completed = 0;
@@ -978,7 +1278,7 @@ int gpma_apply_batches(gpma_t *g, uint32_t count, const uint8_t *ops, const uint
         memset(total, 0, sizeof(*total));
         total->top_level = -1;
     }
-    if (!g || (count && (!ops || !keys || !sizes))) return GPMA_EINVAL;
+    if (!g || g->readonly || (count && (!ops || !keys || !sizes))) return GPMA_EINVAL;
     uint64_t cmax = 0;
     for (uint32_t i = 0; i < count; i++) {
         if (ops[i] > 1 || sizes[i] >= (1ull << 31) || (sizes[i] && !keys[i])) return GPMA_EINVAL;

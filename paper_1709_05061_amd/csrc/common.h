@@ -27,6 +27,8 @@ struct Ctl {
     uint64_t noops;      // updates dropped as no-ops
     int64_t dn;          // change of the stored entry count so far
     uint64_t rewritten;  // sum of capacities of merged segments
+    uint32_t misses;     // learned-locator lookups that fell back to full search
+    uint32_t pad;
 };
 
 __device__ __forceinline__ bool is_guard(uint64_t k) {

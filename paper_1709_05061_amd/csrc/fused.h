@@ -26,6 +26,8 @@ struct BatchOut {
     int64_t dn;
     uint64_t rewritten;
     uint32_t segs;
+    uint32_t misses;    // learned-locator fallbacks
+    uint32_t lookups;   // distinct keys located
     uint32_t pad;
 };
 

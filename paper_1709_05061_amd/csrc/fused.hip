@@ -40,6 +40,7 @@ k_fetch(const BatchDesc *__restrict__ desc, const FusedState *__restrict__ st,
         ctl->noops = 0;
         ctl->dn = 0;
         ctl->rewritten = 0;
+        ctl->misses = 0;
         *cur_n = (uint32_t)n;
     }
 }
@@ -60,6 +61,8 @@ __global__ void k_finish(FusedState *__restrict__ st, uint32_t *__restrict__ sto
     out[b].dn = ctl->dn;
     out[b].segs = ctl->segs;
     out[b].rewritten = ctl->rewritten;
+    out[b].misses = ctl->misses;
+    out[b].lookups = ctl->n_in;
     st->batch = b + 1;
 }
 

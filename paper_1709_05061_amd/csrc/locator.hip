@@ -1,0 +1,241 @@
+// Learned segment locator: a small model of the key CDF predicts each
+// update's leaf, and an exact bounded search corrects it, so the result is
+// always the leaf BinarySearchLeafSegments would return (Algorithm "GPMA+
+// Segment-Oriented Insertion"; the model is a design addition, not the
+// paper's).
+//
+// Model: x = src/V, y = dst'/(V+1) (dst' = V for a guard), 32 hidden units
+// h = relu(W1 [x y]^T + b1), position = x + w2 . h + b2, leaf =
+// floor(position * L).  Layer 1 (a K=2 product that needs full input
+// precision) runs on the vector ALU in fp32; layer 2 runs on MFMA
+// (v_mfma_f32_16x16x16_bf16, fp32 accumulate) with bf16 weights, the
+// activations split into a bf16 high part and a bf16 low part (two MFMAs),
+// which keeps about 16 bits of each activation.
+//
+// The error bound eps is measured over every leaf pivot with this same code;
+// a lookup searches [pred-eps, pred+eps], checks that the window brackets
+// the key (pivot[lo] <= k < pivot[hi+1]) and otherwise falls back to the
+// full binary search.
+#include "common.h"
+#include "locator.h"
+
+using namespace gpma_dev;
+
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    // round to nearest even (inputs here are finite)
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ void key_features(uint64_t k, float inv_v, float inv_v1, uint32_t V, float &x,
+                                             float &y) {
+    const uint32_t src = (uint32_t)(k >> 32), dst = (uint32_t)k;
+    x = (float)src * inv_v;
+    y = (float)(dst == kGuardDst ? V : dst) * inv_v1;
+}
+
+// Positions of the 64 keys kq[lane] of a wave (every lane active).  Lane l
+// supplies row l%16 of the A operand (its key within a 16-key row block) and
+// hidden units 4*(l/16) .. +3 of each 16-unit K block; B holds w2 in every
+// column; the result for key 16*rb + 4*(l/16) + i comes back in lane l's
+// value i.  s_out: 64 floats of LDS for the wave.
+__device__ __forceinline__ float model_position(const LocModel &m, uint64_t kq, float *s_out) {
+    const uint32_t lane = __lane_id();
+    const uint32_t quad = lane >> 4;     // which 4 hidden units / which 4 output rows
+    const uint32_t row = lane & 15;
+    float xq, yq;
+    key_features(kq, m.inv_v, m.inv_v1, m.V, xq, yq);
+    // B operand: w2 for k = 4*quad + i of each K block, the same in every column
+    bf16x4 b[2];
+#pragma unroll
+    for (int kb = 0; kb < 2; kb++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) b[kb][i] = (short)m.w2[kb * 16 + 4 * quad + i];
+#pragma unroll
+    for (int rb = 0; rb < 4; rb++) {
+        // features of key 16*rb + row, fetched from its owner lane
+        const float x = __shfl(xq, 16 * rb + row, kWave);
+        const float y = __shfl(yq, 16 * rb + row, kWave);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; kb++) {
+            bf16x4 ahi, alo;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int u = kb * 16 + 4 * quad + i;
+                const float h = fmaxf(m.w1x[u] * x + m.w1y[u] * y + m.b1[u], 0.f);
+                const uint16_t hi = f32_to_bf16(h);
+                ahi[i] = (short)hi;
+                alo[i] = (short)f32_to_bf16(h - bf16_to_f32(hi));
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, b[kb], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, b[kb], acc, 0, 0, 0);
+        }
+        if (row == 0) {
+#pragma unroll
+            for (int i = 0; i < 4; i++) s_out[16 * rb + 4 * quad + i] = acc[i];
+        }
+    }
+    wave_lds_sync();
+    const float r = s_out[lane];
+    wave_lds_sync();
+    return xq + r + m.b2;
+}
+
+__device__ __forceinline__ uint64_t predict_leaf(const LocModel &m, float pos) {
+    float f = floorf(pos * (float)m.L);
+    if (!(f >= 0.f)) f = 0.f;
+    if (f > (float)(m.L - 1)) f = (float)(m.L - 1);
+    return (uint64_t)f;
+}
+
+// the largest leaf j in [lo, hi] with pivot(j) <= k (lo if none)
+__device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t lf_log2, uint64_t lo,
+                                                 uint64_t hi, uint64_t k) {
+    uint64_t a = lo, b = hi + 1;   // pivots in [a, b) : count of those <= k
+    while (a < b) {
+        const uint64_t mid = (a + b) >> 1;
+        if (slots[mid << lf_log2] <= k) a = mid + 1; else b = mid;
+    }
+    return a > lo ? a - 1 : lo;
+}
+
+// Locate with the model.  The whole wave runs the MFMA inference (lanes past
+// the end use key 0), then each lane corrects its own prediction.
+__global__ void __launch_bounds__(256)
+k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+                 const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2,
+                 const LocModel *__restrict__ model, const Ctl *__restrict__ ctl, uint32_t *__restrict__ leaf,
+                 uint8_t *__restrict__ status, uint32_t *__restrict__ misses) {
+    __shared__ float s_out[256];
+    const LocModel m = *model;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t n = *n_dev < n_max ? *n_dev : n_max;
+    if ((uint64_t)blockIdx.x * blockDim.x >= n || ctl->err) return;   // block-uniform
+    const bool active = i < n;
+    const uint64_t k = active ? keys[i] : 0;
+    const float pos = model_position(m, k, s_out + (threadIdx.x & ~63u));
+    if (!active) return;
+    const uint64_t p = predict_leaf(m, pos);
+    const uint64_t lo = p > m.eps ? p - m.eps : 0;
+    const uint64_t hi = p + m.eps < L - 1 ? p + m.eps : L - 1;
+    const bool ok_lo = lo == 0 || slots[lo << lf_log2] <= k;
+    const bool ok_hi = hi == L - 1 || slots[(hi + 1) << lf_log2] > k;
+    uint64_t j;
+    if (m.valid && m.L == L && ok_lo && ok_hi) {
+        j = search_range(slots, lf_log2, lo, hi, k);
+    } else {
+        j = search_range(slots, lf_log2, 0, L - 1, k);
+        atomicAdd(misses, 1u);
+    }
+    leaf[i] = (uint32_t)j;
+    status[i] = kPending;
+}
+
+// Fit: sampled pivots, their features and the fp64 normal equations.  Each
+// thread owns some entries of the symmetric 33x33 Gram matrix (plus the
+// right-hand side) and walks the block's samples staged in LDS.
+constexpr int kFeat = 33;                    // 32 hidden + bias
+constexpr int kGram = kFeat * kFeat + kFeat; // G and r
+constexpr int kFitChunk = 128;
+
+__global__ void __launch_bounds__(256)
+k_loc_gram(const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2, uint64_t stride, uint64_t S,
+           const LocModel *__restrict__ model, double *__restrict__ gram) {
+    __shared__ double phi[kFitChunk][kFeat + 1];   // features and target
+    const LocModel m = *model;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (uint64_t c0 = (uint64_t)blockIdx.x * kFitChunk; c0 < S; c0 += (uint64_t)gridDim.x * kFitChunk) {
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < kFitChunk; t += blockDim.x) {
+            const uint64_t s = c0 + t;
+            if (s < S) {
+                const uint64_t j = s * stride;
+                float x, y;
+                key_features(slots[j << lf_log2], m.inv_v, m.inv_v1, m.V, x, y);
+                for (int u = 0; u < 32; u++) phi[t][u] = fmax((double)m.w1x[u] * x + (double)m.w1y[u] * y + (double)m.b1[u], 0.0);
+                phi[t][32] = 1.0;
+                phi[t][33] = (double)j / (double)L - (double)x;
+            } else {
+                for (int u = 0; u <= kFeat; u++) phi[t][u] = 0.0;
+            }
+        }
+        __syncthreads();
+        for (int q = 0; q < 5; q++) {
+            const int e = threadIdx.x + q * 256;
+            if (e >= kGram) break;
+            const int a = e < kFeat * kFeat ? e / kFeat : e - kFeat * kFeat;
+            const int bcol = e < kFeat * kFeat ? e % kFeat : kFeat;   // kFeat: the target column
+            double s = 0.0;
+            for (int t = 0; t < kFitChunk; t++) s += phi[t][a] * phi[t][bcol];
+            acc[q] += s;
+        }
+    }
+    for (int q = 0; q < 5; q++) {
+        const int e = threadIdx.x + q * 256;
+        if (e < kGram && acc[q] != 0.0) unsafeAtomicAdd(&gram[e], acc[q]);
+    }
+}
+
+// Error bound: max |predicted leaf - j| over every leaf pivot.
+__global__ void __launch_bounds__(256)
+k_loc_eval(const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2, const LocModel *__restrict__ model,
+           uint32_t *__restrict__ max_err) {
+    __shared__ float s_out[256];
+    const LocModel m = *model;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t worst = 0;
+    // the loop bound is wave-uniform (L is a multiple of 64 or the wave is the last)
+    for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < L; j0 += stride) {
+        const uint64_t j = j0 + threadIdx.x;
+        const uint64_t k = j < L ? slots[j << lf_log2] : 0;
+        const float pos = model_position(m, k, s_out + (threadIdx.x & ~63u));
+        if (j < L) {
+            const uint64_t p = predict_leaf(m, pos);
+            const uint64_t d = p > j ? p - j : j - p;
+            worst = d > worst ? (uint32_t)d : worst;
+        }
+    }
+    for (int d = kWave / 2; d >= 1; d >>= 1) {
+        const uint32_t o = __shfl_xor(worst, d, kWave);
+        worst = o > worst ? o : worst;
+    }
+    if (__lane_id() == 0) atomicMax(max_err, worst);
+}
+
+}  // namespace
+
+namespace gpma_host {
+
+void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
+                           uint64_t L, uint32_t lf_log2, const LocModel *model, const Ctl *ctl, uint32_t *leaf,
+                           uint8_t *status, uint32_t *misses, hipStream_t s) {
+    if (!n_max) return;
+    hipLaunchKernelGGL(k_locate_learned, dim3((uint32_t)((n_max + 255) / 256)), dim3(256), 0, s, keys, n_dev,
+                       n_max, slots, L, lf_log2, model, ctl, leaf, status, misses);
+}
+
+size_t loc_gram_words() { return kGram; }
+
+void launch_loc_gram(const uint64_t *slots, uint64_t L, uint32_t lf_log2, uint64_t stride, uint64_t S,
+                     const LocModel *model, double *gram, hipStream_t s) {
+    uint64_t blocks = (S + kFitChunk - 1) / kFitChunk;
+    if (blocks > 128) blocks = 128;
+    hipLaunchKernelGGL(k_loc_gram, dim3((uint32_t)blocks), dim3(256), 0, s, slots, L, lf_log2, stride, S, model,
+                       gram);
+}
+
+void launch_loc_eval(const uint64_t *slots, uint64_t L, uint32_t lf_log2, const LocModel *model, uint32_t *max_err,
+                     hipStream_t s) {
+    uint64_t blocks = (L + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, slots, L, lf_log2, model, max_err);
+}
+
+}  // namespace gpma_host

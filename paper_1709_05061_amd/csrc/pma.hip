@@ -499,7 +499,7 @@ void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t
                       uint64_t maxh, Ctl *ctl, hipStream_t s) {
     if (!n_max) return;
     size_t lds = seg_merge_lds_bytes(lf, h);
-    const uint32_t grid = (uint32_t)(n_max < 4096 ? n_max : 4096);
+    const uint32_t grid = (uint32_t)(n_max < 512 ? n_max : 512);   // grid-stride over segments
     if (del)
         hipLaunchKernelGGL(k_seg_merge<true>, dim3(grid), dim3(kSegThreads), lds, s, h,
                            keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libgpma.so")
 
 GPMA_OK, GPMA_EINVAL, GPMA_ENOMEM, GPMA_EDEVICE = 0, -1, -2, -3
 GPMA_FLAG_MIRROR = 1
+GPMA_FLAG_LEARNED_LOCATOR = 2
 EMPTY = 0xFFFFFFFFFFFFFFFF
 GUARD_DST = 0xFFFFFFFF
 
@@ -79,6 +80,12 @@ def load_library() -> C.CDLL:
         "gpma_export_degrees": (C.c_int, [vp, vp, u64, vp]),
         "gpma_sync": (C.c_int, [vp]),
         "gpma_get_mirror": (vp, [vp]),
+        "gpma_snapshot": (C.c_int, [vp, C.POINTER(vp), vp]),
+        "gpma_snapshot_refresh": (C.c_int, [vp, vp, vp]),
+        "gpma_device_bytes": (u64, [vp]),
+        "gpma_locate": (C.c_int, [vp, vp, u64, vp, vp]),
+        "gpma_locator_refit": (C.c_int, [vp, vp]),
+        "gpma_locator_info": (C.c_int, [vp, C.POINTER(u32), pu64, pu64, pu64]),
         "gpma_apply_batches": (C.c_int, [vp, u32, C.POINTER(C.c_uint8), C.POINTER(vp), C.POINTER(u64), vp,
                                          C.POINTER(gpma_stats), C.POINTER(u32)]),
         "gpma_strerror": (C.c_char_p, [C.c_int]),
@@ -101,6 +108,8 @@ def exported_symbols() -> List[str]:
             "gpma_capacity", "gpma_leaf_size", "gpma_num_vertices", "gpma_export_slots",
             "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_row_offsets",
             "gpma_export_degrees", "gpma_sync", "gpma_get_mirror", "gpma_apply_batches", "gpma_strerror",
+            "gpma_snapshot", "gpma_snapshot_refresh", "gpma_device_bytes", "gpma_locate",
+            "gpma_locator_refit", "gpma_locator_info",
             "gpma_profile_enable",
             "gpma_profile_reset", "gpma_profile_read"]
 
@@ -296,9 +305,9 @@ class GPMA(_HandleView):
 
     def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
                  tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, mirror: bool = False,
-                 stream=None):
-        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root,
-                        GPMA_FLAG_MIRROR if mirror else 0)
+                 learned: bool = False, stream=None):
+        flags = (GPMA_FLAG_MIRROR if mirror else 0) | (GPMA_FLAG_LEARNED_LOCATOR if learned else 0)
+        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags)
         super().__init__(gpma_create(num_vertices, init_keys, p, stream), num_vertices)
 
     def close(self):
@@ -311,6 +320,20 @@ class GPMA(_HandleView):
             self.close()
         except Exception:
             pass
+
+    def locate(self, keys: torch.Tensor, stream=None) -> torch.Tensor:
+        """Leaf of each key (learned locator if enabled, else binary search)."""
+        k = _dev_u64(keys)
+        out = torch.empty(k.numel(), dtype=torch.int32, device="cuda")
+        _check(self._lib.gpma_locate(self.h, C.c_void_p(k.data_ptr()), k.numel(), C.c_void_p(out.data_ptr()),
+                                     _stream(stream)), "gpma_locate")
+        return out
+
+    def locator_info(self):
+        eps, lk, ms, fits = C.c_uint32(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(self._lib.gpma_locator_info(self.h, C.byref(eps), C.byref(lk), C.byref(ms), C.byref(fits)),
+               "gpma_locator_info")
+        return {"eps": eps.value, "lookups": lk.value, "misses": ms.value, "fits": fits.value}
 
     def mirror(self):
         """The dst-major mirror as a read-only view (None without one)."""

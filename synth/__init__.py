@@ -219,6 +219,56 @@ def rmat_full_stream(scale: int, edge_factor: int, extra_draws: int, seed: int,
     return Stream(1 << scale, torch.cat([win, fresh]), win.numel())
 
 
+def uniform01(counter: torch.Tensor, seed: int) -> torch.Tensor:
+    """Doubles in (0, 1) from the top 53 bits of a draw."""
+    r = _srl(splitmix64(counter, seed), 11)
+    return (r.to(torch.float64) + 0.5) / float(1 << 53)
+
+
+def powerlaw_edges(V: int, m: int, seed: int, alpha: float = 2.1, device="cpu") -> torch.Tensor:
+    """A social-network-shaped directed graph (Chung-Lu style): out-degrees
+    follow a discrete power law with exponent `alpha` (Pareto weights,
+    truncated at V, rescaled to about m edges in total); destinations are
+    drawn with probability proportional to (rank+1)^(-1/(alpha-1)) over a
+    seeded random ranking of the vertices.  Distinct edges without
+    self-loops, in random order; topped up with further draws to m."""
+    idx = torch.arange(V, device=device, dtype=torch.int64)
+    w = uniform01(idx, seed) ** (-1.0 / (alpha - 1.0))
+    w = torch.clamp(w, max=float(V))
+    deg = torch.floor(w * (m * 1.15 / float(w.sum())) + uniform01(idx, seed + 1)).to(torch.int64)
+    rank = torch.argsort(splitmix64(idx, seed + 2))
+    zw = (rank.to(torch.float64) + 1.0) ** (-1.0 / (alpha - 1.0))
+    cdf = torch.cumsum(zw, 0)
+    cdf = cdf / cdf[-1]
+    got = torch.empty(0, dtype=torch.int64, device=device)
+    base = 0
+    rnd = 0
+    while got.numel() < m and rnd < 8:
+        src = torch.repeat_interleave(idx, deg) if rnd == 0 else \
+            uniform_below(torch.arange(base, base + 2 * (m - got.numel()), device=device), seed + 3, V)
+        c = torch.arange(base, base + src.numel(), device=device, dtype=torch.int64)
+        dst = torch.searchsorted(cdf, uniform01(c, seed + 4)).clamp(max=V - 1)
+        k = edge_key(src, dst)[src != dst]
+        k = k[torch.argsort(splitmix64(torch.arange(k.numel(), device=device), seed + 5 + rnd))]
+        got = unique_first(torch.cat([got, k]))
+        base += src.numel()
+        rnd += 1
+    return got[:m]
+
+
+def poisson_times(n: int, rate: float, seed: int, device="cpu") -> torch.Tensor:
+    """Arrival times (seconds, float64, ascending) of the first n events of a
+    Poisson process with the given rate: cumulative exponential gaps."""
+    u = uniform01(torch.arange(n, device=device), seed)
+    return torch.cumsum(-torch.log(u) / rate, 0)
+
+
+def loguniform_sizes(n: int, lo_log2: int, hi_log2: int, seed: int):
+    """n batch sizes, log-uniform on [2^lo, 2^hi] (host integers)."""
+    u = uniform01(torch.arange(n), seed)
+    return [int(round(2.0 ** (lo_log2 + (hi_log2 - lo_log2) * float(x)))) for x in u]
+
+
 def random_batch(V: int, b: int, seed: int, device="cpu") -> torch.Tensor:
     """b uniform random edge keys (repeats and self-loops allowed)."""
     c = torch.arange(b, device=device, dtype=torch.int64)
