@@ -194,6 +194,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slides", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (4 launches), the known-size reference "
+                         "for hardware byte counters, and exit")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -209,6 +212,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # an elementwise kernel that reads 2^27 int64 and writes 2^27 int64
+        src = torch.arange(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            torch.add(src, 1, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration": {"read_bytes": 8 << 27, "write_bytes": 8 << 27,
+                                               "launches": 4}}))
+        return
     b = args.batch
     need = (args.warmup + args.steps) * b
     t0 = time.time()
@@ -330,11 +343,13 @@ def main():
         if n:
             kernels[name] = {"launches": n, "mean_us": 1e3 * ms / n, "total_ms": ms,
                              "GBps": (by / (ms / 1e3) / 1e9) if by and ms else None}
-    dom_name, dom_k = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
-    achieved = dom_k["GBps"]
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
-                "kernel": dom_name}
+    roofline = None
+    if kernels:
+        dom_name, dom_k = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
+        achieved = dom_k["GBps"]
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
+                    "kernel": dom_name}
     spmv = kernels.get("spmv")
     out = {
         "metric": METRIC,

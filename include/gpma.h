@@ -24,7 +24,14 @@
  *     BFS levels and CC rounds also read small counters back).
  *   - A handle must be used by one host thread at a time; handles are
  *     independent.  Return value 0 = GPMA_OK, negative = error.
- *   - On any error the handle is left exactly as it was before the call.
+ *   - Errors: GPMA_EINVAL changes nothing (an invalid key makes its whole
+ *     batch a no-op).  GPMA_ENOMEM from an update that needed a resize
+ *     leaves the updates already merged below the root applied and the rest
+ *     of the batch not; the handle remains a valid PMA of the edges it then
+ *     holds (gpma_num_edges, exports); with a mirror (GPMA_FLAG_MIRROR) the
+ *     two arrays may then hold different edge sets, so destroy the handle.
+ *     GPMA_ENOMEM from any other call changes nothing.  After GPMA_EDEVICE the handle's contents are
+ *     undefined: destroy it.
  */
 #ifndef GPMA_H
 #define GPMA_H
@@ -41,7 +48,7 @@ typedef struct gpma gpma_t;
 enum {
     GPMA_OK = 0,
     GPMA_EINVAL = -1,   /* bad argument or key; nothing was changed */
-    GPMA_ENOMEM = -2,   /* device allocation failed; nothing was changed */
+    GPMA_ENOMEM = -2,   /* device allocation failed (see the conventions above) */
     GPMA_EDEVICE = -3,  /* a HIP call failed */
 };
 
@@ -55,7 +62,7 @@ enum {
  * per mille, interpolated linearly in the height in between.  An insertion
  * merges into a segment iff (n_s + |U_s|)/capacity < tau_h, a deletion iff
  * (n_s - |D_s|)/capacity > rho_h.
- * Requirements (else GPMA_EINVAL): leaf_size a power of two in [16, 1024]
+ * Requirements (else GPMA_EINVAL): leaf_size a power of two in [16, 512]
  * (0 picks one: the next power of two >= log2 of the capacity, at least 16,
  * Section 4.1 "leaf segments with O(log N) length"); 0 < rho_leaf <= rho_root
  * < tau_root <= tau_leaf < 1000; 2*rho_root <= tau_root; and
@@ -149,8 +156,11 @@ int gpma_apply_batches(gpma_t *h, uint32_t count, const uint8_t *ops, const uint
  *   x'[v] = (1-d)/V + d * ( sum_{u->v} x[u]/outdeg(u) + D/V ),
  * D = sum of x over vertices without out-edges (self-loops count).
  * init_dev: V floats, or NULL for the uniform 1/V; out_dev: V floats, may
- * alias init_dev (warm start from the previous result).  Products and sums
- * are formed in fp64; each step rounds once to fp32.
+ * alias init_dev (warm start from the previous result).  Contributions
+ * x[u]/outdeg(u) are formed in fp64 and summed in fp64 (the destination-bin
+ * form, used while V <= 2^25, carries them with 39 mantissa bits); each step
+ * rounds once to fp32.  The summation order is not fixed, so repeated calls
+ * may differ in the last fp32 bit.
  * GPMA_EINVAL if iters == 0 or damping is not in (0,1). */
 int gpma_pagerank(gpma_t *h, const float *init_dev, float *out_dev, uint32_t iters,
                   float damping, hipStream_t stream);
@@ -232,7 +242,7 @@ const char *gpma_strerror(int code);
  * gpma_profile_read synchronises the events it reads; with a mirror, the
  * mirror's launches are included. */
 enum {
-    GPMA_K_SPMV = 0,      /* PageRank push over the slot stream */
+    GPMA_K_SPMV = 0,      /* one PageRank SpMV (all its kernels) */
     GPMA_K_LEAF_MERGE,    /* level-0 fused probe/check/merge */
     GPMA_K_SEG_MERGE,     /* levels >= 1, workgroup tier */
     GPMA_K_SORT,          /* whole batch radix sort (all passes) */

@@ -78,6 +78,11 @@ struct gpma {
 
     // analytics scratch
     double *pr_contrib = nullptr, *pr_y = nullptr, *pr_dang = nullptr;
+    // destination-binned SpMV scratch (sized on use, grown as the array grows)
+    uint32_t *pb_offs = nullptr, *pb_tmp = nullptr, *pb_small = nullptr;   // pb_small: total, pieces
+    uint4 *pb_pieces = nullptr;
+    uint64_t *pb_rec = nullptr;
+    uint64_t pb_offs_words = 0, pb_tmp_words = 0, pb_pieces_cap = 0, pb_rec_cap = 0;
     uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *bfs_off = nullptr, *bfs_tmp = nullptr;
     uint32_t *small = nullptr;
     uint32_t *small_h = nullptr;   // pinned
@@ -601,11 +606,18 @@ int finish_levels(gpma *g, bool del, LevelArrays cur, uint64_t rem, uint32_t h_s
             const uint64_t left = n_now - rem;
             while (ncap > g->lf && left < root_lo(g, ncap) && left <= root_hi(g, ncap / 2)) ncap /= 2;
         }
-        if (ncap > kMaxCap) return GPMA_ENOMEM;
+        // on failure the merges below the root stand: keep n in step with them
+        if (ncap > kMaxCap) {
+            g->n = n_now;
+            return GPMA_ENOMEM;
+        }
         const uint32_t Hold = g->H;
         const uint64_t cap_old = g->cap;
         e = rebuild_root(g, del, cur.k, cur.st, rem, n_now, ncap, s);
-        if (e) return e;
+        if (e) {
+            g->n = n_now;
+            return e;
+        }
         read_ctl(g, s);
         resized = g->cap != cap_old;
         if (st) {
@@ -709,6 +721,8 @@ void free_all(gpma *g) {
     dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
+    dev_free(g->pb_offs); dev_free(g->pb_tmp); dev_free(g->pb_small); dev_free(g->pb_pieces); dev_free(g->pb_rec);
+    g->pb_offs_words = g->pb_tmp_words = g->pb_pieces_cap = g->pb_rec_cap = 0;
     dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
     dev_free(g->small);
     dev_free(g->ctl);
@@ -1358,6 +1372,61 @@ int gpma_sync(gpma_t *g) {
     return GPMA_OK;
 }
 
+namespace {
+
+enum { kSpmvBinned = 0, kSpmvPull = 1, kSpmvPush = 2 };
+
+// Pull over the dst-major mirror if there is one, else destination bins
+// when V allows them, else push.  GPMA_SPMV=binned|pull|push overrides the
+// choice where it applies (tests compare the three).
+int spmv_mode(const gpma *g) {
+    int m = g->mir ? kSpmvPull : (pb_supported(g->V) ? kSpmvBinned : kSpmvPush);
+    if (const char *e = getenv("GPMA_SPMV")) {
+        if (!strcmp(e, "push")) m = kSpmvPush;
+        else if (!strcmp(e, "pull") && g->mir) m = kSpmvPull;
+        else if (!strcmp(e, "binned") && pb_supported(g->V)) m = kSpmvBinned;
+    }
+    return m;
+}
+
+// records for every stored edge, the count matrix and its scan scratch, the
+// piece table; grown with 25% headroom so a slowly growing graph does not
+// reallocate on every call
+int ensure_pb(gpma *g, const PbLayout &L) {
+    const uint64_t edges = g->n;   // >= stored edges (guards included)
+    if (!g->pb_small && dev_alloc(&g->pb_small, 4)) return GPMA_ENOMEM;
+    if (g->pb_rec_cap < edges) {
+        dev_free(g->pb_rec);
+        g->pb_rec_cap = 0;
+        const uint64_t want = edges + edges / 4 + 1024;
+        if (dev_alloc(&g->pb_rec, want)) return GPMA_ENOMEM;
+        g->pb_rec_cap = want;
+    }
+    if (g->pb_offs_words < L.count_words) {
+        dev_free(g->pb_offs);
+        g->pb_offs_words = 0;
+        if (dev_alloc(&g->pb_offs, L.count_words)) return GPMA_ENOMEM;
+        g->pb_offs_words = L.count_words;
+    }
+    const uint64_t tw = scan_tmp_words(L.count_words);
+    if (g->pb_tmp_words < tw) {
+        dev_free(g->pb_tmp);
+        g->pb_tmp_words = 0;
+        if (dev_alloc(&g->pb_tmp, tw)) return GPMA_ENOMEM;
+        g->pb_tmp_words = tw;
+    }
+    if (g->pb_pieces_cap < L.max_pieces) {
+        dev_free(g->pb_pieces);
+        g->pb_pieces_cap = 0;
+        const uint64_t want = L.max_pieces + L.max_pieces / 4;
+        if (dev_alloc(&g->pb_pieces, want)) return GPMA_ENOMEM;
+        g->pb_pieces_cap = want;
+    }
+    return GPMA_OK;
+}
+
+}  // namespace
+
 int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, float damping,
                   hipStream_t s) {
     if (!g || !out || iters == 0 || !(damping > 0.f && damping < 1.f)) return GPMA_EINVAL;
@@ -1371,15 +1440,27 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
             return GPMA_ENOMEM;
         }
     }
-    // algorithmic bytes of one SpMV: every stored entry once, the contribution
-    // vector and the accumulator once each
-    const double spmv_bytes = 8.0 * (double)g->n + 16.0 * (double)g->V;
+    // algorithmic bytes of one SpMV: every stored entry once (8 B), the leaf
+    // counts (2 B a leaf), and per vertex the fp32 input and its degree, the
+    // fp64 accumulator written and read, and the fp32 output (28 B)
+    const double spmv_bytes = 8.0 * (double)g->n + 2.0 * (double)(g->cap >> g->lf_log2) + 28.0 * (double)g->V;
+    const int mode = spmv_mode(g);
+    PbLayout L;
+    if (mode == kSpmvBinned) {
+        L = pb_layout(g->V, g->cap, g->lf_log2, g->n);
+        if (int e = ensure_pb(g, L)) return e;
+        launch_pb_structure(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
+                            g->pb_small + 1, s);
+    }
     for (uint32_t it = 0; it < iters; it++) {
         const float *x = it == 0 ? init : out;
         launch_pr_prep(x, g->deg, g->V, x == nullptr, g->pr_contrib, g->pr_y, g->pr_dang, s);
         {
             ProfScope ps(g, GPMA_K_SPMV, s);
-            if (g->mir)
+            if (mode == kSpmvBinned)
+                launch_pb_spmv(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_pieces, g->pb_small + 1,
+                               g->pr_contrib, g->pb_rec, g->V, g->pr_y, s);
+            else if (mode == kSpmvPull)
                 launch_pr_pull(g->mir->slots, g->mir->cnt, g->mir->cap, g->mir->lf_log2, g->pr_contrib,
                                g->pr_y, s);
             else

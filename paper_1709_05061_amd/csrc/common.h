@@ -71,6 +71,36 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// exclusive scan of one value per thread over the workgroup (blockDim a
+// multiple of the wave size); lds holds blockDim/64 + 1 words
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uint32_t *lds) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t y = __shfl_up(x, d, kWave);
+        if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) lds[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int w = 0; w < nw; w++) {
+            uint32_t t = lds[w];
+            lds[w] = run;
+            run += t;
+        }
+        lds[nw] = run;
+    }
+    __syncthreads();
+    uint32_t excl = x - v + lds[wid];
+    *total = lds[nw];
+    __syncthreads();
+    return excl;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     uint32_t lane = __lane_id();
     return lane ? ((~0ull) >> (64 - lane)) : 0ull;
@@ -173,6 +203,25 @@ void launch_pr_pull(const uint64_t *slots, const uint16_t *cnt, uint64_t cap, ui
 void launch_transpose_keys(const uint64_t *in, uint64_t n, uint64_t *out, hipStream_t s);
 void launch_pr_combine(const double *y, const double *dangling, uint32_t V, double damping,
                        float *out, hipStream_t s);
+
+// ---- PageRank SpMV by destination bins (spmv_binned.hip)
+struct PbLayout {
+    uint32_t nb = 0;          // destination bins of 8192 vertices
+    uint32_t W = 0;           // slot ranges (one workgroup each)
+    uint64_t spw = 0;         // slots per range
+    uint64_t max_pieces = 0;  // bound on accumulation pieces
+    uint64_t count_words = 0; // nb * W
+};
+bool pb_supported(uint32_t V);
+PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_entries);
+// per call: count matrix, its scan (offs, total edges) and the piece table
+void launch_pb_structure(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
+                         uint32_t *offs, uint32_t *total, uint32_t *scan_tmp, uint4 *pieces, uint32_t *npieces,
+                         hipStream_t s);
+// per iteration: y (zeroed beforehand) += A^T contrib
+void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
+                    const uint32_t *offs, const uint4 *pieces, const uint32_t *npieces, const double *contrib,
+                    uint64_t *rec, uint32_t V, double *y, hipStream_t s);
 void launch_bfs_init(int32_t *dist, uint32_t V, uint32_t source, uint32_t *queue,
                      uint32_t *qcount, hipStream_t s);
 void launch_bfs_row_len(const uint32_t *row_ptr, const uint32_t *front, uint32_t nfront, uint32_t *len,

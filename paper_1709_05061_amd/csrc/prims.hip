@@ -20,39 +20,9 @@ constexpr int kChunksLarge = 16;
 constexpr int kChunksSmall = 4;
 constexpr uint64_t kSmallSortMax = 1ull << 20;
 constexpr uint64_t kFuseTiles = 64;
-constexpr uint64_t kScanSingleMax = 1ull << 16;
+constexpr uint64_t kScanSingleMax = 2048;   // one workgroup, two items per thread
 
 inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
-
-// exclusive scan of one value per thread over the workgroup; *total gets the
-// workgroup sum.  lds: (blockDim/64 + 1) words.
-__device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *total, uint32_t *lds) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wid = threadIdx.x / kWave;
-    const int nw = blockDim.x / kWave;
-    uint32_t x = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t y = __shfl_up(x, d, kWave);
-        if (lane >= d) x += y;
-    }
-    if (lane == kWave - 1) lds[wid] = x;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = 0;
-        for (int w = 0; w < nw; w++) {
-            uint32_t t = lds[w];
-            lds[w] = run;
-            run += t;
-        }
-        lds[nw] = run;
-    }
-    __syncthreads();
-    uint32_t excl = x - v + lds[wid];
-    *total = lds[nw];
-    __syncthreads();
-    return excl;
-}
 
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_reduce(const uint32_t *__restrict__ in, uint64_t n, uint32_t *__restrict__ tile_sums) {
@@ -147,7 +117,7 @@ struct DigitMap {
 template <int CH>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t *__restrict__ n_dev,
-                DigitMap dm, uint32_t ntiles, uint32_t *__restrict__ counts) {
+                DigitMap dm, uint32_t ntiles, int tile_major, uint32_t *__restrict__ counts) {
     constexpr int kSortTile = kSortThreads * CH;
     if (n_dev && *n_dev < n) n = *n_dev;
     __shared__ uint32_t hist[256];
@@ -160,8 +130,10 @@ k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t *_
         if (idx < n) atomicAdd(&hist[dm(keys[idx])], 1u);
     }
     __syncthreads();
+    // digit-major for the global scan; tile-major when each downsweep block
+    // derives its own offsets (coalesced reads there)
     for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads)
-        counts[(uint64_t)d * ntiles + blockIdx.x] = hist[d];
+        counts[tile_major ? (uint64_t)blockIdx.x * (dm.mask + 1) + d : (uint64_t)d * ntiles + blockIdx.x] = hist[d];
 }
 
 // Stable scatter of one tile.  Wave w owns keys [w*1024, (w+1)*1024) of the
@@ -215,25 +187,23 @@ k_radix_downsweep(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t 
         __shared__ uint32_t dtot[257];
         for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) {
             uint32_t tot = 0, before = 0;
+            const uint32_t nb = dm.mask + 1;
+#pragma unroll 8
             for (uint32_t t = 0; t < ntiles; t++) {
-                uint32_t c = offs[(uint64_t)d * ntiles + t];
+                const uint32_t c = offs[(uint64_t)t * nb + d];   // tile-major: coalesced over d
                 tot += c;
-                if (t < blockIdx.x) before += c;
+                before += t < blockIdx.x ? c : 0u;
             }
             dtot[d] = tot;
             goff[d] = before;
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (uint32_t d = 0; d <= dm.mask; d++) {
-                uint32_t t = dtot[d];
-                dtot[d] = run;
-                run += t;
-            }
-        }
-        __syncthreads();
-        for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) goff[d] += dtot[d];
+        // one digit per thread (at most 256 digits, 256 threads)
+        __shared__ uint32_t sl[kSortThreads / kWave + 1];
+        const uint32_t d = threadIdx.x;
+        uint32_t tot;
+        const uint32_t ex = block_exclusive_scan(d <= dm.mask ? dtot[d] : 0u, &tot, sl);
+        if (d <= dm.mask) goff[d] += ex;
     }
     for (uint32_t d = threadIdx.x; d <= dm.mask; d += kSortThreads) {
         uint32_t run = 0;
@@ -410,13 +380,13 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
         const int fuse = ntiles <= kFuseTiles;
         if (small) {
             hipLaunchKernelGGL(k_radix_upsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
-                               s, src, n, n_dev, dm, (uint32_t)ntiles, counts);
+                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts);
             if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
             hipLaunchKernelGGL(k_radix_downsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads),
                                0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
         } else {
             hipLaunchKernelGGL(k_radix_upsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
-                               s, src, n, n_dev, dm, (uint32_t)ntiles, counts);
+                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts);
             if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
             hipLaunchKernelGGL(k_radix_downsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads),
                                0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);

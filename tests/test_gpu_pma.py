@@ -327,12 +327,17 @@ def test_mirror_tracks_every_batch(kind):
     g.close()
 
 
-def test_pull_and_push_pagerank_agree_on_rmat():
+@pytest.mark.parametrize("mode", ["binned", "pull", "push"])
+def test_spmv_modes_match_oracle_on_rmat(mode, monkeypatch):
+    """All three SpMV forms (destination bins, pull over the mirror, push with
+    atomics) on R-MAT scale 13 against the fp64 oracle."""
     from paper_1709_05061_amd import GPMA
+    monkeypatch.setenv("GPMA_SPMV", mode)
     u = np.unique(npu64(synth.rmat_unique(13, 16 << 13, seed=9)))
     V = 1 << 13
     a = GPMA(V, dev(u), mirror=True)
     b = GPMA(V, dev(u), mirror=False)
+    say("spmv", mode)
     xa = a.pagerank(iters=10).cpu().numpy()
     xb = b.pagerank(iters=10).cpu().numpy()
     want = O.pagerank(V, u, iters=10)
@@ -340,3 +345,35 @@ def test_pull_and_push_pagerank_agree_on_rmat():
     assert np.max(np.abs(xb - want) / want) < PR_RTOL
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("case", ["rmat16", "powerlaw_ragged"])
+def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
+    """Destination bins of 8192 vertices: R-MAT scale 16 puts ~40% of its
+    ~1M edges into bin 0, which is cut into several accumulation pieces
+    (fp64 atomics between pieces); a power-law graph on 70001 vertices ends
+    in a partial bin.  Warm-started calls after updates too."""
+    from paper_1709_05061_amd import GPMA
+    monkeypatch.setenv("GPMA_SPMV", "binned")
+    if case == "rmat16":
+        V = 1 << 16
+        u = np.unique(npu64(synth.rmat_unique(16, 16 << 16, seed=4)))
+    else:
+        V = 70001
+        u = np.unique(npu64(synth.powerlaw_edges(V, 600000, seed=6)))
+    say("binned", case, V, len(u))
+    half = len(u) // 2
+    g = GPMA(V, dev(u[:half]))
+    ref = O.OraclePMA(V, u[:half], g.leaf_size)
+    x = g.pagerank(iters=10).cpu().numpy()
+    want = O.pagerank(V, u[:half], iters=10)
+    assert np.max(np.abs(x - want) / want) < PR_RTOL
+    for t, (op, keys) in enumerate([("insert", u[half:]), ("delete", u[: half // 3])]):
+        getattr(g, op)(dev(keys))
+        getattr(ref, op)(keys)
+        edges = O.edge_keys(ref.slots())
+        xin = x.copy()
+        x = g.pagerank(init=torch.from_numpy(xin).cuda(), iters=5).cpu().numpy()
+        want = O.pagerank(V, edges, x0=xin, iters=5)
+        assert np.max(np.abs(x - want) / want) < PR_RTOL, (case, t)
+    g.close()
