@@ -425,8 +425,8 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
 void do_locate(gpma *g, const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, uint32_t *leaf,
                uint8_t *status, hipStream_t s) {
     if (g->learned && g->loc)
-        launch_locate_learned(keys, n_dev, n_max, g->slots, g->L, g->lf_log2, g->loc, g->ctl, leaf, status,
-                              &g->ctl->misses, s);
+        launch_locate_learned(keys, n_dev, n_max, g->slots, g->row_ptr, g->L, g->lf_log2, g->loc, g->ctl, leaf,
+                              status, &g->ctl->misses, s);
     else
         launch_locate(keys, n_dev, n_max, g->slots, g->L, g->lf, g->ctl, leaf, status, s);
 }
@@ -468,63 +468,72 @@ uint16_t host_bf16(float f) {
     return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
-// Fit the model to the current leaf pivots: knots at pivot quantiles, layer 2
-// by least squares on (up to) 2^16 sampled pivots, then the error bound over
-// every pivot with the device inference code.
+// Fit the model to the current leaf pivots: knots at quantiles of the pivots'
+// destinations, layer 2 by least squares on (up to) 2^16 sampled long-row
+// pivots, then the error bounds over every long-row pivot with the device
+// inference code.  With no long rows the model is the skip term alone.
 int locator_fit(gpma *g, hipStream_t s) {
     if (!g->loc) {
         int e = GPMA_OK;
         e |= dev_alloc(&g->loc, 1);
         e |= dev_alloc(&g->loc_gram, loc_gram_words());
-        e |= dev_alloc(&g->loc_err, 1);
+        e |= dev_alloc(&g->loc_err, 2);
         if (e) return GPMA_ENOMEM;
     }
     const uint64_t L = g->L;
     const uint64_t S = std::min<uint64_t>(L, 1u << 16), stride = L / S;
-    // knots: x of 32 evenly spaced pivots
-    uint64_t piv[32];
-    const uint64_t step = L >= 32 ? L / 32 : 1;
-    const uint64_t np = std::min<uint64_t>(32, L);
-    hipMemcpy2DAsync(piv, sizeof(uint64_t), g->slots, (step << g->lf_log2) * sizeof(uint64_t), sizeof(uint64_t),
-                     np, hipMemcpyDeviceToHost, s);
+    // knots: destinations of up to 1024 evenly spaced pivots, sorted
+    const uint64_t np = std::min<uint64_t>(1024, L);
+    const uint64_t step = L / np;
+    std::vector<uint64_t> piv(np);
+    hipMemcpy2DAsync(piv.data(), sizeof(uint64_t), g->slots, (step << g->lf_log2) * sizeof(uint64_t),
+                     sizeof(uint64_t), np, hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
+    std::vector<uint32_t> dsts;
+    for (uint64_t k : piv)
+        if ((uint32_t)k != GPMA_GUARD_DST) dsts.push_back((uint32_t)k);
+    std::sort(dsts.begin(), dsts.end());
     LocModel m{};
     m.V = g->V;
     m.inv_v = 1.0f / (float)g->V;
     m.inv_v1 = 1.0f / (float)((double)g->V + 1.0);
     m.L = (uint32_t)L;
     for (int u = 0; u < 31; u++) {
-        const uint64_t k = piv[std::min<uint64_t>((uint64_t)u * np / 31, np - 1)];
-        m.w1x[u] = 1.0f;
-        m.w1y[u] = 0.0f;
-        m.b1[u] = -(float)(k >> 32) * m.inv_v;
+        const float q = dsts.empty() ? (float)u / 31.0f
+                                     : (float)dsts[std::min<size_t>((size_t)u * dsts.size() / 31, dsts.size() - 1)] * m.inv_v1;
+        m.w1x[u] = 0.0f;
+        m.w1y[u] = 1.0f;
+        m.b1[u] = -q;
     }
-    m.w1x[31] = 0.0f;
-    m.w1y[31] = 1.0f;
+    m.w1x[31] = 1.0f;   // the row: R-MAT destinations depend on the source's bits
+    m.w1y[31] = 0.0f;
     m.b1[31] = 0.0f;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
     hipMemsetAsync(g->loc_gram, 0, loc_gram_words() * sizeof(double), s);
-    launch_loc_gram(g->slots, L, g->lf_log2, stride, S, g->loc, g->loc_gram, s);
+    launch_loc_gram(g->slots, g->row_ptr, L, g->lf_log2, stride, S, g->loc, g->loc_gram, s);
     std::vector<double> gram(loc_gram_words());
     hipMemcpyAsync(gram.data(), g->loc_gram, gram.size() * sizeof(double), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
     const int F = 33;
-    std::vector<double> A(gram.begin(), gram.begin() + F * F), b(gram.begin() + F * F, gram.end());
-    if (!solve_spd(A, b, F)) {
-        g->loc_h = m;   // invalid: every lookup falls back
-        return GPMA_OK;
+    const double samples = gram[32 * F + 32];   // bias x bias: the number of samples used
+    if (samples >= 64.0) {
+        std::vector<double> A(gram.begin(), gram.begin() + F * F), b(gram.begin() + F * F, gram.end());
+        if (solve_spd(A, b, F)) {
+            for (int u = 0; u < 32; u++) m.w2[u] = host_bf16((float)b[u]);
+            m.b2 = (float)b[32];
+        }
     }
-    for (int u = 0; u < 32; u++) m.w2[u] = host_bf16((float)b[u]);
-    m.b2 = (float)b[32];
     m.eps = 0;
+    m.delta = 0.f;
     m.valid = 0;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
-    hipMemsetAsync(g->loc_err, 0, sizeof(uint32_t), s);
-    launch_loc_eval(g->slots, L, g->lf_log2, g->loc, g->loc_err, s);
-    uint32_t err = 0;
-    hipMemcpyAsync(&err, g->loc_err, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    hipMemsetAsync(g->loc_err, 0, 2 * sizeof(uint32_t), s);
+    launch_loc_eval(g->slots, g->row_ptr, L, g->lf_log2, g->loc, g->loc_err, s);
+    uint32_t err[2] = {0, 0};
+    hipMemcpyAsync(err, g->loc_err, sizeof(err), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
-    m.eps = err + 1;   // keys between pivots may sit one leaf further
+    m.eps = err[0];
+    memcpy(&m.delta, &err[1], sizeof(float));
     m.valid = 1;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
     hipStreamSynchronize(s);
@@ -534,8 +543,6 @@ int locator_fit(gpma *g, hipStream_t s) {
     return GPMA_OK;
 }
 
-// after a batch: count lookups and misses; refit when the array was rebuilt,
-// every 64 batches, or when more than 1/16 of the lookups missed
 int locator_after_batch(gpma *g, uint64_t lookups, uint64_t misses, bool rebuilt, hipStream_t s) {
     if (!g->learned) return GPMA_OK;
     g->loc_lookups += lookups;

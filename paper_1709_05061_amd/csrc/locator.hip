@@ -1,21 +1,27 @@
-// Learned segment locator: a small model of the key CDF predicts each
-// update's leaf, and an exact bounded search corrects it, so the result is
-// always the leaf BinarySearchLeafSegments would return (Algorithm "GPMA+
+// Learned segment locator: the leaf an update goes to is found from a model
+// of where keys sit, and an exact bounded search corrects it, so the result
+// is always the leaf BinarySearchLeafSegments would return (Algorithm "GPMA+
 // Segment-Oriented Insertion"; the model is a design addition, not the
 // paper's).
 //
-// Model: x = src/V, y = dst'/(V+1) (dst' = V for a guard), 32 hidden units
-// h = relu(W1 [x y]^T + b1), position = x + w2 . h + b2, leaf =
-// floor(position * L).  Layer 1 (a K=2 product that needs full input
-// precision) runs on the vector ALU in fp32; layer 2 runs on MFMA
+// The key CDF has two parts.  The source part is known exactly: row u runs
+// from just after guard u-1 to guard u, and the CSR offsets kept with the
+// array (Section 4.2) give both positions, so the key's leaf lies in the
+// row's leaf span [first, last].  The destination part -- how far through
+// its row's span a key with destination v sits -- is learned: x = u/V,
+// y = v/(V+1), 32 hidden units h = relu(W1 [x y]^T + b1), t = y + w2 . h + b2,
+// predicted leaf = first + floor(t * span).  Rows spanning at most kMinSpan
+// leaves are searched directly.  Layer 1 (a K=2 product that needs full
+// input precision) runs on the vector ALU in fp32; layer 2 runs on MFMA
 // (v_mfma_f32_16x16x16_bf16, fp32 accumulate) with bf16 weights, the
 // activations split into a bf16 high part and a bf16 low part (two MFMAs),
 // which keeps about 16 bits of each activation.
 //
-// The error bound eps is measured over every leaf pivot with this same code;
-// a lookup searches [pred-eps, pred+eps], checks that the window brackets
-// the key (pivot[lo] <= k < pivot[hi+1]) and otherwise falls back to the
-// full binary search.
+// The bound delta (in fractions of a span) is measured over every long-row
+// leaf pivot with this same code; a lookup searches the window of
+// delta*span + 1 leaves around the prediction, checks that the window
+// brackets the key (pivot[lo] <= k < pivot[hi+1]) and otherwise falls back
+// to a binary search over the whole span.
 #include "common.h"
 #include "locator.h"
 
@@ -85,14 +91,26 @@ __device__ __forceinline__ float model_position(const LocModel &m, uint64_t kq, 
     wave_lds_sync();
     const float r = s_out[lane];
     wave_lds_sync();
-    return xq + r + m.b2;
+    return yq + r + m.b2;
 }
 
-__device__ __forceinline__ uint64_t predict_leaf(const LocModel &m, float pos) {
-    float f = floorf(pos * (float)m.L);
+// leaf span of row u: from the leaf of guard u-1 (leaf 0 for u = 0) to the
+// leaf of guard u; row_ptr[u] is one past guard u-1
+struct Span {
+    uint64_t first, last;
+};
+__device__ __forceinline__ Span row_span(const uint32_t *row_ptr, uint32_t u, uint32_t lf_log2) {
+    const uint64_t rs = u ? row_ptr[u] : 0;
+    const uint64_t re = row_ptr[u + 1];
+    return Span{rs ? (rs - 1) >> lf_log2 : 0, (re - 1) >> lf_log2};
+}
+
+__device__ __forceinline__ uint64_t predict_in_span(float t, const Span &sp) {
+    const uint64_t n = sp.last - sp.first + 1;
+    float f = floorf(t * (float)n);
     if (!(f >= 0.f)) f = 0.f;
-    if (f > (float)(m.L - 1)) f = (float)(m.L - 1);
-    return (uint64_t)f;
+    if (f > (float)(n - 1)) f = (float)(n - 1);
+    return sp.first + (uint64_t)f;
 }
 
 // the largest leaf j in [lo, hi] with pivot(j) <= k (lo if none)
@@ -110,9 +128,9 @@ __device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t
 // the end use key 0), then each lane corrects its own prediction.
 __global__ void __launch_bounds__(256)
 k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-                 const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2,
-                 const LocModel *__restrict__ model, const Ctl *__restrict__ ctl, uint32_t *__restrict__ leaf,
-                 uint8_t *__restrict__ status, uint32_t *__restrict__ misses) {
+                 const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L,
+                 uint32_t lf_log2, const LocModel *__restrict__ model, const Ctl *__restrict__ ctl,
+                 uint32_t *__restrict__ leaf, uint8_t *__restrict__ status, uint32_t *__restrict__ misses) {
     __shared__ float s_out[256];
     const LocModel m = *model;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -120,19 +138,26 @@ k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
     if ((uint64_t)blockIdx.x * blockDim.x >= n || ctl->err) return;   // block-uniform
     const bool active = i < n;
     const uint64_t k = active ? keys[i] : 0;
-    const float pos = model_position(m, k, s_out + (threadIdx.x & ~63u));
+    const float t = model_position(m, k, s_out + (threadIdx.x & ~63u));
     if (!active) return;
-    const uint64_t p = predict_leaf(m, pos);
-    const uint64_t lo = p > m.eps ? p - m.eps : 0;
-    const uint64_t hi = p + m.eps < L - 1 ? p + m.eps : L - 1;
-    const bool ok_lo = lo == 0 || slots[lo << lf_log2] <= k;
-    const bool ok_hi = hi == L - 1 || slots[(hi + 1) << lf_log2] > k;
+    const Span sp = row_span(row_ptr, key_src(k), lf_log2);
+    const uint64_t span = sp.last - sp.first + 1;
     uint64_t j;
-    if (m.valid && m.L == L && ok_lo && ok_hi) {
-        j = search_range(slots, lf_log2, lo, hi, k);
+    if (span <= kMinSpan) {
+        j = search_range(slots, lf_log2, sp.first, sp.last, k);
     } else {
-        j = search_range(slots, lf_log2, 0, L - 1, k);
-        atomicAdd(misses, 1u);
+        const uint64_t p = predict_in_span(t, sp);
+        const uint64_t e = (uint64_t)(m.delta * (float)span) + 2;
+        const uint64_t lo = p > sp.first + e ? p - e : sp.first;
+        const uint64_t hi = p + e < sp.last ? p + e : sp.last;
+        const bool ok_lo = lo == sp.first || slots[lo << lf_log2] <= k;
+        const bool ok_hi = hi == sp.last || slots[(hi + 1) << lf_log2] > k;
+        if (m.valid && m.L == L && ok_lo && ok_hi) {
+            j = search_range(slots, lf_log2, lo, hi, k);
+        } else {
+            j = search_range(slots, lf_log2, sp.first, sp.last, k);
+            atomicAdd(misses, 1u);
+        }
     }
     leaf[i] = (uint32_t)j;
     status[i] = kPending;
@@ -146,25 +171,34 @@ constexpr int kGram = kFeat * kFeat + kFeat; // G and r
 constexpr int kFitChunk = 128;
 
 __global__ void __launch_bounds__(256)
-k_loc_gram(const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2, uint64_t stride, uint64_t S,
-           const LocModel *__restrict__ model, double *__restrict__ gram) {
-    __shared__ double phi[kFitChunk][kFeat + 1];   // features and target
+k_loc_gram(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
+           uint64_t stride, uint64_t S, const LocModel *__restrict__ model, double *__restrict__ gram) {
+    __shared__ double phi[kFitChunk][kFeat + 1];   // features and target (all 0: not a sample)
     const LocModel m = *model;
     double acc[5] = {0, 0, 0, 0, 0};
     for (uint64_t c0 = (uint64_t)blockIdx.x * kFitChunk; c0 < S; c0 += (uint64_t)gridDim.x * kFitChunk) {
         __syncthreads();
         for (uint32_t t = threadIdx.x; t < kFitChunk; t += blockDim.x) {
             const uint64_t s = c0 + t;
+            bool use = false;
             if (s < S) {
                 const uint64_t j = s * stride;
-                float x, y;
-                key_features(slots[j << lf_log2], m.inv_v, m.inv_v1, m.V, x, y);
-                for (int u = 0; u < 32; u++) phi[t][u] = fmax((double)m.w1x[u] * x + (double)m.w1y[u] * y + (double)m.b1[u], 0.0);
-                phi[t][32] = 1.0;
-                phi[t][33] = (double)j / (double)L - (double)x;
-            } else {
-                for (int u = 0; u <= kFeat; u++) phi[t][u] = 0.0;
+                const uint64_t k = slots[j << lf_log2];
+                const Span sp = row_span(row_ptr, key_src(k), lf_log2);
+                const uint64_t span = sp.last - sp.first + 1;
+                if (!is_guard(k) && span > kMinSpan) {
+                    float x, y;
+                    key_features(k, m.inv_v, m.inv_v1, m.V, x, y);
+                    for (int u = 0; u < 32; u++)
+                        phi[t][u] = fmax((double)m.w1x[u] * x + (double)m.w1y[u] * y + (double)m.b1[u], 0.0);
+                    phi[t][32] = 1.0;
+                    // target: the middle of leaf j's share of the span, less the skip term
+                    phi[t][33] = ((double)(j - sp.first) + 0.5) / (double)span - (double)y;
+                    use = true;
+                }
             }
+            if (!use)
+                for (int u = 0; u <= kFeat; u++) phi[t][u] = 0.0;
         }
         __syncthreads();
         for (int q = 0; q < 5; q++) {
@@ -183,30 +217,43 @@ k_loc_gram(const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2, uin
     }
 }
 
-// Error bound: max |predicted leaf - j| over every leaf pivot.
+// Error bounds over every long-row leaf pivot: the largest leaf error and the
+// largest error of t against the pivot's fraction of its span.
 __global__ void __launch_bounds__(256)
-k_loc_eval(const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2, const LocModel *__restrict__ model,
-           uint32_t *__restrict__ max_err) {
+k_loc_eval(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
+           const LocModel *__restrict__ model, uint32_t *__restrict__ err) {
     __shared__ float s_out[256];
     const LocModel m = *model;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     uint32_t worst = 0;
+    float worst_f = 0.f;
     // the loop bound is wave-uniform (L is a multiple of 64 or the wave is the last)
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < L; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
         const uint64_t k = j < L ? slots[j << lf_log2] : 0;
-        const float pos = model_position(m, k, s_out + (threadIdx.x & ~63u));
-        if (j < L) {
-            const uint64_t p = predict_leaf(m, pos);
-            const uint64_t d = p > j ? p - j : j - p;
-            worst = d > worst ? (uint32_t)d : worst;
+        const float t = model_position(m, k, s_out + (threadIdx.x & ~63u));
+        if (j < L && !is_guard(k)) {
+            const Span sp = row_span(row_ptr, key_src(k), lf_log2);
+            const uint64_t span = sp.last - sp.first + 1;
+            if (span > kMinSpan) {
+                const uint64_t p = predict_in_span(t, sp);
+                const uint64_t d = p > j ? p - j : j - p;
+                worst = d > worst ? (uint32_t)d : worst;
+                const float fe = fabsf(t - (float)(((double)(j - sp.first) + 0.5) / (double)span));
+                worst_f = fe > worst_f ? fe : worst_f;
+            }
         }
     }
     for (int d = kWave / 2; d >= 1; d >>= 1) {
         const uint32_t o = __shfl_xor(worst, d, kWave);
         worst = o > worst ? o : worst;
+        const float of = __shfl_xor(worst_f, d, kWave);
+        worst_f = of > worst_f ? of : worst_f;
     }
-    if (__lane_id() == 0) atomicMax(max_err, worst);
+    if (__lane_id() == 0) {
+        atomicMax(&err[0], worst);
+        atomicMax(&err[1], __float_as_uint(worst_f));   // non-negative floats order as their bits
+    }
 }
 
 }  // namespace
@@ -214,28 +261,28 @@ k_loc_eval(const uint64_t *__restrict__ slots, uint64_t L, uint32_t lf_log2, con
 namespace gpma_host {
 
 void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
-                           uint64_t L, uint32_t lf_log2, const LocModel *model, const Ctl *ctl, uint32_t *leaf,
-                           uint8_t *status, uint32_t *misses, hipStream_t s) {
+                           const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, const LocModel *model,
+                           const Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses, hipStream_t s) {
     if (!n_max) return;
     hipLaunchKernelGGL(k_locate_learned, dim3((uint32_t)((n_max + 255) / 256)), dim3(256), 0, s, keys, n_dev,
-                       n_max, slots, L, lf_log2, model, ctl, leaf, status, misses);
+                       n_max, slots, row_ptr, L, lf_log2, model, ctl, leaf, status, misses);
 }
 
 size_t loc_gram_words() { return kGram; }
 
-void launch_loc_gram(const uint64_t *slots, uint64_t L, uint32_t lf_log2, uint64_t stride, uint64_t S,
-                     const LocModel *model, double *gram, hipStream_t s) {
+void launch_loc_gram(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, uint64_t stride,
+                     uint64_t S, const LocModel *model, double *gram, hipStream_t s) {
     uint64_t blocks = (S + kFitChunk - 1) / kFitChunk;
     if (blocks > 128) blocks = 128;
-    hipLaunchKernelGGL(k_loc_gram, dim3((uint32_t)blocks), dim3(256), 0, s, slots, L, lf_log2, stride, S, model,
-                       gram);
+    hipLaunchKernelGGL(k_loc_gram, dim3((uint32_t)blocks), dim3(256), 0, s, slots, row_ptr, L, lf_log2, stride, S,
+                       model, gram);
 }
 
-void launch_loc_eval(const uint64_t *slots, uint64_t L, uint32_t lf_log2, const LocModel *model, uint32_t *max_err,
-                     hipStream_t s) {
+void launch_loc_eval(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2,
+                     const LocModel *model, uint32_t *err, hipStream_t s) {
     uint64_t blocks = (L + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, slots, L, lf_log2, model, max_err);
+    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, slots, row_ptr, L, lf_log2, model, err);
 }
 
 }  // namespace gpma_host

@@ -1,6 +1,8 @@
-"""Learned segment locator: the MFMA model plus bounded search returns the
-binary-search leaf for every key, keeps the layout slot-identical to the
-oracle, and on a uniform graph its error window is a few leaves."""
+"""Learned segment locator: the row span from the CSR offsets plus the MFMA
+model of the destination's place in it, corrected by a bounded search,
+returns the binary-search leaf for every key and keeps the layout
+slot-identical to the oracle; its window stays far below the array and
+fallbacks are rare."""
 import numpy as np
 import pytest
 import torch
@@ -42,6 +44,7 @@ def test_learned_locate_equals_binary_search(kind):
         assert info["misses"] * 100 <= info["lookups"]
     else:
         assert info["eps"] < learned.capacity // 32   # a real window, not the whole array
+        assert info["misses"] * 20 <= info["lookups"]
     learned.close()
     plain.close()
 
