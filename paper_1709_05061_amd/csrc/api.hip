@@ -655,12 +655,11 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
 
     // Sort(U) and drop repeats
     hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
-    launch_validate(keys, b, g->V, g->ctl, s);
     const uint32_t sb = bit_width(g->V - 1);
     const uint64_t *sorted;
     {
         ProfScope ps(g, GPMA_K_SORT, s);
-        sorted = radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s);
+        sorted = radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s, nullptr, g->ctl);
         ps.done(16.0 * (double)b * (double)((2 * sb + 7) / 8));
     }
     uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
@@ -777,9 +776,8 @@ int ensure_fused(gpma *g) {
 void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc, uint32_t *stop,
                           bool transpose, hipStream_t s, gpma::GraphEntry *ge) {
     launch_fetch(desc, g->fs, stop, g->kS, g->cur_n, g->ctl, transpose, cls, s);
-    launch_validate(g->kS, cls, g->V, g->ctl, s, g->cur_n);
     const uint32_t sb = bit_width(g->V - 1);
-    const uint64_t *sorted = radix_sort_keys(g->kS, cls, sb, sb, g->V, g->kA, g->kB, g->tmp, s, g->cur_n);
+    const uint64_t *sorted = radix_sort_keys(g->kS, cls, sb, sb, g->V, g->kA, g->kB, g->tmp, s, g->cur_n, g->ctl);
     uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
     LevelArrays cur{ukeys, g->leafA, g->stA, &g->ctl->n_in};
     LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};

@@ -117,18 +117,26 @@ struct DigitMap {
 template <int CH>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_upsweep(const uint64_t *__restrict__ keys, uint64_t n, const uint32_t *__restrict__ n_dev,
-                DigitMap dm, uint32_t ntiles, int tile_major, uint32_t *__restrict__ counts) {
+                DigitMap dm, uint32_t ntiles, int tile_major, uint32_t *__restrict__ counts,
+                Ctl *__restrict__ check) {
     constexpr int kSortTile = kSortThreads * CH;
     if (n_dev && *n_dev < n) n = *n_dev;
     __shared__ uint32_t hist[256];
     for (int i = threadIdx.x; i < 256; i += kSortThreads) hist[i] = 0;
     __syncthreads();
     uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+    bool bad = false;
 #pragma unroll 4
     for (int i = 0; i < CH; i++) {
         uint64_t idx = base + (uint64_t)i * kSortThreads + threadIdx.x;
-        if (idx < n) atomicAdd(&hist[dm(keys[idx])], 1u);
+        if (idx < n) {
+            const uint64_t k = keys[idx];
+            atomicAdd(&hist[dm(k)], 1u);
+            bad |= key_src(k) >= dm.V || key_dst(k) >= dm.V;
+        }
     }
+    // batch validation rides on the first pass: src < V and dst < V
+    if (check && __ballot(bad) && __lane_id() == 0) atomicOr(&check->err, 1u);
     __syncthreads();
     // digit-major for the global scan; tile-major when each downsweep block
     // derives its own offsets (coalesced reads there)
@@ -303,6 +311,170 @@ __global__ void k_scatter_pending(const uint64_t *__restrict__ keys, const uint3
     status_out[p] = kPending;
 }
 
+// Two-launch compaction for up to kCmpMaxTiles tiles of kCmpTile items: a
+// count pass writes per-tile totals (and statistics), a scatter pass derives
+// its tile's offset from the totals before it, scans its items in order and
+// writes the kept ones.  Block 0 of the scatter pass publishes the total.
+constexpr int kCmpItems = 8;
+constexpr int kCmpTile = 256 * kCmpItems;
+constexpr uint64_t kCmpMaxTiles = 1024;
+
+template <int N>
+__device__ __forceinline__ void block_sum_n(uint32_t (&v)[N], uint32_t (*lds)[256 / kWave]) {
+#pragma unroll
+    for (int k = 0; k < N; k++)
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) v[k] += __shfl_xor(v[k], d, kWave);
+    const int w = threadIdx.x / kWave;
+    __syncthreads();
+    if (__lane_id() == 0)
+#pragma unroll
+        for (int k = 0; k < N; k++) lds[k][w] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N; k++) {
+        uint32_t t = 0;
+        for (int j = 0; j < 256 / kWave; j++) t += lds[k][j];
+        v[k] = t;
+    }
+}
+
+// sum of tile counts before tile t, and of all tiles
+__device__ __forceinline__ void tile_prefix(const uint32_t *__restrict__ cnt, uint32_t ntiles, uint32_t t,
+                                            uint32_t *before, uint32_t *total) {
+    __shared__ uint32_t lds[2][256 / kWave];
+    uint32_t v[2] = {0, 0};
+    for (uint32_t i = threadIdx.x; i < ntiles; i += blockDim.x) {
+        const uint32_t c = cnt[i];
+        v[1] += c;
+        v[0] += i < t ? c : 0u;
+    }
+    block_sum_n<2>(v, lds);
+    *before = v[0];
+    *total = v[1];
+}
+
+__device__ __forceinline__ uint64_t dyn_limit(const uint32_t *n_dev, uint64_t n_max) {
+    if (!n_dev) return n_max;
+    const uint64_t n = *n_dev;
+    return n < n_max ? n : n_max;
+}
+
+__device__ __forceinline__ bool unique_head(const uint64_t *a, uint64_t i, uint64_t lim) {
+    return i < lim && (i == 0 || a[i] != a[i - 1]);
+}
+
+__global__ void __launch_bounds__(256)
+k_unique_count(const uint64_t *__restrict__ a, uint64_t n_max, const uint32_t *__restrict__ n_dev,
+               uint32_t *__restrict__ tile_cnt) {
+    __shared__ uint32_t lds[1][256 / kWave];
+    const uint64_t lim = dyn_limit(n_dev, n_max);
+    const uint64_t base = (uint64_t)blockIdx.x * kCmpTile;
+    uint32_t v[1] = {0};
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++) v[0] += unique_head(a, base + q * 256 + threadIdx.x, lim) ? 1u : 0u;
+    block_sum_n<1>(v, lds);
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(256)
+k_unique_scatter(const uint64_t *__restrict__ a, uint64_t n_max, const uint32_t *__restrict__ n_dev,
+                 const uint32_t *__restrict__ tile_cnt, uint32_t ntiles, uint64_t *__restrict__ out,
+                 uint32_t *__restrict__ count_dev) {
+    __shared__ uint32_t lds[256 / kWave + 1];
+    uint32_t before, total;
+    tile_prefix(tile_cnt, ntiles, blockIdx.x, &before, &total);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_dev = total;
+    const uint64_t lim = dyn_limit(n_dev, n_max);
+    const uint64_t base = (uint64_t)blockIdx.x * kCmpTile + (uint64_t)threadIdx.x * kCmpItems;
+    uint32_t f = 0;
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++) f |= (unique_head(a, base + q, lim) ? 1u : 0u) << q;
+    uint32_t tot;
+    uint32_t pos = before + block_exclusive_scan(__popc(f), &tot, lds);
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++)
+        if (f & (1u << q)) out[pos++] = a[base + q];
+}
+
+// pending updates per tile, plus the level's statistics per tile:
+// st[0..ntiles) pending, then done, noop, merged-segment heads
+__global__ void __launch_bounds__(256)
+k_pending_count(const uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+                uint32_t ntiles, uint32_t *__restrict__ st) {
+    __shared__ uint32_t lds[4][256 / kWave];
+    const uint64_t n = dyn_limit(n_dev, n_max);
+    const uint64_t base = (uint64_t)blockIdx.x * kCmpTile;
+    uint32_t v[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++) {
+        const uint64_t i = base + q * 256 + threadIdx.x;
+        if (i < n) {
+            const uint8_t x = status[i];
+            const uint8_t state = x & kStateMask;
+            v[0] += state == kPending;
+            v[1] += state == kDone;
+            v[2] += state == kNoop;
+            v[3] += (x & kHead) ? 1u : 0u;
+        }
+    }
+    block_sum_n<4>(v, lds);
+    if (threadIdx.x < 4) st[(uint64_t)threadIdx.x * ntiles + blockIdx.x] = v[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256)
+k_pending_scatter(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+                  const uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+                  const uint32_t *__restrict__ st, uint32_t ntiles, uint64_t *__restrict__ keys_out,
+                  uint32_t *__restrict__ leaf_out, uint8_t *__restrict__ status_out,
+                  uint32_t *__restrict__ count_dev, int del, uint64_t cap_h, Ctl *__restrict__ ctl) {
+    __shared__ uint32_t lds[256 / kWave + 1];
+    __shared__ uint32_t red[3][256 / kWave];
+    uint32_t before, total;
+    tile_prefix(st, ntiles, blockIdx.x, &before, &total);
+    if (blockIdx.x == 0) {
+        // the level's statistics, once
+        uint32_t v[3] = {0, 0, 0};
+        for (uint32_t i = threadIdx.x; i < ntiles; i += blockDim.x) {
+            v[0] += st[ntiles + i];
+            v[1] += st[2 * (uint64_t)ntiles + i];
+            v[2] += st[3 * (uint64_t)ntiles + i];
+        }
+        block_sum_n<3>(v, red);
+        if (threadIdx.x == 0) {
+            *count_dev = total;
+            if (v[0]) {
+                atomicAdd((unsigned long long *)&ctl->applied, (unsigned long long)v[0]);
+                atomicAdd((unsigned long long *)&ctl->dn,
+                          (unsigned long long)(del ? -(int64_t)v[0] : (int64_t)v[0]));
+            }
+            if (v[1]) atomicAdd((unsigned long long *)&ctl->noops, (unsigned long long)v[1]);
+            if (v[2]) {
+                atomicAdd(&ctl->segs, v[2]);
+                atomicAdd((unsigned long long *)&ctl->rewritten, (unsigned long long)(v[2] * cap_h));
+            }
+        }
+    }
+    const uint64_t n = dyn_limit(n_dev, n_max);
+    const uint64_t base = (uint64_t)blockIdx.x * kCmpTile + (uint64_t)threadIdx.x * kCmpItems;
+    uint32_t f = 0;
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++) {
+        const uint64_t i = base + q;
+        f |= (i < n && (status[i] & kStateMask) == kPending ? 1u : 0u) << q;
+    }
+    uint32_t tot;
+    uint32_t pos = before + block_exclusive_scan(__popc(f), &tot, lds);
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++)
+        if (f & (1u << q)) {
+            keys_out[pos] = keys[base + q];
+            leaf_out[pos] = leaf[base + q];
+            status_out[pos] = kPending;
+            pos++;
+        }
+}
+
 __global__ void k_flag_edges(const uint64_t *__restrict__ slots, uint64_t cap,
                              uint32_t *__restrict__ flags) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -360,7 +532,7 @@ static uint32_t bit_width(uint64_t x) {
 
 const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
                                 uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
-                                hipStream_t s, const uint32_t *n_dev) {
+                                hipStream_t s, const uint32_t *n_dev, Ctl *check) {
     (void)bit_width;
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
@@ -380,13 +552,13 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
         const int fuse = ntiles <= kFuseTiles;
         if (small) {
             hipLaunchKernelGGL(k_radix_upsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
-                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts);
+                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts, p == 0 ? check : nullptr);
             if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
             hipLaunchKernelGGL(k_radix_downsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads),
                                0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
         } else {
             hipLaunchKernelGGL(k_radix_upsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
-                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts);
+                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts, p == 0 ? check : nullptr);
             if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
             hipLaunchKernelGGL(k_radix_downsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads),
                                0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
@@ -401,6 +573,13 @@ void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max
                        uint32_t *count_dev, uint32_t *flags, uint32_t *tmp, hipStream_t s) {
     if (n_max == 0) {
         hipMemsetAsync(count_dev, 0, sizeof(uint32_t), s);
+        return;
+    }
+    const uint64_t ntiles = div_up(n_max, kCmpTile);
+    if (ntiles <= kCmpMaxTiles) {
+        hipLaunchKernelGGL(k_unique_count, dim3((uint32_t)ntiles), dim3(256), 0, s, in, n_max, n_dev, tmp);
+        hipLaunchKernelGGL(k_unique_scatter, dim3((uint32_t)ntiles), dim3(256), 0, s, in, n_max, n_dev, tmp,
+                           (uint32_t)ntiles, out, count_dev);
         return;
     }
     uint32_t g = (uint32_t)div_up(n_max, 256);
@@ -420,6 +599,15 @@ void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *
                      bool del, uint64_t cap_h, Ctl *ctl, hipStream_t s) {
     if (n_max == 0) {
         hipMemsetAsync(count_dev, 0, sizeof(uint32_t), s);
+        return;
+    }
+    const uint64_t ntiles = div_up(n_max, kCmpTile);
+    if (ntiles <= kCmpMaxTiles) {
+        hipLaunchKernelGGL(k_pending_count, dim3((uint32_t)ntiles), dim3(256), 0, s, status, n_dev, n_max,
+                           (uint32_t)ntiles, tmp);
+        hipLaunchKernelGGL(k_pending_scatter, dim3((uint32_t)ntiles), dim3(256), 0, s, keys, leaf, status, n_dev,
+                           n_max, tmp, (uint32_t)ntiles, keys_out, leaf_out, status_out, count_dev, del ? 1 : 0,
+                           cap_h, ctl);
         return;
     }
     uint32_t g = (uint32_t)div_up(n_max, 256);
