@@ -91,7 +91,7 @@ def uneven_section(args):
 
     import synth
     from paper_1709_05061_amd import GPMA
-    from paper_1709_05061_amd.autotune import autotune_leaf_size
+    from paper_1709_05061_amd.autotune import autotune
     V, m = 1_600_000, 30_000_000
     e = synth.powerlaw_edges(V, m, seed=args.seed + 20, device="cuda")
     st = synth.Stream(V, e, e.numel() // 2)
@@ -101,10 +101,12 @@ def uneven_section(args):
         ops += [1, 0]
         bs += [st.order[pos:pos + b], st.order[st.window + pos: st.window + pos + b]]
         pos += b
-    tune = autotune_leaf_size(V, st.initial(), ops[:64], bs[:64], mirror=False, cache_path=None)
+    tune = autotune(V, st.initial(), ops[:64], bs[:64], leaf_sizes=(16, 32, 64), sort_tiles=(512, 1024),
+                    mirror=False, cache_path=None)
     lf = tune["leaf_size"]
     plain = GPMA(V, st.initial(), leaf_size=lf)
-    fused = GPMA(V, st.initial(), leaf_size=lf)
+    fused = GPMA(V, st.initial(), leaf_size=lf, fused_direct=tune["fused_direct"], sort_tile=tune["sort_tile"],
+                 fused_levels=tune["fused_levels"])
     fused.apply_batches(ops[:2], bs[:2])          # captures the first graphs
     plain.delete(bs[0])
     plain.insert(bs[1])
@@ -122,7 +124,9 @@ def uneven_section(args):
     n_upd = sum(int(b.numel()) for b in bs[2:])
     out = {"workload": "power-law graph V=1.6M, 30M edges, out-degree exponent 2.1, window 15M; "
                        "%d slides of log-uniform 2^6..2^18 deletes + inserts" % (len(sizes) - 1),
-           "leaf_size": lf, "autotune_ms": tune["ms"], "updates": n_upd,
+           "leaf_size": lf, "sort_tile": tune["sort_tile"], "fused_direct": tune["fused_direct"],
+           "fused_levels": tune["fused_levels"],
+           "autotune_ms": tune["ms"], "updates": n_upd,
            "plain_updates_per_s": n_upd / t_plain, "fused_updates_per_s": n_upd / t_fused,
            "fused_speedup": t_plain / t_fused, "identical_output": same, "applied": sf.applied}
     plain.close()
@@ -191,6 +195,11 @@ def main():
     ap.add_argument("--query-rate", type=float, default=40.0)
     ap.add_argument("--service-budget-gib", type=int, default=16)
     ap.add_argument("--no-learned", action="store_true", help="binary-search locate in the main path")
+    ap.add_argument("--fused-direct", type=int, default=0,
+                    help="1: fused batches enqueue their kernels directly, 0: replay captured graphs")
+    ap.add_argument("--sort-tile", type=int, default=1024, help="keys per batch-sort workgroup tile")
+    ap.add_argument("--fused-levels", type=int, default=0,
+                    help="tree levels above the leaves each fused batch runs on the device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slides", type=int, default=16)
     ap.add_argument("--seed", type=int, default=1)
@@ -239,7 +248,8 @@ def main():
     fused_mode = not args.plain
     t0 = time.time()
     learned = not args.no_learned
-    g = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror, learned=learned)
+    g = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror, learned=learned,
+             fused_direct=bool(args.fused_direct), sort_tile=args.sort_tile, fused_levels=args.fused_levels)
     torch.cuda.synchronize()
     log("created PMA: %d edges, capacity %d slots, leaf %d in %.1fs"
         % (g.num_edges, g.capacity, g.leaf_size, time.time() - t0))
@@ -370,6 +380,8 @@ def main():
                    "scale": args.scale, "edge_factor": args.edge_factor, "batch": b,
                    "window_edges": int(st.window), "capacity": g.capacity, "leaf_size": g.leaf_size,
                    "mirror": mirror, "update_path": "fused" if fused_mode else "plain",
+                   "fused_direct": bool(args.fused_direct), "sort_tile": args.sort_tile,
+                   "fused_levels": args.fused_levels,
                    "learned_locator": learned},
         "phases_ms": phases,
         "update_ms_p50": pctl(upd_ms, 50),

@@ -72,7 +72,15 @@ typedef struct {
     uint32_t leaf_size;
     uint32_t tau_leaf_pm, tau_root_pm;
     uint32_t rho_leaf_pm, rho_root_pm;
-    uint32_t flags;     /* GPMA_FLAG_* below; other bits must be 0 */
+    uint32_t flags;           /* GPMA_FLAG_* below; other bits must be 0 */
+    uint32_t sort_tile_keys;  /* keys per workgroup tile of the batch radix sort
+                                 for batches up to 2^20: 512, 1024 or 2048
+                                 (0 = 1024); a tuning knob, results identical */
+    uint32_t fused_levels;    /* gpma_apply_batches: tree levels above the
+                                 leaves that a batch runs on the device before
+                                 handing updates still pending to the
+                                 host-driven path, 0..3 (default 1); a tuning
+                                 knob, results identical */
 } gpma_params;
 
 /* Keep a second, dst-major PMA (keys dst<<32 | src, one guard per vertex)
@@ -82,15 +90,23 @@ typedef struct {
  * array.  Not in the paper (its SpMV reads a CSR copy); a design addition. */
 #define GPMA_FLAG_MIRROR 1u
 
-/* Learned segment locator: a 2 -> 32 -> 1 MLP over (src/V, dst/V) with a
- * skip term predicts each update's leaf (layer 2 on MFMA, bf16 weights, fp32
- * accumulation); an exact search inside the measured error window corrects
- * it, checked against the window's bracketing pivots, with the full binary
- * search as fallback, so the leaf (and every later result) is identical to
- * the binary-search locate of Algorithm "GPMA+ Segment-Oriented
+/* Learned segment locator.  The row offsets bound the leaf of key (u, v) to
+ * the leaves spanned by row u; in rows spanning more than 8 leaves a
+ * 2 -> 32 -> 1 MLP over (u/V, v/(V+1)) with a skip term predicts how far
+ * through that span the key sits (layer 2 on MFMA, bf16 weights, fp32
+ * accumulation), and an exact search inside the measured error window
+ * corrects it, checked against the window's bracketing pivots, with a binary
+ * search over the span as fallback, so the leaf (and every later result) is
+ * identical to the binary-search locate of Algorithm "GPMA+ Segment-Oriented
  * Insertion".  Refitted after every rebuild of the array, every 64 batches,
  * or when more than 1/16 of a batch's lookups fall back.  A design addition. */
 #define GPMA_FLAG_LEARNED_LOCATOR 2u
+
+/* gpma_apply_batches enqueues each batch's kernels on the stream directly
+ * instead of replaying a captured HIP graph per (size class, operation).
+ * The device-side control is the same; which is faster depends on the
+ * runtime's graph launch cost (the autotuner measures both). */
+#define GPMA_FLAG_FUSED_DIRECT 4u
 
 /* Per-batch statistics; filled when a non-NULL pointer is passed. */
 typedef struct {

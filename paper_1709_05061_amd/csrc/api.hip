@@ -102,6 +102,8 @@ struct gpma {
     std::vector<GraphEntry> graphs;
     uint32_t geom_version = 1;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side = nullptr;          // fused batching: the mirror's batches run here
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     uint64_t *kS = nullptr;              // staging of the batch being replayed
     FusedState *fs = nullptr;            // device
     uint32_t *stop = nullptr;            // device; the mirror uses its primary's
@@ -118,6 +120,9 @@ struct gpma {
 
     // learned segment locator
     bool learned = false;
+    bool fused_direct = false;     // enqueue fused batches without graph capture
+    int sort_chunks = 4;           // 64-key chunks per wave in batch sort tiles
+    uint32_t fused_levels = 1;     // levels above the leaves in a fused batch
     LocModel *loc = nullptr;       // device
     LocModel loc_h{};              // host copy
     double *loc_gram = nullptr;    // device fp64 normal equations
@@ -202,7 +207,10 @@ bool params_valid(const gpma_params *p, bool allow_auto) {
           p->tau_root_pm <= p->tau_leaf_pm && p->tau_leaf_pm < 1000))
         return false;
     if (2 * p->rho_root_pm > p->tau_root_pm) return false;
-    if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR)) return false;
+    if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT)) return false;
+    if (p->sort_tile_keys != 0 && p->sort_tile_keys != 512 && p->sort_tile_keys != 1024 && p->sort_tile_keys != 2048)
+        return false;
+    if (p->fused_levels > 3) return false;
     return true;
 }
 
@@ -259,7 +267,8 @@ void prof_collect(gpma *g) {
 // scratch management
 
 void drop_graphs(gpma *g) {
-    for (auto &e : g->graphs) hipGraphExecDestroy(e.exec);
+    for (auto &e : g->graphs)
+        if (e.exec) hipGraphExecDestroy(e.exec);
     g->graphs.clear();
     g->geom_version++;
 }
@@ -659,7 +668,7 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     const uint64_t *sorted;
     {
         ProfScope ps(g, GPMA_K_SORT, s);
-        sorted = radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s, nullptr, g->ctl);
+        sorted = radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s, nullptr, g->ctl, g->sort_chunks);
         ps.done(16.0 * (double)b * (double)((2 * sb + 7) / 8));
     }
     uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
@@ -724,6 +733,11 @@ void free_all(gpma *g) {
     g->outs_h = nullptr;
     if (g->cap_stream) hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
+    if (g->side) hipStreamDestroy(g->side);
+    g->side = nullptr;
+    if (g->ev_fork) hipEventDestroy(g->ev_fork);
+    if (g->ev_join) hipEventDestroy(g->ev_join);
+    g->ev_fork = g->ev_join = nullptr;
     dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
@@ -746,9 +760,6 @@ void free_all(gpma *g) {
 // fused batching (host side)
 
 constexpr uint32_t kFusedChunk = 4096;   // batches per descriptor table
-// levels above the leaves that a batch graph covers; a batch with updates
-// left above them stops the replay and finishes on the host-driven path
-constexpr uint32_t kFusedLevels = 2;
 
 uint64_t batch_class(uint64_t b) { return next_pow2(std::max<uint64_t>(b, 1024)); }
 
@@ -766,6 +777,9 @@ int ensure_fused(gpma *g) {
     if (hipHostMalloc((void **)&g->desc_h, kFusedChunk * sizeof(BatchDesc), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (hipHostMalloc((void **)&g->outs_h, kFusedChunk * sizeof(BatchOut), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (!e && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
+    if (!e && hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
+    if (!e && hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
+    if (!e && hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
     return e;
 }
 
@@ -777,7 +791,8 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
                           bool transpose, hipStream_t s, gpma::GraphEntry *ge) {
     launch_fetch(desc, g->fs, stop, g->kS, g->cur_n, g->ctl, transpose, cls, s);
     const uint32_t sb = bit_width(g->V - 1);
-    const uint64_t *sorted = radix_sort_keys(g->kS, cls, sb, sb, g->V, g->kA, g->kB, g->tmp, s, g->cur_n, g->ctl);
+    const uint64_t *sorted =
+        radix_sort_keys(g->kS, cls, sb, sb, g->V, g->kA, g->kB, g->tmp, s, g->cur_n, g->ctl, g->sort_chunks);
     uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
     LevelArrays cur{ukeys, g->leafA, g->stA, &g->ctl->n_in};
     LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
@@ -800,7 +815,10 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     cur = nxt;
     nxt = other(cur);
     uint32_t h_top = 0;
-    for (uint32_t h = 1; h <= kFusedLevels && h < g->H && seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds;
+    // levels above the leaves that a batch covers (g->fused_levels); a batch
+    // with updates left above them stops the sequence and finishes on the
+    // host-driven path
+    for (uint32_t h = 1; h <= g->fused_levels && h < g->H && seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds;
          h++) {
         bounds(g, g->H, h, &lo, &hi);
         launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf,
@@ -827,6 +845,10 @@ gpma::GraphEntry *get_graph(gpma *g, uint64_t cls, bool del, const BatchDesc *de
     ge.cls = cls;
     ge.del = del;
     ge.version = g->geom_version;
+    if (g->fused_direct) {   // no capture: the caller enqueues the batch itself
+        g->graphs.push_back(ge);
+        return &g->graphs.back();
+    }
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
     enqueue_device_batch(g, del, cls, desc, stop, transpose, g->cap_stream, &ge);
@@ -897,72 +919,101 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
     // buffers are free to rewrite
     for (uint32_t i = 0; i < count; i++) g->desc_h[i] = BatchDesc{keys[i], sizes[i]};
     hipMemcpyAsync(g->desc, g->desc_h, count * sizeof(BatchDesc), hipMemcpyHostToDevice, s);
-    hipMemsetAsync(g->stop, 0, sizeof(uint32_t), s);
-    reset_fused(g, 0, s);
-    if (m) reset_fused(m, 0, s);
-    uint32_t next = 0;
-    while (next < count) {
-        for (uint32_t i = next; i < count; i++) {
-            const uint64_t cls = batch_class(sizes[i]);
-            gpma::GraphEntry *ge = get_graph(g, cls, ops[i] != 0, g->desc, g->stop, false);
-            if (!ge) return GPMA_EDEVICE;
-            if (hipGraphLaunch(ge->exec, s) != hipSuccess) return GPMA_EDEVICE;
-            if (m) {
-                gpma::GraphEntry *gm = get_graph(m, cls, ops[i] != 0, g->desc, g->stop, true);
-                if (!gm) return GPMA_EDEVICE;
-                if (hipGraphLaunch(gm->exec, s) != hipSuccess) return GPMA_EDEVICE;
+    // The array and its mirror advance independently, each on its own stream
+    // with its own stop flag (the mirror's batches are the transposed keys);
+    // a handle that stops is completed on the host and resumes after that
+    // batch.  Batches are enqueued in windows: a stop wastes at most the rest
+    // of its window, and the window grows while batches complete on the
+    // device and shrinks after a stop.
+    struct Prog {
+        gpma *h;
+        hipStream_t st;
+        bool transpose;
+        uint32_t next;
+        bool failed;
+    };
+    Prog P[2] = {{g, s, false, 0, false}, {m, m ? m->side : s, true, 0, false}};
+    const int nh = m ? 2 : 1;
+    for (int k = 0; k < nh; k++) {
+        hipMemsetAsync(P[k].h->stop, 0, sizeof(uint32_t), s);
+        reset_fused(P[k].h, 0, s);
+    }
+    uint32_t window = 8;
+    int err = GPMA_OK;
+    uint32_t err_at = count;
+    auto busy = [&](int k) { return !P[k].failed && P[k].next < count; };
+    while (busy(0) || (nh > 1 && busy(1))) {
+        uint32_t end[2] = {0, 0};
+        if (nh > 1) {
+            hipEventRecord(g->ev_fork, s);
+            hipStreamWaitEvent(P[1].st, g->ev_fork, 0);
+        }
+        for (int k = 0; k < nh; k++) end[k] = busy(k) ? std::min(count, P[k].next + window) : P[k].next;
+        // interleave the two streams' batches so both have work queued early
+        for (uint32_t j = 0; j < window; j++) {
+            for (int k = 0; k < nh; k++) {
+                const uint32_t i = P[k].next + j;
+                if (i >= end[k]) continue;
+                gpma *h = P[k].h;
+                const uint64_t cls = batch_class(sizes[i]);
+                gpma::GraphEntry *ge = get_graph(h, cls, ops[i] != 0, g->desc, h->stop, P[k].transpose);
+                if (!ge) return GPMA_EDEVICE;
+                if (h->fused_direct)
+                    enqueue_device_batch(h, ops[i] != 0, cls, g->desc, h->stop, P[k].transpose, P[k].st, ge);
+                else if (hipGraphLaunch(ge->exec, P[k].st) != hipSuccess)
+                    return GPMA_EDEVICE;
             }
         }
-        read_fused(g, s);
-        if (m) read_fused(m, s);
-        hipMemcpyAsync(g->stop_h, g->stop, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-        hipMemcpyAsync(g->outs_h + next, g->outs + next, (count - next) * sizeof(BatchOut),
-                       hipMemcpyDeviceToHost, s);
-        if (m)
-            hipMemcpyAsync(m->outs_h + next, m->outs + next, (count - next) * sizeof(BatchOut),
-                           hipMemcpyDeviceToHost, s);
-        if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
-        const uint32_t bg = g->fs_h->batch, bm = m ? m->fs_h->batch : bg;
-        const bool hg = g->fs_h->halted != 0, hm = m ? m->fs_h->halted != 0 : false;
-        account(g, next, bg, total);
-        if (m) account(m, next, bm, nullptr);
-        if (!*g->stop_h) {
-            next = count;
-            break;
+        if (nh > 1) {
+            hipEventRecord(g->ev_join, P[1].st);
+            hipStreamWaitEvent(s, g->ev_join, 0);
         }
-        // one handle stopped at batch b with updates left above the graph's levels
-        const uint32_t b = hg ? bg : bm;
-        const bool del = ops[b] != 0;
-        int e = GPMA_OK;
-        if (hg) {
-            e = complete_stopped(g, del, s, total);
+        for (int k = 0; k < nh; k++) {
+            gpma *h = P[k].h;
+            read_fused(h, s);
+            hipMemcpyAsync(h->stop_h, h->stop, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+            if (end[k] > P[k].next)
+                hipMemcpyAsync(h->outs_h + P[k].next, h->outs + P[k].next, (end[k] - P[k].next) * sizeof(BatchOut),
+                               hipMemcpyDeviceToHost, s);
+        }
+        if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
+        bool stopped = false;
+        for (int k = 0; k < nh; k++) {
+            if (end[k] == P[k].next) continue;   // idle this round
+            gpma *h = P[k].h;
+            const uint32_t b = h->fs_h->batch;
+            account(h, P[k].next, b, k == 0 ? total : nullptr);
+            if (!*h->stop_h) {
+                P[k].next = end[k];
+                continue;
+            }
+            // stopped at batch b with updates left above the device levels
+            stopped = true;
+            int e = complete_stopped(h, ops[b] != 0, s, k == 0 ? total : nullptr);
+            if (e == GPMA_EINVAL) {   // an invalid key: batches before b stand
+                P[k].failed = true;
+                P[k].next = b;
+                err = GPMA_EINVAL;
+                err_at = std::min(err_at, b);
+                continue;
+            }
             if (e) {
                 *done_out = b;
                 return e;
             }
-            if (total) total->noops += g->ctl_h->noops;
-            if (m) {
-                if (sizes[b] > g->tkeys_cap) {
-                    dev_free(g->tkeys);
-                    g->tkeys_cap = 0;
-                    if (dev_alloc(&g->tkeys, next_pow2(sizes[b]))) return GPMA_ENOMEM;
-                    g->tkeys_cap = next_pow2(sizes[b]);
-                }
-                launch_transpose_keys(keys[b], sizes[b], g->tkeys, s);
-                e = apply_batch(m, g->tkeys, sizes[b], del, s, nullptr);
-            }
-        } else {
-            e = complete_stopped(m, del, s, nullptr);
+            if (k == 0 && total) total->noops += h->ctl_h->noops;
+            hipMemsetAsync(h->stop, 0, sizeof(uint32_t), s);
+            if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;   // frees reset_h
+            reset_fused(h, b + 1, s);
+            P[k].next = b + 1;
         }
-        if (e) {
-            *done_out = b;
-            return e;
-        }
-        hipMemsetAsync(g->stop, 0, sizeof(uint32_t), s);
-        if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;   // frees reset_h
-        reset_fused(g, b + 1, s);
-        if (m) reset_fused(m, b + 1, s);
-        next = b + 1;
+        window = stopped ? std::max<uint32_t>(window / 2, 2) : std::min<uint32_t>(2 * window, 64);
+    }
+    if (err) {
+        // both arrays see the same keys, so both stop at the same batch
+        if (nh > 1 && (!P[0].failed || !P[1].failed || P[0].next != P[1].next)) return GPMA_EDEVICE;
+        *done_out = err_at;
+        return err;
     }
     if (m && m->n != g->n) return GPMA_EDEVICE;
     for (gpma *h : {g, m}) {
@@ -1074,6 +1125,8 @@ void gpma_default_params(gpma_params *p) {
     p->rho_leaf_pm = 80;
     p->rho_root_pm = 400;
     p->flags = 0;
+    p->sort_tile_keys = 0;
+    p->fused_levels = 1;
 }
 
 const char *gpma_strerror(int code) {
@@ -1180,6 +1233,9 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     }
     hipMemsetAsync(g->row_ptr, 0, sizeof(uint32_t), s);
     g->learned = (p.flags & GPMA_FLAG_LEARNED_LOCATOR) != 0;
+    g->fused_direct = (p.flags & GPMA_FLAG_FUSED_DIRECT) != 0;
+    g->sort_chunks = p.sort_tile_keys ? (int)(p.sort_tile_keys / 256) : 4;
+    g->fused_levels = p.fused_levels;
     launch_dispatch(uq, nu, g->slots, g->cnt, g->row_ptr, 0, g->L, lf, s);
     launch_degrees_from_sorted(uq, nu, V, fl, g->deg, s);
     if (hipStreamSynchronize(s) != hipSuccess) {
@@ -1197,7 +1253,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     }
     if (p.flags & GPMA_FLAG_MIRROR) {
         gpma_params mp = p;
-        mp.flags = p.flags & GPMA_FLAG_LEARNED_LOCATOR;
+        mp.flags = p.flags & (GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT);
         mp.leaf_size = g->lf;
         uint64_t *tk = nullptr;
         if (n && dev_alloc(&tk, n)) {

@@ -131,10 +131,13 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev
 size_t radix_tmp_words(uint64_t n);
 // n_dev (optional): the actual count, on the device (<= n, which sizes grids).
 // check (optional): the first pass also validates the keys (src < V and
-// dst < V) and sets check->err on a bad one.
+// dst < V) and sets check->err on a bad one.  small_chunks: 64-key chunks
+// per wave in the tiles of inputs up to 2^20 keys (2, 4 or 8: tiles of 512,
+// 1024 or 2048 keys); larger inputs use 4096-key tiles.
 const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
                                 uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
-                                hipStream_t s, const uint32_t *n_dev = nullptr, gpma_dev::Ctl *check = nullptr);
+                                hipStream_t s, const uint32_t *n_dev = nullptr, gpma_dev::Ctl *check = nullptr,
+                                int small_chunks = 4);
 
 // unique of a sorted array: out receives the distinct keys, *count_dev their
 // number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).

@@ -18,8 +18,9 @@ constexpr int kSortWaves = kSortThreads / kWave;
 // tiles) for batches, so a 2^16-key batch still spreads over 64 workgroups
 constexpr int kChunksLarge = 16;
 constexpr int kChunksSmall = 4;
+constexpr int kChunksMin = 2;
 constexpr uint64_t kSmallSortMax = 1ull << 20;
-constexpr uint64_t kFuseTiles = 64;
+constexpr uint64_t kFuseTiles = 128;
 constexpr uint64_t kScanSingleMax = 2048;   // one workgroup, two items per thread
 
 inline uint64_t div_up(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
@@ -514,32 +515,42 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev
                        tmp);
 }
 
-static uint64_t sort_tile(uint64_t n) {
-    return (uint64_t)kSortThreads * (n <= kSmallSortMax ? kChunksSmall : kChunksLarge);
+// keys per tile: 256 threads x 64-key chunks per wave x CH
+static uint64_t sort_tile(uint64_t n, int small_chunks) {
+    return (uint64_t)kSortThreads * (n <= kSmallSortMax ? (uint64_t)small_chunks : (uint64_t)kChunksLarge);
 }
 
 size_t radix_tmp_words(uint64_t n) {
-    uint64_t ntiles = div_up(n ? n : 1, sort_tile(n));
+    // sized for the smallest tiles a caller may pick
+    uint64_t ntiles = div_up(n ? n : 1, sort_tile(n, kChunksMin));
     uint64_t m = 256 * ntiles;
     return m + scan_tmp_words(m);
 }
 
-static uint32_t bit_width(uint64_t x) {
-    uint32_t b = 0;
-    while (x) { b++; x >>= 1; }
-    return b;
+template <int CH>
+static void radix_pass(const uint64_t *src, uint64_t n, const uint32_t *n_dev, DigitMap dm, uint32_t bits,
+                       uint64_t ntiles, uint32_t *counts, uint32_t *stmp, Ctl *check, uint64_t *dst, hipStream_t s) {
+    const uint64_t mm = (uint64_t)(dm.mask + 1) * ntiles;
+    // up to kFuseTiles tiles the downsweep derives its offsets itself
+    const int fuse = ntiles <= kFuseTiles;
+    hipLaunchKernelGGL(k_radix_upsweep<CH>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, src, n, n_dev, dm,
+                       (uint32_t)ntiles, fuse, counts, check);
+    if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
+    hipLaunchKernelGGL(k_radix_downsweep<CH>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0, s, src, n, n_dev, dm,
+                       bits, (uint32_t)ntiles, counts, fuse, dst);
 }
 
 const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, uint32_t dbits,
                                 uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
-                                hipStream_t s, const uint32_t *n_dev, Ctl *check) {
-    (void)bit_width;
+                                hipStream_t s, const uint32_t *n_dev, Ctl *check, int small_chunks) {
+    if (small_chunks != 2 && small_chunks != 8) small_chunks = kChunksSmall;
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
     uint32_t passes = (total + 7) / 8;
     uint32_t bits = (total + passes - 1) / passes;
     const bool small = n <= kSmallSortMax;
-    uint64_t ntiles = div_up(n ? n : 1, sort_tile(n));
+    const int ch = small ? small_chunks : kChunksLarge;
+    uint64_t ntiles = div_up(n ? n : 1, sort_tile(n, small_chunks));
     uint64_t m = 256 * ntiles;
     uint32_t *counts = tmp;
     uint32_t *stmp = tmp + m;
@@ -547,21 +558,12 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
     uint64_t *dst = buf_a;
     for (uint32_t p = 0; p < passes; p++) {
         DigitMap dm{p * bits, (1u << bits) - 1u, dbits, V};
-        uint64_t mm = (uint64_t)(dm.mask + 1) * ntiles;
-        // up to kFuseTiles tiles the downsweep derives its offsets itself
-        const int fuse = ntiles <= kFuseTiles;
-        if (small) {
-            hipLaunchKernelGGL(k_radix_upsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
-                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts, p == 0 ? check : nullptr);
-            if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
-            hipLaunchKernelGGL(k_radix_downsweep<kChunksSmall>, dim3((uint32_t)ntiles), dim3(kSortThreads),
-                               0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
-        } else {
-            hipLaunchKernelGGL(k_radix_upsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads), 0,
-                               s, src, n, n_dev, dm, (uint32_t)ntiles, fuse, counts, p == 0 ? check : nullptr);
-            if (!fuse) scan_u32(counts, counts, mm, nullptr, stmp, s);
-            hipLaunchKernelGGL(k_radix_downsweep<kChunksLarge>, dim3((uint32_t)ntiles), dim3(kSortThreads),
-                               0, s, src, n, n_dev, dm, bits, (uint32_t)ntiles, counts, fuse, dst);
+        Ctl *chk = p == 0 ? check : nullptr;
+        switch (ch) {
+            case 2: radix_pass<2>(src, n, n_dev, dm, bits, ntiles, counts, stmp, chk, dst, s); break;
+            case 8: radix_pass<8>(src, n, n_dev, dm, bits, ntiles, counts, stmp, chk, dst, s); break;
+            case kChunksLarge: radix_pass<kChunksLarge>(src, n, n_dev, dm, bits, ntiles, counts, stmp, chk, dst, s); break;
+            default: radix_pass<kChunksSmall>(src, n, n_dev, dm, bits, ntiles, counts, stmp, chk, dst, s); break;
         }
         src = dst;
         dst = (dst == buf_a) ? buf_b : buf_a;

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "libgpma.so")
 GPMA_OK, GPMA_EINVAL, GPMA_ENOMEM, GPMA_EDEVICE = 0, -1, -2, -3
 GPMA_FLAG_MIRROR = 1
 GPMA_FLAG_LEARNED_LOCATOR = 2
+GPMA_FLAG_FUSED_DIRECT = 4
 EMPTY = 0xFFFFFFFFFFFFFFFF
 GUARD_DST = 0xFFFFFFFF
 
@@ -31,7 +32,8 @@ KERNEL_NAMES = ["spmv", "leaf_merge", "seg_merge", "sort", "locate", "bfs_expand
 
 class gpma_params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("tau_leaf_pm", C.c_uint32), ("tau_root_pm", C.c_uint32),
-                ("rho_leaf_pm", C.c_uint32), ("rho_root_pm", C.c_uint32), ("flags", C.c_uint32)]
+                ("rho_leaf_pm", C.c_uint32), ("rho_root_pm", C.c_uint32), ("flags", C.c_uint32),
+                ("sort_tile_keys", C.c_uint32), ("fused_levels", C.c_uint32)]
 
 
 class gpma_stats(C.Structure):
@@ -301,13 +303,20 @@ class _HandleView:
 
 class GPMA(_HandleView):
     """A GPU PMA holding a dynamic directed graph (one handle of the C ABI).
-    mirror=True also keeps the dst-major mirror (GPMA_FLAG_MIRROR)."""
+    mirror=True also keeps the dst-major mirror (GPMA_FLAG_MIRROR); learned
+    enables the learned locator; fused_direct makes apply_batches enqueue
+    kernels directly instead of replaying captured graphs; sort_tile picks the
+    batch sort's keys per workgroup tile (512, 1024 or 2048; 0 = 1024);
+    fused_levels is how many tree levels above the leaves a fused batch runs
+    on the device before the host takes over (0..3)."""
 
     def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
                  tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, mirror: bool = False,
-                 learned: bool = False, stream=None):
-        flags = (GPMA_FLAG_MIRROR if mirror else 0) | (GPMA_FLAG_LEARNED_LOCATOR if learned else 0)
-        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags)
+                 learned: bool = False, stream=None, fused_direct: bool = False, sort_tile: int = 0,
+                 fused_levels: int = 1):
+        flags = ((GPMA_FLAG_MIRROR if mirror else 0) | (GPMA_FLAG_LEARNED_LOCATOR if learned else 0)
+                 | (GPMA_FLAG_FUSED_DIRECT if fused_direct else 0))
+        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags, sort_tile, fused_levels)
         super().__init__(gpma_create(num_vertices, init_keys, p, stream), num_vertices)
 
     def close(self):

@@ -63,19 +63,24 @@ def make_sequence(V, live, n, seed):
     return ops, bs
 
 
-@pytest.mark.parametrize("mirror", [False, True])
-def test_fused_equals_plain(mirror):
+@pytest.mark.parametrize("mirror,direct,tile,levels", [(False, False, 0, 1), (True, False, 0, 2),
+                                                       (False, True, 512, 0), (True, True, 2048, 3),
+                                                       (True, True, 1024, 0)])
+def test_fused_equals_plain(mirror, direct, tile, levels):
+    """Fused sequences (graph replay or direct enqueue, every sort tile)
+    equal the plain per-batch path and the oracle."""
     from paper_1709_05061_amd import GPMA
     V, lf = 512, 16
     init = np.unique(npu64(synth.random_batch(V, 6000, 3)))
     ops, bs = make_sequence(V, init, 36, seed=5)
     plain = GPMA(V, dev(init), leaf_size=lf, mirror=mirror)
-    fused = GPMA(V, dev(init), leaf_size=lf, mirror=mirror)
+    fused = GPMA(V, dev(init), leaf_size=lf, mirror=mirror, fused_direct=direct, sort_tile=tile,
+                 fused_levels=levels)
     ref = O.OraclePMA(V, init, lf)
     cuts = [0, 5, 6, 20, 36]
     for c in range(len(cuts) - 1):
         lo, hi = cuts[c], cuts[c + 1]
-        say("fused call", lo, hi, "mirror", mirror)
+        say("fused call", lo, hi, "mirror", mirror, "direct", direct, "tile", tile, "levels", levels)
         for i in range(lo, hi):
             (plain.delete if ops[i] else plain.insert)(dev(bs[i]))
             (ref.delete if ops[i] else ref.insert)(bs[i])
@@ -97,13 +102,14 @@ def test_fused_equals_plain(mirror):
     fused.close()
 
 
-def test_fused_replays_many_batches_same_class():
+@pytest.mark.parametrize("direct", [False, True])
+def test_fused_replays_many_batches_same_class(direct):
     """Many replays of the same cached graphs (one size class)."""
     from paper_1709_05061_amd import GPMA
     V = 1 << 12
     st = synth.er_stream(V, 1 << 15, 700, 24, seed=9)
-    plain = GPMA(V, st.initial().cuda(), leaf_size=32)
-    fused = GPMA(V, st.initial().cuda(), leaf_size=32)
+    plain = GPMA(V, st.initial().cuda(), leaf_size=32, sort_tile=512)
+    fused = GPMA(V, st.initial().cuda(), leaf_size=32, fused_direct=direct)
     ops, bs = [], []
     for t in range(24):
         d, i = st.slide(t, 700)
