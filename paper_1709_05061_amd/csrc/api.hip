@@ -81,8 +81,10 @@ struct gpma {
     // destination-binned SpMV scratch (sized on use, grown as the array grows)
     uint32_t *pb_offs = nullptr, *pb_tmp = nullptr, *pb_small = nullptr;   // pb_small: total, pieces
     uint4 *pb_pieces = nullptr;
-    uint64_t *pb_rec = nullptr;
-    uint64_t pb_offs_words = 0, pb_tmp_words = 0, pb_pieces_cap = 0, pb_rec_cap = 0;
+    uint64_t *pb_rec = nullptr, *pb_rec2 = nullptr;
+    uint32_t *pb_coffs = nullptr;
+    uint64_t pb_offs_words = 0, pb_tmp_words = 0, pb_pieces_cap = 0, pb_rec_cap = 0, pb_rec2_cap = 0;
+    uint64_t pb_coffs_words = 0;
     uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *bfs_off = nullptr, *bfs_tmp = nullptr;
     uint32_t *small = nullptr;
     uint32_t *small_h = nullptr;   // pinned
@@ -742,7 +744,8 @@ void free_all(gpma *g) {
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
     dev_free(g->pb_offs); dev_free(g->pb_tmp); dev_free(g->pb_small); dev_free(g->pb_pieces); dev_free(g->pb_rec);
-    g->pb_offs_words = g->pb_tmp_words = g->pb_pieces_cap = g->pb_rec_cap = 0;
+    dev_free(g->pb_rec2); dev_free(g->pb_coffs);
+    g->pb_offs_words = g->pb_tmp_words = g->pb_pieces_cap = g->pb_rec_cap = g->pb_rec2_cap = g->pb_coffs_words = 0;
     dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
     dev_free(g->small);
     dev_free(g->ctl);
@@ -1437,11 +1440,11 @@ namespace {
 
 enum { kSpmvBinned = 0, kSpmvPull = 1, kSpmvPush = 2 };
 
-// Pull over the dst-major mirror if there is one, else destination bins
-// when V allows them, else push.  GPMA_SPMV=binned|pull|push overrides the
+// Destination bins when V allows them, else pull over the dst-major mirror
+// if there is one, else push.  GPMA_SPMV=binned|pull|push overrides the
 // choice where it applies (tests compare the three).
 int spmv_mode(const gpma *g) {
-    int m = g->mir ? kSpmvPull : (pb_supported(g->V) ? kSpmvBinned : kSpmvPush);
+    int m = pb_supported(g->V) ? kSpmvBinned : (g->mir ? kSpmvPull : kSpmvPush);
     if (const char *e = getenv("GPMA_SPMV")) {
         if (!strcmp(e, "push")) m = kSpmvPush;
         else if (!strcmp(e, "pull") && g->mir) m = kSpmvPull;
@@ -1463,13 +1466,26 @@ int ensure_pb(gpma *g, const PbLayout &L) {
         if (dev_alloc(&g->pb_rec, want)) return GPMA_ENOMEM;
         g->pb_rec_cap = want;
     }
+    if (L.nc && g->pb_rec2_cap < edges) {
+        dev_free(g->pb_rec2);
+        g->pb_rec2_cap = 0;
+        const uint64_t want = edges + edges / 4 + 1024;
+        if (dev_alloc(&g->pb_rec2, want)) return GPMA_ENOMEM;
+        g->pb_rec2_cap = want;
+    }
+    if (L.nc && g->pb_coffs_words < L.coarse_words) {
+        dev_free(g->pb_coffs);
+        g->pb_coffs_words = 0;
+        if (dev_alloc(&g->pb_coffs, L.coarse_words)) return GPMA_ENOMEM;
+        g->pb_coffs_words = L.coarse_words;
+    }
     if (g->pb_offs_words < L.count_words) {
         dev_free(g->pb_offs);
         g->pb_offs_words = 0;
         if (dev_alloc(&g->pb_offs, L.count_words)) return GPMA_ENOMEM;
         g->pb_offs_words = L.count_words;
     }
-    const uint64_t tw = scan_tmp_words(L.count_words);
+    const uint64_t tw = scan_tmp_words(std::max(L.count_words, L.coarse_words));
     if (g->pb_tmp_words < tw) {
         dev_free(g->pb_tmp);
         g->pb_tmp_words = 0;
@@ -1511,7 +1527,7 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
         L = pb_layout(g->V, g->cap, g->lf_log2, g->n);
         if (int e = ensure_pb(g, L)) return e;
         launch_pb_structure(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
-                            g->pb_small + 1, s);
+                            g->pb_small + 1, g->pb_coffs, s);
     }
     for (uint32_t it = 0; it < iters; it++) {
         const float *x = it == 0 ? init : out;
@@ -1519,8 +1535,8 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
         {
             ProfScope ps(g, GPMA_K_SPMV, s);
             if (mode == kSpmvBinned)
-                launch_pb_spmv(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_pieces, g->pb_small + 1,
-                               g->pr_contrib, g->pb_rec, g->V, g->pr_y, s);
+                launch_pb_spmv(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_small, g->pb_pieces,
+                               g->pb_small + 1, g->pb_coffs, g->pr_contrib, g->pb_rec, g->pb_rec2, g->V, g->pr_y, s);
             else if (mode == kSpmvPull)
                 launch_pr_pull(g->mir->slots, g->mir->cnt, g->mir->cap, g->mir->lf_log2, g->pr_contrib,
                                g->pr_y, s);

@@ -211,22 +211,26 @@ void launch_pr_combine(const double *y, const double *dangling, uint32_t V, doub
 
 // ---- PageRank SpMV by destination bins (spmv_binned.hip)
 struct PbLayout {
-    uint32_t nb = 0;          // destination bins of 8192 vertices
-    uint32_t W = 0;           // slot ranges (one workgroup each)
-    uint64_t spw = 0;         // slots per range
-    uint64_t max_pieces = 0;  // bound on accumulation pieces
-    uint64_t count_words = 0; // nb * W
+    uint32_t nb = 0;           // destination bins of 8192 vertices
+    uint32_t nc = 0;           // coarse bins of 64 bins (0: bins are written directly)
+    uint32_t W = 0;            // slot ranges (one workgroup each)
+    uint64_t spw = 0;          // slots per range
+    uint64_t max_pieces = 0;   // bound on accumulation pieces
+    uint64_t count_words = 0;  // nb * W
+    uint64_t coarse_words = 0; // nc * W
 };
 bool pb_supported(uint32_t V);
 PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_entries);
-// per call: count matrix, its scan (offs, total edges) and the piece table
+// per call: count matrix, its scan (offs, total edges), the piece table and
+// the scanned coarse count matrix (coffs, when nc > 0)
 void launch_pb_structure(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
                          uint32_t *offs, uint32_t *total, uint32_t *scan_tmp, uint4 *pieces, uint32_t *npieces,
-                         hipStream_t s);
-// per iteration: y (zeroed beforehand) += A^T contrib
+                         uint32_t *coffs, hipStream_t s);
+// per iteration: y (zeroed beforehand) += A^T contrib; rec2 is used when nc > 0
 void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
-                    const uint32_t *offs, const uint4 *pieces, const uint32_t *npieces, const double *contrib,
-                    uint64_t *rec, uint32_t V, double *y, hipStream_t s);
+                    const uint32_t *offs, const uint32_t *total, const uint4 *pieces, const uint32_t *npieces,
+                    const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
+                    double *y, hipStream_t s);
 void launch_bfs_init(int32_t *dist, uint32_t V, uint32_t source, uint32_t *queue,
                      uint32_t *qcount, hipStream_t s);
 void launch_bfs_row_len(const uint32_t *row_ptr, const uint32_t *front, uint32_t nfront, uint32_t *len,

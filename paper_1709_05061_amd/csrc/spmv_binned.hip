@@ -6,20 +6,31 @@
 // array, contrib[u] is a near-sequential read but y[v] is a random update;
 // read along a dst-major array it is the other way round.  Either way one
 // side is a random access per edge into a vector far larger than L2.  Here
-// the edge stream is instead split by destination into bins of 8192
+// the edge stream is instead split by destination into fine bins of 8192
 // vertices, whose slice of y fits one workgroup's LDS:
-//   count (once per call): per slot range, how many edges fall in each bin;
-//          an exclusive scan of the bin-major count matrix gives every
+//   count (once per call): per slot range, how many edges fall in each fine
+//          bin; an exclusive scan of the bin-major count matrix gives every
 //          (bin, range) pair its place in the record array;
 //   bin   (per iteration):  stream the slots, write one 8-byte record per
-//          edge into its bin: the contribution with its low 13 mantissa bits
-//          replaced by the destination's offset in the bin;
-//   accum (per iteration):  a workgroup per piece of a bin sums its records
-//          into the LDS slice with fp64 LDS atomics and writes the slice out
-//          (store for a bin in one piece, fp64 atomics for a split bin).
+//          edge: the contribution with its low mantissa bits replaced by the
+//          destination's offset in its bin;
+//   split (optional, more than 64 fine bins only): the bin pass writes
+//          coarse bins of 64 fine bins (2^19 vertices), so each workgroup has
+//          at most 64 runs open, and this pass splits each coarse run into
+//          its fine bins; the positions come from the same count matrix (a
+//          coarse run of range w holds exactly range w's records of those
+//          fine bins), so no pass needs an atomic in HBM.  On MI355X the
+//          direct form measured faster at scale 24 (L2 merges the scattered
+//          partial lines well enough), so it is the default;
+//   accum (per iteration):  a workgroup per piece of a fine bin sums its
+//          records into the LDS slice with fp64 LDS atomics and writes the
+//          slice out (store for a bin in one piece, fp64 atomics for a split
+//          bin).
 // Every HBM access is a stream; the random traffic stays in LDS.
-// Contributions are carried with 39 mantissa bits (relative truncation below
-// 2^-39), sums in fp64.
+// Contributions are carried with 39 mantissa bits (33 with coarse bins;
+// relative truncation below 2^-33), sums in fp64.
+#include <cstdlib>
+
 #include "common.h"
 
 using namespace gpma_dev;
@@ -29,6 +40,9 @@ namespace {
 constexpr uint32_t kBinBits = 13;
 constexpr uint32_t kBinWidth = 1u << kBinBits;
 constexpr uint64_t kBinMask = kBinWidth - 1;
+constexpr uint32_t kSplitBits = 6;                       // fine bins per coarse bin: 64
+constexpr uint32_t kCoarseBits = kBinBits + kSplitBits;  // 2^19 vertices per coarse bin
+constexpr uint64_t kCoarseMask = (1ull << kCoarseBits) - 1;
 constexpr uint32_t kCountThreads = 256;
 constexpr uint32_t kAccThreads = 1024;
 constexpr uint32_t kMaxBins = 4096;            // V <= 2^25
@@ -41,22 +55,55 @@ __device__ __forceinline__ uint64_t ld_nt(const uint64_t *p) { return __builtin_
 
 // The slot range of workgroup w is [w*spw, (w+1)*spw); spw is a power of two
 // no smaller than a leaf, so slot pairs (p, p+1) with p even share a leaf.
-// fn(k) is called for every stored edge (guards and gaps skipped).
+// Each thread takes kUnroll pairs per step and issues all their loads before
+// using any (the per-edge work is a chain of dependent accesses), then
+// fn(k) runs for every stored edge among them (guards and gaps skipped: a
+// skipped slot reads as kEmpty).
+constexpr int kUnroll = 4;
+
 template <typename F>
 __device__ __forceinline__ void for_each_edge(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
                                               uint32_t lf_log2, uint64_t spw, F fn) {
     const uint64_t lo = (uint64_t)blockIdx.x * spw;
     const uint64_t hi = lo + spw;
     const uint64_t lfm = (1ull << lf_log2) - 1;
-    for (uint64_t p = lo + 2 * threadIdx.x; p < hi; p += 2 * (uint64_t)blockDim.x) {
-        const uint32_t c = cnt[p >> lf_log2];
-        const uint32_t o = (uint32_t)(p & lfm);
-        if (o >= c) continue;
-        const uint64_t k0 = ld_nt(slots + p);
-        const uint64_t k1 = o + 1 < c ? ld_nt(slots + p + 1) : kEmpty;
-        if (!is_guard(k0)) fn(k0);
-        if (k1 != kEmpty && !is_guard(k1)) fn(k1);
+    const uint64_t step = 2 * (uint64_t)blockDim.x;
+    for (uint64_t p0 = lo + 2 * threadIdx.x; p0 < hi; p0 += step * kUnroll) {
+        uint64_t k[2 * kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint64_t p = p0 + u * step;
+            uint32_t c = 0, o = 0;
+            if (p < hi) {
+                c = cnt[p >> lf_log2];
+                o = (uint32_t)(p & lfm);
+            }
+            k[2 * u] = o < c ? ld_nt(slots + p) : kEmpty;
+            k[2 * u + 1] = o + 1 < c ? ld_nt(slots + p + 1) : kEmpty;
+        }
+        fn(k);
     }
+}
+
+__device__ __forceinline__ bool is_edge(uint64_t k) { return k != kEmpty && !is_guard(k); }
+
+// Place of a lane's record in its bin (bins < 64): the lanes holding the same
+// bin find each other with six ballots; the lowest of them reserves the
+// group's places with one LDS atomic and each lane takes base + its rank in
+// the group.  Every lane of the wave must call this (valid or not).
+__device__ __forceinline__ uint32_t reserve_in_bin(uint32_t *cur, uint32_t bin, bool valid) {
+    uint64_t m = __ballot(valid);
+#pragma unroll
+    for (int t = 0; t < 6; t++) {
+        const uint64_t bt = __ballot(valid && ((bin >> t) & 1u));
+        m &= ((bin >> t) & 1u) ? bt : ~bt;
+    }
+    const uint32_t lane = __lane_id();
+    const uint32_t leader = valid ? (uint32_t)(__ffsll((unsigned long long)m) - 1) : lane;
+    uint32_t base = 0;
+    if (valid && lane == leader) base = atomicAdd(&cur[bin], (uint32_t)__popcll(m));
+    base = __shfl(base, (int)leader, kWave);
+    return base + (uint32_t)__popcll(m & lanemask_lt());
 }
 
 __global__ void __launch_bounds__(kCountThreads)
@@ -65,7 +112,11 @@ k_pb_count(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
     __shared__ uint32_t hist[kMaxBins];
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    for_each_edge(slots, cnt, lf_log2, spw, [&](uint64_t k) { atomicAdd(&hist[key_dst(k) >> kBinBits], 1u); });
+    for_each_edge(slots, cnt, lf_log2, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+#pragma unroll
+        for (int j = 0; j < 2 * kUnroll; j++)
+            if (is_edge(k[j])) atomicAdd(&hist[key_dst(k[j]) >> kBinBits], 1u);
+    });
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) counts[(uint64_t)b * W + blockIdx.x] = hist[b];
 }
@@ -97,19 +148,89 @@ k_pb_pieces(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tota
     if (threadIdx.x == 0) *npieces = carry;
 }
 
+// bins of 2^bits destinations; cur starts at offs[b*W + w].  Up to 64 bins
+// the places are reserved per wave (ballots), beyond that per lane.
+template <bool MANY>
 __global__ void __launch_bounds__(kCountThreads)
 k_pb_bin(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
-         uint32_t nb, uint32_t W, const uint32_t *__restrict__ offs, const double *__restrict__ contrib,
-         uint64_t *__restrict__ rec) {
-    __shared__ uint32_t cur[kMaxBins];
+         uint32_t nb, uint32_t W, uint32_t bits, const uint32_t *__restrict__ offs,
+         const double *__restrict__ contrib, uint64_t *__restrict__ rec) {
+    __shared__ uint32_t cur[MANY ? kMaxBins : (1u << kSplitBits)];
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offs[(uint64_t)b * W + blockIdx.x];
     __syncthreads();
-    for_each_edge(slots, cnt, lf_log2, spw, [&](uint64_t k) {
-        const uint32_t d = key_dst(k);
-        const uint64_t bits = (uint64_t)__double_as_longlong(contrib[key_src(k)]);
-        const uint32_t pos = atomicAdd(&cur[d >> kBinBits], 1u);
-        __builtin_nontemporal_store((bits & ~kBinMask) | (d & kBinMask), rec + pos);
+    const uint64_t mask = (1ull << bits) - 1;
+    for_each_edge(slots, cnt, lf_log2, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+        uint64_t v[2 * kUnroll];
+#pragma unroll
+        for (int j = 0; j < 2 * kUnroll; j++)
+            v[j] = is_edge(k[j]) ? (uint64_t)__double_as_longlong(contrib[key_src(k[j])]) : 0;
+#pragma unroll
+        for (int j = 0; j < 2 * kUnroll; j++) {
+            const bool ok = is_edge(k[j]);
+            const uint32_t d = key_dst(k[j]);
+            uint32_t pos;
+            if (MANY) {
+                if (!ok) continue;
+                pos = atomicAdd(&cur[d >> bits], 1u);
+            } else {
+                pos = reserve_in_bin(cur, ok ? d >> bits : 0u, ok);
+            }
+            if (ok) rec[pos] = (v[j] & ~mask) | (d & mask);   // plain store: L2 merges a run's partial lines
+        }
     });
+}
+
+// coarse count matrix from the scanned fine one: range w's records in coarse
+// bin c = sum over its fine bins of (next scanned entry - this entry)
+__global__ void __launch_bounds__(256)
+k_pb_coarse_counts(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total, uint32_t nb,
+                   uint32_t nc, uint32_t W, uint32_t *__restrict__ ccnt) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)nc * W) return;
+    const uint32_t c = (uint32_t)(i / W), w = (uint32_t)(i % W);
+    const uint64_t last = (uint64_t)nb * W;
+    uint32_t sum = 0;
+    for (uint32_t f = 0; f < (1u << kSplitBits); f++) {
+        const uint32_t b = (c << kSplitBits) + f;
+        if (b >= nb) break;
+        const uint64_t e = (uint64_t)b * W + w;
+        const uint32_t nxt = e + 1 < last ? offs[e + 1] : *total;
+        sum += nxt - offs[e];
+    }
+    ccnt[i] = sum;
+}
+
+// one workgroup per (coarse bin c, slot range w): the range's run of coarse
+// records goes to its fine bins, at the places the fine count matrix gives
+__global__ void __launch_bounds__(kCountThreads)
+k_pb_split(const uint64_t *__restrict__ rec1, const uint32_t *__restrict__ coffs, const uint32_t *__restrict__ total,
+           const uint32_t *__restrict__ offs, uint32_t nb, uint32_t nc, uint32_t W, uint64_t *__restrict__ rec2) {
+    __shared__ uint32_t cur[1u << kSplitBits];
+    const uint32_t c = blockIdx.x / W, w = blockIdx.x % W;
+    const uint64_t e = (uint64_t)c * W + w;
+    const uint64_t beg = coffs[e];
+    const uint64_t end = e + 1 < (uint64_t)nc * W ? coffs[e + 1] : *total;
+    if (beg == end) return;   // block-uniform
+    for (uint32_t f = threadIdx.x; f < (1u << kSplitBits); f += blockDim.x) {
+        const uint32_t b = (c << kSplitBits) + f;
+        cur[f] = b < nb ? offs[(uint64_t)b * W + w] : 0u;
+    }
+    __syncthreads();
+    for (uint64_t i0 = beg + threadIdx.x; i0 < end; i0 += (uint64_t)blockDim.x * kUnroll) {
+        uint64_t r[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const uint64_t i = i0 + (uint64_t)u * blockDim.x;
+            r[u] = i < end ? ld_nt(rec1 + i) : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; u++) {
+            const bool ok = i0 + (uint64_t)u * blockDim.x < end;
+            const uint64_t off = r[u] & kCoarseMask;
+            const uint32_t pos = reserve_in_bin(cur, (uint32_t)(off >> kBinBits), ok);
+            if (ok) rec2[pos] = (r[u] & ~kCoarseMask) | (off & kBinMask);
+        }
+    }
 }
 
 __global__ void __launch_bounds__(kAccThreads)
@@ -154,6 +275,10 @@ bool pb_supported(uint32_t V) { return div_up(V, kBinWidth) <= kMaxBins; }
 PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges) {
     PbLayout L;
     L.nb = (uint32_t)div_up(V, kBinWidth);
+    // bins are written directly; GPMA_PB_LEVELS=2 routes them through coarse
+    // bins of 64 first (same result; faster where scattered stores are dear)
+    const char *lv = getenv("GPMA_PB_LEVELS");
+    L.nc = (lv && atoi(lv) == 2 && L.nb > (1u << kSplitBits)) ? (uint32_t)div_up(V, 1ull << kCoarseBits) : 0;
     uint64_t spw = cap / 1024;
     const uint64_t lf = 1ull << lf_log2;
     if (spw < lf) spw = lf;
@@ -163,22 +288,40 @@ PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges)
     L.W = (uint32_t)(cap / spw);
     L.max_pieces = L.nb + div_up(n_edges, kPieceRecords) + 1;
     L.count_words = (uint64_t)L.nb * L.W;
+    L.coarse_words = (uint64_t)L.nc * L.W;
     return L;
 }
 
 void launch_pb_structure(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
                          uint32_t *offs, uint32_t *total, uint32_t *scan_tmp, uint4 *pieces, uint32_t *npieces,
-                         hipStream_t s) {
+                         uint32_t *coffs, hipStream_t s) {
     hipLaunchKernelGGL(k_pb_count, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb, L.W, offs);
     scan_u32(offs, offs, L.count_words, total, scan_tmp, s);
     hipLaunchKernelGGL(k_pb_pieces, dim3(1), dim3(1024), 0, s, offs, total, L.nb, L.W, pieces, npieces);
+    if (L.nc) {
+        hipLaunchKernelGGL(k_pb_coarse_counts, dim3((uint32_t)div_up(L.coarse_words, 256)), dim3(256), 0, s, offs,
+                           total, L.nb, L.nc, L.W, coffs);
+        scan_u32(coffs, coffs, L.coarse_words, nullptr, scan_tmp, s);
+    }
 }
 
 void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
-                    const uint32_t *offs, const uint4 *pieces, const uint32_t *npieces, const double *contrib,
-                    uint64_t *rec, uint32_t V, double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb, L.W, offs,
-                       contrib, rec);
+                    const uint32_t *offs, const uint32_t *total, const uint4 *pieces, const uint32_t *npieces,
+                    const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
+                    double *y, hipStream_t s) {
+    if (L.nc) {
+        hipLaunchKernelGGL(k_pb_bin<false>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nc,
+                           L.W, kCoarseBits, coffs, contrib, rec);
+        hipLaunchKernelGGL(k_pb_split, dim3((uint32_t)L.coarse_words), dim3(kCountThreads), 0, s, rec, coffs, total,
+                           offs, L.nb, L.nc, L.W, rec2);
+        rec = rec2;
+    } else if (L.nb <= (1u << kSplitBits)) {
+        hipLaunchKernelGGL(k_pb_bin<false>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb,
+                           L.W, kBinBits, offs, contrib, rec);
+    } else {
+        hipLaunchKernelGGL(k_pb_bin<true>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb,
+                           L.W, kBinBits, offs, contrib, rec);
+    }
     hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), 0, s, rec, pieces, npieces, V,
                        y);
 }
