@@ -45,6 +45,33 @@ def pctl(xs, q):
     return xs[i]
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the rocprofv3 counter summaries
+    under profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by a copy kernel of
+    known size), or None when there is none or its kernel source has changed
+    since the counters were taken."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*_traffic.md"))):
+        fields = {}
+        with open(path) as f:
+            for line in f:
+                k, sep, v = line.partition(":")
+                if sep and k.strip() in ("traffic_kernel", "traffic_bytes_per_launch", "source", "source_sha256"):
+                    fields[k.strip()] = v.strip()
+        if fields.get("traffic_kernel") != kernel or "source" not in fields:
+            continue
+        src = os.path.join(here, fields["source"])
+        if not os.path.exists(src):
+            continue
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
+                return None
+        return float(fields["traffic_bytes_per_launch"])
+    return None
+
+
 def cpu_baseline(batch: int, slides: int, scale: int = 20):
     """Time the oracle (as it stands) on one host core over a bounded sample."""
     import numpy as np
@@ -358,8 +385,8 @@ def main():
         dom_name, dom_k = max(kernels.items(), key=lambda kv: kv[1]["total_ms"])
         achieved = dom_k["GBps"]
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                    "frac": (achieved / HBM_PEAK_GBPS) if achieved else None, "traffic": None,
-                    "kernel": dom_name}
+                    "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+                    "traffic": measured_traffic(dom_name), "kernel": dom_name}
     spmv = kernels.get("spmv")
     out = {
         "metric": METRIC,
