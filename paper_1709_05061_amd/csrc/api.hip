@@ -106,10 +106,20 @@ struct gpma {
     hipStream_t cap_stream = nullptr;
     hipStream_t side = nullptr;          // fused batching: the mirror's batches run here
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    uint64_t *kS = nullptr;              // staging of the batch being replayed
+    uint64_t *kS = nullptr;              // window staging, then the current batch's keys
     FusedState *fs = nullptr;            // device
-    uint32_t *stop = nullptr;            // device; the mirror uses its primary's
-    uint32_t *cur_n = nullptr;           // device: size of the batch being replayed
+    uint32_t *werrs = nullptr;           // device: per window batch, generation of its invalid key
+    uint32_t *wcount = nullptr;          // device: window keys, window unique keys
+    uint32_t *ustart = nullptr;          // device: window batch starts in the unique keys
+    uint64_t *wukeys = nullptr;          // which sort buffer holds the window's unique keys
+    struct WindowEntry {
+        hipGraphExec_t exec;
+        uint32_t w;
+        uint64_t cls;
+        uint32_t version;
+    };
+    std::vector<WindowEntry> wgraphs;
+    uint32_t *stop = nullptr;            // device stop flag of this handle's sequence
     BatchDesc *desc = nullptr;           // device table of the current chunk
     BatchOut *outs = nullptr;            // device per-batch results
     FusedState *fs_h = nullptr;          // pinned mirror of *fs
@@ -272,6 +282,9 @@ void drop_graphs(gpma *g) {
     for (auto &e : g->graphs)
         if (e.exec) hipGraphExecDestroy(e.exec);
     g->graphs.clear();
+    for (auto &e : g->wgraphs)
+        if (e.exec) hipGraphExecDestroy(e.exec);
+    g->wgraphs.clear();
     g->geom_version++;
 }
 
@@ -722,7 +735,8 @@ void free_all(gpma *g) {
     free_batch(g);
     dev_free(g->loc); dev_free(g->loc_gram); dev_free(g->loc_err);
     dev_free(g->tkeys);
-    dev_free(g->fs); dev_free(g->stop); dev_free(g->cur_n); dev_free(g->desc); dev_free(g->outs);
+    dev_free(g->fs); dev_free(g->stop); dev_free(g->desc); dev_free(g->outs);
+    dev_free(g->werrs); dev_free(g->wcount); dev_free(g->ustart);
     if (g->fs_h) hipHostFree(g->fs_h);
     if (g->stop_h) hipHostFree(g->stop_h);
     if (g->reset_h) hipHostFree(g->reset_h);
@@ -771,7 +785,6 @@ int ensure_fused(gpma *g) {
     int e = GPMA_OK;
     e |= dev_alloc(&g->fs, 1);
     e |= dev_alloc(&g->stop, 1);
-    e |= dev_alloc(&g->cur_n, 1);
     e |= dev_alloc(&g->desc, kFusedChunk);
     e |= dev_alloc(&g->outs, kFusedChunk);
     if (hipHostMalloc((void **)&g->fs_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
@@ -783,23 +796,77 @@ int ensure_fused(gpma *g) {
     if (!e && hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
+    e |= dev_alloc(&g->werrs, kWindowMax);
+    e |= dev_alloc(&g->wcount, 2);
+    e |= dev_alloc(&g->ustart, kWindowMax + 1);
+    if (!e) {
+        // window generations start at 1 so that zeroed error flags mean valid
+        memset(g->reset_h, 0, sizeof(FusedState));
+        g->reset_h->gen = 1;
+        hipMemcpy(g->fs, g->reset_h, sizeof(FusedState), hipMemcpyHostToDevice);
+        hipMemset(g->werrs, 0, kWindowMax * sizeof(uint32_t));
+    }
     return e;
 }
 
+// Tag bits of a window (0: this handle's vertex ids leave no room, windows
+// hold one batch).
+uint32_t window_tag_bits(const gpma *g) {
+    const uint32_t sb = bit_width(g->V - 1);
+    return sb + kWindowTagBits <= 32 ? kWindowTagBits : 0;
+}
+
+// Enqueue the prefix of a window of w batches from the handle's current batch
+// (at most n_max keys in all): fetch, validate and tag, one radix sort of the
+// whole window (batch tag above the source bits), unique, batch starts.
+void enqueue_window_prefix(gpma *g, uint32_t w, uint64_t n_max, const BatchDesc *desc, const uint32_t *stop,
+                           bool transpose, hipStream_t s) {
+    const uint32_t sb = bit_width(g->V - 1);
+    const uint32_t tb = window_tag_bits(g);
+    launch_window_fetch(desc, g->fs, stop, w, n_max, g->V, sb, transpose, g->kS, g->wcount, g->werrs, s);
+    const uint64_t *sorted =
+        radix_sort_keys(g->kS, n_max, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s, g->wcount, nullptr, g->sort_chunks);
+    uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
+    unique_sorted_dyn(sorted, g->wcount, n_max, ukeys, g->wcount + 1, g->flags, g->tmp, s);
+    launch_window_starts(ukeys, g->wcount + 1, w, sb, g->ustart, g->fs, s);
+    g->wukeys = ukeys;   // the same buffer for every window of this handle (fixed pass count)
+}
+
+gpma::WindowEntry *get_window_graph(gpma *g, uint32_t w, uint64_t cls, const BatchDesc *desc, const uint32_t *stop,
+                                    bool transpose) {
+    for (auto &e : g->wgraphs)
+        if (e.w == w && e.cls == cls && e.version == g->geom_version) return &e;
+    gpma::WindowEntry we{};
+    we.w = w;
+    we.cls = cls;
+    we.version = g->geom_version;
+    if (g->fused_direct) {
+        g->wgraphs.push_back(we);
+        return &g->wgraphs.back();
+    }
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    enqueue_window_prefix(g, w, cls, desc, stop, transpose, g->cap_stream);
+    if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
+    hipError_t r = hipGraphInstantiate(&we.exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (r != hipSuccess) return nullptr;
+    g->wgraphs.push_back(we);
+    return &g->wgraphs.back();
+}
+
 // Enqueue one batch of a fused sequence with device-side control only (no
-// host reads), for batches of at most `cls` keys: fetch, validate, sort,
-// unique, locate, level 0, then levels 1..h_top of the workgroup tier, then
-// finish.  Returns where the pending updates end up.
+// host reads), for batches of at most `cls` keys: take the batch's keys from
+// its window's sorted unique keys, locate, level 0, then levels 1..h_top of
+// the workgroup tier, then finish.  Returns where the pending updates end up.
 void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc, uint32_t *stop,
                           bool transpose, hipStream_t s, gpma::GraphEntry *ge) {
-    launch_fetch(desc, g->fs, stop, g->kS, g->cur_n, g->ctl, transpose, cls, s);
+    (void)desc;
+    (void)transpose;
     const uint32_t sb = bit_width(g->V - 1);
-    const uint64_t *sorted =
-        radix_sort_keys(g->kS, cls, sb, sb, g->V, g->kA, g->kB, g->tmp, s, g->cur_n, g->ctl, g->sort_chunks);
-    uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
-    LevelArrays cur{ukeys, g->leafA, g->stA, &g->ctl->n_in};
+    launch_window_select(g->fs, stop, g->wukeys, g->ustart, g->werrs, sb, cls, g->kS, g->ctl, s);
+    LevelArrays cur{g->kS, g->leafA, g->stA, &g->ctl->n_in};
     LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
-    unique_sorted_dyn(sorted, g->cur_n, cls, ukeys, cur.n, g->flags, g->tmp, s);
     do_locate(g, cur.k, cur.n, cls, cur.l, cur.st, s);
     uint64_t lo, hi;
     bounds(g, g->H, 0, &lo, &hi);
@@ -870,9 +937,10 @@ void read_fused(gpma *g, hipStream_t s) {
 void reset_fused(gpma *g, uint32_t batch, hipStream_t s) {
     // the pinned source is rewritten only after the stream has drained the
     // previous copy (every caller synchronises between resets)
-    memset(g->reset_h, 0, sizeof(uint32_t) * 4);
+    // batch and halted only: the window generation carries on
     g->reset_h->batch = batch;
-    hipMemcpyAsync(g->fs, g->reset_h, sizeof(uint32_t) * 4, hipMemcpyHostToDevice, s);
+    g->reset_h->halted = 0;
+    hipMemcpyAsync(g->fs, g->reset_h, sizeof(uint32_t) * 2, hipMemcpyHostToDevice, s);
 }
 
 // Complete the stopped batch of handle g: restore its control block and run
@@ -951,7 +1019,27 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             hipEventRecord(g->ev_fork, s);
             hipStreamWaitEvent(P[1].st, g->ev_fork, 0);
         }
-        for (int k = 0; k < nh; k++) end[k] = busy(k) ? std::min(count, P[k].next + window) : P[k].next;
+        // a window: at most `window` batches (kWindowMax when tagged, else 1)
+        // whose keys fit the staging buffer; its prefix sorts them together
+        for (int k = 0; k < nh; k++) {
+            end[k] = P[k].next;
+            if (!busy(k)) continue;
+            gpma *h = P[k].h;
+            const uint32_t wmax = window_tag_bits(h) ? std::min<uint32_t>(window, kWindowMax) : 1;
+            uint64_t keys_in = 0;
+            uint32_t e2 = P[k].next;
+            while (e2 < count && e2 - P[k].next < wmax && (e2 == P[k].next || keys_in + sizes[e2] <= h->bcap)) {
+                keys_in += sizes[e2];
+                e2++;
+            }
+            end[k] = e2;
+            const uint32_t w = e2 - P[k].next;
+            const uint64_t wcls = std::min<uint64_t>(batch_class(keys_in), h->bcap);
+            gpma::WindowEntry *we = get_window_graph(h, w, wcls, g->desc, h->stop, P[k].transpose);
+            if (!we) return GPMA_EDEVICE;
+            if (h->fused_direct) enqueue_window_prefix(h, w, wcls, g->desc, h->stop, P[k].transpose, P[k].st);
+            else if (hipGraphLaunch(we->exec, P[k].st) != hipSuccess) return GPMA_EDEVICE;
+        }
         // interleave the two streams' batches so both have work queued early
         for (uint32_t j = 0; j < window; j++) {
             for (int k = 0; k < nh; k++) {
@@ -1357,13 +1445,16 @@ int gpma_apply_batches(gpma_t *g, uint32_t count, const uint8_t *ops, const uint
         total->top_level = -1;
     }
     if (!g || g->readonly || (count && (!ops || !keys || !sizes))) return GPMA_EINVAL;
-    uint64_t cmax = 0;
+    uint64_t cmax = 0, sum = 0;
     for (uint32_t i = 0; i < count; i++) {
         if (ops[i] > 1 || sizes[i] >= (1ull << 31) || (sizes[i] && !keys[i])) return GPMA_EINVAL;
         cmax = std::max(cmax, batch_class(sizes[i]));
+        sum += sizes[i];
         if (total) total->requested += sizes[i];
     }
     if (count == 0) return GPMA_OK;
+    // staging for windows of batches sorted together: up to 2^20 keys
+    cmax = std::max(cmax, std::min<uint64_t>(1ull << 20, batch_class(sum)));
     int e = ensure_batch(g, cmax);
     if (!e) e = ensure_fused(g);
     if (!e && g->mir) e = ensure_batch(g->mir, cmax);

@@ -15,9 +15,15 @@ struct BatchDesc {
 struct FusedState {
     uint32_t batch;    // next batch to run
     uint32_t halted;   // 1: stopped at `batch` with work left for the host
-    uint32_t pad[2];
+    uint32_t wstart;   // first batch of the current window
+    uint32_t gen;      // window generation (starts at 1): errs[j] == gen - 1 marks batch j invalid
     Ctl snap;          // control block of the stopped batch
 };
+
+// a window's batches are sorted together: batch j of the window carries the
+// tag j in the key's source field above the source bits
+constexpr uint32_t kWindowTagBits = 6;
+constexpr uint32_t kWindowMax = 1u << kWindowTagBits;
 
 // statistics of one completed batch
 struct BatchOut {
@@ -35,10 +41,23 @@ struct BatchOut {
 
 namespace gpma_host {
 
-void launch_fetch(const gpma_dev::BatchDesc *desc, const gpma_dev::FusedState *st, const uint32_t *stop,
-                  uint64_t *staging, uint32_t *cur_n, gpma_dev::Ctl *ctl, bool transpose, uint64_t cap,
-                  hipStream_t s);
 void launch_finish(gpma_dev::FusedState *st, uint32_t *stop, const gpma_dev::Ctl *ctl, const uint32_t *pending,
                    gpma_dev::BatchOut *out, hipStream_t s);
+
+// window prefix: the w batches from st->batch, validated, tagged and
+// concatenated into staging (count to *wcount); errs[j] = st->gen for a
+// batch with an invalid key.  n_max bounds the window's total keys.
+void launch_window_fetch(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *st, const uint32_t *stop,
+                         uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, bool transpose, uint64_t *staging,
+                         uint32_t *wcount, uint32_t *errs, hipStream_t s);
+// first position of each batch's keys in the window's sorted unique keys;
+// advances st->gen
+void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
+                          gpma_dev::FusedState *st, hipStream_t s);
+// per batch: the current batch's unique keys, untagged, into dense; its
+// control block zeroed with n_in and err set (nothing when stopped)
+void launch_window_select(const gpma_dev::FusedState *st, const uint32_t *stop, const uint64_t *ukeys,
+                          const uint32_t *ustart, const uint32_t *errs, uint32_t sb, uint64_t n_max, uint64_t *dense,
+                          gpma_dev::Ctl *ctl, hipStream_t s);
 
 }  // namespace gpma_host
