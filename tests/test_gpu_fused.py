@@ -144,3 +144,40 @@ def test_fused_invalid_key_stops_at_that_batch():
     ref.insert(good[1])
     assert np.array_equal(npu64(g.slots()), ref.slots())
     g.close()
+
+
+@pytest.mark.parametrize("mirror", [False, True])
+def test_fused_windows_invalid_batch_then_more_calls(mirror):
+    """40 batches in one call (windows of 8, 16, ... batches sorted together),
+    an invalid key in batch 13: batches 0..12 stand, the call reports it, and
+    later calls (new windows, new generations) are unaffected by the stale
+    error flag."""
+    from paper_1709_05061_amd import GPMA, GpmaError
+    from paper_1709_05061_amd.gpma import gpma_apply_batches
+    V, lf = 700, 16
+    init = np.unique(npu64(synth.random_batch(V, 5000, 2)))
+    ops, bs = make_sequence(V, init, 40, seed=11)
+    bad = bs[13].copy()
+    bad[len(bad) // 2] = np.uint64((V << 32) | 3)
+    seq = bs[:13] + [bad] + bs[14:]
+    g = GPMA(V, dev(init), leaf_size=lf, mirror=mirror)
+    ref = O.OraclePMA(V, init, lf)
+    with pytest.raises(GpmaError) as ei:
+        gpma_apply_batches(g.h, ops, [dev(b) for b in seq])
+    assert ei.value.code == -1
+    for i in range(13):
+        (ref.delete if ops[i] else ref.insert)(bs[i])
+    assert np.array_equal(npu64(g.slots()), ref.slots())
+    # the rest of the sequence, valid, in two more calls
+    g.apply_batches(ops[13:30], [dev(b) for b in bs[13:30]])
+    g.apply_batches(ops[30:], [dev(b) for b in bs[30:]])
+    for i in range(13, 40):
+        (ref.delete if ops[i] else ref.insert)(bs[i])
+    assert np.array_equal(npu64(g.slots()), ref.slots())
+    if mirror:
+        t = lambda a: (a << np.uint64(32)) | (a >> np.uint64(32))
+        mref = O.OraclePMA(V, t(init), lf)
+        for i in range(40):
+            (mref.delete if ops[i] else mref.insert)(t(bs[i]))
+        assert np.array_equal(npu64(g.mirror().slots()), mref.slots())
+    g.close()
