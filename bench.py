@@ -161,6 +161,56 @@ def uneven_section(args):
     return out
 
 
+def workloads_section(args):
+    """The paper's other stream shapes at R-MAT scale 22, b = 2^16: explicit
+    random deletions (each slide deletes random window edges instead of the
+    oldest) and a sorted arrival stream (every insert batch in one narrow key
+    range).  Plain and fused update throughput at identical output."""
+    import torch
+
+    import synth
+    from paper_1709_05061_amd import GPMA
+    b, slides = 1 << 16, 16
+    st = synth.rmat_stream(22, 16, args.seed + 40, device="cuda")
+    out = {"workload": "R-MAT scale 22 edge factor 16, window %d edges; %d slides of %d deletes + %d inserts"
+                       % (st.window, slides, b, b)}
+    arrivals = st.order[st.window:]
+    cases = {
+        "explicit_random_deletions": synth.explicit_deletion_slides(st.initial(), arrivals, b, slides,
+                                                                    args.seed + 41),
+        "sorted_arrivals": [synth.sorted_stream(st).slide(t, b) for t in range(slides)],
+    }
+    for name, sl in cases.items():
+        res = {}
+        handles = {}
+        for mode in ("plain", "fused"):
+            g = GPMA(st.V, st.initial(), mirror=True, learned=(mode == "fused"))
+            d0, i0 = sl[0]
+            if mode == "fused":
+                g.apply_batches([1, 0], [d0, i0])
+            else:
+                g.delete(d0)
+                g.insert(i0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n = 0
+            for d, i in sl[1:]:
+                if mode == "fused":
+                    n += g.apply_batches([1, 0], [d, i]).applied
+                else:
+                    n += g.delete(d, stats=True).applied + g.insert(i, stats=True).applied
+            torch.cuda.synchronize()
+            res[mode + "_updates_per_s"] = n / (time.perf_counter() - t0)
+            handles[mode] = g
+        res["fused_speedup"] = res["fused_updates_per_s"] / res["plain_updates_per_s"]
+        res["identical_output"] = bool(torch.equal(handles["plain"].slots(), handles["fused"].slots()))
+        for g in handles.values():
+            g.close()
+        out[name] = res
+        log("%s: %s" % (name, res))
+    return out
+
+
 def service_section(args):
     """Streaming service on R-MAT scale 22 (window = first half of the
     distinct edges): Poisson edge arrivals at each rate for `service_s`
@@ -218,6 +268,8 @@ def main():
     ap.add_argument("--uneven-slides", type=int, default=128)
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--no-service", action="store_true")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the explicit-deletion / sorted-stream section")
+    ap.add_argument("--rebuild-slides", type=int, default=4, help="slides timed on the rebuild-per-batch CSR")
     ap.add_argument("--service-s", type=float, default=1.0)
     ap.add_argument("--query-rate", type=float, default=40.0)
     ap.add_argument("--service-budget-gib", type=int, default=16)
@@ -316,6 +368,29 @@ def main():
         torch.cuda.synchronize()
         other_ups = n_o / (sum(a.elapsed_time(c) for a, c in ms) / 1e3)
         log("%s path: %.3g updates/s" % ("plain" if fused_mode else "fused", other_ups))
+
+    # comparator: a CSR rebuilt on every batch (the paper's GPU-CSR baseline
+    # role), on the first slides
+    rebuild = None
+    if not args.no_compare and args.rebuild_slides > 0:
+        from paper_1709_05061_amd import CSRRebuild
+        c = CSRRebuild(V, st.initial())
+        d, i = st.slide(0, b)
+        c.delete(d)
+        c.insert(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for t in range(1, 1 + args.rebuild_slides):
+            d, i = st.slide(t, b)
+            c.delete(d)
+            c.insert(i)
+        torch.cuda.synchronize()
+        rebuild = {"updates_per_s": 2 * b * args.rebuild_slides / (time.perf_counter() - t0),
+                   "slides": args.rebuild_slides, "edges": c.num_edges}
+        c.close()
+        del c
+        torch.cuda.empty_cache()
+        log("CSR rebuilt per batch: %.3g updates/s" % rebuild["updates_per_s"])
 
     # BFS sources: vertices with out-edges, drawn with the seeded generator
     deg = g.degrees()
@@ -416,6 +491,7 @@ def main():
         "applied_per_step": applied / args.steps,
         "resizes": resized,
         ("plain_updates_per_s" if fused_mode else "fused_updates_per_s"): other_ups,
+        "csr_rebuild": rebuild,
         "fused_speedup": (updates_per_s / other_ups if fused_mode else other_ups / updates_per_s)
         if other_ups else None,
         "identical_output": identical,
@@ -438,6 +514,10 @@ def main():
     if not args.no_uneven:
         log("uneven-batch workload (power-law graph)")
         out["uneven"] = uneven_section(args)
+        torch.cuda.empty_cache()
+    if not args.no_workloads:
+        log("explicit deletions and sorted arrivals (R-MAT scale 22)")
+        out["workloads"] = workloads_section(args)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")

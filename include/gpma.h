@@ -248,6 +248,29 @@ int gpma_export_degrees(gpma_t *h, uint32_t *out_dev, uint64_t max, hipStream_t 
 /* Wait for all work of the handle.  Returns 0. */
 int gpma_sync(gpma_t *h);
 
+/* ---- Comparator: CSR rebuilt on every batch ------------------------------
+ * A plain CSR (edges sorted, no gaps, 64-bit row offsets) whose updates
+ * rebuild the whole format, the role the GPU CSR of cuSparse plays among the
+ * paper's baselines (Section 6, "GPU-based CSR": updates by rebuilding).
+ * Same set semantics and key rules as the PMA; present for comparison, not
+ * used by the PMA. */
+typedef struct gpma_csr gpma_csr_t;
+/* Build from n keys (device; duplicates allowed).  GPMA_EINVAL as for
+ * gpma_create; *out = NULL on error. */
+int gpma_csr_create(gpma_csr_t **out, uint32_t num_vertices, const uint64_t *init_keys_dev, uint64_t n,
+                    hipStream_t stream);
+void gpma_csr_destroy(gpma_csr_t *h);
+/* Apply one batch (del = 0 insert, 1 delete): sort, drop no-ops, merge into
+ * or remove from the whole edge array, recompute the row offsets.
+ * Synchronises with the host twice.  GPMA_EINVAL on an invalid key (nothing
+ * changed). */
+int gpma_csr_update(gpma_csr_t *h, const uint64_t *keys_dev, uint64_t b, int del, hipStream_t stream);
+uint64_t gpma_csr_num_edges(const gpma_csr_t *h);
+/* Sorted edges (keys_out, at least num_edges) and/or row offsets (V + 1
+ * uint64); either may be NULL. */
+int gpma_csr_export(const gpma_csr_t *h, uint64_t *keys_out_dev, uint64_t max_keys, uint64_t *row_ptr_out_dev,
+                    hipStream_t stream);
+
 /* Static message for an error code. */
 const char *gpma_strerror(int code);
 

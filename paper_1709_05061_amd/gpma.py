@@ -95,6 +95,11 @@ def load_library() -> C.CDLL:
         "gpma_profile_reset": (C.c_int, [vp]),
         "gpma_profile_read": (C.c_int, [vp, C.c_int, C.POINTER(C.c_double), pu64,
                                         C.POINTER(C.c_double)]),
+        "gpma_csr_create": (C.c_int, [C.POINTER(vp), u32, vp, u64, vp]),
+        "gpma_csr_destroy": (None, [vp]),
+        "gpma_csr_update": (C.c_int, [vp, vp, u64, C.c_int, vp]),
+        "gpma_csr_num_edges": (u64, [vp]),
+        "gpma_csr_export": (C.c_int, [vp, vp, u64, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -113,7 +118,8 @@ def exported_symbols() -> List[str]:
             "gpma_snapshot", "gpma_snapshot_refresh", "gpma_device_bytes", "gpma_locate",
             "gpma_locator_refit", "gpma_locator_info",
             "gpma_profile_enable",
-            "gpma_profile_reset", "gpma_profile_read"]
+            "gpma_profile_reset", "gpma_profile_read", "gpma_csr_create", "gpma_csr_destroy",
+            "gpma_csr_update", "gpma_csr_num_edges", "gpma_csr_export"]
 
 
 def strerror(code: int) -> str:
@@ -391,3 +397,55 @@ class GPMA(_HandleView):
         ms, n, by = C.c_double(), C.c_uint64(), C.c_double()
         self._lib.gpma_profile_read(self.h, kernel, C.byref(ms), C.byref(n), C.byref(by))
         return ms.value, n.value, by.value
+
+
+class CSRRebuild:
+    """The rebuild-per-batch CSR comparator (gpma_csr_*): same set semantics
+    as GPMA, every batch rewrites the whole edge array and row offsets."""
+
+    def __init__(self, num_vertices: int, init_keys: torch.Tensor, stream=None):
+        self._lib = load_library()
+        self.V = num_vertices
+        h = C.c_void_p()
+        init_keys = init_keys.contiguous()
+        _check(self._lib.gpma_csr_create(C.byref(h), num_vertices, C.c_void_p(init_keys.data_ptr()),
+                                         init_keys.numel(), _stream(stream)), "gpma_csr_create")
+        self.h = h
+
+    def _update(self, keys: torch.Tensor, delete: bool, stream=None):
+        keys = keys.contiguous()
+        _check(self._lib.gpma_csr_update(self.h, C.c_void_p(keys.data_ptr()), keys.numel(), 1 if delete else 0,
+                                         _stream(stream)), "gpma_csr_update")
+
+    def insert(self, keys: torch.Tensor, stream=None):
+        self._update(keys, False, stream)
+
+    def delete(self, keys: torch.Tensor, stream=None):
+        self._update(keys, True, stream)
+
+    @property
+    def num_edges(self) -> int:
+        return int(self._lib.gpma_csr_num_edges(self.h))
+
+    def keys(self, stream=None) -> torch.Tensor:
+        out = torch.empty(max(self.num_edges, 1), dtype=torch.int64, device="cuda")
+        _check(self._lib.gpma_csr_export(self.h, C.c_void_p(out.data_ptr()), out.numel(), None, _stream(stream)),
+               "gpma_csr_export")
+        return out[: self.num_edges]
+
+    def row_offsets(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.V + 1, dtype=torch.int64, device="cuda")
+        _check(self._lib.gpma_csr_export(self.h, None, 0, C.c_void_p(out.data_ptr()), _stream(stream)),
+               "gpma_csr_export")
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._lib.gpma_csr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,6 +18,8 @@ Workload shapes follow the paper's experiments (Section 6.1 "Datasets",
 """
 from __future__ import annotations
 
+from typing import List, Tuple
+
 import torch
 
 _GAMMA = 0x9E3779B97F4A7C15
@@ -217,6 +219,35 @@ def rmat_full_stream(scale: int, edge_factor: int, extra_draws: int, seed: int,
     fresh = unique_first(rmat_draws(scale, n, extra_draws, seed, device=device))
     fresh = fresh[~torch.isin(fresh, win)]
     return Stream(1 << scale, torch.cat([win, fresh]), win.numel())
+
+
+def explicit_deletion_slides(window: torch.Tensor, arrivals: torch.Tensor, b: int, slides: int,
+                             seed: int) -> List[Tuple[torch.Tensor, torch.Tensor]]:
+    """Graph stream with explicit deletions (the paper's extended experiment,
+    Appendix "Graph Streams with Explicit Deletions"): each slide deletes b
+    edges drawn at random from the current window (not the oldest) and
+    inserts the next b arrivals.  Returns [(deletes, inserts)] per slide."""
+    live = window.clone()
+    out = []
+    for t in range(slides):
+        ins = arrivals[t * b:(t + 1) * b]
+        ctr = torch.arange(2 * b, device=live.device, dtype=torch.int64) + (t << 32)
+        idx = unique_first(uniform_below(ctr, seed, live.numel()))[:b]
+        dels = live[idx]
+        keep = torch.ones(live.numel(), dtype=torch.bool, device=live.device)
+        keep[idx] = False
+        live = torch.cat([live[keep], ins])
+        out.append((dels, ins))
+    return out
+
+
+def sorted_stream(stream: "Stream") -> "Stream":
+    """The same window, with the arrivals in ascending key order: every batch
+    of inserts lands in one narrow key range, so merges climb the tree (the
+    worst case of the PMA's amortized update cost, the lemma of Section 4.1)."""
+    arr = stream.order[stream.window:]
+    arr = torch.sort(arr).values
+    return Stream(stream.V, torch.cat([stream.order[:stream.window], arr]), stream.window)
 
 
 def uniform01(counter: torch.Tensor, seed: int) -> torch.Tensor:

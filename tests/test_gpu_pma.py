@@ -386,3 +386,31 @@ def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
         want = O.pagerank(V, edges, x0=xin, iters=5)
         assert np.max(np.abs(x - want) / want) < PR_RTOL, (case, t)
     g.close()
+
+
+def test_csr_rebuild_comparator_matches_oracle():
+    """The rebuild-per-batch CSR comparator holds exactly the oracle's edge set
+    (sorted) and its row offsets after every batch, including no-ops,
+    repeats, deletes of absent keys and an invalid batch."""
+    from paper_1709_05061_amd import CSRRebuild, GpmaError
+    V = 1 << 12
+    st = synth.er_stream(V, 1 << 15, 1 << 10, 6, seed=21)
+    init = npu64(st.initial())
+    c = CSRRebuild(V, dev(init))
+    ref = O.OraclePMA(V, init, 16)
+    for t in range(6):
+        d, i = st.slide(t, 1 << 10)
+        d = np.concatenate([npu64(d), npu64(synth.random_batch(V, 50, 300 + t))])   # some absent
+        i = np.concatenate([npu64(i), npu64(i)[:100]])                             # repeats
+        c.delete(dev(d))
+        ref.delete(d)
+        c.insert(dev(i))
+        ref.insert(i)
+        e = O.edge_keys(ref.slots())
+        assert np.array_equal(npu64(c.keys()), e), t
+        want = np.searchsorted(e, np.arange(V + 1, dtype=np.uint64) << np.uint64(32))
+        assert np.array_equal(c.row_offsets().cpu().numpy(), want.astype(np.int64)), t
+    with pytest.raises(GpmaError):
+        c.insert(dev(np.array([(V << 32) | 1], np.uint64)))
+    assert np.array_equal(npu64(c.keys()), O.edge_keys(ref.slots()))
+    c.close()

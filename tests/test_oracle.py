@@ -362,3 +362,25 @@ def test_cc_closed_forms_and_scipy():
     want = np.array([np.min(np.nonzero(comp == comp[v])[0]) for v in range(V)])
     assert np.array_equal(O.cc(V, edges), want)
     assert len(set(O.cc(V, edges))) == n
+
+
+def test_stream_generators_explicit_deletions_and_sorted_arrivals():
+    """Input recipes of the extended workloads: explicit deletions remove
+    distinct edges that are live at that slide; sorted arrivals keep the
+    window and order the arrivals by key."""
+    import torch
+
+    import synth
+    st = synth.rmat_stream(11, 16, 4)
+    slides = synth.explicit_deletion_slides(st.initial(), st.order[st.window:], 200, 5, 9)
+    live = set(st.initial().tolist())
+    for d, i in slides:
+        d = d.tolist()
+        assert len(set(d)) == len(d) == 200 and set(d) <= live
+        live -= set(d)
+        live |= set(i.tolist())
+    s2 = synth.sorted_stream(st)
+    assert torch.equal(s2.initial(), st.initial())
+    arr = s2.order[s2.window:]
+    assert bool((arr[1:] >= arr[:-1]).all())
+    assert sorted(arr.tolist()) == sorted(st.order[st.window:].tolist())
