@@ -1656,17 +1656,31 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
     uint32_t *cur = g->bfs_q0, *nxt = g->bfs_q1;
     launch_bfs_init(dist, g->V, source, cur, g->small, s);
     uint32_t nfront = 1;
+    // Direction choice (with a mirror): expand top-down while the frontier's
+    // rows are a small part of the rows not yet expanded; go bottom-up over
+    // the in-edges when they exceed 1/14 of them or the frontier holds 1/64
+    // of the vertices (the usual direction-optimising rule).
+    uint64_t unexplored = g->n;
     for (int32_t level = 0; nfront > 0; level++) {
         hipMemsetAsync(g->small + 1, 0, sizeof(uint32_t), s);
+        bool bottom_up = g->mir && (uint64_t)nfront * 64 >= g->V;
+        if (!bottom_up) {
+            // rows of the frontier end to end: lengths and their scan
+            launch_bfs_row_len(g->row_ptr, cur, nfront, g->bfs_off, s);
+            scan_u32(g->bfs_off, g->bfs_off, nfront, g->small + 3, g->bfs_tmp, s);
+            if (g->mir) {
+                hipMemcpyAsync(g->small_h + 1, g->small + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+                hipStreamSynchronize(s);
+                const uint64_t mf = g->small_h[1];
+                bottom_up = mf * 14 > unexplored;
+                if (!bottom_up) unexplored = unexplored > mf ? unexplored - mf : 0;
+            }
+        }
         {
             ProfScope ps(g, GPMA_K_BFS, s);
-            if (g->mir && (uint64_t)nfront * 64 >= g->V) {
-                // large frontier: bottom-up over the in-edges (mirror)
+            if (bottom_up) {
                 launch_bfs_bottom_up(g->mir->slots, g->mir->row_ptr, g->V, level, dist, nxt, g->small + 1, s);
             } else {
-                // rows of the frontier end to end: lengths, their scan, the expansion
-                launch_bfs_row_len(g->row_ptr, cur, nfront, g->bfs_off, s);
-                scan_u32(g->bfs_off, g->bfs_off, nfront, g->small + 3, g->bfs_tmp, s);
                 launch_bfs_expand(g->slots, g->row_ptr, cur, g->bfs_off, nfront, g->small + 3, g->cap,
                                   level, dist, nxt, g->small + 1, s);
             }

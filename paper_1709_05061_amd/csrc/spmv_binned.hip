@@ -59,7 +59,7 @@ __device__ __forceinline__ uint64_t ld_nt(const uint64_t *p) { return __builtin_
 // using any (the per-edge work is a chain of dependent accesses), then
 // fn(k) runs for every stored edge among them (guards and gaps skipped: a
 // skipped slot reads as kEmpty).
-constexpr int kUnroll = 4;
+constexpr int kUnroll = 8;
 
 template <typename F>
 __device__ __forceinline__ void for_each_edge(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
