@@ -323,6 +323,62 @@ k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uin
     if (__ballot(any) && __lane_id() == 0) atomicOr(changed, 1u);
 }
 
+// Sampling round (the approach of Afforest, Sutton et al.): every vertex is
+// hooked to the first entry of its row (out-row on the array, in-row on the
+// dst-major mirror).  Row v starts after guard v-1; a leaf's gap tail may sit
+// between them, so the scan skips empty slots (at most one leaf's worth).
+__global__ void __launch_bounds__(256)
+k_cc_sample(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint32_t V, uint32_t lf,
+            uint32_t *label) {
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    uint64_t p = v ? row_ptr[v] : 0;
+    const uint64_t end = row_ptr[v + 1];   // one past guard v
+    uint64_t k = kEmpty;
+    for (uint32_t t = 0; t <= lf && p < end; t++, p++) {
+        k = slots[p];
+        if (k != kEmpty) break;
+    }
+    if (k == kEmpty || is_guard(k)) return;
+    const uint32_t a = cc_find(label, key_src(k));
+    const uint32_t b = cc_find(label, key_dst(k));
+    if (a != b) atomicMin(&label[a > b ? a : b], a > b ? b : a);
+}
+
+// Hooking sweep that skips every entry whose row vertex is in component c
+// (the largest after sampling): with the array and its mirror both swept,
+// an edge is skipped on both sides only when both ends are already in c.
+__global__ void __launch_bounds__(256)
+k_cc_hook_skip(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uint32_t c,
+               uint32_t *changed) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    bool any = false;
+    uint32_t last_u = 0xFFFFFFFFu, last_r = 0;
+    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
+        const uint64_t k = ld_stream(slots + p);
+        if (k == kEmpty || is_guard(k)) continue;
+        const uint32_t u = key_src(k);
+        if (u != last_u) {
+            last_u = u;
+            last_r = cc_find(label, u);
+        }
+        if (last_r == c) continue;
+        const uint32_t a = cc_find(label, u);
+        const uint32_t b = cc_find(label, key_dst(k));
+        if (a != b) {
+            atomicMin(&label[a > b ? a : b], a > b ? b : a);
+            any = true;
+        }
+    }
+    if (__ballot(any) && __lane_id() == 0) atomicOr(changed, 1u);
+}
+
+// labels of n vertices at a fixed stride, for picking the largest component
+__global__ void k_cc_pick(const uint32_t *__restrict__ label, uint64_t stride, uint32_t n, uint32_t *__restrict__ out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = label[(uint64_t)i * stride];
+}
+
 __global__ void k_cc_compress(uint32_t *label, uint32_t V) {
     uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= V) return;
@@ -411,6 +467,21 @@ void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32
                     hipStream_t s) {
     hipLaunchKernelGGL(k_cc_hook, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label,
                        changed);
+}
+
+void launch_cc_sample(const uint64_t *slots, const uint32_t *row_ptr, uint32_t V, uint32_t lf, uint32_t *label,
+                      hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_sample, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, slots, row_ptr, V, lf, label);
+}
+
+void launch_cc_hook_skip(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t c, uint32_t *changed,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_hook_skip, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label, c,
+                       changed);
+}
+
+void launch_cc_pick(const uint32_t *label, uint64_t stride, uint32_t n, uint32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_pick, dim3((n + 255) / 256), dim3(256), 0, s, label, stride, n, out);
 }
 
 void launch_cc_compress(uint32_t *label, uint32_t V, hipStream_t s) {

@@ -86,6 +86,7 @@ struct gpma {
     uint64_t pb_offs_words = 0, pb_tmp_words = 0, pb_pieces_cap = 0, pb_rec_cap = 0, pb_rec2_cap = 0;
     uint64_t pb_coffs_words = 0;
     uint32_t *bfs_q0 = nullptr, *bfs_q1 = nullptr, *bfs_off = nullptr, *bfs_tmp = nullptr;
+    uint32_t *cc_pick = nullptr;   // 1024 sampled labels
     uint32_t *small = nullptr;
     uint32_t *small_h = nullptr;   // pinned
 
@@ -761,6 +762,7 @@ void free_all(gpma *g) {
     dev_free(g->pb_rec2); dev_free(g->pb_coffs);
     g->pb_offs_words = g->pb_tmp_words = g->pb_pieces_cap = g->pb_rec_cap = g->pb_rec2_cap = g->pb_coffs_words = 0;
     dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
+    dev_free(g->cc_pick);
     dev_free(g->small);
     dev_free(g->ctl);
     if (g->ctl_h) hipHostFree(g->ctl_h);
@@ -1696,6 +1698,41 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
 int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
     if (!g || !label) return GPMA_EINVAL;
     launch_cc_init(label, g->V, s);
+    if (g->mir && g->V >= 4096) {
+        // sample one out- and one in-neighbour per vertex, find the largest
+        // component from 1024 sampled labels, then sweep both arrays skipping
+        // its rows until nothing changes
+        launch_cc_sample(g->slots, g->row_ptr, g->V, g->lf, label, s);
+        launch_cc_sample(g->mir->slots, g->mir->row_ptr, g->V, g->lf, label, s);
+        launch_cc_compress(label, g->V, s);
+        if (!g->cc_pick && dev_alloc(&g->cc_pick, 1024)) return GPMA_ENOMEM;
+        std::vector<uint32_t> smp(1024);
+        launch_cc_pick(label, g->V / 1024, 1024, g->cc_pick, s);
+        hipMemcpyAsync(smp.data(), g->cc_pick, 1024 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        hipStreamSynchronize(s);
+        std::sort(smp.begin(), smp.end());
+        uint32_t c = smp[0], best = 0;
+        for (size_t i = 0; i < smp.size();) {
+            size_t j = i;
+            while (j < smp.size() && smp[j] == smp[i]) j++;
+            if (j - i > best) { best = (uint32_t)(j - i); c = smp[i]; }
+            i = j;
+        }
+        for (;;) {
+            hipMemsetAsync(g->small + 2, 0, sizeof(uint32_t), s);
+            {
+                ProfScope ps(g, GPMA_K_CC, s);
+                launch_cc_hook_skip(g->slots, g->cap, label, c, g->small + 2, s);
+                launch_cc_hook_skip(g->mir->slots, g->mir->cap, label, c, g->small + 2, s);
+                ps.done(16.0 * (double)g->n + 8.0 * (double)g->V);
+            }
+            launch_cc_compress(label, g->V, s);
+            hipMemcpyAsync(g->small_h + 2, g->small + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+            hipStreamSynchronize(s);
+            if (!g->small_h[2]) break;
+        }
+        return GPMA_OK;
+    }
     for (int round = 0;; round++) {
         hipMemsetAsync(g->small + 2, 0, sizeof(uint32_t), s);
         {

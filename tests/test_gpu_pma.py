@@ -414,3 +414,36 @@ def test_csr_rebuild_comparator_matches_oracle():
         c.insert(dev(np.array([(V << 32) | 1], np.uint64)))
     assert np.array_equal(npu64(c.keys()), O.edge_keys(ref.slots()))
     c.close()
+
+
+@pytest.mark.parametrize("kind", ["rmat", "pieces"])
+def test_cc_with_mirror_sampling_path(kind):
+    """With a mirror and V >= 4096, CC samples a neighbour per row, picks the
+    largest component and sweeps both arrays skipping its rows; labels must
+    equal the oracle's (smallest vertex id per weak component): an R-MAT graph
+    (one giant component plus isolated vertices) and a union of many small
+    directed pieces (no dominant component, long chains)."""
+    from paper_1709_05061_amd import GPMA
+    if kind == "rmat":
+        V = 1 << 14
+        e = np.unique(npu64(synth.rmat_unique(14, 4 << 14, seed=13)))
+    else:
+        V = 6000
+        rng = np.random.default_rng(3)
+        perm = rng.permutation(V).astype(np.uint64)
+        keys = []
+        for c0 in range(0, V, 40):            # pieces of 40 vertices: a path with random direction
+            blk = perm[c0:c0 + 40]
+            for a, b in zip(blk[:-1], blk[1:]):
+                keys.append((a << np.uint64(32)) | b if rng.random() < 0.5 else (b << np.uint64(32)) | a)
+        e = np.unique(np.array(keys, np.uint64))
+    g = GPMA(V, dev(e), mirror=True)
+    lab = g.cc().cpu().numpy().astype(np.int64)
+    want = O.cc(V, e).astype(np.int64)
+    assert np.array_equal(lab, want)
+    # again after updates (the sweep must not depend on a fresh handle)
+    extra = np.unique(npu64(synth.random_batch(V, 300, 14)))
+    g.insert(dev(extra))
+    lab = g.cc().cpu().numpy().astype(np.int64)
+    assert np.array_equal(lab, O.cc(V, np.union1d(e, extra)).astype(np.int64))
+    g.close()
