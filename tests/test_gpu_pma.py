@@ -447,3 +447,46 @@ def test_cc_with_mirror_sampling_path(kind):
     lab = g.cc().cpu().numpy().astype(np.int64)
     assert np.array_equal(lab, O.cc(V, np.union1d(e, extra)).astype(np.int64))
     g.close()
+
+
+@pytest.mark.parametrize("mirror", [False, True])
+def test_degenerate_graphs(mirror):
+    """V = 1 (only the self-loop exists), a graph emptied by deletes and
+    refilled, zero-length batches inside fused sequences, and the analytics
+    on those graphs."""
+    from paper_1709_05061_amd import GPMA
+    # one vertex
+    g = GPMA(1, dev(np.zeros(0, np.uint64)), mirror=mirror)
+    ref = O.OraclePMA(1, np.zeros(0, np.uint64), g.leaf_size)
+    loop = np.array([0], np.uint64)
+    for op in ("insert", "insert", "delete", "delete", "insert"):
+        getattr(g, op)(dev(loop))
+        getattr(ref, op)(loop)
+        assert np.array_equal(npu64(g.slots()), ref.slots())
+    assert g.num_edges == 1
+    assert np.allclose(g.pagerank(iters=3).cpu().numpy(), [1.0])
+    assert g.bfs(0).cpu().numpy().tolist() == [0]
+    assert g.cc().cpu().numpy().tolist() == [0]
+    g.close()
+    # emptied and refilled, with empty batches in a fused sequence
+    V = 2000
+    e = np.unique(npu64(synth.random_batch(V, 6000, 31)))
+    g = GPMA(V, dev(e), leaf_size=16, mirror=mirror)
+    ref = O.OraclePMA(V, e, 16)
+    z = np.zeros(0, np.uint64)
+    ops = [1, 0, 1, 0, 0]
+    bs = [e, z, z, e[:10], e]
+    g.apply_batches(ops, [dev(b) for b in bs])
+    for o, b in zip(ops, bs):
+        (ref.delete if o else ref.insert)(b)
+    assert np.array_equal(npu64(g.slots()), ref.slots())
+    assert g.num_edges == e.size
+    g.delete(dev(e))
+    ref.delete(e)
+    assert g.num_edges == 0 and np.array_equal(npu64(g.slots()), ref.slots())
+    x = g.pagerank(iters=5).cpu().numpy()
+    assert np.allclose(x, 1.0 / V, rtol=PR_RTOL)
+    d = g.bfs(7).cpu().numpy()
+    assert d[7] == 0 and (np.delete(d, 7) == -1).all()
+    assert np.array_equal(g.cc().cpu().numpy(), np.arange(V))
+    g.close()
