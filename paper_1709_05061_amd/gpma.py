@@ -57,7 +57,7 @@ def load_library() -> C.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError("libgpma.so is not built (run __graft_entry__.build() or "
+        raise RuntimeError("libgpma.so is not built (build it with "
                            "python paper_1709_05061_amd/build.py)")
     lib = C.CDLL(LIB_PATH)
     vp, u32, u64, i32, f32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32, C.c_float
