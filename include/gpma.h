@@ -174,7 +174,7 @@ int gpma_apply_batches(gpma_t *h, uint32_t count, const uint8_t *ops, const uint
  * init_dev: V floats, or NULL for the uniform 1/V; out_dev: V floats, may
  * alias init_dev (warm start from the previous result).  Contributions
  * x[u]/outdeg(u) are formed in fp64 and summed in fp64 (the destination-bin
- * form, used while V <= 2^25, carries them with 39 mantissa bits); each step
+ * form, used while V <= 2^26, carries them with 38 mantissa bits); each step
  * rounds once to fp32.  The summation order is not fixed, so repeated calls
  * may differ in the last fp32 bit.
  * GPMA_EINVAL if iters == 0 or damping is not in (0,1). */

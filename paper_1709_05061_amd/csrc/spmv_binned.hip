@@ -6,8 +6,8 @@
 // array, contrib[u] is a near-sequential read but y[v] is a random update;
 // read along a dst-major array it is the other way round.  Either way one
 // side is a random access per edge into a vector far larger than L2.  Here
-// the edge stream is instead split by destination into fine bins of 8192
-// vertices, whose slice of y fits one workgroup's LDS:
+// the edge stream is instead split by destination into fine bins of 16384
+// vertices, whose slice of y (128 KiB of fp64) fits one workgroup's LDS:
 //   count (once per call): per slot range, how many edges fall in each fine
 //          bin; an exclusive scan of the bin-major count matrix gives every
 //          (bin, range) pair its place in the record array;
@@ -15,7 +15,7 @@
 //          edge: the contribution with its low mantissa bits replaced by the
 //          destination's offset in its bin;
 //   split (optional, more than 64 fine bins only): the bin pass writes
-//          coarse bins of 64 fine bins (2^19 vertices), so each workgroup has
+//          coarse bins of 64 fine bins (2^20 vertices), so each workgroup has
 //          at most 64 runs open, and this pass splits each coarse run into
 //          its fine bins; the positions come from the same count matrix (a
 //          coarse run of range w holds exactly range w's records of those
@@ -27,8 +27,8 @@
 //          slice out (store for a bin in one piece, fp64 atomics for a split
 //          bin).
 // Every HBM access is a stream; the random traffic stays in LDS.
-// Contributions are carried with 39 mantissa bits (33 with coarse bins;
-// relative truncation below 2^-33), sums in fp64.
+// Contributions are carried with 38 mantissa bits (32 with coarse bins;
+// relative truncation below 2^-32), sums in fp64.
 #include <cstdlib>
 
 #include "common.h"
@@ -37,15 +37,15 @@ using namespace gpma_dev;
 
 namespace {
 
-constexpr uint32_t kBinBits = 13;
+constexpr uint32_t kBinBits = 14;   // 16384 destinations: a 128 KiB fp64 slice (gfx950: 160 KiB LDS per workgroup)
 constexpr uint32_t kBinWidth = 1u << kBinBits;
 constexpr uint64_t kBinMask = kBinWidth - 1;
 constexpr uint32_t kSplitBits = 6;                       // fine bins per coarse bin: 64
-constexpr uint32_t kCoarseBits = kBinBits + kSplitBits;  // 2^19 vertices per coarse bin
+constexpr uint32_t kCoarseBits = kBinBits + kSplitBits;  // 2^20 vertices per coarse bin
 constexpr uint64_t kCoarseMask = (1ull << kCoarseBits) - 1;
 constexpr uint32_t kCountThreads = 256;
 constexpr uint32_t kAccThreads = 1024;
-constexpr uint32_t kMaxBins = 4096;            // V <= 2^25
+constexpr uint32_t kMaxBins = 4096;            // V <= 2^26
 constexpr uint64_t kPieceRecords = 1ull << 18;  // records per accumulation workgroup
 constexpr uint64_t kMaxRangeSlots = 1ull << 18;
 
@@ -236,7 +236,7 @@ k_pb_split(const uint64_t *__restrict__ rec1, const uint32_t *__restrict__ coffs
 __global__ void __launch_bounds__(kAccThreads)
 k_pb_accum(const uint64_t *__restrict__ rec, const uint4 *__restrict__ pieces, const uint32_t *__restrict__ npieces,
            uint32_t V, double *__restrict__ y) {
-    __shared__ double acc[kBinWidth];
+    extern __shared__ double acc[];   // kBinWidth doubles
     if (blockIdx.x >= *npieces) return;
     const uint4 pc = pieces[blockIdx.x];
     for (uint32_t j = threadIdx.x; j < kBinWidth; j += kAccThreads) acc[j] = 0.0;
@@ -270,7 +270,22 @@ k_pb_accum(const uint64_t *__restrict__ rec, const uint4 *__restrict__ pieces, c
 
 namespace gpma_host {
 
-bool pb_supported(uint32_t V) { return div_up(V, kBinWidth) <= kMaxBins; }
+// The accumulation slice exceeds the default 64 KiB of LDS; the binned form
+// is offered only where the device grants it.
+bool pb_supported(uint32_t V) {
+    static int ok = -1;
+    if (ok < 0) {
+        const size_t bytes = kBinWidth * sizeof(double);
+        int dev = 0, max_lds = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        ok = (size_t)max_lds >= bytes &&
+             hipFuncSetAttribute((const void *)k_pb_accum, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+                 hipSuccess;
+        if (!ok) (void)hipGetLastError();
+    }
+    return ok && div_up(V, kBinWidth) <= kMaxBins;
+}
 
 PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges) {
     PbLayout L;
@@ -322,8 +337,8 @@ void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2
         hipLaunchKernelGGL(k_pb_bin<true>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb,
                            L.W, kBinBits, offs, contrib, rec);
     }
-    hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), 0, s, rec, pieces, npieces, V,
-                       y);
+    hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double), s, rec,
+                       pieces, npieces, V, y);
 }
 
 }  // namespace gpma_host

@@ -349,12 +349,12 @@ def test_spmv_modes_match_oracle_on_rmat(mode, monkeypatch):
 
 @pytest.mark.parametrize("case", ["rmat16", "powerlaw_ragged", "two_level", "many_bins"])
 def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
-    """Destination bins of 8192 vertices: R-MAT scale 16 puts ~40% of its
+    """Destination bins of 16384 vertices: R-MAT scale 16 puts ~40% of its
     ~1M edges into bin 0, which is cut into several accumulation pieces
     (fp64 atomics between pieces); a power-law graph on 70001 vertices ends
-    in a partial bin; R-MAT on 600001 vertices has 74 bins, so records go
-    through coarse bins of 64 bins first (the last coarse bin partial).
-    Warm-started calls after updates too."""
+    in a partial bin; 1200001 vertices make 74 bins, so records go through
+    coarse bins of 64 bins first (two_level; the last coarse bin partial) or
+    are reserved per lane (many_bins).  Warm-started calls after updates too."""
     from paper_1709_05061_amd import GPMA
     monkeypatch.setenv("GPMA_SPMV", "binned")
     if case == "two_level":
@@ -366,7 +366,7 @@ def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
         V = 70001
         u = np.unique(npu64(synth.powerlaw_edges(V, 600000, seed=6)))
     else:   # 74 bins: coarse bins first (two_level) or per-lane reservations (many_bins)
-        V = 600001
+        V = 1200001
         r = np.unique(npu64(synth.rmat_unique(20, 1 << 21, seed=5)))
         r = r[((r >> np.uint64(32)) < np.uint64(V)) & ((r & np.uint64(0xFFFFFFFF)) < np.uint64(V))]
         u = np.unique(np.concatenate([r, npu64(synth.powerlaw_edges(V, 400000, seed=7))]))
