@@ -1251,9 +1251,8 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     g->rho_leaf = p.rho_leaf_pm; g->rho_root = p.rho_root_pm;
     int dev = 0;
     hipGetDevice(&dev);
-    hipDeviceGetAttribute(&g->dev.max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    g->dev.max_lds = seg_merge_max_lds();
     hipDeviceGetAttribute(&g->dev.cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (g->dev.max_lds > 65536) g->dev.max_lds = 65536;
     // GPMA_TIER_LDS caps the LDS the workgroup tier may use, so tests can
     // drive small segments through the device tier
     if (const char *t = getenv("GPMA_TIER_LDS")) g->dev.max_lds = std::min(g->dev.max_lds, atoi(t));

@@ -175,6 +175,7 @@ void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uin
                        uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s);
 // workgroup tier at height h >= 1; needs seg_merge_lds_bytes(lf, h) <= max LDS
 size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h);
+int seg_merge_max_lds();
 void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
                       uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
                       uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t minh,

@@ -488,6 +488,26 @@ void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uin
     }
 }
 
+// LDS the workgroup tier may use: what the device grants a workgroup, once
+// both merge kernels are allowed that much dynamic LDS (64 KiB otherwise)
+int seg_merge_max_lds() {
+    static int bytes = -1;
+    if (bytes < 0) {
+        int dev = 0, max_lds = 65536;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        bytes = 65536;
+        if (max_lds > 65536 &&
+            hipFuncSetAttribute((const void *)k_seg_merge<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                max_lds) == hipSuccess &&
+            hipFuncSetAttribute((const void *)k_seg_merge<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                max_lds) == hipSuccess)
+            bytes = max_lds;
+        (void)hipGetLastError();
+    }
+    return bytes;
+}
+
 size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h) {
     uint64_t cap_h = (uint64_t)lf << h;
     return 2 * cap_h * sizeof(uint64_t) + ((uint64_t)1 << h) * sizeof(uint32_t);
