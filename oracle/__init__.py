@@ -51,6 +51,8 @@ def _load():
     pu64, pi32 = C.POINTER(u64), C.POINTER(i32)
     lib.orc_create.restype = C.c_void_p
     lib.orc_create.argtypes = [u32, pu64, u64, u32, u32, u32, u32, u32, C.POINTER(C.c_int)]
+    lib.orc_set_lazy.restype = None
+    lib.orc_set_lazy.argtypes = [C.c_void_p, C.c_int]
     lib.orc_from_slots.restype = C.c_void_p
     lib.orc_from_slots.argtypes = [pu64, u64, u32, u32, u32, u32, u32, C.POINTER(C.c_int)]
     lib.orc_free.argtypes = [C.c_void_p]
@@ -104,10 +106,12 @@ def level_bounds(lf: int, H: int, tau_leaf=920, tau_root=800, rho_leaf=80, rho_r
 class OraclePMA:
     """Sequential GPMA+ (Section 5.2, Algorithm "GPMA+ Segment-Oriented
     Insertion", and its dual for deletions).  ``V > 0``: CSR-on-GPMA edge mode
-    (guards added, keys checked); ``V == 0``: raw integer keys."""
+    (guards added, keys checked); ``V == 0``: raw integer keys.  ``lazy``:
+    deletions mark entries in place (bit 63) without density maintenance;
+    merges drop the marked entries (Section 6, lazy deletion)."""
 
     def __init__(self, V: int, keys, leaf_size: int, tau_leaf=920, tau_root=800,
-                 rho_leaf=80, rho_root=400, _handle=None):
+                 rho_leaf=80, rho_root=400, _handle=None, lazy: bool = False):
         self._lib = _load()
         if _handle is not None:
             self._h = _handle
@@ -119,6 +123,8 @@ class OraclePMA:
         if not h:
             raise OracleError("orc_create failed (%d)" % err.value)
         self._h = h
+        if lazy:
+            self._lib.orc_set_lazy(h, 1)
 
     @classmethod
     def from_slots(cls, slots, leaf_size: int, tau_leaf=920, tau_root=800,
@@ -183,13 +189,22 @@ class OraclePMA:
 # --------------------------------------------------------------------------
 # read-outs of a slot image (plain numpy)
 
+TOMB = np.uint64(1 << 63)
+
+
 def stored(slots: np.ndarray) -> np.ndarray:
-    """Entries in array order (gaps dropped)."""
-    return slots[slots != EMPTY]
+    """Live entries in array order (gaps and lazily deleted entries dropped)."""
+    return slots[(slots & TOMB) == 0]
+
+
+def occupied(slots: np.ndarray) -> np.ndarray:
+    """Occupied slots in array order, marks cleared (lazily deleted entries
+    still order the array)."""
+    return slots[slots != EMPTY] & ~TOMB
 
 
 def edge_keys(slots: np.ndarray) -> np.ndarray:
-    """Stored edges in order, guards dropped."""
+    """Stored (live) edges in order, guards dropped."""
     s = stored(slots)
     return s[(s & np.uint64(0xFFFFFFFF)) != np.uint64(GUARD_DST)]
 
@@ -219,8 +234,9 @@ def check_invariants(slots: np.ndarray, lf: int, V: int = 0, allow_empty_leaves=
     by gaps; (iii) no leaf is empty (unless allowed); (iv) in edge mode every
     vertex has exactly one guard and the guards of rows u < w appear in order."""
     assert slots.size % lf == 0
+    o = occupied(slots)
+    assert np.all(o[1:] > o[:-1]), "keys not strictly ascending"
     s = stored(slots)
-    assert np.all(s[1:] > s[:-1]), "keys not strictly ascending"
     leaves = slots.reshape(-1, lf)
     occ = leaves != EMPTY
     cnt = occ.sum(axis=1)

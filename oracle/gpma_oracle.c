@@ -50,6 +50,10 @@
 
 #define ORC_EMPTY UINT64_MAX
 #define ORC_GUARD_DST 0xFFFFFFFFull
+/* lazy deletion (Section 6, the GPMA/GPMA+ setup of the experiments): a
+ * deleted entry stays in its slot, marked; keys have src < 2^31, so bit 63
+ * is free for the mark and the masked key keeps the array order */
+#define ORC_TOMB (1ull << 63)
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
 
@@ -66,6 +70,7 @@ typedef struct {
     int32_t *log_level;
     uint64_t *log_seg;
     uint64_t applied, noops;
+    int lazy;      /* deletions mark entries instead of merging */
 } orc_pma;
 
 /* ------------------------------------------------------------------------ */
@@ -113,6 +118,8 @@ static uint32_t log2_u64(uint64_t x)
 }
 
 static int is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+static int is_live(uint64_t k) { return k != ORC_EMPTY && !(k & ORC_TOMB); }
 
 /* ------------------------------------------------------------------------ */
 /* density bounds (Section 4.1, figure "PMA insertion example")             */
@@ -185,12 +192,13 @@ static void dispatch(uint64_t *slots, uint64_t base, uint32_t lf, uint64_t P,
     }
 }
 
-/* the stored entries of slots [base, base+len) in array order */
+/* the live entries of slots [base, base+len) in array order (a merge drops
+ * the marks of lazily deleted entries: their slots are recycled) */
 static uint64_t gather(const uint64_t *slots, uint64_t base, uint64_t len, uint64_t *out)
 {
     uint64_t m = 0;
     for (uint64_t i = 0; i < len; i++)
-        if (slots[base + i] != ORC_EMPTY) out[m++] = slots[base + i];
+        if (is_live(slots[base + i])) out[m++] = slots[base + i];
     return m;
 }
 
@@ -330,6 +338,7 @@ const int32_t *orc_log_levels(const orc_pma *p) { return p->log_level; }
 const uint64_t *orc_log_segs(const orc_pma *p) { return p->log_seg; }
 uint64_t orc_last_applied(const orc_pma *p) { return p->applied; }
 uint64_t orc_last_noops(const orc_pma *p) { return p->noops; }
+void orc_set_lazy(orc_pma *p, int lazy) { p->lazy = lazy ? 1 : 0; }
 
 /* ------------------------------------------------------------------------ */
 /* the batched update (Section 5.2, Algorithm GPMA+ Segment-Oriented
@@ -346,10 +355,10 @@ static int try_segment(orc_pma *p, uint32_t H, uint32_t h, uint64_t s,
     uint64_t mn, mx;
     orc_bounds(p, H, h, &mn, &mx);
 
-    /* CountSegment */
+    /* CountSegment: live entries (marked ones are free space) */
     uint64_t ns = 0;
     for (uint64_t i = 0; i < cap_h; i++)
-        if (p->slots[base + i] != ORC_EMPTY) ns++;
+        if (is_live(p->slots[base + i])) ns++;
 
     if (!del) {
         if (ns + k > mx) return 0;
@@ -380,14 +389,24 @@ static int apply_batch(orc_pma *p, const uint64_t *keys, uint64_t b, int del)
     memcpy(U, keys, b * sizeof(uint64_t));
     uint64_t nu = sort_unique(U, b);
 
-    /* the current content, in order, with the leaf of every entry */
-    uint64_t *ek = (uint64_t *)malloc((p->n ? p->n : 1) * sizeof(uint64_t));
-    uint64_t *el = (uint64_t *)malloc((p->n ? p->n : 1) * sizeof(uint64_t));
-    uint64_t ne = 0;
+    /* the current content, in order: every occupied slot (masked key, leaf,
+       position) and the live keys */
+    uint64_t occ = 0;
     for (uint64_t i = 0; i < p->cap; i++)
-        if (p->slots[i] != ORC_EMPTY) { ek[ne] = p->slots[i]; el[ne] = i / p->lf; ne++; }
+        if (p->slots[i] != ORC_EMPTY) occ++;
+    uint64_t *ok = (uint64_t *)malloc((occ ? occ : 1) * sizeof(uint64_t));
+    uint64_t *el = (uint64_t *)malloc((occ ? occ : 1) * sizeof(uint64_t));
+    uint64_t *ep = (uint64_t *)malloc((occ ? occ : 1) * sizeof(uint64_t));
+    uint64_t *ek = (uint64_t *)malloc((p->n ? p->n : 1) * sizeof(uint64_t));
+    uint64_t no = 0, ne = 0;
+    for (uint64_t i = 0; i < p->cap; i++) {
+        const uint64_t k = p->slots[i];
+        if (k == ORC_EMPTY) continue;
+        ok[no] = k & ~ORC_TOMB; el[no] = i / p->lf; ep[no] = i; no++;
+        if (is_live(k)) ek[ne++] = k;
+    }
 
-    /* drop no-ops: inserting a stored key, deleting an absent one */
+    /* drop no-ops: inserting a live key, deleting a key that is not live */
     uint64_t r = 0;
     for (uint64_t i = 0; i < nu; i++) {
         int present = contains(ek, ne, U[i]);
@@ -396,14 +415,27 @@ static int apply_batch(orc_pma *p, const uint64_t *keys, uint64_t b, int del)
     }
     p->noops += b - nu;   /* in-batch repeats are no-ops too */
 
-    /* BinarySearchLeafSegments: leaf of the greatest stored key <= u */
+    if (del && p->lazy) {
+        /* lazy deletion: mark each entry in place, no density maintenance */
+        for (uint64_t i = 0; i < r; i++) {
+            uint64_t c = count_below(ok, no, U[i]);
+            p->slots[ep[c]] |= ORC_TOMB;
+        }
+        p->n -= r;
+        p->applied = r;
+        free(ok); free(el); free(ep); free(ek); free(U);
+        return ORC_OK;
+    }
+
+    /* BinarySearchLeafSegments: leaf of the greatest occupied key <= u (a
+       marked entry still orders the array) */
     uint64_t *leaf = (uint64_t *)malloc((r ? r : 1) * sizeof(uint64_t));
     for (uint64_t i = 0; i < r; i++) {
-        uint64_t c = count_below(ek, ne, U[i]);           /* stored keys < u */
-        if (c < ne && ek[c] == U[i]) leaf[i] = el[c];      /* u itself (delete) */
+        uint64_t c = count_below(ok, no, U[i]);           /* occupied keys < u */
+        if (c < no && ok[c] == U[i]) leaf[i] = el[c];      /* u itself */
         else leaf[i] = c ? el[c - 1] : 0;
     }
-    free(el);
+    free(el); free(ok); free(ep);
 
     uint64_t *bufE = (uint64_t *)malloc((p->cap + r + 1) * sizeof(uint64_t));
     uint64_t *bufM = (uint64_t *)malloc((p->cap + r + 1) * sizeof(uint64_t));

@@ -384,3 +384,83 @@ def test_stream_generators_explicit_deletions_and_sorted_arrivals():
     arr = s2.order[s2.window:]
     assert bool((arr[1:] >= arr[:-1]).all())
     assert sorted(arr.tolist()) == sorted(st.order[st.window:].tolist())
+
+
+# --------------------------------------------------------------------------
+# lazy deletion (Section 6: deleted entries are marked in place, without
+# density maintenance, and their slots are recycled by later insertions)
+
+def _lazy_pair(V, init, lf, seed):
+    rng = np.random.default_rng(seed)
+    lazy = O.OraclePMA(V, init, lf, lazy=True)
+    eager = O.OraclePMA(V, init, lf)
+    return rng, lazy, eager
+
+
+def test_lazy_deletion_marks_only_the_deleted_entries():
+    V, lf = 64, 16
+    init = np.unique(np.array([(a << 32) | b for a in range(V) for b in range(0, V, 5)], np.uint64))
+    _, lazy, _ = _lazy_pair(V, init, lf, 0)
+    before = lazy.slots()
+    dels = init[::7]
+    absent = np.array([(3 << 32) | 1], np.uint64)
+    lazy.delete(np.concatenate([dels, dels[:5], absent]))
+    after = lazy.slots()
+    changed = np.nonzero(before != after)[0]
+    assert np.array_equal(np.sort(before[changed]), np.sort(dels))      # exactly the deleted keys
+    assert np.all(after[changed] == (before[changed] | O.TOMB))          # marked, not moved
+    assert lazy.last_applied() == dels.size
+    assert lazy.capacity == O.OraclePMA(V, init, lf).capacity           # no density maintenance
+    O.check_invariants(after, lf, V)
+    assert np.array_equal(O.edge_keys(after), np.setdiff1d(init, dels))
+
+
+def test_lazy_deletion_against_sets_and_eager_mode():
+    """Random sequences of lazy deletes and inserts: the live edges equal a
+    Python set (and the eager PMA's edges) after every batch; the structural
+    invariants hold with marked entries in place; re-inserting a deleted key
+    brings it back."""
+    for seed in range(4):
+        V, lf = 40, 16
+        rng = np.random.default_rng(seed)
+        init = np.unique(rng.integers(0, V, (300, 2)).astype(np.uint64) @ np.array([1 << 32, 1], np.uint64))
+        lazy = O.OraclePMA(V, init, lf, lazy=True)
+        eager = O.OraclePMA(V, init, lf)
+        live = set(int(x) for x in init)
+        for t in range(40):
+            if rng.random() < 0.5 and live:
+                pool = np.array(sorted(live), np.uint64)
+                b = np.concatenate([pool[rng.choice(pool.size, min(pool.size, int(rng.integers(1, 60))),
+                                                   replace=False)],
+                                    rng.integers(0, V, (5, 2)).astype(np.uint64) @ np.array([1 << 32, 1],
+                                                                                           np.uint64)])
+                lazy.delete(b)
+                eager.delete(b)
+                live -= set(int(x) for x in b)
+            else:
+                b = rng.integers(0, V, (int(rng.integers(1, 120)), 2)).astype(np.uint64) @ \
+                    np.array([1 << 32, 1], np.uint64)
+                lazy.insert(b)
+                eager.insert(b)
+                live |= set(int(x) for x in b)
+            s = lazy.slots()
+            O.check_invariants(s, lf, V)
+            want = np.array(sorted(live), np.uint64)
+            assert np.array_equal(O.edge_keys(s), want), (seed, t)
+            assert np.array_equal(O.edge_keys(eager.slots()), want)
+
+
+def test_lazy_insert_merge_recycles_marked_slots():
+    """An insert merged into a leaf drops the marked entries of that leaf; a
+    deleted key inserted again is live once, mark gone."""
+    V, lf = 8, 16
+    init = np.array([(0 << 32) | v for v in range(7)], np.uint64)
+    lazy = O.OraclePMA(V, init, lf, lazy=True)
+    lazy.delete(init[[1, 3, 5]])
+    s = lazy.slots()
+    assert ((s & O.TOMB) != 0).sum() - (s == O.EMPTY).sum() == 3
+    lazy.insert(np.array([init[3]], np.uint64))
+    s = lazy.slots()
+    assert ((s != O.EMPTY) & ((s & O.TOMB) != 0)).sum() == 0               # marks dropped by the merge
+    assert np.array_equal(O.edge_keys(s), np.sort(init[[0, 2, 3, 4, 6]]))
+    O.check_invariants(s, lf, V)
