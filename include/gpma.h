@@ -108,6 +108,19 @@ typedef struct {
  * runtime's graph launch cost (the autotuner measures both). */
 #define GPMA_FLAG_FUSED_DIRECT 4u
 
+/* Lazy deletion, the way GPMA and GPMA+ handle deletions in the experiments
+ * of Section 6: a delete marks its entry in place (bit 63 of the slot set)
+ * and moves nothing, so a delete batch never climbs the tree and the array
+ * never shrinks.  A marked entry still orders the array by its key with the
+ * bit cleared (leaf pivots, the locate rule), counts as free space in every
+ * density test, and is dropped by the next merge, rebuild or resize that
+ * rewrites its leaf; re-inserting a marked key merges it like any absent
+ * key.  Exported slots show the marks; exported keys, degrees, row offsets
+ * and the analytics see live edges only; gpma_export_leaf_counts counts
+ * occupied slots (live and marked).  Mirrors are marked alike.  Costs one
+ * uint32 per leaf. */
+#define GPMA_FLAG_LAZY_DELETE 8u
+
 /* Per-batch statistics; filled when a non-NULL pointer is passed. */
 typedef struct {
     uint64_t requested;      /* keys passed in */
@@ -146,7 +159,8 @@ int gpma_insert_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
 /* Set difference (the dual of insertion, Section 4.1): a segment absorbs
  * its deletions iff it stays above its lower bound; the root halves when it
  * falls below its own.  Absent keys are no-ops; guards cannot be named
- * (dst must be < V). */
+ * (dst must be < V).  With GPMA_FLAG_LAZY_DELETE each present key is marked
+ * in its leaf instead (no merge, no resize). */
 int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
                       hipStream_t stream, gpma_stats *stats);
 

@@ -66,8 +66,8 @@ k_pr_push(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, 
         uint64_t k0, k1 = kEmpty;
         if (o + 1 < c) ld_stream2(slots + p, k0, k1);
         else k0 = ld_stream(slots + p);
-        if (!is_guard(k0)) unsafeAtomicAdd(&y[key_dst(k0)], contrib[key_src(k0)]);
-        if (k1 != kEmpty && !is_guard(k1)) unsafeAtomicAdd(&y[key_dst(k1)], contrib[key_src(k1)]);
+        if (is_edge_entry(k0)) unsafeAtomicAdd(&y[key_dst(k0)], contrib[key_src(k0)]);
+        if (is_edge_entry(k1)) unsafeAtomicAdd(&y[key_dst(k1)], contrib[key_src(k1)]);
     }
 }
 
@@ -99,10 +99,10 @@ __device__ __forceinline__ PullLane pull_load(const uint64_t *__restrict__ slots
     else if (o < c) k0 = ld_stream(slots + p);
     uint64_t last = 0;
     if (o + 1 >= c) last = slots[(leaf << lf_log2) + c - 1];
-    L.r0 = (uint32_t)((o < c ? k0 : last) >> 32);
-    L.r1 = (uint32_t)((o + 1 < c ? k1 : last) >> 32);
-    if (o < c && !is_guard(k0)) L.a = contrib[key_dst(k0)];
-    if (o + 1 < c && !is_guard(k1)) L.b = contrib[key_dst(k1)];
+    L.r0 = (uint32_t)(order_key(o < c ? k0 : last) >> 32);
+    L.r1 = (uint32_t)(order_key(o + 1 < c ? k1 : last) >> 32);
+    if (o < c && is_edge_entry(k0)) L.a = contrib[key_dst(k0)];
+    if (o + 1 < c && is_edge_entry(k1)) L.b = contrib[key_dst(k1)];
     return L;
 }
 
@@ -228,7 +228,7 @@ k_bfs_expand(const uint64_t *__restrict__ slots, uint64_t cap, const uint32_t *_
                 }
                 const uint64_t p = rstart + (t - roff);
                 const uint64_t k = p < cap ? slots[p] : kEmpty;
-                if (k != kEmpty && !is_guard(k)) {
+                if (is_edge_entry(k)) {
                     v = key_dst(k);
                     if (__hip_atomic_load(&dist[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0)
                         claim = atomicCAS(&dist[v], -1, level + 1) == -1;
@@ -266,7 +266,7 @@ k_bfs_bottom_up(const uint64_t *__restrict__ mslots, const uint32_t *__restrict_
             const uint32_t end = mrow[v + 1];
             for (uint32_t p = mrow[v]; p < end; p++) {
                 const uint64_t k = mslots[p];
-                if (k == kEmpty) continue;
+                if (!is_live(k)) continue;   // gap or marked entry
                 if (is_guard(k)) break;
                 const uint32_t u = (uint32_t)k;
                 if (__hip_atomic_load(&dist[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == level) {
@@ -311,7 +311,7 @@ k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uin
     bool any = false;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
         uint64_t k = ld_stream(slots + p);
-        if (k == kEmpty || is_guard(k)) continue;
+        if (!is_edge_entry(k)) continue;
         uint32_t a = cc_find(label, key_src(k));
         uint32_t b = cc_find(label, key_dst(k));
         if (a != b) {
@@ -326,7 +326,8 @@ k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uin
 // Sampling round (the approach of Afforest, Sutton et al.): every vertex is
 // hooked to the first entry of its row (out-row on the array, in-row on the
 // dst-major mirror).  Row v starts after guard v-1; a leaf's gap tail may sit
-// between them, so the scan skips empty slots (at most one leaf's worth).
+// between them, so the scan skips empty slots and marked entries (at most
+// one leaf's worth; a row not sampled is left to the sweeps).
 __global__ void __launch_bounds__(256)
 k_cc_sample(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint32_t V, uint32_t lf,
             uint32_t *label) {
@@ -337,9 +338,9 @@ k_cc_sample(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row
     uint64_t k = kEmpty;
     for (uint32_t t = 0; t <= lf && p < end; t++, p++) {
         k = slots[p];
-        if (k != kEmpty) break;
+        if (is_live(k)) break;
     }
-    if (k == kEmpty || is_guard(k)) return;
+    if (!is_edge_entry(k)) return;
     const uint32_t a = cc_find(label, key_src(k));
     const uint32_t b = cc_find(label, key_dst(k));
     if (a != b) atomicMin(&label[a > b ? a : b], a > b ? b : a);
@@ -356,7 +357,7 @@ k_cc_hook_skip(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label
     uint32_t last_u = 0xFFFFFFFFu, last_r = 0;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
         const uint64_t k = ld_stream(slots + p);
-        if (k == kEmpty || is_guard(k)) continue;
+        if (!is_edge_entry(k)) continue;
         const uint32_t u = key_src(k);
         if (u != last_u) {
             last_u = u;

@@ -55,6 +55,7 @@ struct gpma {
     uint16_t *cnt = nullptr;
     uint32_t *row_ptr = nullptr;
     uint32_t *deg = nullptr;
+    uint32_t *dead = nullptr;   // lazy deletion: marked entries per leaf (null when off)
 
     // batch scratch
     uint64_t bcap = 0;
@@ -220,7 +221,9 @@ bool params_valid(const gpma_params *p, bool allow_auto) {
           p->tau_root_pm <= p->tau_leaf_pm && p->tau_leaf_pm < 1000))
         return false;
     if (2 * p->rho_root_pm > p->tau_root_pm) return false;
-    if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT)) return false;
+    if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT |
+                               GPMA_FLAG_LAZY_DELETE))
+        return false;
     if (p->sort_tile_keys != 0 && p->sort_tile_keys != 512 && p->sort_tile_keys != 1024 && p->sort_tile_keys != 2048)
         return false;
     if (p->fused_levels > 3) return false;
@@ -361,7 +364,7 @@ void set_geometry(gpma *g, uint64_t cap) {
 int segment_offsets(gpma *g, uint64_t first, uint64_t P, uint64_t *ns, hipStream_t s) {
     int e = ensure_dt(g, 0, P);
     if (e) return e;
-    launch_leaf_counts_u32(g->cnt, first, P, g->dt_off, s);
+    launch_leaf_counts_u32(g->cnt, g->dead, first, P, g->dt_off, s);
     scan_u32(g->dt_off, g->dt_off, P, g->small, g->dt_tmp, s);
     hipMemcpyAsync(g->small_h, g->small, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
@@ -382,23 +385,27 @@ int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t
     if (e) return e;
     uint64_t *nslots = g->slots;
     uint16_t *ncnt = g->cnt;
+    uint32_t *ndead = g->dead;
     if (ncap != g->cap) {
         if (dev_alloc(&nslots, ncap)) return GPMA_ENOMEM;
-        if (dev_alloc(&ncnt, ncap >> g->lf_log2)) {
+        if (dev_alloc(&ncnt, ncap >> g->lf_log2) || (g->dead && dev_alloc(&ndead, ncap >> g->lf_log2))) {
             dev_free(nslots);
+            dev_free(ncnt);
             return GPMA_ENOMEM;
         }
     }
-    launch_gather_segment(g->slots, g->cnt, 0, g->L, g->lf, g->dt_off, g->dtA, s);
+    launch_gather_segment(g->slots, g->cnt, g->dead, 0, g->L, g->lf, g->dt_off, g->dtA, s);
     launch_merge_sorted(del, g->dtA, ns, U, k, g->dtB, s);
-    launch_dispatch(g->dtB, N, nslots, ncnt, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
+    launch_dispatch(g->dtB, N, nslots, ncnt, ndead, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
     launch_mark_done(del, U, status, 0, k, g->deg, g->ctl, ncap, true, s);
     if (ncap != g->cap) {
         hipStreamSynchronize(s);
         dev_free(g->slots);
         dev_free(g->cnt);
+        if (g->dead) dev_free(g->dead);
         g->slots = nslots;
         g->cnt = ncnt;
+        g->dead = ndead;
         set_geometry(g, ncap);
     }
     return GPMA_OK;
@@ -433,9 +440,10 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
         if (pass) {
             e = ensure_dt(g, ns + k, 0);
             if (e) return e;
-            launch_gather_segment(g->slots, g->cnt, first, P, g->lf, g->dt_off, g->dtA, s);
+            launch_gather_segment(g->slots, g->cnt, g->dead, first, P, g->lf, g->dt_off, g->dtA, s);
             launch_merge_sorted(del, g->dtA, ns, c.k + i, k, g->dtB, s);
-            launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->cnt, g->row_ptr, first, P, g->lf, s);
+            launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->cnt, g->dead, g->row_ptr, first, P, g->lf,
+                            s);
             launch_mark_done(del, c.k, c.st, i, k, g->deg, g->ctl, P << g->lf_log2, false, s);
         }
         i = j;
@@ -604,7 +612,7 @@ int finish_levels(gpma *g, bool del, LevelArrays cur, uint64_t rem, uint32_t h_s
             pa = pb = nullptr;
             if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
             launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, rem, g->slots, g->cnt, g->row_ptr,
-                             g->deg, g->lf, lo, hi, g->ctl, s);
+                             g->deg, g->dead, g->lf, lo, hi, g->ctl, s);
             if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
         } else {
             pa = pb = nullptr;
@@ -699,13 +707,18 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
         ps.done(16.0 * (double)b);
     }
 
-    // level 0 (fused with the no-op probe)
+    // level 0 (fused with the no-op probe); with lazy deletion a delete only
+    // marks its entry and never reaches the levels
+    const bool mark = del && g->dead;
     uint64_t lo, hi;
     bounds(g, g->H, 0, &lo, &hi);
     hipEvent_t pa = nullptr, pb = nullptr;
     if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
-    launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->row_ptr, g->deg,
-                      g->lf, lo, hi, g->ctl, s);
+    if (mark)
+        launch_leaf_mark(cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->dead, g->deg, g->lf, g->ctl, s);
+    else
+        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+                          g->lf, lo, hi, g->ctl, s);
     if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
     compact_pending(cur.k, cur.l, cur.st, cur.n, b, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del,
                     g->lf, g->ctl, s);
@@ -717,7 +730,8 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     const uint64_t distinct = g->ctl_h->n_in;
     uint32_t segs_seen = g->ctl_h->segs;
     if (pa) g->prof_pending.push_back(Prof{GPMA_K_LEAF_MERGE, pa, pb,
-                                           16.0 * g->lf * segs_seen + 12.0 * (double)distinct});
+                                           mark ? 20.0 * (double)distinct
+                                                : 16.0 * g->lf * segs_seen + 12.0 * (double)distinct});
     if (st) {
         st->segments_merged[0] = segs_seen;
         if (segs_seen) st->top_level = 0;
@@ -755,7 +769,7 @@ void free_all(gpma *g) {
     if (g->ev_fork) hipEventDestroy(g->ev_fork);
     if (g->ev_join) hipEventDestroy(g->ev_join);
     g->ev_fork = g->ev_join = nullptr;
-    dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg);
+    dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg); dev_free(g->dead);
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
     dev_free(g->pb_offs); dev_free(g->pb_tmp); dev_free(g->pb_small); dev_free(g->pb_pieces); dev_free(g->pb_rec);
@@ -872,8 +886,12 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     do_locate(g, cur.k, cur.n, cls, cur.l, cur.st, s);
     uint64_t lo, hi;
     bounds(g, g->H, 0, &lo, &hi);
-    launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf, lo,
-                      hi, g->ctl, s);
+    const bool mark = del && g->dead;   // lazy deletion: marks only, no levels
+    if (mark)
+        launch_leaf_mark(cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->dead, g->deg, g->lf, g->ctl, s);
+    else
+        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+                          g->lf, lo, hi, g->ctl, s);
     compact_pending(cur.k, cur.l, cur.st, cur.n, cls, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del, g->lf,
                     g->ctl, s);
     auto other = [&](const LevelArrays &c) {
@@ -890,11 +908,12 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     // levels above the leaves that a batch covers (g->fused_levels); a batch
     // with updates left above them stops the sequence and finishes on the
     // host-driven path
-    for (uint32_t h = 1; h <= g->fused_levels && h < g->H && seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds;
+    for (uint32_t h = 1; !mark && h <= g->fused_levels && h < g->H &&
+                         seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds;
          h++) {
         bounds(g, g->H, h, &lo, &hi);
-        launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->lf,
-                         lo, hi, g->ctl, s);
+        launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+                         g->lf, lo, hi, g->ctl, s);
         compact_pending(cur.k, cur.l, cur.st, cur.n, cls, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del,
                         (uint64_t)g->lf << h, g->ctl, s);
         cur = nxt;
@@ -1203,7 +1222,7 @@ extern "C" int gpma_snapshot_refresh(gpma_t *src, gpma_t *snap, hipStream_t s) {
 
 extern "C" uint64_t gpma_device_bytes(const gpma_t *g) {
     if (!g) return 0;
-    uint64_t b = g->cap * 8 + g->L * 2 + ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4;
+    uint64_t b = g->cap * 8 + g->L * 2 + ((uint64_t)g->V + 1) * 4 + (uint64_t)g->V * 4 + (g->dead ? g->L * 4 : 0);
     if (g->mir) b += gpma_device_bytes(g->mir);
     return b;
 }
@@ -1317,6 +1336,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     e |= dev_alloc(&g->cnt, g->L);
     e |= dev_alloc(&g->row_ptr, (uint64_t)V + 1);
     e |= dev_alloc(&g->deg, V);
+    if (p.flags & GPMA_FLAG_LAZY_DELETE) e |= dev_alloc(&g->dead, g->L);   // zeroed by the dispatch
     if (e) {
         cleanup();
         free_all(g);
@@ -1328,7 +1348,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     g->fused_direct = (p.flags & GPMA_FLAG_FUSED_DIRECT) != 0;
     g->sort_chunks = p.sort_tile_keys ? (int)(p.sort_tile_keys / 256) : 4;
     g->fused_levels = p.fused_levels;
-    launch_dispatch(uq, nu, g->slots, g->cnt, g->row_ptr, 0, g->L, lf, s);
+    launch_dispatch(uq, nu, g->slots, g->cnt, g->dead, g->row_ptr, 0, g->L, lf, s);
     launch_degrees_from_sorted(uq, nu, V, fl, g->deg, s);
     if (hipStreamSynchronize(s) != hipSuccess) {
         cleanup();
@@ -1345,7 +1365,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     }
     if (p.flags & GPMA_FLAG_MIRROR) {
         gpma_params mp = p;
-        mp.flags = p.flags & (GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT);
+        mp.flags = p.flags & (GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT | GPMA_FLAG_LAZY_DELETE);
         mp.leaf_size = g->lf;
         uint64_t *tk = nullptr;
         if (n && dev_alloc(&tk, n)) {

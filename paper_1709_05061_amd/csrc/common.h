@@ -34,6 +34,16 @@ struct Ctl {
 __device__ __forceinline__ bool is_guard(uint64_t k) {
     return (uint32_t)k == kGuardDst;
 }
+
+// Lazy deletion marks an entry in place by setting bit 63 (keys and guards
+// have src < 2^31, so the bit is free).  Gaps (all ones) and marked entries
+// are exactly the slots whose top bit is set.
+constexpr uint64_t kTomb = 1ull << 63;
+__device__ __forceinline__ bool is_live(uint64_t k) { return (int64_t)k >= 0; }
+// a live edge: not a gap, not marked, not a guard
+__device__ __forceinline__ bool is_edge_entry(uint64_t k) { return is_live(k) && !is_guard(k); }
+// the key an occupied slot orders by (a marked entry keeps its place)
+__device__ __forceinline__ uint64_t order_key(uint64_t k) { return k == kEmpty ? k : (k & ~kTomb); }
 __device__ __forceinline__ uint32_t key_src(uint64_t k) { return (uint32_t)(k >> 32); }
 __device__ __forceinline__ uint32_t key_dst(uint64_t k) { return (uint32_t)k; }
 
@@ -171,26 +181,32 @@ void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max,
                    uint32_t *leaf, uint8_t *status, hipStream_t s);
 void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
                        const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
-                       uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t min0,
+                       uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf, uint64_t min0,
                        uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s);
 // workgroup tier at height h >= 1; needs seg_merge_lds_bytes(lf, h) <= max LDS
 size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h);
 int seg_merge_max_lds();
 void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
                       uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
-                      uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t minh,
-                      uint64_t maxh, gpma_dev::Ctl *ctl, hipStream_t s);
+                      uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf,
+                      uint64_t minh, uint64_t maxh, gpma_dev::Ctl *ctl, hipStream_t s);
 // device tier pieces (one segment at a time; also the root rebuild and bulk load)
-void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, uint64_t first_leaf,
-                           uint64_t P, uint32_t lf, const uint32_t *leaf_off, uint64_t *out,
-                           hipStream_t s);
+// (dead: per-leaf marked counts of a lazy-deletion array, else null; the
+// counts and the gather then cover live entries only)
+void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, const uint32_t *dead,
+                           uint64_t first_leaf, uint64_t P, uint32_t lf, const uint32_t *leaf_off,
+                           uint64_t *out, hipStream_t s);
 void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_t *U, uint64_t k,
                          uint64_t *out, hipStream_t s);
-void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt,
+void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *dead,
                      uint32_t *row_ptr, uint64_t first_leaf, uint64_t P, uint32_t lf,
                      hipStream_t s);
-void launch_leaf_counts_u32(const uint16_t *cnt, uint64_t first_leaf, uint64_t P, uint32_t *out,
-                            hipStream_t s);
+void launch_leaf_counts_u32(const uint16_t *cnt, const uint32_t *dead, uint64_t first_leaf, uint64_t P,
+                            uint32_t *out, hipStream_t s);
+// lazy deletion: mark the located unique keys in place (status kDone/kNoop)
+void launch_leaf_mark(const uint64_t *keys, const uint32_t *leaf, uint8_t *status, const uint32_t *n_dev,
+                      uint64_t n_max, uint64_t *slots, const uint16_t *cnt, uint32_t *dead, uint32_t *deg,
+                      uint32_t lf, const gpma_dev::Ctl *ctl, hipStream_t s);
 // count=true: also add to ctl (used by the root rebuild, after which no
 // compaction pass runs)
 void launch_mark_done(bool del, const uint64_t *keys, uint8_t *status, uint64_t first,

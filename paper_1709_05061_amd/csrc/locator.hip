@@ -113,13 +113,18 @@ __device__ __forceinline__ uint64_t predict_in_span(float t, const Span &sp) {
     return sp.first + (uint64_t)f;
 }
 
+// leaf j's pivot: its first entry, a marked one ordering by its masked key
+__device__ __forceinline__ uint64_t pivot(const uint64_t *slots, uint32_t lf_log2, uint64_t j) {
+    return slots[j << lf_log2] & ~kTomb;
+}
+
 // the largest leaf j in [lo, hi] with pivot(j) <= k (lo if none)
 __device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t lf_log2, uint64_t lo,
                                                  uint64_t hi, uint64_t k) {
     uint64_t a = lo, b = hi + 1;   // pivots in [a, b) : count of those <= k
     while (a < b) {
         const uint64_t mid = (a + b) >> 1;
-        if (slots[mid << lf_log2] <= k) a = mid + 1; else b = mid;
+        if (pivot(slots, lf_log2, mid) <= k) a = mid + 1; else b = mid;
     }
     return a > lo ? a - 1 : lo;
 }
@@ -150,8 +155,8 @@ k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
         const uint64_t e = (uint64_t)(m.delta * (float)span) + 2;
         const uint64_t lo = p > sp.first + e ? p - e : sp.first;
         const uint64_t hi = p + e < sp.last ? p + e : sp.last;
-        const bool ok_lo = lo == sp.first || slots[lo << lf_log2] <= k;
-        const bool ok_hi = hi == sp.last || slots[(hi + 1) << lf_log2] > k;
+        const bool ok_lo = lo == sp.first || pivot(slots, lf_log2, lo) <= k;
+        const bool ok_hi = hi == sp.last || pivot(slots, lf_log2, hi + 1) > k;
         if (m.valid && m.L == L && ok_lo && ok_hi) {
             j = search_range(slots, lf_log2, lo, hi, k);
         } else {
@@ -183,7 +188,7 @@ k_loc_gram(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_
             bool use = false;
             if (s < S) {
                 const uint64_t j = s * stride;
-                const uint64_t k = slots[j << lf_log2];
+                const uint64_t k = pivot(slots, lf_log2, j);
                 const Span sp = row_span(row_ptr, key_src(k), lf_log2);
                 const uint64_t span = sp.last - sp.first + 1;
                 if (!is_guard(k) && span > kMinSpan) {
@@ -230,7 +235,7 @@ k_loc_eval(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_
     // the loop bound is wave-uniform (L is a multiple of 64 or the wave is the last)
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < L; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
-        const uint64_t k = j < L ? slots[j << lf_log2] : 0;
+        const uint64_t k = j < L ? pivot(slots, lf_log2, j) : 0;
         const float t = model_position(m, k, s_out + (threadIdx.x & ~63u));
         if (j < L && !is_guard(k)) {
             const Span sp = row_span(row_ptr, key_src(k), lf_log2);

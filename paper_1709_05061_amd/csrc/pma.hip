@@ -3,8 +3,16 @@
 //
 // Layout (HBM): slots[cap] uint64 sorted keys with gaps (kEmpty); leaf j is
 // slots[j*lf, (j+1)*lf) and always holds a packed prefix of cnt[j] >= 1
-// entries followed by gaps; row_ptr[V+1] uint32 CSR offsets (row u ends with
-// its guard); deg[V] uint32 out-degrees.
+// occupied entries followed by gaps; row_ptr[V+1] uint32 CSR offsets (row u
+// ends with its guard); deg[V] uint32 out-degrees.
+//
+// Lazy deletion (the GPMA/GPMA+ setup of Section 6): a delete marks its entry
+// in place (bit 63) and counts it in dead[j] of its leaf; nothing moves.  A
+// marked entry keeps ordering the array by its masked key, so the leaf
+// pivots and the locate rule see it like a live one, but every density test
+// counts live entries only (cnt - dead) and every merge drops the marked
+// entries of the segments it rewrites (and clears their dead counts).  With
+// lazy deletion off, dead is null and nothing below changes.
 //
 // Tiers of TryInsert+ (Section 5.2 and Appendix A, warp / block / device):
 //   level 0   k_leaf_merge: a group of lf/SPL lanes of one wave per leaf, the
@@ -44,7 +52,8 @@ __global__ void k_append_guards(uint64_t *__restrict__ dst, uint32_t V) {
 // BinarySearchLeafSegments: the leaf of key k is the leaf holding the
 // greatest stored key <= k, leaf 0 when there is none.  No leaf is ever empty,
 // so the first slot of every leaf is its smallest key and those pivots
-// ascend strictly: a plain binary search over slots[j*lf].
+// ascend strictly: a plain binary search over slots[j*lf] (a marked entry
+// orders by its masked key).
 
 __global__ void k_locate(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev,
                          uint64_t n_max, const uint64_t *__restrict__ slots, uint64_t L,
@@ -56,7 +65,7 @@ __global__ void k_locate(const uint64_t *__restrict__ keys, const uint32_t *__re
     uint64_t lo = 0, hi = L;   // count of leaves whose pivot is <= k
     while (lo < hi) {
         uint64_t mid = (lo + hi) >> 1;
-        if (slots[mid << lf_log2] <= k) lo = mid + 1; else hi = mid;
+        if ((slots[mid << lf_log2] & ~kTomb) <= k) lo = mid + 1; else hi = mid;
     }
     leaf[i] = (uint32_t)(lo ? lo - 1 : 0);
     status[i] = kPending;
@@ -107,8 +116,8 @@ __global__ void __launch_bounds__(256)
 k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
              uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
              uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
-             uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t min0,
-             uint32_t max0, Ctl *__restrict__ ctl) {
+             uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
+             uint32_t min0, uint32_t max0, Ctl *__restrict__ ctl) {
     constexpr int LF = G * SPL;
     constexpr int GPB = 256 / G;   // groups per block
     __shared__ uint64_t s_leaf[GPB][LF];
@@ -133,11 +142,27 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
     const uint64_t base = (uint64_t)lf_i * LF;
     uint64_t mine[SPL];
 #pragma unroll
-    for (int q = 0; q < SPL; q++) {
-        mine[q] = slots[base + gl * SPL + q];
-        lb[gl * SPL + q] = mine[q];
+    for (int q = 0; q < SPL; q++) mine[q] = slots[base + gl * SPL + q];
+    uint32_t c = cnt[lf_i];
+    if (dead && dead[lf_i]) {
+        // the leaf holds marked entries: stage its live entries only, packed
+        // in order (the merge below drops the marked ones)
+        uint32_t nl = 0;
+#pragma unroll
+        for (int q = 0; q < SPL; q++) nl += (gl * SPL + q < c && is_live(mine[q])) ? 1u : 0u;
+        uint32_t pos = group_excl_scan<G>(nl, gl);
+        const uint32_t live = group_sum<G>(nl);
+#pragma unroll
+        for (int q = 0; q < SPL; q++)
+            if (gl * SPL + q < c && is_live(mine[q])) lb[pos++] = mine[q];
+        c = live;
+        wave_lds_sync();
+#pragma unroll
+        for (int q = 0; q < SPL; q++) mine[q] = lb[gl * SPL + q];
+    } else {
+#pragma unroll
+        for (int q = 0; q < SPL; q++) lb[gl * SPL + q] = mine[q];
     }
-    const uint32_t c = cnt[lf_i];
     wave_lds_sync();
 
     // classify the run: applicable updates are compacted (in key order) into ub
@@ -188,7 +213,10 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
         slots[base + p] = v;
         if (p < N && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(base + p + 1);
     }
-    if (gl == 0) cnt[lf_i] = (uint16_t)N;
+    if (gl == 0) {
+        cnt[lf_i] = (uint16_t)N;
+        if (dead) dead[lf_i] = 0;
+    }
     // statuses of the run were written by the same lanes in the classify loop
     for (uint32_t t = gl; t < k; t += G) {
         uint8_t st = status[i + t];
@@ -250,8 +278,9 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
                                               const uint32_t *__restrict__ leaf,
                                               uint8_t *__restrict__ status, uint64_t *__restrict__ slots,
                                               uint16_t *__restrict__ cnt, uint32_t *__restrict__ row_ptr,
-                                              uint32_t *__restrict__ deg, uint32_t lf_log2, uint64_t minh,
-                                              uint64_t maxh, uint64_t *dyn, uint32_t *s_misc) {
+                                              uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
+                                              uint32_t lf_log2, uint64_t minh, uint64_t maxh, uint64_t *dyn,
+                                              uint32_t *s_misc) {
     const uint32_t s = leaf[i] >> h;
     if (i > 0 && (leaf[i - 1] >> h) == s) return;
     const uint32_t e = run_end(leaf, i, n, s, h);
@@ -266,17 +295,36 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
     uint64_t *E = dyn;
     uint64_t *U = dyn + cap_h;
     uint32_t *off = (uint32_t *)(dyn + 2 * cap_h);
-    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) off[j] = cnt[first_leaf + j];
+    // CountSegment: live entries per leaf (marked ones are free space)
+    for (uint32_t j = threadIdx.x; j < P; j += blockDim.x)
+        off[j] = cnt[first_leaf + j] - (dead ? dead[first_leaf + j] : 0u);
     __syncthreads();
     uint32_t ns;
     block_scan_counts(off, P, &ns, s_misc);
     const bool pass = DEL ? ((uint64_t)ns >= (uint64_t)k + minh) : ((uint64_t)ns + k <= maxh);
     if (!pass) return;
 
-    for (uint64_t p = threadIdx.x; p < cap_h; p += blockDim.x) {
-        uint32_t j = (uint32_t)(p >> lf_log2), o = (uint32_t)(p & (lf - 1));
-        uint32_t cj = (j + 1 < P ? off[j + 1] : ns) - off[j];
-        if (o < cj) E[off[j] + o] = slots[base + p];
+    if (dead) {
+        // marked entries may sit anywhere in a leaf's prefix: one wave per
+        // leaf keeps the live ones, in order, by ballot
+        const uint32_t lane = threadIdx.x & (kWave - 1);
+        for (uint32_t j = threadIdx.x / kWave; j < P; j += blockDim.x / kWave) {
+            const uint32_t cj = cnt[first_leaf + j];
+            uint32_t at = off[j];
+            for (uint32_t o0 = 0; o0 < cj; o0 += kWave) {
+                const uint32_t o = o0 + lane;
+                const uint64_t v = o < cj ? slots[base + ((uint64_t)j << lf_log2) + o] : kEmpty;
+                const uint64_t m = __ballot(is_live(v));
+                if (is_live(v)) E[at + __popcll(m & lanemask_lt())] = v;
+                at += (uint32_t)__popcll(m);
+            }
+        }
+    } else {
+        for (uint64_t p = threadIdx.x; p < cap_h; p += blockDim.x) {
+            uint32_t j = (uint32_t)(p >> lf_log2), o = (uint32_t)(p & (lf - 1));
+            uint32_t cj = (j + 1 < P ? off[j + 1] : ns) - off[j];
+            if (o < cj) E[off[j] + o] = slots[base + p];
+        }
     }
     for (uint32_t t = threadIdx.x; t < k; t += blockDim.x) U[t] = keys[i + t];
     __syncthreads();
@@ -307,7 +355,10 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
         uint64_t j = p >> lf_log2, o = p & (lf - 1);
         uint64_t cj = leaf_start(j + 1, N, P) - leaf_start(j, N, P);
         if (o >= cj) slots[base + p] = kEmpty;
-        if (o == 0) cnt[first_leaf + j] = (uint16_t)cj;
+        if (o == 0) {
+            cnt[first_leaf + j] = (uint16_t)cj;
+            if (dead) dead[first_leaf + j] = 0;
+        }
     }
     for (uint32_t t = threadIdx.x; t < k; t += blockDim.x) {
         status[i + t] = t == 0 ? (uint8_t)(kDone | kHead) : (uint8_t)kDone;
@@ -320,24 +371,25 @@ __global__ void __launch_bounds__(kSegThreads)
 k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
             uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
             uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
-            uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t lf_log2,
-            uint64_t minh, uint64_t maxh, Ctl *__restrict__ ctl) {
+            uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
+            uint32_t lf_log2, uint64_t minh, uint64_t maxh, Ctl *__restrict__ ctl) {
     extern __shared__ uint64_t dyn[];
     __shared__ uint32_t s_misc[kSegThreads / kWave + 4];
     const uint32_t n = *n_dev;
     if (ctl->err) return;
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) seg_merge_one<DEL>(i, n, h, keys, leaf, status, slots,
-                                                                           cnt, row_ptr, deg, lf_log2, minh,
-                                                                           maxh, dyn, s_misc);
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
+        seg_merge_one<DEL>(i, n, h, keys, leaf, status, slots, cnt, row_ptr, deg, dead, lf_log2, minh, maxh, dyn,
+                           s_misc);
 }
 
 // ---------------------------------------------------------------------------
 // device tier (large segments, root rebuild, bulk load)
 
-__global__ void k_leaf_counts_u32(const uint16_t *__restrict__ cnt, uint64_t first_leaf, uint64_t P,
-                                  uint32_t *__restrict__ out) {
+// live entries per leaf
+__global__ void k_leaf_counts_u32(const uint16_t *__restrict__ cnt, const uint32_t *__restrict__ dead,
+                                  uint64_t first_leaf, uint64_t P, uint32_t *__restrict__ out) {
     uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < P) out[j] = cnt[first_leaf + j];
+    if (j < P) out[j] = cnt[first_leaf + j] - (dead ? dead[first_leaf + j] : 0u);
 }
 
 // compacted entries of the segment, in order: leaf j's prefix goes to
@@ -349,6 +401,26 @@ __global__ void k_gather_segment(const uint64_t *__restrict__ slots, const uint1
     if (p >= (P << lf_log2)) return;
     uint64_t j = p >> lf_log2, o = p & ((1u << lf_log2) - 1);
     if (o < cnt[first_leaf + j]) out[leaf_off[j] + o] = slots[(first_leaf << lf_log2) + p];
+}
+
+// the same with marked entries dropped: one wave per leaf, live entries
+// placed by ballot (leaf_off holds live-count offsets)
+__global__ void __launch_bounds__(256)
+k_gather_live(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint64_t first_leaf,
+              uint64_t P, uint32_t lf_log2, const uint32_t *__restrict__ leaf_off, uint64_t *__restrict__ out) {
+    const uint64_t j = (uint64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (j >= P) return;   // wave-uniform
+    const uint32_t lane = __lane_id();
+    const uint32_t cj = cnt[first_leaf + j];
+    const uint64_t base = (first_leaf + j) << lf_log2;
+    uint64_t at = leaf_off[j];
+    for (uint32_t o0 = 0; o0 < cj; o0 += kWave) {
+        const uint32_t o = o0 + lane;
+        const uint64_t v = o < cj ? slots[base + o] : kEmpty;
+        const uint64_t m = __ballot(is_live(v));
+        if (is_live(v)) out[at + __popcll(m & lanemask_lt())] = v;
+        at += (uint64_t)__popcll(m);
+    }
 }
 
 // Merge(s, U_s) by rank: every element finds its output rank with one binary
@@ -386,7 +458,7 @@ __global__ void k_merge_rank_u(const uint64_t *__restrict__ A, uint64_t na,
 
 // even re-dispatch of M[0..N) over leaves first_leaf .. first_leaf+P-1
 __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t *__restrict__ slots,
-                           uint16_t *__restrict__ cnt, uint32_t *__restrict__ row_ptr,
+                           uint16_t *__restrict__ cnt, uint32_t *__restrict__ dead, uint32_t *__restrict__ row_ptr,
                            uint64_t first_leaf, uint64_t P, uint32_t lf_log2) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (P << lf_log2)) return;
@@ -396,8 +468,39 @@ __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t 
     uint64_t pos = (first_leaf << lf_log2) + p;
     uint64_t v = o < cj ? M[st + o] : kEmpty;
     slots[pos] = v;
-    if (o == 0) cnt[first_leaf + j] = (uint16_t)cj;
+    if (o == 0) {
+        cnt[first_leaf + j] = (uint16_t)cj;
+        if (dead) dead[first_leaf + j] = 0;
+    }
     if (o < cj && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(pos + 1);
+}
+
+// Lazy deletion: mark each (unique) key of the batch in its leaf.  A key is
+// deleted when its leaf holds it live; the mark keeps the entry's place and
+// the leaf's dead count grows by one.  Absent and already marked keys are
+// no-ops.  Keys are distinct, so no two threads touch one slot.
+__global__ void k_leaf_mark(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+                            uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+                            uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
+                            uint32_t *__restrict__ dead, uint32_t *__restrict__ deg, uint32_t lf_log2,
+                            const Ctl *__restrict__ ctl) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_max || i >= *n_dev || ctl->err) return;
+    const uint64_t k = keys[i];
+    const uint32_t j = leaf[i];
+    const uint64_t base = (uint64_t)j << lf_log2;
+    uint32_t lo = 0, hi = cnt[j];   // occupied prefix: first masked key >= k
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if ((slots[base + mid] & ~kTomb) < k) lo = mid + 1; else hi = mid;
+    }
+    const bool hit = lo < cnt[j] && slots[base + lo] == k;   // a marked copy differs in bit 63
+    if (hit) {
+        slots[base + lo] = k | kTomb;
+        atomicAdd(&dead[j], 1u);
+        atomicAdd(&deg[key_src(k)], 0xFFFFFFFFu);
+    }
+    status[i] = hit ? kDone : kNoop;
 }
 
 __global__ void k_mark_done(bool del, const uint64_t *__restrict__ keys, uint8_t *__restrict__ status,
@@ -460,31 +563,31 @@ void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, 
 template <int G, int SPL>
 static void leaf_merge_t(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
                          const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
-                         uint32_t *row_ptr, uint32_t *deg, uint32_t min0, uint32_t max0, Ctl *ctl,
-                         hipStream_t s) {
+                         uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t min0, uint32_t max0,
+                         Ctl *ctl, hipStream_t s) {
     constexpr int GPB = 256 / G;
     dim3 grid((uint32_t)div_up(n_max, GPB));
     if (del)
         hipLaunchKernelGGL((k_leaf_merge<G, SPL, true>), grid, dim3(256), 0, s, keys, leaf, status,
-                           n_dev, n_max, slots, cnt, row_ptr, deg, min0, max0, ctl);
+                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl);
     else
         hipLaunchKernelGGL((k_leaf_merge<G, SPL, false>), grid, dim3(256), 0, s, keys, leaf, status,
-                           n_dev, n_max, slots, cnt, row_ptr, deg, min0, max0, ctl);
+                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl);
 }
 
 void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
                        const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
-                       uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t min0, uint64_t max0,
-                       Ctl *ctl, hipStream_t s) {
+                       uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf, uint64_t min0,
+                       uint64_t max0, Ctl *ctl, hipStream_t s) {
     if (!n_max) return;
     uint32_t mn = (uint32_t)min0, mx = (uint32_t)max0;
     switch (lf) {
-        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
-        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
-        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
-        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
-        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
-        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, mn, mx, ctl, s); break;
+        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
+        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
+        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
+        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
+        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
+        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
     }
 }
 
@@ -515,30 +618,35 @@ size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h) {
 
 void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
                       uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
-                      uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t lf, uint64_t minh,
-                      uint64_t maxh, Ctl *ctl, hipStream_t s) {
+                      uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf,
+                      uint64_t minh, uint64_t maxh, Ctl *ctl, hipStream_t s) {
     if (!n_max) return;
     size_t lds = seg_merge_lds_bytes(lf, h);
     const uint32_t grid = (uint32_t)(n_max < 512 ? n_max : 512);   // grid-stride over segments
     if (del)
         hipLaunchKernelGGL(k_seg_merge<true>, dim3(grid), dim3(kSegThreads), lds, s, h,
-                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,
+                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, dead, log2_u32(lf), minh,
                            maxh, ctl);
     else
         hipLaunchKernelGGL(k_seg_merge<false>, dim3(grid), dim3(kSegThreads), lds, s, h,
-                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, log2_u32(lf), minh,
+                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, dead, log2_u32(lf), minh,
                            maxh, ctl);
 }
 
-void launch_leaf_counts_u32(const uint16_t *cnt, uint64_t first_leaf, uint64_t P, uint32_t *out,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_leaf_counts_u32, dim3((uint32_t)div_up(P, 256)), dim3(256), 0, s, cnt,
+void launch_leaf_counts_u32(const uint16_t *cnt, const uint32_t *dead, uint64_t first_leaf, uint64_t P,
+                            uint32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_leaf_counts_u32, dim3((uint32_t)div_up(P, 256)), dim3(256), 0, s, cnt, dead,
                        first_leaf, P, out);
 }
 
-void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, uint64_t first_leaf,
-                           uint64_t P, uint32_t lf, const uint32_t *leaf_off, uint64_t *out,
-                           hipStream_t s) {
+void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, const uint32_t *dead,
+                           uint64_t first_leaf, uint64_t P, uint32_t lf, const uint32_t *leaf_off,
+                           uint64_t *out, hipStream_t s) {
+    if (dead) {
+        hipLaunchKernelGGL(k_gather_live, dim3((uint32_t)div_up(P, 256 / kWave)), dim3(256), 0, s, slots,
+                           cnt, first_leaf, P, log2_u32(lf), leaf_off, out);
+        return;
+    }
     uint64_t total = P * lf;
     hipLaunchKernelGGL(k_gather_segment, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, slots,
                        cnt, first_leaf, P, log2_u32(lf), leaf_off, out);
@@ -554,11 +662,19 @@ void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_
                            k, out);
 }
 
-void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *row_ptr,
-                     uint64_t first_leaf, uint64_t P, uint32_t lf, hipStream_t s) {
+void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *dead,
+                     uint32_t *row_ptr, uint64_t first_leaf, uint64_t P, uint32_t lf, hipStream_t s) {
     uint64_t total = P * lf;
     hipLaunchKernelGGL(k_dispatch, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, M, N, slots,
-                       cnt, row_ptr, first_leaf, P, log2_u32(lf));
+                       cnt, dead, row_ptr, first_leaf, P, log2_u32(lf));
+}
+
+void launch_leaf_mark(const uint64_t *keys, const uint32_t *leaf, uint8_t *status, const uint32_t *n_dev,
+                      uint64_t n_max, uint64_t *slots, const uint16_t *cnt, uint32_t *dead, uint32_t *deg,
+                      uint32_t lf, const Ctl *ctl, hipStream_t s) {
+    if (!n_max) return;
+    hipLaunchKernelGGL(k_leaf_mark, dim3((uint32_t)div_up(n_max, 256)), dim3(256), 0, s, keys, leaf, status, n_dev,
+                       n_max, slots, cnt, dead, deg, log2_u32(lf), ctl);
 }
 
 void launch_mark_done(bool del, const uint64_t *keys, uint8_t *status, uint64_t first, uint64_t count,

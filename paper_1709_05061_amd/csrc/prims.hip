@@ -481,7 +481,7 @@ __global__ void k_flag_edges(const uint64_t *__restrict__ slots, uint64_t cap,
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
     uint64_t k = slots[i];
-    flags[i] = (k != kEmpty && !is_guard(k)) ? 1u : 0u;
+    flags[i] = is_edge_entry(k) ? 1u : 0u;   // live, not a guard
 }
 
 __global__ void k_scatter_edges(const uint64_t *__restrict__ slots, uint64_t cap,
@@ -489,7 +489,7 @@ __global__ void k_scatter_edges(const uint64_t *__restrict__ slots, uint64_t cap
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
     uint64_t k = slots[i];
-    if (k != kEmpty && !is_guard(k)) out[pos[i]] = k;
+    if (is_edge_entry(k)) out[pos[i]] = k;
 }
 
 }  // namespace

@@ -85,7 +85,7 @@ __device__ __forceinline__ void for_each_edge(const uint64_t *__restrict__ slots
     }
 }
 
-__device__ __forceinline__ bool is_edge(uint64_t k) { return k != kEmpty && !is_guard(k); }
+__device__ __forceinline__ bool is_edge(uint64_t k) { return is_edge_entry(k); }   // live, not a guard
 
 // Place of a lane's record in its bin (bins < 64): the lanes holding the same
 // bin find each other with six ballots; the lowest of them reserves the

@@ -22,6 +22,7 @@ GPMA_OK, GPMA_EINVAL, GPMA_ENOMEM, GPMA_EDEVICE = 0, -1, -2, -3
 GPMA_FLAG_MIRROR = 1
 GPMA_FLAG_LEARNED_LOCATOR = 2
 GPMA_FLAG_FUSED_DIRECT = 4
+GPMA_FLAG_LAZY_DELETE = 8
 EMPTY = 0xFFFFFFFFFFFFFFFF
 GUARD_DST = 0xFFFFFFFF
 
@@ -314,14 +315,15 @@ class GPMA(_HandleView):
     kernels directly instead of replaying captured graphs; sort_tile picks the
     batch sort's keys per workgroup tile (512, 1024 or 2048; 0 = 1024);
     fused_levels is how many tree levels above the leaves a fused batch runs
-    on the device before the host takes over (0..3)."""
+    on the device before the host takes over (0..3); lazy_delete makes
+    deletes mark their entries in place (GPMA_FLAG_LAZY_DELETE)."""
 
     def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
                  tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, mirror: bool = False,
                  learned: bool = False, stream=None, fused_direct: bool = False, sort_tile: int = 0,
-                 fused_levels: int = 1):
+                 fused_levels: int = 1, lazy_delete: bool = False):
         flags = ((GPMA_FLAG_MIRROR if mirror else 0) | (GPMA_FLAG_LEARNED_LOCATOR if learned else 0)
-                 | (GPMA_FLAG_FUSED_DIRECT if fused_direct else 0))
+                 | (GPMA_FLAG_FUSED_DIRECT if fused_direct else 0) | (GPMA_FLAG_LAZY_DELETE if lazy_delete else 0))
         p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags, sort_tile, fused_levels)
         super().__init__(gpma_create(num_vertices, init_keys, p, stream), num_vertices)
 
