@@ -164,8 +164,10 @@ def uneven_section(args):
 def workloads_section(args):
     """The paper's other stream shapes at R-MAT scale 22, b = 2^16: explicit
     random deletions (each slide deletes random window edges instead of the
-    oldest) and a sorted arrival stream (every insert batch in one narrow key
-    range).  Plain and fused update throughput at identical output."""
+    oldest), a sorted arrival stream (every insert batch in one narrow key
+    range), and window expiry with lazy deletion (deletes mark their entries
+    in place) beside the same slides with merged deletions.  Plain and fused
+    update throughput at identical output."""
     import torch
 
     import synth
@@ -175,16 +177,19 @@ def workloads_section(args):
     out = {"workload": "R-MAT scale 22 edge factor 16, window %d edges; %d slides of %d deletes + %d inserts"
                        % (st.window, slides, b, b)}
     arrivals = st.order[st.window:]
+    expiry = [st.slide(t, b) for t in range(slides)]
     cases = {
-        "explicit_random_deletions": synth.explicit_deletion_slides(st.initial(), arrivals, b, slides,
-                                                                    args.seed + 41),
-        "sorted_arrivals": [synth.sorted_stream(st).slide(t, b) for t in range(slides)],
+        "explicit_random_deletions": (synth.explicit_deletion_slides(st.initial(), arrivals, b, slides,
+                                                                     args.seed + 41), False),
+        "sorted_arrivals": ([synth.sorted_stream(st).slide(t, b) for t in range(slides)], False),
+        "window_expiry_merged_deletes": (expiry, False),
+        "window_expiry_lazy_deletes": (expiry, True),
     }
-    for name, sl in cases.items():
+    for name, (sl, lazy) in cases.items():
         res = {}
         handles = {}
         for mode in ("plain", "fused"):
-            g = GPMA(st.V, st.initial(), mirror=True, learned=(mode == "fused"))
+            g = GPMA(st.V, st.initial(), mirror=True, learned=(mode == "fused"), lazy_delete=lazy)
             d0, i0 = sl[0]
             if mode == "fused":
                 g.apply_batches([1, 0], [d0, i0])
@@ -204,6 +209,9 @@ def workloads_section(args):
             handles[mode] = g
         res["fused_speedup"] = res["fused_updates_per_s"] / res["plain_updates_per_s"]
         res["identical_output"] = bool(torch.equal(handles["plain"].slots(), handles["fused"].slots()))
+        if lazy:
+            s = handles["fused"].slots()
+            res["marked_entries"] = int(((s < 0) & (s != -1)).sum().item())
         for g in handles.values():
             g.close()
         out[name] = res
@@ -280,7 +288,7 @@ def main():
     ap.add_argument("--fused-levels", type=int, default=0,
                     help="tree levels above the leaves each fused batch runs on the device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slides", type=int, default=16)
+    ap.add_argument("--cpu-slides", type=int, default=64)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 launches), the known-size reference "

@@ -44,6 +44,8 @@ constexpr uint32_t kSplitBits = 6;                       // fine bins per coarse
 constexpr uint32_t kCoarseBits = kBinBits + kSplitBits;  // 2^20 vertices per coarse bin
 constexpr uint64_t kCoarseMask = (1ull << kCoarseBits) - 1;
 constexpr uint32_t kCountThreads = 256;
+constexpr uint32_t kBinThreads = 1024;          // bin pass, more than 64 bins (measured best at scale 24)
+constexpr uint64_t kRanges = 4096;              // slot ranges (workgroups) per pass, at most
 constexpr uint32_t kAccThreads = 1024;
 constexpr uint32_t kMaxBins = 4096;            // V <= 2^26
 constexpr uint64_t kPieceRecords = 1ull << 18;  // records per accumulation workgroup
@@ -150,8 +152,8 @@ k_pb_pieces(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tota
 
 // bins of 2^bits destinations; cur starts at offs[b*W + w].  Up to 64 bins
 // the places are reserved per wave (ballots), beyond that per lane.
-template <bool MANY>
-__global__ void __launch_bounds__(kCountThreads)
+template <bool MANY, int NT>
+__global__ void __launch_bounds__(NT)
 k_pb_bin(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
          uint32_t nb, uint32_t W, uint32_t bits, const uint32_t *__restrict__ offs,
          const double *__restrict__ contrib, uint64_t *__restrict__ rec) {
@@ -294,7 +296,7 @@ PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges)
     // bins of 64 first (same result; faster where scattered stores are dear)
     const char *lv = getenv("GPMA_PB_LEVELS");
     L.nc = (lv && atoi(lv) == 2 && L.nb > (1u << kSplitBits)) ? (uint32_t)div_up(V, 1ull << kCoarseBits) : 0;
-    uint64_t spw = cap / 1024;
+    uint64_t spw = cap / kRanges;
     const uint64_t lf = 1ull << lf_log2;
     if (spw < lf) spw = lf;
     if (spw > kMaxRangeSlots) spw = kMaxRangeSlots;
@@ -325,17 +327,17 @@ void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s) {
     if (L.nc) {
-        hipLaunchKernelGGL(k_pb_bin<false>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nc,
-                           L.W, kCoarseBits, coffs, contrib, rec);
+        hipLaunchKernelGGL((k_pb_bin<false, kCountThreads>), dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt,
+                           lf_log2, L.spw, L.nc, L.W, kCoarseBits, coffs, contrib, rec);
         hipLaunchKernelGGL(k_pb_split, dim3((uint32_t)L.coarse_words), dim3(kCountThreads), 0, s, rec, coffs, total,
                            offs, L.nb, L.nc, L.W, rec2);
         rec = rec2;
     } else if (L.nb <= (1u << kSplitBits)) {
-        hipLaunchKernelGGL(k_pb_bin<false>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb,
-                           L.W, kBinBits, offs, contrib, rec);
+        hipLaunchKernelGGL((k_pb_bin<false, kCountThreads>), dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt,
+                           lf_log2, L.spw, L.nb, L.W, kBinBits, offs, contrib, rec);
     } else {
-        hipLaunchKernelGGL(k_pb_bin<true>, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb,
-                           L.W, kBinBits, offs, contrib, rec);
+        hipLaunchKernelGGL((k_pb_bin<true, kBinThreads>), dim3(L.W), dim3(kBinThreads), 0, s, slots, cnt, lf_log2,
+                           L.spw, L.nb, L.W, kBinBits, offs, contrib, rec);
     }
     hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double), s, rec,
                        pieces, npieces, V, y);
