@@ -237,6 +237,22 @@ int gpma_locator_info(const gpma_t *h, uint32_t *eps, uint64_t *lookups, uint64_
  * must not be updated or destroyed directly. */
 gpma_t *gpma_get_mirror(gpma_t *h);
 
+/* Comparator: the lock-based GPMA insertion of Section 4.1 (paragraph
+ * "Concurrent Insertions in GPMA", Algorithm "GPMA Concurrent Insertion"),
+ * which Section 6 measures against GPMA+.  Same set semantics and the same
+ * density bounds as gpma_insert_batch, but each insertion climbs the tree on
+ * its own: per round, at each height in turn, it tries once to lock its
+ * segment (a loser retries next round), and a winner that fits merges its one
+ * key and re-dispatches the segment; a root that cannot take an insertion is
+ * doubled between rounds.  The resulting slot layout depends on which
+ * insertions win their locks, so only the edge set (and the PMA invariants)
+ * match gpma_insert_batch.  Not for handles with a mirror (GPMA_EINVAL).
+ * Allocates, on first use, a scratch array as large as the slot array and
+ * 8 bytes of lock words per leaf.  *rounds_out (if not NULL) receives the
+ * number of rounds.  Synchronises with the host once per round. */
+int gpma_lock_insert_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b, hipStream_t stream,
+                           gpma_stats *stats, uint32_t *rounds_out);
+
 /* Introspection.  Counts are those after the last completed call. */
 uint64_t gpma_num_edges(const gpma_t *h);     /* guards excluded */
 uint64_t gpma_capacity(const gpma_t *h);      /* slots */

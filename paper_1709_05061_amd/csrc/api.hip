@@ -145,6 +145,12 @@ struct gpma {
     uint64_t loc_lookups = 0, loc_misses = 0, loc_fits = 0;
     uint64_t acc_lookups = 0, acc_misses = 0;   // fused batches since the last check
 
+    // lock-based GPMA comparator (allocated on first use, sized to the array)
+    uint64_t *lk_scratch = nullptr;   // cap slots
+    uint32_t *lk_locks = nullptr;     // 2L epoch words, node (h, s) at (L >> h) + s
+    uint64_t lk_cap = 0;
+    uint32_t lk_epoch = 0;
+
     Device dev;
     int prof_on = 0;
     std::vector<Prof> prof_pending;
@@ -770,6 +776,7 @@ void free_all(gpma *g) {
     if (g->ev_join) hipEventDestroy(g->ev_join);
     g->ev_fork = g->ev_join = nullptr;
     dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg); dev_free(g->dead);
+    dev_free(g->lk_scratch); dev_free(g->lk_locks);
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
     dev_free(g->pb_offs); dev_free(g->pb_tmp); dev_free(g->pb_small); dev_free(g->pb_pieces); dev_free(g->pb_rec);
@@ -1424,6 +1431,103 @@ int gpma_delete_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s
 }
 
 gpma_t *gpma_get_mirror(gpma_t *g) { return g ? g->mir : nullptr; }
+
+// Lock-based GPMA insertion (the comparator of Section 6; kernels and the
+// algorithm's description in gpma_lock.hip): sort, unique, probe, then rounds
+// of locate + one launch per height until every insertion has merged.
+static int lock_state(gpma *g, hipStream_t s) {
+    if (g->lk_cap == g->cap) return GPMA_OK;
+    hipStreamSynchronize(s);
+    dev_free(g->lk_scratch);
+    dev_free(g->lk_locks);
+    g->lk_cap = 0;
+    if (dev_alloc(&g->lk_scratch, g->cap) || dev_alloc(&g->lk_locks, 2 * g->L)) {
+        dev_free(g->lk_scratch);
+        dev_free(g->lk_locks);
+        return GPMA_ENOMEM;
+    }
+    hipMemsetAsync(g->lk_locks, 0, 2 * g->L * sizeof(uint32_t), s);
+    g->lk_epoch = 0;
+    g->lk_cap = g->cap;
+    return GPMA_OK;
+}
+
+int gpma_lock_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st,
+                           uint32_t *rounds_out) {
+    if (rounds_out) *rounds_out = 0;
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->requested = b;
+        st->top_level = -1;
+    }
+    if (!g || g->readonly || g->mir) return GPMA_EINVAL;
+    if (b == 0) return GPMA_OK;
+    if (!keys || b >= (1ull << 31)) return GPMA_EINVAL;
+    int e = ensure_batch(g, b);
+    if (!e) e = lock_state(g, s);
+    if (e) return e;
+    hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
+    const uint32_t sb = bit_width(g->V - 1);
+    const uint64_t *sorted =
+        radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s, nullptr, g->ctl, g->sort_chunks);
+    uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
+    unique_sorted(sorted, b, ukeys, &g->ctl->n_in, g->flags, g->tmp, s);
+    launch_locate(ukeys, &g->ctl->n_in, b, g->slots, g->L, g->lf, g->ctl, g->leafA, g->stA, s);
+    launch_lock_probe(ukeys, g->leafA, g->stA, &g->ctl->n_in, b, g->slots, g->cnt, g->lf_log2, g->ctl, s);
+    LevelArrays cur{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
+    LevelArrays nxt{g->kD, g->leafA, g->stA, &g->ctl->lvl[1]};
+    compact_pending(ukeys, g->leafA, g->stA, &g->ctl->n_in, b, cur.k, cur.l, cur.st, cur.n, g->flags, g->tmp, false,
+                    0, g->ctl, s);
+    read_ctl(g, s);
+    if (g->ctl_h->err) return GPMA_EINVAL;
+    uint64_t rem = g->ctl_h->lvl[0];
+    uint32_t rounds = 0;
+    bool resized = false;
+    while (rem > 0) {
+        // every round merges at least one insertion or doubles the root
+        if (rounds > rem + b + 64) return GPMA_EDEVICE;
+        e = lock_state(g, s);
+        if (e) return e;
+        const uint32_t epoch = ++g->lk_epoch;
+        launch_locate(cur.k, cur.n, rem, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
+        for (uint32_t h = 0; h <= g->H; h++) {
+            uint64_t lo, hi;
+            bounds(g, g->H, h, &lo, &hi);
+            launch_lock_try(h, g->H, cur.k, cur.l, cur.st, rem, g->slots, g->cnt, g->dead, g->row_ptr, g->deg,
+                            g->lk_scratch, g->lk_locks, epoch, g->L, g->lf_log2, hi, g->ctl, s);
+        }
+        compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, false, 0,
+                        g->ctl, s);
+        read_ctl(g, s);
+        rounds++;
+        rem = (nxt.n == &g->ctl->lvl[0]) ? g->ctl_h->lvl[0] : g->ctl_h->lvl[1];
+        std::swap(cur, nxt);
+        if (g->ctl_h->root_full) {
+            // "double the space of the root segment": re-dispatch everything over 2*cap
+            const uint64_t n_now = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+            if (2 * g->cap > kMaxCap) {
+                g->n = n_now;
+                return GPMA_ENOMEM;
+            }
+            e = rebuild_root(g, false, nullptr, nullptr, 0, n_now, 2 * g->cap, s);
+            if (e) {
+                g->n = n_now;
+                return e;
+            }
+            hipMemsetAsync(&g->ctl->root_full, 0, sizeof(uint32_t), s);
+            resized = true;
+        }
+    }
+    read_ctl(g, s);
+    g->n = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+    if (st) {
+        st->applied = g->ctl_h->applied;
+        st->noops = b - st->applied;
+        st->resized = resized ? 1 : 0;
+    }
+    if (rounds_out) *rounds_out = rounds;
+    return GPMA_OK;
+}
 
 int gpma_locate(gpma_t *g, const uint64_t *keys, uint64_t n, uint32_t *leaf_out, hipStream_t s) {
     if (!g || g->readonly || (n && (!keys || !leaf_out)) || n >= (1ull << 31)) return GPMA_EINVAL;

@@ -28,7 +28,7 @@ struct Ctl {
     int64_t dn;          // change of the stored entry count so far
     uint64_t rewritten;  // sum of capacities of merged segments
     uint32_t misses;     // learned-locator lookups that fell back to full search
-    uint32_t pad;
+    uint32_t root_full;  // lock-based comparator: insertions that found even the root full
 };
 
 __device__ __forceinline__ bool is_guard(uint64_t k) {
@@ -203,6 +203,14 @@ void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *c
                      hipStream_t s);
 void launch_leaf_counts_u32(const uint16_t *cnt, const uint32_t *dead, uint64_t first_leaf, uint64_t P,
                             uint32_t *out, hipStream_t s);
+// lock-based GPMA comparator (gpma_lock.hip)
+void launch_lock_probe(const uint64_t *keys, const uint32_t *leaf, uint8_t *status, const uint32_t *n_dev,
+                       uint64_t n_max, const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2,
+                       const gpma_dev::Ctl *ctl, hipStream_t s);
+void launch_lock_try(uint32_t h, uint32_t H, const uint64_t *keys, uint32_t *leaf, uint8_t *status, uint64_t n,
+                     uint64_t *slots, uint16_t *cnt, uint32_t *dead, uint32_t *row_ptr, uint32_t *deg,
+                     uint64_t *scratch, uint32_t *locks, uint32_t epoch, uint64_t L, uint32_t lf_log2, uint64_t maxh,
+                     gpma_dev::Ctl *ctl, hipStream_t s);
 // lazy deletion: mark the located unique keys in place (status kDone/kNoop)
 void launch_leaf_mark(const uint64_t *keys, const uint32_t *leaf, uint8_t *status, const uint32_t *n_dev,
                       uint64_t n_max, uint64_t *slots, const uint16_t *cnt, uint32_t *dead, uint32_t *deg,

@@ -83,6 +83,7 @@ def load_library() -> C.CDLL:
         "gpma_export_degrees": (C.c_int, [vp, vp, u64, vp]),
         "gpma_sync": (C.c_int, [vp]),
         "gpma_get_mirror": (vp, [vp]),
+        "gpma_lock_insert_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats), C.POINTER(u32)]),
         "gpma_snapshot": (C.c_int, [vp, C.POINTER(vp), vp]),
         "gpma_snapshot_refresh": (C.c_int, [vp, vp, vp]),
         "gpma_device_bytes": (u64, [vp]),
@@ -120,7 +121,7 @@ def exported_symbols() -> List[str]:
             "gpma_locator_refit", "gpma_locator_info",
             "gpma_profile_enable",
             "gpma_profile_reset", "gpma_profile_read", "gpma_csr_create", "gpma_csr_destroy",
-            "gpma_csr_update", "gpma_csr_num_edges", "gpma_csr_export"]
+            "gpma_csr_update", "gpma_csr_num_edges", "gpma_csr_export", "gpma_lock_insert_batch"]
 
 
 def strerror(code: int) -> str:
@@ -180,6 +181,17 @@ def gpma_insert_batch(h, keys: torch.Tensor, stream=None, stats: bool = False):
                                           C.byref(st) if st is not None else None)
     _check(rc, "gpma_insert_batch")
     return st
+
+
+def gpma_lock_insert_batch(h, keys: torch.Tensor, stream=None):
+    """The lock-based GPMA insertion (comparator); returns (stats, rounds)."""
+    k = _dev_u64(keys)
+    st = gpma_stats()
+    rounds = C.c_uint32()
+    rc = load_library().gpma_lock_insert_batch(h, C.c_void_p(k.data_ptr()), k.numel(), _stream(stream),
+                                               C.byref(st), C.byref(rounds))
+    _check(rc, "gpma_lock_insert_batch")
+    return st, rounds.value
 
 
 def gpma_delete_batch(h, keys: torch.Tensor, stream=None, stats: bool = False):
@@ -365,6 +377,12 @@ class GPMA(_HandleView):
     def delete(self, keys: torch.Tensor, stream=None, stats=False):
         st = gpma_delete_batch(self.h, keys, stream, stats)
         return BatchStats.of(st) if stats else None
+
+    def lock_insert(self, keys: torch.Tensor, stream=None):
+        """Insert with the lock-based GPMA algorithm (the comparator);
+        returns (BatchStats, rounds)."""
+        st, rounds = gpma_lock_insert_batch(self.h, keys, stream)
+        return BatchStats.of(st), rounds
 
     def apply_batches(self, ops, batches, stream=None) -> BatchStats:
         """Fused batching of a sequence of insert (0) / delete (1) batches."""

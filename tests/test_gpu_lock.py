@@ -1,0 +1,135 @@
+"""The lock-based GPMA insertion (gpma_lock_insert_batch, the comparator of
+Section 6) on the GPU.  Which insertions win their locks decides the slot
+layout, so parity is on what is unique: the edge set (against plain Python
+sets and the oracle's GPMA+ run on the same batches), the PMA invariants of
+the slot array, and the leaf counts, row offsets and degrees derived from
+the slots; the analytics on the result equal the oracle's."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(keys) -> torch.Tensor:
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(keys, dtype=np.uint64)).view(np.int64)).cuda()
+
+
+def npu64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def check(g, live: set, V: int):
+    slots = npu64(g.slots())
+    lf = g.leaf_size
+    O.check_invariants(slots, lf, V)
+    edges = O.edge_keys(slots)
+    assert np.array_equal(edges, np.array(sorted(live), dtype=np.uint64))
+    assert np.array_equal(g.leaf_counts().cpu().numpy().astype(np.int64), O.leaf_counts(slots, lf))
+    assert np.array_equal(g.row_offsets().cpu().numpy().astype(np.int64), O.row_offsets(slots, V))
+    assert np.array_equal(g.degrees().cpu().numpy().astype(np.int64), O.out_degrees(edges, V))
+    assert g.num_edges == len(live)
+    assert np.array_equal(npu64(g.keys()), edges)
+    return edges
+
+
+@pytest.mark.parametrize("lf", [16, 32, 128])
+def test_lock_insert_sets_invariants_and_root_doubling(lf):
+    """Random batches with repeats and present keys, one large enough to
+    double the root, against Python sets and the GPMA+ oracle's edge set."""
+    from paper_1709_05061_amd import GPMA
+    V = 2000
+    init = np.unique(npu64(synth.random_batch(V, 12000, 3)))
+    g = GPMA(V, dev(init), leaf_size=lf)
+    ref = O.OraclePMA(V, init, lf)
+    live = set(int(x) for x in init)
+    cap0 = g.capacity
+    for t, size in enumerate([1, 40, 700, 5000, 30000, 3]):
+        keys = npu64(synth.random_batch(V, size, 50 + t))
+        keys = np.concatenate([keys, keys[: size // 5], init[:7]])
+        st, rounds = g.lock_insert(dev(keys))
+        ref.insert(keys)
+        new = set(int(x) for x in keys) - live
+        live |= new
+        say("lock insert", lf, t, size, "applied", st.applied, "rounds", rounds)
+        assert st.applied == len(new) == ref.last_applied()
+        assert rounds >= 1
+        edges = check(g, live, V)
+        assert np.array_equal(edges, O.edge_keys(ref.slots()))
+    assert g.capacity > cap0
+    g.close()
+
+
+def test_lock_insert_contention_needs_rounds():
+    """Every insertion of a batch aims at the same row: they contend for the
+    same segments, so one wins per segment and round."""
+    from paper_1709_05061_amd import GPMA
+    V = 512
+    init = np.unique(npu64(synth.random_batch(V, 3000, 4)))
+    g = GPMA(V, dev(init), leaf_size=16)
+    live = set(int(x) for x in init)
+    keys = np.array([(7 << 32) | v for v in range(0, V, 2)], np.uint64)
+    st, rounds = g.lock_insert(dev(keys))
+    live |= set(int(x) for x in keys)
+    assert rounds > 8, rounds
+    check(g, live, V)
+    g.close()
+
+
+def test_lock_insert_over_lazy_deletes():
+    """With lazy deletion (the experiments' setup for both GPMA and GPMA+):
+    marked entries are free space for the lock-based merges, which drop them;
+    re-inserted keys come back live."""
+    from paper_1709_05061_amd import GPMA
+    V = 1500
+    st_ = synth.er_stream(V, 20000, 2000, 6, seed=8)
+    init = npu64(st_.initial())
+    g = GPMA(V, dev(init), leaf_size=32, lazy_delete=True)
+    live = set(int(x) for x in init)
+    for t in range(6):
+        d, i = st_.slide(t, 2000)
+        d, i = npu64(d), npu64(i)
+        g.delete(dev(d))
+        live -= set(int(x) for x in d)
+        back = d[: 300]   # some deleted keys come straight back
+        st, rounds = g.lock_insert(dev(np.concatenate([i, back])))
+        live |= set(int(x) for x in i) | set(int(x) for x in back)
+        say("lazy slide", t, "rounds", rounds)
+        edges = check(g, live, V)
+    for src in (0, V // 3):
+        assert np.array_equal(g.bfs(src).cpu().numpy(), O.bfs(V, edges, src))
+    assert np.array_equal(g.cc().cpu().numpy().astype(np.uint32), O.cc(V, edges))
+    x = g.pagerank(iters=10).cpu().numpy()
+    want = O.pagerank(V, edges, iters=10)
+    assert np.max(np.abs(x - want) / want) < 1e-6
+    g.close()
+
+
+def test_lock_insert_rejects_mirror_and_bad_keys():
+    from paper_1709_05061_amd import GPMA, GpmaError
+    V = 64
+    init = np.unique(npu64(synth.random_batch(V, 200, 1)))
+    g = GPMA(V, dev(init), leaf_size=16, mirror=True)
+    with pytest.raises(GpmaError) as ei:
+        g.lock_insert(dev(init[:3]))
+    assert ei.value.code == -1
+    g.close()
+    g = GPMA(V, dev(init), leaf_size=16)
+    before = npu64(g.slots())
+    with pytest.raises(GpmaError) as ei:
+        g.lock_insert(dev([(1 << 32) | 2, (V << 32) | 1]))
+    assert ei.value.code == -1
+    assert np.array_equal(npu64(g.slots()), before)
+    st, rounds = g.lock_insert(dev(np.zeros(0, np.uint64)))
+    assert st.applied == 0 and rounds == 0
+    g.close()
