@@ -6,8 +6,14 @@ initial window (~2.4e8 edges, a 2^29-slot = 4 GiB PMA).  One step slides the
 window once: delete the 2^16 oldest edges, insert 2^16 fresh ones, then run
 the analytics of the stream (PageRank 10 iterations warm-started from the
 previous step, BFS from a random vertex, connected components).  By default
-the handle keeps the dst-major mirror (both arrays take every batch, and
-PageRank pulls over the mirror); --no-mirror pushes with fp64 atomics.
+the handle keeps the dst-major mirror (both arrays take every batch; it
+serves bottom-up BFS and the CC sampling; PageRank uses destination bins
+either way).
+
+Beside the headline: the other update path (plain or fused) on the same
+slides, the same configuration with lazy deletion, and two comparators on
+the first slides: a CSR rebuilt per batch and the lock-based GPMA (against
+GPMA+ on the same handle configuration, both with lazy deletion).
 
 value     = edge updates applied per second of update time (delete + insert
             phases of the timed steps, HIP events on the update stream)
@@ -278,6 +284,8 @@ def main():
     ap.add_argument("--no-service", action="store_true")
     ap.add_argument("--no-workloads", action="store_true", help="skip the explicit-deletion / sorted-stream section")
     ap.add_argument("--rebuild-slides", type=int, default=4, help="slides timed on the rebuild-per-batch CSR")
+    ap.add_argument("--lock-slides", type=int, default=4,
+                    help="slides timed for the lock-based GPMA comparator (0: skip)")
     ap.add_argument("--service-s", type=float, default=1.0)
     ap.add_argument("--query-rate", type=float, default=40.0)
     ap.add_argument("--service-budget-gib", type=int, default=16)
@@ -377,6 +385,30 @@ def main():
         other_ups = n_o / (sum(a.elapsed_time(c) for a, c in ms) / 1e3)
         log("%s path: %.3g updates/s" % ("plain" if fused_mode else "fused", other_ups))
 
+    # the headline configuration with lazy deletion (the paper's experimental
+    # setup for GPMA and GPMA+: expired edges are marked, not merged out)
+    lazy_ups = None
+    if not args.no_compare:
+        h = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror, learned=learned,
+                 fused_direct=bool(args.fused_direct), sort_tile=args.sort_tile, fused_levels=args.fused_levels,
+                 lazy_delete=True)
+        for t in range(args.warmup):
+            update(h, t, fused_mode)
+        ms = []
+        n_z = 0
+        for t in range(args.warmup, args.warmup + args.steps):
+            e0 = ev()
+            a, _ = update(h, t, fused_mode)
+            e1 = ev()
+            n_z += a
+            ms.append((e0, e1))
+        torch.cuda.synchronize()
+        lazy_ups = n_z / (sum(a.elapsed_time(c) for a, c in ms) / 1e3)
+        log("same path with lazy deletes: %.3g updates/s" % lazy_ups)
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+
     # comparator: a CSR rebuilt on every batch (the paper's GPU-CSR baseline
     # role), on the first slides
     rebuild = None
@@ -399,6 +431,44 @@ def main():
         del c
         torch.cuda.empty_cache()
         log("CSR rebuilt per batch: %.3g updates/s" % rebuild["updates_per_s"])
+
+    # comparator: the lock-based GPMA (one insertion per worker, per-height
+    # try-locks, retries in rounds) against GPMA+ (plain per-batch calls), both
+    # with lazy deletion as in the paper's experiments, on the first slides
+    lock = None
+    if not args.no_compare and args.lock_slides > 0:
+        lock = {"slides": args.lock_slides}
+        for name in ("gpma_plus", "gpma_lock"):
+            h = GPMA(V, st.initial(), leaf_size=args.leaf_size, lazy_delete=True)
+            rounds = []
+            d, i = st.slide(0, b)
+            h.delete(d)
+            if name == "gpma_lock":
+                h.lock_insert(i)
+            else:
+                h.insert(i)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            n_l = 0
+            for t in range(1, 1 + args.lock_slides):
+                d, i = st.slide(t, b)
+                n_l += h.delete(d, stats=True).applied
+                if name == "gpma_lock":
+                    si, r = h.lock_insert(i)
+                    rounds.append(r)
+                else:
+                    si = h.insert(i, stats=True)
+                n_l += si.applied
+            torch.cuda.synchronize()
+            lock[name + "_updates_per_s"] = n_l / (time.perf_counter() - t0)
+            if rounds:
+                lock["lock_rounds_per_insert_batch"] = rounds
+            log("%s with lazy deletes: %.3g updates/s%s" % (name, lock[name + "_updates_per_s"],
+                                                             (", rounds %s" % rounds) if rounds else ""))
+            h.close()
+            del h
+            torch.cuda.empty_cache()
+        lock["gpma_plus_speedup"] = lock["gpma_plus_updates_per_s"] / lock["gpma_lock_updates_per_s"]
 
     # BFS sources: vertices with out-edges, drawn with the seeded generator
     deg = g.degrees()
@@ -500,6 +570,8 @@ def main():
         "resizes": resized,
         ("plain_updates_per_s" if fused_mode else "fused_updates_per_s"): other_ups,
         "csr_rebuild": rebuild,
+        "lock_gpma": lock,
+        "lazy_delete_updates_per_s": lazy_ups,
         "fused_speedup": (updates_per_s / other_ups if fused_mode else other_ups / updates_per_s)
         if other_ups else None,
         "identical_output": identical,
