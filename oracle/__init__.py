@@ -252,9 +252,14 @@ def check_invariants(slots: np.ndarray, lf: int, V: int = 0, allow_empty_leaves=
 # --------------------------------------------------------------------------
 # analytics (Section 6.1 "Applications"), fp64
 
+def _sorted(edges) -> np.ndarray:
+    e = _keys(edges)
+    return e if e.size < 2 or bool(np.all(e[1:] >= e[:-1])) else np.sort(e)
+
+
 def pagerank(V: int, edges, x0=None, iters: int = 10, damping: float = 0.85) -> np.ndarray:
     lib = _load()
-    e = np.sort(_keys(edges))
+    e = _sorted(edges)
     out = np.zeros(V, np.float64)
     if x0 is not None:
         x = np.ascontiguousarray(np.asarray(x0, dtype=np.float64))
@@ -267,7 +272,7 @@ def pagerank(V: int, edges, x0=None, iters: int = 10, damping: float = 0.85) -> 
 
 def bfs(V: int, edges, source: int) -> np.ndarray:
     lib = _load()
-    e = np.sort(_keys(edges))
+    e = _sorted(edges)
     out = np.zeros(V, np.int32)
     lib.orc_bfs(V, _p(e, C.c_uint64), e.size, source, _p(out, C.c_int32))
     return out
@@ -275,7 +280,7 @@ def bfs(V: int, edges, source: int) -> np.ndarray:
 
 def cc(V: int, edges) -> np.ndarray:
     lib = _load()
-    e = np.sort(_keys(edges))
+    e = _sorted(edges)
     out = np.zeros(V, np.uint32)
     lib.orc_cc(V, _p(e, C.c_uint64), e.size, _p(out, C.c_uint32))
     return out

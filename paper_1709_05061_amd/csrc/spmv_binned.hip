@@ -13,7 +13,9 @@
 //          (bin, range) pair its place in the record array;
 //   bin   (per iteration):  stream the slots, write one 8-byte record per
 //          edge: the contribution with its low mantissa bits replaced by the
-//          destination's offset in its bin;
+//          destination's offset in its bin (records of the bins this slot
+//          range feeds only a few are staged in LDS and leave as one run per
+//          bin, see k_pb_bin_quiet);
 //   split (optional, more than 64 fine bins only): the bin pass writes
 //          coarse bins of 64 fine bins (2^20 vertices), so each workgroup has
 //          at most 64 runs open, and this pass splits each coarse run into
@@ -44,7 +46,6 @@ constexpr uint32_t kSplitBits = 6;                       // fine bins per coarse
 constexpr uint32_t kCoarseBits = kBinBits + kSplitBits;  // 2^20 vertices per coarse bin
 constexpr uint64_t kCoarseMask = (1ull << kCoarseBits) - 1;
 constexpr uint32_t kCountThreads = 256;
-constexpr uint32_t kBinThreads = 1024;          // bin pass, more than 64 bins (measured best at scale 24)
 constexpr uint64_t kRanges = 4096;              // slot ranges (workgroups) per pass, at most
 constexpr uint32_t kAccThreads = 1024;
 constexpr uint32_t kMaxBins = 4096;            // V <= 2^26
@@ -150,14 +151,13 @@ k_pb_pieces(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tota
     if (threadIdx.x == 0) *npieces = carry;
 }
 
-// bins of 2^bits destinations; cur starts at offs[b*W + w].  Up to 64 bins
-// the places are reserved per wave (ballots), beyond that per lane.
-template <bool MANY, int NT>
-__global__ void __launch_bounds__(NT)
+// Bin pass for at most 64 bins (or coarse bins) of 2^bits destinations;
+// cur starts at offs[b*W + w]; places are reserved per wave (ballots).
+__global__ void __launch_bounds__(kCountThreads)
 k_pb_bin(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
          uint32_t nb, uint32_t W, uint32_t bits, const uint32_t *__restrict__ offs,
          const double *__restrict__ contrib, uint64_t *__restrict__ rec) {
-    __shared__ uint32_t cur[MANY ? kMaxBins : (1u << kSplitBits)];
+    __shared__ uint32_t cur[1u << kSplitBits];
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offs[(uint64_t)b * W + blockIdx.x];
     __syncthreads();
     const uint64_t mask = (1ull << bits) - 1;
@@ -170,16 +170,88 @@ k_pb_bin(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, u
         for (int j = 0; j < 2 * kUnroll; j++) {
             const bool ok = is_edge(k[j]);
             const uint32_t d = key_dst(k[j]);
-            uint32_t pos;
-            if (MANY) {
-                if (!ok) continue;
-                pos = atomicAdd(&cur[d >> bits], 1u);
-            } else {
-                pos = reserve_in_bin(cur, ok ? d >> bits : 0u, ok);
-            }
+            const uint32_t pos = reserve_in_bin(cur, ok ? d >> bits : 0u, ok);
             if (ok) rec[pos] = (v[j] & ~mask) | (d & mask);   // plain store: L2 merges a run's partial lines
         }
     });
+}
+
+// Bin pass for more than 64 bins.  A bin that receives many records from
+// the workgroup's slot range has its lines filled quickly, so L2 merges its
+// scattered 8-byte stores into whole lines; a quiet bin (fewer than
+// kQuietRecords records from this range) keeps partial lines open for the
+// whole pass, and those are what the scattered stores cost.  Staged bins are
+// taken in bin order until the stage is full.  So the quiet
+// bins' records are staged in LDS, in exact-size slices laid out by a scan of
+// their counts (the count matrix gives every bin's count for this range), and
+// each quiet bin is written out at the end as one contiguous run; busy bins
+// (and quiet bins beyond the LDS budget) are stored directly.  Dynamic LDS:
+// stage records, then cur[nb] (the bin's next place in rec), soff[nb] (its
+// slice in the stage, kDirect for a direct bin), fill[nb].
+constexpr uint32_t kQuietRecords = 128;   // measured best of 32..512 at scale 24
+constexpr uint32_t kDirect = 0xFFFFFFFFu;
+constexpr uint32_t kStageThreads = 1024;
+
+__host__ __device__ inline uint32_t stage_records(uint32_t lds_bytes, uint32_t nb) {
+    const uint32_t meta = 3 * nb * (uint32_t)sizeof(uint32_t) + 1024;
+    return lds_bytes > meta ? (lds_bytes - meta) / (uint32_t)sizeof(uint64_t) : 0u;
+}
+
+__global__ void __launch_bounds__(kStageThreads)
+k_pb_bin_quiet(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
+               uint32_t nb, uint32_t W, const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total,
+               const double *__restrict__ contrib, uint64_t *__restrict__ rec, uint32_t n_stage) {
+    extern __shared__ uint64_t stage[];
+    uint32_t *cur = (uint32_t *)(stage + n_stage);
+    uint32_t *soff = cur + nb;
+    uint32_t *fill = soff + nb;
+    __shared__ uint32_t s_scan[kStageThreads / kWave + 1];
+    const uint64_t last = (uint64_t)nb * W;
+    uint32_t used = 0;   // stage records handed out so far (uniform)
+    for (uint32_t base = 0; base < nb; base += kStageThreads) {
+        const uint32_t b = base + threadIdx.x;
+        uint32_t beg = 0, c = 0;
+        if (b < nb) {
+            const uint64_t e = (uint64_t)b * W + blockIdx.x;
+            beg = offs[e];
+            c = (e + 1 < last ? offs[e + 1] : *total) - beg;
+        }
+        const bool quiet = c > 0 && c < kQuietRecords;
+        uint32_t tot;
+        const uint32_t off = used + block_exclusive_scan(quiet ? c : 0u, &tot, s_scan);
+        if (b < nb) {
+            cur[b] = beg;
+            soff[b] = quiet && off + c <= n_stage ? off : kDirect;
+            fill[b] = 0;
+        }
+        used += tot;
+    }
+    __syncthreads();
+    for_each_edge(slots, cnt, lf_log2, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+        uint64_t v[2 * kUnroll];
+#pragma unroll
+        for (int j = 0; j < 2 * kUnroll; j++)
+            v[j] = is_edge(k[j]) ? (uint64_t)__double_as_longlong(contrib[key_src(k[j])]) : 0;
+#pragma unroll
+        for (int j = 0; j < 2 * kUnroll; j++) {
+            if (!is_edge(k[j])) continue;
+            const uint32_t d = key_dst(k[j]);
+            const uint32_t b = d >> kBinBits;
+            const uint64_t r = (v[j] & ~kBinMask) | (d & kBinMask);
+            const uint32_t so = soff[b];
+            if (so == kDirect) rec[atomicAdd(&cur[b], 1u)] = r;   // plain store: L2 merges a busy run's lines
+            else stage[so + atomicAdd(&fill[b], 1u)] = r;
+        }
+    });
+    __syncthreads();
+    // each staged bin leaves as one run (at most two wave stores)
+    const uint32_t lane = __lane_id();
+    for (uint32_t b = threadIdx.x / kWave; b < nb; b += kStageThreads / kWave) {
+        const uint32_t so = soff[b];
+        if (so == kDirect) continue;   // wave-uniform
+        const uint32_t n = fill[b];
+        for (uint32_t t = lane; t < n; t += kWave) rec[cur[b] + t] = stage[so + t];
+    }
 }
 
 // coarse count matrix from the scanned fine one: range w's records in coarse
@@ -274,6 +346,8 @@ namespace gpma_host {
 
 // The accumulation slice exceeds the default 64 KiB of LDS; the binned form
 // is offered only where the device grants it.
+static int g_stage_lds = 0;   // dynamic LDS the quiet-bin stage may use (set with the attribute)
+
 bool pb_supported(uint32_t V) {
     static int ok = -1;
     if (ok < 0) {
@@ -284,6 +358,12 @@ bool pb_supported(uint32_t V) {
         ok = (size_t)max_lds >= bytes &&
              hipFuncSetAttribute((const void *)k_pb_accum, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
                  hipSuccess;
+        // the bin pass stages in what is left of the workgroup's LDS after its scan words
+        const int stage = max_lds - (int)((kStageThreads / kWave + 1) * sizeof(uint32_t)) - 256;
+        ok = ok && stage > 0 &&
+             hipFuncSetAttribute((const void *)k_pb_bin_quiet, hipFuncAttributeMaxDynamicSharedMemorySize, stage) ==
+                 hipSuccess;
+        if (ok) g_stage_lds = stage;
         if (!ok) (void)hipGetLastError();
     }
     return ok && div_up(V, kBinWidth) <= kMaxBins;
@@ -327,17 +407,19 @@ void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s) {
     if (L.nc) {
-        hipLaunchKernelGGL((k_pb_bin<false, kCountThreads>), dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt,
-                           lf_log2, L.spw, L.nc, L.W, kCoarseBits, coffs, contrib, rec);
+        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nc, L.W,
+                           kCoarseBits, coffs, contrib, rec);
         hipLaunchKernelGGL(k_pb_split, dim3((uint32_t)L.coarse_words), dim3(kCountThreads), 0, s, rec, coffs, total,
                            offs, L.nb, L.nc, L.W, rec2);
         rec = rec2;
     } else if (L.nb <= (1u << kSplitBits)) {
-        hipLaunchKernelGGL((k_pb_bin<false, kCountThreads>), dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt,
-                           lf_log2, L.spw, L.nb, L.W, kBinBits, offs, contrib, rec);
+        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb, L.W,
+                           kBinBits, offs, contrib, rec);
     } else {
-        hipLaunchKernelGGL((k_pb_bin<true, kBinThreads>), dim3(L.W), dim3(kBinThreads), 0, s, slots, cnt, lf_log2,
-                           L.spw, L.nb, L.W, kBinBits, offs, contrib, rec);
+        const uint32_t ns = stage_records((uint32_t)g_stage_lds, L.nb);
+        const size_t lds = (size_t)ns * sizeof(uint64_t) + 3 * (size_t)L.nb * sizeof(uint32_t);
+        hipLaunchKernelGGL(k_pb_bin_quiet, dim3(L.W), dim3(kStageThreads), lds, s, slots, cnt, lf_log2, L.spw, L.nb,
+                           L.W, offs, total, contrib, rec, ns);
     }
     hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double), s, rec,
                        pieces, npieces, V, y);
