@@ -1742,7 +1742,7 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
     if (mode == kSpmvBinned) {
         L = pb_layout(g->V, g->cap, g->lf_log2, g->n);
         if (int e = ensure_pb(g, L)) return e;
-        launch_pb_structure(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
+        launch_pb_structure(g->slots, L, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
                             g->pb_small + 1, g->pb_coffs, s);
     }
     for (uint32_t it = 0; it < iters; it++) {
@@ -1751,7 +1751,7 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
         {
             ProfScope ps(g, GPMA_K_SPMV, s);
             if (mode == kSpmvBinned)
-                launch_pb_spmv(g->slots, g->cnt, g->lf_log2, L, g->pb_offs, g->pb_small, g->pb_pieces,
+                launch_pb_spmv(g->slots, L, g->pb_offs, g->pb_small, g->pb_pieces,
                                g->pb_small + 1, g->pb_coffs, g->pr_contrib, g->pb_rec, g->pb_rec2, g->V, g->pr_y, s);
             else if (mode == kSpmvPull)
                 launch_pr_pull(g->mir->slots, g->mir->cnt, g->mir->cap, g->mir->lf_log2, g->pr_contrib,

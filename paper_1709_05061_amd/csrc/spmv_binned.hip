@@ -57,32 +57,29 @@ __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a +
 __device__ __forceinline__ uint64_t ld_nt(const uint64_t *p) { return __builtin_nontemporal_load(p); }
 
 // The slot range of workgroup w is [w*spw, (w+1)*spw); spw is a power of two
-// no smaller than a leaf, so slot pairs (p, p+1) with p even share a leaf.
-// Each thread takes kUnroll pairs per step and issues all their loads before
-// using any (the per-edge work is a chain of dependent accesses), then
-// fn(k) runs for every stored edge among them (guards and gaps skipped: a
-// skipped slot reads as kEmpty).
+// no smaller than a leaf.  Each thread takes kUnroll slot pairs per step, one
+// 16-byte load each, all issued before any is used (the per-edge work is a
+// chain of dependent accesses), then fn(k) runs over them; gaps (all ones),
+// guards and marked entries are not edges.  The leaf counts are not read:
+// a gap holds the empty key, and a load that waited for its leaf's count
+// would serialise the stream (the occupied prefix rarely spares a line).
 constexpr int kUnroll = 8;
 
 template <typename F>
-__device__ __forceinline__ void for_each_edge(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
-                                              uint32_t lf_log2, uint64_t spw, F fn) {
+__device__ __forceinline__ void for_each_edge(const uint64_t *__restrict__ slots, uint64_t spw, F fn) {
+    using u64x2 = uint64_t __attribute__((ext_vector_type(2)));
     const uint64_t lo = (uint64_t)blockIdx.x * spw;
     const uint64_t hi = lo + spw;
-    const uint64_t lfm = (1ull << lf_log2) - 1;
     const uint64_t step = 2 * (uint64_t)blockDim.x;
     for (uint64_t p0 = lo + 2 * threadIdx.x; p0 < hi; p0 += step * kUnroll) {
         uint64_t k[2 * kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
             const uint64_t p = p0 + u * step;
-            uint32_t c = 0, o = 0;
-            if (p < hi) {
-                c = cnt[p >> lf_log2];
-                o = (uint32_t)(p & lfm);
-            }
-            k[2 * u] = o < c ? ld_nt(slots + p) : kEmpty;
-            k[2 * u + 1] = o + 1 < c ? ld_nt(slots + p + 1) : kEmpty;
+            u64x2 q = {kEmpty, kEmpty};
+            if (p < hi) q = __builtin_nontemporal_load((const u64x2 *)(slots + p));
+            k[2 * u] = q.x;
+            k[2 * u + 1] = q.y;
         }
         fn(k);
     }
@@ -110,12 +107,12 @@ __device__ __forceinline__ uint32_t reserve_in_bin(uint32_t *cur, uint32_t bin, 
 }
 
 __global__ void __launch_bounds__(kCountThreads)
-k_pb_count(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
+k_pb_count(const uint64_t *__restrict__ slots, uint64_t spw,
            uint32_t nb, uint32_t W, uint32_t *__restrict__ counts) {
     __shared__ uint32_t hist[kMaxBins];
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
-    for_each_edge(slots, cnt, lf_log2, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+    for_each_edge(slots, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
             if (is_edge(k[j])) atomicAdd(&hist[key_dst(k[j]) >> kBinBits], 1u);
@@ -154,14 +151,14 @@ k_pb_pieces(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tota
 // Bin pass for at most 64 bins (or coarse bins) of 2^bits destinations;
 // cur starts at offs[b*W + w]; places are reserved per wave (ballots).
 __global__ void __launch_bounds__(kCountThreads)
-k_pb_bin(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
+k_pb_bin(const uint64_t *__restrict__ slots, uint64_t spw,
          uint32_t nb, uint32_t W, uint32_t bits, const uint32_t *__restrict__ offs,
          const double *__restrict__ contrib, uint64_t *__restrict__ rec) {
     __shared__ uint32_t cur[1u << kSplitBits];
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offs[(uint64_t)b * W + blockIdx.x];
     __syncthreads();
     const uint64_t mask = (1ull << bits) - 1;
-    for_each_edge(slots, cnt, lf_log2, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+    for_each_edge(slots, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
         uint64_t v[2 * kUnroll];
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
@@ -198,7 +195,7 @@ __host__ __device__ inline uint32_t stage_records(uint32_t lds_bytes, uint32_t n
 }
 
 __global__ void __launch_bounds__(kStageThreads)
-k_pb_bin_quiet(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt, uint32_t lf_log2, uint64_t spw,
+k_pb_bin_quiet(const uint64_t *__restrict__ slots, uint64_t spw,
                uint32_t nb, uint32_t W, const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total,
                const double *__restrict__ contrib, uint64_t *__restrict__ rec, uint32_t n_stage) {
     extern __shared__ uint64_t stage[];
@@ -227,7 +224,7 @@ k_pb_bin_quiet(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ 
         used += tot;
     }
     __syncthreads();
-    for_each_edge(slots, cnt, lf_log2, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+    for_each_edge(slots, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
         uint64_t v[2 * kUnroll];
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
@@ -389,10 +386,10 @@ PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges)
     return L;
 }
 
-void launch_pb_structure(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
+void launch_pb_structure(const uint64_t *slots, const PbLayout &L,
                          uint32_t *offs, uint32_t *total, uint32_t *scan_tmp, uint4 *pieces, uint32_t *npieces,
                          uint32_t *coffs, hipStream_t s) {
-    hipLaunchKernelGGL(k_pb_count, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb, L.W, offs);
+    hipLaunchKernelGGL(k_pb_count, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nb, L.W, offs);
     scan_u32(offs, offs, L.count_words, total, scan_tmp, s);
     hipLaunchKernelGGL(k_pb_pieces, dim3(1), dim3(1024), 0, s, offs, total, L.nb, L.W, pieces, npieces);
     if (L.nc) {
@@ -402,23 +399,23 @@ void launch_pb_structure(const uint64_t *slots, const uint16_t *cnt, uint32_t lf
     }
 }
 
-void launch_pb_spmv(const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2, const PbLayout &L,
+void launch_pb_spmv(const uint64_t *slots, const PbLayout &L,
                     const uint32_t *offs, const uint32_t *total, const uint4 *pieces, const uint32_t *npieces,
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s) {
     if (L.nc) {
-        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nc, L.W,
+        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nc, L.W,
                            kCoarseBits, coffs, contrib, rec);
         hipLaunchKernelGGL(k_pb_split, dim3((uint32_t)L.coarse_words), dim3(kCountThreads), 0, s, rec, coffs, total,
                            offs, L.nb, L.nc, L.W, rec2);
         rec = rec2;
     } else if (L.nb <= (1u << kSplitBits)) {
-        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, cnt, lf_log2, L.spw, L.nb, L.W,
+        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nb, L.W,
                            kBinBits, offs, contrib, rec);
     } else {
         const uint32_t ns = stage_records((uint32_t)g_stage_lds, L.nb);
         const size_t lds = (size_t)ns * sizeof(uint64_t) + 3 * (size_t)L.nb * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_pb_bin_quiet, dim3(L.W), dim3(kStageThreads), lds, s, slots, cnt, lf_log2, L.spw, L.nb,
+        hipLaunchKernelGGL(k_pb_bin_quiet, dim3(L.W), dim3(kStageThreads), lds, s, slots, L.spw, L.nb,
                            L.W, offs, total, contrib, rec, ns);
     }
     hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double), s, rec,
