@@ -83,6 +83,9 @@ struct gpma {
     uint32_t *pb_offs = nullptr, *pb_tmp = nullptr, *pb_small = nullptr;   // pb_small: total, pieces
     uint4 *pb_pieces = nullptr;
     uint64_t *pb_rec = nullptr, *pb_rec2 = nullptr;
+    uint64_t *pb_keys = nullptr;   // each slot range's edges, packed once per call (cap words)
+    uint32_t *pb_ne = nullptr;     // edges packed per range
+    uint64_t pb_keys_cap = 0, pb_ne_cap = 0;
     uint32_t *pb_coffs = nullptr;
     uint64_t pb_offs_words = 0, pb_tmp_words = 0, pb_pieces_cap = 0, pb_rec_cap = 0, pb_rec2_cap = 0;
     uint64_t pb_coffs_words = 0;
@@ -780,8 +783,9 @@ void free_all(gpma *g) {
     dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
     dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
     dev_free(g->pb_offs); dev_free(g->pb_tmp); dev_free(g->pb_small); dev_free(g->pb_pieces); dev_free(g->pb_rec);
-    dev_free(g->pb_rec2); dev_free(g->pb_coffs);
+    dev_free(g->pb_rec2); dev_free(g->pb_coffs); dev_free(g->pb_keys); dev_free(g->pb_ne);
     g->pb_offs_words = g->pb_tmp_words = g->pb_pieces_cap = g->pb_rec_cap = g->pb_rec2_cap = g->pb_coffs_words = 0;
+    g->pb_keys_cap = g->pb_ne_cap = 0;
     dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
     dev_free(g->cc_pick);
     dev_free(g->small);
@@ -1708,6 +1712,18 @@ int ensure_pb(gpma *g, const PbLayout &L) {
         if (dev_alloc(&g->pb_tmp, tw)) return GPMA_ENOMEM;
         g->pb_tmp_words = tw;
     }
+    if (g->pb_keys_cap < g->cap) {
+        dev_free(g->pb_keys);
+        g->pb_keys_cap = 0;
+        if (dev_alloc(&g->pb_keys, g->cap)) return GPMA_ENOMEM;
+        g->pb_keys_cap = g->cap;
+    }
+    if (g->pb_ne_cap < L.W) {
+        dev_free(g->pb_ne);
+        g->pb_ne_cap = 0;
+        if (dev_alloc(&g->pb_ne, L.W)) return GPMA_ENOMEM;
+        g->pb_ne_cap = L.W;
+    }
     if (g->pb_pieces_cap < L.max_pieces) {
         dev_free(g->pb_pieces);
         g->pb_pieces_cap = 0;
@@ -1742,7 +1758,7 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
     if (mode == kSpmvBinned) {
         L = pb_layout(g->V, g->cap, g->lf_log2, g->n);
         if (int e = ensure_pb(g, L)) return e;
-        launch_pb_structure(g->slots, L, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
+        launch_pb_structure(g->slots, L, g->pb_keys, g->pb_ne, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
                             g->pb_small + 1, g->pb_coffs, s);
     }
     for (uint32_t it = 0; it < iters; it++) {
@@ -1751,7 +1767,7 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
         {
             ProfScope ps(g, GPMA_K_SPMV, s);
             if (mode == kSpmvBinned)
-                launch_pb_spmv(g->slots, L, g->pb_offs, g->pb_small, g->pb_pieces,
+                launch_pb_spmv(g->pb_keys, g->pb_ne, L, g->pb_offs, g->pb_small, g->pb_pieces,
                                g->pb_small + 1, g->pb_coffs, g->pr_contrib, g->pb_rec, g->pb_rec2, g->V, g->pr_y, s);
             else if (mode == kSpmvPull)
                 launch_pr_pull(g->mir->slots, g->mir->cnt, g->mir->cap, g->mir->lf_log2, g->pr_contrib,

@@ -246,13 +246,14 @@ struct PbLayout {
 };
 bool pb_supported(uint32_t V);
 PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_entries);
-// per call: count matrix, its scan (offs, total edges), the piece table and
-// the scanned coarse count matrix (coffs, when nc > 0)
-void launch_pb_structure(const uint64_t *slots, const PbLayout &L,
+// per call: count matrix, its scan (offs, total edges), the piece table, the
+// scanned coarse count matrix (coffs, when nc > 0), and each slot range's
+// edges packed at keys[w*spw ..] (cap words), ne[w] of them (W words)
+void launch_pb_structure(const uint64_t *slots, const PbLayout &L, uint64_t *keys, uint32_t *ne,
                          uint32_t *offs, uint32_t *total, uint32_t *scan_tmp, uint4 *pieces, uint32_t *npieces,
                          uint32_t *coffs, hipStream_t s);
 // per iteration: y (zeroed beforehand) += A^T contrib; rec2 is used when nc > 0
-void launch_pb_spmv(const uint64_t *slots, const PbLayout &L,
+void launch_pb_spmv(const uint64_t *keys, const uint32_t *ne, const PbLayout &L,
                     const uint32_t *offs, const uint32_t *total, const uint4 *pieces, const uint32_t *npieces,
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s);

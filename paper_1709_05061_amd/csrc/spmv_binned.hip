@@ -10,10 +10,13 @@
 // vertices, whose slice of y (128 KiB of fp64) fits one workgroup's LDS:
 //   count (once per call): per slot range, how many edges fall in each fine
 //          bin; an exclusive scan of the bin-major count matrix gives every
-//          (bin, range) pair its place in the record array;
-//   bin   (per iteration):  stream the slots, write one 8-byte record per
-//          edge: the contribution with its low mantissa bits replaced by the
-//          destination's offset in its bin (records of the bins this slot
+//          (bin, range) pair its place in the record array.  The same pass
+//          packs each range's edges (gaps, guards and marked entries dropped)
+//          into a scratch copy, so the iterations read 8 bytes per edge
+//          instead of 8 bytes per slot;
+//   bin   (per iteration):  stream the packed edges, write one 8-byte record
+//          per edge: the contribution with its low mantissa bits replaced by
+//          the destination's offset in its bin (records of the bins this
 //          range feeds only a few are staged in LDS and leave as one run per
 //          bin, see k_pb_bin_quiet);
 //   split (optional, more than 64 fine bins only): the bin pass writes
@@ -56,28 +59,30 @@ __host__ __device__ inline uint64_t div_up(uint64_t a, uint64_t b) { return (a +
 
 __device__ __forceinline__ uint64_t ld_nt(const uint64_t *p) { return __builtin_nontemporal_load(p); }
 
-// The slot range of workgroup w is [w*spw, (w+1)*spw); spw is a power of two
-// no smaller than a leaf.  Each thread takes kUnroll slot pairs per step, one
-// 16-byte load each, all issued before any is used (the per-edge work is a
-// chain of dependent accesses), then fn(k) runs over them; gaps (all ones),
-// guards and marked entries are not edges.  The leaf counts are not read:
-// a gap holds the empty key, and a load that waited for its leaf's count
-// would serialise the stream (the occupied prefix rarely spares a line).
+// Workgroup w owns the slot range [w*spw, (w+1)*spw).  Once per call the
+// count pass streams that range and also packs its edges (in no particular
+// order) at keys[w*spw ..], ne[w] of them; every iteration's bin pass then
+// streams the packed edges instead of the gapped slots.  Each thread takes
+// kUnroll pairs per step, one 16-byte load each, all issued before any is
+// used (the per-edge work is a chain of dependent accesses), then fn(k) runs
+// over them; entries past the end read as the empty key.  The slot pass
+// reads gaps too: a gap holds the empty key, and a load that waited for its
+// leaf's count would serialise the stream (the occupied prefix rarely spares
+// a line).  The loop is uniform over the workgroup.
 constexpr int kUnroll = 8;
 
 template <typename F>
-__device__ __forceinline__ void for_each_edge(const uint64_t *__restrict__ slots, uint64_t spw, F fn) {
+__device__ __forceinline__ void for_each_pair_chunk(const uint64_t *__restrict__ base, uint64_t n, F fn) {
     using u64x2 = uint64_t __attribute__((ext_vector_type(2)));
-    const uint64_t lo = (uint64_t)blockIdx.x * spw;
-    const uint64_t hi = lo + spw;
     const uint64_t step = 2 * (uint64_t)blockDim.x;
-    for (uint64_t p0 = lo + 2 * threadIdx.x; p0 < hi; p0 += step * kUnroll) {
+    for (uint64_t c0 = 0; c0 < n; c0 += step * kUnroll) {
         uint64_t k[2 * kUnroll];
 #pragma unroll
         for (int u = 0; u < kUnroll; u++) {
-            const uint64_t p = p0 + u * step;
+            const uint64_t p = c0 + 2 * threadIdx.x + u * step;
             u64x2 q = {kEmpty, kEmpty};
-            if (p < hi) q = __builtin_nontemporal_load((const u64x2 *)(slots + p));
+            if (p + 1 < n) q = __builtin_nontemporal_load((const u64x2 *)(base + p));
+            else if (p < n) q.x = ld_nt(base + p);
             k[2 * u] = q.x;
             k[2 * u + 1] = q.y;
         }
@@ -107,18 +112,40 @@ __device__ __forceinline__ uint32_t reserve_in_bin(uint32_t *cur, uint32_t bin, 
 }
 
 __global__ void __launch_bounds__(kCountThreads)
-k_pb_count(const uint64_t *__restrict__ slots, uint64_t spw,
-           uint32_t nb, uint32_t W, uint32_t *__restrict__ counts) {
+k_pb_count(const uint64_t *__restrict__ slots, uint64_t spw, uint32_t nb, uint32_t W, uint32_t *__restrict__ counts,
+           uint64_t *__restrict__ keys, uint32_t *__restrict__ ne) {
     __shared__ uint32_t hist[kMaxBins];
+    __shared__ uint32_t packed;
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+    if (threadIdx.x == 0) packed = 0;
     __syncthreads();
-    for_each_edge(slots, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+    const uint32_t lane = __lane_id();
+    uint64_t *out = keys + (uint64_t)blockIdx.x * spw;
+    for_each_pair_chunk(slots + (uint64_t)blockIdx.x * spw, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+        uint32_t c = 0;
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
-            if (is_edge(k[j])) atomicAdd(&hist[key_dst(k[j]) >> kBinBits], 1u);
+            if (is_edge(k[j])) {
+                atomicAdd(&hist[key_dst(k[j]) >> kBinBits], 1u);
+                c++;
+            }
+        // the wave's edges go to one reserved stretch of the packed range
+        uint32_t x = c;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, kWave);
+            if (lane >= (uint32_t)d) x += y;
+        }
+        uint32_t at = 0;
+        if (lane == kWave - 1) at = atomicAdd(&packed, x);
+        at = __shfl(at, kWave - 1, kWave) + x - c;
+#pragma unroll
+        for (int j = 0; j < 2 * kUnroll; j++)
+            if (is_edge(k[j])) out[at++] = k[j];
     });
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) counts[(uint64_t)b * W + blockIdx.x] = hist[b];
+    if (threadIdx.x == 0) ne[blockIdx.x] = packed;
 }
 
 // bin b's records occupy [offs[b*W], offs[(b+1)*W]) (the last ends at the
@@ -151,14 +178,14 @@ k_pb_pieces(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tota
 // Bin pass for at most 64 bins (or coarse bins) of 2^bits destinations;
 // cur starts at offs[b*W + w]; places are reserved per wave (ballots).
 __global__ void __launch_bounds__(kCountThreads)
-k_pb_bin(const uint64_t *__restrict__ slots, uint64_t spw,
+k_pb_bin(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ne, uint64_t spw,
          uint32_t nb, uint32_t W, uint32_t bits, const uint32_t *__restrict__ offs,
          const double *__restrict__ contrib, uint64_t *__restrict__ rec) {
     __shared__ uint32_t cur[1u << kSplitBits];
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = offs[(uint64_t)b * W + blockIdx.x];
     __syncthreads();
     const uint64_t mask = (1ull << bits) - 1;
-    for_each_edge(slots, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+    for_each_pair_chunk(keys + (uint64_t)blockIdx.x * spw, ne[blockIdx.x], [&](const uint64_t (&k)[2 * kUnroll]) {
         uint64_t v[2 * kUnroll];
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
@@ -195,7 +222,7 @@ __host__ __device__ inline uint32_t stage_records(uint32_t lds_bytes, uint32_t n
 }
 
 __global__ void __launch_bounds__(kStageThreads)
-k_pb_bin_quiet(const uint64_t *__restrict__ slots, uint64_t spw,
+k_pb_bin_quiet(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ne, uint64_t spw,
                uint32_t nb, uint32_t W, const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total,
                const double *__restrict__ contrib, uint64_t *__restrict__ rec, uint32_t n_stage) {
     extern __shared__ uint64_t stage[];
@@ -224,7 +251,7 @@ k_pb_bin_quiet(const uint64_t *__restrict__ slots, uint64_t spw,
         used += tot;
     }
     __syncthreads();
-    for_each_edge(slots, spw, [&](const uint64_t (&k)[2 * kUnroll]) {
+    for_each_pair_chunk(keys + (uint64_t)blockIdx.x * spw, ne[blockIdx.x], [&](const uint64_t (&k)[2 * kUnroll]) {
         uint64_t v[2 * kUnroll];
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
@@ -386,10 +413,10 @@ PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges)
     return L;
 }
 
-void launch_pb_structure(const uint64_t *slots, const PbLayout &L,
+void launch_pb_structure(const uint64_t *slots, const PbLayout &L, uint64_t *keys, uint32_t *ne,
                          uint32_t *offs, uint32_t *total, uint32_t *scan_tmp, uint4 *pieces, uint32_t *npieces,
                          uint32_t *coffs, hipStream_t s) {
-    hipLaunchKernelGGL(k_pb_count, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nb, L.W, offs);
+    hipLaunchKernelGGL(k_pb_count, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nb, L.W, offs, keys, ne);
     scan_u32(offs, offs, L.count_words, total, scan_tmp, s);
     hipLaunchKernelGGL(k_pb_pieces, dim3(1), dim3(1024), 0, s, offs, total, L.nb, L.W, pieces, npieces);
     if (L.nc) {
@@ -399,23 +426,23 @@ void launch_pb_structure(const uint64_t *slots, const PbLayout &L,
     }
 }
 
-void launch_pb_spmv(const uint64_t *slots, const PbLayout &L,
+void launch_pb_spmv(const uint64_t *keys, const uint32_t *ne, const PbLayout &L,
                     const uint32_t *offs, const uint32_t *total, const uint4 *pieces, const uint32_t *npieces,
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s) {
     if (L.nc) {
-        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nc, L.W,
+        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nc, L.W,
                            kCoarseBits, coffs, contrib, rec);
         hipLaunchKernelGGL(k_pb_split, dim3((uint32_t)L.coarse_words), dim3(kCountThreads), 0, s, rec, coffs, total,
                            offs, L.nb, L.nc, L.W, rec2);
         rec = rec2;
     } else if (L.nb <= (1u << kSplitBits)) {
-        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, slots, L.spw, L.nb, L.W,
+        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nb, L.W,
                            kBinBits, offs, contrib, rec);
     } else {
         const uint32_t ns = stage_records((uint32_t)g_stage_lds, L.nb);
         const size_t lds = (size_t)ns * sizeof(uint64_t) + 3 * (size_t)L.nb * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_pb_bin_quiet, dim3(L.W), dim3(kStageThreads), lds, s, slots, L.spw, L.nb,
+        hipLaunchKernelGGL(k_pb_bin_quiet, dim3(L.W), dim3(kStageThreads), lds, s, keys, ne, L.spw, L.nb,
                            L.W, offs, total, contrib, rec, ns);
     }
     hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double), s, rec,
