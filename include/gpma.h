@@ -21,7 +21,7 @@
  *   - Calls are ordered on the caller's `stream`.  They return to the host
  *     once their work is enqueued, except where noted (each update batch
  *     synchronises with the host once per tree level it climbs; resizes,
- *     BFS levels and CC rounds also read small counters back).
+ *     BFS levels and the CC component pick also read small counters back).
  *   - A handle must be used by one host thread at a time; handles are
  *     independent.  Return value 0 = GPMA_OK, negative = error.
  *   - Errors: GPMA_EINVAL changes nothing (an invalid key makes its whole

@@ -300,27 +300,35 @@ __device__ __forceinline__ uint32_t cc_find(const uint32_t *label, uint32_t x) {
     return x;
 }
 
+// Union of the trees rooted at a and b: hook the larger root under the
+// smaller with a compare-and-swap that succeeds only while the larger is
+// still a root; when another thread hooked it first, look up both roots
+// again and retry.  Every union is therefore applied (one sweep over the
+// edges suffices), links always point to smaller ids (no cycles), and each
+// retry follows a hook that some other thread completed.
+__device__ __forceinline__ void cc_union(uint32_t *label, uint32_t a, uint32_t b) {
+    while (a != b) {
+        const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+        const uint32_t old = atomicCAS(&label[hi], hi, lo);
+        if (old == hi) return;
+        a = cc_find(label, old);
+        b = cc_find(label, lo);
+    }
+}
+
 __global__ void k_cc_init(uint32_t *__restrict__ label, uint32_t V) {
     uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < V) label[v] = (uint32_t)v;
 }
 
 __global__ void __launch_bounds__(256)
-k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uint32_t *changed) {
+k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    bool any = false;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
         uint64_t k = ld_stream(slots + p);
         if (!is_edge_entry(k)) continue;
-        uint32_t a = cc_find(label, key_src(k));
-        uint32_t b = cc_find(label, key_dst(k));
-        if (a != b) {
-            uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
-            atomicMin(&label[hi], lo);
-            any = true;
-        }
+        cc_union(label, cc_find(label, key_src(k)), cc_find(label, key_dst(k)));
     }
-    if (__ballot(any) && __lane_id() == 0) atomicOr(changed, 1u);
 }
 
 // Sampling round (the approach of Afforest, Sutton et al.): every vertex is
@@ -341,19 +349,15 @@ k_cc_sample(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row
         if (is_live(k)) break;
     }
     if (!is_edge_entry(k)) return;
-    const uint32_t a = cc_find(label, key_src(k));
-    const uint32_t b = cc_find(label, key_dst(k));
-    if (a != b) atomicMin(&label[a > b ? a : b], a > b ? b : a);
+    cc_union(label, cc_find(label, key_src(k)), cc_find(label, key_dst(k)));
 }
 
 // Hooking sweep that skips every entry whose row vertex is in component c
 // (the largest after sampling): with the array and its mirror both swept,
 // an edge is skipped on both sides only when both ends are already in c.
 __global__ void __launch_bounds__(256)
-k_cc_hook_skip(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uint32_t c,
-               uint32_t *changed) {
+k_cc_hook_skip(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uint32_t c) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    bool any = false;
     uint32_t last_u = 0xFFFFFFFFu, last_r = 0;
     for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
         const uint64_t k = ld_stream(slots + p);
@@ -364,14 +368,8 @@ k_cc_hook_skip(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label
             last_r = cc_find(label, u);
         }
         if (last_r == c) continue;
-        const uint32_t a = cc_find(label, u);
-        const uint32_t b = cc_find(label, key_dst(k));
-        if (a != b) {
-            atomicMin(&label[a > b ? a : b], a > b ? b : a);
-            any = true;
-        }
+        cc_union(label, cc_find(label, u), cc_find(label, key_dst(k)));
     }
-    if (__ballot(any) && __lane_id() == 0) atomicOr(changed, 1u);
 }
 
 // labels of n vertices at a fixed stride, for picking the largest component
@@ -464,10 +462,8 @@ void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s) {
     hipLaunchKernelGGL(k_cc_init, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, label, V);
 }
 
-void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t *changed,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_hook, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label,
-                       changed);
+void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_hook, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label);
 }
 
 void launch_cc_sample(const uint64_t *slots, const uint32_t *row_ptr, uint32_t V, uint32_t lf, uint32_t *label,
@@ -475,10 +471,8 @@ void launch_cc_sample(const uint64_t *slots, const uint32_t *row_ptr, uint32_t V
     hipLaunchKernelGGL(k_cc_sample, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, slots, row_ptr, V, lf, label);
 }
 
-void launch_cc_hook_skip(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t c, uint32_t *changed,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_hook_skip, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label, c,
-                       changed);
+void launch_cc_hook_skip(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t c, hipStream_t s) {
+    hipLaunchKernelGGL(k_cc_hook_skip, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label, c);
 }
 
 void launch_cc_pick(const uint32_t *label, uint64_t stride, uint32_t n, uint32_t *out, hipStream_t s) {

@@ -1839,8 +1839,9 @@ int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
     launch_cc_init(label, g->V, s);
     if (g->mir && g->V >= 4096) {
         // sample one out- and one in-neighbour per vertex, find the largest
-        // component from 1024 sampled labels, then sweep both arrays skipping
-        // its rows until nothing changes
+        // component from 1024 sampled labels, then sweep both arrays once,
+        // skipping the rows of that component (an edge is skipped on both
+        // sides only when both its ends are already in it)
         launch_cc_sample(g->slots, g->row_ptr, g->V, g->lf, label, s);
         launch_cc_sample(g->mir->slots, g->mir->row_ptr, g->V, g->lf, label, s);
         launch_cc_compress(label, g->V, s);
@@ -1857,33 +1858,22 @@ int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
             if (j - i > best) { best = (uint32_t)(j - i); c = smp[i]; }
             i = j;
         }
-        for (;;) {
-            hipMemsetAsync(g->small + 2, 0, sizeof(uint32_t), s);
-            {
-                ProfScope ps(g, GPMA_K_CC, s);
-                launch_cc_hook_skip(g->slots, g->cap, label, c, g->small + 2, s);
-                launch_cc_hook_skip(g->mir->slots, g->mir->cap, label, c, g->small + 2, s);
-                ps.done(16.0 * (double)g->n + 8.0 * (double)g->V);
-            }
-            launch_cc_compress(label, g->V, s);
-            hipMemcpyAsync(g->small_h + 2, g->small + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-            hipStreamSynchronize(s);
-            if (!g->small_h[2]) break;
-        }
-        return GPMA_OK;
-    }
-    for (int round = 0;; round++) {
-        hipMemsetAsync(g->small + 2, 0, sizeof(uint32_t), s);
         {
+            // one sweep of each array: every union is applied (cc_union)
             ProfScope ps(g, GPMA_K_CC, s);
-            launch_cc_hook(g->slots, g->cap, label, g->small + 2, s);
-            ps.done(8.0 * (double)g->n + 8.0 * (double)g->V);
+            launch_cc_hook_skip(g->slots, g->cap, label, c, s);
+            launch_cc_hook_skip(g->mir->slots, g->mir->cap, label, c, s);
+            ps.done(16.0 * (double)g->n + 8.0 * (double)g->V);
         }
         launch_cc_compress(label, g->V, s);
-        hipMemcpyAsync(g->small_h + 2, g->small + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-        hipStreamSynchronize(s);
-        if (!g->small_h[2]) break;
+        return GPMA_OK;
     }
+    {
+        ProfScope ps(g, GPMA_K_CC, s);
+        launch_cc_hook(g->slots, g->cap, label, s);
+        ps.done(8.0 * (double)g->n + 8.0 * (double)g->V);
+    }
+    launch_cc_compress(label, g->V, s);
     return GPMA_OK;
 }
 

@@ -268,12 +268,10 @@ void launch_bfs_expand(const uint64_t *slots, const uint32_t *row_ptr, const uin
 void launch_bfs_bottom_up(const uint64_t *mslots, const uint32_t *mrow, uint32_t V, int32_t level,
                           int32_t *dist, uint32_t *next, uint32_t *next_count, hipStream_t s);
 void launch_cc_init(uint32_t *label, uint32_t V, hipStream_t s);
-void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t *changed,
-                    hipStream_t s);
+void launch_cc_hook(const uint64_t *slots, uint64_t cap, uint32_t *label, hipStream_t s);
 void launch_cc_sample(const uint64_t *slots, const uint32_t *row_ptr, uint32_t V, uint32_t lf, uint32_t *label,
                       hipStream_t s);
-void launch_cc_hook_skip(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t c, uint32_t *changed,
-                         hipStream_t s);
+void launch_cc_hook_skip(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t c, hipStream_t s);
 void launch_cc_pick(const uint32_t *label, uint64_t stride, uint32_t n, uint32_t *out, hipStream_t s);
 void launch_cc_compress(uint32_t *label, uint32_t V, hipStream_t s);
 
