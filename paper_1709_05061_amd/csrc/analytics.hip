@@ -253,6 +253,8 @@ k_bfs_expand(const uint64_t *__restrict__ slots, uint64_t cap, const uint32_t *_
 // step has dist[u] = level+1 and is correctly not taken as a parent.  Used
 // for large frontiers (most unvisited vertices then find a parent within a
 // few in-edges).
+constexpr int kBuStep = 4;
+
 __global__ void __launch_bounds__(256)
 k_bfs_bottom_up(const uint64_t *__restrict__ mslots, const uint32_t *__restrict__ mrow, uint32_t V,
                 int32_t level, int32_t *__restrict__ dist, uint32_t *__restrict__ next,
@@ -263,18 +265,23 @@ k_bfs_bottom_up(const uint64_t *__restrict__ mslots, const uint32_t *__restrict_
         const uint32_t v = (uint32_t)v0;
         bool claim = false;
         if (dist[v] < 0) {
+            // kBuStep entries at a time: their loads, then their parents'
+            // distances, are in flight together (a row ends with its guard,
+            // which, like gaps and marked entries, is not an edge).  A
+            // distance equal to `level` cannot change during the step (only
+            // unvisited vertices are written), so plain loads may hit cache.
             const uint32_t end = mrow[v + 1];
-            for (uint32_t p = mrow[v]; p < end; p++) {
-                const uint64_t k = mslots[p];
-                if (!is_live(k)) continue;   // gap or marked entry
-                if (is_guard(k)) break;
-                const uint32_t u = (uint32_t)k;
-                if (__hip_atomic_load(&dist[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == level) {
-                    claim = true;
-                    break;
-                }
+            for (uint32_t p = mrow[v]; p < end && !claim; p += kBuStep) {
+                uint64_t k[kBuStep];
+#pragma unroll
+                for (int j = 0; j < kBuStep; j++) k[j] = p + j < end ? mslots[p + j] : kEmpty;
+                int32_t d[kBuStep];
+#pragma unroll
+                for (int j = 0; j < kBuStep; j++) d[j] = is_edge_entry(k[j]) ? dist[(uint32_t)k[j]] : -2;
+#pragma unroll
+                for (int j = 0; j < kBuStep; j++) claim |= d[j] == level;
             }
-            if (claim) __hip_atomic_store(&dist[v], level + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (claim) dist[v] = level + 1;
         }
         const uint64_t m = __ballot(claim);
         if (m) {
