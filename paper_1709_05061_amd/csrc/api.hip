@@ -127,6 +127,10 @@ struct gpma {
     uint32_t *stop = nullptr;            // device stop flag of this handle's sequence
     BatchDesc *desc = nullptr;           // device table of the current chunk
     BatchOut *outs = nullptr;            // device per-batch results
+    // fs, stop and outs live in one device block, mirrored by one pinned
+    // block, so a window's results come back in one copy per handle
+    uint64_t *fblk = nullptr;            // device block
+    void *fblk_h = nullptr;              // pinned block
     FusedState *fs_h = nullptr;          // pinned mirror of *fs
     uint32_t *stop_h = nullptr;          // pinned
     FusedState *reset_h = nullptr;       // pinned source of state resets
@@ -303,6 +307,7 @@ void drop_graphs(gpma *g) {
 
 void free_batch(gpma *g) {
     drop_graphs(g);
+    g->wukeys = nullptr;   // the sort buffers go; the next window prefix picks them again
     dev_free(g->kS);
     dev_free(g->kA); dev_free(g->kB); dev_free(g->kC); dev_free(g->kD);
     dev_free(g->leafA); dev_free(g->leafB); dev_free(g->stA); dev_free(g->stB);
@@ -759,13 +764,15 @@ void free_all(gpma *g) {
     free_batch(g);
     dev_free(g->loc); dev_free(g->loc_gram); dev_free(g->loc_err);
     dev_free(g->tkeys);
-    dev_free(g->fs); dev_free(g->stop); dev_free(g->desc); dev_free(g->outs);
+    dev_free(g->fblk); dev_free(g->desc);
+    g->fs = nullptr;
+    g->stop = nullptr;
+    g->outs = nullptr;
     dev_free(g->werrs); dev_free(g->wcount); dev_free(g->ustart);
-    if (g->fs_h) hipHostFree(g->fs_h);
-    if (g->stop_h) hipHostFree(g->stop_h);
+    if (g->fblk_h) hipHostFree(g->fblk_h);
+    g->fblk_h = nullptr;
     if (g->reset_h) hipHostFree(g->reset_h);
     if (g->desc_h) hipHostFree(g->desc_h);
-    if (g->outs_h) hipHostFree(g->outs_h);
     g->fs_h = nullptr;
     g->stop_h = nullptr;
     g->reset_h = nullptr;
@@ -807,18 +814,33 @@ constexpr uint32_t kFusedChunk = 4096;   // batches per descriptor table
 
 uint64_t batch_class(uint64_t b) { return next_pow2(std::max<uint64_t>(b, 1024)); }
 
+// layout of the fused block: FusedState, the stop flag, the per-batch results
+constexpr size_t kFbStop = (sizeof(FusedState) + 15) / 16 * 16;
+constexpr size_t kFbOuts = kFbStop + 16;
+constexpr size_t kFbBytes = kFbOuts + kFusedChunk * sizeof(BatchOut);
+
 int ensure_fused(gpma *g) {
     if (g->fs) return GPMA_OK;
     int e = GPMA_OK;
-    e |= dev_alloc(&g->fs, 1);
-    e |= dev_alloc(&g->stop, 1);
+    e |= dev_alloc(&g->fblk, (kFbBytes + 7) / 8);
+    if (!e) {
+        uint8_t *b = (uint8_t *)g->fblk;
+        g->fs = (FusedState *)b;
+        g->stop = (uint32_t *)(b + kFbStop);
+        g->outs = (BatchOut *)(b + kFbOuts);
+    }
     e |= dev_alloc(&g->desc, kFusedChunk);
-    e |= dev_alloc(&g->outs, kFusedChunk);
-    if (hipHostMalloc((void **)&g->fs_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
-    if (hipHostMalloc((void **)&g->stop_h, sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc(&g->fblk_h, kFbBytes, 0) != hipSuccess) {
+        g->fblk_h = nullptr;
+        e = GPMA_ENOMEM;
+    } else {
+        uint8_t *b = (uint8_t *)g->fblk_h;
+        g->fs_h = (FusedState *)b;
+        g->stop_h = (uint32_t *)(b + kFbStop);
+        g->outs_h = (BatchOut *)(b + kFbOuts);
+    }
     if (hipHostMalloc((void **)&g->reset_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (hipHostMalloc((void **)&g->desc_h, kFusedChunk * sizeof(BatchDesc), 0) != hipSuccess) e = GPMA_ENOMEM;
-    if (hipHostMalloc((void **)&g->outs_h, kFusedChunk * sizeof(BatchOut), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (!e && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
@@ -943,6 +965,8 @@ gpma::GraphEntry *get_graph(gpma *g, uint64_t cls, bool del, const BatchDesc *de
                             bool transpose) {
     for (auto &e : g->graphs)
         if (e.cls == cls && e.del == del && e.version == g->geom_version) return &e;
+    // a batch reads its keys from the buffer a window prefix sorted them into
+    if (!g->wukeys) return nullptr;
     gpma::GraphEntry ge{};
     ge.cls = cls;
     ge.del = del;
@@ -1091,13 +1115,10 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             hipEventRecord(g->ev_join, P[1].st);
             hipStreamWaitEvent(s, g->ev_join, 0);
         }
+        // state, stop flag and results up to the window's end: one copy per handle
         for (int k = 0; k < nh; k++) {
             gpma *h = P[k].h;
-            read_fused(h, s);
-            hipMemcpyAsync(h->stop_h, h->stop, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-            if (end[k] > P[k].next)
-                hipMemcpyAsync(h->outs_h + P[k].next, h->outs + P[k].next, (end[k] - P[k].next) * sizeof(BatchOut),
-                               hipMemcpyDeviceToHost, s);
+            hipMemcpyAsync(h->fblk_h, h->fblk, kFbOuts + end[k] * sizeof(BatchOut), hipMemcpyDeviceToHost, s);
         }
         if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
         bool stopped = false;
