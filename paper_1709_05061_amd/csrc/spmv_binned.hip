@@ -116,6 +116,7 @@ k_pb_count(const uint64_t *__restrict__ slots, uint64_t spw, uint32_t nb, uint32
            uint64_t *__restrict__ keys, uint32_t *__restrict__ ne) {
     __shared__ uint32_t hist[kMaxBins];
     __shared__ uint32_t packed;
+    __shared__ uint64_t wbuf[kCountThreads / kWave][2 * kUnroll * kWave];   // a wave's edges, packed
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     if (threadIdx.x == 0) packed = 0;
     __syncthreads();
@@ -129,19 +130,26 @@ k_pb_count(const uint64_t *__restrict__ slots, uint64_t spw, uint32_t nb, uint32
                 atomicAdd(&hist[key_dst(k[j]) >> kBinBits], 1u);
                 c++;
             }
-        // the wave's edges go to one reserved stretch of the packed range
+        // the wave packs its edges in LDS, reserves one stretch of the packed
+        // range and writes it with consecutive lanes on consecutive edges
         uint32_t x = c;
 #pragma unroll
         for (int d = 1; d < kWave; d <<= 1) {
             const uint32_t y = __shfl_up(x, d, kWave);
             if (lane >= (uint32_t)d) x += y;
         }
-        uint32_t at = 0;
-        if (lane == kWave - 1) at = atomicAdd(&packed, x);
-        at = __shfl(at, kWave - 1, kWave) + x - c;
+        uint64_t *wb = wbuf[threadIdx.x / kWave];
+        uint32_t q = x - c;
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++)
-            if (is_edge(k[j])) out[at++] = k[j];
+            if (is_edge(k[j])) wb[q++] = k[j];
+        const uint32_t total = __shfl(x, kWave - 1, kWave);
+        uint32_t at = 0;
+        if (lane == kWave - 1) at = atomicAdd(&packed, total);
+        at = __shfl(at, kWave - 1, kWave);
+        wave_lds_sync();
+        for (uint32_t t = lane; t < total; t += kWave) out[at + t] = wb[t];
+        wave_lds_sync();   // the buffer is refilled next step
     });
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) counts[(uint64_t)b * W + blockIdx.x] = hist[b];
