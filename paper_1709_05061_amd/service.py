@@ -13,6 +13,8 @@ is the control loop of such a service, MI355X-side:
   holds a snapshot of the graph (device copies of the arrays the analytics
   read) plus its scratch, so the number of slots is the HBM budget divided
   by the bytes of one slot; a query waits in the queue until a slot is free;
+  every slot takes its memory when the service starts (a snapshot and one
+  run of each analytic), so no query pays for an allocation;
 * an admitted query snapshots the current version on the update stream and
   runs on its slot's own stream, overlapping the updates that follow;
 * latency: an edge from its arrival time to the completion of the batch that
@@ -113,13 +115,24 @@ class GraphService:
         self.max_batch = max_batch
         self.pr_iters = pr_iters
         self.ustream = torch.cuda.Stream()
-        slot_bytes = int(self._lib.gpma_device_bytes(self.g.h)) + V * (4 + 4 + 8 + 8 + 4 + 4 + 4)
+        # a slot: the snapshot (array and mirror), PageRank's scratch (packed
+        # edges, 8 B a slot of the array; binned records, 10 B an entry; fp64
+        # vectors), BFS queues and the slot's own vectors
+        cap, n_ent = int(self.g.capacity), int(self.g.num_edges) + V
+        slot_bytes = (int(self._lib.gpma_device_bytes(self.g.h)) + 8 * cap + 10 * n_ent
+                      + V * (4 + 4 + 8 + 8 + 4 + 4 + 4))
         self.slot_bytes = slot_bytes
         if hbm_budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
             hbm_budget_bytes = free // 4
         n = int(max(1, min(max_slots, hbm_budget_bytes // slot_bytes)))
         self.slots = [_Slot(V) for _ in range(n)]
+        for slot in self.slots:   # reserve every slot's memory now
+            self._snapshot_into(slot)
+            self.ustream.synchronize()
+            gpma_pagerank(slot.snap, None, slot.x, 1, 0.85, stream=slot.stream)
+            gpma_bfs(slot.snap, 0, slot.dist, stream=slot.stream)
+            slot.stream.synchronize()
         self.version = 0
         self.record = False
         self.batch_log = []                 # (deleted, inserted) per version step, on host, if record
