@@ -490,3 +490,38 @@ def test_degenerate_graphs(mirror):
     assert d[7] == 0 and (np.delete(d, 7) == -1).all()
     assert np.array_equal(g.cc().cpu().numpy(), np.arange(V))
     g.close()
+
+
+@pytest.mark.parametrize("mirror", [False, True])
+@pytest.mark.parametrize("shape", ["permuted_path", "star_in", "star_out", "many_components"])
+def test_cc_contended_unions(shape, mirror):
+    """CC applies each union once, by compare-and-swap on roots, in a single
+    sweep: shapes that make many threads race on one root (stars), build
+    deep trees (a long path whose vertex ids are shuffled), or mix one giant
+    component with many small ones (the sampling path skips the giant one)
+    must still equal the oracle's union-find."""
+    from paper_1709_05061_amd import GPMA
+    V = 1 << 14
+    rng = np.random.default_rng(["permuted_path", "star_in", "star_out", "many_components"].index(shape) + 40)
+    if shape == "permuted_path":
+        perm = rng.permutation(V).astype(np.uint64)
+        e = (perm[:-1] << np.uint64(32)) | perm[1:]
+    elif shape == "star_in":
+        leaves = np.arange(1, V, dtype=np.uint64)
+        e = (leaves << np.uint64(32)) | np.uint64(V - 1)          # every edge into one hub
+    elif shape == "star_out":
+        leaves = np.arange(0, V - 1, dtype=np.uint64)
+        e = (np.uint64(V // 2) << np.uint64(32)) | leaves          # one hub out to all
+        e = e[leaves != np.uint64(V // 2)]
+    else:
+        big = rng.permutation(V // 2).astype(np.uint64)
+        e1 = (big[:-1] << np.uint64(32)) | big[1:]
+        small = np.arange(V // 2, V, dtype=np.uint64).reshape(-1, 4)
+        e2 = np.concatenate([(small[:, 0] << np.uint64(32)) | small[:, 1],
+                             (small[:, 3] << np.uint64(32)) | small[:, 2]])
+        e = np.concatenate([e1, e2, rng.choice(e1, 100)])
+    e = np.unique(e)
+    g, _ = make(V, e, 16, mirror=mirror)
+    for _ in range(2):   # repeated calls give the same labels
+        assert np.array_equal(g.cc().cpu().numpy().astype(np.uint32), O.cc(V, e))
+    g.close()
