@@ -31,7 +31,7 @@
 //          records into the LDS slice with fp64 LDS atomics and writes the
 //          slice out (store for a bin in one piece, fp64 atomics for a split
 //          bin).
-// Every HBM access is a stream; the random traffic stays in LDS.
+// The HBM traffic is streams and per-bin runs; the random updates stay in LDS.
 // Contributions are carried with 38 mantissa bits (32 with coarse bins;
 // relative truncation below 2^-32), sums in fp64.
 #include <cstdlib>
@@ -49,7 +49,7 @@ constexpr uint32_t kSplitBits = 6;                       // fine bins per coarse
 constexpr uint32_t kCoarseBits = kBinBits + kSplitBits;  // 2^20 vertices per coarse bin
 constexpr uint64_t kCoarseMask = (1ull << kCoarseBits) - 1;
 constexpr uint32_t kCountThreads = 256;
-constexpr uint64_t kRanges = 4096;              // slot ranges (workgroups) per pass, at most
+constexpr uint64_t kRanges = 4096;              // slot ranges (workgroups) per pass, unless a range would pass kMaxRangeSlots
 constexpr uint32_t kAccThreads = 1024;
 constexpr uint32_t kMaxBins = 4096;            // V <= 2^26
 constexpr uint64_t kPieceRecords = 1ull << 18;  // records per accumulation workgroup
