@@ -525,3 +525,27 @@ def test_cc_contended_unions(shape, mirror):
     for _ in range(2):   # repeated calls give the same labels
         assert np.array_equal(g.cc().cpu().numpy().astype(np.uint32), O.cc(V, e))
     g.close()
+
+
+@pytest.mark.parametrize("V,mirror", [(1 << 26, False), ((1 << 26) + 5, True), ((1 << 26) + 5, False)])
+def test_spmv_at_the_bin_limit(V, mirror):
+    """The destination-binned SpMV takes up to 4096 bins (V <= 2^26; the
+    quiet-bin stage then has the least LDS); one more vertex falls back to
+    pull over the mirror or push.  Sparse, skewed graphs at those sizes (the
+    67M guards dominate the array) against the fp64 oracle, and BFS/CC."""
+    from paper_1709_05061_amd import GPMA
+    r = np.unique(npu64(synth.rmat_unique(20, 1 << 21, seed=9)))
+    # spread the R-MAT ids over the whole range so every bin sees edges
+    src = (r >> np.uint64(32)) * np.uint64(64) + np.uint64(3)
+    dst = (r & np.uint64(0xFFFFFFFF)) * np.uint64(64) + np.uint64(1)
+    e = np.unique((src << np.uint64(32)) | dst)
+    e = e[((e >> np.uint64(32)) < np.uint64(V)) & ((e & np.uint64(0xFFFFFFFF)) < np.uint64(V))]
+    say("bin limit", V, mirror, e.size)
+    g = GPMA(V, dev(e), mirror=mirror)
+    x = g.pagerank(iters=5).cpu().numpy()
+    want = O.pagerank(V, e, iters=5)
+    assert np.max(np.abs(x - want) / want) < PR_RTOL
+    s0 = int(e[0] >> np.uint64(32))
+    assert np.array_equal(g.bfs(s0).cpu().numpy(), O.bfs(V, e, s0))
+    assert np.array_equal(g.cc().cpu().numpy().astype(np.uint32), O.cc(V, e))
+    g.close()
