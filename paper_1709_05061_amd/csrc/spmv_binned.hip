@@ -92,6 +92,20 @@ __device__ __forceinline__ void for_each_pair_chunk(const uint64_t *__restrict__
 
 __device__ __forceinline__ bool is_edge(uint64_t k) { return is_edge_entry(k); }   // live, not a guard
 
+// The contributions of a step's packed edges.  The two edges of a pair are
+// neighbours in the src-major array, so they mostly share their source (a
+// skewed graph's edges sit mostly in long rows): the second reuses the
+// first's value then, which spares the address unit a gather lane.
+__device__ __forceinline__ void pair_contribs(const uint64_t (&k)[2 * kUnroll], const double *__restrict__ contrib,
+                                              uint64_t (&v)[2 * kUnroll]) {
+#pragma unroll
+    for (int j = 0; j < 2 * kUnroll; j++) {
+        const bool same = (j & 1) && key_src(k[j]) == key_src(k[j - 1]);
+        if (is_edge(k[j]) && !same) v[j] = (uint64_t)__double_as_longlong(contrib[key_src(k[j])]);
+        else v[j] = (j & 1) ? v[j - 1] : 0;
+    }
+}
+
 // Place of a lane's record in its bin (bins < 64): the lanes holding the same
 // bin find each other with six ballots; the lowest of them reserves the
 // group's places with one LDS atomic and each lane takes base + its rank in
@@ -195,9 +209,7 @@ k_pb_bin(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ne, uin
     const uint64_t mask = (1ull << bits) - 1;
     for_each_pair_chunk(keys + (uint64_t)blockIdx.x * spw, ne[blockIdx.x], [&](const uint64_t (&k)[2 * kUnroll]) {
         uint64_t v[2 * kUnroll];
-#pragma unroll
-        for (int j = 0; j < 2 * kUnroll; j++)
-            v[j] = is_edge(k[j]) ? (uint64_t)__double_as_longlong(contrib[key_src(k[j])]) : 0;
+        pair_contribs(k, contrib, v);
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++) {
             const bool ok = is_edge(k[j]);
@@ -261,9 +273,7 @@ k_pb_bin_quiet(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n
     __syncthreads();
     for_each_pair_chunk(keys + (uint64_t)blockIdx.x * spw, ne[blockIdx.x], [&](const uint64_t (&k)[2 * kUnroll]) {
         uint64_t v[2 * kUnroll];
-#pragma unroll
-        for (int j = 0; j < 2 * kUnroll; j++)
-            v[j] = is_edge(k[j]) ? (uint64_t)__double_as_longlong(contrib[key_src(k[j])]) : 0;
+        pair_contribs(k, contrib, v);
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++) {
             if (!is_edge(k[j])) continue;
