@@ -328,6 +328,35 @@ __global__ void k_cc_init(uint32_t *__restrict__ label, uint32_t V) {
     if (v < V) label[v] = (uint32_t)v;
 }
 
+// A grid-stride pass over slot pairs: each thread issues kCcPairs 16-byte
+// loads before it uses any (the per-edge work is a chain of dependent label
+// reads), then fn(k) runs over the 2*kCcPairs slots; slots past the end read
+// as the empty key.  The two slots of a pair are neighbours, so an edge at an
+// odd place usually shares its source with the one before it.
+constexpr int kCcPairs = 4;
+
+template <typename F>
+__device__ __forceinline__ void for_slot_pairs(const uint64_t *__restrict__ slots, uint64_t cap, F fn) {
+    using u64x2 = uint64_t __attribute__((ext_vector_type(2)));
+    const uint64_t np = (cap + 1) >> 1;
+    const uint64_t nt = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t q0 = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; q0 < np; q0 += nt * kCcPairs) {
+        uint64_t k[2 * kCcPairs];
+#pragma unroll
+        for (int u = 0; u < kCcPairs; u++) {
+            const uint64_t p = 2 * (q0 + (uint64_t)u * nt);
+            u64x2 v = {kEmpty, kEmpty};
+            if (p + 1 < cap) v = __builtin_nontemporal_load((const u64x2 *)(slots + p));
+            else if (p < cap) v.x = ld_stream(slots + p);
+            k[2 * u] = v.x;
+            k[2 * u + 1] = v.y;
+        }
+        fn(k);
+    }
+}
+
+// Without a mirror every edge takes a union, and one slot per thread and
+// step measured faster than the pair loop of the skipping sweep below.
 __global__ void __launch_bounds__(256)
 k_cc_hook(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label) {
     uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -364,19 +393,17 @@ k_cc_sample(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row
 // an edge is skipped on both sides only when both ends are already in c.
 __global__ void __launch_bounds__(256)
 k_cc_hook_skip(const uint64_t *__restrict__ slots, uint64_t cap, uint32_t *label, uint32_t c) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint32_t last_u = 0xFFFFFFFFu, last_r = 0;
-    for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < cap; p += stride) {
-        const uint64_t k = ld_stream(slots + p);
-        if (!is_edge_entry(k)) continue;
-        const uint32_t u = key_src(k);
-        if (u != last_u) {
-            last_u = u;
-            last_r = cc_find(label, u);
+    for_slot_pairs(slots, cap, [&](const uint64_t (&k)[2 * kCcPairs]) {
+        uint32_t ru = 0;   // a root the source had (once in c's tree, always in c's component)
+#pragma unroll
+        for (int j = 0; j < 2 * kCcPairs; j++) {
+            if (!is_edge_entry(k[j])) continue;
+            const uint32_t u = key_src(k[j]);
+            if (!(j & 1) || !is_edge_entry(k[j - 1]) || key_src(k[j - 1]) != u) ru = cc_find(label, u);
+            if (ru == c) continue;
+            cc_union(label, cc_find(label, u), cc_find(label, key_dst(k[j])));
         }
-        if (last_r == c) continue;
-        cc_union(label, cc_find(label, u), cc_find(label, key_dst(k)));
-    }
+    });
 }
 
 // labels of n vertices at a fixed stride, for picking the largest component
@@ -479,7 +506,8 @@ void launch_cc_sample(const uint64_t *slots, const uint32_t *row_ptr, uint32_t V
 }
 
 void launch_cc_hook_skip(const uint64_t *slots, uint64_t cap, uint32_t *label, uint32_t c, hipStream_t s) {
-    hipLaunchKernelGGL(k_cc_hook_skip, dim3(grid_for_stream(cap, 4)), dim3(256), 0, s, slots, cap, label, c);
+    hipLaunchKernelGGL(k_cc_hook_skip, dim3(grid_for_stream(div_up(cap, 2), kCcPairs)), dim3(256), 0, s, slots, cap,
+                       label, c);
 }
 
 void launch_cc_pick(const uint32_t *label, uint64_t stride, uint32_t n, uint32_t *out, hipStream_t s) {
