@@ -181,3 +181,39 @@ def test_fused_windows_invalid_batch_then_more_calls(mirror):
             (mref.delete if ops[i] else mref.insert)(t(bs[i]))
         assert np.array_equal(npu64(g.mirror().slots()), mref.slots())
     g.close()
+
+
+@pytest.mark.parametrize("n_extra", [0, 1, 2, 3, 5])
+def test_fused_mirror_under_other_streams(n_extra):
+    """With a mirror the two fused pipelines run on library streams forked
+    from and joined to the caller's stream.  Other live streams in the
+    process change which hardware queues those streams sit on; the result
+    must not change: fused equals plain on the array and the mirror, also
+    when the caller works on a non-default stream."""
+    from paper_1709_05061_amd import GPMA
+    extra = []
+    for _ in range(n_extra):
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            torch.zeros(1, device="cuda")
+        extra.append(s)
+    V, lf = 700, 16
+    init = np.unique(npu64(synth.random_batch(V, 8000, 7)))
+    ops, bs = make_sequence(V, init, 24, seed=11 + n_extra)
+    plain = GPMA(V, dev(init), leaf_size=lf, mirror=True)
+    fused = GPMA(V, dev(init), leaf_size=lf, mirror=True, fused_levels=1)
+    caller = torch.cuda.Stream() if n_extra % 2 else torch.cuda.current_stream()
+    say("fused under", n_extra, "extra streams, caller stream", caller)
+    for lo, hi in ((0, 10), (10, 11), (11, 24)):
+        for i in range(lo, hi):
+            (plain.delete if ops[i] else plain.insert)(dev(bs[i]))
+        keys = [dev(b) for b in bs[lo:hi]]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(caller):
+            fused.apply_batches(ops[lo:hi], keys)
+        torch.cuda.synchronize()
+        assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
+        assert np.array_equal(npu64(fused.mirror().slots()), npu64(plain.mirror().slots())), (lo, hi)
+        assert fused.num_edges == plain.num_edges
+    plain.close()
+    fused.close()
