@@ -109,12 +109,16 @@ struct gpma {
     std::vector<GraphEntry> graphs;
     uint32_t geom_version = 1;
     hipStream_t cap_stream = nullptr;
-    // fused batching with a mirror: the array's batches run on `side`, the
-    // mirror's on `side2`; the two are created one after the other so that
-    // the runtime puts them on different hardware queues (a caller's stream
-    // can share a queue with a stream created later, and two pipelines on
-    // one queue run one after the other)
+    // fused batching with a mirror: the mirror's batches run on `pair` (side
+    // or side2, whichever a probe found running beside the caller's stream
+    // `probed`), the array's on the caller's stream.  Two pipelines on one
+    // hardware queue run one after the other, and the runtime may put a
+    // library stream on the caller's queue; when neither does better, the
+    // array's batches take side and the mirror's side2 (created one after
+    // the other, so on different queues).
     hipStream_t side = nullptr, side2 = nullptr;
+    hipStream_t probed = nullptr, pair = nullptr;
+    bool probe_done = false;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     uint64_t *kS = nullptr;              // window staging, then the current batch's keys
     FusedState *fs = nullptr;            // device
@@ -1048,6 +1052,47 @@ void account(gpma *g, uint32_t from, uint32_t to, gpma_stats *total) {
     }
 }
 
+// Probe kernels: a bounded wait (n sleeps of a single wave) and an empty mark.
+__global__ void k_probe_wait(uint32_t n) {
+    for (uint32_t i = 0; i < n; i++) __builtin_amdgcn_s_sleep(8);
+}
+__global__ void k_probe_mark() {}
+
+// Which library stream runs beside caller stream s: a wait of ~0.1 ms goes on
+// s, an empty kernel on the candidate; if the candidate's kernel completes
+// while s's wait has not, the two sit on different hardware queues.  Once per
+// caller stream; nullptr when neither candidate does.
+hipStream_t pick_pair_stream(gpma *g, hipStream_t s) {
+    if (g->probe_done && g->probed == s) return g->pair;
+    constexpr uint32_t kProbeSleeps = 2000;
+    hipEvent_t e_wait = nullptr, e_mark = nullptr;
+    hipStream_t pick = nullptr;
+    if (hipEventCreateWithFlags(&e_wait, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&e_mark, hipEventDisableTiming) == hipSuccess) {
+        for (hipStream_t c : {g->side, g->side2}) {
+            if (hipStreamSynchronize(s) != hipSuccess || hipStreamSynchronize(c) != hipSuccess) break;
+            hipLaunchKernelGGL(k_probe_wait, dim3(1), dim3(kWave), 0, s, kProbeSleeps);
+            hipEventRecord(e_wait, s);
+            hipLaunchKernelGGL(k_probe_mark, dim3(1), dim3(kWave), 0, c);
+            hipEventRecord(e_mark, c);
+            if (hipEventSynchronize(e_mark) != hipSuccess) break;
+            const bool beside = hipEventQuery(e_wait) == hipErrorNotReady;
+            if (hipStreamSynchronize(s) != hipSuccess) break;
+            if (beside) {
+                pick = c;
+                break;
+            }
+        }
+    }
+    (void)hipGetLastError();   // a not-ready query is not an error of the next call
+    if (e_wait) hipEventDestroy(e_wait);
+    if (e_mark) hipEventDestroy(e_mark);
+    g->probed = s;
+    g->pair = pick;
+    g->probe_done = true;
+    return pick;
+}
+
 int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys, const uint64_t *sizes,
                 hipStream_t s, gpma_stats *total, uint32_t *done_out) {
     gpma *m = g->mir;
@@ -1068,11 +1113,15 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
         uint32_t next;
         bool failed;
     };
-    // with a mirror both pipelines leave the caller's stream (fork and join
-    // by events): measured on MI355X, the mirror's pipeline on a stream that
-    // shared the caller's hardware queue cost the overlap (2.9e8 -> 2.1e8
-    // updates/s at R-MAT scale 22)
-    Prog P[2] = {{g, m ? g->side : s, false, 0, false}, {m, m ? g->side2 : s, true, 0, false}};
+    // with a mirror: the array's pipeline on the caller's stream and the
+    // mirror's on a library stream found running beside it; failing that,
+    // both on library streams, forked from and joined to the caller's (the
+    // extra hop costs ~10 % of a slide at R-MAT scale 24; a mirror pipeline
+    // on the caller's hardware queue cost the overlap: 2.9e8 -> 2.1e8
+    // updates/s at scale 22)
+    const hipStream_t pair = m ? pick_pair_stream(g, s) : nullptr;
+    const bool lib0 = m && !pair;   // the array's pipeline leaves the caller's stream
+    Prog P[2] = {{g, lib0 ? g->side : s, false, 0, false}, {m, m ? (pair ? pair : g->side2) : s, true, 0, false}};
     const int nh = m ? 2 : 1;
     for (int k = 0; k < nh; k++) {
         hipMemsetAsync(P[k].h->stop, 0, sizeof(uint32_t), s);
@@ -1086,7 +1135,7 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
         uint32_t end[2] = {0, 0};
         if (nh > 1) {
             hipEventRecord(g->ev_fork, s);
-            hipStreamWaitEvent(P[0].st, g->ev_fork, 0);
+            if (lib0) hipStreamWaitEvent(P[0].st, g->ev_fork, 0);
             hipStreamWaitEvent(P[1].st, g->ev_fork, 0);
         }
         // a window: at most `window` batches (kWindowMax when tagged, else 1)
@@ -1127,9 +1176,11 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
         }
         if (nh > 1) {
             hipEventRecord(g->ev_join, P[1].st);
-            hipEventRecord(g->ev_join2, P[0].st);
             hipStreamWaitEvent(s, g->ev_join, 0);
-            hipStreamWaitEvent(s, g->ev_join2, 0);
+            if (lib0) {
+                hipEventRecord(g->ev_join2, P[0].st);
+                hipStreamWaitEvent(s, g->ev_join2, 0);
+            }
         }
         // state, stop flag and results up to the window's end: one copy per handle
         for (int k = 0; k < nh; k++) {
