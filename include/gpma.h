@@ -177,7 +177,12 @@ int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
  * batches.  On an invalid key in batch i, batches before i stay applied,
  * batch i and later are not, and GPMA_EINVAL is returned; *completed (if
  * non-NULL) receives the number of batches applied.  `total` (if non-NULL)
- * receives summed statistics (per-level counts are not filled). */
+ * receives summed statistics (per-level counts are not filled).  With a
+ * mirror the mirror's batches run on a stream of the handle, forked from and
+ * joined to `stream` by events; the first call on a given `stream`
+ * synchronises it once more to pick that stream (a ~0.4 ms probe: the
+ * handle's stream must run beside `stream`, not behind it on one hardware
+ * queue). */
 int gpma_apply_batches(gpma_t *h, uint32_t count, const uint8_t *ops, const uint64_t *const *keys_dev,
                        const uint64_t *sizes, hipStream_t stream, gpma_stats *total,
                        uint32_t *completed);
