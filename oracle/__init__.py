@@ -51,7 +51,7 @@ def _load():
     pu64, pi32 = C.POINTER(u64), C.POINTER(i32)
     lib.orc_create.restype = C.c_void_p
     lib.orc_create.argtypes = [u32, pu64, u64, u32, u32, u32, u32, u32, C.POINTER(C.c_int)]
-    lib.orc_set_lazy.restype = None
+    lib.orc_set_lazy.restype = C.c_int
     lib.orc_set_lazy.argtypes = [C.c_void_p, C.c_int]
     lib.orc_from_slots.restype = C.c_void_p
     lib.orc_from_slots.argtypes = [pu64, u64, u32, u32, u32, u32, u32, C.POINTER(C.c_int)]
@@ -67,6 +67,10 @@ def _load():
     lib.orc_log_levels.argtypes = [C.c_void_p]
     lib.orc_log_segs.restype = pu64
     lib.orc_log_segs.argtypes = [C.c_void_p]
+    lib.orc_log_counts.restype = pu64
+    lib.orc_log_counts.argtypes = [C.c_void_p]
+    lib.orc_log_updates.restype = pu64
+    lib.orc_log_updates.argtypes = [C.c_void_p]
     lib.orc_insert.restype = C.c_int
     lib.orc_insert.argtypes = [C.c_void_p, pu64, u64]
     lib.orc_delete.restype = C.c_int
@@ -123,8 +127,8 @@ class OraclePMA:
         if not h:
             raise OracleError("orc_create failed (%d)" % err.value)
         self._h = h
-        if lazy:
-            self._lib.orc_set_lazy(h, 1)
+        if lazy and self._lib.orc_set_lazy(h, 1) != 0:
+            raise OracleError("lazy deletion needs 1 <= V <= 2^31")
 
     @classmethod
     def from_slots(cls, slots, leaf_size: int, tau_leaf=920, tau_root=800,
@@ -168,6 +172,17 @@ class OraclePMA:
         lv = np.ctypeslib.as_array(self._lib.orc_log_levels(self._h), shape=(n,))
         sg = np.ctypeslib.as_array(self._lib.orc_log_segs(self._h), shape=(n,))
         return [(int(a), int(b)) for a, b in zip(lv, sg)]
+
+    def merge_log_counts(self):
+        """Per merge-log entry: (live entries of the segment before the
+        merge, updates merged into it); for a root rebuild, (entries of the
+        whole array, updates left at the root)."""
+        n = int(self._lib.orc_log_len(self._h))
+        if n == 0:
+            return []
+        ns = np.ctypeslib.as_array(self._lib.orc_log_counts(self._h), shape=(n,))
+        k = np.ctypeslib.as_array(self._lib.orc_log_updates(self._h), shape=(n,))
+        return [(int(a), int(b)) for a, b in zip(ns, k)]
 
     def last_applied(self) -> int:
         return int(self._lib.orc_last_applied(self._h))

@@ -42,7 +42,11 @@
  *   - the root is tried like any other segment; when it fails, an insert
  *     doubles the capacity until the bound holds and a delete halves it while
  *     the lower bound fails (never below one leaf, never above the upper
- *     bound of the halved array); every entry is then re-dispatched.
+ *     bound of the halved array); every entry is then re-dispatched;
+ *   - edge mode takes 1 <= V <= 2^31 (the V guards must fit the GPU
+ *     library's 2^31-slot array); raw-key mode (V = 0) stores any key but
+ *     the empty one, and lazy deletion, which takes bit 63 of a key for its
+ *     mark, is refused there.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -51,9 +55,11 @@
 #define ORC_EMPTY UINT64_MAX
 #define ORC_GUARD_DST 0xFFFFFFFFull
 /* lazy deletion (Section 6, the GPMA/GPMA+ setup of the experiments): a
- * deleted entry stays in its slot, marked; keys have src < 2^31, so bit 63
- * is free for the mark and the masked key keeps the array order */
+ * deleted entry stays in its slot, marked; lazy mode needs src < 2^31 for
+ * every key, so bit 63 is free for the mark and the masked key keeps the
+ * array order.  Outside lazy mode bit 63 is an ordinary key bit. */
 #define ORC_TOMB (1ull << 63)
+#define ORC_MAX_V (1u << 31)
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
 
@@ -64,11 +70,12 @@ typedef struct {
     uint64_t cap;  /* slots */
     uint64_t n;    /* stored entries, guards included */
     uint64_t *slots;
-    /* merge log of the last batch: (level, segment); a root rebuild is logged
-       as level -1 with the new capacity in place of the segment */
+    /* merge log of the last batch: (level, segment, live entries of the
+       segment before the merge, updates merged into it); a root rebuild is
+       logged as level -1 with the new capacity in place of the segment */
     uint64_t log_len, log_cap;
     int32_t *log_level;
-    uint64_t *log_seg;
+    uint64_t *log_seg, *log_ns, *log_k;
     uint64_t applied, noops;
     int lazy;      /* deletions mark entries instead of merging */
 } orc_pma;
@@ -119,7 +126,16 @@ static uint32_t log2_u64(uint64_t x)
 
 static int is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
-static int is_live(uint64_t k) { return k != ORC_EMPTY && !(k & ORC_TOMB); }
+/* an occupied slot that holds a live key (in lazy mode a marked entry is
+ * free space); mark_free() is the key with the mark cleared */
+static int is_live(const orc_pma *p, uint64_t k)
+{
+    return k != ORC_EMPTY && !(p->lazy && (k & ORC_TOMB));
+}
+static uint64_t mark_free(const orc_pma *p, uint64_t k)
+{
+    return p->lazy ? (k & ~ORC_TOMB) : k;
+}
 
 /* ------------------------------------------------------------------------ */
 /* density bounds (Section 4.1, figure "PMA insertion example")             */
@@ -194,11 +210,11 @@ static void dispatch(uint64_t *slots, uint64_t base, uint32_t lf, uint64_t P,
 
 /* the live entries of slots [base, base+len) in array order (a merge drops
  * the marks of lazily deleted entries: their slots are recycled) */
-static uint64_t gather(const uint64_t *slots, uint64_t base, uint64_t len, uint64_t *out)
+static uint64_t gather(const orc_pma *p, uint64_t base, uint64_t len, uint64_t *out)
 {
     uint64_t m = 0;
     for (uint64_t i = 0; i < len; i++)
-        if (is_live(slots[base + i])) out[m++] = slots[base + i];
+        if (is_live(p, p->slots[base + i])) out[m++] = p->slots[base + i];
     return m;
 }
 
@@ -224,16 +240,20 @@ static uint64_t merge_minus(const uint64_t *a, uint64_t na, const uint64_t *b,
     return m;
 }
 
-static void log_push(orc_pma *p, int32_t level, uint64_t seg)
+static void log_push(orc_pma *p, int32_t level, uint64_t seg, uint64_t ns, uint64_t k)
 {
     if (p->log_len == p->log_cap) {
         uint64_t nc = p->log_cap ? 2 * p->log_cap : 64;
         p->log_level = (int32_t *)realloc(p->log_level, nc * sizeof(int32_t));
         p->log_seg = (uint64_t *)realloc(p->log_seg, nc * sizeof(uint64_t));
+        p->log_ns = (uint64_t *)realloc(p->log_ns, nc * sizeof(uint64_t));
+        p->log_k = (uint64_t *)realloc(p->log_k, nc * sizeof(uint64_t));
         p->log_cap = nc;
     }
     p->log_level[p->log_len] = level;
     p->log_seg[p->log_len] = seg;
+    p->log_ns[p->log_len] = ns;
+    p->log_k[p->log_len] = k;
     p->log_len++;
 }
 
@@ -266,7 +286,8 @@ orc_pma *orc_create(uint32_t V, const uint64_t *keys, uint64_t n,
     *err = ORC_EINVAL;
     if (!params_ok(lf, tau_leaf, tau_root, rho_leaf, rho_root)) return NULL;
     if (V) {
-        if (V == UINT32_MAX) return NULL;
+        /* the GPU library's domain: V guards must fit a 2^31-slot array */
+        if (V > ORC_MAX_V) return NULL;
         for (uint64_t i = 0; i < n; i++)
             if (!key_ok(V, keys[i])) return NULL;
     }
@@ -326,7 +347,8 @@ orc_pma *orc_from_slots(const uint64_t *slots, uint64_t cap, uint32_t lf,
 void orc_free(orc_pma *p)
 {
     if (!p) return;
-    free(p->slots); free(p->log_level); free(p->log_seg); free(p);
+    free(p->slots); free(p->log_level); free(p->log_seg);
+    free(p->log_ns); free(p->log_k); free(p);
 }
 
 uint64_t orc_capacity(const orc_pma *p) { return p->cap; }
@@ -336,9 +358,18 @@ const uint64_t *orc_slots(const orc_pma *p) { return p->slots; }
 uint64_t orc_log_len(const orc_pma *p) { return p->log_len; }
 const int32_t *orc_log_levels(const orc_pma *p) { return p->log_level; }
 const uint64_t *orc_log_segs(const orc_pma *p) { return p->log_seg; }
+const uint64_t *orc_log_counts(const orc_pma *p) { return p->log_ns; }
+const uint64_t *orc_log_updates(const orc_pma *p) { return p->log_k; }
 uint64_t orc_last_applied(const orc_pma *p) { return p->applied; }
 uint64_t orc_last_noops(const orc_pma *p) { return p->noops; }
-void orc_set_lazy(orc_pma *p, int lazy) { p->lazy = lazy ? 1 : 0; }
+/* Lazy mode takes bit 63 of a key for the mark, so it refuses an array
+ * that may hold keys with that bit set: raw-key mode (V = 0) or V > 2^31. */
+int orc_set_lazy(orc_pma *p, int lazy)
+{
+    if (lazy && (p->V == 0 || p->V > ORC_MAX_V)) return ORC_EINVAL;
+    p->lazy = lazy ? 1 : 0;
+    return ORC_OK;
+}
 
 /* ------------------------------------------------------------------------ */
 /* the batched update (Section 5.2, Algorithm GPMA+ Segment-Oriented
@@ -358,18 +389,18 @@ static int try_segment(orc_pma *p, uint32_t H, uint32_t h, uint64_t s,
     /* CountSegment: live entries (marked ones are free space) */
     uint64_t ns = 0;
     for (uint64_t i = 0; i < cap_h; i++)
-        if (is_live(p->slots[base + i])) ns++;
+        if (is_live(p, p->slots[base + i])) ns++;
 
     if (!del) {
         if (ns + k > mx) return 0;
     } else {
         if (ns < k + mn) return 0;   /* ns - k < mn */
     }
-    uint64_t ne = gather(p->slots, base, cap_h, bufE);
+    uint64_t ne = gather(p, base, cap_h, bufE);
     uint64_t N = del ? merge_minus(bufE, ne, u, k, bufM)
                      : merge_union(bufE, ne, u, k, bufM);
     dispatch(p->slots, base, p->lf, (uint64_t)1 << h, bufM, N);
-    log_push(p, (int32_t)h, s);
+    log_push(p, (int32_t)h, s, ns, k);
     p->n = p->n - ne + N;
     return 1;
 }
@@ -402,8 +433,8 @@ static int apply_batch(orc_pma *p, const uint64_t *keys, uint64_t b, int del)
     for (uint64_t i = 0; i < p->cap; i++) {
         const uint64_t k = p->slots[i];
         if (k == ORC_EMPTY) continue;
-        ok[no] = k & ~ORC_TOMB; el[no] = i / p->lf; ep[no] = i; no++;
-        if (is_live(k)) ek[ne++] = k;
+        ok[no] = mark_free(p, k); el[no] = i / p->lf; ep[no] = i; no++;
+        if (is_live(p, k)) ek[ne++] = k;
     }
 
     /* drop no-ops: inserting a live key, deleting a key that is not live */
@@ -474,7 +505,7 @@ static int apply_batch(orc_pma *p, const uint64_t *keys, uint64_t b, int del)
                    left <= root_max(p, ncap / 2))
                 ncap /= 2;
         }
-        uint64_t nall = gather(p->slots, 0, p->cap, bufE);
+        uint64_t nall = gather(p, 0, p->cap, bufE);
         uint64_t *M = (uint64_t *)malloc((nall + r + 1) * sizeof(uint64_t));
         uint64_t N = del ? merge_minus(bufE, nall, U, r, M)
                          : merge_union(bufE, nall, U, r, M);
@@ -484,7 +515,7 @@ static int apply_batch(orc_pma *p, const uint64_t *keys, uint64_t b, int del)
         p->slots = ns;
         p->cap = ncap;
         p->n = N;
-        log_push(p, -1, ncap);
+        log_push(p, -1, ncap, nall, r);
         free(M);
     }
     p->applied = total;

@@ -153,6 +153,115 @@ def test_example3_under_a_successor_leaf_rule_would_differ():
     assert p.merge_log() == [(0, 0)]
 
 
+def test_delete_dual_bounds_at_equality_and_uneven_split():
+    """Deletions (the dual of insertions, Section 4.1): a failed leaf hands
+    its deletions to its parent, a segment passes when the live count after
+    the deletions still reaches min_h (three segments pass exactly at their
+    bound), and an odd count is re-dispatched floor-evenly."""
+    g = golden("delete_dual_uneven.json")
+    lf = g["leaf_size"]
+    mn, _ = O.level_bounds(lf, 3)
+    assert [int(x) for x in mn] == g["min_entries"]
+    p = O.OraclePMA.from_slots(slots_from_json(g["slots"]), lf)
+    p.delete(np.array(g["delete"], dtype=np.uint64))
+    assert [list(m) for m in p.merge_log()] == g["expected_merges"]
+    assert np.array_equal(p.slots(), slots_from_json(g["expected_slots"]))
+    assert p.last_applied() == len(g["delete"])
+
+
+def test_insert_bound_at_equality_and_uneven_split():
+    g = golden("insert_uneven_dispatch.json")
+    lf = g["leaf_size"]
+    _, mx = O.level_bounds(lf, 3)
+    assert [int(x) for x in mx] == g["max_entries"]
+    p = O.OraclePMA.from_slots(slots_from_json(g["slots"]), lf)
+    p.insert(np.array(g["insert"], dtype=np.uint64))
+    assert [list(m) for m in p.merge_log()] == g["expected_merges"]
+    assert np.array_equal(p.slots(), slots_from_json(g["expected_slots"]))
+
+
+def test_even_dispatch_counts_closed_form():
+    """Bulk load spreads n entries over the L leaves of the array: leaf j
+    holds floor((j+1)n/L) - floor(jn/L) of them, in key order, packed at the
+    front (the reading of "re-dispatch evenly"), for every n up to a few
+    arrays' worth, including the uneven ones."""
+    lf = 4
+    for n in range(1, 200):
+        keys = np.arange(3, 3 + 7 * n, 7, dtype=np.uint64)
+        p = O.OraclePMA(0, keys, lf)
+        s = p.slots()
+        L = s.size // lf
+        want = [(j + 1) * n // L - j * n // L for j in range(L)]
+        assert list(O.leaf_counts(s, lf)) == want, n
+        assert np.array_equal(O.stored(s), keys)
+        O.check_invariants(s, lf, allow_empty_leaves=True)
+
+
+def test_eager_mode_keeps_keys_with_the_top_bit():
+    """Bit 63 marks a lazily deleted entry only in lazy mode; an eager array
+    of raw keys stores, merges and deletes keys >= 2^63 like any other, and
+    lazy mode refuses an array whose keys may use that bit."""
+    lf = 4
+    top = 1 << 63
+    init = [top + 5 * i for i in range(20)] + list(range(0, 40, 4))
+    p = O.OraclePMA(0, np.array(init, dtype=np.uint64), lf)
+    ref = set(init)
+    rng = np.random.default_rng(11)
+    for t in range(30):
+        ks = [int(x) | (top if rng.random() < 0.5 else 0) for x in rng.integers(0, 200, 9)]
+        if t % 2:
+            p.insert(np.array(ks, dtype=np.uint64))
+            ref |= set(ks)
+        else:
+            p.delete(np.array(ks + sorted(ref)[::5], dtype=np.uint64))
+            ref -= set(ks + sorted(ref)[::5])
+        s = p.slots()
+        assert [int(x) for x in s[s != O.EMPTY]] == sorted(ref)
+    with pytest.raises(O.OracleError):
+        O.OraclePMA(0, np.array(init, dtype=np.uint64), lf, lazy=True)
+    with pytest.raises(O.OracleError):
+        O.OraclePMA((1 << 31) + 1, np.array([], dtype=np.uint64), 16)
+
+
+def _frac_bounds(lf, H, h, pm=O.DEFAULT_PM):
+    """rho_h * cap_h and tau_h * cap_h as exact fractions (linear in the
+    height between the figure's leaf and root values; one leaf = the root)."""
+    cap = Fraction(lf << h)
+    if H == 0:
+        return Fraction(pm["rho_root"], 1000) * cap, Fraction(pm["tau_root"], 1000) * cap
+    rho = (Fraction(pm["rho_leaf"]) * (H - h) + Fraction(pm["rho_root"]) * h) / (1000 * H)
+    tau = (Fraction(pm["tau_leaf"]) * (H - h) + Fraction(pm["tau_root"]) * h) / (1000 * H)
+    return rho * cap, tau * cap
+
+
+def assert_merge_log(p, lf, cap_before, delete):
+    """Invariants (vi) and (vii) of a batch, from the oracle's merge log and
+    exact fractions: every segment merged at height h met its bound at merge
+    time (insert: (n_s+k)/cap_h < tau_h; delete: (n_s-k)/cap_h > rho_h); a
+    root rebuild leaves n' < tau_root * cap' at the capacity the resize rule
+    picks (a grown root is the smallest power of two that holds n'; a shrunk
+    root stops halving once n' clears rho_root or the half would overflow)."""
+    H = int(np.log2(cap_before // lf))
+    for (lvl, seg), (ns, k) in zip(p.merge_log(), p.merge_log_counts()):
+        if lvl >= 0:
+            assert seg < (cap_before // lf) >> lvl
+            rho_c, tau_c = _frac_bounds(lf, H, lvl)
+            if delete:
+                assert ns - k > rho_c, (lvl, seg, ns, k)
+            else:
+                assert ns + k < tau_c, (lvl, seg, ns, k)
+        else:
+            ncap = seg
+            n2 = ns - k if delete else ns + k
+            Hn = int(np.log2(ncap // lf))
+            rho_c, tau_c = _frac_bounds(lf, Hn, Hn)
+            assert n2 < tau_c
+            if ncap > cap_before:
+                assert n2 >= _frac_bounds(lf, Hn - 1, Hn - 1)[1]
+            elif ncap < cap_before and ncap > lf:
+                assert n2 > rho_c or n2 >= _frac_bounds(lf, Hn - 1, Hn - 1)[1]
+
+
 # --------------------------------------------------------------------------
 # set semantics by brute force, invariants after every batch
 
@@ -194,16 +303,19 @@ def test_random_batches_vs_set(seed, V, lf):
     _check(p, ref, V, lf)
     for t in range(40):
         b = int(rng.integers(1, 4 * V))
+        cap0 = p.capacity
         if rng.random() < 0.5:
             ins = rnd(b)
             p.insert(np.array(ins, dtype=np.uint64))
             ref |= set(ins)
+            assert_merge_log(p, lf, cap0, False)
         else:
             pool = sorted(ref)
             dl = [pool[i] for i in rng.integers(0, len(pool), b)] if pool else []
             dl += rnd(b // 4)     # some absent keys: no-ops
             p.delete(np.array(dl, dtype=np.uint64))
             ref -= set(dl)
+            assert_merge_log(p, lf, cap0, True)
         _check(p, ref, V, lf)
 
 
@@ -216,9 +328,11 @@ def test_growth_and_shrink_resize_rules():
     rng = np.random.default_rng(7)
     rng.shuffle(allk)
     for i in range(0, len(allk), 23):
+        cap0 = p.capacity
         p.insert(np.array(allk[i:i + 23], dtype=np.uint64))
         ref |= set(allk[i:i + 23])
         _check(p, ref, V, lf)
+        assert_merge_log(p, lf, cap0, False)
         caps.append(p.capacity)
         for lvl, seg in p.merge_log():
             if lvl < 0:    # a root rebuild: the new capacity is the smallest that fits
@@ -229,9 +343,11 @@ def test_growth_and_shrink_resize_rules():
                     assert p.size > int(mx2[-1])
     assert caps == sorted(caps) and caps[-1] > caps[0]
     for i in range(0, len(allk), 31):
+        cap0 = p.capacity
         p.delete(np.array(allk[i:i + 31], dtype=np.uint64))
         ref -= set(allk[i:i + 31])
         _check(p, ref, V, lf)
+        assert_merge_log(p, lf, cap0, True)
         for lvl, seg in p.merge_log():
             if lvl < 0 and seg > lf:
                 mn, mx = O.level_bounds(lf, int(np.log2(seg // lf)))
