@@ -115,6 +115,51 @@ def cpu_baseline(batch: int, slides: int, scale: int = 20):
     }
 
 
+def sweep_slides(z: int) -> int:
+    """Slides per batch size in the latency sweep (one of them a warm-up)."""
+    return 11 if z <= (1 << 16) else (5 if z <= (1 << 18) else 4)
+
+
+def spmv_forms_section(args, g, st, V, kernels):
+    """PageRank's SpMV in both binned forms on the headline graph: the
+    headline handle's own form (timed in the steps) and the other one on a
+    handle of the initial window (no mirror).  Per form: mean SpMV time over
+    the iterations of two 10-iteration calls, algorithmic GB/s, and the
+    whole call's time (the per-call binning included)."""
+    import torch
+
+    from paper_1709_05061_amd import GPMA
+    from paper_1709_05061_amd import gpma as G
+    own = "binned" if args.spmv in ("auto", "binned") else args.spmv
+    out = {own: {"spmv_mean_us": kernels["spmv"]["mean_us"], "GBps": kernels["spmv"]["GBps"],
+                 "source": "headline steps"}} if "spmv" in kernels else {}
+    for form in ("binned", "binned_gather"):
+        if form in out:
+            continue
+        h = GPMA(V, st.initial(), spmv=form)
+        x = torch.full((V,), 1.0 / V, dtype=torch.float32, device="cuda")
+        h.pagerank(init=x, iters=args.pr_iters, out=x)
+        torch.cuda.synchronize()
+        h.profile_reset()
+        h.profile(True)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for _ in range(2):
+            h.pagerank(init=x, iters=args.pr_iters, out=x)
+        t1.record()
+        torch.cuda.synchronize()
+        h.profile(False)
+        ms, n, by = h.profile_read(G.K_SPMV)
+        out[form] = {"spmv_mean_us": 1e3 * ms / n, "GBps": by / (ms / 1e3) / 1e9,
+                     "pagerank_call_ms": t0.elapsed_time(t1) / 2, "source": "initial window, no mirror"}
+        log("SpMV form %s: %s" % (form, out[form]))
+        h.close()
+        del h
+        torch.cuda.empty_cache()
+    return out
+
+
 def uneven_section(args):
     """The fused-batching workload: a power-law social graph (1.6M vertices,
     30M edges, out-degree exponent 2.1), window = first half, then `n` slides
@@ -298,6 +343,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-slides", type=int, default=64)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--sweep", default="1,16,256,1024,4096,16384,65536,262144,1048576",
+                    help="batch sizes of the latency sweep (fused + learned, fused + binary search, plain)")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--spmv", default="auto", help="SpMV form of the headline handle (a key of SPMV_FORMS)")
+    ap.add_argument("--no-spmv-forms", action="store_true", help="skip timing the other binned SpMV form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 launches), the known-size reference "
                          "for hardware byte counters, and exit")
@@ -327,7 +377,8 @@ def main():
                                                "launches": 4}}))
         return
     b = args.batch
-    need = (args.warmup + args.steps) * b
+    sweep = [] if args.no_sweep else [int(x) for x in args.sweep.split(",")]
+    need = (args.warmup + args.steps) * b + sum(sweep_slides(z) * z for z in sweep)
     t0 = time.time()
     extra = max(4 * need, 1 << 22)
     while True:
@@ -344,7 +395,8 @@ def main():
     t0 = time.time()
     learned = not args.no_learned
     g = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror, learned=learned,
-             fused_direct=bool(args.fused_direct), sort_tile=args.sort_tile, fused_levels=args.fused_levels)
+             fused_direct=bool(args.fused_direct), sort_tile=args.sort_tile, fused_levels=args.fused_levels,
+             spmv=args.spmv)
     torch.cuda.synchronize()
     log("created PMA: %d edges, capacity %d slots, leaf %d in %.1fs"
         % (g.num_edges, g.capacity, g.leaf_size, time.time() - t0))
@@ -355,14 +407,24 @@ def main():
         e.record(stream)
         return e
 
-    def update(h, t, fused):
-        d, i = st.slide(t, b)
+    def update(h, t, fused, bsz=None, t0=0):
+        """One slide; returns (applied, resizes, algorithmic bytes): per
+        handle 8 B per batch key plus, per merged segment, 16 B per slot and
+        10 B per leaf (read and written slots, leaf counts), over the array
+        and its mirror."""
+        d, i = st.slide(t, b) if bsz is None else (st.order[t0:t0 + bsz],
+                                                  st.order[st.window + t0: st.window + t0 + bsz])
+        per_slot = 16.0 + 10.0 / h.leaf_size
+        nh = 2 if h.mirror() is not None else 1
         if fused:
             s = h.apply_batches([1, 0], [d, i])
-            return s.applied, int(s.resized)
+            by = nh * 8.0 * (d.numel() + i.numel()) + per_slot * (s.slots_rewritten + s.mirror_slots_rewritten)
+            return s.applied, int(s.resized), by
         sd = h.delete(d, stats=True)
         si = h.insert(i, stats=True)
-        return sd.applied + si.applied, int(sd.resized) + int(si.resized)
+        rw = sd.slots_rewritten + sd.mirror_slots_rewritten + si.slots_rewritten + si.mirror_slots_rewritten
+        by = nh * 8.0 * (d.numel() + i.numel()) + per_slot * rw
+        return sd.applied + si.applied, int(sd.resized) + int(si.resized), by
 
     # the other update path on a second handle, same slides: throughput and
     # identical output
@@ -377,7 +439,7 @@ def main():
         n_o = 0
         for t in range(args.warmup, args.warmup + args.steps):
             e0 = ev()
-            a, _ = update(other, t, not fused_mode)
+            a, _, _ = update(other, t, not fused_mode)
             e1 = ev()
             n_o += a
             ms.append((e0, e1))
@@ -398,7 +460,7 @@ def main():
         n_z = 0
         for t in range(args.warmup, args.warmup + args.steps):
             e0 = ev()
-            a, _ = update(h, t, fused_mode)
+            a, _, _ = update(h, t, fused_mode)
             e1 = ev()
             n_z += a
             ms.append((e0, e1))
@@ -480,9 +542,9 @@ def main():
 
     def step(t):
         e0 = ev()
-        a, r = update(g, t, fused_mode)
+        a, r, by = update(g, t, fused_mode)
         e1 = ev()
-        marks = [e0, e1]
+        marks = [e0, e1, by]
         if not args.no_analytics:
             g.pagerank(init=x, iters=args.pr_iters, out=x)
             marks.append(ev())
@@ -495,6 +557,7 @@ def main():
     for t in range(args.warmup):
         step(t)
     torch.cuda.synchronize()
+    loc0 = g.locator_info() if learned else None
     g.profile_reset()
     g.profile(True)
     recs = []
@@ -512,12 +575,67 @@ def main():
     g.profile(False)
 
     upd_ms = [m[0].elapsed_time(m[1]) for m in recs]
+    upd_bytes = sum(m[2] for m in recs)
     phases = {"update": sum(upd_ms) / len(recs)}
     if not args.no_analytics:
-        phases["pagerank"] = sum(m[1].elapsed_time(m[2]) for m in recs) / len(recs)
-        phases["bfs"] = sum(m[2].elapsed_time(m[3]) for m in recs) / len(recs)
-        phases["cc"] = sum(m[3].elapsed_time(m[4]) for m in recs) / len(recs)
+        phases["pagerank"] = sum(m[1].elapsed_time(m[3]) for m in recs) / len(recs)
+        phases["bfs"] = sum(m[3].elapsed_time(m[4]) for m in recs) / len(recs)
+        phases["cc"] = sum(m[4].elapsed_time(m[5]) for m in recs) / len(recs)
     updates_per_s = applied / (sum(upd_ms) / 1e3)
+    upd_gbps = upd_bytes / (sum(upd_ms) / 1e3) / 1e9
+    roofline_update = {"bound": "hbm", "achieved": upd_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                       "frac": upd_gbps / HBM_PEAK_GBPS, "traffic": None,
+                       "bytes_per_slide": upd_bytes / len(recs),
+                       "note": "whole update phase (every kernel of a slide, array and mirror) against "
+                               "8 B per batch key + (16 + 10/leaf) B per slot of every merged segment"}
+    loc_timed = None
+    if learned:
+        loc1 = g.locator_info()
+        loc_timed = {"fits": loc1["fits"] - loc0["fits"], "lookups": loc1["lookups"] - loc0["lookups"],
+                     "misses": loc1["misses"] - loc0["misses"], "eps": loc1["eps"]}
+
+    # latency against batch size (the paper's update experiment, Section 6.2):
+    # the same slides on the headline handle (fused + learned locator), on a
+    # fused handle with binary-search locate and on the plain handle
+    sweep_out = None
+    if sweep and other is not None and fused_mode:
+        log("batch-size sweep %s" % sweep)
+        fb = GPMA(V, st.initial(), leaf_size=args.leaf_size, mirror=mirror, learned=False,
+                  fused_direct=bool(args.fused_direct), sort_tile=args.sort_tile, fused_levels=args.fused_levels)
+        for t in range(args.warmup + args.steps):   # catch up with the headline handle
+            update(fb, t, True)
+        paths = {"fused_learned": (g, True), "fused_binary": (fb, True), "plain": (other, False)}
+        sweep_out = {"sizes": sweep, "slides": [], **{k: {"ms_per_slide": [], "updates_per_s": []} for k in paths}}
+        t0 = (args.warmup + args.steps) * b
+        for z in sweep:
+            k = sweep_slides(z)
+            for name, (h, fz) in paths.items():
+                update(h, 0, fz, bsz=z, t0=t0)            # warm-up slide: graphs for this size class
+                marks, n = [], 0
+                for j in range(1, k):
+                    e0 = ev()
+                    a, _, _ = update(h, 0, fz, bsz=z, t0=t0 + j * z)
+                    e1 = ev()
+                    n += a
+                    marks.append((e0, e1))
+                torch.cuda.synchronize()
+                ms = sum(x.elapsed_time(y) for x, y in marks) / len(marks)
+                sweep_out[name]["ms_per_slide"].append(ms)
+                sweep_out[name]["updates_per_s"].append(n / len(marks) / (ms / 1e3))
+            sweep_out["slides"].append(k - 1)
+            log("b=%d: %s" % (z, {name: "%.3f ms" % sweep_out[name]["ms_per_slide"][-1] for name in paths}))
+            t0 += k * z
+        sweep_out["learned_over_binary"] = [a / c for a, c in zip(sweep_out["fused_learned"]["updates_per_s"],
+                                                                   sweep_out["fused_binary"]["updates_per_s"])]
+        sweep_out["fused_over_plain"] = [a / c for a, c in zip(sweep_out["fused_learned"]["updates_per_s"],
+                                                                sweep_out["plain"]["updates_per_s"])]
+        sweep_out["identical_output"] = bool(torch.equal(g.slots(), fb.slots()) and torch.equal(g.slots(),
+                                                                                                other.slots()))
+        if learned:
+            sweep_out["locator"] = g.locator_info()
+        fb.close()
+        del fb
+        torch.cuda.empty_cache()
 
     identical = None
     if other is not None:
@@ -579,9 +697,14 @@ def main():
         "spmv_frac": (spmv["GBps"] / HBM_PEAK_GBPS) if spmv and spmv["GBps"] else None,
         "kernels": kernels,
         "roofline": roofline,
+        "roofline_update": roofline_update,
+        "batch_sweep": sweep_out,
     }
     if learned:
         out["locator"] = g.locator_info()
+        out["locator_timed_steps"] = loc_timed
+    if not args.no_spmv_forms:
+        out["spmv_forms"] = spmv_forms_section(args, g, st, V, kernels)
     g.close()
     del st
     torch.cuda.empty_cache()

@@ -24,14 +24,15 @@
  *     BFS levels and the CC component pick also read small counters back).
  *   - A handle must be used by one host thread at a time; handles are
  *     independent.  Return value 0 = GPMA_OK, negative = error.
+ *   - Device memory comes from the allocator given to gpma_create (hipMalloc
+ *     and hipFree when none is given).  The library hands a block back only
+ *     after the device has finished the library's work on it.
  *   - Errors: GPMA_EINVAL changes nothing (an invalid key makes its whole
- *     batch a no-op).  GPMA_ENOMEM from an update that needed a resize
- *     leaves the updates already merged below the root applied and the rest
- *     of the batch not; the handle remains a valid PMA of the edges it then
- *     holds (gpma_num_edges, exports); with a mirror (GPMA_FLAG_MIRROR) the
- *     two arrays may then hold different edge sets, so destroy the handle.
- *     GPMA_ENOMEM from any other call changes nothing.  After GPMA_EDEVICE the handle's contents are
- *     undefined: destroy it.
+ *     batch a no-op).  GPMA_ENOMEM changes nothing either: an update call
+ *     reserves everything it may need (batch scratch, the merge workspace of
+ *     the upper levels and the root, and the arrays of a root resize when
+ *     one is possible) on the array and its mirror before either changes.
+ *     After GPMA_EDEVICE the handle's contents are undefined: destroy it.
  */
 #ifndef GPMA_H
 #define GPMA_H
@@ -81,7 +82,41 @@ typedef struct {
                                  handing updates still pending to the
                                  host-driven path, 0..3 (default 1); a tuning
                                  knob, results identical */
+    uint32_t lds_tier_bytes;  /* LDS bytes a workgroup of the segment tier may
+                                 use (0 = all the device grants, 160 KiB on
+                                 gfx950); a smaller cap hands smaller
+                                 segments to the host-driven device tier,
+                                 results identical */
+    uint32_t spmv_form;       /* PageRank's SpMV, GPMA_SPMV_* below */
 } gpma_params;
+
+/* The SpMV of gpma_pagerank.  AUTO: destination bins while V <= 2^26, else
+ * pull over the mirror when there is one, else push.  BINNED and
+ * BINNED_COARSE (the bins filled through 64 coarse bins first) write the
+ * contributions into destination bins every iteration; BINNED_GATHER bins
+ * the edges once per call (each record names its source) and every
+ * iteration fetches the sources' contributions.  The binned forms need
+ * V <= 2^26, PULL needs GPMA_FLAG_MIRROR (else gpma_create returns
+ * GPMA_EINVAL).  The forms agree within the fp32 rounding of the result. */
+enum {
+    GPMA_SPMV_AUTO = 0,
+    GPMA_SPMV_BINNED = 1,
+    GPMA_SPMV_BINNED_COARSE = 2,
+    GPMA_SPMV_PULL = 3,
+    GPMA_SPMV_PUSH = 4,
+    GPMA_SPMV_BINNED_GATHER = 5,
+};
+
+/* Device memory provider.  alloc returns `bytes` of device memory of the
+ * current device for use on `stream` (the stream of the call that needs it),
+ * or NULL when it cannot; free takes back a block with the size it was
+ * allocated with.  ctx is passed through.  The torch binding passes the
+ * caching allocator of PyTorch. */
+typedef struct {
+    void *(*alloc)(size_t bytes, hipStream_t stream, void *ctx);
+    void (*free)(void *ptr, size_t bytes, hipStream_t stream, void *ctx);
+    void *ctx;
+} gpma_allocator;
 
 /* Keep a second, dst-major PMA (keys dst<<32 | src, one guard per vertex)
  * updated by the same GPMA+ batches.  It holds every vertex's in-edges as a
@@ -98,8 +133,8 @@ typedef struct {
  * corrects it, checked against the window's bracketing pivots, with a binary
  * search over the span as fallback, so the leaf (and every later result) is
  * identical to the binary-search locate of Algorithm "GPMA+ Segment-Oriented
- * Insertion".  Refitted after every rebuild of the array, every 64 batches,
- * or when more than 1/16 of a batch's lookups fall back.  A design addition. */
+ * Insertion".  Refitted after every rebuild or resize of the array, and when
+ * more than 1/16 of a call's lookups fall back.  A design addition. */
 #define GPMA_FLAG_LEARNED_LOCATOR 2u
 
 /* gpma_apply_batches enqueues each batch's kernels on the stream directly
@@ -121,6 +156,11 @@ typedef struct {
  * uint32 per leaf. */
 #define GPMA_FLAG_LAZY_DELETE 8u
 
+/* gpma_apply_batches with a mirror: run both pipelines on streams of the
+ * handle, forked from and joined to the caller's stream, instead of keeping
+ * the array's on the caller's stream (a test knob; results identical). */
+#define GPMA_FLAG_FUSED_LIB_STREAMS 16u
+
 /* Per-batch statistics; filled when a non-NULL pointer is passed. */
 typedef struct {
     uint64_t requested;      /* keys passed in */
@@ -130,19 +170,26 @@ typedef struct {
     uint32_t resized;        /* 1 when the root was rebuilt at a new capacity */
     uint64_t segments_merged[40];  /* per level */
     uint64_t slots_rewritten;      /* sum of capacities of merged segments */
+    uint64_t mirror_slots_rewritten;  /* the same over the mirror's merges */
 } gpma_stats;
 
 /* Fill *p with the defaults above. */
 void gpma_default_params(gpma_params *p);
 
 /* Build the PMA for `num_vertices` vertices (1 <= V <= 2^31) holding the set
- * of `n` keys at init_keys_dev (unsorted; repeats collapse) plus V guards.
- * Keys need src < V and dst < V.  The capacity is the smallest leaf_size*2^k
- * whose root upper bound admits every entry (at most 2^31 slots); entries
- * are spread evenly over all leaves.  Synchronises with the host once.
- * *out receives the handle (NULL on error). */
+ * of `n` keys at init_keys_dev (unsorted; repeats collapse) plus V guards:
+ * the sliding window's initial graph of the problem statement (Section 3)
+ * laid out as CSR on a PMA (Section 4.2, "CSR as a case study", one guard
+ * per row).  Keys need src < V and dst < V.  The capacity is the smallest
+ * leaf_size*2^k whose root upper bound admits every entry (at most 2^31
+ * slots); entries are spread evenly over all leaves ("re-dispatch evenly",
+ * Section 4.1).  `params` NULL = gpma_default_params; `alloc` NULL =
+ * hipMalloc / hipFree (the allocator is copied, and used for the mirror and
+ * for snapshots too).  Synchronises with the host once.  *out receives the
+ * handle (NULL on error).  GPMA_EINVAL: bad parameters, V out of range, an
+ * invalid key, more than 2^31 slots needed; GPMA_ENOMEM; GPMA_EDEVICE. */
 int gpma_create(gpma_t **out, uint32_t num_vertices, const uint64_t *init_keys_dev,
-                uint64_t n, const gpma_params *params, hipStream_t stream);
+                uint64_t n, const gpma_params *params, const gpma_allocator *alloc, hipStream_t stream);
 
 /* Free every device buffer of the handle (after `stream`-ordered work on it
  * has finished: the call synchronises the device). */
@@ -176,7 +223,9 @@ int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
  * answer to its observation that GPMA+ pays for many kernel calls on small
  * batches.  On an invalid key in batch i, batches before i stay applied,
  * batch i and later are not, and GPMA_EINVAL is returned; *completed (if
- * non-NULL) receives the number of batches applied.  `total` (if non-NULL)
+ * non-NULL) receives the number of batches applied.  Memory for the whole
+ * sequence (its insertions and deletions summed) is reserved before the
+ * first batch runs: GPMA_ENOMEM applies nothing.  `total` (if non-NULL)
  * receives summed statistics (per-level counts are not filled).  With a
  * mirror the mirror's batches run on a stream of the handle, forked from and
  * joined to `stream` by events; the first call on a given `stream`
@@ -186,6 +235,11 @@ int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
 int gpma_apply_batches(gpma_t *h, uint32_t count, const uint8_t *ops, const uint64_t *const *keys_dev,
                        const uint64_t *sizes, hipStream_t stream, gpma_stats *total,
                        uint32_t *completed);
+/* Which arrangement gpma_apply_batches uses with a mirror on caller stream
+ * `stream`: 1 = the array's pipeline on `stream` and the mirror's on a
+ * handle stream that runs beside it, 0 = both on handle streams (forked and
+ * joined), GPMA_EINVAL = no mirror or no fused call on `stream` yet. */
+int gpma_fused_pairing(gpma_t *h, hipStream_t stream);
 
 /* PageRank by power iteration (Section 6.1): exactly `iters` steps of
  *   x'[v] = (1-d)/V + d * ( sum_{u->v} x[u]/outdeg(u) + D/V ),
@@ -257,6 +311,9 @@ gpma_t *gpma_get_mirror(gpma_t *h);
  * number of rounds.  Synchronises with the host once per round. */
 int gpma_lock_insert_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b, hipStream_t stream,
                            gpma_stats *stats, uint32_t *rounds_out);
+
+/* Device bytes the handle (with its mirror) holds from its allocator. */
+uint64_t gpma_allocated_bytes(const gpma_t *h);
 
 /* Introspection.  Counts are those after the last completed call. */
 uint64_t gpma_num_edges(const gpma_t *h);     /* guards excluded */

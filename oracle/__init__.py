@@ -80,6 +80,15 @@ def _load():
     lib.orc_pagerank.argtypes = [u32, pu64, u64, C.POINTER(C.c_double), u32, C.c_double,
                                  C.POINTER(C.c_double)]
     lib.orc_bfs.argtypes = [u32, pu64, u64, u32, pi32]
+    lib.orc_set_create.restype = C.c_void_p
+    lib.orc_set_create.argtypes = [pu64, u64]
+    lib.orc_set_free.argtypes = [C.c_void_p]
+    lib.orc_set_size.restype = u64
+    lib.orc_set_size.argtypes = [C.c_void_p]
+    lib.orc_set_keys.restype = pu64
+    lib.orc_set_keys.argtypes = [C.c_void_p]
+    lib.orc_set_apply.restype = C.c_int64
+    lib.orc_set_apply.argtypes = [C.c_void_p, pu64, u64, C.c_int]
     lib.orc_cc.argtypes = [u32, pu64, u64, C.POINTER(u32)]
     _lib = lib
     return lib
@@ -199,6 +208,45 @@ class OraclePMA:
         k = _keys(keys)
         if self._lib.orc_delete(self._h, _p(k, C.c_uint64), k.size) != 0:
             raise OracleError("invalid key in delete batch")
+
+
+class OracleSet:
+    """The semantic layer: the edge set as a sorted vector of unique keys,
+    batches merged in (union) or out (difference).  No layout; what the PMA
+    must hold after any batch sequence, and a rebuild-style timing
+    baseline (Section 6's CSR updated by rebuilding)."""
+
+    def __init__(self, keys):
+        self._lib = _load()
+        k = _keys(keys)
+        self._h = self._lib.orc_set_create(_p(k, C.c_uint64), k.size)
+        if not self._h:
+            raise OracleError("orc_set_create failed")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._lib.orc_set_free(h)
+            self._h = None
+
+    def _apply(self, keys, delete: bool) -> int:
+        k = _keys(keys)
+        r = int(self._lib.orc_set_apply(self._h, _p(k, C.c_uint64), k.size, 1 if delete else 0))
+        if r < 0:
+            raise OracleError("out of memory")
+        return r
+
+    def insert(self, keys) -> int:
+        return self._apply(keys, False)
+
+    def delete(self, keys) -> int:
+        return self._apply(keys, True)
+
+    def keys(self) -> np.ndarray:
+        n = int(self._lib.orc_set_size(self._h))
+        if n == 0:
+            return np.zeros(0, np.uint64)
+        return np.ctypeslib.as_array(self._lib.orc_set_keys(self._h), shape=(n,)).copy()
 
 
 # --------------------------------------------------------------------------

@@ -609,3 +609,68 @@ void orc_cc(uint32_t V, const uint64_t *edges, uint64_t m, uint32_t *label)
     for (uint32_t v = 0; v < V; v++) label[v] = uf_find(par, v);
     free(par);
 }
+
+/* ------------------------------------------------------------------------ */
+/* the semantic layer: the graph's edge set as one sorted vector of unique
+ * keys, each batch merged in (set union) or out (set difference).  It fixes
+ * what the PMA must hold after any batch sequence, without any layout, and
+ * plays the role of the rebuild-based baselines of Section 6 (CSR updated
+ * by rebuilding; the single-threaded CPU structures) as a timing baseline. */
+
+typedef struct {
+    uint64_t *k;
+    uint64_t n, cap;
+} orc_set;
+
+orc_set *orc_set_create(const uint64_t *keys, uint64_t n)
+{
+    orc_set *s = (orc_set *)calloc(1, sizeof(orc_set));
+    if (!s) return NULL;
+    s->cap = n ? n : 1;
+    s->k = (uint64_t *)malloc(s->cap * sizeof(uint64_t));
+    if (!s->k) { free(s); return NULL; }
+    memcpy(s->k, keys, n * sizeof(uint64_t));
+    s->n = sort_unique(s->k, n);
+    return s;
+}
+
+void orc_set_free(orc_set *s)
+{
+    if (!s) return;
+    free(s->k);
+    free(s);
+}
+
+uint64_t orc_set_size(const orc_set *s) { return s->n; }
+const uint64_t *orc_set_keys(const orc_set *s) { return s->k; }
+
+/* Apply one batch: del = 0 union, 1 difference.  Returns the number of keys
+ * that changed the set, or -1 when memory runs out (set unchanged). */
+int64_t orc_set_apply(orc_set *s, const uint64_t *keys, uint64_t b, int del)
+{
+    uint64_t *U = (uint64_t *)malloc((b ? b : 1) * sizeof(uint64_t));
+    if (!U) return -1;
+    memcpy(U, keys, b * sizeof(uint64_t));
+    uint64_t nu = sort_unique(U, b);
+    uint64_t *out = (uint64_t *)malloc((s->n + nu + 1) * sizeof(uint64_t));
+    if (!out) { free(U); return -1; }
+    uint64_t i = 0, j = 0, m = 0, changed = 0;
+    while (i < s->n || j < nu) {
+        if (j >= nu || (i < s->n && s->k[i] < U[j])) {
+            out[m++] = s->k[i++];
+        } else if (i >= s->n || U[j] < s->k[i]) {
+            if (!del) { out[m++] = U[j]; changed++; }
+            j++;
+        } else {                     /* present in both */
+            if (!del) out[m++] = s->k[i];
+            else changed++;
+            i++; j++;
+        }
+    }
+    free(U);
+    free(s->k);
+    s->k = out;
+    s->n = m;
+    s->cap = s->n + nu + 1;
+    return (int64_t)changed;
+}

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -109,16 +110,17 @@ struct gpma {
     std::vector<GraphEntry> graphs;
     uint32_t geom_version = 1;
     hipStream_t cap_stream = nullptr;
-    // fused batching with a mirror: the mirror's batches run on `pair` (side
-    // or side2, whichever a probe found running beside the caller's stream
-    // `probed`), the array's on the caller's stream.  Two pipelines on one
+    // fused batching with a mirror: the mirror's batches run on side or
+    // side2, whichever a probe found running beside the caller's stream, the
+    // array's on the caller's stream.  Two pipelines on one
     // hardware queue run one after the other, and the runtime may put a
     // library stream on the caller's queue; when neither does better, the
     // array's batches take side and the mirror's side2 (created one after
     // the other, so on different queues).
     hipStream_t side = nullptr, side2 = nullptr;
-    hipStream_t probed = nullptr, pair = nullptr;
-    bool probe_done = false;
+    // probe results: caller stream -> the library stream that runs beside it
+    // (nullptr: neither does); the most recent kProbeMemo callers
+    std::vector<std::pair<hipStream_t, hipStream_t>> probes;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
     uint64_t *kS = nullptr;              // window staging, then the current batch's keys
     FusedState *fs = nullptr;            // device
@@ -164,8 +166,29 @@ struct gpma {
     // lock-based GPMA comparator (allocated on first use, sized to the array)
     uint64_t *lk_scratch = nullptr;   // cap slots
     uint32_t *lk_locks = nullptr;     // 2L epoch words, node (h, s) at (L >> h) + s
-    uint64_t lk_cap = 0;
+    uint64_t lk_cap = 0;              // capacity the lock words were reset for
+    uint64_t lk_buf = 0;              // capacity the two buffers hold
     uint32_t lk_epoch = 0;
+
+    // device memory: the caller's allocator (hipMalloc/hipFree when none),
+    // the stream of the call in progress (handed to the allocator), the size
+    // of every live block and their total
+    gpma_allocator alloc{};
+    hipStream_t astream = nullptr;
+    std::unordered_map<void *, size_t> blocks;
+    uint64_t held_bytes = 0;
+    // arrays for a root resize, reserved before a batch changes anything;
+    // after a resize the old arrays join them until the call ends
+    struct ArrBuf {
+        uint64_t *slots;
+        uint16_t *cnt;
+        uint32_t *dead;
+        uint64_t cap;   // slots the buffer holds (>= the capacity it serves)
+    };
+    std::vector<ArrBuf> pool;
+    uint64_t slots_buf = 0;    // slots the live arrays' buffers hold (>= cap)
+    uint32_t spmv_form = 0;    // GPMA_SPMV_*
+    bool lib_streams = false;  // GPMA_FLAG_FUSED_LIB_STREAMS
 
     Device dev;
     int prof_on = 0;
@@ -178,22 +201,51 @@ struct gpma {
 
 namespace {
 
+// Device memory of a handle, through its allocator (hipMalloc / hipFree
+// when the caller gave none).  The allocator gets the stream of the call in
+// progress; a block goes back to it only after the device has finished every
+// piece of the library's work (hipFree synchronises by itself).
 template <typename T>
-int dev_alloc(T **p, uint64_t count) {
+int dev_alloc(gpma *g, T **p, uint64_t count) {
     *p = nullptr;
     if (count == 0) count = 1;
-    if (hipMalloc((void **)p, count * sizeof(T)) != hipSuccess) {
-        *p = nullptr;
+    const size_t bytes = (size_t)count * sizeof(T);
+    void *q = nullptr;
+    if (g->alloc.alloc) {
+        q = g->alloc.alloc(bytes, g->astream, g->alloc.ctx);
+    } else if (hipMalloc(&q, bytes) != hipSuccess) {
+        q = nullptr;
         (void)hipGetLastError();
-        return GPMA_ENOMEM;
     }
+    if (!q) return GPMA_ENOMEM;
+    g->blocks[q] = bytes;
+    g->held_bytes += bytes;
+    *p = (T *)q;
     return GPMA_OK;
 }
 
 template <typename T>
-void dev_free(T *&p) {
-    if (p) hipFree((void *)p);
+void dev_free(gpma *g, T *&p) {
+    if (!p) return;
+    size_t bytes = 0;
+    auto it = g->blocks.find((void *)p);
+    if (it != g->blocks.end()) {
+        bytes = it->second;
+        g->blocks.erase(it);
+        g->held_bytes -= bytes;
+    }
+    if (g->alloc.free) {
+        hipDeviceSynchronize();
+        g->alloc.free((void *)p, bytes, g->astream, g->alloc.ctx);
+    } else {
+        hipFree((void *)p);
+    }
     p = nullptr;
+}
+
+void set_stream(gpma *g, hipStream_t s) {
+    g->astream = s;
+    if (g->mir) g->mir->astream = s;
 }
 
 // ---------------------------------------------------------------------------
@@ -244,8 +296,10 @@ bool params_valid(const gpma_params *p, bool allow_auto) {
         return false;
     if (2 * p->rho_root_pm > p->tau_root_pm) return false;
     if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT |
-                               GPMA_FLAG_LAZY_DELETE))
+                               GPMA_FLAG_LAZY_DELETE | GPMA_FLAG_FUSED_LIB_STREAMS))
         return false;
+    if (p->spmv_form > GPMA_SPMV_BINNED_GATHER) return false;
+    if (p->spmv_form == GPMA_SPMV_PULL && !(p->flags & GPMA_FLAG_MIRROR)) return false;
     if (p->sort_tile_keys != 0 && p->sort_tile_keys != 512 && p->sort_tile_keys != 1024 && p->sort_tile_keys != 2048)
         return false;
     if (p->fused_levels > 3) return false;
@@ -317,10 +371,10 @@ void drop_graphs(gpma *g) {
 void free_batch(gpma *g) {
     drop_graphs(g);
     g->wukeys = nullptr;   // the sort buffers go; the next window prefix picks them again
-    dev_free(g->kS);
-    dev_free(g->kA); dev_free(g->kB); dev_free(g->kC); dev_free(g->kD);
-    dev_free(g->leafA); dev_free(g->leafB); dev_free(g->stA); dev_free(g->stB);
-    dev_free(g->flags); dev_free(g->tmp);
+    dev_free(g, g->kS);
+    dev_free(g, g->kA); dev_free(g, g->kB); dev_free(g, g->kC); dev_free(g, g->kD);
+    dev_free(g, g->leafA); dev_free(g, g->leafB); dev_free(g, g->stA); dev_free(g, g->stB);
+    dev_free(g, g->flags); dev_free(g, g->tmp);
     g->bcap = 0;
 }
 
@@ -330,12 +384,12 @@ int ensure_batch(gpma *g, uint64_t b) {
     uint64_t c = next_pow2(std::max<uint64_t>(b, 4096));
     size_t tw = std::max(radix_tmp_words(c), scan_tmp_words(c + 1));
     int e = GPMA_OK;
-    e |= dev_alloc(&g->kS, c);
-    e |= dev_alloc(&g->kA, c); e |= dev_alloc(&g->kB, c);
-    e |= dev_alloc(&g->kC, c); e |= dev_alloc(&g->kD, c);
-    e |= dev_alloc(&g->leafA, c); e |= dev_alloc(&g->leafB, c);
-    e |= dev_alloc(&g->stA, c); e |= dev_alloc(&g->stB, c);
-    e |= dev_alloc(&g->flags, c + 1); e |= dev_alloc(&g->tmp, tw);
+    e |= dev_alloc(g, &g->kS, c);
+    e |= dev_alloc(g, &g->kA, c); e |= dev_alloc(g, &g->kB, c);
+    e |= dev_alloc(g, &g->kC, c); e |= dev_alloc(g, &g->kD, c);
+    e |= dev_alloc(g, &g->leafA, c); e |= dev_alloc(g, &g->leafB, c);
+    e |= dev_alloc(g, &g->stA, c); e |= dev_alloc(g, &g->stB, c);
+    e |= dev_alloc(g, &g->flags, c + 1); e |= dev_alloc(g, &g->tmp, tw);
     if (e) {
         free_batch(g);
         return GPMA_ENOMEM;
@@ -346,25 +400,82 @@ int ensure_batch(gpma *g, uint64_t b) {
 
 int ensure_dt(gpma *g, uint64_t entries, uint64_t leaves) {
     if (entries > g->dt_cap) {
-        dev_free(g->dtA); dev_free(g->dtB);
+        dev_free(g, g->dtA); dev_free(g, g->dtB);
         g->dt_cap = 0;
-        uint64_t c = next_pow2(entries);
-        if (dev_alloc(&g->dtA, c) || dev_alloc(&g->dtB, c)) {
-            dev_free(g->dtA); dev_free(g->dtB);
+        const uint64_t c = entries + entries / 8 + 4096;
+        if (dev_alloc(g, &g->dtA, c) || dev_alloc(g, &g->dtB, c)) {
+            dev_free(g, g->dtA); dev_free(g, g->dtB);
             return GPMA_ENOMEM;
         }
         g->dt_cap = c;
     }
     if (leaves > g->dt_off_cap) {
-        dev_free(g->dt_off); dev_free(g->dt_tmp);
+        dev_free(g, g->dt_off); dev_free(g, g->dt_tmp);
         g->dt_off_cap = 0;
         uint64_t c = next_pow2(leaves);
-        if (dev_alloc(&g->dt_off, c) || dev_alloc(&g->dt_tmp, scan_tmp_words(c))) {
-            dev_free(g->dt_off); dev_free(g->dt_tmp);
+        if (dev_alloc(g, &g->dt_off, c) || dev_alloc(g, &g->dt_tmp, scan_tmp_words(c))) {
+            dev_free(g, g->dt_off); dev_free(g, g->dt_tmp);
             return GPMA_ENOMEM;
         }
         g->dt_off_cap = c;
     }
+    return GPMA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// reservation before a batch changes anything (so that GPMA_ENOMEM leaves
+// the handle as it was)
+
+// Add one set of root arrays holding `cap` slots to the pool.
+int pool_add(gpma *g, uint64_t cap) {
+    gpma::ArrBuf b{nullptr, nullptr, nullptr, cap};
+    int e = dev_alloc(g, &b.slots, cap);
+    if (!e) e = dev_alloc(g, &b.cnt, cap >> g->lf_log2);
+    if (!e && g->dead) e = dev_alloc(g, &b.dead, cap >> g->lf_log2);
+    if (e) {
+        dev_free(g, b.slots); dev_free(g, b.cnt); dev_free(g, b.dead);
+        return GPMA_ENOMEM;
+    }
+    g->pool.push_back(b);
+    return GPMA_OK;
+}
+
+// Free the pool: resize arrays that were not needed, and the arrays a resize
+// replaced (after the device has finished with them).
+void release_pool(gpma *g) {
+    for (auto &b : g->pool) {
+        dev_free(g, b.slots); dev_free(g, b.cnt); dev_free(g, b.dead);
+    }
+    g->pool.clear();
+}
+
+// Everything batches with at most ins_max insertions and del_max deletions
+// in all may allocate below the root and at it: the merge workspace of the
+// device tier and of the root (every entry plus the insertions, over the
+// leaves of the largest capacity they can reach) and, when the root may be
+// resized, `nres` sets of root arrays of the largest capacity a resize can
+// pick (one for a single batch; two for a sequence, where the arrays a
+// resize frees join the pool and one large set is always free).  A sequence
+// whose entries could outgrow the largest array is refused (GPMA_ENOMEM).
+int reserve_update(gpma *g, uint64_t ins_max, uint64_t del_max, int nres) {
+    const uint64_t entries = g->n + ins_max;
+    uint64_t cmax = g->cap;
+    while (entries > root_hi(g, cmax)) {
+        cmax *= 2;
+        if (cmax > kMaxCap) return GPMA_ENOMEM;
+    }
+    int e = ensure_dt(g, entries, cmax >> g->lf_log2);
+    if (e) return e;
+    const bool grow = cmax > g->cap;
+    const bool shrink = del_max > 0 && !g->dead && g->cap > g->lf &&
+                        g->n - std::min(g->n - g->V, del_max) < root_lo(g, g->cap);
+    if (!grow && !shrink) return GPMA_OK;
+    const uint64_t need = nres > 1 ? cmax : (grow ? cmax : g->cap / 2);
+    int have = 0;
+    for (auto &b : g->pool)
+        if (b.cap >= need) have++;
+    for (; have < nres; have++)
+        if ((e = pool_add(g, need))) return e;
     return GPMA_OK;
 }
 
@@ -396,7 +507,9 @@ int segment_offsets(gpma *g, uint64_t first, uint64_t P, uint64_t *ns, hipStream
 }
 
 // Root rebuild: merge every stored entry with the k remaining updates U and
-// re-dispatch all of them evenly over ncap slots (ncap == cap: in place).
+// re-dispatch all of them evenly over ncap slots (ncap == cap: in place).  A
+// new capacity takes the smallest reserved set of arrays that holds it; the
+// replaced arrays join the pool (freed when the call ends).
 int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t k, uint64_t n_now,
                  uint64_t ncap, hipStream_t s) {
     uint64_t ns = 0;
@@ -406,29 +519,28 @@ int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t
     uint64_t N = del ? ns - k : ns + k;
     e = ensure_dt(g, ns + k, 0);
     if (e) return e;
-    uint64_t *nslots = g->slots;
-    uint16_t *ncnt = g->cnt;
-    uint32_t *ndead = g->dead;
+    gpma::ArrBuf nb{g->slots, g->cnt, g->dead, g->slots_buf};
     if (ncap != g->cap) {
-        if (dev_alloc(&nslots, ncap)) return GPMA_ENOMEM;
-        if (dev_alloc(&ncnt, ncap >> g->lf_log2) || (g->dead && dev_alloc(&ndead, ncap >> g->lf_log2))) {
-            dev_free(nslots);
-            dev_free(ncnt);
-            return GPMA_ENOMEM;
+        int best = -1;
+        for (size_t i = 0; i < g->pool.size(); i++)
+            if (g->pool[i].cap >= ncap && (best < 0 || g->pool[i].cap < g->pool[(size_t)best].cap)) best = (int)i;
+        if (best < 0) {   // nothing reserved (a caller outside the update calls)
+            if ((e = pool_add(g, ncap))) return e;
+            best = (int)g->pool.size() - 1;
         }
+        nb = g->pool[(size_t)best];
+        g->pool.erase(g->pool.begin() + best);
     }
     launch_gather_segment(g->slots, g->cnt, g->dead, 0, g->L, g->lf, g->dt_off, g->dtA, s);
     launch_merge_sorted(del, g->dtA, ns, U, k, g->dtB, s);
-    launch_dispatch(g->dtB, N, nslots, ncnt, ndead, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
+    launch_dispatch(g->dtB, N, nb.slots, nb.cnt, nb.dead, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
     launch_mark_done(del, U, status, 0, k, g->deg, g->ctl, ncap, true, s);
     if (ncap != g->cap) {
-        hipStreamSynchronize(s);
-        dev_free(g->slots);
-        dev_free(g->cnt);
-        if (g->dead) dev_free(g->dead);
-        g->slots = nslots;
-        g->cnt = ncnt;
-        g->dead = ndead;
+        g->pool.push_back(gpma::ArrBuf{g->slots, g->cnt, g->dead, g->slots_buf});
+        g->slots = nb.slots;
+        g->cnt = nb.cnt;
+        g->dead = nb.dead;
+        g->slots_buf = nb.cap;
         set_geometry(g, ncap);
     }
     return GPMA_OK;
@@ -531,9 +643,9 @@ uint16_t host_bf16(float f) {
 int locator_fit(gpma *g, hipStream_t s) {
     if (!g->loc) {
         int e = GPMA_OK;
-        e |= dev_alloc(&g->loc, 1);
-        e |= dev_alloc(&g->loc_gram, loc_gram_words());
-        e |= dev_alloc(&g->loc_err, 2);
+        e |= dev_alloc(g, &g->loc, 1);
+        e |= dev_alloc(g, &g->loc_gram, loc_gram_words());
+        e |= dev_alloc(g, &g->loc_err, 2);
         if (e) return GPMA_ENOMEM;
     }
     const uint64_t L = g->L;
@@ -599,13 +711,16 @@ int locator_fit(gpma *g, hipStream_t s) {
     return GPMA_OK;
 }
 
+// Refit after the array was rebuilt or resized (the pivots all moved), or
+// when more than 1/16 of the lookups since the last check fell back to the
+// binary search (merges have shifted the pivots the model was fitted to).
+// The result never depends on the fit; only the lookup cost does.
 int locator_after_batch(gpma *g, uint64_t lookups, uint64_t misses, bool rebuilt, hipStream_t s) {
     if (!g->learned) return GPMA_OK;
     g->loc_lookups += lookups;
     g->loc_misses += misses;
     g->batches_since_fit++;
-    if (rebuilt || g->loc_h.L != g->L || g->batches_since_fit >= 64 || misses * 16 > lookups)
-        return locator_fit(g, s);
+    if (rebuilt || g->loc_h.L != g->L || misses * 16 > lookups) return locator_fit(g, s);
     return GPMA_OK;
 }
 
@@ -640,7 +755,12 @@ int finish_levels(gpma *g, bool del, LevelArrays cur, uint64_t rem, uint32_t h_s
         } else {
             pa = pb = nullptr;
             e = device_tier_level(g, del, h, cur, rem, lo, hi, s);
-            if (e) return e;
+            if (e) {
+                // the merges made so far stand: keep the entry count in step
+                read_ctl(g, s);
+                g->n = (uint64_t)((int64_t)g->n + g->ctl_h->dn);
+                return e;
+            }
         }
         compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags,
                         g->tmp, del, (uint64_t)g->lf << h, g->ctl, s);
@@ -770,14 +890,15 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
 }
 
 void free_all(gpma *g) {
+    release_pool(g);
     free_batch(g);
-    dev_free(g->loc); dev_free(g->loc_gram); dev_free(g->loc_err);
-    dev_free(g->tkeys);
-    dev_free(g->fblk); dev_free(g->desc);
+    dev_free(g, g->loc); dev_free(g, g->loc_gram); dev_free(g, g->loc_err);
+    dev_free(g, g->tkeys);
+    dev_free(g, g->fblk); dev_free(g, g->desc);
     g->fs = nullptr;
     g->stop = nullptr;
     g->outs = nullptr;
-    dev_free(g->werrs); dev_free(g->wcount); dev_free(g->ustart);
+    dev_free(g, g->werrs); dev_free(g, g->wcount); dev_free(g, g->ustart);
     if (g->fblk_h) hipHostFree(g->fblk_h);
     g->fblk_h = nullptr;
     if (g->reset_h) hipHostFree(g->reset_h);
@@ -796,18 +917,18 @@ void free_all(gpma *g) {
     if (g->ev_join) hipEventDestroy(g->ev_join);
     if (g->ev_join2) hipEventDestroy(g->ev_join2);
     g->ev_fork = g->ev_join = g->ev_join2 = nullptr;
-    dev_free(g->slots); dev_free(g->cnt); dev_free(g->row_ptr); dev_free(g->deg); dev_free(g->dead);
-    dev_free(g->lk_scratch); dev_free(g->lk_locks);
-    dev_free(g->dtA); dev_free(g->dtB); dev_free(g->dt_off); dev_free(g->dt_tmp);
-    dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
-    dev_free(g->pb_offs); dev_free(g->pb_tmp); dev_free(g->pb_small); dev_free(g->pb_pieces); dev_free(g->pb_rec);
-    dev_free(g->pb_rec2); dev_free(g->pb_coffs); dev_free(g->pb_keys); dev_free(g->pb_ne);
+    dev_free(g, g->slots); dev_free(g, g->cnt); dev_free(g, g->row_ptr); dev_free(g, g->deg); dev_free(g, g->dead);
+    dev_free(g, g->lk_scratch); dev_free(g, g->lk_locks);
+    dev_free(g, g->dtA); dev_free(g, g->dtB); dev_free(g, g->dt_off); dev_free(g, g->dt_tmp);
+    dev_free(g, g->pr_contrib); dev_free(g, g->pr_y); dev_free(g, g->pr_dang);
+    dev_free(g, g->pb_offs); dev_free(g, g->pb_tmp); dev_free(g, g->pb_small); dev_free(g, g->pb_pieces); dev_free(g, g->pb_rec);
+    dev_free(g, g->pb_rec2); dev_free(g, g->pb_coffs); dev_free(g, g->pb_keys); dev_free(g, g->pb_ne);
     g->pb_offs_words = g->pb_tmp_words = g->pb_pieces_cap = g->pb_rec_cap = g->pb_rec2_cap = g->pb_coffs_words = 0;
     g->pb_keys_cap = g->pb_ne_cap = 0;
-    dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
-    dev_free(g->cc_pick);
-    dev_free(g->small);
-    dev_free(g->ctl);
+    dev_free(g, g->bfs_q0); dev_free(g, g->bfs_q1); dev_free(g, g->bfs_off); dev_free(g, g->bfs_tmp);
+    dev_free(g, g->cc_pick);
+    dev_free(g, g->small);
+    dev_free(g, g->ctl);
     if (g->ctl_h) hipHostFree(g->ctl_h);
     if (g->small_h) hipHostFree(g->small_h);
     g->ctl_h = nullptr;
@@ -833,14 +954,14 @@ constexpr size_t kFbBytes = kFbOuts + kFusedChunk * sizeof(BatchOut);
 int ensure_fused(gpma *g) {
     if (g->fs) return GPMA_OK;
     int e = GPMA_OK;
-    e |= dev_alloc(&g->fblk, (kFbBytes + 7) / 8);
+    e |= dev_alloc(g, &g->fblk, (kFbBytes + 7) / 8);
     if (!e) {
         uint8_t *b = (uint8_t *)g->fblk;
         g->fs = (FusedState *)b;
         g->stop = (uint32_t *)(b + kFbStop);
         g->outs = (BatchOut *)(b + kFbOuts);
     }
-    e |= dev_alloc(&g->desc, kFusedChunk);
+    e |= dev_alloc(g, &g->desc, kFusedChunk);
     if (hipHostMalloc(&g->fblk_h, kFbBytes, 0) != hipSuccess) {
         g->fblk_h = nullptr;
         e = GPMA_ENOMEM;
@@ -858,9 +979,9 @@ int ensure_fused(gpma *g) {
     if (!e && hipEventCreateWithFlags(&g->ev_fork, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipEventCreateWithFlags(&g->ev_join, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipEventCreateWithFlags(&g->ev_join2, hipEventDisableTiming) != hipSuccess) e = GPMA_EDEVICE;
-    e |= dev_alloc(&g->werrs, kWindowMax);
-    e |= dev_alloc(&g->wcount, 2);
-    e |= dev_alloc(&g->ustart, kWindowMax + 1);
+    e |= dev_alloc(g, &g->werrs, kWindowMax);
+    e |= dev_alloc(g, &g->wcount, 2);
+    e |= dev_alloc(g, &g->ustart, kWindowMax + 1);
     if (!e) {
         // window generations start at 1 so that zeroed error flags mean valid
         memset(g->reset_h, 0, sizeof(FusedState));
@@ -1058,12 +1179,18 @@ __global__ void k_probe_wait(uint32_t n) {
 }
 __global__ void k_probe_mark() {}
 
-// Which library stream runs beside caller stream s: a wait of ~0.1 ms goes on
-// s, an empty kernel on the candidate; if the candidate's kernel completes
-// while s's wait has not, the two sit on different hardware queues.  Once per
-// caller stream; nullptr when neither candidate does.
+constexpr size_t kProbeMemo = 16;
+
+// Which library stream runs beside caller stream s: a wait of ~0.4 ms goes
+// on s, an empty kernel on the candidate; if the candidate's kernel
+// completes while s's wait has not, the two sit on different hardware
+// queues.  Once per caller stream (the last kProbeMemo streams are
+// remembered); nullptr when neither candidate does, or when the handle was
+// created with GPMA_FLAG_FUSED_LIB_STREAMS.
 hipStream_t pick_pair_stream(gpma *g, hipStream_t s) {
-    if (g->probe_done && g->probed == s) return g->pair;
+    if (g->lib_streams) return nullptr;
+    for (auto &p : g->probes)
+        if (p.first == s) return p.second;
     constexpr uint32_t kProbeSleeps = 2000;
     hipEvent_t e_wait = nullptr, e_mark = nullptr;
     hipStream_t pick = nullptr;
@@ -1076,7 +1203,10 @@ hipStream_t pick_pair_stream(gpma *g, hipStream_t s) {
             hipLaunchKernelGGL(k_probe_mark, dim3(1), dim3(kWave), 0, c);
             hipEventRecord(e_mark, c);
             if (hipEventSynchronize(e_mark) != hipSuccess) break;
-            const bool beside = hipEventQuery(e_wait) == hipErrorNotReady;
+            const hipError_t q = hipEventQuery(e_wait);
+            // a not-ready query is no error of the caller's next call
+            if (q == hipErrorNotReady) (void)hipGetLastError();
+            const bool beside = q == hipErrorNotReady;
             if (hipStreamSynchronize(s) != hipSuccess) break;
             if (beside) {
                 pick = c;
@@ -1084,18 +1214,25 @@ hipStream_t pick_pair_stream(gpma *g, hipStream_t s) {
             }
         }
     }
-    (void)hipGetLastError();   // a not-ready query is not an error of the next call
     if (e_wait) hipEventDestroy(e_wait);
     if (e_mark) hipEventDestroy(e_mark);
-    g->probed = s;
-    g->pair = pick;
-    g->probe_done = true;
+    if (g->probes.size() >= kProbeMemo) g->probes.erase(g->probes.begin());
+    g->probes.emplace_back(s, pick);
     return pick;
 }
 
 int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *const *keys, const uint64_t *sizes,
                 hipStream_t s, gpma_stats *total, uint32_t *done_out) {
     gpma *m = g->mir;
+    // the mirror's batch results, for its share of the rewritten slots
+    gpma_stats mst{};
+    gpma_stats *mtot = total ? &mst : nullptr;
+    struct MirrorSum {
+        gpma_stats *t, *m;
+        ~MirrorSum() {
+            if (t) t->mirror_slots_rewritten += m->slots_rewritten;
+        }
+    } msum{total, &mst};
     // the previous call ended with a synchronisation, so the pinned staging
     // buffers are free to rewrite
     for (uint32_t i = 0; i < count; i++) g->desc_h[i] = BatchDesc{keys[i], sizes[i]};
@@ -1193,14 +1330,14 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             if (end[k] == P[k].next) continue;   // idle this round
             gpma *h = P[k].h;
             const uint32_t b = h->fs_h->batch;
-            account(h, P[k].next, b, k == 0 ? total : nullptr);
+            account(h, P[k].next, b, k == 0 ? total : mtot);
             if (!*h->stop_h) {
                 P[k].next = end[k];
                 continue;
             }
             // stopped at batch b with updates left above the device levels
             stopped = true;
-            int e = complete_stopped(h, ops[b] != 0, s, k == 0 ? total : nullptr);
+            int e = complete_stopped(h, ops[b] != 0, s, k == 0 ? total : mtot);
             if (e == GPMA_EINVAL) {   // an invalid key: batches before b stand
                 P[k].failed = true;
                 P[k].next = b;
@@ -1233,7 +1370,7 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
         h->acc_lookups = h->acc_misses = 0;
         if (h->learned) {
             h->batches_since_fit += count > 0 ? count - 1 : 0;   // locator_after_batch adds one
-            int e = locator_after_batch(h, lk, ms, h->loc_h.L != h->L, s);
+            int e = locator_after_batch(h, lk, ms, false, s);
             if (e) return e;
         }
     }
@@ -1249,6 +1386,8 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
 // Snapshots: a read-only copy of the arrays the analytics read (slots, leaf
 // counts, row offsets, degrees; the mirror's too), taken in stream order.
 static int snapshot_alloc(gpma *src, gpma *c) {
+    c->alloc = src->alloc;
+    c->astream = src->astream;
     c->V = src->V; c->lf = src->lf; c->lf_log2 = src->lf_log2;
     c->tau_leaf = src->tau_leaf; c->tau_root = src->tau_root;
     c->rho_leaf = src->rho_leaf; c->rho_root = src->rho_root;
@@ -1256,12 +1395,12 @@ static int snapshot_alloc(gpma *src, gpma *c) {
     c->dev = src->dev;
     c->readonly = true;
     int e = GPMA_OK;
-    e |= dev_alloc(&c->slots, src->cap);
-    e |= dev_alloc(&c->cnt, src->L);
-    e |= dev_alloc(&c->row_ptr, (uint64_t)src->V + 1);
-    e |= dev_alloc(&c->deg, src->V);
-    if (!c->ctl) e |= dev_alloc(&c->ctl, 1);
-    if (!c->small) e |= dev_alloc(&c->small, 8);
+    e |= dev_alloc(c, &c->slots, src->cap);
+    e |= dev_alloc(c, &c->cnt, src->L);
+    e |= dev_alloc(c, &c->row_ptr, (uint64_t)src->V + 1);
+    e |= dev_alloc(c, &c->deg, src->V);
+    if (!c->ctl) e |= dev_alloc(c, &c->ctl, 1);
+    if (!c->small) e |= dev_alloc(c, &c->small, 8);
     if (!c->ctl_h && hipHostMalloc((void **)&c->ctl_h, sizeof(Ctl), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (!c->small_h && hipHostMalloc((void **)&c->small_h, 4 * sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
     return e;
@@ -1278,7 +1417,7 @@ static void snapshot_copy(gpma *src, gpma *c, hipStream_t s) {
 static int snapshot_refresh_one(gpma *src, gpma *c, hipStream_t s) {
     if (c->cap != src->cap || c->V != src->V) {
         hipStreamSynchronize(s);
-        dev_free(c->slots); dev_free(c->cnt); dev_free(c->row_ptr); dev_free(c->deg);
+        dev_free(c, c->slots); dev_free(c, c->cnt); dev_free(c, c->row_ptr); dev_free(c, c->deg);
         int e = snapshot_alloc(src, c);
         if (e) return e;
     }
@@ -1292,6 +1431,7 @@ extern "C" int gpma_snapshot(gpma_t *src, gpma_t **out, hipStream_t s) {
     if (!out) return GPMA_EINVAL;
     *out = nullptr;
     if (!src || src->readonly) return GPMA_EINVAL;
+    set_stream(src, s);
     gpma *c = new (std::nothrow) gpma();
     if (!c) return GPMA_ENOMEM;
     int e = snapshot_alloc(src, c);
@@ -1314,6 +1454,7 @@ extern "C" int gpma_snapshot(gpma_t *src, gpma_t **out, hipStream_t s) {
 extern "C" int gpma_snapshot_refresh(gpma_t *src, gpma_t *snap, hipStream_t s) {
     if (!src || !snap || src->readonly || !snap->readonly) return GPMA_EINVAL;
     if (!src->mir != !snap->mir) return GPMA_EINVAL;
+    set_stream(snap, s);
     int e = snapshot_refresh_one(src, snap, s);
     if (!e && src->mir) e = snapshot_refresh_one(src->mir, snap->mir, s);
     return e;
@@ -1338,6 +1479,8 @@ void gpma_default_params(gpma_params *p) {
     p->flags = 0;
     p->sort_tile_keys = 0;
     p->fused_levels = 1;
+    p->lds_tier_bytes = 0;
+    p->spmv_form = GPMA_SPMV_AUTO;
 }
 
 const char *gpma_strerror(int code) {
@@ -1351,7 +1494,7 @@ const char *gpma_strerror(int code) {
 }
 
 int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, const gpma_params *params,
-                hipStream_t s) {
+                const gpma_allocator *alloc, hipStream_t s) {
     if (!out) return GPMA_EINVAL;
     *out = nullptr;
     gpma_params p;
@@ -1359,11 +1502,19 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     if (!params_valid(&p, true)) return GPMA_EINVAL;
     if (V == 0 || V > (1u << 31)) return GPMA_EINVAL;
     if (n && !keys) return GPMA_EINVAL;
+    if (alloc && (!alloc->alloc || !alloc->free)) return GPMA_EINVAL;
     const uint64_t tot = n + V;
     if (tot >= kMaxCap) return GPMA_EINVAL;
+    if ((p.spmv_form == GPMA_SPMV_BINNED || p.spmv_form == GPMA_SPMV_BINNED_COARSE ||
+         p.spmv_form == GPMA_SPMV_BINNED_GATHER) && !pb_supported(V))
+        return GPMA_EINVAL;
 
     gpma *g = new (std::nothrow) gpma();
     if (!g) return GPMA_ENOMEM;
+    if (alloc) g->alloc = *alloc;
+    g->astream = s;
+    g->spmv_form = p.spmv_form;
+    g->lib_streams = (p.flags & GPMA_FLAG_FUSED_LIB_STREAMS) != 0;
     g->V = V;
     g->tau_leaf = p.tau_leaf_pm; g->tau_root = p.tau_root_pm;
     g->rho_leaf = p.rho_leaf_pm; g->rho_root = p.rho_root_pm;
@@ -1371,22 +1522,22 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     hipGetDevice(&dev);
     g->dev.max_lds = seg_merge_max_lds();
     hipDeviceGetAttribute(&g->dev.cus, hipDeviceAttributeMultiprocessorCount, dev);
-    // GPMA_TIER_LDS caps the LDS the workgroup tier may use, so tests can
-    // drive small segments through the device tier
-    if (const char *t = getenv("GPMA_TIER_LDS")) g->dev.max_lds = std::min(g->dev.max_lds, atoi(t));
+    // a cap on the LDS of the workgroup tier sends smaller segments to the
+    // host-driven device tier (same results; tests use it to reach that tier)
+    if (p.lds_tier_bytes) g->dev.max_lds = std::min<int>(g->dev.max_lds, (int)std::min<uint32_t>(p.lds_tier_bytes, 1u << 30));
 
     int e = GPMA_OK;
     uint64_t *in = nullptr, *ba = nullptr, *bb = nullptr, *uq = nullptr;
     uint32_t *fl = nullptr, *tmp = nullptr;
-    e |= dev_alloc(&g->ctl, 1);
-    e |= dev_alloc(&g->small, 8);
+    e |= dev_alloc(g, &g->ctl, 1);
+    e |= dev_alloc(g, &g->small, 8);
     if (hipHostMalloc((void **)&g->ctl_h, sizeof(Ctl), 0) != hipSuccess) e = GPMA_ENOMEM;
     if (hipHostMalloc((void **)&g->small_h, 4 * sizeof(uint32_t), 0) != hipSuccess) e = GPMA_ENOMEM;
-    e |= dev_alloc(&in, tot); e |= dev_alloc(&ba, tot); e |= dev_alloc(&bb, tot);
-    e |= dev_alloc(&fl, tot + 1);
-    e |= dev_alloc(&tmp, std::max(radix_tmp_words(tot), scan_tmp_words(tot + 1)));
+    e |= dev_alloc(g, &in, tot); e |= dev_alloc(g, &ba, tot); e |= dev_alloc(g, &bb, tot);
+    e |= dev_alloc(g, &fl, tot + 1);
+    e |= dev_alloc(g, &tmp, std::max(radix_tmp_words(tot), scan_tmp_words(tot + 1)));
     if (e) {
-        dev_free(in); dev_free(ba); dev_free(bb); dev_free(fl); dev_free(tmp);
+        dev_free(g, in); dev_free(g, ba); dev_free(g, bb); dev_free(g, fl); dev_free(g, tmp);
         free_all(g);
         delete g;
         return GPMA_ENOMEM;
@@ -1402,7 +1553,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     unique_sorted(sorted, tot, uq, &g->ctl->n_in, fl, tmp, s);
     read_ctl(g, s);
     const uint64_t nu = g->ctl_h->n_in;
-    auto cleanup = [&]() { dev_free(in); dev_free(ba); dev_free(bb); dev_free(fl); dev_free(tmp); };
+    auto cleanup = [&]() { dev_free(g, in); dev_free(g, ba); dev_free(g, bb); dev_free(g, fl); dev_free(g, tmp); };
     if (g->ctl_h->err) {
         cleanup();
         free_all(g);
@@ -1431,11 +1582,12 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
         return GPMA_EINVAL;
     }
     set_geometry(g, cap);
-    e |= dev_alloc(&g->slots, cap);
-    e |= dev_alloc(&g->cnt, g->L);
-    e |= dev_alloc(&g->row_ptr, (uint64_t)V + 1);
-    e |= dev_alloc(&g->deg, V);
-    if (p.flags & GPMA_FLAG_LAZY_DELETE) e |= dev_alloc(&g->dead, g->L);   // zeroed by the dispatch
+    g->slots_buf = cap;
+    e |= dev_alloc(g, &g->slots, cap);
+    e |= dev_alloc(g, &g->cnt, g->L);
+    e |= dev_alloc(g, &g->row_ptr, (uint64_t)V + 1);
+    e |= dev_alloc(g, &g->deg, V);
+    if (p.flags & GPMA_FLAG_LAZY_DELETE) e |= dev_alloc(g, &g->dead, g->L);   // zeroed by the dispatch
     if (e) {
         cleanup();
         free_all(g);
@@ -1466,15 +1618,16 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
         gpma_params mp = p;
         mp.flags = p.flags & (GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT | GPMA_FLAG_LAZY_DELETE);
         mp.leaf_size = g->lf;
+        mp.spmv_form = GPMA_SPMV_AUTO;
         uint64_t *tk = nullptr;
-        if (n && dev_alloc(&tk, n)) {
+        if (n && dev_alloc(g, &tk, n)) {
             free_all(g);
             delete g;
             return GPMA_ENOMEM;
         }
         launch_transpose_keys(keys, n, tk, s);
-        int e2 = gpma_create(&g->mir, V, tk, n, &mp, s);
-        dev_free(tk);
+        int e2 = gpma_create(&g->mir, V, tk, n, &mp, alloc, s);
+        dev_free(g, tk);
         if (e2) {
             free_all(g);
             delete g;
@@ -1495,23 +1648,40 @@ int gpma_destroy(gpma_t *g) {
     return GPMA_OK;
 }
 
+// Reserve, on the array and its mirror, everything a batch of b updates may
+// allocate, then apply it to both: an allocation failure returns before
+// either changes.
 static int apply_with_mirror(gpma_t *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t s,
                              gpma_stats *st) {
     if (!g || g->readonly) return GPMA_EINVAL;
-    int e = apply_batch(g, keys, b, del, s, st);
-    if (e || !g->mir || b == 0) return e;
-    if (b > g->tkeys_cap) {
-        dev_free(g->tkeys);
-        g->tkeys_cap = 0;
-        if (dev_alloc(&g->tkeys, next_pow2(b))) return GPMA_ENOMEM;
-        g->tkeys_cap = next_pow2(b);
+    if (b && (!keys || b >= (1ull << 31))) return GPMA_EINVAL;
+    set_stream(g, s);
+    int e = GPMA_OK;
+    if (b) {
+        for (gpma *h : {g, g->mir}) {
+            if (!h || e) continue;
+            e = ensure_batch(h, b);
+            if (!e) e = reserve_update(h, del ? 0 : b, del ? b : 0, 1);
+        }
+        if (!e && g->mir && b > g->tkeys_cap) {
+            dev_free(g, g->tkeys);
+            g->tkeys_cap = 0;
+            e = dev_alloc(g, &g->tkeys, next_pow2(b));
+            if (!e) g->tkeys_cap = next_pow2(b);
+        }
     }
-    launch_transpose_keys(keys, b, g->tkeys, s);
-    e = apply_batch(g->mir, g->tkeys, b, del, s, nullptr);
-    if (e) return e;
-    // both arrays hold the same edge set
-    if (g->mir->n != g->n) return GPMA_EDEVICE;
-    return GPMA_OK;
+    if (!e) e = apply_batch(g, keys, b, del, s, st);
+    if (!e && g->mir && b) {
+        launch_transpose_keys(keys, b, g->tkeys, s);
+        gpma_stats mst;
+        e = apply_batch(g->mir, g->tkeys, b, del, s, st ? &mst : nullptr);
+        if (!e && st) st->mirror_slots_rewritten = mst.slots_rewritten;
+        // both arrays hold the same edge set
+        if (!e && g->mir->n != g->n) e = GPMA_EDEVICE;
+    }
+    release_pool(g);
+    if (g->mir) release_pool(g->mir);
+    return e;
 }
 
 int gpma_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st) {
@@ -1527,22 +1697,33 @@ gpma_t *gpma_get_mirror(gpma_t *g) { return g ? g->mir : nullptr; }
 // Lock-based GPMA insertion (the comparator of Section 6; kernels and the
 // algorithm's description in gpma_lock.hip): sort, unique, probe, then rounds
 // of locate + one launch per height until every insertion has merged.
-static int lock_state(gpma *g, hipStream_t s) {
-    if (g->lk_cap == g->cap) return GPMA_OK;
-    hipStreamSynchronize(s);
-    dev_free(g->lk_scratch);
-    dev_free(g->lk_locks);
-    g->lk_cap = 0;
-    if (dev_alloc(&g->lk_scratch, g->cap) || dev_alloc(&g->lk_locks, 2 * g->L)) {
-        dev_free(g->lk_scratch);
-        dev_free(g->lk_locks);
-        return GPMA_ENOMEM;
+// The comparator's merge scratch (one slot per slot) and lock words (two
+// per leaf), sized for capacities up to cap_max; reset whenever the
+// capacity changed since the last batch or round.
+static int lock_state(gpma *g, uint64_t cap_max, hipStream_t s) {
+    cap_max = std::max(cap_max, g->cap);
+    if (g->lk_buf < cap_max) {
+        dev_free(g, g->lk_scratch);
+        dev_free(g, g->lk_locks);
+        g->lk_buf = 0;
+        g->lk_cap = 0;
+        if (dev_alloc(g, &g->lk_scratch, cap_max) || dev_alloc(g, &g->lk_locks, 2 * (cap_max >> g->lf_log2))) {
+            dev_free(g, g->lk_scratch);
+            dev_free(g, g->lk_locks);
+            return GPMA_ENOMEM;
+        }
+        g->lk_buf = cap_max;
     }
-    hipMemsetAsync(g->lk_locks, 0, 2 * g->L * sizeof(uint32_t), s);
-    g->lk_epoch = 0;
-    g->lk_cap = g->cap;
+    if (g->lk_cap != g->cap) {
+        hipMemsetAsync(g->lk_locks, 0, 2 * g->L * sizeof(uint32_t), s);
+        g->lk_epoch = 0;
+        g->lk_cap = g->cap;
+    }
     return GPMA_OK;
 }
+
+static int lock_rounds(gpma *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st,
+                       uint32_t *rounds_out);
 
 int gpma_lock_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st,
                            uint32_t *rounds_out) {
@@ -1555,9 +1736,25 @@ int gpma_lock_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStrea
     if (!g || g->readonly || g->mir) return GPMA_EINVAL;
     if (b == 0) return GPMA_OK;
     if (!keys || b >= (1ull << 31)) return GPMA_EINVAL;
+    set_stream(g, s);
+    uint64_t cmax = g->cap;
+    while (g->n + b > root_hi(g, cmax) && cmax <= kMaxCap) cmax *= 2;
     int e = ensure_batch(g, b);
-    if (!e) e = lock_state(g, s);
-    if (e) return e;
+    if (!e) e = reserve_update(g, b, 0, 2);
+    if (!e) e = lock_state(g, cmax, s);
+    if (e) {
+        release_pool(g);
+        return e;
+    }
+    e = lock_rounds(g, keys, b, s, st, rounds_out);
+    release_pool(g);
+    return e;
+}
+
+// The rounds of gpma_lock_insert_batch once its memory is reserved.
+static int lock_rounds(gpma *g, const uint64_t *keys, uint64_t b, hipStream_t s, gpma_stats *st,
+                       uint32_t *rounds_out) {
+    int e = GPMA_OK;
     hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
     const uint32_t sb = bit_width(g->V - 1);
     const uint64_t *sorted =
@@ -1578,7 +1775,7 @@ int gpma_lock_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStrea
     while (rem > 0) {
         // every round merges at least one insertion or doubles the root
         if (rounds > rem + b + 64) return GPMA_EDEVICE;
-        e = lock_state(g, s);
+        e = lock_state(g, 0, s);
         if (e) return e;
         const uint32_t epoch = ++g->lk_epoch;
         launch_locate(cur.k, cur.n, rem, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
@@ -1624,6 +1821,7 @@ int gpma_lock_insert_batch(gpma_t *g, const uint64_t *keys, uint64_t b, hipStrea
 int gpma_locate(gpma_t *g, const uint64_t *keys, uint64_t n, uint32_t *leaf_out, hipStream_t s) {
     if (!g || g->readonly || (n && (!keys || !leaf_out)) || n >= (1ull << 31)) return GPMA_EINVAL;
     if (!n) return GPMA_OK;
+    set_stream(g, s);
     int e = ensure_batch(g, n);
     if (e) return e;
     hipMemsetAsync(g->ctl, 0, sizeof(Ctl), s);
@@ -1642,6 +1840,7 @@ int gpma_locate(gpma_t *g, const uint64_t *keys, uint64_t n, uint32_t *leaf_out,
 
 int gpma_locator_refit(gpma_t *g, hipStream_t s) {
     if (!g || !g->learned) return GPMA_EINVAL;
+    set_stream(g, s);
     return locator_fit(g, s);
 }
 
@@ -1662,31 +1861,51 @@ int gpma_apply_batches(gpma_t *g, uint32_t count, const uint8_t *ops, const uint
         total->top_level = -1;
     }
     if (!g || g->readonly || (count && (!ops || !keys || !sizes))) return GPMA_EINVAL;
-    uint64_t cmax = 0, sum = 0;
+    uint64_t cmax = 0, sum = 0, sum_ins = 0, sum_del = 0;
     for (uint32_t i = 0; i < count; i++) {
         if (ops[i] > 1 || sizes[i] >= (1ull << 31) || (sizes[i] && !keys[i])) return GPMA_EINVAL;
         cmax = std::max(cmax, batch_class(sizes[i]));
         sum += sizes[i];
+        (ops[i] ? sum_del : sum_ins) += sizes[i];
         if (total) total->requested += sizes[i];
     }
     if (count == 0) return GPMA_OK;
-    // staging for windows of batches sorted together: up to 2^20 keys
+    set_stream(g, s);
+    // staging for windows of batches sorted together: up to 2^20 keys; then
+    // everything the whole sequence may allocate, on both arrays, before any
+    // batch runs
     cmax = std::max(cmax, std::min<uint64_t>(1ull << 20, batch_class(sum)));
-    int e = ensure_batch(g, cmax);
-    if (!e) e = ensure_fused(g);
-    if (!e && g->mir) e = ensure_batch(g->mir, cmax);
-    if (!e && g->mir) e = ensure_fused(g->mir);
-    if (e) return e;
+    int e = GPMA_OK;
+    for (gpma *h : {g, g->mir}) {
+        if (!h || e) continue;
+        e = ensure_batch(h, cmax);
+        if (!e) e = ensure_fused(h);
+        if (!e) e = reserve_update(h, sum_ins, sum_del, 2);
+    }
     uint32_t done = 0;
-    for (uint32_t c0 = 0; c0 < count; c0 += kFusedChunk) {
+    for (uint32_t c0 = 0; !e && c0 < count; c0 += kFusedChunk) {
         const uint32_t n = std::min(kFusedChunk, count - c0);
         uint32_t d = 0;
         e = apply_chunk(g, n, ops + c0, keys + c0, sizes + c0, s, total, &d);
         done += d;
-        if (e) break;
     }
+    release_pool(g);
+    if (g->mir) release_pool(g->mir);
     if (completed) *completed = done;
     return e;
+}
+
+int gpma_fused_pairing(gpma_t *g, hipStream_t s) {
+    if (!g || !g->mir) return GPMA_EINVAL;
+    if (g->lib_streams) return 0;
+    for (auto &p : g->probes)
+        if (p.first == s) return p.second ? 1 : 0;
+    return GPMA_EINVAL;
+}
+
+uint64_t gpma_allocated_bytes(const gpma_t *g) {
+    if (!g) return 0;
+    return g->held_bytes + (g->mir ? g->mir->held_bytes : 0);
 }
 
 uint64_t gpma_num_edges(const gpma_t *g) { return g ? g->n - g->V : 0; }
@@ -1707,16 +1926,17 @@ int gpma_export_keys(gpma_t *g, uint64_t *out, uint64_t max, uint64_t *n_out, hi
     const uint64_t m = g->n - g->V;
     if (n_out) *n_out = m;
     if (!out || max < m) return GPMA_EINVAL;
+    set_stream(g, s);
     uint32_t *fl = nullptr, *tmp = nullptr;
-    if (dev_alloc(&fl, g->cap + 1) || dev_alloc(&tmp, scan_tmp_words(g->cap))) {
-        dev_free(fl);
-        dev_free(tmp);
+    if (dev_alloc(g, &fl, g->cap + 1) || dev_alloc(g, &tmp, scan_tmp_words(g->cap))) {
+        dev_free(g, fl);
+        dev_free(g, tmp);
         return GPMA_ENOMEM;
     }
     compact_edges(g->slots, g->cap, out, g->small, fl, tmp, s);
     hipStreamSynchronize(s);
-    dev_free(fl);
-    dev_free(tmp);
+    dev_free(g, fl);
+    dev_free(g, tmp);
     return GPMA_OK;
 }
 
@@ -1746,19 +1966,20 @@ int gpma_sync(gpma_t *g) {
 
 namespace {
 
-enum { kSpmvBinned = 0, kSpmvPull = 1, kSpmvPush = 2 };
+enum { kSpmvBinned = 0, kSpmvPull = 1, kSpmvPush = 2, kSpmvGather = 3 };
 
 // Destination bins when V allows them, else pull over the dst-major mirror
-// if there is one, else push.  GPMA_SPMV=binned|pull|push overrides the
-// choice where it applies (tests compare the three).
+// if there is one, else push; gpma_params.spmv_form picks one (tests compare
+// them; validated at create).
 int spmv_mode(const gpma *g) {
-    int m = pb_supported(g->V) ? kSpmvBinned : (g->mir ? kSpmvPull : kSpmvPush);
-    if (const char *e = getenv("GPMA_SPMV")) {
-        if (!strcmp(e, "push")) m = kSpmvPush;
-        else if (!strcmp(e, "pull") && g->mir) m = kSpmvPull;
-        else if (!strcmp(e, "binned") && pb_supported(g->V)) m = kSpmvBinned;
+    switch (g->spmv_form) {
+        case GPMA_SPMV_BINNED:
+        case GPMA_SPMV_BINNED_COARSE: return kSpmvBinned;
+        case GPMA_SPMV_PULL: return kSpmvPull;
+        case GPMA_SPMV_PUSH: return kSpmvPush;
+        case GPMA_SPMV_BINNED_GATHER: return kSpmvGather;
+        default: return pb_supported(g->V) ? kSpmvBinned : (g->mir ? kSpmvPull : kSpmvPush);
     }
-    return m;
 }
 
 // records for every stored edge, the count matrix and its scan scratch, the
@@ -1766,57 +1987,57 @@ int spmv_mode(const gpma *g) {
 // reallocate on every call
 int ensure_pb(gpma *g, const PbLayout &L) {
     const uint64_t edges = g->n;   // >= stored edges (guards included)
-    if (!g->pb_small && dev_alloc(&g->pb_small, 4)) return GPMA_ENOMEM;
+    if (!g->pb_small && dev_alloc(g, &g->pb_small, 4)) return GPMA_ENOMEM;
     if (g->pb_rec_cap < edges) {
-        dev_free(g->pb_rec);
+        dev_free(g, g->pb_rec);
         g->pb_rec_cap = 0;
         const uint64_t want = edges + edges / 4 + 1024;
-        if (dev_alloc(&g->pb_rec, want)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_rec, want)) return GPMA_ENOMEM;
         g->pb_rec_cap = want;
     }
     if (L.nc && g->pb_rec2_cap < edges) {
-        dev_free(g->pb_rec2);
+        dev_free(g, g->pb_rec2);
         g->pb_rec2_cap = 0;
         const uint64_t want = edges + edges / 4 + 1024;
-        if (dev_alloc(&g->pb_rec2, want)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_rec2, want)) return GPMA_ENOMEM;
         g->pb_rec2_cap = want;
     }
     if (L.nc && g->pb_coffs_words < L.coarse_words) {
-        dev_free(g->pb_coffs);
+        dev_free(g, g->pb_coffs);
         g->pb_coffs_words = 0;
-        if (dev_alloc(&g->pb_coffs, L.coarse_words)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_coffs, L.coarse_words)) return GPMA_ENOMEM;
         g->pb_coffs_words = L.coarse_words;
     }
     if (g->pb_offs_words < L.count_words) {
-        dev_free(g->pb_offs);
+        dev_free(g, g->pb_offs);
         g->pb_offs_words = 0;
-        if (dev_alloc(&g->pb_offs, L.count_words)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_offs, L.count_words)) return GPMA_ENOMEM;
         g->pb_offs_words = L.count_words;
     }
     const uint64_t tw = scan_tmp_words(std::max(L.count_words, L.coarse_words));
     if (g->pb_tmp_words < tw) {
-        dev_free(g->pb_tmp);
+        dev_free(g, g->pb_tmp);
         g->pb_tmp_words = 0;
-        if (dev_alloc(&g->pb_tmp, tw)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_tmp, tw)) return GPMA_ENOMEM;
         g->pb_tmp_words = tw;
     }
     if (g->pb_keys_cap < g->cap) {
-        dev_free(g->pb_keys);
+        dev_free(g, g->pb_keys);
         g->pb_keys_cap = 0;
-        if (dev_alloc(&g->pb_keys, g->cap)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_keys, g->cap)) return GPMA_ENOMEM;
         g->pb_keys_cap = g->cap;
     }
     if (g->pb_ne_cap < L.W) {
-        dev_free(g->pb_ne);
+        dev_free(g, g->pb_ne);
         g->pb_ne_cap = 0;
-        if (dev_alloc(&g->pb_ne, L.W)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_ne, L.W)) return GPMA_ENOMEM;
         g->pb_ne_cap = L.W;
     }
     if (g->pb_pieces_cap < L.max_pieces) {
-        dev_free(g->pb_pieces);
+        dev_free(g, g->pb_pieces);
         g->pb_pieces_cap = 0;
         const uint64_t want = L.max_pieces + L.max_pieces / 4;
-        if (dev_alloc(&g->pb_pieces, want)) return GPMA_ENOMEM;
+        if (dev_alloc(g, &g->pb_pieces, want)) return GPMA_ENOMEM;
         g->pb_pieces_cap = want;
     }
     return GPMA_OK;
@@ -1827,13 +2048,14 @@ int ensure_pb(gpma *g, const PbLayout &L) {
 int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, float damping,
                   hipStream_t s) {
     if (!g || !out || iters == 0 || !(damping > 0.f && damping < 1.f)) return GPMA_EINVAL;
+    set_stream(g, s);
     if (!g->pr_contrib) {
         int e = GPMA_OK;
-        e |= dev_alloc(&g->pr_contrib, g->V);
-        e |= dev_alloc(&g->pr_y, g->V);
-        e |= dev_alloc(&g->pr_dang, 1);
+        e |= dev_alloc(g, &g->pr_contrib, g->V);
+        e |= dev_alloc(g, &g->pr_y, g->V);
+        e |= dev_alloc(g, &g->pr_dang, 1);
         if (e) {
-            dev_free(g->pr_contrib); dev_free(g->pr_y); dev_free(g->pr_dang);
+            dev_free(g, g->pr_contrib); dev_free(g, g->pr_y); dev_free(g, g->pr_dang);
             return GPMA_ENOMEM;
         }
     }
@@ -1843,11 +2065,15 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
     const double spmv_bytes = 8.0 * (double)g->n + 2.0 * (double)(g->cap >> g->lf_log2) + 28.0 * (double)g->V;
     const int mode = spmv_mode(g);
     PbLayout L;
-    if (mode == kSpmvBinned) {
-        L = pb_layout(g->V, g->cap, g->lf_log2, g->n);
+    if (mode == kSpmvBinned || mode == kSpmvGather) {
+        L = pb_layout(g->V, g->cap, g->lf_log2, g->n, g->spmv_form == GPMA_SPMV_BINNED_COARSE);
         if (int e = ensure_pb(g, L)) return e;
         launch_pb_structure(g->slots, L, g->pb_keys, g->pb_ne, g->pb_offs, g->pb_small, g->pb_tmp, g->pb_pieces,
                             g->pb_small + 1, g->pb_coffs, s);
+        // the gather form bins the edges once per call (records name their
+        // source); every iteration then reads each record once
+        if (mode == kSpmvGather)
+            launch_pb_bin(g->pb_keys, g->pb_ne, L, g->pb_offs, g->pb_small, nullptr, g->pb_rec, true, s);
     }
     for (uint32_t it = 0; it < iters; it++) {
         const float *x = it == 0 ? init : out;
@@ -1857,6 +2083,8 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
             if (mode == kSpmvBinned)
                 launch_pb_spmv(g->pb_keys, g->pb_ne, L, g->pb_offs, g->pb_small, g->pb_pieces,
                                g->pb_small + 1, g->pb_coffs, g->pr_contrib, g->pb_rec, g->pb_rec2, g->V, g->pr_y, s);
+            else if (mode == kSpmvGather)
+                launch_pb_gather(L, g->pb_pieces, g->pb_small + 1, g->pr_contrib, g->pb_rec, g->V, g->pr_y, s);
             else if (mode == kSpmvPull)
                 launch_pr_pull(g->mir->slots, g->mir->cnt, g->mir->cap, g->mir->lf_log2, g->pr_contrib,
                                g->pr_y, s);
@@ -1869,21 +2097,18 @@ int gpma_pagerank(gpma_t *g, const float *init, float *out, uint32_t iters, floa
     return GPMA_OK;
 }
 
-int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
-    if (!g || !dist || source >= g->V) return GPMA_EINVAL;
-    if (!g->bfs_q0) {
-        int e = GPMA_OK;
-        e |= dev_alloc(&g->bfs_q0, g->V);
-        e |= dev_alloc(&g->bfs_q1, g->V);
-        e |= dev_alloc(&g->bfs_off, g->V);
-        e |= dev_alloc(&g->bfs_tmp, scan_tmp_words(g->V));
-        if (e) {
-            dev_free(g->bfs_q0); dev_free(g->bfs_q1); dev_free(g->bfs_off); dev_free(g->bfs_tmp);
-            return GPMA_ENOMEM;
-        }
-    }
-    uint32_t *cur = g->bfs_q0, *nxt = g->bfs_q1;
-    launch_bfs_init(dist, g->V, source, cur, g->small, s);
+}  // extern "C"
+
+namespace {
+
+// BFS levels (Section 4.2, Algorithm "Breadth-First Search") with the
+// caller's scratch: two frontier queues and the row-length scan (V words
+// each), the scan's tmp (scan_tmp_words(V)) and 4 counter words (0: the
+// frontier count, 1: the next frontier's count, 3: the scan total).
+int bfs_run(gpma *g, uint32_t source, int32_t *dist, hipStream_t s, uint32_t *q0, uint32_t *q1, uint32_t *off,
+            uint32_t *tmp, uint32_t *counters) {
+    uint32_t *cur = q0, *nxt = q1;
+    launch_bfs_init(dist, g->V, source, cur, counters, s);
     uint32_t nfront = 1;
     // Direction choice (with a mirror): expand top-down while the frontier's
     // rows are a small part of the rows not yet expanded; go bottom-up over
@@ -1891,15 +2116,15 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
     // of the vertices (the usual direction-optimising rule).
     uint64_t unexplored = g->n;
     for (int32_t level = 0; nfront > 0; level++) {
-        hipMemsetAsync(g->small + 1, 0, sizeof(uint32_t), s);
+        if (hipMemsetAsync(counters + 1, 0, sizeof(uint32_t), s) != hipSuccess) return GPMA_EDEVICE;
         bool bottom_up = g->mir && (uint64_t)nfront * 64 >= g->V;
         if (!bottom_up) {
             // rows of the frontier end to end: lengths and their scan
-            launch_bfs_row_len(g->row_ptr, cur, nfront, g->bfs_off, s);
-            scan_u32(g->bfs_off, g->bfs_off, nfront, g->small + 3, g->bfs_tmp, s);
+            launch_bfs_row_len(g->row_ptr, cur, nfront, off, s);
+            scan_u32(off, off, nfront, counters + 3, tmp, s);
             if (g->mir) {
-                hipMemcpyAsync(g->small_h + 1, g->small + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-                hipStreamSynchronize(s);
+                hipMemcpyAsync(g->small_h + 1, counters + 3, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+                if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
                 const uint64_t mf = g->small_h[1];
                 bottom_up = mf * 14 > unexplored;
                 if (!bottom_up) unexplored = unexplored > mf ? unexplored - mf : 0;
@@ -1908,22 +2133,44 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
         {
             ProfScope ps(g, GPMA_K_BFS, s);
             if (bottom_up) {
-                launch_bfs_bottom_up(g->mir->slots, g->mir->row_ptr, g->V, level, dist, nxt, g->small + 1, s);
+                launch_bfs_bottom_up(g->mir->slots, g->mir->row_ptr, g->V, level, dist, nxt, counters + 1, s);
             } else {
-                launch_bfs_expand(g->slots, g->row_ptr, cur, g->bfs_off, nfront, g->small + 3, g->cap,
-                                  level, dist, nxt, g->small + 1, s);
+                launch_bfs_expand(g->slots, g->row_ptr, cur, off, nfront, counters + 3, g->cap, level, dist, nxt,
+                                  counters + 1, s);
             }
         }
-        hipMemcpyAsync(g->small_h, g->small + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-        hipStreamSynchronize(s);
+        hipMemcpyAsync(g->small_h, counters + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
         nfront = g->small_h[0];
         std::swap(cur, nxt);
     }
     return GPMA_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
+    if (!g || !dist || source >= g->V) return GPMA_EINVAL;
+    set_stream(g, s);
+    if (!g->bfs_q0) {
+        int e = GPMA_OK;
+        e |= dev_alloc(g, &g->bfs_q0, g->V);
+        e |= dev_alloc(g, &g->bfs_q1, g->V);
+        e |= dev_alloc(g, &g->bfs_off, g->V);
+        e |= dev_alloc(g, &g->bfs_tmp, scan_tmp_words(g->V));
+        if (e) {
+            dev_free(g, g->bfs_q0); dev_free(g, g->bfs_q1); dev_free(g, g->bfs_off); dev_free(g, g->bfs_tmp);
+            return GPMA_ENOMEM;
+        }
+    }
+    return bfs_run(g, source, dist, s, g->bfs_q0, g->bfs_q1, g->bfs_off, g->bfs_tmp, g->small);
+}
+
 int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
     if (!g || !label) return GPMA_EINVAL;
+    set_stream(g, s);
     launch_cc_init(label, g->V, s);
     if (g->mir && g->V >= 4096) {
         // sample one out- and one in-neighbour per vertex, find the largest
@@ -1933,7 +2180,7 @@ int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {
         launch_cc_sample(g->slots, g->row_ptr, g->V, g->lf, label, s);
         launch_cc_sample(g->mir->slots, g->mir->row_ptr, g->V, g->lf, label, s);
         launch_cc_compress(label, g->V, s);
-        if (!g->cc_pick && dev_alloc(&g->cc_pick, 1024)) return GPMA_ENOMEM;
+        if (!g->cc_pick && dev_alloc(g, &g->cc_pick, 1024)) return GPMA_ENOMEM;
         std::vector<uint32_t> smp(1024);
         launch_cc_pick(label, g->V / 1024, 1024, g->cc_pick, s);
         hipMemcpyAsync(smp.data(), g->cc_pick, 1024 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);

@@ -64,14 +64,23 @@ __device__ __forceinline__ bool contains_u64(PtrT a, uint32_t n, uint64_t k) {
     return i < n && a[i] == k;
 }
 
-// Even re-dispatch of N ranked entries over P leaves: leaf j holds ranks
-// [floor(jN/P), floor((j+1)N/P)).  Rank r therefore sits in leaf
-// ceil((r+1)P/N) - 1 at offset r - floor(leaf*N/P).
-__device__ __forceinline__ uint64_t leaf_start(uint64_t j, uint64_t N, uint64_t P) {
-    return (uint64_t)(((unsigned __int128)j * N) / P);
+// Even re-dispatch of N ranked entries over P = 2^h leaves: leaf j holds
+// ranks [floor(jN/P), floor((j+1)N/P)).  Rank r therefore sits in leaf
+// ceil((r+1)P/N) - 1 at offset r - floor(leaf*N/P).  P is a power of two,
+// so the leaf starts are shifts (j*N < 2^58: j < 2^27 leaves, N < 2^31).
+__device__ __forceinline__ uint64_t leaf_start(uint64_t j, uint64_t N, uint32_t h) {
+    return (j * N) >> h;
 }
-__device__ __forceinline__ uint64_t rank_leaf(uint64_t r, uint64_t N, uint64_t P) {
-    return (uint64_t)((((unsigned __int128)(r + 1)) * P - 1) / N);
+// The leaf of rank r: an fp64 quotient (relative error ~2^-52 on a value
+// below 2^27, so off by at most one) corrected against the leaf starts.
+__device__ __forceinline__ uint64_t rank_leaf(uint64_t r, uint64_t N, uint32_t h) {
+    const uint64_t num = ((r + 1) << h) - 1;
+    uint64_t j = (uint64_t)((double)num / (double)N);
+    const uint64_t P = 1ull << h;
+    if (j >= P) j = P - 1;
+    while (j > 0 && leaf_start(j, N, h) > r) j--;
+    while (j + 1 < P && leaf_start(j + 1, N, h) <= r) j++;
+    return j;
 }
 
 // wave-level ordering of LDS traffic between lanes of one wave
@@ -245,7 +254,7 @@ struct PbLayout {
     uint64_t coarse_words = 0; // nc * W
 };
 bool pb_supported(uint32_t V);
-PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_entries);
+PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_entries, bool coarse);
 // per call: count matrix, its scan (offs, total edges), the piece table, the
 // scanned coarse count matrix (coffs, when nc > 0), and each slot range's
 // edges packed at keys[w*spw ..] (cap words), ne[w] of them (W words)
@@ -257,6 +266,13 @@ void launch_pb_spmv(const uint64_t *keys, const uint32_t *ne, const PbLayout &L,
                     const uint32_t *offs, const uint32_t *total, const uint4 *pieces, const uint32_t *npieces,
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s);
+// the bin pass alone (fine bins, nc == 0): records of contributions, or
+// (src_records) of source vertices, written once per call
+void launch_pb_bin(const uint64_t *keys, const uint32_t *ne, const PbLayout &L, const uint32_t *offs,
+                   const uint32_t *total, const double *contrib, uint64_t *rec, bool src_records, hipStream_t s);
+// per iteration over source records: y (zeroed beforehand) += A^T contrib
+void launch_pb_gather(const PbLayout &L, const uint4 *pieces, const uint32_t *npieces, const double *contrib,
+                      const uint64_t *rec, uint32_t V, double *y, hipStream_t s);
 void launch_bfs_init(int32_t *dist, uint32_t V, uint32_t source, uint32_t *queue,
                      uint32_t *qcount, hipStream_t s);
 void launch_bfs_row_len(const uint32_t *row_ptr, const uint32_t *front, uint32_t nfront, uint32_t *len,

@@ -114,8 +114,8 @@ k_lock_try(uint32_t h, uint32_t H, const uint64_t *__restrict__ keys, uint32_t *
     const uint64_t N = at + 1;
     for (uint64_t p = lane; p < cap_h; p += kWave) {
         const uint64_t j = p >> lf_log2, o = p & (lf - 1);
-        const uint64_t st = leaf_start(j, N, P);
-        const uint64_t cj = leaf_start(j + 1, N, P) - st;
+        const uint64_t st = leaf_start(j, N, h);
+        const uint64_t cj = leaf_start(j + 1, N, h) - st;
         const uint64_t v = o < cj ? scratch[base + st + o] : kEmpty;
         slots[base + p] = v;
         if (o == 0) {

@@ -331,8 +331,8 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
 
     const uint64_t N = DEL ? (uint64_t)ns - k : (uint64_t)ns + k;
     auto put = [&](uint64_t r, uint64_t v) {
-        uint64_t j = rank_leaf(r, N, P);
-        uint64_t pos = base + (j << lf_log2) + (r - leaf_start(j, N, P));
+        uint64_t j = rank_leaf(r, N, h);
+        uint64_t pos = base + (j << lf_log2) + (r - leaf_start(j, N, h));
         slots[pos] = v;
         if (is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(pos + 1);
     };
@@ -353,7 +353,7 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
     }
     for (uint64_t p = threadIdx.x; p < cap_h; p += blockDim.x) {
         uint64_t j = p >> lf_log2, o = p & (lf - 1);
-        uint64_t cj = leaf_start(j + 1, N, P) - leaf_start(j, N, P);
+        uint64_t cj = leaf_start(j + 1, N, h) - leaf_start(j, N, h);
         if (o >= cj) slots[base + p] = kEmpty;
         if (o == 0) {
             cnt[first_leaf + j] = (uint16_t)cj;
@@ -463,8 +463,9 @@ __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t 
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (P << lf_log2)) return;
     uint64_t j = p >> lf_log2, o = p & ((1u << lf_log2) - 1);
-    uint64_t st = leaf_start(j, N, P);
-    uint64_t cj = leaf_start(j + 1, N, P) - st;
+    const uint32_t h = 63 - __clzll(P);   // P is a power of two
+    uint64_t st = leaf_start(j, N, h);
+    uint64_t cj = leaf_start(j + 1, N, h) - st;
     uint64_t pos = (first_leaf << lf_log2) + p;
     uint64_t v = o < cj ? M[st + o] : kEmpty;
     slots[pos] = v;

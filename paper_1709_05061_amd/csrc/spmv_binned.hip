@@ -197,8 +197,20 @@ k_pb_pieces(const uint32_t *__restrict__ offs, const uint32_t *__restrict__ tota
     if (threadIdx.x == 0) *npieces = carry;
 }
 
+// A record: the destination's offset in its bin in the low `bits` bits and,
+// above them, either the contribution's fp64 bits (SRC = false: written
+// every iteration) or the source vertex (SRC = true: written once per call,
+// the iterations fetch contrib[source]).
+template <bool SRC>
+__device__ __forceinline__ uint64_t make_record(uint64_t key, uint64_t contrib_bits, uint64_t mask) {
+    const uint32_t d = key_dst(key);
+    if (SRC) return ((uint64_t)key_src(key) << kBinBits) | (d & mask);
+    return (contrib_bits & ~mask) | (d & mask);
+}
+
 // Bin pass for at most 64 bins (or coarse bins) of 2^bits destinations;
 // cur starts at offs[b*W + w]; places are reserved per wave (ballots).
+template <bool SRC>
 __global__ void __launch_bounds__(kCountThreads)
 k_pb_bin(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ne, uint64_t spw,
          uint32_t nb, uint32_t W, uint32_t bits, const uint32_t *__restrict__ offs,
@@ -208,14 +220,14 @@ k_pb_bin(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ne, uin
     __syncthreads();
     const uint64_t mask = (1ull << bits) - 1;
     for_each_pair_chunk(keys + (uint64_t)blockIdx.x * spw, ne[blockIdx.x], [&](const uint64_t (&k)[2 * kUnroll]) {
-        uint64_t v[2 * kUnroll];
-        pair_contribs(k, contrib, v);
+        uint64_t v[2 * kUnroll] = {};
+        if (!SRC) pair_contribs(k, contrib, v);
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++) {
             const bool ok = is_edge(k[j]);
             const uint32_t d = key_dst(k[j]);
             const uint32_t pos = reserve_in_bin(cur, ok ? d >> bits : 0u, ok);
-            if (ok) rec[pos] = (v[j] & ~mask) | (d & mask);   // plain store: L2 merges a run's partial lines
+            if (ok) rec[pos] = make_record<SRC>(k[j], v[j], mask);   // plain store: L2 merges a run's partial lines
         }
     });
 }
@@ -241,6 +253,7 @@ __host__ __device__ inline uint32_t stage_records(uint32_t lds_bytes, uint32_t n
     return lds_bytes > meta ? (lds_bytes - meta) / (uint32_t)sizeof(uint64_t) : 0u;
 }
 
+template <bool SRC>
 __global__ void __launch_bounds__(kStageThreads)
 k_pb_bin_quiet(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ ne, uint64_t spw,
                uint32_t nb, uint32_t W, const uint32_t *__restrict__ offs, const uint32_t *__restrict__ total,
@@ -272,14 +285,14 @@ k_pb_bin_quiet(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n
     }
     __syncthreads();
     for_each_pair_chunk(keys + (uint64_t)blockIdx.x * spw, ne[blockIdx.x], [&](const uint64_t (&k)[2 * kUnroll]) {
-        uint64_t v[2 * kUnroll];
-        pair_contribs(k, contrib, v);
+        uint64_t v[2 * kUnroll] = {};
+        if (!SRC) pair_contribs(k, contrib, v);
 #pragma unroll
         for (int j = 0; j < 2 * kUnroll; j++) {
             if (!is_edge(k[j])) continue;
             const uint32_t d = key_dst(k[j]);
             const uint32_t b = d >> kBinBits;
-            const uint64_t r = (v[j] & ~kBinMask) | (d & kBinMask);
+            const uint64_t r = make_record<SRC>(k[j], v[j], kBinMask);
             const uint32_t so = soff[b];
             if (so == kDirect) rec[atomicAdd(&cur[b], 1u)] = r;   // plain store: L2 merges a busy run's lines
             else stage[so + atomicAdd(&fill[b], 1u)] = r;
@@ -349,27 +362,38 @@ k_pb_split(const uint64_t *__restrict__ rec1, const uint32_t *__restrict__ coffs
     }
 }
 
+// The value a record adds: its own high bits (SRC = false) or the
+// contribution of the source it names (SRC = true).
+template <bool SRC>
+__device__ __forceinline__ double record_value(uint64_t r, const double *__restrict__ contrib) {
+    if (SRC) return contrib[r >> kBinBits];
+    return __longlong_as_double((long long)(r & ~kBinMask));
+}
+
+template <bool SRC>
 __global__ void __launch_bounds__(kAccThreads)
 k_pb_accum(const uint64_t *__restrict__ rec, const uint4 *__restrict__ pieces, const uint32_t *__restrict__ npieces,
-           uint32_t V, double *__restrict__ y) {
+           uint32_t V, const double *__restrict__ contrib, double *__restrict__ y) {
     extern __shared__ double acc[];   // kBinWidth doubles
     if (blockIdx.x >= *npieces) return;
     const uint4 pc = pieces[blockIdx.x];
     for (uint32_t j = threadIdx.x; j < kBinWidth; j += kAccThreads) acc[j] = 0.0;
     __syncthreads();
-    constexpr uint32_t kU = 4;
+    constexpr uint32_t kU = SRC ? 8 : 4;
     uint64_t i = (uint64_t)pc.x + threadIdx.x;
     for (; i + (kU - 1) * kAccThreads < pc.y; i += kU * kAccThreads) {
         uint64_t r[kU];
 #pragma unroll
         for (uint32_t u = 0; u < kU; u++) r[u] = ld_nt(rec + i + u * kAccThreads);
+        double c[kU];
 #pragma unroll
-        for (uint32_t u = 0; u < kU; u++)
-            atomicAdd(&acc[r[u] & kBinMask], __longlong_as_double((long long)(r[u] & ~kBinMask)));
+        for (uint32_t u = 0; u < kU; u++) c[u] = record_value<SRC>(r[u], contrib);
+#pragma unroll
+        for (uint32_t u = 0; u < kU; u++) atomicAdd(&acc[r[u] & kBinMask], c[u]);
     }
     for (; i < pc.y; i += kAccThreads) {
         const uint64_t r = ld_nt(rec + i);
-        atomicAdd(&acc[r & kBinMask], __longlong_as_double((long long)(r & ~kBinMask)));
+        atomicAdd(&acc[r & kBinMask], record_value<SRC>(r, contrib));
     }
     __syncthreads();
     const uint64_t v0 = (uint64_t)pc.z << kBinBits;
@@ -398,26 +422,29 @@ bool pb_supported(uint32_t V) {
         hipGetDevice(&dev);
         hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         ok = (size_t)max_lds >= bytes &&
-             hipFuncSetAttribute((const void *)k_pb_accum, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
-                 hipSuccess;
+             hipFuncSetAttribute((const void *)k_pb_accum<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)bytes) == hipSuccess &&
+             hipFuncSetAttribute((const void *)k_pb_accum<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)bytes) == hipSuccess;
         // the bin pass stages in what is left of the workgroup's LDS after its scan words
         const int stage = max_lds - (int)((kStageThreads / kWave + 1) * sizeof(uint32_t)) - 256;
         ok = ok && stage > 0 &&
-             hipFuncSetAttribute((const void *)k_pb_bin_quiet, hipFuncAttributeMaxDynamicSharedMemorySize, stage) ==
-                 hipSuccess;
+             hipFuncSetAttribute((const void *)k_pb_bin_quiet<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 stage) == hipSuccess &&
+             hipFuncSetAttribute((const void *)k_pb_bin_quiet<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 stage) == hipSuccess;
         if (ok) g_stage_lds = stage;
         if (!ok) (void)hipGetLastError();
     }
     return ok && div_up(V, kBinWidth) <= kMaxBins;
 }
 
-PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges) {
+PbLayout pb_layout(uint32_t V, uint64_t cap, uint32_t lf_log2, uint64_t n_edges, bool coarse) {
     PbLayout L;
     L.nb = (uint32_t)div_up(V, kBinWidth);
-    // bins are written directly; GPMA_PB_LEVELS=2 routes them through coarse
-    // bins of 64 first (same result; faster where scattered stores are dear)
-    const char *lv = getenv("GPMA_PB_LEVELS");
-    L.nc = (lv && atoi(lv) == 2 && L.nb > (1u << kSplitBits)) ? (uint32_t)div_up(V, 1ull << kCoarseBits) : 0;
+    // bins are written directly; `coarse` routes them through coarse bins of
+    // 64 first (same result; faster where scattered stores are dear)
+    L.nc = (coarse && L.nb > (1u << kSplitBits)) ? (uint32_t)div_up(V, 1ull << kCoarseBits) : 0;
     uint64_t spw = cap / kRanges;
     const uint64_t lf = 1ull << lf_log2;
     if (spw < lf) spw = lf;
@@ -449,22 +476,43 @@ void launch_pb_spmv(const uint64_t *keys, const uint32_t *ne, const PbLayout &L,
                     const uint32_t *coffs, const double *contrib, uint64_t *rec, uint64_t *rec2, uint32_t V,
                     double *y, hipStream_t s) {
     if (L.nc) {
-        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nc, L.W,
+        hipLaunchKernelGGL(k_pb_bin<false>, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nc, L.W,
                            kCoarseBits, coffs, contrib, rec);
         hipLaunchKernelGGL(k_pb_split, dim3((uint32_t)L.coarse_words), dim3(kCountThreads), 0, s, rec, coffs, total,
                            offs, L.nb, L.nc, L.W, rec2);
         rec = rec2;
-    } else if (L.nb <= (1u << kSplitBits)) {
-        hipLaunchKernelGGL(k_pb_bin, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nb, L.W,
-                           kBinBits, offs, contrib, rec);
     } else {
-        const uint32_t ns = stage_records((uint32_t)g_stage_lds, L.nb);
-        const size_t lds = (size_t)ns * sizeof(uint64_t) + 3 * (size_t)L.nb * sizeof(uint32_t);
-        hipLaunchKernelGGL(k_pb_bin_quiet, dim3(L.W), dim3(kStageThreads), lds, s, keys, ne, L.spw, L.nb,
-                           L.W, offs, total, contrib, rec, ns);
+        launch_pb_bin(keys, ne, L, offs, total, contrib, rec, false, s);
     }
-    hipLaunchKernelGGL(k_pb_accum, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double), s, rec,
-                       pieces, npieces, V, y);
+    hipLaunchKernelGGL(k_pb_accum<false>, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double),
+                       s, rec, pieces, npieces, V, contrib, y);
+}
+
+void launch_pb_bin(const uint64_t *keys, const uint32_t *ne, const PbLayout &L, const uint32_t *offs,
+                   const uint32_t *total, const double *contrib, uint64_t *rec, bool src_records, hipStream_t s) {
+    if (L.nb <= (1u << kSplitBits)) {
+        if (src_records)
+            hipLaunchKernelGGL(k_pb_bin<true>, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nb, L.W,
+                               kBinBits, offs, contrib, rec);
+        else
+            hipLaunchKernelGGL(k_pb_bin<false>, dim3(L.W), dim3(kCountThreads), 0, s, keys, ne, L.spw, L.nb, L.W,
+                               kBinBits, offs, contrib, rec);
+        return;
+    }
+    const uint32_t ns = stage_records((uint32_t)g_stage_lds, L.nb);
+    const size_t lds = (size_t)ns * sizeof(uint64_t) + 3 * (size_t)L.nb * sizeof(uint32_t);
+    if (src_records)
+        hipLaunchKernelGGL(k_pb_bin_quiet<true>, dim3(L.W), dim3(kStageThreads), lds, s, keys, ne, L.spw, L.nb, L.W,
+                           offs, total, contrib, rec, ns);
+    else
+        hipLaunchKernelGGL(k_pb_bin_quiet<false>, dim3(L.W), dim3(kStageThreads), lds, s, keys, ne, L.spw, L.nb, L.W,
+                           offs, total, contrib, rec, ns);
+}
+
+void launch_pb_gather(const PbLayout &L, const uint4 *pieces, const uint32_t *npieces, const double *contrib,
+                      const uint64_t *rec, uint32_t V, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_pb_accum<true>, dim3((uint32_t)L.max_pieces), dim3(kAccThreads), kBinWidth * sizeof(double),
+                       s, rec, pieces, npieces, V, contrib, y);
 }
 
 }  // namespace gpma_host

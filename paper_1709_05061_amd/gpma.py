@@ -23,6 +23,8 @@ GPMA_FLAG_MIRROR = 1
 GPMA_FLAG_LEARNED_LOCATOR = 2
 GPMA_FLAG_FUSED_DIRECT = 4
 GPMA_FLAG_LAZY_DELETE = 8
+GPMA_FLAG_FUSED_LIB_STREAMS = 16
+SPMV_FORMS = {"auto": 0, "binned": 1, "binned_coarse": 2, "pull": 3, "push": 4, "binned_gather": 5}
 EMPTY = 0xFFFFFFFFFFFFFFFF
 GUARD_DST = 0xFFFFFFFF
 
@@ -34,13 +36,65 @@ KERNEL_NAMES = ["spmv", "leaf_merge", "seg_merge", "sort", "locate", "bfs_expand
 class gpma_params(C.Structure):
     _fields_ = [("leaf_size", C.c_uint32), ("tau_leaf_pm", C.c_uint32), ("tau_root_pm", C.c_uint32),
                 ("rho_leaf_pm", C.c_uint32), ("rho_root_pm", C.c_uint32), ("flags", C.c_uint32),
-                ("sort_tile_keys", C.c_uint32), ("fused_levels", C.c_uint32)]
+                ("sort_tile_keys", C.c_uint32), ("fused_levels", C.c_uint32),
+                ("lds_tier_bytes", C.c_uint32), ("spmv_form", C.c_uint32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class gpma_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class TorchAllocator:
+    """Device memory of a handle from PyTorch's caching allocator, so the
+    library's arrays share torch's pool (and its accounting) on the stream of
+    the call that allocates them.  held_bytes counts what the library holds
+    through this allocator; a failed allocation returns NULL, which the
+    library turns into GPMA_ENOMEM with nothing changed.  Keep the object
+    alive as long as a handle created with it."""
+
+    def __init__(self, device=None):
+        self.device = torch.cuda.current_device() if device is None else device
+        self.held_bytes = 0
+        self.peak_bytes = 0
+        self._sizes = {}
+        self._alloc_cb = ALLOC_FN(self._alloc)
+        self._free_cb = FREE_FN(self._free)
+        self.struct = gpma_allocator(self._alloc_cb, self._free_cb, None)
+
+    def allow(self, nbytes: int) -> bool:
+        """Whether an allocation of nbytes may be made (a subclass may
+        refuse, e.g. to keep an HBM budget)."""
+        return True
+
+    def _alloc(self, nbytes, stream, ctx):
+        try:
+            if not self.allow(int(nbytes)):
+                return None
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+        except Exception:
+            return None
+        self._sizes[ptr] = int(nbytes)
+        self.held_bytes += int(nbytes)
+        self.peak_bytes = max(self.peak_bytes, self.held_bytes)
+        return ptr
+
+    def _free(self, ptr, nbytes, stream, ctx):
+        try:
+            self.held_bytes -= self._sizes.pop(ptr, int(nbytes))
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
 
 
 class gpma_stats(C.Structure):
     _fields_ = [("requested", C.c_uint64), ("applied", C.c_uint64), ("noops", C.c_uint64),
                 ("top_level", C.c_int32), ("resized", C.c_uint32),
-                ("segments_merged", C.c_uint64 * 40), ("slots_rewritten", C.c_uint64)]
+                ("segments_merged", C.c_uint64 * 40), ("slots_rewritten", C.c_uint64),
+                ("mirror_slots_rewritten", C.c_uint64)]
 
 
 class GpmaError(RuntimeError):
@@ -65,7 +119,10 @@ def load_library() -> C.CDLL:
     pu64 = C.POINTER(u64)
     sig = {
         "gpma_default_params": (None, [C.POINTER(gpma_params)]),
-        "gpma_create": (C.c_int, [C.POINTER(vp), u32, vp, u64, C.POINTER(gpma_params), vp]),
+        "gpma_create": (C.c_int, [C.POINTER(vp), u32, vp, u64, C.POINTER(gpma_params),
+                                  C.POINTER(gpma_allocator), vp]),
+        "gpma_fused_pairing": (C.c_int, [vp, vp]),
+        "gpma_allocated_bytes": (u64, [vp]),
         "gpma_destroy": (C.c_int, [vp]),
         "gpma_insert_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
         "gpma_delete_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
@@ -121,7 +178,8 @@ def exported_symbols() -> List[str]:
             "gpma_locator_refit", "gpma_locator_info",
             "gpma_profile_enable",
             "gpma_profile_reset", "gpma_profile_read", "gpma_csr_create", "gpma_csr_destroy",
-            "gpma_csr_update", "gpma_csr_num_edges", "gpma_csr_export", "gpma_lock_insert_batch"]
+            "gpma_csr_update", "gpma_csr_num_edges", "gpma_csr_export", "gpma_lock_insert_batch",
+            "gpma_fused_pairing", "gpma_allocated_bytes"]
 
 
 def strerror(code: int) -> str:
@@ -160,12 +218,13 @@ def gpma_default_params() -> gpma_params:
 
 
 def gpma_create(num_vertices: int, init_keys: torch.Tensor, params: Optional[gpma_params] = None,
-                stream=None) -> C.c_void_p:
+                stream=None, allocator: Optional[TorchAllocator] = None) -> C.c_void_p:
     lib = load_library()
     h = C.c_void_p()
     k = _dev_u64(init_keys)
     rc = lib.gpma_create(C.byref(h), num_vertices, C.c_void_p(k.data_ptr()), k.numel(),
-                         C.byref(params) if params is not None else None, _stream(stream))
+                         C.byref(params) if params is not None else None,
+                         C.byref(allocator.struct) if allocator is not None else None, _stream(stream))
     _check(rc, "gpma_create")
     return h
 
@@ -255,6 +314,7 @@ class BatchStats:
     resized: bool
     segments_merged: List[int] = field(default_factory=list)
     slots_rewritten: int = 0
+    mirror_slots_rewritten: int = 0
 
     @classmethod
     def of(cls, st: gpma_stats) -> "BatchStats":
@@ -262,7 +322,7 @@ class BatchStats:
         while segs and segs[-1] == 0:
             segs.pop()
         return cls(st.requested, st.applied, st.noops, st.top_level, bool(st.resized), segs,
-                   st.slots_rewritten)
+                   st.slots_rewritten, st.mirror_slots_rewritten)
 
 
 class _HandleView:
@@ -328,16 +388,28 @@ class GPMA(_HandleView):
     batch sort's keys per workgroup tile (512, 1024 or 2048; 0 = 1024);
     fused_levels is how many tree levels above the leaves a fused batch runs
     on the device before the host takes over (0..3); lazy_delete makes
-    deletes mark their entries in place (GPMA_FLAG_LAZY_DELETE)."""
+    deletes mark their entries in place (GPMA_FLAG_LAZY_DELETE); lds_tier
+    caps the LDS bytes of the workgroup merge tier (0 = all; 1 sends every
+    level above the leaves to the device tier); spmv picks PageRank's SpMV
+    (a key of SPMV_FORMS); lib_streams forces fused batching with a mirror
+    onto two handle streams.  allocator: a TorchAllocator (the default: a new
+    one per handle, so the library's memory comes from torch's caching
+    allocator), or False for the library's own hipMalloc."""
 
     def __init__(self, num_vertices: int, init_keys: torch.Tensor, leaf_size: int = 0,
                  tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, mirror: bool = False,
                  learned: bool = False, stream=None, fused_direct: bool = False, sort_tile: int = 0,
-                 fused_levels: int = 1, lazy_delete: bool = False):
+                 fused_levels: int = 1, lazy_delete: bool = False, lds_tier: int = 0, spmv: str = "auto",
+                 lib_streams: bool = False, allocator=None):
         flags = ((GPMA_FLAG_MIRROR if mirror else 0) | (GPMA_FLAG_LEARNED_LOCATOR if learned else 0)
-                 | (GPMA_FLAG_FUSED_DIRECT if fused_direct else 0) | (GPMA_FLAG_LAZY_DELETE if lazy_delete else 0))
-        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags, sort_tile, fused_levels)
-        super().__init__(gpma_create(num_vertices, init_keys, p, stream), num_vertices)
+                 | (GPMA_FLAG_FUSED_DIRECT if fused_direct else 0) | (GPMA_FLAG_LAZY_DELETE if lazy_delete else 0)
+                 | (GPMA_FLAG_FUSED_LIB_STREAMS if lib_streams else 0))
+        p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags, sort_tile, fused_levels,
+                        lds_tier, SPMV_FORMS[spmv])
+        if allocator is None:
+            allocator = TorchAllocator()
+        self.allocator = allocator or None
+        super().__init__(gpma_create(num_vertices, init_keys, p, stream, self.allocator), num_vertices)
 
     def close(self):
         if getattr(self, "h", None):
@@ -349,6 +421,17 @@ class GPMA(_HandleView):
             self.close()
         except Exception:
             pass
+
+    @property
+    def allocated_bytes(self) -> int:
+        """Device bytes the handle and its mirror hold from their allocator."""
+        return int(self._lib.gpma_allocated_bytes(self.h))
+
+    def fused_pairing(self, stream=None) -> int:
+        """1: fused batching keeps the array's pipeline on `stream` with the
+        mirror's beside it; 0: both on handle streams; GPMA_EINVAL: no mirror
+        or no fused call on that stream yet."""
+        return int(self._lib.gpma_fused_pairing(self.h, _stream(stream)))
 
     def locate(self, keys: torch.Tensor, stream=None) -> torch.Tensor:
         """Leaf of each key (learned locator if enabled, else binary search)."""

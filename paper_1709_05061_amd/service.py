@@ -55,7 +55,8 @@ class QueryResult:
 @dataclass
 class ServiceReport:
     batches: int = 0
-    edges_applied: int = 0
+    edges_applied: int = 0          # arrivals taken into the window
+    updates_applied: int = 0        # inserts + deletes that changed the graph
     duration_s: float = 0.0
     edge_latency_s: List[float] = field(default_factory=list)
     queries: List[QueryResult] = field(default_factory=list)
@@ -74,7 +75,8 @@ class ServiceReport:
         return {
             "batches": self.batches,
             "edges_applied": self.edges_applied,
-            "updates_per_s": (2 * self.edges_applied / self.duration_s) if self.duration_s else None,
+            "updates_applied": self.updates_applied,
+            "updates_per_s": (self.updates_applied / self.duration_s) if self.duration_s else None,
             "edge_latency_ms_p50": None if not self.edge_latency_s else 1e3 * self._pct(self.edge_latency_s, 50),
             "edge_latency_ms_p99": None if not self.edge_latency_s else 1e3 * self._pct(self.edge_latency_s, 99),
             "queries": len(self.queries),
@@ -109,9 +111,11 @@ class GraphService:
         self._lib = load_library()
         self.V = V
         self.g = GPMA(V, window, leaf_size=leaf_size, mirror=mirror)
-        self.order = window                 # arrival order: window, then the stream (oldest first)
-        self.head = 0                       # oldest live edge in self.order
-        self.tail = window.numel()          # one past the newest live edge
+        # the live window in arrival order (oldest first), then the arrivals of
+        # the current run: order[head:tail] are live, order[tail:] still to come
+        self.order = window
+        self.head = 0
+        self.tail = window.numel()
         self.max_batch = max_batch
         self.pr_iters = pr_iters
         self.ustream = torch.cuda.Stream()
@@ -143,17 +147,20 @@ class GraphService:
         self.g.close()
 
     # ---- one sliding-window step on the update stream: the k oldest edges
-    # expire, the k arrivals order[tail:tail+k] enter
+    # expire, the k arrivals order[tail:tail+k] enter (Section 3: a sliding
+    # window over the edge stream); returns the step's summed statistics
     def _apply(self, k: int):
         dels = self.order[self.head:self.head + k]
         ins = self.order[self.tail:self.tail + k]
+        assert ins.numel() == k, "arrivals past the end of the stream"
         with torch.cuda.stream(self.ustream):
-            self.g.apply_batches([1, 0], [dels, ins], stream=self.ustream)
+            st = self.g.apply_batches([1, 0], [dels, ins], stream=self.ustream)
         self.head += k
         self.tail += k
         self.version += 1
         if self.record:
             self.batch_log.append((dels.cpu(), ins.cpu()))
+        return st
 
     # ---- a query on a slot
     def _snapshot_into(self, slot: _Slot):
@@ -188,6 +195,10 @@ class GraphService:
         keys, same length); queries: parallel host lists.  Runs until every
         edge is applied and every query answered (or the time limit)."""
         rep = ServiceReport(slots=len(self.slots))
+        # arrival order from here on: the live window, then this run's edges
+        self.order = torch.cat([self.order[self.head:self.tail], edges.to(self.order.device)])
+        self.tail -= self.head
+        self.head = 0
         et = edge_times.numpy()
         ne = len(et)
         nq = len(query_times)
@@ -225,11 +236,12 @@ class GraphService:
             hi = int(np.searchsorted(et, now, side="right"))
             hi = min(hi, applied_to + self.max_batch)
             if hi > applied_to:
-                self._apply(hi - applied_to)
+                st = self._apply(hi - applied_to)
                 done_t = time.perf_counter() - t0
                 rep.edge_latency_s.extend((done_t - et[applied_to:hi]).tolist())
                 rep.batches += 1
                 rep.edges_applied += hi - applied_to
+                rep.updates_applied += st.applied
                 rep.batch_sizes.append(hi - applied_to)
                 applied_to = hi
             elif applied_to >= ne and released_q >= nq and not queue and not running:

@@ -112,20 +112,18 @@ def test_lazy_sliding_window_er(mirror):
     g.close()
 
 
-@pytest.mark.parametrize("tier_lds", [None, "0"])
-def test_lazy_growth_marks_and_recycling(tier_lds, monkeypatch):
+@pytest.mark.parametrize("tier_lds", [0, 1])
+def test_lazy_growth_marks_and_recycling(tier_lds):
     """A small graph grown past several doublings (the root rebuild drops
     marks), most of it deleted (marks only: capacity stays), then the
     deleted keys inserted again (merges recycle marked slots and climb
-    levels); with tier_lds=0 every level above the leaves runs through the
+    levels); with tier_lds=1 every level above the leaves runs through the
     device tier (live-count offsets, ballot gather)."""
-    if tier_lds is not None:
-        monkeypatch.setenv("GPMA_TIER_LDS", tier_lds)
     V, lf = 64, 16
     rng = np.random.default_rng(7)
     allk = np.array([(u << 32) | v for u in range(V) for v in range(V)], dtype=np.uint64)
     rng.shuffle(allk)
-    g, ref = make(V, allk[:40], lf)
+    g, ref = make(V, allk[:40], lf, lds_tier=tier_lds)
     batches = []
     pos = 40
     for sz in [3, 17, 200, 500, 999]:
@@ -232,15 +230,14 @@ def test_lazy_fused_equals_plain(mirror, direct, levels):
     fused.close()
 
 
-@pytest.mark.parametrize("mode", ["binned", "pull", "push"])
-def test_lazy_analytics_skip_marks(mode, monkeypatch):
+@pytest.mark.parametrize("mode", ["binned", "binned_gather", "pull", "push"])
+def test_lazy_analytics_skip_marks(mode):
     """PageRank (every SpMV form), BFS (top-down and, over the mirror,
     bottom-up) and CC (label propagation and the sampling path) over an
     array with many marked entries equal the oracle on the live edges."""
-    monkeypatch.setenv("GPMA_SPMV", mode)
     u = npu64(synth.rmat_unique(13, 16 << 13, seed=8))
     V = 1 << 13
-    g, ref = make(V, u, 32, mirror=mode == "pull")
+    g, ref = make(V, u, 32, mirror=mode == "pull", spmv=mode)
     rng = np.random.default_rng(5)
     d = u[rng.choice(u.size, u.size // 2, replace=False)]
     g.delete(dev(d))

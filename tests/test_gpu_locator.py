@@ -52,8 +52,8 @@ def test_learned_locate_equals_binary_search(kind):
 @pytest.mark.parametrize("mirror", [False, True])
 def test_learned_locator_keeps_layout(mirror):
     """Sliding window with the learned locator (refits after resizes and
-    periodically): slot-identical to the oracle after every batch, plain and
-    fused."""
+    when lookups fall back): slot-identical to the oracle after every batch,
+    plain and fused."""
     from paper_1709_05061_amd import GPMA
     V, lf = 1 << 12, 16
     st = synth.er_stream(V, 1 << 15, 1 << 9, 12, seed=7)

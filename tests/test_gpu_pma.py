@@ -53,11 +53,11 @@ def check_state(g, ref, V):
     return edges
 
 
-def make(V, init, lf, mirror=False, **kw):
+def make(V, init, lf, mirror=False, gpu_kw=None, **kw):
     from paper_1709_05061_amd import GPMA
     init_np = np.asarray(init.numpy() if isinstance(init, torch.Tensor) else init).view(np.uint64) \
         if len(init) else np.zeros(0, np.uint64)
-    g = GPMA(V, dev(init_np), leaf_size=lf, mirror=mirror, **kw)
+    g = GPMA(V, dev(init_np), leaf_size=lf, mirror=mirror, **kw, **(gpu_kw or {}))
     ref = O.OraclePMA(V, init_np, lf, **kw)
     return g, ref
 
@@ -128,18 +128,17 @@ def test_sliding_window_er_2e14():
     g.close()
 
 
-@pytest.mark.parametrize("tier_lds", [None, "0"])
-def test_growth_and_shrink_climbs_levels(tier_lds, monkeypatch):
+@pytest.mark.parametrize("tier_lds", [0, 1])
+def test_growth_and_shrink_climbs_levels(tier_lds):
     """Small graph grown well past several doublings and shrunk back: every
-    level of the tree and the root resize are exercised; with tier_lds=0 the
-    levels above the leaves run through the device tier."""
-    if tier_lds is not None:
-        monkeypatch.setenv("GPMA_TIER_LDS", tier_lds)
+    level of the tree and the root resize are exercised; with the workgroup
+    tier capped at 1 byte of LDS the levels above the leaves run through the
+    device tier."""
     V, lf = 64, 16
     rng = np.random.default_rng(3)
     allk = np.array([(u << 32) | v for u in range(V) for v in range(V)], dtype=np.uint64)
     rng.shuffle(allk)
-    g, ref = make(V, allk[:40], lf)
+    g, ref = make(V, allk[:40], lf, gpu_kw=dict(lds_tier=tier_lds))
     batches = []
     pos = 40
     for sz in [1, 3, 17, 64, 200, 333, 500, 800, 999, 1]:
@@ -327,16 +326,15 @@ def test_mirror_tracks_every_batch(kind):
     g.close()
 
 
-@pytest.mark.parametrize("mode", ["binned", "pull", "push"])
-def test_spmv_modes_match_oracle_on_rmat(mode, monkeypatch):
+@pytest.mark.parametrize("mode", ["binned", "binned_gather", "pull", "push"])
+def test_spmv_modes_match_oracle_on_rmat(mode):
     """All three SpMV forms (destination bins, pull over the mirror, push with
     atomics) on R-MAT scale 13 against the fp64 oracle."""
     from paper_1709_05061_amd import GPMA
-    monkeypatch.setenv("GPMA_SPMV", mode)
     u = np.unique(npu64(synth.rmat_unique(13, 16 << 13, seed=9)))
     V = 1 << 13
-    a = GPMA(V, dev(u), mirror=True)
-    b = GPMA(V, dev(u), mirror=False)
+    a = GPMA(V, dev(u), mirror=True, spmv=mode)
+    b = GPMA(V, dev(u), mirror=False, spmv=mode if mode != "pull" else "auto")
     say("spmv", mode)
     xa = a.pagerank(iters=10).cpu().numpy()
     xb = b.pagerank(iters=10).cpu().numpy()
@@ -347,8 +345,9 @@ def test_spmv_modes_match_oracle_on_rmat(mode, monkeypatch):
     b.close()
 
 
-@pytest.mark.parametrize("case", ["rmat16", "powerlaw_ragged", "two_level", "many_bins"])
-def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
+@pytest.mark.parametrize("case", ["rmat16", "powerlaw_ragged", "two_level", "many_bins", "rmat16_gather",
+                                  "powerlaw_ragged_gather", "many_bins_gather"])
+def test_binned_spmv_split_bins_and_ragged_tail(case):
     """Destination bins of 16384 vertices: R-MAT scale 16 puts ~40% of its
     ~1M edges into bin 0, which is cut into several accumulation pieces
     (fp64 atomics between pieces); a power-law graph on 70001 vertices ends
@@ -356,9 +355,10 @@ def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
     coarse bins of 64 bins first (two_level; the last coarse bin partial) or
     are reserved per lane (many_bins).  Warm-started calls after updates too."""
     from paper_1709_05061_amd import GPMA
-    monkeypatch.setenv("GPMA_SPMV", "binned")
-    if case == "two_level":
-        monkeypatch.setenv("GPMA_PB_LEVELS", "2")
+    form = "binned_coarse" if case == "two_level" else "binned"
+    if case.endswith("_gather"):     # the same graphs, edges binned once per call
+        form = "binned_gather"
+        case = case[: -len("_gather")]
     if case == "rmat16":
         V = 1 << 16
         u = np.unique(npu64(synth.rmat_unique(16, 16 << 16, seed=4)))
@@ -372,7 +372,7 @@ def test_binned_spmv_split_bins_and_ragged_tail(case, monkeypatch):
         u = np.unique(np.concatenate([r, npu64(synth.powerlaw_edges(V, 400000, seed=7))]))
     say("binned", case, V, len(u))
     half = len(u) // 2
-    g = GPMA(V, dev(u[:half]))
+    g = GPMA(V, dev(u[:half]), spmv=form)
     ref = O.OraclePMA(V, u[:half], g.leaf_size)
     x = g.pagerank(iters=10).cpu().numpy()
     want = O.pagerank(V, u[:half], iters=10)

@@ -37,6 +37,14 @@ def test_service_results_alone_equal_mix():
     s = rep.summary()
     print(s, flush=True)
     assert rep.edges_applied == n_arr
+    # the window slid over the whole stream: every arrival was inserted and
+    # as many of the oldest edges expired (arrivals are distinct and not in
+    # the window, so every update changed the graph)
+    assert sum(int(i.numel()) for _, i in svc.batch_log) == n_arr
+    assert sum(int(d.numel()) for d, _ in svc.batch_log) == n_arr
+    assert rep.updates_applied == 2 * n_arr
+    want_final = np.union1d(npu64(window)[n_arr:], npu64(arrivals))
+    assert np.array_equal(npu64(svc.g.keys()), want_final)
     assert len(rep.queries) == nq
     assert s["query_slots"] == 2 and rep.max_queue >= 2
     # the edge set at every version, from the batch log

@@ -355,6 +355,36 @@ def test_growth_and_shrink_resize_rules():
     assert p.capacity < caps[-1]
 
 
+def test_semantic_set_against_python_sets_and_layout_oracle():
+    """The sorted-vector set follows Python's set union / difference batch
+    by batch (repeats, absent deletes, present inserts), reports how many
+    keys changed the set, and holds exactly the layout oracle's edges."""
+    rng = np.random.default_rng(12)
+    V = 50
+    def rnd(n):
+        return [key(a, b) for a, b in zip(rng.integers(0, V, n), rng.integers(0, V, n))]
+    init = rnd(400)
+    s = O.OracleSet(np.array(init, dtype=np.uint64))
+    p = O.OraclePMA(V, np.array(init, dtype=np.uint64), 16)
+    ref = set(init)
+    assert [int(x) for x in s.keys()] == sorted(ref)
+    for t in range(60):
+        b = rnd(int(rng.integers(0, 300)))
+        if t % 3 == 2:
+            b += sorted(ref)[::7]
+            changed = s.delete(np.array(b, dtype=np.uint64))
+            p.delete(np.array(b, dtype=np.uint64))
+            assert changed == len(ref & set(b))
+            ref -= set(b)
+        else:
+            changed = s.insert(np.array(b, dtype=np.uint64))
+            p.insert(np.array(b, dtype=np.uint64))
+            assert changed == len(set(b) - ref)
+            ref |= set(b)
+        assert [int(x) for x in s.keys()] == sorted(ref)
+        assert np.array_equal(s.keys(), O.edge_keys(p.slots()))
+
+
 def test_invalid_keys_leave_state_unchanged():
     p = O.OraclePMA(4, [key(0, 1), key(1, 2)], 16)
     before = p.slots()
