@@ -260,6 +260,21 @@ int gpma_pagerank(gpma_t *h, const float *init_dev, float *out_dev, uint32_t ite
  * GPMA_EINVAL if source >= V. */
 int gpma_bfs(gpma_t *h, uint32_t source, int32_t *dist_dev, hipStream_t stream);
 
+/* gpma_bfs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same result as gpma_bfs, bit for bit, but the frontier queues, the
+ * row-length scan and the level counters live in a fixed device array of
+ * the library (about 48 MiB, one per GPU, held until the process ends)
+ * instead of the handle's lazily allocated scratch, so the call allocates
+ * nothing.  Limit: V <= 2^22 (else GPMA_EINVAL, nothing written).  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (from
+ * several threads, or on several streams before the earlier ones finish)
+ * race and must not be made; each call synchronises `stream` once per BFS
+ * level, so consecutive calls from one thread do not overlap.
+ * GPMA_EINVAL if source >= V; GPMA_EDEVICE if the array's address cannot be
+ * had. */
+int gpma_bfs_noalloc(gpma_t *h, uint32_t source, int32_t *dist_dev, hipStream_t stream);
+
 /* Connected components with edge direction ignored (Section 6.1); every
  * vertex gets the smallest vertex id of its component.  label_dev: V uint32. */
 int gpma_cc(gpma_t *h, uint32_t *label_dev, hipStream_t stream);

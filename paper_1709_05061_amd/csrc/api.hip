@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -2147,6 +2148,41 @@ int bfs_run(gpma *g, uint32_t source, int32_t *dist, hipStream_t s, uint32_t *q0
     return GPMA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of gpma_bfs_noalloc: one file-scope device array per GPU (each GPU
+// the library runs on holds its own copy until the process ends).  Host code
+// never passes `scratch` itself to a kernel (on the host it only names the
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device with that device current, and every use goes through it.
+constexpr uint32_t kNoallocMaxV = 1u << 22;
+constexpr uint64_t kScrCounters = 64;       // counter words (256 B)
+constexpr uint64_t kScrScanTmp = 4096;      // >= scan_tmp_words(kNoallocMaxV)
+constexpr uint64_t kScrWords = kScrCounters + 3ull * kNoallocMaxV + kScrScanTmp;
+constexpr int kScrMaxDevices = 64;
+
+static __device__ __align__(256) uint32_t scratch[kScrWords];
+
+std::mutex g_scr_mu;
+uint32_t *g_scr_ptr[kScrMaxDevices] = {};
+
+// The current device's address of `scratch` (nullptr if it cannot be had).
+uint32_t *noalloc_scratch() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kScrMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scr_mu);
+    if (!g_scr_ptr[dev]) {
+        if (scan_tmp_words(kNoallocMaxV) > kScrScanTmp) return nullptr;
+        void *p = nullptr;
+        const hipError_t r = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (r != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scr_ptr[dev] = (uint32_t *)p;
+    }
+    return g_scr_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
@@ -2166,6 +2202,16 @@ int gpma_bfs(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
         }
     }
     return bfs_run(g, source, dist, s, g->bfs_q0, g->bfs_q1, g->bfs_off, g->bfs_tmp, g->small);
+}
+
+int gpma_bfs_noalloc(gpma_t *g, uint32_t source, int32_t *dist, hipStream_t s) {
+    if (!g || !dist || source >= g->V) return GPMA_EINVAL;
+    if (g->V > kNoallocMaxV) return GPMA_EINVAL;
+    uint32_t *scr = noalloc_scratch();
+    if (!scr) return GPMA_EDEVICE;
+    uint32_t *q0 = scr + kScrCounters, *q1 = q0 + kNoallocMaxV, *off = q1 + kNoallocMaxV;
+    uint32_t *tmp = off + kNoallocMaxV;
+    return bfs_run(g, source, dist, s, q0, q1, off, tmp, scr);
 }
 
 int gpma_cc(gpma_t *g, uint32_t *label, hipStream_t s) {

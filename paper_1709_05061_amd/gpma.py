@@ -128,6 +128,7 @@ def load_library() -> C.CDLL:
         "gpma_delete_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
         "gpma_pagerank": (C.c_int, [vp, vp, vp, u32, f32, vp]),
         "gpma_bfs": (C.c_int, [vp, u32, vp, vp]),
+        "gpma_bfs_noalloc": (C.c_int, [vp, u32, vp, vp]),
         "gpma_cc": (C.c_int, [vp, vp, vp]),
         "gpma_num_edges": (u64, [vp]),
         "gpma_capacity": (u64, [vp]),
@@ -170,7 +171,7 @@ def load_library() -> C.CDLL:
 
 def exported_symbols() -> List[str]:
     return ["gpma_default_params", "gpma_create", "gpma_destroy", "gpma_insert_batch",
-            "gpma_delete_batch", "gpma_pagerank", "gpma_bfs", "gpma_cc", "gpma_num_edges",
+            "gpma_delete_batch", "gpma_pagerank", "gpma_bfs", "gpma_bfs_noalloc", "gpma_cc", "gpma_num_edges",
             "gpma_capacity", "gpma_leaf_size", "gpma_num_vertices", "gpma_export_slots",
             "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_row_offsets",
             "gpma_export_degrees", "gpma_sync", "gpma_get_mirror", "gpma_apply_batches", "gpma_strerror",
@@ -293,6 +294,15 @@ def gpma_pagerank(h, init: Optional[torch.Tensor], out: torch.Tensor, iters: int
 def gpma_bfs(h, source: int, dist: torch.Tensor, stream=None) -> torch.Tensor:
     assert dist.is_cuda and dist.dtype == torch.int32 and dist.is_contiguous()
     _check(load_library().gpma_bfs(h, source, C.c_void_p(dist.data_ptr()), _stream(stream)), "gpma_bfs")
+    return dist
+
+
+def gpma_bfs_noalloc(h, source: int, dist: torch.Tensor, stream=None) -> torch.Tensor:
+    """gpma_bfs without device allocation (scratch in the library's fixed
+    per-GPU array; V <= 2^22)."""
+    assert dist.is_cuda and dist.dtype == torch.int32 and dist.is_contiguous()
+    _check(load_library().gpma_bfs_noalloc(h, source, C.c_void_p(dist.data_ptr()), _stream(stream)),
+           "gpma_bfs_noalloc")
     return dist
 
 
