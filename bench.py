@@ -19,8 +19,9 @@ value     = edge updates applied per second of update time (delete + insert
             phases of the timed steps, HIP events on the update stream)
 roofline  = the dominant kernel by time (PageRank's SpMV), algorithmic bytes
             per launch / its mean launch time from HIP events
-cpu_baseline = the CPU oracle (single thread) on a bounded sample: an R-MAT
-            scale-20 window with the same 2^16-edge slides.
+cpu_baseline = the CPU oracle (single thread) on the headline inputs: the
+            first slides through the sequential layout oracle (and the
+            sorted-vector set), with the host's CPU model and core count.
 
 Inputs are generated on the device before the timed region starts.
 """
@@ -78,41 +79,79 @@ def measured_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(batch: int, slides: int, scale: int = 20):
-    """Time the oracle (as it stands) on one host core over a bounded sample."""
+def host_cpu() -> dict:
+    """The host's CPU model and core counts (what the CPU figures ran on)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(st, batch: int, layout_slides: int, set_slides: int, pr: bool = True):
+    """Time the oracle (as it stands, one thread) on the headline inputs: the
+    same R-MAT window and the same slides the GPU path applies.  The layout
+    oracle (the sequential GPMA+) does work linear in the capacity per batch,
+    seconds at this size, so it takes `layout_slides` slides; the semantic
+    sorted-vector set takes `set_slides`.  PageRank: one fp64 10-step call on
+    the oracle's edge set."""
     import numpy as np
     import torch
 
     import oracle as O
-    import synth
-    dev = "cuda" if torch.cuda.is_available() else "cpu"
-    st = synth.rmat_stream(scale, 16, seed=1, device=dev)
-    order = st.order.cpu().numpy().view(np.uint64)
-    p = O.OraclePMA(st.V, order[: st.window], 32)
+    win = torch.sort(st.order[: st.window])[0]      # a set: sorted only to spare the oracle's sort
+    init = win.cpu().numpy().view(np.uint64)
+    del win
+
+    def slide(t):
+        d, i = st.slide(t, batch)
+        return d.cpu().numpy().view(np.uint64), i.cpu().numpy().view(np.uint64)
+
+    slides = {t: slide(t) for t in range(max(layout_slides, set_slides))}
+    out = {"unit": "edge updates/s", "cores": 1, "kind": "oracle", "host": host_cpu()}
+    p = O.OraclePMA(st.V, init, 32)
     t0 = time.perf_counter()
     applied = 0
-    for t in range(slides):
-        p.delete(order[t * batch:(t + 1) * batch])
+    for t in range(layout_slides):
+        d, i = slides[t]
+        p.delete(d)
         applied += p.last_applied()
-        p.insert(order[st.window + t * batch: st.window + (t + 1) * batch])
+        p.insert(i)
         applied += p.last_applied()
     dt = time.perf_counter() - t0
+    out["value"] = applied / dt
+    out["seconds"] = dt
+    out["sample"] = ("the headline inputs (R-MAT scale %d window of %d edges, %d-slot array, leaf 32): "
+                     "%d slides of %d deletes + %d inserts through the sequential layout oracle, "
+                     "single thread" % (int(np.log2(st.V)), st.window, p.capacity, layout_slides, batch, batch))
     edges = O.edge_keys(p.slots())
-    t1 = time.perf_counter()
-    O.pagerank(st.V, edges, iters=10)
-    dpr = time.perf_counter() - t1
-    spmv_bytes = 10 * (8.0 * (edges.size + st.V) + 16.0 * st.V)
-    return {
-        "value": applied / dt,
-        "unit": "edge updates/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": "R-MAT scale %d edge factor 16 window (%d edges), %d slides of %d deletes + %d "
-                  "inserts, single thread" % (scale, st.window, slides, batch, batch),
-        "seconds": dt,
-        "pagerank_spmv_GBps": spmv_bytes / dpr / 1e9,
-        "pagerank_seconds": dpr,
-    }
+    del p
+    s = O.OracleSet(init)
+    t0 = time.perf_counter()
+    n = 0
+    for t in range(set_slides):
+        d, i = slides[t]
+        n += s.delete(d) + s.insert(i)
+    ds = time.perf_counter() - t0
+    out["semantic_set"] = {"value": n / ds, "seconds": ds, "slides": set_slides,
+                           "what": "sorted unique vector, each batch merged in or out (one thread)"}
+    del s
+    if pr:
+        t1 = time.perf_counter()
+        O.pagerank(st.V, edges, iters=10)
+        dpr = time.perf_counter() - t1
+        out["pagerank_seconds"] = dpr
+        out["pagerank_spmv_GBps"] = 10 * (8.0 * (edges.size + st.V) + 28.0 * st.V) / dpr / 1e9
+    return out
 
 
 def sweep_slides(z: int) -> int:
@@ -130,7 +169,7 @@ def spmv_forms_section(args, g, st, V, kernels):
 
     from paper_1709_05061_amd import GPMA
     from paper_1709_05061_amd import gpma as G
-    own = "binned" if args.spmv in ("auto", "binned") else args.spmv
+    own = "binned_gather" if args.spmv in ("auto", "binned_gather") else args.spmv
     out = {own: {"spmv_mean_us": kernels["spmv"]["mean_us"], "GBps": kernels["spmv"]["GBps"],
                  "source": "headline steps"}} if "spmv" in kernels else {}
     for form in ("binned", "binned_gather"):
@@ -272,25 +311,32 @@ def workloads_section(args):
 
 def service_section(args):
     """Streaming service on R-MAT scale 22 (window = first half of the
-    distinct edges): Poisson edge arrivals at each rate for `service_s`
-    seconds, continuous batching, BFS and 10-iteration PageRank queries at a
-    Poisson rate, query slots admitted by an HBM budget."""
+    distinct edges): for each rate, Poisson edge arrivals for `service_s`
+    seconds with continuous batching, BFS and 10-iteration PageRank queries at
+    a Poisson rate, the graph and the query slots under one HBM budget; then
+    a saturated run (every edge already arrived, the update stream applies
+    steps back to back) for the sustained update throughput beside queries."""
     import torch
 
     import synth
     from paper_1709_05061_amd.service import GraphService
     st = synth.rmat_stream(22, 16, seed=args.seed + 30, device="cuda")
     V = st.V
-    out = {"workload": "R-MAT scale 22 edge factor 16, window %d edges; Poisson arrivals %gs per rate; "
-                       "BFS + PageRank(10) queries at %g/s; HBM budget %d GiB"
+    out = {"workload": "R-MAT scale 22 edge factor 16, window %d edges; Poisson arrivals for %gs per rate; "
+                       "BFS + PageRank(10) queries at %g/s; HBM budget %d GiB for graph and query slots"
                        % (st.window, args.service_s, args.query_rate, args.service_budget_gib),
            "rates": {}}
     pos = st.window
-    for k, rate in enumerate((1e5, 1e6, 1e7)):
-        n = int(rate * args.service_s)
-        n = min(n, st.order.numel() - pos)
+    cases = [(1e5, False), (1e6, False), (1e7, False), (None, True)]
+    for k, (rate, saturated) in enumerate(cases):
+        if saturated:
+            n = min(1 << 22, st.order.numel() - pos)
+            times = torch.zeros(n, dtype=torch.float64)
+        else:
+            # (at most 2e7 arrivals, so the saturated run still has 4M left)
+            n = min(int(rate * args.service_s), 20_000_000, st.order.numel() - pos)
+            times = synth.poisson_times(n, rate, seed=args.seed + 31 + k)
         arrivals = st.order[pos:pos + n]
-        times = synth.poisson_times(n, rate, seed=args.seed + 31 + k)
         nq = max(4, int(args.query_rate * args.service_s))
         qt = synth.poisson_times(nq, args.query_rate, seed=args.seed + 41 + k).tolist()
         kinds = ["bfs" if i % 2 == 0 else "pagerank" for i in range(nq)]
@@ -299,9 +345,10 @@ def service_section(args):
         window = st.order[pos - st.window:pos]
         svc = GraphService(V, window, mirror=True, hbm_budget_bytes=args.service_budget_gib << 30,
                            max_batch=1 << 18, max_slots=4)
-        rep = svc.run(times, arrivals, qt, kinds, qargs, time_limit_s=60)
-        out["rates"]["%g" % rate] = rep.summary()
-        log("service at %g edges/s: %s" % (rate, rep.summary()))
+        rep = svc.run(times, arrivals, qt, kinds, qargs, time_limit_s=120)
+        name = "saturated" if saturated else "%g" % rate
+        out["rates"][name] = rep.summary()
+        log("service %s: %s" % (name, rep.summary()))
         svc.close()
         del svc
         torch.cuda.empty_cache()
@@ -331,8 +378,8 @@ def main():
     ap.add_argument("--rebuild-slides", type=int, default=4, help="slides timed on the rebuild-per-batch CSR")
     ap.add_argument("--lock-slides", type=int, default=4,
                     help="slides timed for the lock-based GPMA comparator (0: skip)")
-    ap.add_argument("--service-s", type=float, default=1.0)
-    ap.add_argument("--query-rate", type=float, default=40.0)
+    ap.add_argument("--service-s", type=float, default=5.0)
+    ap.add_argument("--query-rate", type=float, default=200.0)
     ap.add_argument("--service-budget-gib", type=int, default=16)
     ap.add_argument("--no-learned", action="store_true", help="binary-search locate in the main path")
     ap.add_argument("--fused-direct", type=int, default=0,
@@ -341,7 +388,8 @@ def main():
     ap.add_argument("--fused-levels", type=int, default=0,
                     help="tree levels above the leaves each fused batch runs on the device")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-slides", type=int, default=64)
+    ap.add_argument("--cpu-slides", type=int, default=2, help="slides through the layout oracle")
+    ap.add_argument("--cpu-set-slides", type=int, default=4, help="slides through the sorted-vector set")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--sweep", default="1,16,256,1024,4096,16384,65536,262144,1048576",
                     help="batch sizes of the latency sweep (fused + learned, fused + binary search, plain)")
@@ -548,10 +596,13 @@ def main():
         if not args.no_analytics:
             g.pagerank(init=x, iters=args.pr_iters, out=x)
             marks.append(ev())
-            g.bfs(sources[t])
+            dist = g.bfs(sources[t])
             marks.append(ev())
             g.cc()
             marks.append(ev())
+            # BFS algorithmic bytes: 8 B per slot of every reached row, 12 B per vertex
+            ro = g.row_offsets().to(torch.int64)
+            marks.append(8.0 * float(((ro[1:] - ro[:-1])[dist >= 0]).sum().item()) + 12.0 * V)
         return a, r, marks
 
     for t in range(args.warmup):
@@ -588,6 +639,14 @@ def main():
                        "bytes_per_slide": upd_bytes / len(recs),
                        "note": "whole update phase (every kernel of a slide, array and mirror) against "
                                "8 B per batch key + (16 + 10/leaf) B per slot of every merged segment"}
+    roofline_bfs = None
+    if not args.no_analytics:
+        bfs_ms = [m[3].elapsed_time(m[4]) for m in recs]
+        bfs_gbps = sum(m[6] for m in recs) / (sum(bfs_ms) / 1e3) / 1e9
+        roofline_bfs = {"bound": "hbm", "achieved": bfs_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                        "frac": bfs_gbps / HBM_PEAK_GBPS, "traffic": None,
+                        "bytes_per_bfs": sum(m[6] for m in recs) / len(recs),
+                        "note": "whole BFS call against 8 B per slot of every reached row + 12 B per vertex"}
     loc_timed = None
     if learned:
         loc1 = g.locator_info()
@@ -698,6 +757,7 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
         "roofline_update": roofline_update,
+        "roofline_bfs": roofline_bfs,
         "batch_sweep": sweep_out,
     }
     if learned:
@@ -706,6 +766,12 @@ def main():
     if not args.no_spmv_forms:
         out["spmv_forms"] = spmv_forms_section(args, g, st, V, kernels)
     g.close()
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on the headline inputs")
+        out["cpu_baseline"] = cpu_baseline(st, b, args.cpu_slides, args.cpu_set_slides)
+    else:
+        out["cpu_baseline"] = None
     del st
     torch.cuda.empty_cache()
     if not args.no_service:
@@ -722,11 +788,6 @@ def main():
         log("explicit deletions and sorted arrivals (R-MAT scale 22)")
         out["workloads"] = workloads_section(args)
         torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        out["cpu_baseline"] = cpu_baseline(b, args.cpu_slides)
-    else:
-        out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
 
 

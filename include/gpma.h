@@ -90,7 +90,7 @@ typedef struct {
     uint32_t spmv_form;       /* PageRank's SpMV, GPMA_SPMV_* below */
 } gpma_params;
 
-/* The SpMV of gpma_pagerank.  AUTO: destination bins while V <= 2^26, else
+/* The SpMV of gpma_pagerank.  AUTO: BINNED_GATHER while V <= 2^26, else
  * pull over the mirror when there is one, else push.  BINNED and
  * BINNED_COARSE (the bins filled through 64 coarse bins first) write the
  * contributions into destination bins every iteration; BINNED_GATHER bins
@@ -329,6 +329,14 @@ int gpma_lock_insert_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b, hipS
 
 /* Device bytes the handle (with its mirror) holds from its allocator. */
 uint64_t gpma_allocated_bytes(const gpma_t *h);
+
+/* Take now, on the array and its mirror, the memory that update batches of
+ * up to b keys need short of a root resize (batch scratch, fused-batching
+ * state, the merge workspace of the upper levels and the root), so that
+ * later calls allocate only to resize.  For callers that budget device
+ * memory (the streaming service admits work against an HBM budget).
+ * GPMA_ENOMEM if the allocator refuses (what was taken stays taken). */
+int gpma_reserve(gpma_t *h, uint64_t b, hipStream_t stream);
 
 /* Introspection.  Counts are those after the last completed call. */
 uint64_t gpma_num_edges(const gpma_t *h);     /* guards excluded */

@@ -1896,6 +1896,25 @@ int gpma_apply_batches(gpma_t *g, uint32_t count, const uint8_t *ops, const uint
     return e;
 }
 
+int gpma_reserve(gpma_t *g, uint64_t b, hipStream_t s) {
+    if (!g || g->readonly || b >= (1ull << 31)) return GPMA_EINVAL;
+    set_stream(g, s);
+    int e = GPMA_OK;
+    for (gpma *h : {g, g->mir}) {
+        if (!h || e) continue;
+        e = ensure_batch(h, std::max<uint64_t>(b, 1));
+        if (!e) e = ensure_fused(h);
+        if (!e) e = ensure_dt(h, h->n + b, h->L);
+    }
+    if (!e && g->mir && b > g->tkeys_cap) {
+        dev_free(g, g->tkeys);
+        g->tkeys_cap = 0;
+        e = dev_alloc(g, &g->tkeys, next_pow2(b));
+        if (!e) g->tkeys_cap = next_pow2(b);
+    }
+    return e;
+}
+
 int gpma_fused_pairing(gpma_t *g, hipStream_t s) {
     if (!g || !g->mir) return GPMA_EINVAL;
     if (g->lib_streams) return 0;
@@ -1969,9 +1988,10 @@ namespace {
 
 enum { kSpmvBinned = 0, kSpmvPull = 1, kSpmvPush = 2, kSpmvGather = 3 };
 
-// Destination bins when V allows them, else pull over the dst-major mirror
-// if there is one, else push; gpma_params.spmv_form picks one (tests compare
-// them; validated at create).
+// Destination bins (edges binned once per call, contributions fetched by
+// source) when V allows them, else pull over the dst-major mirror if there
+// is one, else push; gpma_params.spmv_form picks one (tests compare them;
+// validated at create).
 int spmv_mode(const gpma *g) {
     switch (g->spmv_form) {
         case GPMA_SPMV_BINNED:
@@ -1979,7 +1999,7 @@ int spmv_mode(const gpma *g) {
         case GPMA_SPMV_PULL: return kSpmvPull;
         case GPMA_SPMV_PUSH: return kSpmvPush;
         case GPMA_SPMV_BINNED_GATHER: return kSpmvGather;
-        default: return pb_supported(g->V) ? kSpmvBinned : (g->mir ? kSpmvPull : kSpmvPush);
+        default: return pb_supported(g->V) ? kSpmvGather : (g->mir ? kSpmvPull : kSpmvPush);
     }
 }
 

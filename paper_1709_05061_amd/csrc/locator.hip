@@ -143,10 +143,14 @@ k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
     if ((uint64_t)blockIdx.x * blockDim.x >= n || ctl->err) return;   // block-uniform
     const bool active = i < n;
     const uint64_t k = active ? keys[i] : 0;
-    const float t = model_position(m, k, s_out + (threadIdx.x & ~63u));
-    if (!active) return;
     const Span sp = row_span(row_ptr, key_src(k), lf_log2);
     const uint64_t span = sp.last - sp.first + 1;
+    // the model runs (wave-wide, on MFMA) only for waves with a key in a
+    // long row; the batch is sorted, so most waves hold short rows only or
+    // long rows only
+    float t = 0.f;
+    if (__ballot(active && span > kMinSpan)) t = model_position(m, k, s_out + (threadIdx.x & ~63u));
+    if (!active) return;
     uint64_t j;
     if (span <= kMinSpan) {
         j = search_range(slots, lf_log2, sp.first, sp.last, k);

@@ -123,6 +123,7 @@ def load_library() -> C.CDLL:
                                   C.POINTER(gpma_allocator), vp]),
         "gpma_fused_pairing": (C.c_int, [vp, vp]),
         "gpma_allocated_bytes": (u64, [vp]),
+        "gpma_reserve": (C.c_int, [vp, u64, vp]),
         "gpma_destroy": (C.c_int, [vp]),
         "gpma_insert_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
         "gpma_delete_batch": (C.c_int, [vp, vp, u64, vp, C.POINTER(gpma_stats)]),
@@ -180,7 +181,7 @@ def exported_symbols() -> List[str]:
             "gpma_profile_enable",
             "gpma_profile_reset", "gpma_profile_read", "gpma_csr_create", "gpma_csr_destroy",
             "gpma_csr_update", "gpma_csr_num_edges", "gpma_csr_export", "gpma_lock_insert_batch",
-            "gpma_fused_pairing", "gpma_allocated_bytes"]
+            "gpma_fused_pairing", "gpma_allocated_bytes", "gpma_reserve"]
 
 
 def strerror(code: int) -> str:
@@ -436,6 +437,11 @@ class GPMA(_HandleView):
     def allocated_bytes(self) -> int:
         """Device bytes the handle and its mirror hold from their allocator."""
         return int(self._lib.gpma_allocated_bytes(self.h))
+
+    def reserve(self, b: int, stream=None):
+        """Take now the memory update batches of up to b keys need short of a
+        root resize (gpma_reserve)."""
+        _check(self._lib.gpma_reserve(self.h, b, _stream(stream)), "gpma_reserve")
 
     def fused_pairing(self, stream=None) -> int:
         """1: fused batching keeps the array's pipeline on `stream` with the

@@ -2,13 +2,13 @@
 R-MAT scale 24, edge factor 16 (all distinct edges of 2^28 draws, ~2.6e8,
 a 2^29-slot array), dst-major mirror, learned locator, fused batching with
 1024-key sort tiles and no device levels above the leaves; two slides of
-2^16 deletes + 2^16 inserts.  The oracle's analytics (plain C) finish in
-seconds at this size, so PageRank, BFS and CC are compared on every vertex;
-the edge set is compared with the stream's window after the slides, the
-degrees with a count of the exported edges, the mirror with the transposed
-set, and the slot array with the structural invariants.  The PMA layout
-itself is not replayed by the sequential oracle at this size (that is what
-the smaller parity tests do slot for slot)."""
+2^16 deletes + 2^16 inserts.  The sequential layout oracle replays the same
+two slides (a few seconds per batch at this size, its work is linear in the
+capacity), so the raw slot arrays of the array and of the mirror are
+compared byte for byte; the oracle's analytics (plain C) compare PageRank,
+BFS and CC on every vertex; the edge set is compared with the stream's
+window after the slides and the degrees with a count of the exported
+edges."""
 import sys
 
 import numpy as np
@@ -40,7 +40,31 @@ def test_fullsize_rmat24_bench_configuration():
         s = g.apply_batches([1, 0], [d, i])
         assert s.applied == 2 * b, (t, s)
     torch.cuda.synchronize()
-    say("slides applied; comparing the edge set")
+    say("slides applied; replaying them through the layout oracle")
+    lf = g.leaf_size
+    for name, h, tr in (("array", g, False), ("mirror", g.mirror(), True)):
+        def t(k):   # device keys, transposed for the mirror, as host uint64
+            k = ((k & 0xFFFFFFFF) << 32) | (k >> 32) if tr else k
+            return k.cpu().numpy().view(np.uint64)
+        # the initial set handed over sorted (a set: the order of the input
+        # does not change what the oracle builds, only how long its sort takes)
+        k0 = st.initial()
+        k0 = ((k0 & 0xFFFFFFFF) << 32) | (k0 >> 32) if tr else k0
+        ref = O.OraclePMA(V, torch.sort(k0)[0].cpu().numpy().view(np.uint64), lf)
+        del k0
+        for s_ in range(2):
+            d, i = st.slide(s_, b)
+            ref.delete(t(d))
+            ref.insert(t(i))
+        want = ref.slots()
+        del ref
+        got = h.slots().cpu().numpy().view(np.uint64)
+        assert got.size == want.size
+        bad = np.nonzero(got != want)[0]
+        assert bad.size == 0, "%s: %d slots differ, first at %s" % (name, bad.size, bad[:5])
+        say(name, "slot for slot equal to the oracle")
+        del want, got
+    say("comparing the edge set")
     keys = g.keys()
     want = torch.sort(st.order[2 * b: st.window + 2 * b])[0]
     assert torch.equal(keys, want)

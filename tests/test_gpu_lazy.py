@@ -73,9 +73,12 @@ def marked(slots: np.ndarray) -> int:
 
 
 def run_stream(g, ref, V, batches, mref=None, pr_every=0):
+    from test_gpu_pma import check_merge_log
     for t, (op, keys) in enumerate(batches):
+        cap0 = ref.capacity
         st = getattr(g, op)(dev(keys), stats=True)
         getattr(ref, op)(keys)
+        check_merge_log(st, ref, g.leaf_size, cap0)
         if mref is not None:
             getattr(mref, op)(transpose(keys))
         assert st.applied == ref.last_applied(), (t, op, st.applied, ref.last_applied())

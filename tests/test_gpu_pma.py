@@ -85,13 +85,35 @@ def test_create_csr_example_and_auto_leaf():
     g.close()
 
 
+def check_merge_log(st, ref, lf, cap_before):
+    """The batch's merges, level by level, equal the oracle's merge log
+    (Example 3 of Section 5.2 narrates such rounds): as many segments merged
+    at every height, the root counted at the old height whether it took the
+    batch in place or was rebuilt at a new capacity, and the same sum of
+    rewritten segment capacities."""
+    H = int(np.log2(cap_before // lf))
+    want = {}
+    rew = 0
+    for lvl, seg in ref.merge_log():
+        h = H if lvl < 0 else lvl
+        want[h] = want.get(h, 0) + 1
+        rew += seg if lvl < 0 else lf << lvl
+    got = {h: c for h, c in enumerate(st.segments_merged) if c}
+    assert got == want, (got, want)
+    assert st.slots_rewritten == rew, (st.slots_rewritten, rew)
+    assert st.top_level == (max(want) if want else -1)
+
+
 def run_stream(g, ref, V, batches, pr_every=0, check_every=1):
     """batches: list of (op, numpy uint64 keys)."""
     x = None
     for t, (op, keys) in enumerate(batches):
+        cap0 = ref.capacity
         st = getattr(g, op)(dev(keys), stats=True)
         getattr(ref, op)(keys)
         assert st.applied == ref.last_applied(), (t, op, st, ref.last_applied())
+        assert st.noops == ref.last_noops(), (t, op, st.noops, ref.last_noops())
+        check_merge_log(st, ref, g.leaf_size, cap0)
         if t % check_every == 0 or t == len(batches) - 1:
             edges = check_state(g, ref, V)
             if pr_every and t % pr_every == 0:

@@ -99,3 +99,57 @@ def test_snapshot_is_frozen_while_updates_continue():
     assert np.array_equal(npu64(_HandleView(h, V).slots()), npu64(g.slots()))
     lib.gpma_destroy(h)
     g.close()
+
+
+def test_service_budget_admits_growth_by_giving_up_slots():
+    """One HBM budget for the graph and the query slots: the window only
+    grows (no expiry), so the array resizes; under a budget that holds the
+    grown graph but not all slots beside it, a refused update batch waits
+    while idle slots give their memory up, queries queue for the slots that
+    are left, and every answer still equals the oracle on the version it
+    saw."""
+    from paper_1709_05061_amd.service import GraphService
+    st = synth.rmat_stream(13, 16, seed=8, device="cuda")
+    V = st.V
+    window = st.order[: st.window // 8]
+    arrivals = st.order[st.window // 8: st.window // 8 + 40000]
+    times = torch.zeros(arrivals.numel(), dtype=torch.float64)      # all arrived: back-to-back steps
+    nq = 30
+    qt = [0.0] * nq
+    kinds = ["bfs" if i % 2 == 0 else "pagerank" for i in range(nq)]
+    srcs = synth.uniform_below(torch.arange(nq), 9, V).tolist()
+    args = [srcs[i] if kinds[i] == "bfs" else 10 for i in range(nq)]
+    # a dry run with room for everything measures the peak of one slot beside the grown graph
+    probe = GraphService(V, window, leaf_size=16, mirror=True, max_slots=1, max_batch=1 << 12, expire=False,
+                         hbm_budget_bytes=1 << 36)
+    probe.run(times, arrivals, [], [], [], time_limit_s=60)
+    peak = probe.alloc.peak_bytes
+    probe.close()
+    svc = GraphService(V, window, leaf_size=16, mirror=True, max_slots=3, max_batch=1 << 12, expire=False,
+                       hbm_budget_bytes=peak)
+    svc.record = True
+    slots0 = sum(1 for s in svc.slots if s is not None)
+    rep = svc.run(times, arrivals, qt, kinds, args, time_limit_s=120)
+    s = rep.summary()
+    print(s, flush=True)
+    assert slots0 >= 2, slots0
+    assert rep.update_waits >= 1 and rep.slots_given_up >= 1
+    assert rep.max_queue >= nq - slots0
+    assert len(rep.queries) == nq
+    assert rep.peak_bytes <= peak
+    want_final = np.unique(np.concatenate([npu64(window), npu64(arrivals)]))
+    assert np.array_equal(npu64(svc.g.keys()), want_final)
+    cur = set(int(x) for x in npu64(window))
+    versions = {0: sorted(cur)}
+    for v, (d, i) in enumerate(svc.batch_log, start=1):
+        assert d.numel() == 0
+        cur |= set(int(x) for x in i.numpy().view(np.uint64))
+        versions[v] = sorted(cur)
+    for q in rep.queries:
+        e = np.array(versions[q.version], dtype=np.uint64)
+        if q.kind == "bfs":
+            assert np.array_equal(q.result, O.bfs(V, e, q.arg)), (q.qid, q.version)
+        else:
+            want = O.pagerank(V, e, iters=q.arg)
+            assert np.max(np.abs(q.result - want) / want) < 1e-6
+    svc.close()
