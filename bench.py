@@ -74,7 +74,7 @@ def measured_traffic(kernel: str):
             continue
         with open(src, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != fields.get("source_sha256"):
-                return None
+                continue
         return float(fields["traffic_bytes_per_launch"])
     return None
 
