@@ -199,6 +199,97 @@ def spmv_forms_section(args, g, st, V, kernels):
     return out
 
 
+def resize_section(args):
+    """A root doubling at the headline size (Algorithm GPMA+, the root's
+    resize): the scale-24 window in a handle whose upper bound is the same at
+    every level (tau about .53, rho_root .25), which puts its 2.8e8 entries just
+    under the bound of 2^29 slots, then one insert batch of 2^22 fresh edges:
+    the leaves and every segment above them fail their bound, so the batch
+    climbs to the root, which cannot take it either: every entry is gathered,
+    merged with the batch and re-dispatched over 2^30 slots (4 -> 8 GiB).  Reported: the batch's time, the capacities and
+    its bytes (read 8 B a slot of the old array, write 8 B a slot of the new
+    one, the merge's read and write of every entry)."""
+    import torch
+
+    import synth
+    from paper_1709_05061_amd import GPMA
+    st = synth.rmat_full_stream(24, 16, 1 << 23, args.seed + 60, device="cuda")
+    # the root bound just above the window's entries plus half the batch
+    n_entries = st.window + st.V
+    tau_pm = -(-1000 * (n_entries + (1 << 21)) // (1 << 29))
+    g = GPMA(st.V, st.initial(), tau_leaf=tau_pm, tau_root=tau_pm, rho_root=250)
+    cap0, n0 = g.capacity, g.num_edges + st.V
+    batch = st.order[st.window: st.window + (1 << 22)]
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s = g.insert(batch, stats=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    n1 = g.num_edges + st.V
+    by = 8.0 * cap0 + 8.0 * g.capacity + 16.0 * n1 + 8.0 * batch.numel()
+    out = {"workload": "R-MAT scale 24 window (%d edges) under tau .%03d at every level; one insert batch of %d edges"
+                       % (st.window, tau_pm, batch.numel()),
+           "capacity_before": cap0, "capacity_after": g.capacity, "resized": bool(s.resized),
+           "entries_before": n0, "entries_after": n1, "applied": s.applied, "ms": ms,
+           "bytes": by, "GBps": by / (ms / 1e3) / 1e9, "frac": by / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS}
+    g.close()
+    return out
+
+
+def rmat20_section(args):
+    """R-MAT scale 20 (window = the first half of the distinct edges): per
+    batch size 2^10..2^20, 4 slides (fused, mirror, learned locator), each
+    followed by BFS from 8 sources with out-edges, CC and 10-step PageRank."""
+    import torch
+
+    import synth
+    from paper_1709_05061_amd import GPMA
+    st = synth.rmat_stream(20, 16, args.seed + 70, device="cuda")
+    g = GPMA(st.V, st.initial(), mirror=True, learned=True)
+    deg = g.degrees()
+    cand = torch.nonzero(deg > 0).flatten()
+    srcs = cand[synth.uniform_below(torch.arange(8, device="cuda"), args.seed + 71, cand.numel())].tolist()
+    out = {"workload": "R-MAT scale 20 edge factor 16, window %d edges; 4 slides per batch size, each "
+                       "followed by BFS from 8 sources, CC and PageRank(10)" % st.window, "sizes": [],
+           "update_ms": [], "updates_per_s": [], "bfs8_ms": [], "cc_ms": [], "pagerank_ms": []}
+    t0 = 0
+    x = torch.full((st.V,), 1.0 / st.V, dtype=torch.float32, device="cuda")
+    for lb in range(10, 21, 2):
+        z = 1 << lb
+        rec = []
+        for j in range(5):
+            d, i = st.order[t0:t0 + z], st.order[st.window + t0: st.window + t0 + z]
+            t0 += z
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+            ev[0].record()
+            a = g.apply_batches([1, 0], [d, i]).applied
+            ev[1].record()
+            for src in srcs:
+                g.bfs(src)
+            ev[2].record()
+            g.cc()
+            ev[3].record()
+            g.pagerank(init=x, iters=10, out=x)
+            ev[4].record()
+            torch.cuda.synchronize()
+            if j:   # the first slide of a size captures its graphs
+                rec.append([a] + [ev[k].elapsed_time(ev[k + 1]) for k in range(4)])
+        n = len(rec)
+        out["sizes"].append(z)
+        out["update_ms"].append(sum(r[1] for r in rec) / n)
+        out["updates_per_s"].append(sum(r[0] for r in rec) / (sum(r[1] for r in rec) / 1e3))
+        out["bfs8_ms"].append(sum(r[2] for r in rec) / n)
+        out["cc_ms"].append(sum(r[3] for r in rec) / n)
+        out["pagerank_ms"].append(sum(r[4] for r in rec) / n)
+        log("R-MAT 20 b=%d: update %.3f ms, BFS x8 %.2f ms, CC %.2f ms, PageRank %.2f ms"
+            % (z, out["update_ms"][-1], out["bfs8_ms"][-1], out["cc_ms"][-1], out["pagerank_ms"][-1]))
+    g.close()
+    return out
+
+
 def uneven_section(args):
     """The fused-batching workload: a power-law social graph (1.6M vertices,
     30M edges, out-degree exponent 2.1), window = first half, then `n` slides
@@ -396,6 +487,8 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--spmv", default="auto", help="SpMV form of the headline handle (a key of SPMV_FORMS)")
     ap.add_argument("--no-spmv-forms", action="store_true", help="skip timing the other binned SpMV form")
+    ap.add_argument("--no-resize", action="store_true", help="skip the scale-24 root doubling")
+    ap.add_argument("--no-rmat20", action="store_true", help="skip the scale-20 batch-size section")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 launches), the known-size reference "
                          "for hardware byte counters, and exit")
@@ -763,6 +856,10 @@ def main():
     if learned:
         out["locator"] = g.locator_info()
         out["locator_timed_steps"] = loc_timed
+    if mirror and fused_mode:
+        # 1: the array's pipeline on the caller's stream, the mirror's beside
+        # it; 0: both on handle streams (forked and joined)
+        out["fused_pairing"] = g.fused_pairing()
     if not args.no_spmv_forms:
         out["spmv_forms"] = spmv_forms_section(args, g, st, V, kernels)
     g.close()
@@ -779,6 +876,15 @@ def main():
         out["service"] = service_section(args)
         r7 = out["service"]["rates"].get("1e+07") or {}
         out["stream_latency_ms_p99"] = r7.get("edge_latency_ms_p99")
+        torch.cuda.empty_cache()
+    if not args.no_resize:
+        log("root doubling at scale 24")
+        out["resize"] = resize_section(args)
+        log("resize: %s" % out["resize"])
+        torch.cuda.empty_cache()
+    if not args.no_rmat20:
+        log("R-MAT scale 20 batch sizes with analytics")
+        out["rmat20"] = rmat20_section(args)
         torch.cuda.empty_cache()
     if not args.no_uneven:
         log("uneven-batch workload (power-law graph)")

@@ -379,7 +379,11 @@ k_pb_accum(const uint64_t *__restrict__ rec, const uint4 *__restrict__ pieces, c
     const uint4 pc = pieces[blockIdx.x];
     for (uint32_t j = threadIdx.x; j < kBinWidth; j += kAccThreads) acc[j] = 0.0;
     __syncthreads();
-    constexpr uint32_t kU = SRC ? 8 : 4;
+    // records per thread in flight: two for source records (measured at scale 24:
+    // 1302-1327 us per step with 2, 1385 with 1, 1414 with 3, 1470-1500 with 4,
+    // 1527-1542 with 8; fewer outstanding fetches per workgroup contend less
+    // for the fabric), four for value records (2 was 1.4 % slower)
+    constexpr uint32_t kU = SRC ? 2 : 4;
     uint64_t i = (uint64_t)pc.x + threadIdx.x;
     for (; i + (kU - 1) * kAccThreads < pc.y; i += kU * kAccThreads) {
         uint64_t r[kU];

@@ -77,6 +77,7 @@ class ServiceReport:
     slots_made: int = 0             # slots made during the run (budget freed)
     budget_bytes: int = 0
     peak_bytes: int = 0
+    t_last_update: float = 0.0      # when the last step completed (from the start of the run)
 
     @staticmethod
     def _pct(xs, q):
@@ -91,6 +92,8 @@ class ServiceReport:
             "edges_applied": self.edges_applied,
             "updates_applied": self.updates_applied,
             "updates_per_s": (self.updates_applied / self.duration_s) if self.duration_s else None,
+            "updates_per_s_until_last_step": (self.updates_applied / self.t_last_update)
+            if self.t_last_update else None,
             "edges": len(self.edge_latency_s),
             "edge_latency_ms_p50": None if not self.edge_latency_s else 1e3 * self._pct(self.edge_latency_s, 50),
             "edge_latency_ms_p99": None if not self.edge_latency_s else 1e3 * self._pct(self.edge_latency_s, 99),
@@ -342,6 +345,7 @@ class GraphService:
                         waited = True
                 rep.update_waits += int(waited)
                 done_t = time.perf_counter() - t0
+                rep.t_last_update = done_t
                 rep.edge_latency_s.extend((done_t - et[applied_to:hi]).tolist())
                 rep.batches += 1
                 rep.edges_applied += hi - applied_to

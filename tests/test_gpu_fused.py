@@ -183,13 +183,18 @@ def test_fused_windows_invalid_batch_then_more_calls(mirror):
     g.close()
 
 
-@pytest.mark.parametrize("n_extra", [0, 1, 2, 3, 5])
-def test_fused_mirror_under_other_streams(n_extra):
-    """With a mirror the two fused pipelines run on library streams forked
-    from and joined to the caller's stream.  Other live streams in the
-    process change which hardware queues those streams sit on; the result
-    must not change: fused equals plain on the array and the mirror, also
-    when the caller works on a non-default stream."""
+@pytest.mark.parametrize("n_extra,lib_streams", [(0, False), (1, False), (2, False), (3, False), (5, False),
+                                                 (0, True), (3, True)])
+def test_fused_mirror_under_other_streams(n_extra, lib_streams):
+    """With a mirror the fused pipelines run in one of two arrangements: the
+    array's on the caller's stream and the mirror's on a handle stream that a
+    probe found running beside it (pairing 1), or both on handle streams
+    forked from and joined to the caller's (pairing 0, forced here by
+    GPMA_FLAG_FUSED_LIB_STREAMS and taken when no handle stream runs
+    beside the caller's).  Other live streams in the process change which
+    hardware queues the streams sit on; the result must not change: fused
+    equals plain on the array and the mirror, also when the caller works on
+    a non-default stream."""
     from paper_1709_05061_amd import GPMA
     extra = []
     for _ in range(n_extra):
@@ -201,9 +206,9 @@ def test_fused_mirror_under_other_streams(n_extra):
     init = np.unique(npu64(synth.random_batch(V, 8000, 7)))
     ops, bs = make_sequence(V, init, 24, seed=11 + n_extra)
     plain = GPMA(V, dev(init), leaf_size=lf, mirror=True)
-    fused = GPMA(V, dev(init), leaf_size=lf, mirror=True, fused_levels=1)
+    fused = GPMA(V, dev(init), leaf_size=lf, mirror=True, fused_levels=1, lib_streams=lib_streams)
     caller = torch.cuda.Stream() if n_extra % 2 else torch.cuda.current_stream()
-    say("fused under", n_extra, "extra streams, caller stream", caller)
+    say("fused under", n_extra, "extra streams, caller stream", caller, "library streams", lib_streams)
     for lo, hi in ((0, 10), (10, 11), (11, 24)):
         for i in range(lo, hi):
             (plain.delete if ops[i] else plain.insert)(dev(bs[i]))
@@ -215,5 +220,11 @@ def test_fused_mirror_under_other_streams(n_extra):
         assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
         assert np.array_equal(npu64(fused.mirror().slots()), npu64(plain.mirror().slots())), (lo, hi)
         assert fused.num_edges == plain.num_edges
+    pairing = fused.fused_pairing(caller)
+    say("pairing", pairing)
+    if lib_streams:
+        assert pairing == 0
+    else:
+        assert pairing in (0, 1)
     plain.close()
     fused.close()
