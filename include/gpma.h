@@ -161,6 +161,12 @@ typedef struct {
  * the array's on the caller's stream (a test knob; results identical). */
 #define GPMA_FLAG_FUSED_LIB_STREAMS 16u
 
+/* gpma_apply_batches sorts the keys of a window of batches with the LSD
+ * radix sort (two launches per 8-bit digit) instead of the splitter sort
+ * (five launches, windows of up to 2^20 keys); a test knob, results
+ * identical. */
+#define GPMA_FLAG_WINDOW_RADIX 32u
+
 /* Per-batch statistics; filled when a non-NULL pointer is passed. */
 typedef struct {
     uint64_t requested;      /* keys passed in */

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgpma.so")
-SOURCES = ["prims.hip", "pma.hip", "analytics.hip", "spmv_binned.hip", "csr_rebuild.hip", "gpma_lock.hip", "fused.hip", "locator.hip", "api.hip"]
+SOURCES = ["prims.hip", "splitter_sort.hip", "pma.hip", "analytics.hip", "spmv_binned.hip", "csr_rebuild.hip", "gpma_lock.hip", "fused.hip", "locator.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

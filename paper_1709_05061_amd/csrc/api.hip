@@ -107,6 +107,7 @@ struct gpma {
         uint8_t *fin_st;
         uint32_t *fin_n;
         uint32_t h_top;
+        bool fin_raw;   // the leaf level was the last: pending updates left in place, uncompacted
     };
     std::vector<GraphEntry> graphs;
     uint32_t geom_version = 1;
@@ -190,6 +191,7 @@ struct gpma {
     uint64_t slots_buf = 0;    // slots the live arrays' buffers hold (>= cap)
     uint32_t spmv_form = 0;    // GPMA_SPMV_*
     bool lib_streams = false;  // GPMA_FLAG_FUSED_LIB_STREAMS
+    bool window_radix = false; // GPMA_FLAG_WINDOW_RADIX
 
     Device dev;
     int prof_on = 0;
@@ -297,7 +299,7 @@ bool params_valid(const gpma_params *p, bool allow_auto) {
         return false;
     if (2 * p->rho_root_pm > p->tau_root_pm) return false;
     if (p->flags & ~(uint32_t)(GPMA_FLAG_MIRROR | GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT |
-                               GPMA_FLAG_LAZY_DELETE | GPMA_FLAG_FUSED_LIB_STREAMS))
+                               GPMA_FLAG_LAZY_DELETE | GPMA_FLAG_FUSED_LIB_STREAMS | GPMA_FLAG_WINDOW_RADIX))
         return false;
     if (p->spmv_form > GPMA_SPMV_BINNED_GATHER) return false;
     if (p->spmv_form == GPMA_SPMV_PULL && !(p->flags & GPMA_FLAG_MIRROR)) return false;
@@ -383,7 +385,7 @@ int ensure_batch(gpma *g, uint64_t b) {
     if (b <= g->bcap) return GPMA_OK;
     free_batch(g);
     uint64_t c = next_pow2(std::max<uint64_t>(b, 4096));
-    size_t tw = std::max(radix_tmp_words(c), scan_tmp_words(c + 1));
+    size_t tw = std::max({radix_tmp_words(c), scan_tmp_words(c + 1), splitter_tmp_words(c)});
     int e = GPMA_OK;
     e |= dev_alloc(g, &g->kS, c);
     e |= dev_alloc(g, &g->kA, c); e |= dev_alloc(g, &g->kB, c);
@@ -592,12 +594,12 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
 // learned locator: fit and dispatch
 
 void do_locate(gpma *g, const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, uint32_t *leaf,
-               uint8_t *status, hipStream_t s) {
+               uint8_t *status, hipStream_t s, const WinSrc *ws = nullptr) {
     if (g->learned && g->loc)
         launch_locate_learned(keys, n_dev, n_max, g->slots, g->row_ptr, g->L, g->lf_log2, g->loc, g->ctl, leaf,
-                              status, &g->ctl->misses, s);
+                              status, &g->ctl->misses, s, ws);
     else
-        launch_locate(keys, n_dev, n_max, g->slots, g->L, g->lf, g->ctl, leaf, status, s);
+        launch_locate(keys, n_dev, n_max, g->slots, g->L, g->lf, g->ctl, leaf, status, s, ws);
 }
 
 // Cholesky solve of the (ridge-regularised) n x n normal equations
@@ -1008,11 +1010,15 @@ void enqueue_window_prefix(gpma *g, uint32_t w, uint64_t n_max, const BatchDesc 
     const uint32_t sb = bit_width(g->V - 1);
     const uint32_t tb = window_tag_bits(g);
     launch_window_fetch(desc, g->fs, stop, w, n_max, g->V, sb, transpose, g->kS, g->wcount, g->werrs, s);
+    // both sorts leave the keys in the same buffer (fixed by the bit count)
     const uint64_t *sorted =
-        radix_sort_keys(g->kS, n_max, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s, g->wcount, nullptr, g->sort_chunks);
+        (!g->window_radix && splitter_sort_fits(n_max))
+            ? splitter_sort_keys(g->kS, n_max, g->wcount, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s)
+            : radix_sort_keys(g->kS, n_max, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s, g->wcount, nullptr,
+                              g->sort_chunks);
     uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
     unique_sorted_dyn(sorted, g->wcount, n_max, ukeys, g->wcount + 1, g->flags, g->tmp, s);
-    launch_window_starts(ukeys, g->wcount + 1, w, sb, g->ustart, g->fs, s);
+    launch_window_starts(ukeys, g->wcount + 1, w, sb, g->ustart, g->fs, g->ctl, s);
     g->wukeys = ukeys;   // the same buffer for every window of this handle (fixed pass count)
 }
 
@@ -1048,13 +1054,34 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     (void)desc;
     (void)transpose;
     const uint32_t sb = bit_width(g->V - 1);
-    launch_window_select(g->fs, stop, g->wukeys, g->ustart, g->werrs, sb, cls, g->kS, g->ctl, s);
+    // the locate kernel takes the batch's keys from the window itself (into
+    // kS) and resets the control block
+    const WinSrc ws{&g->fs->batch, &g->fs->wstart, &g->fs->gen, stop, g->wukeys, g->ustart, g->werrs,
+                    ~(((1ull << kWindowTagBits) - 1) << (32 + sb)), g->kS, g->ctl};
     LevelArrays cur{g->kS, g->leafA, g->stA, &g->ctl->n_in};
     LevelArrays nxt{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
-    do_locate(g, cur.k, cur.n, cls, cur.l, cur.st, s);
+    do_locate(g, nullptr, cur.n, cls, cur.l, cur.st, s, &ws);
     uint64_t lo, hi;
     bounds(g, g->H, 0, &lo, &hi);
     const bool mark = del && g->dead;   // lazy deletion: marks only, no levels
+    // no level above the leaves on the device: the leaf merge leaves
+    // per-block figures (in the batch scratch, free until the next window's
+    // sort) that the finishing kernel sums; the host gathers the pending
+    // updates only for a batch that stops
+    const bool upper = !mark && g->fused_levels >= 1 && g->H > 1 &&
+                       seg_merge_lds_bytes(g->lf, 1) <= (size_t)g->dev.max_lds;
+    if (!mark && !upper) {
+        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+                          g->lf, lo, hi, g->ctl, s, g->tmp);
+        launch_finish_leaf(g->fs, stop, g->ctl, g->tmp, leaf_merge_blocks(g->lf, cls), del, g->lf, g->outs, s);
+        ge->fin_k = cur.k;
+        ge->fin_l = cur.l;
+        ge->fin_st = cur.st;
+        ge->fin_n = nxt.n;
+        ge->h_top = 0;
+        ge->fin_raw = true;
+        return;
+    }
     if (mark)
         launch_leaf_mark(cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->dead, g->deg, g->lf, g->ctl, s);
     else
@@ -1094,6 +1121,7 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     ge->fin_st = cur.st;
     ge->fin_n = cur.n;
     ge->h_top = h_top;
+    ge->fin_raw = false;
 }
 
 gpma::GraphEntry *get_graph(gpma *g, uint64_t cls, bool del, const BatchDesc *desc, uint32_t *stop,
@@ -1147,6 +1175,14 @@ int complete_stopped(gpma *g, bool del, hipStream_t s, gpma_stats *st) {
     read_ctl(g, s);
     if (g->ctl_h->err) return GPMA_EINVAL;
     const uint64_t rem = (ge->fin_n == &g->ctl->lvl[0]) ? g->ctl_h->lvl[0] : g->ctl_h->lvl[1];
+    if (ge->fin_raw) {
+        // gather the leaf level's pending updates (its statistics are in the
+        // control block already), then the levels above
+        LevelArrays nxt{g->kC, g->leafB, g->stB, ge->fin_n};
+        compact_pending(ge->fin_k, ge->fin_l, ge->fin_st, &g->ctl->n_in, g->bcap, nxt.k, nxt.l, nxt.st, nxt.n,
+                        g->flags, g->tmp, del, g->lf, nullptr, s);
+        return finish_levels(g, del, nxt, rem, 1, g->ctl_h->segs, st, s);
+    }
     LevelArrays cur{ge->fin_k, ge->fin_l, ge->fin_st, ge->fin_n};
     return finish_levels(g, del, cur, rem, ge->h_top + 1, g->ctl_h->segs, st, s);
 }
@@ -1516,6 +1552,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     g->astream = s;
     g->spmv_form = p.spmv_form;
     g->lib_streams = (p.flags & GPMA_FLAG_FUSED_LIB_STREAMS) != 0;
+    g->window_radix = (p.flags & GPMA_FLAG_WINDOW_RADIX) != 0;
     g->V = V;
     g->tau_leaf = p.tau_leaf_pm; g->tau_root = p.tau_root_pm;
     g->rho_leaf = p.rho_leaf_pm; g->rho_root = p.rho_root_pm;
@@ -1617,7 +1654,8 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     }
     if (p.flags & GPMA_FLAG_MIRROR) {
         gpma_params mp = p;
-        mp.flags = p.flags & (GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT | GPMA_FLAG_LAZY_DELETE);
+        mp.flags = p.flags & (GPMA_FLAG_LEARNED_LOCATOR | GPMA_FLAG_FUSED_DIRECT | GPMA_FLAG_LAZY_DELETE |
+                              GPMA_FLAG_WINDOW_RADIX);
         mp.leaf_size = g->lf;
         mp.spmv_form = GPMA_SPMV_AUTO;
         uint64_t *tk = nullptr;

@@ -31,6 +31,57 @@ struct Ctl {
     uint32_t root_full;  // lock-based comparator: insertions that found even the root full
 };
 
+// Where a locate kernel takes its batch from.  ukeys == nullptr: the keys
+// passed to it, n from *n_dev, err from ctl->err.  Else the current batch of
+// a fused window: batch j = *batch - *wstart of the window's sorted unique
+// keys ukeys[ustart[j] .. ustart[j+1]), tag bits cleared (none while *stop
+// is set; err when errs[j] == *gen - 1); the kernel writes them to dense[]
+// for the kernels after it, and its first thread resets the batch's control
+// block (n_in, err, level counts, statistics; `misses` is reset by the
+// kernels that read it).
+struct WinSrc {
+    const uint32_t *batch, *wstart, *gen, *stop;
+    const uint64_t *ukeys;
+    const uint32_t *ustart, *errs;
+    uint64_t tag_mask;
+    uint64_t *dense;
+    Ctl *ctl;
+};
+
+struct BatchView {
+    const uint64_t *keys;
+    uint64_t n;
+    bool err;
+    uint64_t mask;
+};
+
+__device__ __forceinline__ BatchView batch_view(const WinSrc &w, const uint64_t *keys, const uint32_t *n_dev,
+                                                uint64_t n_max, const Ctl *ctl) {
+    if (!w.ukeys) {
+        const uint64_t n = *n_dev < n_max ? *n_dev : n_max;
+        return BatchView{keys, n, ctl->err != 0, ~0ull};
+    }
+    const uint32_t j = *w.batch - *w.wstart;
+    const bool stopped = *w.stop != 0;
+    const uint64_t beg = w.ustart[j];
+    uint64_t n = stopped ? 0 : w.ustart[j + 1] - beg;
+    if (n > n_max) n = n_max;
+    const bool err = !stopped && w.errs[j] == *w.gen - 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl *c = w.ctl;
+        c->err = err ? 1u : 0u;
+        c->n_in = (uint32_t)n;
+        c->lvl[0] = 0;
+        c->lvl[1] = 0;
+        c->segs = 0;
+        c->applied = 0;
+        c->noops = 0;
+        c->dn = 0;
+        c->rewritten = 0;
+    }
+    return BatchView{w.ukeys + beg, n, err, w.tag_mask};
+}
+
 __device__ __forceinline__ bool is_guard(uint64_t k) {
     return (uint32_t)k == kGuardDst;
 }
@@ -144,6 +195,9 @@ size_t scan_tmp_words(uint64_t n);
 void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev,
               uint32_t *tmp, hipStream_t s);
 
+// the same in one workgroup (one launch; for up to ~2^16 words)
+void scan_u32_one_block(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev, hipStream_t s);
+
 // keys-only LSD radix sort of n uint64 keys on the bits of the compressed
 // key (src << dbits) | dst', where dst' = dst, or V for a guard.  Result in
 // *out (one of buf_a/buf_b); `in` is not modified.  tmp: radix_tmp_words(n).
@@ -158,6 +212,17 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
                                 hipStream_t s, const uint32_t *n_dev = nullptr, gpma_dev::Ctl *check = nullptr,
                                 int small_chunks = 4);
 
+// splitter sort (splitter_sort.hip): the order of radix_sort_keys for up to
+// 2^20 keys in five launches; n from *n_dev when non-null (<= n_max).  The
+// result is in the buffer radix_sort_keys would return for the same bit
+// counts (buf_a for an odd number of 8-bit passes); the other buffer is
+// overwritten.  tmp: splitter_tmp_words(n_max) words.
+bool splitter_sort_fits(uint64_t n_max);
+size_t splitter_tmp_words(uint64_t n_max);
+const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uint32_t *n_dev, uint32_t sbits,
+                                   uint32_t dbits, uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
+                                   hipStream_t s);
+
 // unique of a sorted array: out receives the distinct keys, *count_dev their
 // number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).
 void unique_sorted(const uint64_t *in, uint64_t n, uint64_t *out, uint32_t *count_dev,
@@ -170,7 +235,7 @@ void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max
 // the number kept goes to *count_dev and the kept pairs get status pending.
 // Also accumulates the level's statistics into ctl (one atomic per block):
 // applied / dn (+-merged updates), noops, merged segments and their slots
-// (cap_h each).
+// (cap_h each); no statistics when ctl is null.
 void compact_pending(const uint64_t *keys, const uint32_t *leaf, const uint8_t *status,
                      const uint32_t *n_dev, uint64_t n_max, uint64_t *keys_out,
                      uint32_t *leaf_out, uint8_t *status_out, uint32_t *count_dev,
@@ -187,11 +252,13 @@ void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, gpma_dev::Ctl
 void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s);
 void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max,
                    const uint64_t *slots, uint64_t L, uint32_t lf, const gpma_dev::Ctl *ctl,
-                   uint32_t *leaf, uint8_t *status, hipStream_t s);
+                   uint32_t *leaf, uint8_t *status, hipStream_t s, const gpma_dev::WinSrc *ws = nullptr);
 void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
                        const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
                        uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf, uint64_t min0,
-                       uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s);
+                       uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s, uint32_t *part = nullptr);
+// blocks of one leaf merge launch over n_max updates (4 words of `part` each)
+uint64_t leaf_merge_blocks(uint32_t lf, uint64_t n_max);
 // workgroup tier at height h >= 1; needs seg_merge_lds_bytes(lf, h) <= max LDS
 size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h);
 int seg_merge_max_lds();

@@ -41,8 +41,12 @@ struct BatchOut {
 
 namespace gpma_host {
 
-void launch_finish(gpma_dev::FusedState *st, uint32_t *stop, const gpma_dev::Ctl *ctl, const uint32_t *pending,
+void launch_finish(gpma_dev::FusedState *st, uint32_t *stop, gpma_dev::Ctl *ctl, const uint32_t *pending,
                    gpma_dev::BatchOut *out, hipStream_t s);
+// the same after a leaf merge that wrote per-block figures to part (nparts
+// blocks): their sums go into ctl (lvl[0]: the updates left pending) first
+void launch_finish_leaf(gpma_dev::FusedState *st, uint32_t *stop, gpma_dev::Ctl *ctl, const uint32_t *part,
+                        uint64_t nparts, bool del, uint32_t lf, gpma_dev::BatchOut *out, hipStream_t s);
 
 // window prefix: the w batches from st->batch, validated, tagged and
 // concatenated into staging (count to *wcount); errs[j] = st->gen for a
@@ -51,13 +55,8 @@ void launch_window_fetch(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *
                          uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, bool transpose, uint64_t *staging,
                          uint32_t *wcount, uint32_t *errs, hipStream_t s);
 // first position of each batch's keys in the window's sorted unique keys;
-// advances st->gen
+// advances st->gen and zeroes ctl->misses
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
-                          gpma_dev::FusedState *st, hipStream_t s);
-// per batch: the current batch's unique keys, untagged, into dense; its
-// control block zeroed with n_in and err set (nothing when stopped)
-void launch_window_select(const gpma_dev::FusedState *st, const uint32_t *stop, const uint64_t *ukeys,
-                          const uint32_t *ustart, const uint32_t *errs, uint32_t sb, uint64_t n_max, uint64_t *dense,
-                          gpma_dev::Ctl *ctl, hipStream_t s);
+                          gpma_dev::FusedState *st, gpma_dev::Ctl *ctl, hipStream_t s);
 
 }  // namespace gpma_host

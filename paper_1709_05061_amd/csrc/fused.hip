@@ -1,16 +1,19 @@
 // Device side of fused batching: a sequence of update batches run without
 // host synchronisation between batches.
 //
-// Batches go in windows.  A window's prefix (k_window_fetch, one radix sort,
-// unique, k_window_starts) sorts all its batches at once: each key carries its
+// Batches go in windows.  A window's prefix (k_window_fetch, one sort --
+// the splitter sort up to 2^20 keys, else the radix sort -- unique,
+// k_window_starts) sorts all its batches at once: each key carries its
 // batch's place in the window above the source bits, so one sort groups the
-// keys by batch and orders them within.  Then, per batch, k_window_select
+// keys by batch and orders them within.  Then, per batch, the locate kernel
 // takes the batch's keys from the window's unique keys (or nothing when the
 // sequence is stopped), the state-dependent steps run (locate, merges,
-// compactions), and k_finish either records the batch's statistics and
-// advances to the next batch, or stops the sequence when the batch still has
-// updates pending above the levels run on the device (those need the
-// host-driven tiers: segments larger than LDS, or the root).  Batches that
+// compactions; with no level above the leaves on the device, the leaf merge
+// counts the batch's statistics and what is left itself), and k_finish either
+// records the batch's statistics and advances to the next batch, or stops the
+// sequence when the batch still has updates pending above the levels run on
+// the device (those need the host-driven tiers: segments larger than LDS, or
+// the root).  Batches that
 // follow a stop see an empty batch and change nothing, so the pending state of
 // the stopped batch survives until the host completes it.
 #include "common.h"
@@ -20,7 +23,7 @@ using namespace gpma_dev;
 
 namespace {
 
-__global__ void k_finish(FusedState *__restrict__ st, uint32_t *__restrict__ stop, const Ctl *__restrict__ ctl,
+__global__ void k_finish(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__restrict__ ctl,
                          const uint32_t *__restrict__ pending, BatchOut *__restrict__ out) {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
     if (*stop) return;   // this replay ran on an empty batch
@@ -37,6 +40,61 @@ __global__ void k_finish(FusedState *__restrict__ st, uint32_t *__restrict__ sto
     out[b].segs = ctl->segs;
     out[b].rewritten = ctl->rewritten;
     out[b].misses = ctl->misses;
+    ctl->misses = 0;   // the next batch's locate counts from zero
+    out[b].lookups = ctl->n_in;
+    st->batch = b + 1;
+}
+
+// k_finish after a leaf merge that left per-block figures in part[4*i ..]
+// (merged, no-ops, leaves merged, pending) instead of compacting: sum them
+// into the control block (reset by the batch's locate), then finish.
+__global__ void __launch_bounds__(1024)
+k_finish_leaf(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__restrict__ ctl,
+              const uint4 *__restrict__ part, uint64_t nparts, int del, uint32_t lf, BatchOut *__restrict__ out) {
+    __shared__ uint32_t red[4][1024 / kWave];
+    if (*stop) return;   // this replay ran on an empty batch (block-uniform)
+    uint32_t v[4] = {0, 0, 0, 0};
+#pragma unroll 4
+    for (uint64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+        const uint4 p = part[i];
+        v[0] += p.x;
+        v[1] += p.y;
+        v[2] += p.z;
+        v[3] += p.w;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++)
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) v[q] += __shfl_xor(v[q], d, kWave);
+    if (__lane_id() == 0)
+#pragma unroll
+        for (int q = 0; q < 4; q++) red[q][threadIdx.x / kWave] = v[q];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    uint32_t t[4] = {0, 0, 0, 0};
+    for (int x = 0; x < 1024 / kWave; x++)
+#pragma unroll
+        for (int q = 0; q < 4; q++) t[q] += red[q][x];
+    ctl->applied = t[0];
+    ctl->dn = del ? -(int64_t)t[0] : (int64_t)t[0];
+    ctl->noops = t[1];
+    ctl->segs = t[2];
+    ctl->rewritten = (uint64_t)t[2] * lf;
+    ctl->lvl[0] = t[3];
+    const uint32_t b = st->batch;
+    if (ctl->err || t[3]) {
+        st->snap = *ctl;
+        st->halted = 1;
+        *stop = 1;
+        return;
+    }
+    out[b].applied = t[0];
+    out[b].noops = t[1];
+    out[b].dn = ctl->dn;
+    out[b].segs = t[2];
+    out[b].rewritten = ctl->rewritten;
+    out[b].misses = ctl->misses;
+    ctl->misses = 0;
     out[b].lookups = ctl->n_in;
     st->batch = b + 1;
 }
@@ -85,48 +143,30 @@ k_window_fetch(const BatchDesc *__restrict__ desc, FusedState *__restrict__ st, 
 
 __global__ void __launch_bounds__(256)
 k_window_starts(const uint64_t *__restrict__ ukeys, const uint32_t *__restrict__ nuniq, uint32_t w, uint32_t sb,
-                uint32_t *__restrict__ ustart, FusedState *__restrict__ st) {
+                uint32_t *__restrict__ ustart, FusedState *__restrict__ st, Ctl *__restrict__ ctl) {
     const uint32_t j = threadIdx.x;
-    if (j == 0) st->gen = st->gen + 1;   // the fetch of this window is done with it
+    if (j == 0) {
+        st->gen = st->gen + 1;   // the fetch of this window is done with it
+        ctl->misses = 0;         // the window's first locate counts from zero
+    }
     if (j > w) return;
     const uint32_t n = *nuniq;
     ustart[j] = j == w ? n : lower_bound_u64(ukeys, n, (uint64_t)j << (32 + sb));
-}
-
-__global__ void __launch_bounds__(256)
-k_window_select(const FusedState *__restrict__ st, const uint32_t *__restrict__ stop, const uint64_t *__restrict__ ukeys,
-                const uint32_t *__restrict__ ustart, const uint32_t *__restrict__ errs, uint32_t sb, uint64_t n_max,
-                uint64_t *__restrict__ dense, Ctl *__restrict__ ctl) {
-    const uint32_t j = st->batch - st->wstart;
-    const bool stopped = *stop != 0;
-    const uint64_t beg = ustart[j];
-    uint64_t n = stopped ? 0 : ustart[j + 1] - beg;
-    if (n > n_max) n = n_max;
-    const uint64_t tag_mask = ~(((1ull << kWindowTagBits) - 1) << (32 + sb));
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        dense[i] = ukeys[beg + i] & tag_mask;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->err = (!stopped && errs[j] == st->gen - 1) ? 1u : 0u;
-        ctl->n_in = (uint32_t)n;
-        ctl->lvl[0] = 0;
-        ctl->lvl[1] = 0;
-        ctl->segs = 0;
-        ctl->applied = 0;
-        ctl->noops = 0;
-        ctl->dn = 0;
-        ctl->rewritten = 0;
-        ctl->misses = 0;
-    }
 }
 
 }  // namespace
 
 namespace gpma_host {
 
-void launch_finish(FusedState *st, uint32_t *stop, const Ctl *ctl, const uint32_t *pending, BatchOut *out,
+void launch_finish(FusedState *st, uint32_t *stop, Ctl *ctl, const uint32_t *pending, BatchOut *out,
                    hipStream_t s) {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, s, st, stop, ctl, pending, out);
+}
+
+void launch_finish_leaf(FusedState *st, uint32_t *stop, Ctl *ctl, const uint32_t *part, uint64_t nparts, bool del,
+                        uint32_t lf, BatchOut *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_leaf, dim3(1), dim3(1024), 0, s, st, stop, ctl, reinterpret_cast<const uint4 *>(part),
+                       nparts, del ? 1 : 0, lf, out);
 }
 
 static uint32_t copy_blocks(uint64_t n) {
@@ -142,15 +182,8 @@ void launch_window_fetch(const BatchDesc *desc, FusedState *st, const uint32_t *
 }
 
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
-                          FusedState *st, hipStream_t s) {
-    hipLaunchKernelGGL(k_window_starts, dim3(1), dim3(128), 0, s, ukeys, nuniq, w, sb, ustart, st);
-}
-
-void launch_window_select(const FusedState *st, const uint32_t *stop, const uint64_t *ukeys, const uint32_t *ustart,
-                          const uint32_t *errs, uint32_t sb, uint64_t n_max, uint64_t *dense, Ctl *ctl,
-                          hipStream_t s) {
-    hipLaunchKernelGGL(k_window_select, dim3(copy_blocks(n_max)), dim3(256), 0, s, st, stop, ukeys, ustart, errs, sb,
-                       n_max, dense, ctl);
+                          FusedState *st, Ctl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_window_starts, dim3(1), dim3(128), 0, s, ukeys, nuniq, w, sb, ustart, st, ctl);
 }
 
 }  // namespace gpma_host

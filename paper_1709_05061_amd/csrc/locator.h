@@ -32,7 +32,7 @@ namespace gpma_host {
 void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
                            const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, const gpma_dev::LocModel *model,
                            const gpma_dev::Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses,
-                           hipStream_t s);
+                           hipStream_t s, const gpma_dev::WinSrc *ws = nullptr);
 size_t loc_gram_words();
 void launch_loc_gram(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, uint64_t stride,
                      uint64_t S, const gpma_dev::LocModel *model, double *gram, hipStream_t s);

@@ -134,15 +134,17 @@ __device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t
 __global__ void __launch_bounds__(256)
 k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint64_t n_max,
                  const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L,
-                 uint32_t lf_log2, const LocModel *__restrict__ model, const Ctl *__restrict__ ctl,
-                 uint32_t *__restrict__ leaf, uint8_t *__restrict__ status, uint32_t *__restrict__ misses) {
+                 uint32_t lf_log2, const LocModel *__restrict__ model, const Ctl *ctl,
+                 uint32_t *__restrict__ leaf, uint8_t *__restrict__ status, uint32_t *misses, WinSrc ws) {
     __shared__ float s_out[256];
     const LocModel m = *model;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t n = *n_dev < n_max ? *n_dev : n_max;
-    if ((uint64_t)blockIdx.x * blockDim.x >= n || ctl->err) return;   // block-uniform
+    const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
+    const uint64_t n = bv.n;
+    if ((uint64_t)blockIdx.x * blockDim.x >= n || bv.err) return;   // block-uniform
     const bool active = i < n;
-    const uint64_t k = active ? keys[i] : 0;
+    const uint64_t k = active ? (bv.keys[i] & bv.mask) : 0;
+    if (active && ws.ukeys) ws.dense[i] = k;
     const Span sp = row_span(row_ptr, key_src(k), lf_log2);
     const uint64_t span = sp.last - sp.first + 1;
     // the model runs (wave-wide, on MFMA) only for waves with a key in a
@@ -271,10 +273,12 @@ namespace gpma_host {
 
 void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
                            const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, const LocModel *model,
-                           const Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses, hipStream_t s) {
+                           const Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses, hipStream_t s,
+                           const WinSrc *ws) {
     if (!n_max) return;
+    const WinSrc w = ws ? *ws : WinSrc{};
     hipLaunchKernelGGL(k_locate_learned, dim3((uint32_t)((n_max + 255) / 256)), dim3(256), 0, s, keys, n_dev,
-                       n_max, slots, row_ptr, L, lf_log2, model, ctl, leaf, status, misses);
+                       n_max, slots, row_ptr, L, lf_log2, model, ctl, leaf, status, misses, w);
 }
 
 size_t loc_gram_words() { return kGram; }

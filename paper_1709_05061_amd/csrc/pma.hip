@@ -57,11 +57,13 @@ __global__ void k_append_guards(uint64_t *__restrict__ dst, uint32_t V) {
 
 __global__ void k_locate(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev,
                          uint64_t n_max, const uint64_t *__restrict__ slots, uint64_t L,
-                         uint32_t lf_log2, const Ctl *__restrict__ ctl, uint32_t *__restrict__ leaf,
-                         uint8_t *__restrict__ status) {
+                         uint32_t lf_log2, const Ctl *ctl, uint32_t *__restrict__ leaf,
+                         uint8_t *__restrict__ status, WinSrc ws) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_max || i >= *n_dev || ctl->err) return;
-    uint64_t k = keys[i];
+    const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
+    if (i >= bv.n || bv.err) return;
+    uint64_t k = bv.keys[i] & bv.mask;
+    if (ws.ukeys) ws.dense[i] = k;
     uint64_t lo = 0, hi = L;   // count of leaves whose pivot is <= k
     while (lo < hi) {
         uint64_t mid = (lo + hi) >> 1;
@@ -111,34 +113,34 @@ __device__ __forceinline__ uint32_t run_end(const uint32_t *__restrict__ leaf, u
 // reads the same leaf, and at level 0 no other group writes that leaf).
 // Group = G lanes, each holding SPL consecutive slots of the leaf (lf = G*SPL).
 
+// What one group's run came to: updates merged, no-ops, merged leaves (0/1)
+// and updates left pending for the level above.
+struct RunStats {
+    uint32_t done, noop, head, pend;
+};
+
 template <int G, int SPL, bool DEL>
-__global__ void __launch_bounds__(256)
-k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
-             uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-             uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
-             uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
-             uint32_t min0, uint32_t max0, Ctl *__restrict__ ctl) {
+__device__ __forceinline__ RunStats
+leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+                 uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+                 uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+                 uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
+                 uint32_t min0, uint32_t max0, const Ctl *__restrict__ ctl, uint64_t *lb, uint64_t *ub,
+                 uint64_t *ob) {
     constexpr int LF = G * SPL;
     constexpr int GPB = 256 / G;   // groups per block
-    __shared__ uint64_t s_leaf[GPB][LF];
-    __shared__ uint64_t s_upd[GPB][LF];
-    __shared__ uint64_t s_out[GPB][LF];
-
     const uint32_t gib = threadIdx.x / G;          // group in block
     const uint32_t gl = threadIdx.x & (G - 1);     // lane in group
     const uint64_t gi = (uint64_t)blockIdx.x * GPB + gib;
-    if (gi >= n_max) return;
+    RunStats rs{0, 0, 0, 0};
+    if (gi >= n_max) return rs;
     const uint32_t n = *n_dev;
-    if (gi >= n || ctl->err) return;
+    if (gi >= n || ctl->err) return rs;
     const uint32_t i = (uint32_t)gi;
     const uint32_t lf_i = leaf[i];
-    if (i > 0 && leaf[i - 1] == lf_i) return;      // not the head of its run
+    if (i > 0 && leaf[i - 1] == lf_i) return rs;   // not the head of its run
     const uint32_t e = run_end(leaf, i, n, lf_i, 0);
     const uint32_t k = e - i;
-
-    uint64_t *lb = s_leaf[gib];
-    uint64_t *ub = s_upd[gib];
-    uint64_t *ob = s_out[gib];
     const uint64_t base = (uint64_t)lf_i * LF;
     uint64_t mine[SPL];
 #pragma unroll
@@ -178,9 +180,15 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
         if (valid) status[i + t] = app ? kPending : kNoop;
         kapp += group_sum<G>(app ? 1u : 0u);
     }
-    if (kapp == 0) return;
+    rs.noop = k - kapp;
+    if (kapp == 0) return rs;
     const bool pass = DEL ? (c >= kapp + min0) : (c + kapp <= max0);
-    if (!pass) return;
+    if (!pass) {
+        rs.pend = kapp;
+        return rs;
+    }
+    rs.done = kapp;
+    rs.head = 1;
     wave_lds_sync();
 
     // Merge + even re-dispatch: a leaf is one segment of one leaf, so the
@@ -225,6 +233,51 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
             atomicAdd(&deg[key_src(keys[i + t])], DEL ? 0xFFFFFFFFu : 1u);
         }
         status[i + t] = t == 0 ? (uint8_t)(st | kHead) : st;
+    }
+    return rs;
+}
+
+// One group of G lanes per update; the head of each run of updates bound for
+// one leaf merges the run.  part (optional): each block writes what its runs
+// came to -- updates merged, no-ops, leaves merged, updates left pending --
+// to part[4*block .. +3] (plain stores: per-block atomics on one control
+// block serialise at the L2), for a finishing kernel to sum in place of a
+// compaction's count.
+template <int G, int SPL, bool DEL>
+__global__ void __launch_bounds__(256)
+k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
+             uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
+             uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+             uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
+             uint32_t min0, uint32_t max0, Ctl *__restrict__ ctl, uint32_t *__restrict__ part) {
+    constexpr int LF = G * SPL;
+    constexpr int GPB = 256 / G;   // groups per block
+    __shared__ uint64_t s_leaf[GPB][LF];
+    __shared__ uint64_t s_upd[GPB][LF];
+    __shared__ uint64_t s_out[GPB][LF];
+    __shared__ uint32_t s_red[4][256 / kWave];
+    const uint32_t gib = threadIdx.x / G;
+    RunStats rs = leaf_merge_group<G, SPL, DEL>(keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead,
+                                                min0, max0, ctl, s_leaf[gib], s_upd[gib], s_out[gib]);
+    if (!part) return;   // grid-uniform
+    // every lane of a group holds the group's figures: count lane 0's
+    uint32_t v[4] = {rs.done, rs.noop, rs.head, rs.pend};
+    const bool lead = (threadIdx.x & (G - 1)) == 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        v[q] = lead ? v[q] : 0u;
+#pragma unroll
+        for (int d = kWave / 2; d >= 1; d >>= 1) v[q] += __shfl_xor(v[q], d, kWave);
+    }
+    const uint32_t w = threadIdx.x / kWave;
+    if (__lane_id() == 0)
+#pragma unroll
+        for (int q = 0; q < 4; q++) s_red[q][w] = v[q];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        uint32_t t = 0;
+        for (int x = 0; x < 256 / kWave; x++) t += s_red[threadIdx.x][x];
+        part[4 * (uint64_t)blockIdx.x + threadIdx.x] = t;
     }
 }
 
@@ -555,40 +608,53 @@ void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s) {
 
 void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
                    uint64_t L, uint32_t lf, const Ctl *ctl, uint32_t *leaf, uint8_t *status,
-                   hipStream_t s) {
+                   hipStream_t s, const WinSrc *ws) {
     if (!n_max) return;
+    const WinSrc w = ws ? *ws : WinSrc{};
     hipLaunchKernelGGL(k_locate, dim3((uint32_t)div_up(n_max, 256)), dim3(256), 0, s, keys, n_dev,
-                       n_max, slots, L, log2_u32(lf), ctl, leaf, status);
+                       n_max, slots, L, log2_u32(lf), ctl, leaf, status, w);
 }
 
 template <int G, int SPL>
 static void leaf_merge_t(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
                          const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
                          uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t min0, uint32_t max0,
-                         Ctl *ctl, hipStream_t s) {
+                         Ctl *ctl, uint32_t *part, hipStream_t s) {
     constexpr int GPB = 256 / G;
     dim3 grid((uint32_t)div_up(n_max, GPB));
     if (del)
         hipLaunchKernelGGL((k_leaf_merge<G, SPL, true>), grid, dim3(256), 0, s, keys, leaf, status,
-                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl);
+                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl, part);
     else
         hipLaunchKernelGGL((k_leaf_merge<G, SPL, false>), grid, dim3(256), 0, s, keys, leaf, status,
-                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl);
+                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl, part);
 }
+
+// groups of one leaf merge launch: G = lf / SPL lanes each, 256 / G per block
+static uint32_t leaf_group_lanes(uint32_t lf) {
+    switch (lf) {
+        case 16: return 8;
+        case 32: return 16;
+        case 64: return 32;
+        default: return 64;
+    }
+}
+
+uint64_t leaf_merge_blocks(uint32_t lf, uint64_t n_max) { return div_up(n_max, 256 / leaf_group_lanes(lf)); }
 
 void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
                        const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
                        uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf, uint64_t min0,
-                       uint64_t max0, Ctl *ctl, hipStream_t s) {
+                       uint64_t max0, Ctl *ctl, hipStream_t s, uint32_t *part) {
     if (!n_max) return;
     uint32_t mn = (uint32_t)min0, mx = (uint32_t)max0;
     switch (lf) {
-        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
-        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
-        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
-        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
-        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
-        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, s); break;
+        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
     }
 }
 

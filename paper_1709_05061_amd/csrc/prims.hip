@@ -284,7 +284,7 @@ k_flag_pending(const uint8_t *__restrict__ status, const uint32_t *__restrict__ 
     const int w = threadIdx.x / kWave;
     if (__lane_id() == 0) { red[0][w] = done; red[1][w] = noop; red[2][w] = head; }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && ctl) {
         uint32_t a = 0, b = 0, c = 0;
         for (int k = 0; k < 256 / kWave; k++) { a += red[0][k]; b += red[1][k]; c += red[2][k]; }
         if (a) {
@@ -433,7 +433,8 @@ k_pending_scatter(const uint64_t *__restrict__ keys, const uint32_t *__restrict_
     __shared__ uint32_t red[3][256 / kWave];
     uint32_t before, total;
     tile_prefix(st, ntiles, blockIdx.x, &before, &total);
-    if (blockIdx.x == 0) {
+    if (blockIdx.x == 0 && !ctl && threadIdx.x == 0) *count_dev = total;
+    if (blockIdx.x == 0 && ctl) {
         // the level's statistics, once
         uint32_t v[3] = {0, 0, 0};
         for (uint32_t i = threadIdx.x; i < ntiles; i += blockDim.x) {
@@ -513,6 +514,10 @@ void scan_u32(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tmp, ntiles, total_dev);
     hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)ntiles), dim3(kScanThreads), 0, s, in, out, n,
                        tmp);
+}
+
+void scan_u32_one_block(const uint32_t *in, uint32_t *out, uint64_t n, uint32_t *total_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n, total_dev);
 }
 
 // keys per tile: 256 threads x 64-key chunks per wave x CH

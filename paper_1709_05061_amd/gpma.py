@@ -24,6 +24,7 @@ GPMA_FLAG_LEARNED_LOCATOR = 2
 GPMA_FLAG_FUSED_DIRECT = 4
 GPMA_FLAG_LAZY_DELETE = 8
 GPMA_FLAG_FUSED_LIB_STREAMS = 16
+GPMA_FLAG_WINDOW_RADIX = 32
 SPMV_FORMS = {"auto": 0, "binned": 1, "binned_coarse": 2, "pull": 3, "push": 4, "binned_gather": 5}
 EMPTY = 0xFFFFFFFFFFFFFFFF
 GUARD_DST = 0xFFFFFFFF
@@ -403,7 +404,8 @@ class GPMA(_HandleView):
     caps the LDS bytes of the workgroup merge tier (0 = all; 1 sends every
     level above the leaves to the device tier); spmv picks PageRank's SpMV
     (a key of SPMV_FORMS); lib_streams forces fused batching with a mirror
-    onto two handle streams.  allocator: a TorchAllocator (the default: a new
+    onto two handle streams; window_sort picks the sort of a fused window's
+    keys ("splitter", or "radix" for the LSD radix sort).  allocator: a TorchAllocator (the default: a new
     one per handle, so the library's memory comes from torch's caching
     allocator), or False for the library's own hipMalloc."""
 
@@ -411,10 +413,13 @@ class GPMA(_HandleView):
                  tau_leaf=920, tau_root=800, rho_leaf=80, rho_root=400, mirror: bool = False,
                  learned: bool = False, stream=None, fused_direct: bool = False, sort_tile: int = 0,
                  fused_levels: int = 1, lazy_delete: bool = False, lds_tier: int = 0, spmv: str = "auto",
-                 lib_streams: bool = False, allocator=None):
+                 lib_streams: bool = False, window_sort: str = "splitter", allocator=None):
+        if window_sort not in ("splitter", "radix"):
+            raise ValueError("window_sort must be 'splitter' or 'radix'")
         flags = ((GPMA_FLAG_MIRROR if mirror else 0) | (GPMA_FLAG_LEARNED_LOCATOR if learned else 0)
                  | (GPMA_FLAG_FUSED_DIRECT if fused_direct else 0) | (GPMA_FLAG_LAZY_DELETE if lazy_delete else 0)
-                 | (GPMA_FLAG_FUSED_LIB_STREAMS if lib_streams else 0))
+                 | (GPMA_FLAG_FUSED_LIB_STREAMS if lib_streams else 0)
+                 | (GPMA_FLAG_WINDOW_RADIX if window_sort == "radix" else 0))
         p = gpma_params(leaf_size, tau_leaf, tau_root, rho_leaf, rho_root, flags, sort_tile, fused_levels,
                         lds_tier, SPMV_FORMS[spmv])
         if allocator is None:

@@ -228,3 +228,71 @@ def test_fused_mirror_under_other_streams(n_extra, lib_streams):
         assert pairing in (0, 1)
     plain.close()
     fused.close()
+
+
+def _window_case(kind, seed):
+    """(V, leaf size, initial keys, ops, batches) of one window-sort case."""
+    rng = np.random.default_rng(seed)
+
+    def rand(V, n):
+        return (rng.integers(0, V, n).astype(np.uint64) << np.uint64(32)) | rng.integers(0, V, n).astype(np.uint64)
+
+    if kind == "duplicates":
+        # one key repeated past what a bucket sorts in LDS, in an insert and
+        # in a delete window: the bucket takes the global-memory path
+        V = 1 << 12
+        init = np.unique(rand(V, 1 << 15))
+        hot = np.uint64((7 << 32) | 9)
+        live_hot = init[len(init) // 2]
+        ops = [0, 1, 0, 1]
+        bs = [np.concatenate([np.full(9000, hot, np.uint64), rand(V, 3000)]),
+              np.concatenate([np.full(5000, live_hot, np.uint64), init[:2000]]),
+              np.full(6000, hot, np.uint64),
+              np.concatenate([rand(V, 700), np.full(4500, hot, np.uint64)])]
+        return V, 16, init, ops, bs
+    if kind == "tiny":
+        V = 1 << 10
+        init = np.unique(rand(V, 1 << 13))
+        ops = [0, 1, 0, 0, 1, 0, 1]
+        bs = [rand(V, 1), init[:1], rand(V, 2), rand(V, 3), init[5:8], np.zeros(0, np.uint64), rand(V, 1)]
+        return V, 16, init, ops, bs
+    # "large": windows of 2^20 keys (the splitter sort's largest) and of
+    # 1.5 * 2^20 keys (the radix sort)
+    V = 1 << 16
+    init = np.unique(rand(V, 1 << 20))
+    ops = [1, 0, 0, 1, 0]
+    half = 1 << 19
+    bs = [init[rng.choice(init.size, half, replace=False)], rand(V, half),
+          rand(V, half), init[rng.choice(init.size, half, replace=False)], rand(V, half)]
+    return V, 32, init, ops, bs
+
+
+@pytest.mark.parametrize("kind", ["duplicates", "tiny", "large"])
+@pytest.mark.parametrize("window_sort", ["splitter", "radix"])
+def test_window_sorts_agree_with_the_oracle(kind, window_sort):
+    """Both sorts of a fused window's keys (the splitter sort, and the radix
+    sort it replaces) give the oracle's slots: repeated keys beyond a bucket's
+    LDS capacity, windows of 1-3 keys and an empty batch, and windows at and
+    above the splitter sort's 2^20-key limit."""
+    from paper_1709_05061_amd import GPMA
+    V, lf, init, ops, bs = _window_case(kind, 31)
+    mirror = kind != "large"
+    g = GPMA(V, dev(init), leaf_size=lf, mirror=mirror, window_sort=window_sort)
+    ref = O.OraclePMA(V, init, lf)
+    cuts = [0, 2, len(ops)]
+    for c in range(len(cuts) - 1):
+        lo, hi = cuts[c], cuts[c + 1]
+        say(kind, window_sort, "batches", lo, hi, [b.size for b in bs[lo:hi]])
+        st = g.apply_batches(ops[lo:hi], [dev(b) for b in bs[lo:hi]])
+        applied = 0
+        for i in range(lo, hi):
+            (ref.delete if ops[i] else ref.insert)(bs[i])
+            applied += ref.last_applied()
+        assert st.applied == applied, (kind, window_sort, lo, hi)
+        assert np.array_equal(npu64(g.slots()), ref.slots()), (kind, window_sort, lo, hi)
+        if mirror:
+            k = g.keys()
+            tr = ((k & 0xFFFFFFFF) << 32) | (k >> 32)
+            assert torch.equal(g.mirror().keys(), torch.sort(tr)[0])
+    assert g.num_edges + V == ref.size   # the oracle counts the V guards
+    g.close()
