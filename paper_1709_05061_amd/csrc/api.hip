@@ -562,23 +562,40 @@ struct LevelArrays {
 // checked and (if it passes) gathered, merged and re-dispatched by kernels.
 int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint64_t rem,
                       uint64_t lo, uint64_t hi, hipStream_t s) {
-    std::vector<uint32_t> lh(rem);
+    // one scan of every leaf's live count, then the live entries of each
+    // run's segment from it, read back with the runs' leaves in one round trip
+    int e = ensure_dt(g, 0, g->L);
+    if (e) return e;
+    launch_leaf_counts_u32(g->cnt, g->dead, 0, g->L, g->dt_off, s);
+    scan_u32(g->dt_off, g->dt_off, g->L, g->small, g->dt_tmp, s);
+    launch_seg_live(c.l, rem, h, g->dt_off, g->L, g->small, g->flags, s);
+    std::vector<uint32_t> lh(rem), nsh(rem);
     hipMemcpyAsync(lh.data(), c.l, rem * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
+    hipMemcpyAsync(nsh.data(), g->flags, rem * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
     const uint64_t P = 1ull << h;
+    // the merge buffers for the largest passing segment, before any write
+    uint64_t need = 0;
+    for (uint64_t i = 0; i < rem;) {
+        const uint32_t seg = lh[i] >> h;
+        uint64_t j = i;
+        while (j < rem && (lh[j] >> h) == seg) j++;
+        const uint64_t k = j - i, ns = nsh[i];
+        if (del ? (ns >= k + lo) : (ns + k <= hi)) need = std::max<uint64_t>(need, ns + k);
+        i = j;
+    }
+    if (need && (e = ensure_dt(g, need, 0))) return e;
     for (uint64_t i = 0; i < rem;) {
         const uint32_t seg = lh[i] >> h;
         uint64_t j = i;
         while (j < rem && (lh[j] >> h) == seg) j++;
         const uint64_t k = j - i, first = (uint64_t)seg << h;
-        uint64_t ns = 0;
-        int e = segment_offsets(g, first, P, &ns, s);
-        if (e) return e;
+        const uint64_t ns = nsh[i];
         const bool pass = del ? (ns >= k + lo) : (ns + k <= hi);
         if (pass) {
-            e = ensure_dt(g, ns + k, 0);
-            if (e) return e;
-            launch_gather_segment(g->slots, g->cnt, g->dead, first, P, g->lf, g->dt_off, g->dtA, s);
+            // the scan's part from this segment's first leaf (segments
+            // rewritten earlier in the loop are disjoint from it)
+            launch_gather_segment(g->slots, g->cnt, g->dead, first, P, g->lf, g->dt_off + first, g->dtA, s);
             launch_merge_sorted(del, g->dtA, ns, c.k + i, k, g->dtB, s);
             launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->cnt, g->dead, g->row_ptr, first, P, g->lf,
                             s);

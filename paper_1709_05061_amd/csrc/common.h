@@ -269,9 +269,17 @@ void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t
 // device tier pieces (one segment at a time; also the root rebuild and bulk load)
 // (dead: per-leaf marked counts of a lazy-deletion array, else null; the
 // counts and the gather then cover live entries only)
+// (leaf_off: exclusive scan of the segment's live leaf counts, or the part
+// of one over more leaves that starts at the segment: offsets are taken
+// relative to leaf_off[0])
 void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, const uint32_t *dead,
                            uint64_t first_leaf, uint64_t P, uint32_t lf, const uint32_t *leaf_off,
                            uint64_t *out, hipStream_t s);
+// live entries of the level-h segment of each run of pending updates, at the
+// run's head in ns_out (pre: exclusive scan of all L live leaf counts, *total
+// their sum)
+void launch_seg_live(const uint32_t *leaf, uint64_t rem, uint32_t h, const uint32_t *pre, uint64_t L,
+                     const uint32_t *total, uint32_t *ns_out, hipStream_t s);
 void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_t *U, uint64_t k,
                          uint64_t *out, hipStream_t s);
 void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *dead,

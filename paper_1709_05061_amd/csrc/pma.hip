@@ -446,14 +446,30 @@ __global__ void k_leaf_counts_u32(const uint16_t *__restrict__ cnt, const uint32
 }
 
 // compacted entries of the segment, in order: leaf j's prefix goes to
-// out[leaf_off[j] ..]
+// out[leaf_off[j] - leaf_off[0] ..] (leaf_off: an exclusive scan of live
+// counts that may start anywhere)
 __global__ void k_gather_segment(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
                                  uint64_t first_leaf, uint64_t P, uint32_t lf_log2,
                                  const uint32_t *__restrict__ leaf_off, uint64_t *__restrict__ out) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (P << lf_log2)) return;
     uint64_t j = p >> lf_log2, o = p & ((1u << lf_log2) - 1);
-    if (o < cnt[first_leaf + j]) out[leaf_off[j] + o] = slots[(first_leaf << lf_log2) + p];
+    if (o < cnt[first_leaf + j]) out[leaf_off[j] - leaf_off[0] + o] = slots[(first_leaf << lf_log2) + p];
+}
+
+// The live entries of each segment of P = 2^h leaves that a run of pending
+// updates falls in, written at the run's head: pre is the exclusive scan of
+// all L live leaf counts, *total their sum.
+__global__ void k_seg_live(const uint32_t *__restrict__ leaf, uint64_t rem, uint32_t h,
+                           const uint32_t *__restrict__ pre, uint64_t L, const uint32_t *__restrict__ total,
+                           uint32_t *__restrict__ ns_out) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rem) return;
+    const uint32_t seg = leaf[i] >> h;
+    if (i > 0 && (leaf[i - 1] >> h) == seg) return;
+    const uint64_t first = (uint64_t)seg << h;
+    const uint64_t last = first + (1ull << h);
+    ns_out[i] = (last < L ? pre[last] : *total) - pre[first];
 }
 
 // the same with marked entries dropped: one wave per leaf, live entries
@@ -466,7 +482,7 @@ k_gather_live(const uint64_t *__restrict__ slots, const uint16_t *__restrict__ c
     const uint32_t lane = __lane_id();
     const uint32_t cj = cnt[first_leaf + j];
     const uint64_t base = (first_leaf + j) << lf_log2;
-    uint64_t at = leaf_off[j];
+    uint64_t at = leaf_off[j] - leaf_off[0];
     for (uint32_t o0 = 0; o0 < cj; o0 += kWave) {
         const uint32_t o = o0 + lane;
         const uint64_t v = o < cj ? slots[base + o] : kEmpty;
@@ -717,6 +733,13 @@ void launch_gather_segment(const uint64_t *slots, const uint16_t *cnt, const uin
     uint64_t total = P * lf;
     hipLaunchKernelGGL(k_gather_segment, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, slots,
                        cnt, first_leaf, P, log2_u32(lf), leaf_off, out);
+}
+
+void launch_seg_live(const uint32_t *leaf, uint64_t rem, uint32_t h, const uint32_t *pre, uint64_t L,
+                     const uint32_t *total, uint32_t *ns_out, hipStream_t s) {
+    if (rem)
+        hipLaunchKernelGGL(k_seg_live, dim3((uint32_t)div_up(rem, 256)), dim3(256), 0, s, leaf, rem, h, pre, L,
+                           total, ns_out);
 }
 
 void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_t *U, uint64_t k,

@@ -35,7 +35,7 @@ constexpr int kSsTileThreads = 256;
 constexpr int kSsTileItems = 8;
 constexpr uint32_t kSsTile = kSsTileThreads * kSsTileItems;   // 2048 keys a count / scatter tile
 constexpr uint32_t kSsMaxBuckets = 1024;
-constexpr uint32_t kSsOversample = 8;                    // sample keys per bucket
+constexpr uint32_t kSsOversample = 4;                    // sample keys per bucket
 constexpr uint64_t kSsMaxKeys = 1ull << 20;
 constexpr uint64_t kSsTarget = 512;                      // keys a bucket holds on average (at most)
 constexpr uint64_t kSsFuseCounts = 1ull << 14;           // counts a scatter tile prefixes itself
@@ -54,14 +54,17 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, uint32_t m) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Bitonic sort, ascending, of the P = 1024*R keys a 1024-thread workgroup
-// holds: k[r] of thread t is the key at index r*1024 + t.  Partners closer
-// than a wave trade through lane shuffles, partners in other waves through
-// lds (P words), partners 1024 or more apart sit in the same thread.
+// Bitonic sort, ascending, of the first P keys (P a power of two, 64 <= P <=
+// 1024*R) a 1024-thread workgroup holds: k[r] of thread t is the key at index
+// r*1024 + t.  Partners closer than a wave trade through lane shuffles,
+// partners in other waves through lds (1024*R words), partners 1024 or more
+// apart sit in the same thread.  The sort is bound by vector ALU issue (some
+// 20 instructions per key and stage), so waves wholly past P skip the
+// arithmetic and only keep to the barriers.
 template <int R>
-__device__ void block_bitonic(uint64_t (&k)[R], uint64_t *lds) {
-    constexpr uint32_t P = 1024u * R;
+__device__ void block_bitonic(uint64_t (&k)[R], uint64_t *lds, uint32_t P) {
     const uint32_t t = threadIdx.x;
+    const bool live = (t & ~(uint32_t)(kWave - 1)) < P;   // wave-uniform
     for (uint32_t kk = 2; kk <= P; kk <<= 1) {
         for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
             if (j >= 1024) {
@@ -77,18 +80,20 @@ __device__ void block_bitonic(uint64_t (&k)[R], uint64_t *lds) {
                     k[r | rj] = sw ? a : b;
                 }
             } else if (j >= (uint32_t)kWave) {
+                if (live)
 #pragma unroll
-                for (int r = 0; r < R; r++) lds[(uint32_t)r * 1024u + t] = k[r];
+                    for (int r = 0; r < R; r++) lds[(uint32_t)r * 1024u + t] = k[r];
                 __syncthreads();
+                if (live)
 #pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const uint32_t idx = (uint32_t)r * 1024u + t;
-                    const uint64_t o = lds[idx ^ j];
-                    const bool want_min = ((idx & j) == 0) == ((idx & kk) == 0);
-                    k[r] = want_min ? (o < k[r] ? o : k[r]) : (o > k[r] ? o : k[r]);
-                }
+                    for (int r = 0; r < R; r++) {
+                        const uint32_t idx = (uint32_t)r * 1024u + t;
+                        const uint64_t o = lds[idx ^ j];
+                        const bool want_min = ((idx & j) == 0) == ((idx & kk) == 0);
+                        k[r] = want_min ? (o < k[r] ? o : k[r]) : (o > k[r] ? o : k[r]);
+                    }
                 __syncthreads();
-            } else {
+            } else if (live) {
 #pragma unroll
                 for (int r = 0; r < R; r++) {
                     const uint32_t idx = (uint32_t)r * 1024u + t;
@@ -104,13 +109,15 @@ __device__ void block_bitonic(uint64_t (&k)[R], uint64_t *lds) {
 // the m <= 1024*R keys src[0..m) sorted into dst[0..m) (src may equal dst)
 template <int R>
 __device__ void sort_small(const uint64_t *src, uint64_t *dst, uint32_t m, uint64_t *lds) {
+    uint32_t P = kWave;
+    while (P < m) P <<= 1;
     uint64_t k[R];
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const uint32_t idx = (uint32_t)r * 1024u + threadIdx.x;
         k[r] = idx < m ? src[idx] : ~0ull;   // padding sorts last
     }
-    block_bitonic<R>(k, lds);
+    block_bitonic<R>(k, lds, P);
 #pragma unroll
     for (int r = 0; r < R; r++) {
         const uint32_t idx = (uint32_t)r * 1024u + threadIdx.x;
@@ -147,7 +154,7 @@ k_ss_splitters(const uint64_t *__restrict__ keys, uint64_t n_max, const uint32_t
         const uint32_t idx = (uint32_t)r * 1024u + threadIdx.x;
         k[r] = keys[((uint64_t)idx * n) / S];
     }
-    block_bitonic<R>(k, lds);
+    block_bitonic<R>(k, lds, S);
 #pragma unroll
     for (int r = 0; r < R; r++) lds[(uint32_t)r * 1024u + threadIdx.x] = k[r];
     __syncthreads();
