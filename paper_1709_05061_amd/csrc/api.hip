@@ -110,6 +110,17 @@ struct gpma {
         bool fin_raw;   // the leaf level was the last: pending updates left in place, uncompacted
     };
     std::vector<GraphEntry> graphs;
+    // paired windows (this handle with its mirror, one launch per step):
+    // graphs of window prefixes and of batches, valid while both handles'
+    // geom_version are unchanged
+    struct PairEntry {
+        hipGraphExec_t exec;
+        uint32_t w;       // window prefix: batches in the window (0 for a batch graph)
+        uint64_t cls;
+        bool del;
+        uint32_t vg, vm;  // geom_version of this handle and of its mirror
+    };
+    std::vector<PairEntry> pgraphs;
     uint32_t geom_version = 1;
     hipStream_t cap_stream = nullptr;
     // fused batching with a mirror: the mirror's batches run on side or
@@ -368,6 +379,9 @@ void drop_graphs(gpma *g) {
     for (auto &e : g->wgraphs)
         if (e.exec) hipGraphExecDestroy(e.exec);
     g->wgraphs.clear();
+    for (auto &e : g->pgraphs)
+        if (e.exec) hipGraphExecDestroy(e.exec);
+    g->pgraphs.clear();
     g->geom_version++;
 }
 
@@ -1141,6 +1155,144 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     ge->fin_raw = false;
 }
 
+// ---- paired windows: the array g and its mirror m run every step of a
+// window in one launch (the grid's y index picks the side), so a window takes
+// half the launches.  Used when both sides take the same kernels: the
+// splitter sort without a count scan, the two-kernel unique, the leaf level
+// as the last device level, no lazy-deletion marks, the same locate.
+
+bool pairable_window(const gpma *g, const gpma *m, uint64_t wcls, const uint8_t *ops, uint32_t from, uint32_t to) {
+    for (const gpma *h : {g, m})
+        if (h->fused_direct || h->window_radix || h->lib_streams || !window_tag_bits(h) || h->bcap != g->bcap)
+            return false;
+    if (g->lf != m->lf || g->V != m->V || (g->learned && g->loc) != (m->learned && m->loc)) return false;
+    if (!splitter_sort_pairable(wcls) || !unique_pairable(wcls)) return false;
+    for (const gpma *h : {g, m}) {
+        const bool upper = h->fused_levels >= 1 && h->H > 1 && seg_merge_lds_bytes(h->lf, 1) <= (size_t)h->dev.max_lds;
+        if (upper) return false;
+        for (uint32_t i = from; i < to; i++)
+            if (ops[i] && h->dead) return false;
+    }
+    return true;
+}
+
+void enqueue_window_prefix2(gpma *g, gpma *m, uint32_t w, uint64_t n_max, const BatchDesc *desc, hipStream_t s) {
+    const uint32_t sb = bit_width(g->V - 1);
+    const uint32_t tb = window_tag_bits(g);
+    gpma *h[2] = {g, m};
+    FusedState *st[2] = {g->fs, m->fs};
+    const uint32_t *stop[2] = {g->stop, m->stop};
+    uint64_t *kS[2] = {g->kS, m->kS};
+    uint32_t *wcount[2] = {g->wcount, m->wcount};
+    uint32_t *errs[2] = {g->werrs, m->werrs};
+    launch_window_fetch2(desc, st, stop, w, n_max, g->V, sb, kS, wcount, errs, s);
+    const uint64_t *in[2] = {g->kS, m->kS};
+    const uint32_t *nd[2] = {g->wcount, m->wcount};
+    uint64_t *ba[2] = {g->kA, m->kA}, *bb[2] = {g->kB, m->kB};
+    uint32_t *tmp[2] = {g->tmp, m->tmp};
+    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s);
+    const uint64_t *sorted[2];
+    uint64_t *ukeys[2];
+    uint32_t *nuniq[2];
+    const uint64_t *uk_c[2];
+    const uint32_t *nu_c[2];
+    uint32_t *ustart[2];
+    Ctl *ctl[2];
+    for (int k = 0; k < 2; k++) {
+        sorted[k] = which ? h[k]->kB : h[k]->kA;
+        ukeys[k] = which ? h[k]->kA : h[k]->kB;
+        nuniq[k] = h[k]->wcount + 1;
+        uk_c[k] = ukeys[k];
+        nu_c[k] = nuniq[k];
+        ustart[k] = h[k]->ustart;
+        ctl[k] = h[k]->ctl;
+        h[k]->wukeys = ukeys[k];
+    }
+    unique_sorted_dyn2(sorted, nd, n_max, ukeys, nuniq, tmp, s);
+    launch_window_starts2(uk_c, nu_c, w, sb, ustart, st, ctl, s);
+}
+
+void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t s) {
+    const uint32_t sb = bit_width(g->V - 1);
+    const uint64_t tmask = ~(((1ull << kWindowTagBits) - 1) << (32 + sb));
+    gpma *h[2] = {g, m};
+    WinSrc ws[2];
+    const uint64_t *slots_c[2], *keys_c[2];
+    uint64_t *slots[2], L[2], lo[2], hi[2];
+    const uint32_t *row_ptr_c[2], *leaf_c[2], *nd[2];
+    uint32_t *leaf[2], *misses[2], *row_ptr[2], *deg[2], *dead[2], *part[2], *stop[2];
+    uint8_t *status[2];
+    uint16_t *cnt[2];
+    Ctl *ctl[2];
+    const Ctl *ctl_c[2];
+    const LocModel *model[2];
+    FusedState *st[2];
+    BatchOut *outs[2];
+    const uint32_t *part_c[2];
+    for (int k = 0; k < 2; k++) {
+        gpma *x = h[k];
+        ws[k] = WinSrc{&x->fs->batch, &x->fs->wstart, &x->fs->gen, x->stop, x->wukeys, x->ustart, x->werrs, tmask,
+                       x->kS, x->ctl};
+        slots[k] = x->slots;
+        slots_c[k] = x->slots;
+        keys_c[k] = x->kS;
+        L[k] = x->L;
+        bounds(x, x->H, 0, &lo[k], &hi[k]);
+        row_ptr[k] = x->row_ptr;
+        row_ptr_c[k] = x->row_ptr;
+        leaf[k] = x->leafA;
+        leaf_c[k] = x->leafA;
+        status[k] = x->stA;
+        nd[k] = &x->ctl->n_in;
+        misses[k] = &x->ctl->misses;
+        deg[k] = x->deg;
+        dead[k] = x->dead;
+        cnt[k] = x->cnt;
+        ctl[k] = x->ctl;
+        ctl_c[k] = x->ctl;
+        model[k] = x->loc;
+        part[k] = x->tmp;
+        part_c[k] = x->tmp;
+        stop[k] = x->stop;
+        st[k] = x->fs;
+        outs[k] = x->outs;
+    }
+    if (g->learned && g->loc)
+        launch_locate_learned2(cls, slots_c, row_ptr_c, L, g->lf_log2, model, ctl_c, leaf, status, misses, ws, s);
+    else
+        launch_locate2(cls, slots_c, L, g->lf, ctl_c, leaf, status, ws, s);
+    launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, cnt, row_ptr, deg, dead, g->lf, lo, hi, ctl,
+                       part, s);
+    launch_finish_leaf2(st, stop, ctl, part_c, leaf_merge_blocks(g->lf, cls), del, g->lf, outs, s);
+}
+
+// The cached graph of a paired window prefix (w > 0) or batch (w == 0).
+hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint32_t w, uint64_t cls, bool del, const BatchDesc *desc) {
+    // entries of an older geometry of either side go first
+    for (size_t i = 0; i < g->pgraphs.size();) {
+        auto &e = g->pgraphs[i];
+        if (e.vg != g->geom_version || e.vm != m->geom_version) {
+            if (e.exec) hipGraphExecDestroy(e.exec);
+            g->pgraphs.erase(g->pgraphs.begin() + (ptrdiff_t)i);
+        } else {
+            i++;
+        }
+    }
+    for (auto &e : g->pgraphs)
+        if (e.w == w && e.cls == cls && (w || e.del == del)) return e.exec;
+    hipGraph_t graph = nullptr;
+    if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    if (w) enqueue_window_prefix2(g, m, w, cls, desc, g->cap_stream);
+    else enqueue_device_batch2(g, m, del, cls, g->cap_stream);
+    if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
+    hipGraphExec_t exec = nullptr;
+    const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (r != hipSuccess) return nullptr;
+    g->pgraphs.push_back(gpma::PairEntry{exec, w, cls, del, g->geom_version, m->geom_version});
+    return exec;
+}
+
 gpma::GraphEntry *get_graph(gpma *g, uint64_t cls, bool del, const BatchDesc *desc, uint32_t *stop,
                             bool transpose) {
     for (auto &e : g->graphs)
@@ -1181,12 +1333,23 @@ void reset_fused(gpma *g, uint32_t batch, hipStream_t s) {
 
 // Complete the stopped batch of handle g: restore its control block and run
 // the host-driven levels above the graph's, then the root.
-int complete_stopped(gpma *g, bool del, hipStream_t s, gpma_stats *st) {
+int complete_stopped(gpma *g, bool del, hipStream_t s, gpma_stats *st, bool paired = false) {
     const gpma::GraphEntry *ge = nullptr;
-    // the entry that ran is any with the batch's class/op; its final arrays
-    // depend only on H and the tier limit, identical across classes
+    // a paired window ends every batch at the leaf level with its pending
+    // updates in place (the level-0 arrays)
+    gpma::GraphEntry pe{};
+    if (paired) {
+        pe.fin_k = g->kS;
+        pe.fin_l = g->leafA;
+        pe.fin_st = g->stA;
+        pe.fin_n = &g->ctl->lvl[0];
+        pe.fin_raw = true;
+        ge = &pe;
+    }
+    // else the entry that ran is any with the batch's class/op; its final
+    // arrays depend only on H and the tier limit, identical across classes
     for (auto &e : g->graphs)
-        if (e.del == del && e.version == g->geom_version) { ge = &e; break; }
+        if (!ge && e.del == del && e.version == g->geom_version) { ge = &e; break; }
     if (!ge) return GPMA_EDEVICE;
     hipMemcpyAsync(g->ctl, &g->fs->snap, sizeof(Ctl), hipMemcpyDeviceToDevice, s);
     read_ctl(g, s);
@@ -1324,53 +1487,79 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
     auto busy = [&](int k) { return !P[k].failed && P[k].next < count; };
     while (busy(0) || (nh > 1 && busy(1))) {
         uint32_t end[2] = {0, 0};
-        if (nh > 1) {
-            hipEventRecord(g->ev_fork, s);
-            if (lib0) hipStreamWaitEvent(P[0].st, g->ev_fork, 0);
-            hipStreamWaitEvent(P[1].st, g->ev_fork, 0);
-        }
-        // a window: at most `window` batches (kWindowMax when tagged, else 1)
-        // whose keys fit the staging buffer; its prefix sorts them together
-        for (int k = 0; k < nh; k++) {
-            end[k] = P[k].next;
-            if (!busy(k)) continue;
-            gpma *h = P[k].h;
-            const uint32_t wmax = window_tag_bits(h) ? std::min<uint32_t>(window, kWindowMax) : 1;
+        // with a mirror at the same batch: one launch per step for both
+        bool paired = false;
+        if (nh > 1 && busy(0) && busy(1) && P[0].next == P[1].next) {
+            const uint32_t wmax = std::min<uint32_t>(window, kWindowMax);
             uint64_t keys_in = 0;
-            uint32_t e2 = P[k].next;
-            while (e2 < count && e2 - P[k].next < wmax && (e2 == P[k].next || keys_in + sizes[e2] <= h->bcap)) {
+            uint32_t e2 = P[0].next;
+            while (e2 < count && e2 - P[0].next < wmax && (e2 == P[0].next || keys_in + sizes[e2] <= g->bcap)) {
                 keys_in += sizes[e2];
                 e2++;
             }
-            end[k] = e2;
-            const uint32_t w = e2 - P[k].next;
-            const uint64_t wcls = std::min<uint64_t>(batch_class(keys_in), h->bcap);
-            gpma::WindowEntry *we = get_window_graph(h, w, wcls, g->desc, h->stop, P[k].transpose);
-            if (!we) return GPMA_EDEVICE;
-            if (h->fused_direct) enqueue_window_prefix(h, w, wcls, g->desc, h->stop, P[k].transpose, P[k].st);
-            else if (hipGraphLaunch(we->exec, P[k].st) != hipSuccess) return GPMA_EDEVICE;
-        }
-        // interleave the two streams' batches so both have work queued early
-        for (uint32_t j = 0; j < window; j++) {
-            for (int k = 0; k < nh; k++) {
-                const uint32_t i = P[k].next + j;
-                if (i >= end[k]) continue;
-                gpma *h = P[k].h;
-                const uint64_t cls = batch_class(sizes[i]);
-                gpma::GraphEntry *ge = get_graph(h, cls, ops[i] != 0, g->desc, h->stop, P[k].transpose);
-                if (!ge) return GPMA_EDEVICE;
-                if (h->fused_direct)
-                    enqueue_device_batch(h, ops[i] != 0, cls, g->desc, h->stop, P[k].transpose, P[k].st, ge);
-                else if (hipGraphLaunch(ge->exec, P[k].st) != hipSuccess)
-                    return GPMA_EDEVICE;
+            const uint64_t wcls = std::min<uint64_t>(batch_class(keys_in), g->bcap);
+            if (pairable_window(g, m, wcls, ops, P[0].next, e2)) {
+                hipGraphExec_t pw = get_pair_graph(g, m, e2 - P[0].next, wcls, false, g->desc);
+                if (!pw || hipGraphLaunch(pw, s) != hipSuccess) return GPMA_EDEVICE;
+                for (uint32_t i = P[0].next; i < e2; i++) {
+                    hipGraphExec_t pb = get_pair_graph(g, m, 0, batch_class(sizes[i]), ops[i] != 0, g->desc);
+                    if (!pb || hipGraphLaunch(pb, s) != hipSuccess) return GPMA_EDEVICE;
+                }
+                end[0] = end[1] = e2;
+                paired = true;
             }
         }
-        if (nh > 1) {
-            hipEventRecord(g->ev_join, P[1].st);
-            hipStreamWaitEvent(s, g->ev_join, 0);
-            if (lib0) {
-                hipEventRecord(g->ev_join2, P[0].st);
-                hipStreamWaitEvent(s, g->ev_join2, 0);
+        if (!paired) {
+            if (nh > 1) {
+                hipEventRecord(g->ev_fork, s);
+                if (lib0) hipStreamWaitEvent(P[0].st, g->ev_fork, 0);
+                hipStreamWaitEvent(P[1].st, g->ev_fork, 0);
+            }
+            // a window: at most `window` batches (kWindowMax when tagged,
+            // else 1) whose keys fit the staging buffer; its prefix sorts
+            // them together
+            for (int k = 0; k < nh; k++) {
+                end[k] = P[k].next;
+                if (!busy(k)) continue;
+                gpma *h = P[k].h;
+                const uint32_t wmax = window_tag_bits(h) ? std::min<uint32_t>(window, kWindowMax) : 1;
+                uint64_t keys_in = 0;
+                uint32_t e2 = P[k].next;
+                while (e2 < count && e2 - P[k].next < wmax &&
+                       (e2 == P[k].next || keys_in + sizes[e2] <= h->bcap)) {
+                    keys_in += sizes[e2];
+                    e2++;
+                }
+                end[k] = e2;
+                const uint32_t w = e2 - P[k].next;
+                const uint64_t wcls = std::min<uint64_t>(batch_class(keys_in), h->bcap);
+                gpma::WindowEntry *we = get_window_graph(h, w, wcls, g->desc, h->stop, P[k].transpose);
+                if (!we) return GPMA_EDEVICE;
+                if (h->fused_direct) enqueue_window_prefix(h, w, wcls, g->desc, h->stop, P[k].transpose, P[k].st);
+                else if (hipGraphLaunch(we->exec, P[k].st) != hipSuccess) return GPMA_EDEVICE;
+            }
+            // interleave the two streams' batches so both have work queued early
+            for (uint32_t j = 0; j < window; j++) {
+                for (int k = 0; k < nh; k++) {
+                    const uint32_t i = P[k].next + j;
+                    if (i >= end[k]) continue;
+                    gpma *h = P[k].h;
+                    const uint64_t cls = batch_class(sizes[i]);
+                    gpma::GraphEntry *ge = get_graph(h, cls, ops[i] != 0, g->desc, h->stop, P[k].transpose);
+                    if (!ge) return GPMA_EDEVICE;
+                    if (h->fused_direct)
+                        enqueue_device_batch(h, ops[i] != 0, cls, g->desc, h->stop, P[k].transpose, P[k].st, ge);
+                    else if (hipGraphLaunch(ge->exec, P[k].st) != hipSuccess)
+                        return GPMA_EDEVICE;
+                }
+            }
+            if (nh > 1) {
+                hipEventRecord(g->ev_join, P[1].st);
+                hipStreamWaitEvent(s, g->ev_join, 0);
+                if (lib0) {
+                    hipEventRecord(g->ev_join2, P[0].st);
+                    hipStreamWaitEvent(s, g->ev_join2, 0);
+                }
             }
         }
         // state, stop flag and results up to the window's end: one copy per handle
@@ -1391,7 +1580,7 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             }
             // stopped at batch b with updates left above the device levels
             stopped = true;
-            int e = complete_stopped(h, ops[b] != 0, s, k == 0 ? total : mtot);
+            int e = complete_stopped(h, ops[b] != 0, s, k == 0 ? total : mtot, paired);
             if (e == GPMA_EINVAL) {   // an invalid key: batches before b stand
                 P[k].failed = true;
                 P[k].next = b;

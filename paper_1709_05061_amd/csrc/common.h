@@ -222,6 +222,13 @@ size_t splitter_tmp_words(uint64_t n_max);
 const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uint32_t *n_dev, uint32_t sbits,
                                    uint32_t dbits, uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
                                    hipStream_t s);
+// two sorts of n_max-key inputs in one set of launches (the array's and its
+// mirror's window), while the bucket counts need no separate scan; returns
+// 0 when the results are in buf_a, 1 for buf_b
+bool splitter_sort_pairable(uint64_t n_max);
+int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint32_t *const n_dev[2], uint32_t sbits,
+                        uint32_t dbits, uint64_t *const buf_a[2], uint64_t *const buf_b[2], uint32_t *const tmp[2],
+                        hipStream_t s);
 
 // unique of a sorted array: out receives the distinct keys, *count_dev their
 // number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).
@@ -230,6 +237,11 @@ void unique_sorted(const uint64_t *in, uint64_t n, uint64_t *out, uint32_t *coun
 // same, reading n from a device counter (upper bound n_max on the host)
 void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max, uint64_t *out,
                        uint32_t *count_dev, uint32_t *flags, uint32_t *tmp, hipStream_t s);
+// two of them (same n_max) in one pair of launches, while n_max fits the
+// two-kernel form
+bool unique_pairable(uint64_t n_max);
+void unique_sorted_dyn2(const uint64_t *const in[2], const uint32_t *const n_dev[2], uint64_t n_max,
+                        uint64_t *const out[2], uint32_t *const count_dev[2], uint32_t *const tmp[2], hipStream_t s);
 
 // keep (key, leaf) pairs whose status is pending; n from *n_dev (<= n_max);
 // the number kept goes to *count_dev and the kept pairs get status pending.
@@ -259,6 +271,17 @@ void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uin
                        uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s, uint32_t *part = nullptr);
 // blocks of one leaf merge launch over n_max updates (4 words of `part` each)
 uint64_t leaf_merge_blocks(uint32_t lf, uint64_t n_max);
+// binary-search locate and the leaf merge for the array (index 0) and its
+// mirror (index 1) in one launch each; the locate takes each side's batch
+// from its window (ws)
+void launch_locate2(uint64_t n_max, const uint64_t *const slots[2], const uint64_t L[2], uint32_t lf,
+                    const gpma_dev::Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2],
+                    const gpma_dev::WinSrc ws[2], hipStream_t s);
+void launch_leaf_merge2(bool del, const uint64_t *const keys[2], const uint32_t *const leaf[2],
+                        uint8_t *const status[2], const uint32_t *const n_dev[2], uint64_t n_max,
+                        uint64_t *const slots[2], uint16_t *const cnt[2], uint32_t *const row_ptr[2],
+                        uint32_t *const deg[2], uint32_t *const dead[2], uint32_t lf, const uint64_t min0[2],
+                        const uint64_t max0[2], gpma_dev::Ctl *const ctl[2], uint32_t *const part[2], hipStream_t s);
 // workgroup tier at height h >= 1; needs seg_merge_lds_bytes(lf, h) <= max LDS
 size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h);
 int seg_merge_max_lds();

@@ -59,4 +59,17 @@ void launch_window_fetch(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
                           gpma_dev::FusedState *st, gpma_dev::Ctl *ctl, hipStream_t s);
 
+// The same three for the array (index 0) and its mirror (index 1, keys
+// transposed) in one launch each.
+void launch_window_fetch2(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *const st[2],
+                          const uint32_t *const stop[2], uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb,
+                          uint64_t *const staging[2], uint32_t *const wcount[2], uint32_t *const errs[2], hipStream_t s);
+void launch_window_starts2(const uint64_t *const ukeys[2], const uint32_t *const nuniq[2], uint32_t w, uint32_t sb,
+                           uint32_t *const ustart[2], gpma_dev::FusedState *const st[2], gpma_dev::Ctl *const ctl[2],
+                           hipStream_t s);
+void launch_finish_leaf2(gpma_dev::FusedState *const st[2], uint32_t *const stop[2], gpma_dev::Ctl *const ctl[2],
+                         const uint32_t *const part[2], uint64_t nparts, bool del, uint32_t lf,
+                         gpma_dev::BatchOut *const out[2], hipStream_t s);
+
 }  // namespace gpma_host
+

@@ -18,6 +18,7 @@
 // the stopped batch survives until the host completes it.
 #include "common.h"
 #include "fused.h"
+#include "pair.h"
 
 using namespace gpma_dev;
 
@@ -48,55 +49,79 @@ __global__ void k_finish(FusedState *__restrict__ st, uint32_t *__restrict__ sto
 // k_finish after a leaf merge that left per-block figures in part[4*i ..]
 // (merged, no-ops, leaves merged, pending) instead of compacting: sum them
 // into the control block (reset by the batch's locate), then finish.
+struct FinishLeafOp {
+    struct Args {
+        FusedState *st;
+        uint32_t *stop;
+        Ctl *ctl;
+        const uint4 *part;
+        uint64_t nparts;
+        int del;
+        uint32_t lf;
+        BatchOut *out;
+    };
+    static __device__ __forceinline__ void run(const Args &a) {
+        FusedState *__restrict__ st = a.st;
+        uint32_t *__restrict__ stop = a.stop;
+        Ctl *__restrict__ ctl = a.ctl;
+        const uint4 *__restrict__ part = a.part;
+        uint64_t nparts = a.nparts;
+        int del = a.del;
+        uint32_t lf = a.lf;
+        BatchOut *__restrict__ out = a.out;
+        __shared__ uint32_t red[4][1024 / kWave];
+        if (*stop) return;   // this replay ran on an empty batch (block-uniform)
+        uint32_t v[4] = {0, 0, 0, 0};
+#pragma unroll 4
+        for (uint64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+            const uint4 p = part[i];
+            v[0] += p.x;
+            v[1] += p.y;
+            v[2] += p.z;
+            v[3] += p.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+#pragma unroll
+            for (int d = kWave / 2; d >= 1; d >>= 1) v[q] += __shfl_xor(v[q], d, kWave);
+        if (__lane_id() == 0)
+#pragma unroll
+            for (int q = 0; q < 4; q++) red[q][threadIdx.x / kWave] = v[q];
+        __syncthreads();
+        if (threadIdx.x != 0) return;
+        uint32_t t[4] = {0, 0, 0, 0};
+        for (int x = 0; x < 1024 / kWave; x++)
+#pragma unroll
+            for (int q = 0; q < 4; q++) t[q] += red[q][x];
+        ctl->applied = t[0];
+        ctl->dn = del ? -(int64_t)t[0] : (int64_t)t[0];
+        ctl->noops = t[1];
+        ctl->segs = t[2];
+        ctl->rewritten = (uint64_t)t[2] * lf;
+        ctl->lvl[0] = t[3];
+        const uint32_t b = st->batch;
+        if (ctl->err || t[3]) {
+            st->snap = *ctl;
+            st->halted = 1;
+            *stop = 1;
+            return;
+        }
+        out[b].applied = t[0];
+        out[b].noops = t[1];
+        out[b].dn = ctl->dn;
+        out[b].segs = t[2];
+        out[b].rewritten = ctl->rewritten;
+        out[b].misses = ctl->misses;
+        ctl->misses = 0;
+        out[b].lookups = ctl->n_in;
+        st->batch = b + 1;
+    }
+};
+
 __global__ void __launch_bounds__(1024)
 k_finish_leaf(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__restrict__ ctl,
               const uint4 *__restrict__ part, uint64_t nparts, int del, uint32_t lf, BatchOut *__restrict__ out) {
-    __shared__ uint32_t red[4][1024 / kWave];
-    if (*stop) return;   // this replay ran on an empty batch (block-uniform)
-    uint32_t v[4] = {0, 0, 0, 0};
-#pragma unroll 4
-    for (uint64_t i = threadIdx.x; i < nparts; i += blockDim.x) {
-        const uint4 p = part[i];
-        v[0] += p.x;
-        v[1] += p.y;
-        v[2] += p.z;
-        v[3] += p.w;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; q++)
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) v[q] += __shfl_xor(v[q], d, kWave);
-    if (__lane_id() == 0)
-#pragma unroll
-        for (int q = 0; q < 4; q++) red[q][threadIdx.x / kWave] = v[q];
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    uint32_t t[4] = {0, 0, 0, 0};
-    for (int x = 0; x < 1024 / kWave; x++)
-#pragma unroll
-        for (int q = 0; q < 4; q++) t[q] += red[q][x];
-    ctl->applied = t[0];
-    ctl->dn = del ? -(int64_t)t[0] : (int64_t)t[0];
-    ctl->noops = t[1];
-    ctl->segs = t[2];
-    ctl->rewritten = (uint64_t)t[2] * lf;
-    ctl->lvl[0] = t[3];
-    const uint32_t b = st->batch;
-    if (ctl->err || t[3]) {
-        st->snap = *ctl;
-        st->halted = 1;
-        *stop = 1;
-        return;
-    }
-    out[b].applied = t[0];
-    out[b].noops = t[1];
-    out[b].dn = ctl->dn;
-    out[b].segs = t[2];
-    out[b].rewritten = ctl->rewritten;
-    out[b].misses = ctl->misses;
-    ctl->misses = 0;
-    out[b].lookups = ctl->n_in;
-    st->batch = b + 1;
+    FinishLeafOp::run(FinishLeafOp::Args{st, stop, ctl, part, nparts, del, lf, out});
 }
 
 // Window prefix.  Block-local table of the window's batch offsets (w <= 64),
@@ -104,54 +129,106 @@ k_finish_leaf(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__r
 // mirror's transposed, tagged with its batch's place in the window.  An
 // invalid key marks its batch and is stored as the tagged key (0, 0); the
 // batch is skipped as a whole later.
+struct WindowFetchOp {
+    struct Args {
+        const BatchDesc *desc;
+        FusedState *st;
+        const uint32_t *stop;
+        uint32_t w;
+        uint64_t n_max;
+        uint32_t V;
+        uint32_t sb;
+        int transpose;
+        uint64_t *staging;
+        uint32_t *wcount;
+        uint32_t *errs;
+    };
+    static __device__ __forceinline__ void run(const Args &a) {
+        const BatchDesc *__restrict__ desc = a.desc;
+        FusedState *__restrict__ st = a.st;
+        const uint32_t *__restrict__ stop = a.stop;
+        uint32_t w = a.w;
+        uint64_t n_max = a.n_max;
+        uint32_t V = a.V;
+        uint32_t sb = a.sb;
+        int transpose = a.transpose;
+        uint64_t *__restrict__ staging = a.staging;
+        uint32_t *__restrict__ wcount = a.wcount;
+        uint32_t *__restrict__ errs = a.errs;
+        __shared__ uint64_t off[kWindowMax + 1];
+        __shared__ const uint64_t *src[kWindowMax];
+        const uint32_t b0 = st->batch;
+        const uint32_t gen = st->gen;
+        if (threadIdx.x == 0) {
+            uint64_t o = 0;
+            for (uint32_t j = 0; j < w; j++) {
+                off[j] = o;
+                src[j] = desc[b0 + j].keys;
+                o += *stop ? 0 : desc[b0 + j].n;
+            }
+            off[w] = o < n_max ? o : n_max;
+        }
+        __syncthreads();
+        const uint64_t total = off[w];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            *wcount = (uint32_t)total;
+            st->wstart = b0;
+        }
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+            uint32_t j = 0;
+            while (j + 1 < w && off[j + 1] <= t) j++;
+            uint64_t k = src[j][t - off[j]];
+            if (transpose) k = (k << 32) | (k >> 32);
+            if (key_src(k) >= V || key_dst(k) >= V) {
+                errs[j] = gen;
+                k = 0;
+            }
+            staging[t] = k | ((uint64_t)j << (32 + sb));
+        }
+    }
+};
+
 __global__ void __launch_bounds__(256)
 k_window_fetch(const BatchDesc *__restrict__ desc, FusedState *__restrict__ st, const uint32_t *__restrict__ stop,
                uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, int transpose, uint64_t *__restrict__ staging,
                uint32_t *__restrict__ wcount, uint32_t *__restrict__ errs) {
-    __shared__ uint64_t off[kWindowMax + 1];
-    __shared__ const uint64_t *src[kWindowMax];
-    const uint32_t b0 = st->batch;
-    const uint32_t gen = st->gen;
-    if (threadIdx.x == 0) {
-        uint64_t o = 0;
-        for (uint32_t j = 0; j < w; j++) {
-            off[j] = o;
-            src[j] = desc[b0 + j].keys;
-            o += *stop ? 0 : desc[b0 + j].n;
-        }
-        off[w] = o < n_max ? o : n_max;
-    }
-    __syncthreads();
-    const uint64_t total = off[w];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        *wcount = (uint32_t)total;
-        st->wstart = b0;
-    }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-        uint32_t j = 0;
-        while (j + 1 < w && off[j + 1] <= t) j++;
-        uint64_t k = src[j][t - off[j]];
-        if (transpose) k = (k << 32) | (k >> 32);
-        if (key_src(k) >= V || key_dst(k) >= V) {
-            errs[j] = gen;
-            k = 0;
-        }
-        staging[t] = k | ((uint64_t)j << (32 + sb));
-    }
+    WindowFetchOp::run(WindowFetchOp::Args{desc, st, stop, w, n_max, V, sb, transpose, staging, wcount, errs});
 }
+
+struct WindowStartsOp {
+    struct Args {
+        const uint64_t *ukeys;
+        const uint32_t *nuniq;
+        uint32_t w;
+        uint32_t sb;
+        uint32_t *ustart;
+        FusedState *st;
+        Ctl *ctl;
+    };
+    static __device__ __forceinline__ void run(const Args &a) {
+        const uint64_t *__restrict__ ukeys = a.ukeys;
+        const uint32_t *__restrict__ nuniq = a.nuniq;
+        uint32_t w = a.w;
+        uint32_t sb = a.sb;
+        uint32_t *__restrict__ ustart = a.ustart;
+        FusedState *__restrict__ st = a.st;
+        Ctl *__restrict__ ctl = a.ctl;
+        const uint32_t j = threadIdx.x;
+        if (j == 0) {
+            st->gen = st->gen + 1;   // the fetch of this window is done with it
+            ctl->misses = 0;         // the window's first locate counts from zero
+        }
+        if (j > w) return;
+        const uint32_t n = *nuniq;
+        ustart[j] = j == w ? n : lower_bound_u64(ukeys, n, (uint64_t)j << (32 + sb));
+    }
+};
 
 __global__ void __launch_bounds__(256)
 k_window_starts(const uint64_t *__restrict__ ukeys, const uint32_t *__restrict__ nuniq, uint32_t w, uint32_t sb,
                 uint32_t *__restrict__ ustart, FusedState *__restrict__ st, Ctl *__restrict__ ctl) {
-    const uint32_t j = threadIdx.x;
-    if (j == 0) {
-        st->gen = st->gen + 1;   // the fetch of this window is done with it
-        ctl->misses = 0;         // the window's first locate counts from zero
-    }
-    if (j > w) return;
-    const uint32_t n = *nuniq;
-    ustart[j] = j == w ? n : lower_bound_u64(ukeys, n, (uint64_t)j << (32 + sb));
+    WindowStartsOp::run(WindowStartsOp::Args{ukeys, nuniq, w, sb, ustart, st, ctl});
 }
 
 }  // namespace
@@ -184,6 +261,32 @@ void launch_window_fetch(const BatchDesc *desc, FusedState *st, const uint32_t *
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
                           FusedState *st, Ctl *ctl, hipStream_t s) {
     hipLaunchKernelGGL(k_window_starts, dim3(1), dim3(128), 0, s, ukeys, nuniq, w, sb, ustart, st, ctl);
+}
+
+// ---- paired launches (the array at y = 0, its mirror at y = 1)
+
+void launch_window_fetch2(const BatchDesc *desc, FusedState *const st[2], const uint32_t *const stop[2], uint32_t w,
+                          uint64_t n_max, uint32_t V, uint32_t sb, uint64_t *const staging[2],
+                          uint32_t *const wcount[2], uint32_t *const errs[2], hipStream_t s) {
+    WindowFetchOp::Args a[2];
+    for (int k = 0; k < 2; k++) a[k] = {desc, st[k], stop[k], w, n_max, V, sb, k, staging[k], wcount[k], errs[k]};
+    launch_pair<WindowFetchOp, 256>(copy_blocks(n_max), a[0], a[1], s);
+}
+
+void launch_window_starts2(const uint64_t *const ukeys[2], const uint32_t *const nuniq[2], uint32_t w, uint32_t sb,
+                           uint32_t *const ustart[2], FusedState *const st[2], Ctl *const ctl[2], hipStream_t s) {
+    WindowStartsOp::Args a[2];
+    for (int k = 0; k < 2; k++) a[k] = {ukeys[k], nuniq[k], w, sb, ustart[k], st[k], ctl[k]};
+    hipLaunchKernelGGL((k_pair<WindowStartsOp, 256>), dim3(1, 2), dim3(128), 0, s, a[0], a[1]);
+}
+
+void launch_finish_leaf2(FusedState *const st[2], uint32_t *const stop[2], Ctl *const ctl[2],
+                         const uint32_t *const part[2], uint64_t nparts, bool del, uint32_t lf,
+                         BatchOut *const out[2], hipStream_t s) {
+    FinishLeafOp::Args a[2];
+    for (int k = 0; k < 2; k++)
+        a[k] = {st[k], stop[k], ctl[k], reinterpret_cast<const uint4 *>(part[k]), nparts, del ? 1 : 0, lf, out[k]};
+    launch_pair<FinishLeafOp, 1024>(1, a[0], a[1], s);
 }
 
 }  // namespace gpma_host

@@ -24,6 +24,7 @@
 // to a binary search over the whole span.
 #include "common.h"
 #include "locator.h"
+#include "pair.h"
 
 using namespace gpma_dev;
 
@@ -131,47 +132,82 @@ __device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t
 
 // Locate with the model.  The whole wave runs the MFMA inference (lanes past
 // the end use key 0), then each lane corrects its own prediction.
+struct LocateLearnedOp {
+    struct Args {
+        const uint64_t *keys;
+        const uint32_t *n_dev;
+        uint64_t n_max;
+        const uint64_t *slots;
+        const uint32_t *row_ptr;
+        uint64_t L;
+        uint32_t lf_log2;
+        const LocModel *model;
+        const Ctl *ctl;
+        uint32_t *leaf;
+        uint8_t *status;
+        uint32_t *misses;
+        WinSrc ws;
+    };
+    static __device__ __forceinline__ void run(const Args &args) {
+        const uint64_t *__restrict__ keys = args.keys;
+        const uint32_t *__restrict__ n_dev = args.n_dev;
+        uint64_t n_max = args.n_max;
+        const uint64_t *__restrict__ slots = args.slots;
+        const uint32_t *__restrict__ row_ptr = args.row_ptr;
+        uint64_t L = args.L;
+        uint32_t lf_log2 = args.lf_log2;
+        const LocModel *__restrict__ model = args.model;
+        const Ctl * ctl = args.ctl;
+        uint32_t *__restrict__ leaf = args.leaf;
+        uint8_t *__restrict__ status = args.status;
+        uint32_t * misses = args.misses;
+        WinSrc ws = args.ws;
+        __shared__ float s_out[256];
+        const LocModel m = *model;
+        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
+        const uint64_t n = bv.n;
+        if ((uint64_t)blockIdx.x * blockDim.x >= n || bv.err) return;   // block-uniform
+        const bool active = i < n;
+        const uint64_t k = active ? (bv.keys[i] & bv.mask) : 0;
+        if (active && ws.ukeys) ws.dense[i] = k;
+        const Span sp = row_span(row_ptr, key_src(k), lf_log2);
+        const uint64_t span = sp.last - sp.first + 1;
+        // the model runs (wave-wide, on MFMA) only for waves with a key in a
+        // long row; the batch is sorted, so most waves hold short rows only or
+        // long rows only
+        float t = 0.f;
+        if (__ballot(active && span > kMinSpan)) t = model_position(m, k, s_out + (threadIdx.x & ~63u));
+        if (!active) return;
+        uint64_t j;
+        if (span <= kMinSpan) {
+            j = search_range(slots, lf_log2, sp.first, sp.last, k);
+        } else {
+            const uint64_t p = predict_in_span(t, sp);
+            const uint64_t e = (uint64_t)(m.delta * (float)span) + 2;
+            const uint64_t lo = p > sp.first + e ? p - e : sp.first;
+            const uint64_t hi = p + e < sp.last ? p + e : sp.last;
+            const bool ok_lo = lo == sp.first || pivot(slots, lf_log2, lo) <= k;
+            const bool ok_hi = hi == sp.last || pivot(slots, lf_log2, hi + 1) > k;
+            if (m.valid && m.L == L && ok_lo && ok_hi) {
+                j = search_range(slots, lf_log2, lo, hi, k);
+            } else {
+                j = search_range(slots, lf_log2, sp.first, sp.last, k);
+                atomicAdd(misses, 1u);
+            }
+        }
+        leaf[i] = (uint32_t)j;
+        status[i] = kPending;
+    }
+};
+
 __global__ void __launch_bounds__(256)
 k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint64_t n_max,
                  const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L,
                  uint32_t lf_log2, const LocModel *__restrict__ model, const Ctl *ctl,
                  uint32_t *__restrict__ leaf, uint8_t *__restrict__ status, uint32_t *misses, WinSrc ws) {
-    __shared__ float s_out[256];
-    const LocModel m = *model;
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
-    const uint64_t n = bv.n;
-    if ((uint64_t)blockIdx.x * blockDim.x >= n || bv.err) return;   // block-uniform
-    const bool active = i < n;
-    const uint64_t k = active ? (bv.keys[i] & bv.mask) : 0;
-    if (active && ws.ukeys) ws.dense[i] = k;
-    const Span sp = row_span(row_ptr, key_src(k), lf_log2);
-    const uint64_t span = sp.last - sp.first + 1;
-    // the model runs (wave-wide, on MFMA) only for waves with a key in a
-    // long row; the batch is sorted, so most waves hold short rows only or
-    // long rows only
-    float t = 0.f;
-    if (__ballot(active && span > kMinSpan)) t = model_position(m, k, s_out + (threadIdx.x & ~63u));
-    if (!active) return;
-    uint64_t j;
-    if (span <= kMinSpan) {
-        j = search_range(slots, lf_log2, sp.first, sp.last, k);
-    } else {
-        const uint64_t p = predict_in_span(t, sp);
-        const uint64_t e = (uint64_t)(m.delta * (float)span) + 2;
-        const uint64_t lo = p > sp.first + e ? p - e : sp.first;
-        const uint64_t hi = p + e < sp.last ? p + e : sp.last;
-        const bool ok_lo = lo == sp.first || pivot(slots, lf_log2, lo) <= k;
-        const bool ok_hi = hi == sp.last || pivot(slots, lf_log2, hi + 1) > k;
-        if (m.valid && m.L == L && ok_lo && ok_hi) {
-            j = search_range(slots, lf_log2, lo, hi, k);
-        } else {
-            j = search_range(slots, lf_log2, sp.first, sp.last, k);
-            atomicAdd(misses, 1u);
-        }
-    }
-    leaf[i] = (uint32_t)j;
-    status[i] = kPending;
+    LocateLearnedOp::run(LocateLearnedOp::Args{keys, n_dev, n_max, slots, row_ptr, L, lf_log2, model, ctl, leaf,
+        status, misses, ws});
 }
 
 // Fit: sampled pivots, their features and the fp64 normal equations.  Each
@@ -298,4 +334,17 @@ void launch_loc_eval(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L,
     hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, slots, row_ptr, L, lf_log2, model, err);
 }
 
+void launch_locate_learned2(uint64_t n_max, const uint64_t *const slots[2], const uint32_t *const row_ptr[2],
+                            const uint64_t L[2], uint32_t lf_log2, const LocModel *const model[2],
+                            const Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2],
+                            uint32_t *const misses[2], const WinSrc ws[2], hipStream_t s) {
+    if (!n_max) return;
+    LocateLearnedOp::Args a[2];
+    for (int k = 0; k < 2; k++)
+        a[k] = {nullptr, nullptr, n_max, slots[k], row_ptr[k], L[k], lf_log2, model[k], ctl[k], leaf[k], status[k],
+                misses[k], ws[k]};
+    launch_pair<LocateLearnedOp, 256>((uint32_t)((n_max + 255) / 256), a[0], a[1], s);
+}
+
 }  // namespace gpma_host
+

@@ -21,6 +21,7 @@
 //             LDS (up to what one workgroup may allocate);
 //   above     host-driven device tier: gather -> merge -> dispatch kernels.
 #include "common.h"
+#include "pair.h"
 
 using namespace gpma_dev;
 
@@ -55,22 +56,51 @@ __global__ void k_append_guards(uint64_t *__restrict__ dst, uint32_t V) {
 // ascend strictly: a plain binary search over slots[j*lf] (a marked entry
 // orders by its masked key).
 
-__global__ void k_locate(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev,
+struct LocateOp {
+    struct Args {
+        const uint64_t *keys;
+        const uint32_t *n_dev;
+        uint64_t n_max;
+        const uint64_t *slots;
+        uint64_t L;
+        uint32_t lf_log2;
+        const Ctl *ctl;
+        uint32_t *leaf;
+        uint8_t *status;
+        WinSrc ws;
+    };
+    static __device__ __forceinline__ void run(const Args &args) {
+        const uint64_t *__restrict__ keys = args.keys;
+        const uint32_t *__restrict__ n_dev = args.n_dev;
+        uint64_t n_max = args.n_max;
+        const uint64_t *__restrict__ slots = args.slots;
+        uint64_t L = args.L;
+        uint32_t lf_log2 = args.lf_log2;
+        const Ctl * ctl = args.ctl;
+        uint32_t *__restrict__ leaf = args.leaf;
+        uint8_t *__restrict__ status = args.status;
+        WinSrc ws = args.ws;
+        uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
+        if (i >= bv.n || bv.err) return;
+        uint64_t k = bv.keys[i] & bv.mask;
+        if (ws.ukeys) ws.dense[i] = k;
+        uint64_t lo = 0, hi = L;   // count of leaves whose pivot is <= k
+        while (lo < hi) {
+            uint64_t mid = (lo + hi) >> 1;
+            if ((slots[mid << lf_log2] & ~kTomb) <= k) lo = mid + 1; else hi = mid;
+        }
+        leaf[i] = (uint32_t)(lo ? lo - 1 : 0);
+        status[i] = kPending;
+    }
+};
+
+__global__ void __launch_bounds__(256)
+k_locate(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev,
                          uint64_t n_max, const uint64_t *__restrict__ slots, uint64_t L,
                          uint32_t lf_log2, const Ctl *ctl, uint32_t *__restrict__ leaf,
                          uint8_t *__restrict__ status, WinSrc ws) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
-    if (i >= bv.n || bv.err) return;
-    uint64_t k = bv.keys[i] & bv.mask;
-    if (ws.ukeys) ws.dense[i] = k;
-    uint64_t lo = 0, hi = L;   // count of leaves whose pivot is <= k
-    while (lo < hi) {
-        uint64_t mid = (lo + hi) >> 1;
-        if ((slots[mid << lf_log2] & ~kTomb) <= k) lo = mid + 1; else hi = mid;
-    }
-    leaf[i] = (uint32_t)(lo ? lo - 1 : 0);
-    status[i] = kPending;
+    LocateOp::run(LocateOp::Args{keys, n_dev, n_max, slots, L, lf_log2, ctl, leaf, status, ws});
 }
 
 // ---------------------------------------------------------------------------
@@ -243,6 +273,71 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
 // to part[4*block .. +3] (plain stores: per-block atomics on one control
 // block serialise at the L2), for a finishing kernel to sum in place of a
 // compaction's count.
+struct LeafMergeArgs {
+    const uint64_t *keys;
+    const uint32_t *leaf;
+    uint8_t *status;
+    const uint32_t *n_dev;
+    uint64_t n_max;
+    uint64_t *slots;
+    uint16_t *cnt;
+    uint32_t *row_ptr;
+    uint32_t *deg;
+    uint32_t *dead;
+    uint32_t min0, max0;
+    Ctl *ctl;
+    uint32_t *part;
+};
+
+template <int G, int SPL, bool DEL>
+struct LeafMergeOp {
+    using Args = LeafMergeArgs;
+    static __device__ __forceinline__ void run(const Args &args) {
+        const uint64_t *__restrict__ keys = args.keys;
+        const uint32_t *__restrict__ leaf = args.leaf;
+        uint8_t *__restrict__ status = args.status;
+        const uint32_t *__restrict__ n_dev = args.n_dev;
+        const uint64_t n_max = args.n_max;
+        uint64_t *__restrict__ slots = args.slots;
+        uint16_t *__restrict__ cnt = args.cnt;
+        uint32_t *__restrict__ row_ptr = args.row_ptr;
+        uint32_t *__restrict__ deg = args.deg;
+        uint32_t *__restrict__ dead = args.dead;
+        const uint32_t min0 = args.min0, max0 = args.max0;
+        Ctl *__restrict__ ctl = args.ctl;
+        uint32_t *__restrict__ part = args.part;
+        constexpr int LF = G * SPL;
+        constexpr int GPB = 256 / G;   // groups per block
+        __shared__ uint64_t s_leaf[GPB][LF];
+        __shared__ uint64_t s_upd[GPB][LF];
+        __shared__ uint64_t s_out[GPB][LF];
+        __shared__ uint32_t s_red[4][256 / kWave];
+        const uint32_t gib = threadIdx.x / G;
+        RunStats rs = leaf_merge_group<G, SPL, DEL>(keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead,
+                                                    min0, max0, ctl, s_leaf[gib], s_upd[gib], s_out[gib]);
+        if (!part) return;   // grid-uniform
+        // every lane of a group holds the group's figures: count lane 0's
+        uint32_t v[4] = {rs.done, rs.noop, rs.head, rs.pend};
+        const bool lead = (threadIdx.x & (G - 1)) == 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            v[q] = lead ? v[q] : 0u;
+#pragma unroll
+            for (int d = kWave / 2; d >= 1; d >>= 1) v[q] += __shfl_xor(v[q], d, kWave);
+        }
+        const uint32_t w = threadIdx.x / kWave;
+        if (__lane_id() == 0)
+#pragma unroll
+            for (int q = 0; q < 4; q++) s_red[q][w] = v[q];
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            uint32_t t = 0;
+            for (int x = 0; x < 256 / kWave; x++) t += s_red[threadIdx.x][x];
+            part[4 * (uint64_t)blockIdx.x + threadIdx.x] = t;
+        }
+    }
+};
+
 template <int G, int SPL, bool DEL>
 __global__ void __launch_bounds__(256)
 k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
@@ -250,35 +345,8 @@ k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ lea
              uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
              uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
              uint32_t min0, uint32_t max0, Ctl *__restrict__ ctl, uint32_t *__restrict__ part) {
-    constexpr int LF = G * SPL;
-    constexpr int GPB = 256 / G;   // groups per block
-    __shared__ uint64_t s_leaf[GPB][LF];
-    __shared__ uint64_t s_upd[GPB][LF];
-    __shared__ uint64_t s_out[GPB][LF];
-    __shared__ uint32_t s_red[4][256 / kWave];
-    const uint32_t gib = threadIdx.x / G;
-    RunStats rs = leaf_merge_group<G, SPL, DEL>(keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead,
-                                                min0, max0, ctl, s_leaf[gib], s_upd[gib], s_out[gib]);
-    if (!part) return;   // grid-uniform
-    // every lane of a group holds the group's figures: count lane 0's
-    uint32_t v[4] = {rs.done, rs.noop, rs.head, rs.pend};
-    const bool lead = (threadIdx.x & (G - 1)) == 0;
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        v[q] = lead ? v[q] : 0u;
-#pragma unroll
-        for (int d = kWave / 2; d >= 1; d >>= 1) v[q] += __shfl_xor(v[q], d, kWave);
-    }
-    const uint32_t w = threadIdx.x / kWave;
-    if (__lane_id() == 0)
-#pragma unroll
-        for (int q = 0; q < 4; q++) s_red[q][w] = v[q];
-    __syncthreads();
-    if (threadIdx.x < 4) {
-        uint32_t t = 0;
-        for (int x = 0; x < 256 / kWave; x++) t += s_red[threadIdx.x][x];
-        part[4 * (uint64_t)blockIdx.x + threadIdx.x] = t;
-    }
+    LeafMergeOp<G, SPL, DEL>::run(
+        LeafMergeArgs{keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl, part});
 }
 
 // ---------------------------------------------------------------------------
@@ -671,6 +739,46 @@ void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uin
         case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
         case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
         default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+    }
+}
+
+// ---- paired launches (the array at y = 0, its mirror at y = 1)
+
+void launch_locate2(uint64_t n_max, const uint64_t *const slots[2], const uint64_t L[2], uint32_t lf,
+                    const Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2], const WinSrc ws[2],
+                    hipStream_t s) {
+    if (!n_max) return;
+    LocateOp::Args a[2];
+    for (int k = 0; k < 2; k++)
+        a[k] = {nullptr, nullptr, n_max, slots[k], L[k], log2_u32(lf), ctl[k], leaf[k], status[k], ws[k]};
+    launch_pair<LocateOp, 256>((uint32_t)div_up(n_max, 256), a[0], a[1], s);
+}
+
+template <int G, int SPL>
+static void leaf_merge2_t(bool del, const LeafMergeArgs (&a)[2], hipStream_t s) {
+    constexpr int GPB = 256 / G;
+    const uint32_t gx = (uint32_t)div_up(a[0].n_max, GPB);
+    if (del) launch_pair<LeafMergeOp<G, SPL, true>, 256>(gx, a[0], a[1], s);
+    else launch_pair<LeafMergeOp<G, SPL, false>, 256>(gx, a[0], a[1], s);
+}
+
+void launch_leaf_merge2(bool del, const uint64_t *const keys[2], const uint32_t *const leaf[2],
+                        uint8_t *const status[2], const uint32_t *const n_dev[2], uint64_t n_max,
+                        uint64_t *const slots[2], uint16_t *const cnt[2], uint32_t *const row_ptr[2],
+                        uint32_t *const deg[2], uint32_t *const dead[2], uint32_t lf, const uint64_t min0[2],
+                        const uint64_t max0[2], Ctl *const ctl[2], uint32_t *const part[2], hipStream_t s) {
+    if (!n_max) return;
+    LeafMergeArgs a[2];
+    for (int k = 0; k < 2; k++)
+        a[k] = {keys[k], leaf[k], status[k], n_dev[k], n_max, slots[k], cnt[k], row_ptr[k], deg[k], dead[k],
+                (uint32_t)min0[k], (uint32_t)max0[k], ctl[k], part[k]};
+    switch (lf) {
+        case 16: leaf_merge2_t<8, 2>(del, a, s); break;
+        case 32: leaf_merge2_t<16, 2>(del, a, s); break;
+        case 64: leaf_merge2_t<32, 2>(del, a, s); break;
+        case 128: leaf_merge2_t<64, 2>(del, a, s); break;
+        case 256: leaf_merge2_t<64, 4>(del, a, s); break;
+        default: leaf_merge2_t<64, 8>(del, a, s); break;
     }
 }
 

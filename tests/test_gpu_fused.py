@@ -296,3 +296,37 @@ def test_window_sorts_agree_with_the_oracle(kind, window_sort):
             assert torch.equal(g.mirror().keys(), torch.sort(tr)[0])
     assert g.num_edges + V == ref.size   # the oracle counts the V guards
     g.close()
+
+
+@pytest.mark.parametrize("learned,lazy", [(False, False), (True, False), (False, True)])
+def test_paired_windows_equal_plain(learned, lazy):
+    """With a mirror and no device level above the leaves, both sides of a
+    window run each step in one launch (paired windows).  Uneven sequences
+    with batches that climb above the leaves, a resize, repeats and absent
+    deletes give the plain path's and the oracle's slots, array and mirror;
+    the sides stop at different batches and pair again afterwards."""
+    from paper_1709_05061_amd import GPMA
+    V, lf = 512, 16
+    init = np.unique(npu64(synth.random_batch(V, 6000, 13)))
+    ops, bs = make_sequence(V, init, 40, seed=15)
+    kw = dict(leaf_size=lf, mirror=True, learned=learned, lazy_delete=lazy)
+    plain = GPMA(V, dev(init), **kw)
+    fused = GPMA(V, dev(init), fused_levels=0, **kw)
+    cuts = [0, 4, 5, 19, 40]
+    for c in range(len(cuts) - 1):
+        lo, hi = cuts[c], cuts[c + 1]
+        say("paired call", lo, hi, "learned", learned, "lazy", lazy)
+        for i in range(lo, hi):
+            (plain.delete if ops[i] else plain.insert)(dev(bs[i]))
+        st = fused.apply_batches(ops[lo:hi], [dev(b) for b in bs[lo:hi]])
+        assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
+        assert np.array_equal(npu64(fused.mirror().slots()), npu64(plain.mirror().slots())), (lo, hi)
+        assert fused.num_edges == plain.num_edges
+        assert np.array_equal(fused.degrees().cpu().numpy(), plain.degrees().cpu().numpy())
+    if not lazy:
+        ref = O.OraclePMA(V, init, lf)
+        for o, b in zip(ops, bs):
+            (ref.delete if o else ref.insert)(b)
+        assert np.array_equal(npu64(fused.slots()), ref.slots())
+    plain.close()
+    fused.close()
