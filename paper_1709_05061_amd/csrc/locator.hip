@@ -119,7 +119,9 @@ __device__ __forceinline__ uint64_t pivot(const uint64_t *slots, uint32_t lf_log
     return slots[j << lf_log2] & ~kTomb;
 }
 
-// the largest leaf j in [lo, hi] with pivot(j) <= k (lo if none)
+// the largest leaf j in [lo, hi] with pivot(j) <= k (lo if none).  (An
+// 8-way search, seven pivots loaded per step, measured slower: 71 against
+// 43 us for a paired locate of 2^16 keys at scale 24.)
 __device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t lf_log2, uint64_t lo,
                                                  uint64_t hi, uint64_t k) {
     uint64_t a = lo, b = hi + 1;   // pivots in [a, b) : count of those <= k

@@ -167,6 +167,9 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
     const uint32_t n = *n_dev;
     if (gi >= n || ctl->err) return rs;
     const uint32_t i = (uint32_t)gi;
+    // the lane's first update of the run, loaded beside the leaf ids (its
+    // address does not wait for them)
+    const uint64_t kpre = i + gl < n ? keys[i + gl] : 0;
     const uint32_t lf_i = leaf[i];
     if (i > 0 && leaf[i - 1] == lf_i) return rs;   // not the head of its run
     const uint32_t e = run_end(leaf, i, n, lf_i, 0);
@@ -199,12 +202,14 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
 
     // classify the run: applicable updates are compacted (in key order) into ub
     uint32_t kapp = 0;
+    bool app0 = false;   // the lane's first update is applicable
     for (uint32_t r0 = 0; r0 < k; r0 += G) {
         const uint32_t t = r0 + gl;
         const bool valid = t < k;
-        const uint64_t key = valid ? keys[i + t] : 0;
+        const uint64_t key = valid ? (r0 == 0 ? kpre : keys[i + t]) : 0;
         const bool present = valid && contains_u64(lb, c, key);
         const bool app = valid && (DEL ? present : !present);
+        if (r0 == 0) app0 = app;
         const uint32_t pos = kapp + group_excl_scan<G>(app ? 1u : 0u, gl);
         if (app && pos < LF) ub[pos] = key;
         if (valid) status[i + t] = app ? kPending : kNoop;
@@ -255,12 +260,14 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
         cnt[lf_i] = (uint16_t)N;
         if (dead) dead[lf_i] = 0;
     }
-    // statuses of the run were written by the same lanes in the classify loop
+    // statuses of the run were written by the same lanes in the classify
+    // loop; the lane's first update is still in registers
     for (uint32_t t = gl; t < k; t += G) {
-        uint8_t st = status[i + t];
+        const bool first = t < (uint32_t)G;
+        uint8_t st = first ? (app0 ? kPending : kNoop) : status[i + t];
         if (st == kPending) {
             st = kDone;
-            atomicAdd(&deg[key_src(keys[i + t])], DEL ? 0xFFFFFFFFu : 1u);
+            atomicAdd(&deg[key_src(first ? kpre : keys[i + t])], DEL ? 0xFFFFFFFFu : 1u);
         }
         status[i + t] = t == 0 ? (uint8_t)(st | kHead) : st;
     }
