@@ -138,9 +138,9 @@ struct gpma {
     uint64_t *kS = nullptr;              // window staging, then the current batch's keys
     FusedState *fs = nullptr;            // device
     uint32_t *werrs = nullptr;           // device: per window batch, generation of its invalid key
-    uint32_t *wcount = nullptr;          // device: window keys, window unique keys
-    uint32_t *ustart = nullptr;          // device: window batch starts in the unique keys
-    uint64_t *wukeys = nullptr;          // which sort buffer holds the window's unique keys
+    uint32_t *wcount = nullptr;          // device: window keys
+    uint32_t *ustart = nullptr;          // device: window batch starts in the sorted keys
+    uint64_t *wukeys = nullptr;          // which sort buffer holds the window's sorted keys
     struct WindowEntry {
         hipGraphExec_t exec;
         uint32_t w;
@@ -1034,8 +1034,10 @@ uint32_t window_tag_bits(const gpma *g) {
 }
 
 // Enqueue the prefix of a window of w batches from the handle's current batch
-// (at most n_max keys in all): fetch, validate and tag, one radix sort of the
-// whole window (batch tag above the source bits), unique, batch starts.
+// (at most n_max keys in all): fetch, validate and tag, one sort of the whole
+// window (batch tag above the source bits), batch starts.  Repeats stay in
+// the sorted keys, next to each other: the leaf merge and the mark kernel
+// treat a key equal to the one before it as a no-op.
 void enqueue_window_prefix(gpma *g, uint32_t w, uint64_t n_max, const BatchDesc *desc, const uint32_t *stop,
                            bool transpose, hipStream_t s) {
     const uint32_t sb = bit_width(g->V - 1);
@@ -1047,10 +1049,8 @@ void enqueue_window_prefix(gpma *g, uint32_t w, uint64_t n_max, const BatchDesc 
             ? splitter_sort_keys(g->kS, n_max, g->wcount, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s)
             : radix_sort_keys(g->kS, n_max, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s, g->wcount, nullptr,
                               g->sort_chunks);
-    uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
-    unique_sorted_dyn(sorted, g->wcount, n_max, ukeys, g->wcount + 1, g->flags, g->tmp, s);
-    launch_window_starts(ukeys, g->wcount + 1, w, sb, g->ustart, g->fs, g->ctl, s);
-    g->wukeys = ukeys;   // the same buffer for every window of this handle (fixed pass count)
+    launch_window_starts(sorted, g->wcount, w, sb, g->ustart, g->fs, g->ctl, s);
+    g->wukeys = const_cast<uint64_t *>(sorted);   // the same buffer for every window (fixed pass count)
 }
 
 gpma::WindowEntry *get_window_graph(gpma *g, uint32_t w, uint64_t cls, const BatchDesc *desc, const uint32_t *stop,
@@ -1078,7 +1078,7 @@ gpma::WindowEntry *get_window_graph(gpma *g, uint32_t w, uint64_t cls, const Bat
 
 // Enqueue one batch of a fused sequence with device-side control only (no
 // host reads), for batches of at most `cls` keys: take the batch's keys from
-// its window's sorted unique keys, locate, level 0, then levels 1..h_top of
+// its window's sorted keys, locate, level 0, then levels 1..h_top of
 // the workgroup tier, then finish.  Returns where the pending updates end up.
 void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc, uint32_t *stop,
                           bool transpose, hipStream_t s, gpma::GraphEntry *ge) {
@@ -1158,15 +1158,15 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
 // ---- paired windows: the array g and its mirror m run every step of a
 // window in one launch (the grid's y index picks the side), so a window takes
 // half the launches.  Used when both sides take the same kernels: the
-// splitter sort without a count scan, the two-kernel unique, the leaf level
-// as the last device level, no lazy-deletion marks, the same locate.
+// splitter sort without a count scan, the leaf level as the last device
+// level, no lazy-deletion marks, the same locate.
 
 bool pairable_window(const gpma *g, const gpma *m, uint64_t wcls, const uint8_t *ops, uint32_t from, uint32_t to) {
     for (const gpma *h : {g, m})
         if (h->fused_direct || h->window_radix || h->lib_streams || !window_tag_bits(h) || h->bcap != g->bcap)
             return false;
     if (g->lf != m->lf || g->V != m->V || (g->learned && g->loc) != (m->learned && m->loc)) return false;
-    if (!splitter_sort_pairable(wcls) || !unique_pairable(wcls)) return false;
+    if (!splitter_sort_pairable(wcls)) return false;
     for (const gpma *h : {g, m}) {
         const bool upper = h->fused_levels >= 1 && h->H > 1 && seg_merge_lds_bytes(h->lf, 1) <= (size_t)h->dev.max_lds;
         if (upper) return false;
@@ -1192,24 +1192,16 @@ void enqueue_window_prefix2(gpma *g, gpma *m, uint32_t w, uint64_t n_max, const 
     uint32_t *tmp[2] = {g->tmp, m->tmp};
     const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s);
     const uint64_t *sorted[2];
-    uint64_t *ukeys[2];
-    uint32_t *nuniq[2];
-    const uint64_t *uk_c[2];
-    const uint32_t *nu_c[2];
     uint32_t *ustart[2];
     Ctl *ctl[2];
     for (int k = 0; k < 2; k++) {
-        sorted[k] = which ? h[k]->kB : h[k]->kA;
-        ukeys[k] = which ? h[k]->kA : h[k]->kB;
-        nuniq[k] = h[k]->wcount + 1;
-        uk_c[k] = ukeys[k];
-        nu_c[k] = nuniq[k];
+        uint64_t *out = which ? h[k]->kB : h[k]->kA;
+        sorted[k] = out;
         ustart[k] = h[k]->ustart;
         ctl[k] = h[k]->ctl;
-        h[k]->wukeys = ukeys[k];
+        h[k]->wukeys = out;
     }
-    unique_sorted_dyn2(sorted, nd, n_max, ukeys, nuniq, tmp, s);
-    launch_window_starts2(uk_c, nu_c, w, sb, ustart, st, ctl, s);
+    launch_window_starts2(sorted, nd, w, sb, ustart, st, ctl, s);
 }
 
 void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t s) {

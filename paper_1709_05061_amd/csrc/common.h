@@ -237,11 +237,7 @@ void unique_sorted(const uint64_t *in, uint64_t n, uint64_t *out, uint32_t *coun
 // same, reading n from a device counter (upper bound n_max on the host)
 void unique_sorted_dyn(const uint64_t *in, const uint32_t *n_dev, uint64_t n_max, uint64_t *out,
                        uint32_t *count_dev, uint32_t *flags, uint32_t *tmp, hipStream_t s);
-// two of them (same n_max) in one pair of launches, while n_max fits the
-// two-kernel form
-bool unique_pairable(uint64_t n_max);
-void unique_sorted_dyn2(const uint64_t *const in[2], const uint32_t *const n_dev[2], uint64_t n_max,
-                        uint64_t *const out[2], uint32_t *const count_dev[2], uint32_t *const tmp[2], hipStream_t s);
+
 
 // keep (key, leaf) pairs whose status is pending; n from *n_dev (<= n_max);
 // the number kept goes to *count_dev and the kept pairs get status pending.

@@ -33,7 +33,7 @@ struct BatchOut {
     uint64_t rewritten;
     uint32_t segs;
     uint32_t misses;    // learned-locator fallbacks
-    uint32_t lookups;   // distinct keys located
+    uint32_t lookups;   // keys located (repeats included)
     uint32_t pad;
 };
 
@@ -54,7 +54,7 @@ void launch_finish_leaf(gpma_dev::FusedState *st, uint32_t *stop, gpma_dev::Ctl 
 void launch_window_fetch(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *st, const uint32_t *stop,
                          uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, bool transpose, uint64_t *staging,
                          uint32_t *wcount, uint32_t *errs, hipStream_t s);
-// first position of each batch's keys in the window's sorted unique keys;
+// first position of each batch's keys in the window's sorted keys;
 // advances st->gen and zeroes ctl->misses
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
                           gpma_dev::FusedState *st, gpma_dev::Ctl *ctl, hipStream_t s);

@@ -2,20 +2,21 @@
 // host synchronisation between batches.
 //
 // Batches go in windows.  A window's prefix (k_window_fetch, one sort --
-// the splitter sort up to 2^20 keys, else the radix sort -- unique,
+// the splitter sort up to 2^20 keys, else the radix sort -- and
 // k_window_starts) sorts all its batches at once: each key carries its
 // batch's place in the window above the source bits, so one sort groups the
-// keys by batch and orders them within.  Then, per batch, the locate kernel
-// takes the batch's keys from the window's unique keys (or nothing when the
-// sequence is stopped), the state-dependent steps run (locate, merges,
-// compactions; with no level above the leaves on the device, the leaf merge
-// counts the batch's statistics and what is left itself), and k_finish either
-// records the batch's statistics and advances to the next batch, or stops the
-// sequence when the batch still has updates pending above the levels run on
-// the device (those need the host-driven tiers: segments larger than LDS, or
-// the root).  Batches that
-// follow a stop see an empty batch and change nothing, so the pending state of
-// the stopped batch survives until the host completes it.
+// keys by batch and orders them within; repeats stay, next to each other,
+// and the leaf level takes a key equal to the one before it as a no-op.
+// Then, per batch, the locate kernel takes the batch's keys from the window's
+// sorted keys (or nothing when the sequence is stopped), the state-dependent
+// steps run (locate, merges, compactions; with no level above the leaves on
+// the device, the leaf merge counts the batch's statistics and what is left
+// itself), and k_finish either records the batch's statistics and advances to
+// the next batch, or stops the sequence when the batch still has updates
+// pending above the levels run on the device (those need the host-driven
+// tiers: segments larger than LDS, or the root).  Batches that follow a stop
+// see an empty batch and change nothing, so the pending state of the stopped
+// batch survives until the host completes it.
 #include "common.h"
 #include "fused.h"
 #include "pair.h"

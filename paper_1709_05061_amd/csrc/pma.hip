@@ -207,8 +207,13 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
         const uint32_t t = r0 + gl;
         const bool valid = t < k;
         const uint64_t key = valid ? (r0 == 0 ? kpre : keys[i + t]) : 0;
-        const bool present = valid && contains_u64(lb, c, key);
-        const bool app = valid && (DEL ? present : !present);
+        // a key equal to the one before it (keys are sorted; a run head's
+        // predecessor lies in another leaf) is a repeat, a no-op
+        const uint64_t prev = r0 == 0 ? (uint64_t)__shfl_up((unsigned long long)kpre, 1, G)
+                                      : (valid ? keys[i + t - 1] : 0);
+        const bool rep = valid && t > 0 && prev == key;
+        const bool present = valid && !rep && contains_u64(lb, c, key);
+        const bool app = valid && !rep && (DEL ? present : !present);
         if (r0 == 0) app0 = app;
         const uint32_t pos = kapp + group_excl_scan<G>(app ? 1u : 0u, gl);
         if (app && pos < LF) ub[pos] = key;
@@ -632,6 +637,10 @@ __global__ void k_leaf_mark(const uint64_t *__restrict__ keys, const uint32_t *_
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_max || i >= *n_dev || ctl->err) return;
     const uint64_t k = keys[i];
+    if (i > 0 && keys[i - 1] == k) {   // a repeat (sorted keys): its first copy marks
+        status[i] = kNoop;
+        return;
+    }
     const uint32_t j = leaf[i];
     const uint64_t base = (uint64_t)j << lf_log2;
     uint32_t lo = 0, hi = cnt[j];   // occupied prefix: first masked key >= k

@@ -3,7 +3,6 @@
 // The paper builds its update from such primitives (Section 5.2: sort,
 // run-length encoding, exclusive scan); these are our own.
 #include "common.h"
-#include "pair.h"
 
 using namespace gpma_dev;
 
@@ -366,75 +365,37 @@ __device__ __forceinline__ bool unique_head(const uint64_t *a, uint64_t i, uint6
     return i < lim && (i == 0 || a[i] != a[i - 1]);
 }
 
-struct UniqueCountOp {
-    struct Args {
-        const uint64_t *a;
-        uint64_t n_max;
-        const uint32_t *n_dev;
-        uint32_t *tile_cnt;
-    };
-    static __device__ __forceinline__ void run(const Args &args) {
-        const uint64_t *__restrict__ a = args.a;
-        uint64_t n_max = args.n_max;
-        const uint32_t *__restrict__ n_dev = args.n_dev;
-        uint32_t *__restrict__ tile_cnt = args.tile_cnt;
-        __shared__ uint32_t lds[1][256 / kWave];
-        const uint64_t lim = dyn_limit(n_dev, n_max);
-        const uint64_t base = (uint64_t)blockIdx.x * kCmpTile;
-        uint32_t v[1] = {0};
-#pragma unroll
-        for (int q = 0; q < kCmpItems; q++) v[0] += unique_head(a, base + q * 256 + threadIdx.x, lim) ? 1u : 0u;
-        block_sum_n<1>(v, lds);
-        if (threadIdx.x == 0) tile_cnt[blockIdx.x] = v[0];
-    }
-};
-
 __global__ void __launch_bounds__(256)
 k_unique_count(const uint64_t *__restrict__ a, uint64_t n_max, const uint32_t *__restrict__ n_dev,
                uint32_t *__restrict__ tile_cnt) {
-    UniqueCountOp::run(UniqueCountOp::Args{a, n_max, n_dev, tile_cnt});
+    __shared__ uint32_t lds[1][256 / kWave];
+    const uint64_t lim = dyn_limit(n_dev, n_max);
+    const uint64_t base = (uint64_t)blockIdx.x * kCmpTile;
+    uint32_t v[1] = {0};
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++) v[0] += unique_head(a, base + q * 256 + threadIdx.x, lim) ? 1u : 0u;
+    block_sum_n<1>(v, lds);
+    if (threadIdx.x == 0) tile_cnt[blockIdx.x] = v[0];
 }
-
-struct UniqueScatterOp {
-    struct Args {
-        const uint64_t *a;
-        uint64_t n_max;
-        const uint32_t *n_dev;
-        const uint32_t *tile_cnt;
-        uint32_t ntiles;
-        uint64_t *out;
-        uint32_t *count_dev;
-    };
-    static __device__ __forceinline__ void run(const Args &args) {
-        const uint64_t *__restrict__ a = args.a;
-        uint64_t n_max = args.n_max;
-        const uint32_t *__restrict__ n_dev = args.n_dev;
-        const uint32_t *__restrict__ tile_cnt = args.tile_cnt;
-        uint32_t ntiles = args.ntiles;
-        uint64_t *__restrict__ out = args.out;
-        uint32_t *__restrict__ count_dev = args.count_dev;
-        __shared__ uint32_t lds[256 / kWave + 1];
-        uint32_t before, total;
-        tile_prefix(tile_cnt, ntiles, blockIdx.x, &before, &total);
-        if (blockIdx.x == 0 && threadIdx.x == 0) *count_dev = total;
-        const uint64_t lim = dyn_limit(n_dev, n_max);
-        const uint64_t base = (uint64_t)blockIdx.x * kCmpTile + (uint64_t)threadIdx.x * kCmpItems;
-        uint32_t f = 0;
-#pragma unroll
-        for (int q = 0; q < kCmpItems; q++) f |= (unique_head(a, base + q, lim) ? 1u : 0u) << q;
-        uint32_t tot;
-        uint32_t pos = before + block_exclusive_scan(__popc(f), &tot, lds);
-#pragma unroll
-        for (int q = 0; q < kCmpItems; q++)
-            if (f & (1u << q)) out[pos++] = a[base + q];
-    }
-};
 
 __global__ void __launch_bounds__(256)
 k_unique_scatter(const uint64_t *__restrict__ a, uint64_t n_max, const uint32_t *__restrict__ n_dev,
                  const uint32_t *__restrict__ tile_cnt, uint32_t ntiles, uint64_t *__restrict__ out,
                  uint32_t *__restrict__ count_dev) {
-    UniqueScatterOp::run(UniqueScatterOp::Args{a, n_max, n_dev, tile_cnt, ntiles, out, count_dev});
+    __shared__ uint32_t lds[256 / kWave + 1];
+    uint32_t before, total;
+    tile_prefix(tile_cnt, ntiles, blockIdx.x, &before, &total);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *count_dev = total;
+    const uint64_t lim = dyn_limit(n_dev, n_max);
+    const uint64_t base = (uint64_t)blockIdx.x * kCmpTile + (uint64_t)threadIdx.x * kCmpItems;
+    uint32_t f = 0;
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++) f |= (unique_head(a, base + q, lim) ? 1u : 0u) << q;
+    uint32_t tot;
+    uint32_t pos = before + block_exclusive_scan(__popc(f), &tot, lds);
+#pragma unroll
+    for (int q = 0; q < kCmpItems; q++)
+        if (f & (1u << q)) out[pos++] = a[base + q];
 }
 
 // pending updates per tile, plus the level's statistics per tile:
@@ -673,20 +634,4 @@ void compact_edges(const uint64_t *slots, uint64_t cap, uint64_t *out, uint32_t 
     hipLaunchKernelGGL(k_scatter_edges, dim3(g), dim3(256), 0, s, slots, cap, flags, out);
 }
 
-bool unique_pairable(uint64_t n_max) { return n_max > 0 && div_up(n_max, kCmpTile) <= kCmpMaxTiles; }
-
-void unique_sorted_dyn2(const uint64_t *const in[2], const uint32_t *const n_dev[2], uint64_t n_max,
-                        uint64_t *const out[2], uint32_t *const count_dev[2], uint32_t *const tmp[2], hipStream_t s) {
-    const uint64_t ntiles = div_up(n_max, kCmpTile);
-    UniqueCountOp::Args ca[2];
-    UniqueScatterOp::Args sa[2];
-    for (int k = 0; k < 2; k++) {
-        ca[k] = {in[k], n_max, n_dev[k], tmp[k]};
-        sa[k] = {in[k], n_max, n_dev[k], tmp[k], (uint32_t)ntiles, out[k], count_dev[k]};
-    }
-    launch_pair<UniqueCountOp, 256>((uint32_t)ntiles, ca[0], ca[1], s);
-    launch_pair<UniqueScatterOp, 256>((uint32_t)ntiles, sa[0], sa[1], s);
-}
-
 }  // namespace gpma_host
-
