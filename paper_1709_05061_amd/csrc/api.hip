@@ -110,15 +110,15 @@ struct gpma {
         bool fin_raw;   // the leaf level was the last: pending updates left in place, uncompacted
     };
     std::vector<GraphEntry> graphs;
-    // paired windows (this handle with its mirror, one launch per step):
-    // graphs of window prefixes and of batches, valid while both handles'
-    // geom_version are unchanged
+    // paired windows (this handle with its mirror, one launch per step): one
+    // graph per window shape (the window's size class, then each batch's
+    // size class and operation), valid while both handles' geom_version are
+    // unchanged
     struct PairEntry {
         hipGraphExec_t exec;
-        uint32_t w;       // window prefix: batches in the window (0 for a batch graph)
-        uint64_t cls;
-        bool del;
-        uint32_t vg, vm;  // geom_version of this handle and of its mirror
+        uint64_t wcls;
+        std::vector<uint64_t> sig;   // per batch: size class * 2 + delete
+        uint32_t vg, vm;             // geom_version of this handle and of its mirror
     };
     std::vector<PairEntry> pgraphs;
     uint32_t geom_version = 1;
@@ -1258,8 +1258,13 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
     launch_finish_leaf2(st, stop, ctl, part_c, leaf_merge_blocks(g->lf, cls), del, g->lf, outs, s);
 }
 
-// The cached graph of a paired window prefix (w > 0) or batch (w == 0).
-hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint32_t w, uint64_t cls, bool del, const BatchDesc *desc) {
+constexpr size_t kPairGraphs = 32;   // window shapes kept per handle
+
+// The cached graph of a whole paired window: its prefix, then every batch.
+hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint64_t wcls, const uint8_t *ops, const uint64_t *sizes,
+                              uint32_t from, uint32_t to, const BatchDesc *desc) {
+    std::vector<uint64_t> sig;
+    for (uint32_t i = from; i < to; i++) sig.push_back(batch_class(sizes[i]) * 2 + (ops[i] ? 1 : 0));
     // entries of an older geometry of either side go first
     for (size_t i = 0; i < g->pgraphs.size();) {
         auto &e = g->pgraphs[i];
@@ -1271,17 +1276,22 @@ hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint32_t w, uint64_t cls, bool d
         }
     }
     for (auto &e : g->pgraphs)
-        if (e.w == w && e.cls == cls && (w || e.del == del)) return e.exec;
+        if (e.wcls == wcls && e.sig == sig) return e.exec;
+    if (g->pgraphs.size() >= kPairGraphs) {   // the oldest shape makes room
+        if (g->pgraphs.front().exec) hipGraphExecDestroy(g->pgraphs.front().exec);
+        g->pgraphs.erase(g->pgraphs.begin());
+    }
     hipGraph_t graph = nullptr;
     if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
-    if (w) enqueue_window_prefix2(g, m, w, cls, desc, g->cap_stream);
-    else enqueue_device_batch2(g, m, del, cls, g->cap_stream);
+    enqueue_window_prefix2(g, m, to - from, wcls, desc, g->cap_stream);
+    for (uint32_t i = from; i < to; i++)
+        enqueue_device_batch2(g, m, ops[i] != 0, batch_class(sizes[i]), g->cap_stream);
     if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
     hipGraphExec_t exec = nullptr;
     const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (r != hipSuccess) return nullptr;
-    g->pgraphs.push_back(gpma::PairEntry{exec, w, cls, del, g->geom_version, m->geom_version});
+    g->pgraphs.push_back(gpma::PairEntry{exec, wcls, sig, g->geom_version, m->geom_version});
     return exec;
 }
 
@@ -1491,12 +1501,8 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             }
             const uint64_t wcls = std::min<uint64_t>(batch_class(keys_in), g->bcap);
             if (pairable_window(g, m, wcls, ops, P[0].next, e2)) {
-                hipGraphExec_t pw = get_pair_graph(g, m, e2 - P[0].next, wcls, false, g->desc);
+                hipGraphExec_t pw = get_pair_graph(g, m, wcls, ops, sizes, P[0].next, e2, g->desc);
                 if (!pw || hipGraphLaunch(pw, s) != hipSuccess) return GPMA_EDEVICE;
-                for (uint32_t i = P[0].next; i < e2; i++) {
-                    hipGraphExec_t pb = get_pair_graph(g, m, 0, batch_class(sizes[i]), ops[i] != 0, g->desc);
-                    if (!pb || hipGraphLaunch(pb, s) != hipSuccess) return GPMA_EDEVICE;
-                }
                 end[0] = end[1] = e2;
                 paired = true;
             }
