@@ -360,6 +360,12 @@ int gpma_export_keys(gpma_t *h, uint64_t *out_dev, uint64_t max, uint64_t *n_out
                      hipStream_t stream);
 /* Per-leaf entry counts (capacity/leaf_size uint16). */
 int gpma_export_leaf_counts(gpma_t *h, uint16_t *out_dev, uint64_t max, hipStream_t stream);
+/* Per-leaf pivots (capacity/leaf_size uint64): the first slot of each leaf
+ * with the deletion mark cleared, the array BinarySearchLeafSegments searches
+ * (Section 5.1, Algorithm "GPMA+ Segment-Oriented Insertion").  Every update
+ * keeps it equal to that definition.  GPMA_EINVAL if max is too small or h is
+ * a snapshot (which keeps no pivots). */
+int gpma_export_pivots(gpma_t *h, uint64_t *out_dev, uint64_t max, hipStream_t stream);
 /* CSR row offsets on the PMA (V+1 uint32): row u spans slots
  * [off[u], off[u+1]) and ends with its guard; off[0] = 0. */
 int gpma_export_row_offsets(gpma_t *h, uint32_t *out_dev, uint64_t max, hipStream_t stream);

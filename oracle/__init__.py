@@ -276,6 +276,12 @@ def leaf_counts(slots: np.ndarray, lf: int) -> np.ndarray:
     return (slots.reshape(-1, lf) != EMPTY).sum(axis=1).astype(np.int64)
 
 
+def leaf_pivots(slots: np.ndarray, lf: int) -> np.ndarray:
+    """Each leaf's pivot: its first slot, a lazily deleted entry counting by
+    its key (the locate rule's search keys, Section 5.1)."""
+    return slots.reshape(-1, lf)[:, 0] & ~TOMB
+
+
 def row_offsets(slots: np.ndarray, V: int) -> np.ndarray:
     """CSR row offsets on the PMA (Section 4.2, "CSR as a case study"): the
     guard of row u ends the row, so offset[u+1] = position(guard_u) + 1 and

@@ -54,6 +54,7 @@ struct gpma {
     uint32_t H = 0;
     uint64_t n = 0;   // stored entries, guards included
     uint64_t *slots = nullptr;
+    uint64_t *piv = nullptr;    // per leaf: its first slot, mark bit cleared (the locate's search array)
     uint16_t *cnt = nullptr;
     uint32_t *row_ptr = nullptr;
     uint32_t *deg = nullptr;
@@ -194,6 +195,7 @@ struct gpma {
     // after a resize the old arrays join them until the call ends
     struct ArrBuf {
         uint64_t *slots;
+        uint64_t *piv;
         uint16_t *cnt;
         uint32_t *dead;
         uint64_t cap;   // slots the buffer holds (>= the capacity it serves)
@@ -445,12 +447,13 @@ int ensure_dt(gpma *g, uint64_t entries, uint64_t leaves) {
 
 // Add one set of root arrays holding `cap` slots to the pool.
 int pool_add(gpma *g, uint64_t cap) {
-    gpma::ArrBuf b{nullptr, nullptr, nullptr, cap};
+    gpma::ArrBuf b{nullptr, nullptr, nullptr, nullptr, cap};
     int e = dev_alloc(g, &b.slots, cap);
+    if (!e) e = dev_alloc(g, &b.piv, cap >> g->lf_log2);
     if (!e) e = dev_alloc(g, &b.cnt, cap >> g->lf_log2);
     if (!e && g->dead) e = dev_alloc(g, &b.dead, cap >> g->lf_log2);
     if (e) {
-        dev_free(g, b.slots); dev_free(g, b.cnt); dev_free(g, b.dead);
+        dev_free(g, b.slots); dev_free(g, b.piv); dev_free(g, b.cnt); dev_free(g, b.dead);
         return GPMA_ENOMEM;
     }
     g->pool.push_back(b);
@@ -461,7 +464,7 @@ int pool_add(gpma *g, uint64_t cap) {
 // replaced (after the device has finished with them).
 void release_pool(gpma *g) {
     for (auto &b : g->pool) {
-        dev_free(g, b.slots); dev_free(g, b.cnt); dev_free(g, b.dead);
+        dev_free(g, b.slots); dev_free(g, b.piv); dev_free(g, b.cnt); dev_free(g, b.dead);
     }
     g->pool.clear();
 }
@@ -536,7 +539,7 @@ int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t
     uint64_t N = del ? ns - k : ns + k;
     e = ensure_dt(g, ns + k, 0);
     if (e) return e;
-    gpma::ArrBuf nb{g->slots, g->cnt, g->dead, g->slots_buf};
+    gpma::ArrBuf nb{g->slots, g->piv, g->cnt, g->dead, g->slots_buf};
     if (ncap != g->cap) {
         int best = -1;
         for (size_t i = 0; i < g->pool.size(); i++)
@@ -550,11 +553,12 @@ int rebuild_root(gpma *g, bool del, const uint64_t *U, uint8_t *status, uint64_t
     }
     launch_gather_segment(g->slots, g->cnt, g->dead, 0, g->L, g->lf, g->dt_off, g->dtA, s);
     launch_merge_sorted(del, g->dtA, ns, U, k, g->dtB, s);
-    launch_dispatch(g->dtB, N, nb.slots, nb.cnt, nb.dead, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
+    launch_dispatch(g->dtB, N, nb.slots, nb.piv, nb.cnt, nb.dead, g->row_ptr, 0, ncap >> g->lf_log2, g->lf, s);
     launch_mark_done(del, U, status, 0, k, g->deg, g->ctl, ncap, true, s);
     if (ncap != g->cap) {
-        g->pool.push_back(gpma::ArrBuf{g->slots, g->cnt, g->dead, g->slots_buf});
+        g->pool.push_back(gpma::ArrBuf{g->slots, g->piv, g->cnt, g->dead, g->slots_buf});
         g->slots = nb.slots;
+        g->piv = nb.piv;
         g->cnt = nb.cnt;
         g->dead = nb.dead;
         g->slots_buf = nb.cap;
@@ -611,8 +615,8 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
             // rewritten earlier in the loop are disjoint from it)
             launch_gather_segment(g->slots, g->cnt, g->dead, first, P, g->lf, g->dt_off + first, g->dtA, s);
             launch_merge_sorted(del, g->dtA, ns, c.k + i, k, g->dtB, s);
-            launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->cnt, g->dead, g->row_ptr, first, P, g->lf,
-                            s);
+            launch_dispatch(g->dtB, del ? ns - k : ns + k, g->slots, g->piv, g->cnt, g->dead, g->row_ptr, first, P,
+                            g->lf, s);
             launch_mark_done(del, c.k, c.st, i, k, g->deg, g->ctl, P << g->lf_log2, false, s);
         }
         i = j;
@@ -627,10 +631,10 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
 void do_locate(gpma *g, const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, uint32_t *leaf,
                uint8_t *status, hipStream_t s, const WinSrc *ws = nullptr) {
     if (g->learned && g->loc)
-        launch_locate_learned(keys, n_dev, n_max, g->slots, g->row_ptr, g->L, g->lf_log2, g->loc, g->ctl, leaf,
+        launch_locate_learned(keys, n_dev, n_max, g->piv, g->row_ptr, g->L, g->lf_log2, g->loc, g->ctl, leaf,
                               status, &g->ctl->misses, s, ws);
     else
-        launch_locate(keys, n_dev, n_max, g->slots, g->L, g->lf, g->ctl, leaf, status, s, ws);
+        launch_locate(keys, n_dev, n_max, g->piv, g->L, g->ctl, leaf, status, s, ws);
 }
 
 // Cholesky solve of the (ridge-regularised) n x n normal equations
@@ -688,7 +692,7 @@ int locator_fit(gpma *g, hipStream_t s) {
     const uint64_t np = std::min<uint64_t>(1024, L);
     const uint64_t step = L / np;
     std::vector<uint64_t> piv(np);
-    hipMemcpy2DAsync(piv.data(), sizeof(uint64_t), g->slots, (step << g->lf_log2) * sizeof(uint64_t),
+    hipMemcpy2DAsync(piv.data(), sizeof(uint64_t), g->piv, step * sizeof(uint64_t),
                      sizeof(uint64_t), np, hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
     std::vector<uint32_t> dsts;
@@ -712,7 +716,7 @@ int locator_fit(gpma *g, hipStream_t s) {
     m.b1[31] = 0.0f;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
     hipMemsetAsync(g->loc_gram, 0, loc_gram_words() * sizeof(double), s);
-    launch_loc_gram(g->slots, g->row_ptr, L, g->lf_log2, stride, S, g->loc, g->loc_gram, s);
+    launch_loc_gram(g->piv, g->row_ptr, L, g->lf_log2, stride, S, g->loc, g->loc_gram, s);
     std::vector<double> gram(loc_gram_words());
     hipMemcpyAsync(gram.data(), g->loc_gram, gram.size() * sizeof(double), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
@@ -730,7 +734,7 @@ int locator_fit(gpma *g, hipStream_t s) {
     m.valid = 0;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
     hipMemsetAsync(g->loc_err, 0, 2 * sizeof(uint32_t), s);
-    launch_loc_eval(g->slots, g->row_ptr, L, g->lf_log2, g->loc, g->loc_err, s);
+    launch_loc_eval(g->piv, g->row_ptr, L, g->lf_log2, g->loc, g->loc_err, s);
     uint32_t err[2] = {0, 0};
     hipMemcpyAsync(err, g->loc_err, sizeof(err), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
@@ -783,7 +787,7 @@ int finish_levels(gpma *g, bool del, LevelArrays cur, uint64_t rem, uint32_t h_s
         if (seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds) {
             pa = pb = nullptr;
             if (g->prof_on) { pa = ev_get(g); hipEventRecord(pa, s); }
-            launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, rem, g->slots, g->cnt, g->row_ptr,
+            launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, rem, g->slots, g->piv, g->cnt, g->row_ptr,
                              g->deg, g->dead, g->lf, lo, hi, g->ctl, s);
             if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
         } else {
@@ -894,7 +898,7 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
     if (mark)
         launch_leaf_mark(cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->dead, g->deg, g->lf, g->ctl, s);
     else
-        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, b, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, b, g->slots, g->piv, g->cnt, g->row_ptr, g->deg, g->dead,
                           g->lf, lo, hi, g->ctl, s);
     if (g->prof_on) { pb = ev_get(g); hipEventRecord(pb, s); }
     compact_pending(cur.k, cur.l, cur.st, cur.n, b, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del,
@@ -951,7 +955,8 @@ void free_all(gpma *g) {
     if (g->ev_join) hipEventDestroy(g->ev_join);
     if (g->ev_join2) hipEventDestroy(g->ev_join2);
     g->ev_fork = g->ev_join = g->ev_join2 = nullptr;
-    dev_free(g, g->slots); dev_free(g, g->cnt); dev_free(g, g->row_ptr); dev_free(g, g->deg); dev_free(g, g->dead);
+    dev_free(g, g->slots); dev_free(g, g->piv); dev_free(g, g->cnt); dev_free(g, g->row_ptr); dev_free(g, g->deg);
+    dev_free(g, g->dead);
     dev_free(g, g->lk_scratch); dev_free(g, g->lk_locks);
     dev_free(g, g->dtA); dev_free(g, g->dtB); dev_free(g, g->dt_off); dev_free(g, g->dt_tmp);
     dev_free(g, g->pr_contrib); dev_free(g, g->pr_y); dev_free(g, g->pr_dang);
@@ -1102,7 +1107,7 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     const bool upper = !mark && g->fused_levels >= 1 && g->H > 1 &&
                        seg_merge_lds_bytes(g->lf, 1) <= (size_t)g->dev.max_lds;
     if (!mark && !upper) {
-        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->piv, g->cnt, g->row_ptr, g->deg, g->dead,
                           g->lf, lo, hi, g->ctl, s, g->tmp);
         launch_finish_leaf(g->fs, stop, g->ctl, g->tmp, leaf_merge_blocks(g->lf, cls), del, g->lf, g->outs, s);
         ge->fin_k = cur.k;
@@ -1116,7 +1121,7 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
     if (mark)
         launch_leaf_mark(cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->dead, g->deg, g->lf, g->ctl, s);
     else
-        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+        launch_leaf_merge(del, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->piv, g->cnt, g->row_ptr, g->deg, g->dead,
                           g->lf, lo, hi, g->ctl, s);
     compact_pending(cur.k, cur.l, cur.st, cur.n, cls, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del, g->lf,
                     g->ctl, s);
@@ -1138,7 +1143,7 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
                          seg_merge_lds_bytes(g->lf, h) <= (size_t)g->dev.max_lds;
          h++) {
         bounds(g, g->H, h, &lo, &hi);
-        launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->cnt, g->row_ptr, g->deg, g->dead,
+        launch_seg_merge(del, h, cur.k, cur.l, cur.st, cur.n, cls, g->slots, g->piv, g->cnt, g->row_ptr, g->deg, g->dead,
                          g->lf, lo, hi, g->ctl, s);
         compact_pending(cur.k, cur.l, cur.st, cur.n, cls, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, del,
                         (uint64_t)g->lf << h, g->ctl, s);
@@ -1209,8 +1214,8 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
     const uint64_t tmask = ~(((1ull << kWindowTagBits) - 1) << (32 + sb));
     gpma *h[2] = {g, m};
     WinSrc ws[2];
-    const uint64_t *slots_c[2], *keys_c[2];
-    uint64_t *slots[2], L[2], lo[2], hi[2];
+    const uint64_t *piv_c[2], *keys_c[2];
+    uint64_t *slots[2], *piv[2], L[2], lo[2], hi[2];
     const uint32_t *row_ptr_c[2], *leaf_c[2], *nd[2];
     uint32_t *leaf[2], *misses[2], *row_ptr[2], *deg[2], *dead[2], *part[2], *stop[2];
     uint8_t *status[2];
@@ -1226,7 +1231,8 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
         ws[k] = WinSrc{&x->fs->batch, &x->fs->wstart, &x->fs->gen, x->stop, x->wukeys, x->ustart, x->werrs, tmask,
                        x->kS, x->ctl};
         slots[k] = x->slots;
-        slots_c[k] = x->slots;
+        piv[k] = x->piv;
+        piv_c[k] = x->piv;
         keys_c[k] = x->kS;
         L[k] = x->L;
         bounds(x, x->H, 0, &lo[k], &hi[k]);
@@ -1250,10 +1256,10 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
         outs[k] = x->outs;
     }
     if (g->learned && g->loc)
-        launch_locate_learned2(cls, slots_c, row_ptr_c, L, g->lf_log2, model, ctl_c, leaf, status, misses, ws, s);
+        launch_locate_learned2(cls, piv_c, row_ptr_c, L, g->lf_log2, model, ctl_c, leaf, status, misses, ws, s);
     else
-        launch_locate2(cls, slots_c, L, g->lf, ctl_c, leaf, status, ws, s);
-    launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, cnt, row_ptr, deg, dead, g->lf, lo, hi, ctl,
+        launch_locate2(cls, piv_c, L, ctl_c, leaf, status, ws, s);
+    launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, piv, cnt, row_ptr, deg, dead, g->lf, lo, hi, ctl,
                        part, s);
     launch_finish_leaf2(st, stop, ctl, part_c, leaf_merge_blocks(g->lf, cls), del, g->lf, outs, s);
 }
@@ -1826,6 +1832,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     set_geometry(g, cap);
     g->slots_buf = cap;
     e |= dev_alloc(g, &g->slots, cap);
+    e |= dev_alloc(g, &g->piv, g->L);
     e |= dev_alloc(g, &g->cnt, g->L);
     e |= dev_alloc(g, &g->row_ptr, (uint64_t)V + 1);
     e |= dev_alloc(g, &g->deg, V);
@@ -1841,7 +1848,7 @@ int gpma_create(gpma_t **out, uint32_t V, const uint64_t *keys, uint64_t n, cons
     g->fused_direct = (p.flags & GPMA_FLAG_FUSED_DIRECT) != 0;
     g->sort_chunks = p.sort_tile_keys ? (int)(p.sort_tile_keys / 256) : 4;
     g->fused_levels = p.fused_levels;
-    launch_dispatch(uq, nu, g->slots, g->cnt, g->dead, g->row_ptr, 0, g->L, lf, s);
+    launch_dispatch(uq, nu, g->slots, g->piv, g->cnt, g->dead, g->row_ptr, 0, g->L, lf, s);
     launch_degrees_from_sorted(uq, nu, V, fl, g->deg, s);
     if (hipStreamSynchronize(s) != hipSuccess) {
         cleanup();
@@ -2004,7 +2011,7 @@ static int lock_rounds(gpma *g, const uint64_t *keys, uint64_t b, hipStream_t s,
         radix_sort_keys(keys, b, sb, sb, g->V, g->kA, g->kB, g->tmp, s, nullptr, g->ctl, g->sort_chunks);
     uint64_t *ukeys = (sorted == g->kA) ? g->kB : g->kA;
     unique_sorted(sorted, b, ukeys, &g->ctl->n_in, g->flags, g->tmp, s);
-    launch_locate(ukeys, &g->ctl->n_in, b, g->slots, g->L, g->lf, g->ctl, g->leafA, g->stA, s);
+    launch_locate(ukeys, &g->ctl->n_in, b, g->piv, g->L, g->ctl, g->leafA, g->stA, s);
     launch_lock_probe(ukeys, g->leafA, g->stA, &g->ctl->n_in, b, g->slots, g->cnt, g->lf_log2, g->ctl, s);
     LevelArrays cur{g->kC, g->leafB, g->stB, &g->ctl->lvl[0]};
     LevelArrays nxt{g->kD, g->leafA, g->stA, &g->ctl->lvl[1]};
@@ -2021,11 +2028,11 @@ static int lock_rounds(gpma *g, const uint64_t *keys, uint64_t b, hipStream_t s,
         e = lock_state(g, 0, s);
         if (e) return e;
         const uint32_t epoch = ++g->lk_epoch;
-        launch_locate(cur.k, cur.n, rem, g->slots, g->L, g->lf, g->ctl, cur.l, cur.st, s);
+        launch_locate(cur.k, cur.n, rem, g->piv, g->L, g->ctl, cur.l, cur.st, s);
         for (uint32_t h = 0; h <= g->H; h++) {
             uint64_t lo, hi;
             bounds(g, g->H, h, &lo, &hi);
-            launch_lock_try(h, g->H, cur.k, cur.l, cur.st, rem, g->slots, g->cnt, g->dead, g->row_ptr, g->deg,
+            launch_lock_try(h, g->H, cur.k, cur.l, cur.st, rem, g->slots, g->piv, g->cnt, g->dead, g->row_ptr, g->deg,
                             g->lk_scratch, g->lk_locks, epoch, g->L, g->lf_log2, hi, g->ctl, s);
         }
         compact_pending(cur.k, cur.l, cur.st, cur.n, rem, nxt.k, nxt.l, nxt.st, nxt.n, g->flags, g->tmp, false, 0,
@@ -2205,6 +2212,12 @@ int gpma_export_keys(gpma_t *g, uint64_t *out, uint64_t max, uint64_t *n_out, hi
 int gpma_export_leaf_counts(gpma_t *g, uint16_t *out, uint64_t max, hipStream_t s) {
     if (!g || !out || max < g->L) return GPMA_EINVAL;
     hipMemcpyAsync(out, g->cnt, g->L * sizeof(uint16_t), hipMemcpyDeviceToDevice, s);
+    return GPMA_OK;
+}
+
+int gpma_export_pivots(gpma_t *g, uint64_t *out, uint64_t max, hipStream_t s) {
+    if (!g || !out || !g->piv || max < g->L) return GPMA_EINVAL;
+    hipMemcpyAsync(out, g->piv, g->L * sizeof(uint64_t), hipMemcpyDeviceToDevice, s);
     return GPMA_OK;
 }
 

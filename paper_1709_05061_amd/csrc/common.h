@@ -258,11 +258,13 @@ void compact_edges(const uint64_t *slots, uint64_t cap, uint64_t *out, uint32_t 
 void launch_validate(const uint64_t *keys, uint64_t n, uint32_t V, gpma_dev::Ctl *ctl,
                      hipStream_t s, const uint32_t *n_dev = nullptr);
 void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s);
+// (piv: each leaf's first slot with the mark bit cleared, L words; every
+// kernel below that writes a leaf's first slot writes its pivot too)
 void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max,
-                   const uint64_t *slots, uint64_t L, uint32_t lf, const gpma_dev::Ctl *ctl,
+                   const uint64_t *piv, uint64_t L, const gpma_dev::Ctl *ctl,
                    uint32_t *leaf, uint8_t *status, hipStream_t s, const gpma_dev::WinSrc *ws = nullptr);
 void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
-                       const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
+                       const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint64_t *piv, uint16_t *cnt,
                        uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf, uint64_t min0,
                        uint64_t max0, gpma_dev::Ctl *ctl, hipStream_t s, uint32_t *part = nullptr);
 // blocks of one leaf merge launch over n_max updates (4 words of `part` each)
@@ -270,19 +272,20 @@ uint64_t leaf_merge_blocks(uint32_t lf, uint64_t n_max);
 // binary-search locate and the leaf merge for the array (index 0) and its
 // mirror (index 1) in one launch each; the locate takes each side's batch
 // from its window (ws)
-void launch_locate2(uint64_t n_max, const uint64_t *const slots[2], const uint64_t L[2], uint32_t lf,
+void launch_locate2(uint64_t n_max, const uint64_t *const piv[2], const uint64_t L[2],
                     const gpma_dev::Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2],
                     const gpma_dev::WinSrc ws[2], hipStream_t s);
 void launch_leaf_merge2(bool del, const uint64_t *const keys[2], const uint32_t *const leaf[2],
                         uint8_t *const status[2], const uint32_t *const n_dev[2], uint64_t n_max,
-                        uint64_t *const slots[2], uint16_t *const cnt[2], uint32_t *const row_ptr[2],
-                        uint32_t *const deg[2], uint32_t *const dead[2], uint32_t lf, const uint64_t min0[2],
-                        const uint64_t max0[2], gpma_dev::Ctl *const ctl[2], uint32_t *const part[2], hipStream_t s);
+                        uint64_t *const slots[2], uint64_t *const piv[2], uint16_t *const cnt[2],
+                        uint32_t *const row_ptr[2], uint32_t *const deg[2], uint32_t *const dead[2], uint32_t lf,
+                        const uint64_t min0[2], const uint64_t max0[2], gpma_dev::Ctl *const ctl[2],
+                        uint32_t *const part[2], hipStream_t s);
 // workgroup tier at height h >= 1; needs seg_merge_lds_bytes(lf, h) <= max LDS
 size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h);
 int seg_merge_max_lds();
 void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
-                      uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
+                      uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint64_t *piv,
                       uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf,
                       uint64_t minh, uint64_t maxh, gpma_dev::Ctl *ctl, hipStream_t s);
 // device tier pieces (one segment at a time; also the root rebuild and bulk load)
@@ -301,7 +304,7 @@ void launch_seg_live(const uint32_t *leaf, uint64_t rem, uint32_t h, const uint3
                      const uint32_t *total, uint32_t *ns_out, hipStream_t s);
 void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_t *U, uint64_t k,
                          uint64_t *out, hipStream_t s);
-void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *dead,
+void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint64_t *piv, uint16_t *cnt, uint32_t *dead,
                      uint32_t *row_ptr, uint64_t first_leaf, uint64_t P, uint32_t lf,
                      hipStream_t s);
 void launch_leaf_counts_u32(const uint16_t *cnt, const uint32_t *dead, uint64_t first_leaf, uint64_t P,
@@ -311,7 +314,7 @@ void launch_lock_probe(const uint64_t *keys, const uint32_t *leaf, uint8_t *stat
                        uint64_t n_max, const uint64_t *slots, const uint16_t *cnt, uint32_t lf_log2,
                        const gpma_dev::Ctl *ctl, hipStream_t s);
 void launch_lock_try(uint32_t h, uint32_t H, const uint64_t *keys, uint32_t *leaf, uint8_t *status, uint64_t n,
-                     uint64_t *slots, uint16_t *cnt, uint32_t *dead, uint32_t *row_ptr, uint32_t *deg,
+                     uint64_t *slots, uint64_t *piv, uint16_t *cnt, uint32_t *dead, uint32_t *row_ptr, uint32_t *deg,
                      uint64_t *scratch, uint32_t *locks, uint32_t epoch, uint64_t L, uint32_t lf_log2, uint64_t maxh,
                      gpma_dev::Ctl *ctl, hipStream_t s);
 // lazy deletion: mark the located unique keys in place (status kDone/kNoop)

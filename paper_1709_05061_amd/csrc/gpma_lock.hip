@@ -60,7 +60,8 @@ __global__ void k_lock_probe(const uint64_t *__restrict__ keys, const uint32_t *
 // One height of one round: a wave per pending insertion.
 __global__ void __launch_bounds__(kLockThreads)
 k_lock_try(uint32_t h, uint32_t H, const uint64_t *__restrict__ keys, uint32_t *__restrict__ leaf,
-           uint8_t *__restrict__ status, uint64_t n, uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+           uint8_t *__restrict__ status, uint64_t n, uint64_t *__restrict__ slots, uint64_t *__restrict__ piv,
+           uint16_t *__restrict__ cnt,
            uint32_t *__restrict__ dead, uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg,
            uint64_t *__restrict__ scratch, uint32_t *__restrict__ locks, uint32_t epoch, uint64_t L,
            uint32_t lf_log2, uint64_t maxh, Ctl *__restrict__ ctl) {
@@ -119,6 +120,7 @@ k_lock_try(uint32_t h, uint32_t H, const uint64_t *__restrict__ keys, uint32_t *
         const uint64_t v = o < cj ? scratch[base + st + o] : kEmpty;
         slots[base + p] = v;
         if (o == 0) {
+            piv[first + j] = v & ~kTomb;
             cnt[first + j] = (uint16_t)cj;
             if (dead) dead[first + j] = 0;
         }
@@ -143,12 +145,12 @@ void launch_lock_probe(const uint64_t *keys, const uint32_t *leaf, uint8_t *stat
 }
 
 void launch_lock_try(uint32_t h, uint32_t H, const uint64_t *keys, uint32_t *leaf, uint8_t *status, uint64_t n,
-                     uint64_t *slots, uint16_t *cnt, uint32_t *dead, uint32_t *row_ptr, uint32_t *deg,
+                     uint64_t *slots, uint64_t *piv, uint16_t *cnt, uint32_t *dead, uint32_t *row_ptr, uint32_t *deg,
                      uint64_t *scratch, uint32_t *locks, uint32_t epoch, uint64_t L, uint32_t lf_log2, uint64_t maxh,
                      Ctl *ctl, hipStream_t s) {
     if (!n) return;
     hipLaunchKernelGGL(k_lock_try, dim3((uint32_t)div_up(n, kLockThreads / kWave)), dim3(kLockThreads), 0, s, h, H,
-                       keys, leaf, status, n, slots, cnt, dead, row_ptr, deg, scratch, locks, epoch, L, lf_log2, maxh,
+                       keys, leaf, status, n, slots, piv, cnt, dead, row_ptr, deg, scratch, locks, epoch, L, lf_log2, maxh,
                        ctl);
 }
 

@@ -29,21 +29,21 @@ struct LocModel {
 
 namespace gpma_host {
 
-void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
+void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *piv,
                            const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, const gpma_dev::LocModel *model,
                            const gpma_dev::Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses,
                            hipStream_t s, const gpma_dev::WinSrc *ws = nullptr);
 // the same for the array (index 0) and its mirror (index 1) in one launch,
 // each taking its batch from its window (ws)
-void launch_locate_learned2(uint64_t n_max, const uint64_t *const slots[2], const uint32_t *const row_ptr[2],
+void launch_locate_learned2(uint64_t n_max, const uint64_t *const piv[2], const uint32_t *const row_ptr[2],
                             const uint64_t L[2], uint32_t lf_log2, const gpma_dev::LocModel *const model[2],
                             const gpma_dev::Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2],
                             uint32_t *const misses[2], const gpma_dev::WinSrc ws[2], hipStream_t s);
 size_t loc_gram_words();
-void launch_loc_gram(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, uint64_t stride,
+void launch_loc_gram(const uint64_t *piv, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, uint64_t stride,
                      uint64_t S, const gpma_dev::LocModel *model, double *gram, hipStream_t s);
 // err[0]: max leaf error, err[1]: bits of the max fraction error (both start at 0)
-void launch_loc_eval(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2,
+void launch_loc_eval(const uint64_t *piv, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2,
                      const gpma_dev::LocModel *model, uint32_t *err, hipStream_t s);
 
 }  // namespace gpma_host

@@ -115,19 +115,17 @@ __device__ __forceinline__ uint64_t predict_in_span(float t, const Span &sp) {
 }
 
 // leaf j's pivot: its first entry, a marked one ordering by its masked key
-__device__ __forceinline__ uint64_t pivot(const uint64_t *slots, uint32_t lf_log2, uint64_t j) {
-    return slots[j << lf_log2] & ~kTomb;
-}
+// (the dense pivot array the update kernels keep)
+__device__ __forceinline__ uint64_t pivot(const uint64_t *piv, uint64_t j) { return piv[j]; }
 
 // the largest leaf j in [lo, hi] with pivot(j) <= k (lo if none).  (An
 // 8-way search, seven pivots loaded per step, measured slower: 71 against
 // 43 us for a paired locate of 2^16 keys at scale 24.)
-__device__ __forceinline__ uint64_t search_range(const uint64_t *slots, uint32_t lf_log2, uint64_t lo,
-                                                 uint64_t hi, uint64_t k) {
+__device__ __forceinline__ uint64_t search_range(const uint64_t *piv, uint64_t lo, uint64_t hi, uint64_t k) {
     uint64_t a = lo, b = hi + 1;   // pivots in [a, b) : count of those <= k
     while (a < b) {
         const uint64_t mid = (a + b) >> 1;
-        if (pivot(slots, lf_log2, mid) <= k) a = mid + 1; else b = mid;
+        if (pivot(piv, mid) <= k) a = mid + 1; else b = mid;
     }
     return a > lo ? a - 1 : lo;
 }
@@ -139,7 +137,7 @@ struct LocateLearnedOp {
         const uint64_t *keys;
         const uint32_t *n_dev;
         uint64_t n_max;
-        const uint64_t *slots;
+        const uint64_t *piv;
         const uint32_t *row_ptr;
         uint64_t L;
         uint32_t lf_log2;
@@ -154,7 +152,7 @@ struct LocateLearnedOp {
         const uint64_t *__restrict__ keys = args.keys;
         const uint32_t *__restrict__ n_dev = args.n_dev;
         uint64_t n_max = args.n_max;
-        const uint64_t *__restrict__ slots = args.slots;
+        const uint64_t *__restrict__ piv = args.piv;
         const uint32_t *__restrict__ row_ptr = args.row_ptr;
         uint64_t L = args.L;
         uint32_t lf_log2 = args.lf_log2;
@@ -183,18 +181,18 @@ struct LocateLearnedOp {
         if (!active) return;
         uint64_t j;
         if (span <= kMinSpan) {
-            j = search_range(slots, lf_log2, sp.first, sp.last, k);
+            j = search_range(piv, sp.first, sp.last, k);
         } else {
             const uint64_t p = predict_in_span(t, sp);
             const uint64_t e = (uint64_t)(m.delta * (float)span) + 2;
             const uint64_t lo = p > sp.first + e ? p - e : sp.first;
             const uint64_t hi = p + e < sp.last ? p + e : sp.last;
-            const bool ok_lo = lo == sp.first || pivot(slots, lf_log2, lo) <= k;
-            const bool ok_hi = hi == sp.last || pivot(slots, lf_log2, hi + 1) > k;
+            const bool ok_lo = lo == sp.first || pivot(piv, lo) <= k;
+            const bool ok_hi = hi == sp.last || pivot(piv, hi + 1) > k;
             if (m.valid && m.L == L && ok_lo && ok_hi) {
-                j = search_range(slots, lf_log2, lo, hi, k);
+                j = search_range(piv, lo, hi, k);
             } else {
-                j = search_range(slots, lf_log2, sp.first, sp.last, k);
+                j = search_range(piv, sp.first, sp.last, k);
                 atomicAdd(misses, 1u);
             }
         }
@@ -205,10 +203,10 @@ struct LocateLearnedOp {
 
 __global__ void __launch_bounds__(256)
 k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-                 const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L,
+                 const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_ptr, uint64_t L,
                  uint32_t lf_log2, const LocModel *__restrict__ model, const Ctl *ctl,
                  uint32_t *__restrict__ leaf, uint8_t *__restrict__ status, uint32_t *misses, WinSrc ws) {
-    LocateLearnedOp::run(LocateLearnedOp::Args{keys, n_dev, n_max, slots, row_ptr, L, lf_log2, model, ctl, leaf,
+    LocateLearnedOp::run(LocateLearnedOp::Args{keys, n_dev, n_max, piv, row_ptr, L, lf_log2, model, ctl, leaf,
         status, misses, ws});
 }
 
@@ -220,7 +218,7 @@ constexpr int kGram = kFeat * kFeat + kFeat; // G and r
 constexpr int kFitChunk = 128;
 
 __global__ void __launch_bounds__(256)
-k_loc_gram(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
+k_loc_gram(const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
            uint64_t stride, uint64_t S, const LocModel *__restrict__ model, double *__restrict__ gram) {
     __shared__ double phi[kFitChunk][kFeat + 1];   // features and target (all 0: not a sample)
     const LocModel m = *model;
@@ -232,7 +230,7 @@ k_loc_gram(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_
             bool use = false;
             if (s < S) {
                 const uint64_t j = s * stride;
-                const uint64_t k = pivot(slots, lf_log2, j);
+                const uint64_t k = pivot(piv, j);
                 const Span sp = row_span(row_ptr, key_src(k), lf_log2);
                 const uint64_t span = sp.last - sp.first + 1;
                 if (!is_guard(k) && span > kMinSpan) {
@@ -269,7 +267,7 @@ k_loc_gram(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_
 // Error bounds over every long-row leaf pivot: the largest leaf error and the
 // largest error of t against the pivot's fraction of its span.
 __global__ void __launch_bounds__(256)
-k_loc_eval(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
+k_loc_eval(const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
            const LocModel *__restrict__ model, uint32_t *__restrict__ err) {
     __shared__ float s_out[256];
     const LocModel m = *model;
@@ -279,7 +277,7 @@ k_loc_eval(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_
     // the loop bound is wave-uniform (L is a multiple of 64 or the wave is the last)
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < L; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
-        const uint64_t k = j < L ? pivot(slots, lf_log2, j) : 0;
+        const uint64_t k = j < L ? pivot(piv, j) : 0;
         const float t = model_position(m, k, s_out + (threadIdx.x & ~63u));
         if (j < L && !is_guard(k)) {
             const Span sp = row_span(row_ptr, key_src(k), lf_log2);
@@ -309,41 +307,41 @@ k_loc_eval(const uint64_t *__restrict__ slots, const uint32_t *__restrict__ row_
 
 namespace gpma_host {
 
-void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
+void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *piv,
                            const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, const LocModel *model,
                            const Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses, hipStream_t s,
                            const WinSrc *ws) {
     if (!n_max) return;
     const WinSrc w = ws ? *ws : WinSrc{};
     hipLaunchKernelGGL(k_locate_learned, dim3((uint32_t)((n_max + 255) / 256)), dim3(256), 0, s, keys, n_dev,
-                       n_max, slots, row_ptr, L, lf_log2, model, ctl, leaf, status, misses, w);
+                       n_max, piv, row_ptr, L, lf_log2, model, ctl, leaf, status, misses, w);
 }
 
 size_t loc_gram_words() { return kGram; }
 
-void launch_loc_gram(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, uint64_t stride,
+void launch_loc_gram(const uint64_t *piv, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, uint64_t stride,
                      uint64_t S, const LocModel *model, double *gram, hipStream_t s) {
     uint64_t blocks = (S + kFitChunk - 1) / kFitChunk;
     if (blocks > 128) blocks = 128;
-    hipLaunchKernelGGL(k_loc_gram, dim3((uint32_t)blocks), dim3(256), 0, s, slots, row_ptr, L, lf_log2, stride, S,
+    hipLaunchKernelGGL(k_loc_gram, dim3((uint32_t)blocks), dim3(256), 0, s, piv, row_ptr, L, lf_log2, stride, S,
                        model, gram);
 }
 
-void launch_loc_eval(const uint64_t *slots, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2,
+void launch_loc_eval(const uint64_t *piv, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2,
                      const LocModel *model, uint32_t *err, hipStream_t s) {
     uint64_t blocks = (L + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, slots, row_ptr, L, lf_log2, model, err);
+    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, piv, row_ptr, L, lf_log2, model, err);
 }
 
-void launch_locate_learned2(uint64_t n_max, const uint64_t *const slots[2], const uint32_t *const row_ptr[2],
+void launch_locate_learned2(uint64_t n_max, const uint64_t *const piv[2], const uint32_t *const row_ptr[2],
                             const uint64_t L[2], uint32_t lf_log2, const LocModel *const model[2],
                             const Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2],
                             uint32_t *const misses[2], const WinSrc ws[2], hipStream_t s) {
     if (!n_max) return;
     LocateLearnedOp::Args a[2];
     for (int k = 0; k < 2; k++)
-        a[k] = {nullptr, nullptr, n_max, slots[k], row_ptr[k], L[k], lf_log2, model[k], ctl[k], leaf[k], status[k],
+        a[k] = {nullptr, nullptr, n_max, piv[k], row_ptr[k], L[k], lf_log2, model[k], ctl[k], leaf[k], status[k],
                 misses[k], ws[k]};
     launch_pair<LocateLearnedOp, 256>((uint32_t)((n_max + 255) / 256), a[0], a[1], s);
 }

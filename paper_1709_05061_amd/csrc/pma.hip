@@ -53,17 +53,20 @@ __global__ void k_append_guards(uint64_t *__restrict__ dst, uint32_t V) {
 // BinarySearchLeafSegments: the leaf of key k is the leaf holding the
 // greatest stored key <= k, leaf 0 when there is none.  No leaf is ever empty,
 // so the first slot of every leaf is its smallest key and those pivots
-// ascend strictly: a plain binary search over slots[j*lf] (a marked entry
-// orders by its masked key).
+// ascend strictly: a plain binary search over them (a marked entry orders by
+// its masked key).  The pivots sit in their own dense array, piv[j] = the
+// first slot of leaf j with the mark cleared, which every kernel that writes
+// a leaf's first slot keeps; the search then touches one 8-byte word per step
+// where the slots would cost a 256-byte leaf apart each (at 2^24 leaves the
+// array is 128 MiB, and its last four steps share a cache line).
 
 struct LocateOp {
     struct Args {
         const uint64_t *keys;
         const uint32_t *n_dev;
         uint64_t n_max;
-        const uint64_t *slots;
+        const uint64_t *piv;
         uint64_t L;
-        uint32_t lf_log2;
         const Ctl *ctl;
         uint32_t *leaf;
         uint8_t *status;
@@ -73,9 +76,8 @@ struct LocateOp {
         const uint64_t *__restrict__ keys = args.keys;
         const uint32_t *__restrict__ n_dev = args.n_dev;
         uint64_t n_max = args.n_max;
-        const uint64_t *__restrict__ slots = args.slots;
+        const uint64_t *__restrict__ piv = args.piv;
         uint64_t L = args.L;
-        uint32_t lf_log2 = args.lf_log2;
         const Ctl * ctl = args.ctl;
         uint32_t *__restrict__ leaf = args.leaf;
         uint8_t *__restrict__ status = args.status;
@@ -88,7 +90,7 @@ struct LocateOp {
         uint64_t lo = 0, hi = L;   // count of leaves whose pivot is <= k
         while (lo < hi) {
             uint64_t mid = (lo + hi) >> 1;
-            if ((slots[mid << lf_log2] & ~kTomb) <= k) lo = mid + 1; else hi = mid;
+            if (piv[mid] <= k) lo = mid + 1; else hi = mid;
         }
         leaf[i] = (uint32_t)(lo ? lo - 1 : 0);
         status[i] = kPending;
@@ -97,10 +99,10 @@ struct LocateOp {
 
 __global__ void __launch_bounds__(256)
 k_locate(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev,
-                         uint64_t n_max, const uint64_t *__restrict__ slots, uint64_t L,
-                         uint32_t lf_log2, const Ctl *ctl, uint32_t *__restrict__ leaf,
+                         uint64_t n_max, const uint64_t *__restrict__ piv, uint64_t L,
+                         const Ctl *ctl, uint32_t *__restrict__ leaf,
                          uint8_t *__restrict__ status, WinSrc ws) {
-    LocateOp::run(LocateOp::Args{keys, n_dev, n_max, slots, L, lf_log2, ctl, leaf, status, ws});
+    LocateOp::run(LocateOp::Args{keys, n_dev, n_max, piv, L, ctl, leaf, status, ws});
 }
 
 // ---------------------------------------------------------------------------
@@ -153,7 +155,7 @@ template <int G, int SPL, bool DEL>
 __device__ __forceinline__ RunStats
 leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
                  uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-                 uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+                 uint64_t *__restrict__ slots, uint64_t *__restrict__ piv, uint16_t *__restrict__ cnt,
                  uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
                  uint32_t min0, uint32_t max0, const Ctl *__restrict__ ctl, uint64_t *lb, uint64_t *ub,
                  uint64_t *ob) {
@@ -259,6 +261,7 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
         const uint32_t p = gl * SPL + q;
         const uint64_t v = p < N ? ob[p] : kEmpty;
         slots[base + p] = v;
+        if (p == 0) piv[lf_i] = v & ~kTomb;
         if (p < N && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(base + p + 1);
     }
     if (gl == 0) {
@@ -292,6 +295,7 @@ struct LeafMergeArgs {
     const uint32_t *n_dev;
     uint64_t n_max;
     uint64_t *slots;
+    uint64_t *piv;
     uint16_t *cnt;
     uint32_t *row_ptr;
     uint32_t *deg;
@@ -311,6 +315,7 @@ struct LeafMergeOp {
         const uint32_t *__restrict__ n_dev = args.n_dev;
         const uint64_t n_max = args.n_max;
         uint64_t *__restrict__ slots = args.slots;
+        uint64_t *__restrict__ piv = args.piv;
         uint16_t *__restrict__ cnt = args.cnt;
         uint32_t *__restrict__ row_ptr = args.row_ptr;
         uint32_t *__restrict__ deg = args.deg;
@@ -325,7 +330,7 @@ struct LeafMergeOp {
         __shared__ uint64_t s_out[GPB][LF];
         __shared__ uint32_t s_red[4][256 / kWave];
         const uint32_t gib = threadIdx.x / G;
-        RunStats rs = leaf_merge_group<G, SPL, DEL>(keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead,
+        RunStats rs = leaf_merge_group<G, SPL, DEL>(keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead,
                                                     min0, max0, ctl, s_leaf[gib], s_upd[gib], s_out[gib]);
         if (!part) return;   // grid-uniform
         // every lane of a group holds the group's figures: count lane 0's
@@ -354,11 +359,11 @@ template <int G, int SPL, bool DEL>
 __global__ void __launch_bounds__(256)
 k_leaf_merge(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
              uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-             uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+             uint64_t *__restrict__ slots, uint64_t *__restrict__ piv, uint16_t *__restrict__ cnt,
              uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
              uint32_t min0, uint32_t max0, Ctl *__restrict__ ctl, uint32_t *__restrict__ part) {
-    LeafMergeOp<G, SPL, DEL>::run(
-        LeafMergeArgs{keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl, part});
+    LeafMergeOp<G, SPL, DEL>::run(LeafMergeArgs{keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg,
+                                                dead, min0, max0, ctl, part});
 }
 
 // ---------------------------------------------------------------------------
@@ -410,6 +415,7 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
                                               const uint64_t *__restrict__ keys,
                                               const uint32_t *__restrict__ leaf,
                                               uint8_t *__restrict__ status, uint64_t *__restrict__ slots,
+                                              uint64_t *__restrict__ piv,
                                               uint16_t *__restrict__ cnt, uint32_t *__restrict__ row_ptr,
                                               uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
                                               uint32_t lf_log2, uint64_t minh, uint64_t maxh, uint64_t *dyn,
@@ -465,8 +471,10 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
     const uint64_t N = DEL ? (uint64_t)ns - k : (uint64_t)ns + k;
     auto put = [&](uint64_t r, uint64_t v) {
         uint64_t j = rank_leaf(r, N, h);
-        uint64_t pos = base + (j << lf_log2) + (r - leaf_start(j, N, h));
+        const uint64_t o = r - leaf_start(j, N, h);
+        uint64_t pos = base + (j << lf_log2) + o;
         slots[pos] = v;
+        if (o == 0) piv[first_leaf + j] = v & ~kTomb;
         if (is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(pos + 1);
     };
     for (uint32_t x = threadIdx.x; x < ns; x += blockDim.x) {
@@ -489,6 +497,7 @@ __device__ __forceinline__ void seg_merge_one(uint32_t i, uint32_t n, uint32_t h
         uint64_t cj = leaf_start(j + 1, N, h) - leaf_start(j, N, h);
         if (o >= cj) slots[base + p] = kEmpty;
         if (o == 0) {
+            if (cj == 0) piv[first_leaf + j] = kEmpty & ~kTomb;
             cnt[first_leaf + j] = (uint16_t)cj;
             if (dead) dead[first_leaf + j] = 0;
         }
@@ -503,7 +512,7 @@ template <bool DEL>
 __global__ void __launch_bounds__(kSegThreads)
 k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
             uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev,
-            uint64_t *__restrict__ slots, uint16_t *__restrict__ cnt,
+            uint64_t *__restrict__ slots, uint64_t *__restrict__ piv, uint16_t *__restrict__ cnt,
             uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t *__restrict__ dead,
             uint32_t lf_log2, uint64_t minh, uint64_t maxh, Ctl *__restrict__ ctl) {
     extern __shared__ uint64_t dyn[];
@@ -511,8 +520,8 @@ k_seg_merge(uint32_t h, const uint64_t *__restrict__ keys, const uint32_t *__res
     const uint32_t n = *n_dev;
     if (ctl->err) return;
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x)
-        seg_merge_one<DEL>(i, n, h, keys, leaf, status, slots, cnt, row_ptr, deg, dead, lf_log2, minh, maxh, dyn,
-                           s_misc);
+        seg_merge_one<DEL>(i, n, h, keys, leaf, status, slots, piv, cnt, row_ptr, deg, dead, lf_log2, minh, maxh,
+                           dyn, s_misc);
 }
 
 // ---------------------------------------------------------------------------
@@ -607,8 +616,8 @@ __global__ void k_merge_rank_u(const uint64_t *__restrict__ A, uint64_t na,
 
 // even re-dispatch of M[0..N) over leaves first_leaf .. first_leaf+P-1
 __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t *__restrict__ slots,
-                           uint16_t *__restrict__ cnt, uint32_t *__restrict__ dead, uint32_t *__restrict__ row_ptr,
-                           uint64_t first_leaf, uint64_t P, uint32_t lf_log2) {
+                           uint64_t *__restrict__ piv, uint16_t *__restrict__ cnt, uint32_t *__restrict__ dead,
+                           uint32_t *__restrict__ row_ptr, uint64_t first_leaf, uint64_t P, uint32_t lf_log2) {
     uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (P << lf_log2)) return;
     uint64_t j = p >> lf_log2, o = p & ((1u << lf_log2) - 1);
@@ -619,6 +628,7 @@ __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t 
     uint64_t v = o < cj ? M[st + o] : kEmpty;
     slots[pos] = v;
     if (o == 0) {
+        piv[first_leaf + j] = v & ~kTomb;
         cnt[first_leaf + j] = (uint16_t)cj;
         if (dead) dead[first_leaf + j] = 0;
     }
@@ -706,28 +716,28 @@ void launch_append_guards(uint64_t *dst, uint32_t V, hipStream_t s) {
     hipLaunchKernelGGL(k_append_guards, dim3((uint32_t)div_up(V, 256)), dim3(256), 0, s, dst, V);
 }
 
-void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *slots,
-                   uint64_t L, uint32_t lf, const Ctl *ctl, uint32_t *leaf, uint8_t *status,
+void launch_locate(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *piv,
+                   uint64_t L, const Ctl *ctl, uint32_t *leaf, uint8_t *status,
                    hipStream_t s, const WinSrc *ws) {
     if (!n_max) return;
     const WinSrc w = ws ? *ws : WinSrc{};
     hipLaunchKernelGGL(k_locate, dim3((uint32_t)div_up(n_max, 256)), dim3(256), 0, s, keys, n_dev,
-                       n_max, slots, L, log2_u32(lf), ctl, leaf, status, w);
+                       n_max, piv, L, ctl, leaf, status, w);
 }
 
 template <int G, int SPL>
 static void leaf_merge_t(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
-                         const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
+                         const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint64_t *piv, uint16_t *cnt,
                          uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t min0, uint32_t max0,
                          Ctl *ctl, uint32_t *part, hipStream_t s) {
     constexpr int GPB = 256 / G;
     dim3 grid((uint32_t)div_up(n_max, GPB));
     if (del)
         hipLaunchKernelGGL((k_leaf_merge<G, SPL, true>), grid, dim3(256), 0, s, keys, leaf, status,
-                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl, part);
+                           n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, min0, max0, ctl, part);
     else
         hipLaunchKernelGGL((k_leaf_merge<G, SPL, false>), grid, dim3(256), 0, s, keys, leaf, status,
-                           n_dev, n_max, slots, cnt, row_ptr, deg, dead, min0, max0, ctl, part);
+                           n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, min0, max0, ctl, part);
 }
 
 // groups of one leaf merge launch: G = lf / SPL lanes each, 256 / G per block
@@ -743,30 +753,30 @@ static uint32_t leaf_group_lanes(uint32_t lf) {
 uint64_t leaf_merge_blocks(uint32_t lf, uint64_t n_max) { return div_up(n_max, 256 / leaf_group_lanes(lf)); }
 
 void launch_leaf_merge(bool del, const uint64_t *keys, const uint32_t *leaf, uint8_t *status,
-                       const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint16_t *cnt,
+                       const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint64_t *piv, uint16_t *cnt,
                        uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf, uint64_t min0,
                        uint64_t max0, Ctl *ctl, hipStream_t s, uint32_t *part) {
     if (!n_max) return;
     uint32_t mn = (uint32_t)min0, mx = (uint32_t)max0;
     switch (lf) {
-        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
-        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
-        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
-        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
-        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
-        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 16: leaf_merge_t<8, 2>(del, keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 32: leaf_merge_t<16, 2>(del, keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 64: leaf_merge_t<32, 2>(del, keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 128: leaf_merge_t<64, 2>(del, keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        case 256: leaf_merge_t<64, 4>(del, keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
+        default: leaf_merge_t<64, 8>(del, keys, leaf, status, n_dev, n_max, slots, piv, cnt, row_ptr, deg, dead, mn, mx, ctl, part, s); break;
     }
 }
 
 // ---- paired launches (the array at y = 0, its mirror at y = 1)
 
-void launch_locate2(uint64_t n_max, const uint64_t *const slots[2], const uint64_t L[2], uint32_t lf,
+void launch_locate2(uint64_t n_max, const uint64_t *const piv[2], const uint64_t L[2],
                     const Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2], const WinSrc ws[2],
                     hipStream_t s) {
     if (!n_max) return;
     LocateOp::Args a[2];
     for (int k = 0; k < 2; k++)
-        a[k] = {nullptr, nullptr, n_max, slots[k], L[k], log2_u32(lf), ctl[k], leaf[k], status[k], ws[k]};
+        a[k] = {nullptr, nullptr, n_max, piv[k], L[k], ctl[k], leaf[k], status[k], ws[k]};
     launch_pair<LocateOp, 256>((uint32_t)div_up(n_max, 256), a[0], a[1], s);
 }
 
@@ -780,13 +790,14 @@ static void leaf_merge2_t(bool del, const LeafMergeArgs (&a)[2], hipStream_t s) 
 
 void launch_leaf_merge2(bool del, const uint64_t *const keys[2], const uint32_t *const leaf[2],
                         uint8_t *const status[2], const uint32_t *const n_dev[2], uint64_t n_max,
-                        uint64_t *const slots[2], uint16_t *const cnt[2], uint32_t *const row_ptr[2],
-                        uint32_t *const deg[2], uint32_t *const dead[2], uint32_t lf, const uint64_t min0[2],
-                        const uint64_t max0[2], Ctl *const ctl[2], uint32_t *const part[2], hipStream_t s) {
+                        uint64_t *const slots[2], uint64_t *const piv[2], uint16_t *const cnt[2],
+                        uint32_t *const row_ptr[2], uint32_t *const deg[2], uint32_t *const dead[2], uint32_t lf,
+                        const uint64_t min0[2], const uint64_t max0[2], Ctl *const ctl[2], uint32_t *const part[2],
+                        hipStream_t s) {
     if (!n_max) return;
     LeafMergeArgs a[2];
     for (int k = 0; k < 2; k++)
-        a[k] = {keys[k], leaf[k], status[k], n_dev[k], n_max, slots[k], cnt[k], row_ptr[k], deg[k], dead[k],
+        a[k] = {keys[k], leaf[k], status[k], n_dev[k], n_max, slots[k], piv[k], cnt[k], row_ptr[k], deg[k], dead[k],
                 (uint32_t)min0[k], (uint32_t)max0[k], ctl[k], part[k]};
     switch (lf) {
         case 16: leaf_merge2_t<8, 2>(del, a, s); break;
@@ -824,7 +835,7 @@ size_t seg_merge_lds_bytes(uint32_t lf, uint32_t h) {
 }
 
 void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t *leaf,
-                      uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots,
+                      uint8_t *status, const uint32_t *n_dev, uint64_t n_max, uint64_t *slots, uint64_t *piv,
                       uint16_t *cnt, uint32_t *row_ptr, uint32_t *deg, uint32_t *dead, uint32_t lf,
                       uint64_t minh, uint64_t maxh, Ctl *ctl, hipStream_t s) {
     if (!n_max) return;
@@ -832,11 +843,11 @@ void launch_seg_merge(bool del, uint32_t h, const uint64_t *keys, const uint32_t
     const uint32_t grid = (uint32_t)(n_max < 512 ? n_max : 512);   // grid-stride over segments
     if (del)
         hipLaunchKernelGGL(k_seg_merge<true>, dim3(grid), dim3(kSegThreads), lds, s, h,
-                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, dead, log2_u32(lf), minh,
+                           keys, leaf, status, n_dev, slots, piv, cnt, row_ptr, deg, dead, log2_u32(lf), minh,
                            maxh, ctl);
     else
         hipLaunchKernelGGL(k_seg_merge<false>, dim3(grid), dim3(kSegThreads), lds, s, h,
-                           keys, leaf, status, n_dev, slots, cnt, row_ptr, deg, dead, log2_u32(lf), minh,
+                           keys, leaf, status, n_dev, slots, piv, cnt, row_ptr, deg, dead, log2_u32(lf), minh,
                            maxh, ctl);
 }
 
@@ -876,10 +887,10 @@ void launch_merge_sorted(bool del, const uint64_t *A, uint64_t na, const uint64_
                            k, out);
 }
 
-void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint16_t *cnt, uint32_t *dead,
+void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint64_t *piv, uint16_t *cnt, uint32_t *dead,
                      uint32_t *row_ptr, uint64_t first_leaf, uint64_t P, uint32_t lf, hipStream_t s) {
     uint64_t total = P * lf;
-    hipLaunchKernelGGL(k_dispatch, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, M, N, slots,
+    hipLaunchKernelGGL(k_dispatch, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, M, N, slots, piv,
                        cnt, dead, row_ptr, first_leaf, P, log2_u32(lf));
 }
 

@@ -139,6 +139,7 @@ def load_library() -> C.CDLL:
         "gpma_export_slots": (C.c_int, [vp, vp, u64, pu64, vp]),
         "gpma_export_keys": (C.c_int, [vp, vp, u64, pu64, vp]),
         "gpma_export_leaf_counts": (C.c_int, [vp, vp, u64, vp]),
+        "gpma_export_pivots": (C.c_int, [vp, vp, u64, vp]),
         "gpma_export_row_offsets": (C.c_int, [vp, vp, u64, vp]),
         "gpma_export_degrees": (C.c_int, [vp, vp, u64, vp]),
         "gpma_sync": (C.c_int, [vp]),
@@ -175,7 +176,7 @@ def exported_symbols() -> List[str]:
     return ["gpma_default_params", "gpma_create", "gpma_destroy", "gpma_insert_batch",
             "gpma_delete_batch", "gpma_pagerank", "gpma_bfs", "gpma_bfs_noalloc", "gpma_cc", "gpma_num_edges",
             "gpma_capacity", "gpma_leaf_size", "gpma_num_vertices", "gpma_export_slots",
-            "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_row_offsets",
+            "gpma_export_keys", "gpma_export_leaf_counts", "gpma_export_pivots", "gpma_export_row_offsets",
             "gpma_export_degrees", "gpma_sync", "gpma_get_mirror", "gpma_apply_batches", "gpma_strerror",
             "gpma_snapshot", "gpma_snapshot_refresh", "gpma_device_bytes", "gpma_locate",
             "gpma_locator_refit", "gpma_locator_info",
@@ -376,6 +377,14 @@ class _HandleView:
         out = torch.empty(self.capacity // self.leaf_size, dtype=torch.int16, device="cuda")
         _check(self._lib.gpma_export_leaf_counts(self.h, C.c_void_p(out.data_ptr()), out.numel(),
                                                  _stream(stream)), "gpma_export_leaf_counts")
+        return out
+
+    def pivots(self, stream=None) -> torch.Tensor:
+        """Each leaf's first slot with the deletion mark cleared (int64 bit
+        patterns), the array the locate searches."""
+        out = torch.empty(self.capacity // self.leaf_size, dtype=torch.int64, device="cuda")
+        _check(self._lib.gpma_export_pivots(self.h, C.c_void_p(out.data_ptr()), out.numel(),
+                                            _stream(stream)), "gpma_export_pivots")
         return out
 
     def row_offsets(self, stream=None) -> torch.Tensor:

@@ -82,6 +82,7 @@ def test_fullsize_rmat24_bench_configuration():
     O.check_invariants(slots, g.leaf_size, V)
     assert np.array_equal(g.row_offsets().cpu().numpy().astype(np.int64), O.row_offsets(slots, V))
     assert np.array_equal(g.leaf_counts().cpu().numpy().astype(np.int64), O.leaf_counts(slots, g.leaf_size))
+    assert np.array_equal(g.pivots().cpu().numpy().view(np.uint64), O.leaf_pivots(slots, g.leaf_size))
     del slots
     say("PageRank")
     x0 = torch.rand(V, device="cuda", dtype=torch.float32) + 0.1

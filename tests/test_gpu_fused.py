@@ -26,6 +26,13 @@ def npu64(t):
     return t.cpu().numpy().view(np.uint64)
 
 
+def check_pivots(g):
+    """The locate's pivot array equals each leaf's first slot, mark cleared
+    (array and mirror)."""
+    for h in ((g, g.mirror()) if g.mirror() is not None else (g,)):
+        assert np.array_equal(npu64(h.pivots()), O.leaf_pivots(npu64(h.slots()), h.leaf_size))
+
+
 def make_sequence(V, live, n, seed):
     """n uneven batches (sizes log-uniform 2^3..2^12): inserts of random keys,
     deletes of live keys plus absent ones; one sorted run and one large
@@ -87,6 +94,7 @@ def test_fused_equals_plain(mirror, direct, tile, levels):
         st = fused.apply_batches(ops[lo:hi], [dev(b) for b in bs[lo:hi]])
         assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
         assert np.array_equal(npu64(fused.slots()), ref.slots())
+        check_pivots(fused)
         assert fused.num_edges == plain.num_edges
         assert np.array_equal(fused.degrees().cpu().numpy(), plain.degrees().cpu().numpy())
         assert np.array_equal(fused.row_offsets().cpu().numpy(), plain.row_offsets().cpu().numpy())
@@ -290,6 +298,7 @@ def test_window_sorts_agree_with_the_oracle(kind, window_sort):
             applied += ref.last_applied()
         assert st.applied == applied, (kind, window_sort, lo, hi)
         assert np.array_equal(npu64(g.slots()), ref.slots()), (kind, window_sort, lo, hi)
+        check_pivots(g)
         if mirror:
             k = g.keys()
             tr = ((k & 0xFFFFFFFF) << 32) | (k >> 32)
@@ -321,6 +330,7 @@ def test_paired_windows_equal_plain(learned, lazy):
         st = fused.apply_batches(ops[lo:hi], [dev(b) for b in bs[lo:hi]])
         assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
         assert np.array_equal(npu64(fused.mirror().slots()), npu64(plain.mirror().slots())), (lo, hi)
+        check_pivots(fused)
         assert fused.num_edges == plain.num_edges
         assert np.array_equal(fused.degrees().cpu().numpy(), plain.degrees().cpu().numpy())
     if not lazy:

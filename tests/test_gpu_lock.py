@@ -36,6 +36,7 @@ def check(g, live: set, V: int):
     edges = O.edge_keys(slots)
     assert np.array_equal(edges, np.array(sorted(live), dtype=np.uint64))
     assert np.array_equal(g.leaf_counts().cpu().numpy().astype(np.int64), O.leaf_counts(slots, lf))
+    assert np.array_equal(npu64(g.pivots()), O.leaf_pivots(slots, lf))
     assert np.array_equal(g.row_offsets().cpu().numpy().astype(np.int64), O.row_offsets(slots, V))
     assert np.array_equal(g.degrees().cpu().numpy().astype(np.int64), O.out_degrees(edges, V))
     assert g.num_edges == len(live)

@@ -46,6 +46,7 @@ def check_state(g, ref, V):
                              % (bad.size, bad[:5], slots[bad[0]], want[bad[0]]))
     lf = g.leaf_size
     assert np.array_equal(g.leaf_counts().cpu().numpy().astype(np.int64), O.leaf_counts(want, lf))
+    assert np.array_equal(npu64(g.pivots()), O.leaf_pivots(want, lf))
     assert np.array_equal(g.row_offsets().cpu().numpy().astype(np.int64), O.row_offsets(want, V))
     edges = O.edge_keys(want)
     assert np.array_equal(g.degrees().cpu().numpy().astype(np.int64), O.out_degrees(edges, V))

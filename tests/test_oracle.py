@@ -197,6 +197,34 @@ def test_even_dispatch_counts_closed_form():
         O.check_invariants(s, lf, allow_empty_leaves=True)
 
 
+def test_leaf_pivots_are_leaf_minima_and_locate_by_them():
+    """A leaf's pivot is the smallest key it holds (marked entries by their
+    key), so the pivots ascend, and the predecessor-leaf rule (Example 3:
+    the leaf holding the greatest stored key <= k, leaf 0 if none) is a
+    search over them: checked by brute force over every leaf for keys
+    below, between and above the stored ones, after lazy marks."""
+    rng = np.random.default_rng(11)
+    lf, V = 8, 40
+    keys = np.unique(rng.integers(0, V, 300).astype(np.uint64) << np.uint64(32)
+                     | rng.integers(0, V, 300).astype(np.uint64))
+    p = O.OraclePMA(V, keys, lf, lazy=True)
+    p.delete(keys[::3])
+    s = p.slots()
+    piv = O.leaf_pivots(s, lf)
+    leaves = s.reshape(-1, lf)
+    for j in range(leaves.shape[0]):
+        occ = leaves[j][leaves[j] != O.EMPTY] & ~O.TOMB
+        assert occ.size and piv[j] == occ.min()
+    assert np.all(piv[1:] > piv[:-1])
+    occ_all = O.occupied(s)
+    for k in np.concatenate([occ_all, occ_all + np.uint64(1), [np.uint64(0)]]):
+        owner = [j for j in range(leaves.shape[0])
+                 if np.any((leaves[j] != O.EMPTY) & ((leaves[j] & ~O.TOMB) <= k))]
+        want = max(owner) if owner else 0
+        got = max(int(np.searchsorted(piv, k, side="right")) - 1, 0)
+        assert got == want, k
+
+
 def test_eager_mode_keeps_keys_with_the_top_bit():
     """Bit 63 marks a lazily deleted entry only in lazy mode; an eager array
     of raw keys stores, merges and deletes keys >= 2^63 like any other, and
