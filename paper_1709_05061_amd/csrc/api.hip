@@ -173,6 +173,7 @@ struct gpma {
     LocModel loc_h{};              // host copy
     double *loc_gram = nullptr;    // device fp64 normal equations
     uint32_t *loc_err = nullptr;   // device
+    uint32_t *loc_row_eps = nullptr;   // device, V: each row's leaf error bound
     uint32_t batches_since_fit = 0;
     uint64_t loc_lookups = 0, loc_misses = 0, loc_fits = 0;
     uint64_t acc_lookups = 0, acc_misses = 0;   // fused batches since the last check
@@ -631,8 +632,8 @@ int device_tier_level(gpma *g, bool del, uint32_t h, const LevelArrays &c, uint6
 void do_locate(gpma *g, const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, uint32_t *leaf,
                uint8_t *status, hipStream_t s, const WinSrc *ws = nullptr) {
     if (g->learned && g->loc)
-        launch_locate_learned(keys, n_dev, n_max, g->piv, g->row_ptr, g->L, g->lf_log2, g->loc, g->ctl, leaf,
-                              status, &g->ctl->misses, s, ws);
+        launch_locate_learned(keys, n_dev, n_max, g->piv, g->row_ptr, g->loc_row_eps, g->L, g->lf_log2, g->loc,
+                              g->ctl, leaf, status, &g->ctl->misses, s, ws);
     else
         launch_locate(keys, n_dev, n_max, g->piv, g->L, g->ctl, leaf, status, s, ws);
 }
@@ -683,7 +684,8 @@ int locator_fit(gpma *g, hipStream_t s) {
         int e = GPMA_OK;
         e |= dev_alloc(g, &g->loc, 1);
         e |= dev_alloc(g, &g->loc_gram, loc_gram_words());
-        e |= dev_alloc(g, &g->loc_err, 2);
+        e |= dev_alloc(g, &g->loc_err, 1);
+        e |= dev_alloc(g, &g->loc_row_eps, g->V);
         if (e) return GPMA_ENOMEM;
     }
     const uint64_t L = g->L;
@@ -730,16 +732,15 @@ int locator_fit(gpma *g, hipStream_t s) {
         }
     }
     m.eps = 0;
-    m.delta = 0.f;
     m.valid = 0;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
-    hipMemsetAsync(g->loc_err, 0, 2 * sizeof(uint32_t), s);
-    launch_loc_eval(g->piv, g->row_ptr, L, g->lf_log2, g->loc, g->loc_err, s);
-    uint32_t err[2] = {0, 0};
-    hipMemcpyAsync(err, g->loc_err, sizeof(err), hipMemcpyDeviceToHost, s);
+    hipMemsetAsync(g->loc_err, 0, sizeof(uint32_t), s);
+    hipMemsetAsync(g->loc_row_eps, 0, (uint64_t)g->V * sizeof(uint32_t), s);
+    launch_loc_eval(g->piv, g->row_ptr, L, g->lf_log2, g->loc, g->loc_err, g->loc_row_eps, s);
+    uint32_t err = 0;
+    hipMemcpyAsync(&err, g->loc_err, sizeof(err), hipMemcpyDeviceToHost, s);
     hipStreamSynchronize(s);
-    m.eps = err[0];
-    memcpy(&m.delta, &err[1], sizeof(float));
+    m.eps = err;
     m.valid = 1;
     hipMemcpyAsync(g->loc, &m, sizeof(m), hipMemcpyHostToDevice, s);
     hipStreamSynchronize(s);
@@ -930,7 +931,7 @@ int apply_batch(gpma *g, const uint64_t *keys, uint64_t b, bool del, hipStream_t
 void free_all(gpma *g) {
     release_pool(g);
     free_batch(g);
-    dev_free(g, g->loc); dev_free(g, g->loc_gram); dev_free(g, g->loc_err);
+    dev_free(g, g->loc); dev_free(g, g->loc_gram); dev_free(g, g->loc_err); dev_free(g, g->loc_row_eps);
     dev_free(g, g->tkeys);
     dev_free(g, g->fblk); dev_free(g, g->desc);
     g->fs = nullptr;
@@ -1216,7 +1217,7 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
     WinSrc ws[2];
     const uint64_t *piv_c[2], *keys_c[2];
     uint64_t *slots[2], *piv[2], L[2], lo[2], hi[2];
-    const uint32_t *row_ptr_c[2], *leaf_c[2], *nd[2];
+    const uint32_t *row_ptr_c[2], *reps[2], *leaf_c[2], *nd[2];
     uint32_t *leaf[2], *misses[2], *row_ptr[2], *deg[2], *dead[2], *part[2], *stop[2];
     uint8_t *status[2];
     uint16_t *cnt[2];
@@ -1238,6 +1239,7 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
         bounds(x, x->H, 0, &lo[k], &hi[k]);
         row_ptr[k] = x->row_ptr;
         row_ptr_c[k] = x->row_ptr;
+        reps[k] = x->loc_row_eps;
         leaf[k] = x->leafA;
         leaf_c[k] = x->leafA;
         status[k] = x->stA;
@@ -1256,7 +1258,8 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
         outs[k] = x->outs;
     }
     if (g->learned && g->loc)
-        launch_locate_learned2(cls, piv_c, row_ptr_c, L, g->lf_log2, model, ctl_c, leaf, status, misses, ws, s);
+        launch_locate_learned2(cls, piv_c, row_ptr_c, reps, L, g->lf_log2, model, ctl_c, leaf, status, misses, ws,
+                               s);
     else
         launch_locate2(cls, piv_c, L, ctl_c, leaf, status, ws, s);
     launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, piv, cnt, row_ptr, deg, dead, g->lf, lo, hi, ctl,

@@ -17,11 +17,15 @@
 // activations split into a bf16 high part and a bf16 low part (two MFMAs),
 // which keeps about 16 bits of each activation.
 //
-// The bound delta (in fractions of a span) is measured over every long-row
-// leaf pivot with this same code; a lookup searches the window of
-// delta*span + 1 leaves around the prediction, checks that the window
-// brackets the key (pivot[lo] <= k < pivot[hi+1]) and otherwise falls back
-// to a binary search over the whole span.
+// Error bounds are kept per row: row_eps[u] is the largest leaf error over
+// row u's pivots, measured at the fit with this same code.  A lookup
+// searches the window of e + e/4 + 2 leaves (e = row_eps[u]) on either side
+// of the prediction, the slack absorbing merges since the fit.  The search
+// runs over the window and the leaf past it, so it also tells whether the
+// window brackets the key (pivot[lo] <= k < pivot[hi+1]); when it does not,
+// a binary search over the whole span takes over.  One bound per row rather
+// than one for the array keeps the windows of the long rows, where the model
+// fits well, from taking the width the worst row needs.
 #include "common.h"
 #include "locator.h"
 #include "pair.h"
@@ -45,6 +49,15 @@ __device__ __forceinline__ void key_features(uint64_t k, float inv_v, float inv_
     const uint32_t src = (uint32_t)(k >> 32), dst = (uint32_t)k;
     x = (float)src * inv_v;
     y = (float)(dst == kGuardDst ? V : dst) * inv_v1;
+}
+
+// The model, copied into LDS by the whole block (lanes index its weights by
+// their quad, which a register copy could only serve from scratch memory).
+__device__ __forceinline__ void stage_model(const LocModel *__restrict__ model, LocModel *s_m) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(model);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(s_m);
+    for (uint32_t t = threadIdx.x; t < sizeof(LocModel) / 4; t += blockDim.x) dst[t] = src[t];
+    __syncthreads();
 }
 
 // Positions of the 64 keys kq[lane] of a wave (every lane active).  Lane l
@@ -139,6 +152,7 @@ struct LocateLearnedOp {
         uint64_t n_max;
         const uint64_t *piv;
         const uint32_t *row_ptr;
+        const uint32_t *row_eps;
         uint64_t L;
         uint32_t lf_log2;
         const LocModel *model;
@@ -154,6 +168,7 @@ struct LocateLearnedOp {
         uint64_t n_max = args.n_max;
         const uint64_t *__restrict__ piv = args.piv;
         const uint32_t *__restrict__ row_ptr = args.row_ptr;
+        const uint32_t *__restrict__ row_eps = args.row_eps;
         uint64_t L = args.L;
         uint32_t lf_log2 = args.lf_log2;
         const LocModel *__restrict__ model = args.model;
@@ -163,14 +178,17 @@ struct LocateLearnedOp {
         uint32_t * misses = args.misses;
         WinSrc ws = args.ws;
         __shared__ float s_out[256];
-        const LocModel m = *model;
+        __shared__ LocModel s_m;
         const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
         const BatchView bv = batch_view(ws, keys, n_dev, n_max, ctl);
         const uint64_t n = bv.n;
         if ((uint64_t)blockIdx.x * blockDim.x >= n || bv.err) return;   // block-uniform
+        stage_model(model, &s_m);
+        const LocModel &m = s_m;
         const bool active = i < n;
         const uint64_t k = active ? (bv.keys[i] & bv.mask) : 0;
         if (active && ws.ukeys) ws.dense[i] = k;
+        const uint32_t re = row_eps[key_src(k)];   // issued beside the row offsets
         const Span sp = row_span(row_ptr, key_src(k), lf_log2);
         const uint64_t span = sp.last - sp.first + 1;
         // the model runs (wave-wide, on MFMA) only for waves with a key in a
@@ -184,13 +202,21 @@ struct LocateLearnedOp {
             j = search_range(piv, sp.first, sp.last, k);
         } else {
             const uint64_t p = predict_in_span(t, sp);
-            const uint64_t e = (uint64_t)(m.delta * (float)span) + 2;
+            const uint64_t e = (uint64_t)re + (re >> 2) + 2;
             const uint64_t lo = p > sp.first + e ? p - e : sp.first;
             const uint64_t hi = p + e < sp.last ? p + e : sp.last;
-            const bool ok_lo = lo == sp.first || pivot(piv, lo) <= k;
-            const bool ok_hi = hi == sp.last || pivot(piv, hi + 1) > k;
-            if (m.valid && m.L == L && ok_lo && ok_hi) {
-                j = search_range(piv, lo, hi, k);
+            // count the pivots <= k over leaves lo .. top (the window and the
+            // leaf past it, inside the span)
+            const uint64_t top = hi < sp.last ? hi + 1 : hi;
+            uint64_t a = lo, b = top + 1;
+            while (a < b) {
+                const uint64_t mid = (a + b) >> 1;
+                if (pivot(piv, mid) <= k) a = mid + 1; else b = mid;
+            }
+            const bool below = a == lo && lo > sp.first;   // pivot[lo] > k
+            const bool above = a == top + 1 && top > hi;    // pivot[hi+1] <= k
+            if (m.valid && m.L == L && !below && !above) {
+                j = a > lo ? a - 1 : lo;
             } else {
                 j = search_range(piv, sp.first, sp.last, k);
                 atomicAdd(misses, 1u);
@@ -203,11 +229,12 @@ struct LocateLearnedOp {
 
 __global__ void __launch_bounds__(256)
 k_locate_learned(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-                 const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_ptr, uint64_t L,
-                 uint32_t lf_log2, const LocModel *__restrict__ model, const Ctl *ctl,
-                 uint32_t *__restrict__ leaf, uint8_t *__restrict__ status, uint32_t *misses, WinSrc ws) {
-    LocateLearnedOp::run(LocateLearnedOp::Args{keys, n_dev, n_max, piv, row_ptr, L, lf_log2, model, ctl, leaf,
-        status, misses, ws});
+                 const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_ptr,
+                 const uint32_t *__restrict__ row_eps, uint64_t L, uint32_t lf_log2,
+                 const LocModel *__restrict__ model, const Ctl *ctl, uint32_t *__restrict__ leaf,
+                 uint8_t *__restrict__ status, uint32_t *misses, WinSrc ws) {
+    LocateLearnedOp::run(LocateLearnedOp::Args{keys, n_dev, n_max, piv, row_ptr, row_eps, L, lf_log2, model, ctl,
+        leaf, status, misses, ws});
 }
 
 // Fit: sampled pivots, their features and the fp64 normal equations.  Each
@@ -264,43 +291,53 @@ k_loc_gram(const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_pt
     }
 }
 
-// Error bounds over every long-row leaf pivot: the largest leaf error and the
-// largest error of t against the pivot's fraction of its span.
+// Error bounds over every long-row leaf pivot: the largest leaf error of
+// each row (row_eps) and of the array (*err).  A wave's pivots are
+// consecutive leaves, so lanes of one row are adjacent: a segmented max
+// leaves each row's largest at its first lane, which alone takes the atomic.
 __global__ void __launch_bounds__(256)
 k_loc_eval(const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_ptr, uint64_t L, uint32_t lf_log2,
-           const LocModel *__restrict__ model, uint32_t *__restrict__ err) {
+           const LocModel *__restrict__ model, uint32_t *__restrict__ err, uint32_t *__restrict__ row_eps) {
     __shared__ float s_out[256];
-    const LocModel m = *model;
+    __shared__ LocModel s_m;
+    stage_model(model, &s_m);
+    const LocModel &m = s_m;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t lane = __lane_id();
     uint32_t worst = 0;
-    float worst_f = 0.f;
     // the loop bound is wave-uniform (L is a multiple of 64 or the wave is the last)
     for (uint64_t j0 = (uint64_t)blockIdx.x * blockDim.x; j0 < L; j0 += stride) {
         const uint64_t j = j0 + threadIdx.x;
         const uint64_t k = j < L ? pivot(piv, j) : 0;
         const float t = model_position(m, k, s_out + (threadIdx.x & ~63u));
+        uint32_t d = 0;
+        bool use = false;
         if (j < L && !is_guard(k)) {
             const Span sp = row_span(row_ptr, key_src(k), lf_log2);
-            const uint64_t span = sp.last - sp.first + 1;
-            if (span > kMinSpan) {
+            if (sp.last - sp.first + 1 > kMinSpan) {
                 const uint64_t p = predict_in_span(t, sp);
-                const uint64_t d = p > j ? p - j : j - p;
-                worst = d > worst ? (uint32_t)d : worst;
-                const float fe = fabsf(t - (float)(((double)(j - sp.first) + 0.5) / (double)span));
-                worst_f = fe > worst_f ? fe : worst_f;
+                const uint64_t dd = p > j ? p - j : j - p;
+                d = dd > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)dd;
+                use = true;
             }
         }
+        worst = d > worst ? d : worst;
+        // rows of the lanes that measured one (others take a row no lane has)
+        const uint32_t u = use ? key_src(k) : 0xFFFFFFFFu;
+#pragma unroll
+        for (int w = 1; w < kWave; w <<= 1) {
+            const uint32_t od = __shfl_down(d, w, kWave);
+            const uint32_t ou = __shfl_down(u, w, kWave);
+            if (lane + w < (uint32_t)kWave && ou == u && od > d) d = od;
+        }
+        const uint32_t pu = __shfl_up(u, 1, kWave);
+        if (use && (lane == 0 || pu != u)) atomicMax(&row_eps[u], d);
     }
     for (int d = kWave / 2; d >= 1; d >>= 1) {
         const uint32_t o = __shfl_xor(worst, d, kWave);
         worst = o > worst ? o : worst;
-        const float of = __shfl_xor(worst_f, d, kWave);
-        worst_f = of > worst_f ? of : worst_f;
     }
-    if (__lane_id() == 0) {
-        atomicMax(&err[0], worst);
-        atomicMax(&err[1], __float_as_uint(worst_f));   // non-negative floats order as their bits
-    }
+    if (lane == 0) atomicMax(err, worst);
 }
 
 }  // namespace
@@ -308,13 +345,14 @@ k_loc_eval(const uint64_t *__restrict__ piv, const uint32_t *__restrict__ row_pt
 namespace gpma_host {
 
 void launch_locate_learned(const uint64_t *keys, const uint32_t *n_dev, uint64_t n_max, const uint64_t *piv,
-                           const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2, const LocModel *model,
+                           const uint32_t *row_ptr, const uint32_t *row_eps, uint64_t L, uint32_t lf_log2,
+                           const LocModel *model,
                            const Ctl *ctl, uint32_t *leaf, uint8_t *status, uint32_t *misses, hipStream_t s,
                            const WinSrc *ws) {
     if (!n_max) return;
     const WinSrc w = ws ? *ws : WinSrc{};
     hipLaunchKernelGGL(k_locate_learned, dim3((uint32_t)((n_max + 255) / 256)), dim3(256), 0, s, keys, n_dev,
-                       n_max, piv, row_ptr, L, lf_log2, model, ctl, leaf, status, misses, w);
+                       n_max, piv, row_ptr, row_eps, L, lf_log2, model, ctl, leaf, status, misses, w);
 }
 
 size_t loc_gram_words() { return kGram; }
@@ -328,20 +366,22 @@ void launch_loc_gram(const uint64_t *piv, const uint32_t *row_ptr, uint64_t L, u
 }
 
 void launch_loc_eval(const uint64_t *piv, const uint32_t *row_ptr, uint64_t L, uint32_t lf_log2,
-                     const LocModel *model, uint32_t *err, hipStream_t s) {
+                     const LocModel *model, uint32_t *err, uint32_t *row_eps, hipStream_t s) {
     uint64_t blocks = (L + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, piv, row_ptr, L, lf_log2, model, err);
+    hipLaunchKernelGGL(k_loc_eval, dim3((uint32_t)blocks), dim3(256), 0, s, piv, row_ptr, L, lf_log2, model, err,
+                       row_eps);
 }
 
 void launch_locate_learned2(uint64_t n_max, const uint64_t *const piv[2], const uint32_t *const row_ptr[2],
+                            const uint32_t *const row_eps[2],
                             const uint64_t L[2], uint32_t lf_log2, const LocModel *const model[2],
                             const Ctl *const ctl[2], uint32_t *const leaf[2], uint8_t *const status[2],
                             uint32_t *const misses[2], const WinSrc ws[2], hipStream_t s) {
     if (!n_max) return;
     LocateLearnedOp::Args a[2];
     for (int k = 0; k < 2; k++)
-        a[k] = {nullptr, nullptr, n_max, piv[k], row_ptr[k], L[k], lf_log2, model[k], ctl[k], leaf[k], status[k],
+        a[k] = {nullptr, nullptr, n_max, piv[k], row_ptr[k], row_eps[k], L[k], lf_log2, model[k], ctl[k], leaf[k], status[k],
                 misses[k], ws[k]};
     launch_pair<LocateLearnedOp, 256>((uint32_t)((n_max + 255) / 256), a[0], a[1], s);
 }
