@@ -151,6 +151,68 @@ struct RunStats {
     uint32_t done, noop, head, pend;
 };
 
+// A run of one update into a leaf holding no marked entries (at 2^16 updates
+// over 2^24 leaves almost every run), done in registers: the update's rank
+// comes from two ballots per slot column, and the entries from that rank on
+// shift one place (insert: right, delete: left), each lane taking its
+// neighbour's boundary entry by a shuffle.  Only the shifted slots are
+// written; the rest of the leaf, the pivot (unless slot 0 moved) and the
+// row offsets of guards that stay put are unchanged.  The outcome is the
+// general run merge's for a run of one.
+template <int G, int SPL, bool DEL>
+__device__ __forceinline__ RunStats
+leaf_single(uint64_t key, uint32_t i, uint32_t lf_i, uint32_t c, const uint64_t (&mine)[SPL], uint32_t gl,
+            uint8_t *__restrict__ status, uint64_t *__restrict__ slots, uint64_t *__restrict__ piv,
+            uint16_t *__restrict__ cnt, uint32_t *__restrict__ row_ptr, uint32_t *__restrict__ deg, uint32_t min0,
+            uint32_t max0) {
+    constexpr uint32_t LF = G * SPL;
+    const uint32_t gbase = __lane_id() & ~(uint32_t)(G - 1);
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << G) - 1);
+    uint32_t below = 0;   // entries < key
+    bool present = false;
+#pragma unroll
+    for (int q = 0; q < SPL; q++) {
+        const uint32_t x = gl * SPL + q;
+        below += (uint32_t)__popcll((__ballot(x < c && mine[q] < key) >> gbase) & gmask);
+        present |= ((__ballot(x < c && mine[q] == key) >> gbase) & gmask) != 0;
+    }
+    RunStats rs{0, 0, 0, 0};
+    if (DEL ? !present : present) {
+        if (gl == 0) status[i] = kNoop;
+        rs.noop = 1;
+        return rs;
+    }
+    if (DEL ? (c < 1 + min0) : (c + 1 > max0)) {   // the leaf fails its bound
+        if (gl == 0) status[i] = kPending;
+        rs.pend = 1;
+        return rs;
+    }
+    const uint32_t N = DEL ? c - 1 : c + 1;
+    const uint32_t end = DEL ? c : N;   // slots below .. end-1 change
+    const uint64_t base = (uint64_t)lf_i * LF;
+    const uint64_t prev = __shfl_up(mine[SPL - 1], 1, G);   // the entry before the lane's first
+    const uint64_t next = __shfl_down(mine[0], 1, G);       // the entry after the lane's last
+#pragma unroll
+    for (int q = 0; q < SPL; q++) {
+        const uint32_t x = gl * SPL + q;
+        if (x < below || x >= end) continue;
+        uint64_t v;
+        if (DEL) v = x + 1 < c ? (q + 1 < SPL ? mine[q + 1] : next) : kEmpty;
+        else v = x == below ? key : (q > 0 ? mine[q - 1] : prev);
+        slots[base + x] = v;
+        if (x == 0) piv[lf_i] = v & ~kTomb;
+        if (x < N && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(base + x + 1);
+    }
+    if (gl == 0) {
+        cnt[lf_i] = (uint16_t)N;
+        status[i] = (uint8_t)(kDone | kHead);
+        atomicAdd(&deg[key_src(key)], DEL ? 0xFFFFFFFFu : 1u);
+    }
+    rs.done = 1;
+    rs.head = 1;
+    return rs;
+}
+
 template <int G, int SPL, bool DEL>
 __device__ __forceinline__ RunStats
 leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
@@ -181,7 +243,11 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
 #pragma unroll
     for (int q = 0; q < SPL; q++) mine[q] = slots[base + gl * SPL + q];
     uint32_t c = cnt[lf_i];
-    if (dead && dead[lf_i]) {
+    const bool marked = dead && dead[lf_i];
+    if (k == 1 && !marked)
+        return leaf_single<G, SPL, DEL>(__shfl(kpre, 0, G), i, lf_i, c, mine, gl, status, slots, piv, cnt, row_ptr,
+                                        deg, min0, max0);
+    if (marked) {
         // the leaf holds marked entries: stage its live entries only, packed
         // in order (the merge below drops the marked ones)
         uint32_t nl = 0;
