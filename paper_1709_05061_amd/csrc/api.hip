@@ -1048,14 +1048,18 @@ void enqueue_window_prefix(gpma *g, uint32_t w, uint64_t n_max, const BatchDesc 
                            bool transpose, hipStream_t s) {
     const uint32_t sb = bit_width(g->V - 1);
     const uint32_t tb = window_tag_bits(g);
-    launch_window_fetch(desc, g->fs, stop, w, n_max, g->V, sb, transpose, g->kS, g->wcount, g->werrs, s);
-    // both sorts leave the keys in the same buffer (fixed by the bit count)
+    launch_window_fetch(desc, g->fs, stop, w, n_max, g->V, sb, transpose, g->kS, g->wcount, g->werrs, g->ustart, s);
+    // both sorts leave the keys in the same buffer (fixed by the bit count);
+    // the splitter sort's first launch also advances the window generation
+    // and zeroes the locate's miss count, the radix sort leaves that to
+    // launch_window_starts
+    const bool splitter = !g->window_radix && splitter_sort_fits(n_max);
     const uint64_t *sorted =
-        (!g->window_radix && splitter_sort_fits(n_max))
-            ? splitter_sort_keys(g->kS, n_max, g->wcount, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s)
-            : radix_sort_keys(g->kS, n_max, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s, g->wcount, nullptr,
-                              g->sort_chunks);
-    launch_window_starts(sorted, g->wcount, w, sb, g->ustart, g->fs, g->ctl, s);
+        splitter ? splitter_sort_keys(g->kS, n_max, g->wcount, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s,
+                                      &g->fs->gen, &g->ctl->misses)
+                 : radix_sort_keys(g->kS, n_max, sb + tb, sb, g->V, g->kA, g->kB, g->tmp, s, g->wcount, nullptr,
+                                   g->sort_chunks);
+    if (!splitter) launch_window_starts(sorted, g->wcount, w, sb, g->ustart, g->fs, g->ctl, s);
     g->wukeys = const_cast<uint64_t *>(sorted);   // the same buffer for every window (fixed pass count)
 }
 
@@ -1191,23 +1195,16 @@ void enqueue_window_prefix2(gpma *g, gpma *m, uint32_t w, uint64_t n_max, const 
     uint64_t *kS[2] = {g->kS, m->kS};
     uint32_t *wcount[2] = {g->wcount, m->wcount};
     uint32_t *errs[2] = {g->werrs, m->werrs};
-    launch_window_fetch2(desc, st, stop, w, n_max, g->V, sb, kS, wcount, errs, s);
+    uint32_t *ustart[2] = {g->ustart, m->ustart};
+    uint32_t *gen[2] = {&g->fs->gen, &m->fs->gen};
+    uint32_t *misses[2] = {&g->ctl->misses, &m->ctl->misses};
+    launch_window_fetch2(desc, st, stop, w, n_max, g->V, sb, kS, wcount, errs, ustart, s);
     const uint64_t *in[2] = {g->kS, m->kS};
     const uint32_t *nd[2] = {g->wcount, m->wcount};
     uint64_t *ba[2] = {g->kA, m->kA}, *bb[2] = {g->kB, m->kB};
     uint32_t *tmp[2] = {g->tmp, m->tmp};
-    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s);
-    const uint64_t *sorted[2];
-    uint32_t *ustart[2];
-    Ctl *ctl[2];
-    for (int k = 0; k < 2; k++) {
-        uint64_t *out = which ? h[k]->kB : h[k]->kA;
-        sorted[k] = out;
-        ustart[k] = h[k]->ustart;
-        ctl[k] = h[k]->ctl;
-        h[k]->wukeys = out;
-    }
-    launch_window_starts2(sorted, nd, w, sb, ustart, st, ctl, s);
+    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s, gen, misses);
+    for (int k = 0; k < 2; k++) h[k]->wukeys = which ? h[k]->kB : h[k]->kA;
 }
 
 void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t s) {

@@ -50,23 +50,24 @@ void launch_finish_leaf(gpma_dev::FusedState *st, uint32_t *stop, gpma_dev::Ctl 
 
 // window prefix: the w batches from st->batch, validated, tagged and
 // concatenated into staging (count to *wcount); errs[j] = st->gen for a
-// batch with an invalid key.  n_max bounds the window's total keys.
+// batch with an invalid key; ustart[j] = where batch j's keys will start in
+// the sorted window (j <= w).  n_max bounds the window's total keys.  Before
+// the window's first locate, st->gen must advance and ctl->misses be zeroed
+// (by launch_window_starts, or by the splitter sort's bookkeeping).
 void launch_window_fetch(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *st, const uint32_t *stop,
                          uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, bool transpose, uint64_t *staging,
-                         uint32_t *wcount, uint32_t *errs, hipStream_t s);
-// first position of each batch's keys in the window's sorted keys;
-// advances st->gen and zeroes ctl->misses
+                         uint32_t *wcount, uint32_t *errs, uint32_t *ustart, hipStream_t s);
+// first position of each batch's keys in the window's sorted keys (the
+// values the fetch wrote); advances st->gen and zeroes ctl->misses
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
                           gpma_dev::FusedState *st, gpma_dev::Ctl *ctl, hipStream_t s);
 
-// The same three for the array (index 0) and its mirror (index 1, keys
-// transposed) in one launch each.
+// The fetch and the finishing step for the array (index 0) and its mirror
+// (index 1, keys transposed) in one launch each.
 void launch_window_fetch2(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *const st[2],
                           const uint32_t *const stop[2], uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb,
-                          uint64_t *const staging[2], uint32_t *const wcount[2], uint32_t *const errs[2], hipStream_t s);
-void launch_window_starts2(const uint64_t *const ukeys[2], const uint32_t *const nuniq[2], uint32_t w, uint32_t sb,
-                           uint32_t *const ustart[2], gpma_dev::FusedState *const st[2], gpma_dev::Ctl *const ctl[2],
-                           hipStream_t s);
+                          uint64_t *const staging[2], uint32_t *const wcount[2], uint32_t *const errs[2],
+                          uint32_t *const ustart[2], hipStream_t s);
 void launch_finish_leaf2(gpma_dev::FusedState *const st[2], uint32_t *const stop[2], gpma_dev::Ctl *const ctl[2],
                          const uint32_t *const part[2], uint64_t nparts, bool del, uint32_t lf,
                          gpma_dev::BatchOut *const out[2], hipStream_t s);

@@ -1,12 +1,15 @@
 // Device side of fused batching: a sequence of update batches run without
 // host synchronisation between batches.
 //
-// Batches go in windows.  A window's prefix (k_window_fetch, one sort --
-// the splitter sort up to 2^20 keys, else the radix sort -- and
-// k_window_starts) sorts all its batches at once: each key carries its
-// batch's place in the window above the source bits, so one sort groups the
-// keys by batch and orders them within; repeats stay, next to each other,
-// and the leaf level takes a key equal to the one before it as a no-op.
+// Batches go in windows.  A window's prefix (k_window_fetch, then one sort --
+// the splitter sort up to 2^20 keys, else the radix sort) sorts all its
+// batches at once: each key carries its batch's place in the window above
+// the source bits, so one sort groups the keys by batch and orders them
+// within; repeats stay, next to each other, and the leaf level takes a key
+// equal to the one before it as a no-op.  As every key stays, batch j's keys
+// start at the sum of the earlier batches' lengths, which the fetch writes.
+// The window generation advances once the fetch is done: in the splitter
+// sort's first launch, or in k_window_starts after the radix sort.
 // Then, per batch, the locate kernel takes the batch's keys from the window's
 // sorted keys (or nothing when the sequence is stopped), the state-dependent
 // steps run (locate, merges, compactions; with no level above the leaves on
@@ -129,7 +132,9 @@ k_finish_leaf(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__r
 // then a grid-stride copy of every key: validated (src < V, dst < V), the
 // mirror's transposed, tagged with its batch's place in the window.  An
 // invalid key marks its batch and is stored as the tagged key (0, 0); the
-// batch is skipped as a whole later.
+// batch is skipped as a whole later.  Every key of batch j carries tag j and
+// the sort keeps repeats, so batch j's keys will start at offset j of the
+// sorted window: the first block writes the offsets to ustart[0 .. w].
 struct WindowFetchOp {
     struct Args {
         const BatchDesc *desc;
@@ -143,6 +148,7 @@ struct WindowFetchOp {
         uint64_t *staging;
         uint32_t *wcount;
         uint32_t *errs;
+        uint32_t *ustart;
     };
     static __device__ __forceinline__ void run(const Args &a) {
         const BatchDesc *__restrict__ desc = a.desc;
@@ -156,6 +162,7 @@ struct WindowFetchOp {
         uint64_t *__restrict__ staging = a.staging;
         uint32_t *__restrict__ wcount = a.wcount;
         uint32_t *__restrict__ errs = a.errs;
+        uint32_t *__restrict__ ustart = a.ustart;
         __shared__ uint64_t off[kWindowMax + 1];
         __shared__ const uint64_t *src[kWindowMax];
         const uint32_t b0 = st->batch;
@@ -175,6 +182,7 @@ struct WindowFetchOp {
             *wcount = (uint32_t)total;
             st->wstart = b0;
         }
+        if (blockIdx.x == 0 && threadIdx.x <= w) ustart[threadIdx.x] = (uint32_t)off[threadIdx.x];
         const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
         for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
             uint32_t j = 0;
@@ -193,8 +201,8 @@ struct WindowFetchOp {
 __global__ void __launch_bounds__(256)
 k_window_fetch(const BatchDesc *__restrict__ desc, FusedState *__restrict__ st, const uint32_t *__restrict__ stop,
                uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, int transpose, uint64_t *__restrict__ staging,
-               uint32_t *__restrict__ wcount, uint32_t *__restrict__ errs) {
-    WindowFetchOp::run(WindowFetchOp::Args{desc, st, stop, w, n_max, V, sb, transpose, staging, wcount, errs});
+               uint32_t *__restrict__ wcount, uint32_t *__restrict__ errs, uint32_t *__restrict__ ustart) {
+    WindowFetchOp::run(WindowFetchOp::Args{desc, st, stop, w, n_max, V, sb, transpose, staging, wcount, errs, ustart});
 }
 
 struct WindowStartsOp {
@@ -254,9 +262,9 @@ static uint32_t copy_blocks(uint64_t n) {
 
 void launch_window_fetch(const BatchDesc *desc, FusedState *st, const uint32_t *stop, uint32_t w, uint64_t n_max,
                          uint32_t V, uint32_t sb, bool transpose, uint64_t *staging, uint32_t *wcount, uint32_t *errs,
-                         hipStream_t s) {
+                         uint32_t *ustart, hipStream_t s) {
     hipLaunchKernelGGL(k_window_fetch, dim3(copy_blocks(n_max)), dim3(256), 0, s, desc, st, stop, w, n_max, V, sb,
-                       transpose ? 1 : 0, staging, wcount, errs);
+                       transpose ? 1 : 0, staging, wcount, errs, ustart);
 }
 
 void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t w, uint32_t sb, uint32_t *ustart,
@@ -268,17 +276,12 @@ void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t
 
 void launch_window_fetch2(const BatchDesc *desc, FusedState *const st[2], const uint32_t *const stop[2], uint32_t w,
                           uint64_t n_max, uint32_t V, uint32_t sb, uint64_t *const staging[2],
-                          uint32_t *const wcount[2], uint32_t *const errs[2], hipStream_t s) {
+                          uint32_t *const wcount[2], uint32_t *const errs[2], uint32_t *const ustart[2],
+                          hipStream_t s) {
     WindowFetchOp::Args a[2];
-    for (int k = 0; k < 2; k++) a[k] = {desc, st[k], stop[k], w, n_max, V, sb, k, staging[k], wcount[k], errs[k]};
+    for (int k = 0; k < 2; k++)
+        a[k] = {desc, st[k], stop[k], w, n_max, V, sb, k, staging[k], wcount[k], errs[k], ustart[k]};
     launch_pair<WindowFetchOp, 256>(copy_blocks(n_max), a[0], a[1], s);
-}
-
-void launch_window_starts2(const uint64_t *const ukeys[2], const uint32_t *const nuniq[2], uint32_t w, uint32_t sb,
-                           uint32_t *const ustart[2], FusedState *const st[2], Ctl *const ctl[2], hipStream_t s) {
-    WindowStartsOp::Args a[2];
-    for (int k = 0; k < 2; k++) a[k] = {ukeys[k], nuniq[k], w, sb, ustart[k], st[k], ctl[k]};
-    hipLaunchKernelGGL((k_pair<WindowStartsOp, 256>), dim3(1, 2), dim3(128), 0, s, a[0], a[1]);
 }
 
 void launch_finish_leaf2(FusedState *const st[2], uint32_t *const stop[2], Ctl *const ctl[2],

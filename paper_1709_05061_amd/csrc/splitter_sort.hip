@@ -143,6 +143,8 @@ struct SsSplitArgs {
     const uint32_t *n_dev;
     uint32_t B;
     uint64_t *spl;
+    uint32_t *bump;    // optional: a counter advanced by one once the keys are in place
+    uint32_t *clear;   // optional (with bump): a word set to zero at the same time
 };
 
 template <int R>
@@ -155,6 +157,10 @@ struct SsSplittersOp {
         const uint32_t B = a.B;
         uint64_t *__restrict__ spl = a.spl;
         __shared__ uint64_t lds[1024 * R];
+        if (a.bump && threadIdx.x == 0) {
+            *a.bump += 1;
+            *a.clear = 0;
+        }
         const uint64_t n = dyn_n(n_dev, n_max);
         if (B < 2) return;
         if (n == 0) {
@@ -179,8 +185,8 @@ struct SsSplittersOp {
 template <int R>
 __global__ void __launch_bounds__(kSsThreads)
 k_ss_splitters(const uint64_t *__restrict__ keys, uint64_t n_max, const uint32_t *__restrict__ n_dev, uint32_t B,
-               uint64_t *__restrict__ spl) {
-    SsSplittersOp<R>::run(SsSplitArgs{keys, n_max, n_dev, B, spl});
+               uint64_t *__restrict__ spl, uint32_t *bump, uint32_t *clear) {
+    SsSplittersOp<R>::run(SsSplitArgs{keys, n_max, n_dev, B, spl, bump, clear});
 }
 
 // 2. per-tile bucket counts, bucket-major: cnt[b * ntiles + tile]
@@ -462,7 +468,7 @@ size_t splitter_tmp_words(uint64_t n_max) {
 
 const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uint32_t *n_dev, uint32_t sbits,
                                    uint32_t dbits, uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
-                                   hipStream_t s) {
+                                   hipStream_t s, uint32_t *bump, uint32_t *clear) {
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
     const uint32_t passes = (total + 7) / 8;
@@ -479,11 +485,14 @@ const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uin
     uint32_t *stmp = cnt + cw;
     const uint32_t S = B * kSsOversample;
     if (S <= 1024)
-        hipLaunchKernelGGL(k_ss_splitters<1>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl);
+        hipLaunchKernelGGL(k_ss_splitters<1>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl, bump,
+                           clear);
     else if (S <= 2048)
-        hipLaunchKernelGGL(k_ss_splitters<2>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl);
+        hipLaunchKernelGGL(k_ss_splitters<2>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl, bump,
+                           clear);
     else
-        hipLaunchKernelGGL(k_ss_splitters<4>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl);
+        hipLaunchKernelGGL(k_ss_splitters<4>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl, bump,
+                           clear);
     hipLaunchKernelGGL(k_ss_count, dim3((uint32_t)ntiles), dim3(kSsTileThreads), 0, s, in, n_max, n_dev, spl, B,
                        (uint32_t)ntiles, cnt);
     const bool fused = cw <= kSsFuseCounts;
@@ -504,7 +513,7 @@ bool splitter_sort_pairable(uint64_t n_max) {
 // as 0 (buf_a) or 1 (buf_b).
 int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint32_t *const n_dev[2], uint32_t sbits,
                         uint32_t dbits, uint64_t *const buf_a[2], uint64_t *const buf_b[2], uint32_t *const tmp[2],
-                        hipStream_t s) {
+                        hipStream_t s, uint32_t *const bump[2], uint32_t *const clear[2]) {
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
     const uint32_t passes = (total + 7) / 8;
@@ -522,7 +531,7 @@ int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint3
         uint64_t *spl = reinterpret_cast<uint64_t *>(tmp[k]);
         uint32_t *bst = tmp[k] + 2 * kSsMaxBuckets;
         uint32_t *cnt = bst + kSsMaxBuckets + 4;
-        sp[k] = {in[k], n_max, n_dev[k], B, spl};
+        sp[k] = {in[k], n_max, n_dev[k], B, spl, bump ? bump[k] : nullptr, bump ? clear[k] : nullptr};
         ca[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt};
         sa[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt, 1, bst, mid};
         ba[k] = {mid, fin, n_max, n_dev[k], bst, 1u, B, dbits, bits, passes};
