@@ -234,9 +234,13 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
     // the lane's first update of the run, loaded beside the leaf ids (its
     // address does not wait for them)
     const uint64_t kpre = i + gl < n ? keys[i + gl] : 0;
+    // the leaf ids of the update and both neighbours in one round trip: a
+    // run of one (the common case) needs no search for its end
     const uint32_t lf_i = leaf[i];
-    if (i > 0 && leaf[i - 1] == lf_i) return rs;   // not the head of its run
-    const uint32_t e = run_end(leaf, i, n, lf_i, 0);
+    const uint32_t lf_prev = i > 0 ? leaf[i - 1] : ~0u;   // leaf ids are < 2^32 - 1
+    const uint32_t lf_next = i + 1 < n ? leaf[i + 1] : ~0u;
+    if (lf_prev == lf_i) return rs;   // not the head of its run
+    const uint32_t e = lf_next != lf_i ? i + 1 : run_end(leaf, i, n, lf_i, 0);
     const uint32_t k = e - i;
     const uint64_t base = (uint64_t)lf_i * LF;
     uint64_t mine[SPL];
