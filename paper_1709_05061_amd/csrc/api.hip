@@ -1207,7 +1207,7 @@ void enqueue_window_prefix2(gpma *g, gpma *m, uint32_t w, uint64_t n_max, const 
     for (int k = 0; k < 2; k++) h[k]->wukeys = which ? h[k]->kB : h[k]->kA;
 }
 
-void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t s) {
+void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, uint32_t pos, hipStream_t s) {
     const uint32_t sb = bit_width(g->V - 1);
     const uint64_t tmask = ~(((1ull << kWindowTagBits) - 1) << (32 + sb));
     gpma *h[2] = {g, m};
@@ -1226,8 +1226,9 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, hipStream_t
     const uint32_t *part_c[2];
     for (int k = 0; k < 2; k++) {
         gpma *x = h[k];
+        // the window's graph runs its batches in order: this one is at pos
         ws[k] = WinSrc{&x->fs->batch, &x->fs->wstart, &x->fs->gen, x->stop, x->wukeys, x->ustart, x->werrs, tmask,
-                       x->kS, x->ctl};
+                       x->kS, x->ctl, (int32_t)pos};
         slots[k] = x->slots;
         piv[k] = x->piv;
         piv_c[k] = x->piv;
@@ -1291,7 +1292,7 @@ hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint64_t wcls, const uint8_t *op
     if (hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
     enqueue_window_prefix2(g, m, to - from, wcls, desc, g->cap_stream);
     for (uint32_t i = from; i < to; i++)
-        enqueue_device_batch2(g, m, ops[i] != 0, batch_class(sizes[i]), g->cap_stream);
+        enqueue_device_batch2(g, m, ops[i] != 0, batch_class(sizes[i]), i - from, g->cap_stream);
     if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
     hipGraphExec_t exec = nullptr;
     const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

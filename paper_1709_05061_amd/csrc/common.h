@@ -33,7 +33,7 @@ struct Ctl {
 
 // Where a locate kernel takes its batch from.  ukeys == nullptr: the keys
 // passed to it, n from *n_dev, err from ctl->err.  Else the current batch of
-// a fused window: batch j = *batch - *wstart of the window's sorted unique
+// a fused window: batch j (pos when set, else *batch - *wstart) of the window's sorted
 // keys ukeys[ustart[j] .. ustart[j+1]), tag bits cleared (none while *stop
 // is set; err when errs[j] == *gen - 1); the kernel writes them to dense[]
 // for the kernels after it, and its first thread resets the batch's control
@@ -46,6 +46,7 @@ struct WinSrc {
     uint64_t tag_mask;
     uint64_t *dense;
     Ctl *ctl;
+    int32_t pos = -1;   // >= 0: the batch's place in its window, fixed when the launch was made
 };
 
 struct BatchView {
@@ -61,7 +62,7 @@ __device__ __forceinline__ BatchView batch_view(const WinSrc &w, const uint64_t 
         const uint64_t n = *n_dev < n_max ? *n_dev : n_max;
         return BatchView{keys, n, ctl->err != 0, ~0ull};
     }
-    const uint32_t j = *w.batch - *w.wstart;
+    const uint32_t j = w.pos >= 0 ? (uint32_t)w.pos : *w.batch - *w.wstart;
     const bool stopped = *w.stop != 0;
     const uint64_t beg = w.ustart[j];
     uint64_t n = stopped ? 0 : w.ustart[j + 1] - beg;

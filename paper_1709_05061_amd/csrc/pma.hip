@@ -228,17 +228,20 @@ leaf_merge_group(const uint64_t *__restrict__ keys, const uint32_t *__restrict__
     const uint64_t gi = (uint64_t)blockIdx.x * GPB + gib;
     RunStats rs{0, 0, 0, 0};
     if (gi >= n_max) return rs;
-    const uint32_t n = *n_dev;
-    if (gi >= n || ctl->err) return rs;
     const uint32_t i = (uint32_t)gi;
-    // the lane's first update of the run, loaded beside the leaf ids (its
-    // address does not wait for them)
-    const uint64_t kpre = i + gl < n ? keys[i + gl] : 0;
-    // the leaf ids of the update and both neighbours in one round trip: a
-    // run of one (the common case) needs no search for its end
+    // One round trip for what a run's head needs first: the batch size and
+    // error flag, the lane's first update of the run, and the leaf ids of the
+    // update and both neighbours (a run of one, the common case, then needs
+    // no search for its end).  The arrays hold n_max entries; those past the
+    // batch size are stale and dropped once it is known.
+    const uint32_t n = *n_dev;
+    const uint32_t err = ctl->err;
+    const uint64_t kpre = i + gl < n_max ? keys[i + gl] : 0;
     const uint32_t lf_i = leaf[i];
     const uint32_t lf_prev = i > 0 ? leaf[i - 1] : ~0u;   // leaf ids are < 2^32 - 1
-    const uint32_t lf_next = i + 1 < n ? leaf[i + 1] : ~0u;
+    const uint32_t lf_nx = i + 1 < n_max ? leaf[i + 1] : ~0u;
+    if (gi >= n || err) return rs;
+    const uint32_t lf_next = i + 1 < n ? lf_nx : ~0u;
     if (lf_prev == lf_i) return rs;   // not the head of its run
     const uint32_t e = lf_next != lf_i ? i + 1 : run_end(leaf, i, n, lf_i, 0);
     const uint32_t k = e - i;
