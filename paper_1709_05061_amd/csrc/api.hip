@@ -156,10 +156,12 @@ struct gpma {
     // block, so a window's results come back in one copy per handle
     uint64_t *fblk = nullptr;            // device block
     void *fblk_h = nullptr;              // pinned block
+    void *fblk_hd = nullptr;             // its device view (kernels write the results there)
     FusedState *fs_h = nullptr;          // pinned mirror of *fs
     uint32_t *stop_h = nullptr;          // pinned
     FusedState *reset_h = nullptr;       // pinned source of state resets
     BatchDesc *desc_h = nullptr;         // pinned staging of the descriptor table
+    BatchDesc *desc_hd = nullptr;        // its device view (read by the call's first kernel)
     BatchOut *outs_h = nullptr;          // pinned copy of the per-batch results
 
     bool readonly = false;   // a snapshot: analytics and exports only
@@ -946,6 +948,8 @@ void free_all(gpma *g) {
     g->stop_h = nullptr;
     g->reset_h = nullptr;
     g->desc_h = nullptr;
+    g->desc_hd = nullptr;
+    g->fblk_hd = nullptr;
     g->outs_h = nullptr;
     if (g->cap_stream) hipStreamDestroy(g->cap_stream);
     g->cap_stream = nullptr;
@@ -1002,7 +1006,10 @@ int ensure_fused(gpma *g) {
         g->outs = (BatchOut *)(b + kFbOuts);
     }
     e |= dev_alloc(g, &g->desc, kFusedChunk);
-    if (hipHostMalloc(&g->fblk_h, kFbBytes, 0) != hipSuccess) {
+    // the pinned blocks that kernels read or write over the bus are coherent
+    // (not cached on the device), so each side sees the other's latest writes
+    constexpr unsigned kBusFlags = hipHostMallocMapped | hipHostMallocCoherent;
+    if (hipHostMalloc(&g->fblk_h, kFbBytes, kBusFlags) != hipSuccess) {
         g->fblk_h = nullptr;
         e = GPMA_ENOMEM;
     } else {
@@ -1010,9 +1017,11 @@ int ensure_fused(gpma *g) {
         g->fs_h = (FusedState *)b;
         g->stop_h = (uint32_t *)(b + kFbStop);
         g->outs_h = (BatchOut *)(b + kFbOuts);
+        if (hipHostGetDevicePointer(&g->fblk_hd, g->fblk_h, 0) != hipSuccess) e = GPMA_EDEVICE;
     }
     if (hipHostMalloc((void **)&g->reset_h, sizeof(FusedState), 0) != hipSuccess) e = GPMA_ENOMEM;
-    if (hipHostMalloc((void **)&g->desc_h, kFusedChunk * sizeof(BatchDesc), 0) != hipSuccess) e = GPMA_ENOMEM;
+    if (hipHostMalloc((void **)&g->desc_h, kFusedChunk * sizeof(BatchDesc), kBusFlags) != hipSuccess) e = GPMA_ENOMEM;
+    else if (hipHostGetDevicePointer((void **)&g->desc_hd, g->desc_h, 0) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipStreamCreateWithFlags(&g->side, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
     if (!e && hipStreamCreateWithFlags(&g->side2, hipStreamNonBlocking) != hipSuccess) e = GPMA_EDEVICE;
@@ -1293,6 +1302,9 @@ hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint64_t wcls, const uint8_t *op
     enqueue_window_prefix2(g, m, to - from, wcls, desc, g->cap_stream);
     for (uint32_t i = from; i < to; i++)
         enqueue_device_batch2(g, m, ops[i] != 0, batch_class(sizes[i]), i - from, g->cap_stream);
+    const void *blk[2] = {g->fblk, m->fblk};
+    void *host[2] = {g->fblk_hd, m->fblk_hd};
+    launch_fused_publish2(blk, host, (uint32_t)kFbOuts, (uint32_t)kFbOuts, g->cap_stream);
     if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
     hipGraphExec_t exec = nullptr;
     const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1462,7 +1474,6 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
     // the previous call ended with a synchronisation, so the pinned staging
     // buffers are free to rewrite
     for (uint32_t i = 0; i < count; i++) g->desc_h[i] = BatchDesc{keys[i], sizes[i]};
-    hipMemcpyAsync(g->desc, g->desc_h, count * sizeof(BatchDesc), hipMemcpyHostToDevice, s);
     // The array and its mirror advance independently, each on its own stream
     // with its own stop flag (the mirror's batches are the transposed keys);
     // a handle that stops is completed on the host and resumes after that
@@ -1486,10 +1497,8 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
     const bool lib0 = m && !pair;   // the array's pipeline leaves the caller's stream
     Prog P[2] = {{g, lib0 ? g->side : s, false, 0, false}, {m, m ? (pair ? pair : g->side2) : s, true, 0, false}};
     const int nh = m ? 2 : 1;
-    for (int k = 0; k < nh; k++) {
-        hipMemsetAsync(P[k].h->stop, 0, sizeof(uint32_t), s);
-        reset_fused(P[k].h, 0, s);
-    }
+    // one launch copies the descriptors and clears both handles' state
+    launch_fused_begin(g->fs, g->stop, m ? m->fs : nullptr, m ? m->stop : nullptr, 0, g->desc_hd, g->desc, count, s);
     uint32_t window = 8;
     int err = GPMA_OK;
     uint32_t err_at = count;
@@ -1567,11 +1576,13 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
                 }
             }
         }
-        // state, stop flag and results up to the window's end: one copy per handle
-        for (int k = 0; k < nh; k++) {
-            gpma *h = P[k].h;
-            hipMemcpyAsync(h->fblk_h, h->fblk, kFbOuts + end[k] * sizeof(BatchOut), hipMemcpyDeviceToHost, s);
-        }
+        // state, stop flag and results up to the window's end: one copy per
+        // handle (a paired window's graph ends by writing them to the host)
+        if (!paired)
+            for (int k = 0; k < nh; k++) {
+                gpma *h = P[k].h;
+                hipMemcpyAsync(h->fblk_h, h->fblk, kFbOuts + end[k] * sizeof(BatchOut), hipMemcpyDeviceToHost, s);
+            }
         if (hipStreamSynchronize(s) != hipSuccess) return GPMA_EDEVICE;
         bool stopped = false;
         for (int k = 0; k < nh; k++) {

@@ -72,5 +72,17 @@ void launch_finish_leaf2(gpma_dev::FusedState *const st[2], uint32_t *const stop
                          const uint32_t *const part[2], uint64_t nparts, bool del, uint32_t lf,
                          gpma_dev::BatchOut *const out[2], hipStream_t s);
 
+// Start of a fused call: count descriptors copied from src (the caller's
+// pinned table, device view) to dst, and each handle's state set to run from
+// `batch` with its halted and stop flags cleared (st1/stop1 may be null).
+void launch_fused_begin(gpma_dev::FusedState *st0, uint32_t *stop0, gpma_dev::FusedState *st1, uint32_t *stop1,
+                        uint32_t batch, const gpma_dev::BatchDesc *src, gpma_dev::BatchDesc *dst, uint32_t count,
+                        hipStream_t s);
+// End of a paired window: each handle's fused block (head bytes of state and
+// stop flag, then the results of batches [wstart, batch) at outs_off) copied
+// into host[k], the device view of its pinned block of the same layout.
+void launch_fused_publish2(const void *const blk[2], void *const host[2], uint32_t head, uint32_t outs_off,
+                           hipStream_t s);
+
 }  // namespace gpma_host
 

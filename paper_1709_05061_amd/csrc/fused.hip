@@ -240,9 +240,63 @@ k_window_starts(const uint64_t *__restrict__ ukeys, const uint32_t *__restrict__
     WindowStartsOp::run(WindowStartsOp::Args{ukeys, nuniq, w, sb, ustart, st, ctl});
 }
 
+// Start of a fused call: the batch descriptors copied from the caller's
+// pinned table (read over the bus) and each handle's state set to run from
+// `batch`, halted and stop flags cleared (the window generation carries on).
+__global__ void __launch_bounds__(256)
+k_fused_begin(FusedState *__restrict__ st0, uint32_t *__restrict__ stop0, FusedState *__restrict__ st1,
+              uint32_t *__restrict__ stop1, uint32_t batch, const BatchDesc *__restrict__ src,
+              BatchDesc *__restrict__ dst, uint32_t count) {
+    for (uint32_t i = threadIdx.x; i < count; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x == 0) {
+        st0->batch = batch;
+        st0->halted = 0;
+        *stop0 = 0;
+        if (st1) {
+            st1->batch = batch;
+            st1->halted = 0;
+            *stop1 = 0;
+        }
+    }
+}
+
+// End of a window: the handle's fused block -- its state and stop flag (the
+// first `head` bytes) and the results of the window's batches [wstart,
+// batch) -- copied word by word into the host's pinned block of the same
+// layout, so the host reads it after the stream's synchronisation without a
+// copy of its own.
+struct PublishOp {
+    struct Args {
+        const uint32_t *blk;
+        uint32_t *host;
+        uint32_t head;       // bytes
+        uint32_t outs_off;   // bytes
+    };
+    static __device__ __forceinline__ void run(const Args &a) {
+        const FusedState *st = reinterpret_cast<const FusedState *>(a.blk);
+        const uint32_t lo = (a.outs_off + st->wstart * (uint32_t)sizeof(BatchOut)) / 4;
+        const uint32_t hi = (a.outs_off + st->batch * (uint32_t)sizeof(BatchOut)) / 4;
+        for (uint32_t i = threadIdx.x; i < a.head / 4; i += blockDim.x) a.host[i] = a.blk[i];
+        for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) a.host[i] = a.blk[i];
+    }
+};
+
 }  // namespace
 
 namespace gpma_host {
+
+void launch_fused_begin(FusedState *st0, uint32_t *stop0, FusedState *st1, uint32_t *stop1, uint32_t batch,
+                        const BatchDesc *src, BatchDesc *dst, uint32_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_fused_begin, dim3(1), dim3(256), 0, s, st0, stop0, st1, stop1, batch, src, dst, count);
+}
+
+void launch_fused_publish2(const void *const blk[2], void *const host[2], uint32_t head, uint32_t outs_off,
+                           hipStream_t s) {
+    PublishOp::Args a[2];
+    for (int k = 0; k < 2; k++)
+        a[k] = {static_cast<const uint32_t *>(blk[k]), static_cast<uint32_t *>(host[k]), head, outs_off};
+    launch_pair<PublishOp, 256>(1, a[0], a[1], s);
+}
 
 void launch_finish(FusedState *st, uint32_t *stop, Ctl *ctl, const uint32_t *pending, BatchOut *out,
                    hipStream_t s) {
