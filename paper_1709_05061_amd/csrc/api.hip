@@ -1271,7 +1271,10 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, uint32_t po
         launch_locate2(cls, piv_c, L, ctl_c, leaf, status, ws, s);
     launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, piv, cnt, row_ptr, deg, dead, g->lf, lo, hi, ctl,
                        part, s);
-    launch_finish_leaf2(st, stop, ctl, part_c, leaf_merge_blocks(g->lf, cls), del, g->lf, outs, s);
+    // each finished batch also lands in the handle's pinned block
+    void *host[2] = {g->fblk_hd, m->fblk_hd};
+    launch_finish_leaf2(st, stop, ctl, part_c, leaf_merge_blocks(g->lf, cls), del, g->lf, outs, host,
+                        (uint32_t)kFbOuts, s);
 }
 
 constexpr size_t kPairGraphs = 32;   // window shapes kept per handle
@@ -1302,9 +1305,6 @@ hipGraphExec_t get_pair_graph(gpma *g, gpma *m, uint64_t wcls, const uint8_t *op
     enqueue_window_prefix2(g, m, to - from, wcls, desc, g->cap_stream);
     for (uint32_t i = from; i < to; i++)
         enqueue_device_batch2(g, m, ops[i] != 0, batch_class(sizes[i]), i - from, g->cap_stream);
-    const void *blk[2] = {g->fblk, m->fblk};
-    void *host[2] = {g->fblk_hd, m->fblk_hd};
-    launch_fused_publish2(blk, host, (uint32_t)kFbOuts, (uint32_t)kFbOuts, g->cap_stream);
     if (hipStreamEndCapture(g->cap_stream, &graph) != hipSuccess || !graph) return nullptr;
     hipGraphExec_t exec = nullptr;
     const hipError_t r = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1577,7 +1577,7 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
             }
         }
         // state, stop flag and results up to the window's end: one copy per
-        // handle (a paired window's graph ends by writing them to the host)
+        // handle (a paired window's finishing kernels write them to the host)
         if (!paired)
             for (int k = 0; k < nh; k++) {
                 gpma *h = P[k].h;

@@ -36,6 +36,7 @@ struct BatchOut {
     uint32_t lookups;   // keys located (repeats included)
     uint32_t pad;
 };
+static_assert(sizeof(BatchOut) % 16 == 0, "results are copied in 16-byte words");
 
 }  // namespace gpma_dev
 
@@ -68,9 +69,11 @@ void launch_window_fetch2(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState 
                           const uint32_t *const stop[2], uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb,
                           uint64_t *const staging[2], uint32_t *const wcount[2], uint32_t *const errs[2],
                           uint32_t *const ustart[2], hipStream_t s);
+// (host[k]: the device view of side k's pinned block of the fused block's
+// layout; each finished batch's state, stop flag and results go there too)
 void launch_finish_leaf2(gpma_dev::FusedState *const st[2], uint32_t *const stop[2], gpma_dev::Ctl *const ctl[2],
                          const uint32_t *const part[2], uint64_t nparts, bool del, uint32_t lf,
-                         gpma_dev::BatchOut *const out[2], hipStream_t s);
+                         gpma_dev::BatchOut *const out[2], void *const host[2], uint32_t head, hipStream_t s);
 
 // Start of a fused call: count descriptors copied from src (the caller's
 // pinned table, device view) to dst, and each handle's state set to run from
@@ -78,11 +81,6 @@ void launch_finish_leaf2(gpma_dev::FusedState *const st[2], uint32_t *const stop
 void launch_fused_begin(gpma_dev::FusedState *st0, uint32_t *stop0, gpma_dev::FusedState *st1, uint32_t *stop1,
                         uint32_t batch, const gpma_dev::BatchDesc *src, gpma_dev::BatchDesc *dst, uint32_t count,
                         hipStream_t s);
-// End of a paired window: each handle's fused block (head bytes of state and
-// stop flag, then the results of batches [wstart, batch) at outs_off) copied
-// into host[k], the device view of its pinned block of the same layout.
-void launch_fused_publish2(const void *const blk[2], void *const host[2], uint32_t head, uint32_t outs_off,
-                           hipStream_t s);
 
 }  // namespace gpma_host
 

@@ -53,6 +53,11 @@ __global__ void k_finish(FusedState *__restrict__ st, uint32_t *__restrict__ sto
 // k_finish after a leaf merge that left per-block figures in part[4*i ..]
 // (merged, no-ops, leaves merged, pending) instead of compacting: sum them
 // into the control block (reset by the batch's locate), then finish.
+// host (optional): the device view of the handle's pinned block, laid out
+// like its fused block (state, then the stop flag, `head` bytes in all,
+// then the per-batch results at `head`); the finished batch's state, stop
+// flag and results are written there too, so the host reads them after the
+// stream's synchronisation without a copy of its own.
 struct FinishLeafOp {
     struct Args {
         FusedState *st;
@@ -63,7 +68,20 @@ struct FinishLeafOp {
         int del;
         uint32_t lf;
         BatchOut *out;
+        uint4 *host;
+        uint32_t head;   // bytes, a multiple of 16
     };
+    // thread 0, after its own stores to the fused block
+    static __device__ __forceinline__ void publish(const Args &a, uint32_t b, bool with_out) {
+        if (!a.host) return;
+        const uint4 *blk = reinterpret_cast<const uint4 *>(a.st);   // the state opens the fused block
+        for (uint32_t i = 0; i < a.head / 16; i++) a.host[i] = blk[i];
+        if (with_out) {
+            const uint4 *o = reinterpret_cast<const uint4 *>(a.out + b);
+            uint4 *h = a.host + a.head / 16 + (uint64_t)b * (sizeof(BatchOut) / 16);
+            for (uint32_t i = 0; i < sizeof(BatchOut) / 16; i++) h[i] = o[i];
+        }
+    }
     static __device__ __forceinline__ void run(const Args &a) {
         FusedState *__restrict__ st = a.st;
         uint32_t *__restrict__ stop = a.stop;
@@ -108,6 +126,7 @@ struct FinishLeafOp {
             st->snap = *ctl;
             st->halted = 1;
             *stop = 1;
+            publish(a, b, false);
             return;
         }
         out[b].applied = t[0];
@@ -119,13 +138,14 @@ struct FinishLeafOp {
         ctl->misses = 0;
         out[b].lookups = ctl->n_in;
         st->batch = b + 1;
+        publish(a, b, true);
     }
 };
 
 __global__ void __launch_bounds__(1024)
 k_finish_leaf(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__restrict__ ctl,
               const uint4 *__restrict__ part, uint64_t nparts, int del, uint32_t lf, BatchOut *__restrict__ out) {
-    FinishLeafOp::run(FinishLeafOp::Args{st, stop, ctl, part, nparts, del, lf, out});
+    FinishLeafOp::run(FinishLeafOp::Args{st, stop, ctl, part, nparts, del, lf, out, nullptr, 0});
 }
 
 // Window prefix.  Block-local table of the window's batch offsets (w <= 64),
@@ -260,27 +280,6 @@ k_fused_begin(FusedState *__restrict__ st0, uint32_t *__restrict__ stop0, FusedS
     }
 }
 
-// End of a window: the handle's fused block -- its state and stop flag (the
-// first `head` bytes) and the results of the window's batches [wstart,
-// batch) -- copied word by word into the host's pinned block of the same
-// layout, so the host reads it after the stream's synchronisation without a
-// copy of its own.
-struct PublishOp {
-    struct Args {
-        const uint32_t *blk;
-        uint32_t *host;
-        uint32_t head;       // bytes
-        uint32_t outs_off;   // bytes
-    };
-    static __device__ __forceinline__ void run(const Args &a) {
-        const FusedState *st = reinterpret_cast<const FusedState *>(a.blk);
-        const uint32_t lo = (a.outs_off + st->wstart * (uint32_t)sizeof(BatchOut)) / 4;
-        const uint32_t hi = (a.outs_off + st->batch * (uint32_t)sizeof(BatchOut)) / 4;
-        for (uint32_t i = threadIdx.x; i < a.head / 4; i += blockDim.x) a.host[i] = a.blk[i];
-        for (uint32_t i = lo + threadIdx.x; i < hi; i += blockDim.x) a.host[i] = a.blk[i];
-    }
-};
-
 }  // namespace
 
 namespace gpma_host {
@@ -290,13 +289,6 @@ void launch_fused_begin(FusedState *st0, uint32_t *stop0, FusedState *st1, uint3
     hipLaunchKernelGGL(k_fused_begin, dim3(1), dim3(256), 0, s, st0, stop0, st1, stop1, batch, src, dst, count);
 }
 
-void launch_fused_publish2(const void *const blk[2], void *const host[2], uint32_t head, uint32_t outs_off,
-                           hipStream_t s) {
-    PublishOp::Args a[2];
-    for (int k = 0; k < 2; k++)
-        a[k] = {static_cast<const uint32_t *>(blk[k]), static_cast<uint32_t *>(host[k]), head, outs_off};
-    launch_pair<PublishOp, 256>(1, a[0], a[1], s);
-}
 
 void launch_finish(FusedState *st, uint32_t *stop, Ctl *ctl, const uint32_t *pending, BatchOut *out,
                    hipStream_t s) {
@@ -340,10 +332,11 @@ void launch_window_fetch2(const BatchDesc *desc, FusedState *const st[2], const 
 
 void launch_finish_leaf2(FusedState *const st[2], uint32_t *const stop[2], Ctl *const ctl[2],
                          const uint32_t *const part[2], uint64_t nparts, bool del, uint32_t lf,
-                         BatchOut *const out[2], hipStream_t s) {
+                         BatchOut *const out[2], void *const host[2], uint32_t head, hipStream_t s) {
     FinishLeafOp::Args a[2];
     for (int k = 0; k < 2; k++)
-        a[k] = {st[k], stop[k], ctl[k], reinterpret_cast<const uint4 *>(part[k]), nparts, del ? 1 : 0, lf, out[k]};
+        a[k] = {st[k], stop[k], ctl[k], reinterpret_cast<const uint4 *>(part[k]), nparts, del ? 1 : 0, lf, out[k],
+                static_cast<uint4 *>(host[k]), head};
     launch_pair<FinishLeafOp, 1024>(1, a[0], a[1], s);
 }
 
