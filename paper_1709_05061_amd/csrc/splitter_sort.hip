@@ -32,8 +32,8 @@ namespace {
 constexpr int kSsThreads = 1024;                         // sample and bucket workgroups
 constexpr int kSsWaves = kSsThreads / kWave;             // 16
 constexpr uint32_t kSsLdsKeys = 4096;                    // keys a bucket workgroup sorts in registers / LDS
-constexpr int kSsTileThreads = 256;
-constexpr int kSsTileItems = 8;
+constexpr int kSsTileThreads = 1024;
+constexpr int kSsTileItems = 2;
 constexpr uint32_t kSsTile = kSsTileThreads * kSsTileItems;   // 2048 keys a count / scatter tile
 constexpr uint32_t kSsMaxBuckets = 1024;
 constexpr uint32_t kSsOversample = 4;                    // sample keys per bucket
@@ -227,7 +227,7 @@ struct SsCountOp {
     }
 };
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kSsTileThreads)
 k_ss_count(const uint64_t *__restrict__ keys, uint64_t n_max, const uint32_t *__restrict__ n_dev,
            const uint64_t *__restrict__ spl, uint32_t B, uint32_t ntiles, uint32_t *__restrict__ cnt) {
     SsCountOp::run(SsCountOp::Args{keys, n_max, n_dev, spl, B, ntiles, cnt});
@@ -297,7 +297,7 @@ struct SsScatterOp {
                 cur[b] = before;
             }
             __syncthreads();
-            // bucket starts: thread t prefixes buckets [4t, 4t+4) (B <= 1024)
+            // bucket starts: thread t prefixes kPer buckets from kPer*t (B <= 1024)
             constexpr uint32_t kPer = kSsMaxBuckets / kSsTileThreads;
             uint32_t mine = 0;
 #pragma unroll
@@ -333,7 +333,7 @@ struct SsScatterOp {
     }
 };
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kSsTileThreads)
 k_ss_scatter(const uint64_t *__restrict__ keys, uint64_t n_max, const uint32_t *__restrict__ n_dev,
              const uint64_t *__restrict__ spl, uint32_t B, uint32_t ntiles, const uint32_t *__restrict__ cnt,
              int fused, uint32_t *__restrict__ bst, uint64_t *__restrict__ out) {
