@@ -1207,12 +1207,15 @@ void enqueue_window_prefix2(gpma *g, gpma *m, uint32_t w, uint64_t n_max, const 
     uint32_t *ustart[2] = {g->ustart, m->ustart};
     uint32_t *gen[2] = {&g->fs->gen, &m->fs->gen};
     uint32_t *misses[2] = {&g->ctl->misses, &m->ctl->misses};
-    launch_window_fetch2(desc, st, stop, w, n_max, g->V, sb, kS, wcount, errs, ustart, s);
+    // the fetch also samples and sorts the splitters
+    uint64_t *spl[2] = {splitter_spl(g->tmp), splitter_spl(m->tmp)};
+    launch_window_fetch2(desc, st, stop, w, n_max, g->V, sb, kS, wcount, errs, ustart, spl, splitter_buckets(n_max),
+                         splitter_sample_size(n_max), s);
     const uint64_t *in[2] = {g->kS, m->kS};
     const uint32_t *nd[2] = {g->wcount, m->wcount};
     uint64_t *ba[2] = {g->kA, m->kA}, *bb[2] = {g->kB, m->kB};
     uint32_t *tmp[2] = {g->tmp, m->tmp};
-    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s, gen, misses);
+    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s, gen, misses, true);
     for (int k = 0; k < 2; k++) h[k]->wukeys = which ? h[k]->kB : h[k]->kA;
 }
 

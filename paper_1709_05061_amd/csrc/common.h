@@ -218,10 +218,16 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
 // result is in the buffer radix_sort_keys would return for the same bit
 // counts (buf_a for an odd number of 8-bit passes); the other buffer is
 // overwritten.  tmp: splitter_tmp_words(n_max) words.  bump/clear
-// (optional, for a caller's bookkeeping): the first launch, once the input
-// is in place, adds one to *bump and zeroes *clear.
+// (optional, for a caller's bookkeeping): the counting launch, once the
+// input is in place, adds one to *bump and zeroes *clear.
 bool splitter_sort_fits(uint64_t n_max);
 size_t splitter_tmp_words(uint64_t n_max);
+// For a caller that samples the splitters itself (spl_ready below): the
+// bucket count, the sample size (a regular sample of that many keys, sorted,
+// gives splitter j = sample[(j+1)*S/B], j < B-1) and where they go in tmp.
+uint32_t splitter_buckets(uint64_t n_max);
+uint32_t splitter_sample_size(uint64_t n_max);
+uint64_t *splitter_spl(uint32_t *tmp);
 const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uint32_t *n_dev, uint32_t sbits,
                                    uint32_t dbits, uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
                                    hipStream_t s, uint32_t *bump = nullptr, uint32_t *clear = nullptr);
@@ -231,7 +237,8 @@ const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uin
 bool splitter_sort_pairable(uint64_t n_max);
 int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint32_t *const n_dev[2], uint32_t sbits,
                         uint32_t dbits, uint64_t *const buf_a[2], uint64_t *const buf_b[2], uint32_t *const tmp[2],
-                        hipStream_t s, uint32_t *const bump[2] = nullptr, uint32_t *const clear[2] = nullptr);
+                        hipStream_t s, uint32_t *const bump[2] = nullptr, uint32_t *const clear[2] = nullptr,
+                        bool spl_ready = false);
 
 // unique of a sorted array: out receives the distinct keys, *count_dev their
 // number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).

@@ -64,11 +64,13 @@ void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t
                           gpma_dev::FusedState *st, gpma_dev::Ctl *ctl, hipStream_t s);
 
 // The fetch and the finishing step for the array (index 0) and its mirror
-// (index 1, keys transposed) in one launch each.
+// (index 1, keys transposed) in one launch each.  The paired fetch also
+// writes the splitter sort's splitters to spl[k] (B buckets, sample size S:
+// splitter_buckets, splitter_sample_size, splitter_spl).
 void launch_window_fetch2(const gpma_dev::BatchDesc *desc, gpma_dev::FusedState *const st[2],
                           const uint32_t *const stop[2], uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb,
                           uint64_t *const staging[2], uint32_t *const wcount[2], uint32_t *const errs[2],
-                          uint32_t *const ustart[2], hipStream_t s);
+                          uint32_t *const ustart[2], uint64_t *const spl[2], uint32_t B, uint32_t S, hipStream_t s);
 // (host[k]: the device view of side k's pinned block of the fused block's
 // layout; each finished batch's state, stop flag and results go there too)
 void launch_finish_leaf2(gpma_dev::FusedState *const st[2], uint32_t *const stop[2], gpma_dev::Ctl *const ctl[2],

@@ -22,6 +22,7 @@
 // batch survives until the host completes it.
 #include "common.h"
 #include "fused.h"
+#include "bitonic.h"
 #include "pair.h"
 
 using namespace gpma_dev;
@@ -155,6 +156,41 @@ k_finish_leaf(FusedState *__restrict__ st, uint32_t *__restrict__ stop, Ctl *__r
 // batch is skipped as a whole later.  Every key of batch j carries tag j and
 // the sort keeps repeats, so batch j's keys will start at offset j of the
 // sorted window: the first block writes the offsets to ustart[0 .. w].
+// With spl set (1024-thread blocks), the last block does not copy: it takes
+// the splitter sort's regular sample of the window's keys straight from the
+// batches, sorts it and writes the B-1 splitters, as the sort's own sampling
+// launch would from the copied keys, while the other blocks copy.
+
+// the window's key at position t (batch j = its tag); bad: src or dst >= V
+__device__ __forceinline__ uint64_t window_key(const uint64_t *const *src, const uint64_t *off, uint32_t j,
+                                               uint64_t t, int transpose, uint32_t V, uint32_t sb, bool &bad) {
+    uint64_t k = src[j][t - off[j]];
+    if (transpose) k = (k << 32) | (k >> 32);
+    bad = key_src(k) >= V || key_dst(k) >= V;
+    if (bad) k = 0;
+    return k | ((uint64_t)j << (32 + sb));
+}
+
+template <int R>
+__device__ void window_splitters(const uint64_t *const *src, const uint64_t *off, uint32_t w, uint64_t n,
+                                 int transpose, uint32_t V, uint32_t sb, uint32_t B, uint64_t *spl, uint64_t *lds) {
+    constexpr uint32_t S = 1024u * R;
+    uint64_t k[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const uint64_t t = ((uint64_t)((uint32_t)r * 1024u + threadIdx.x) * n) / S;
+        uint32_t j = 0;
+        while (j + 1 < w && off[j + 1] <= t) j++;
+        bool bad;
+        k[r] = window_key(src, off, j, t, transpose, V, sb, bad);
+    }
+    block_bitonic<R>(k, lds, S);
+#pragma unroll
+    for (int r = 0; r < R; r++) lds[(uint32_t)r * 1024u + threadIdx.x] = k[r];
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j + 1 < B; j += blockDim.x) spl[j] = lds[((uint64_t)(j + 1) * S) / B];
+}
+
 struct WindowFetchOp {
     struct Args {
         const BatchDesc *desc;
@@ -169,6 +205,9 @@ struct WindowFetchOp {
         uint32_t *wcount;
         uint32_t *errs;
         uint32_t *ustart;
+        uint64_t *spl;      // optional: the splitters, sampled by the last block
+        uint32_t B;         // with spl: buckets of the splitter sort
+        uint32_t S;         // with spl: its sample size (1024, 2048 or 4096)
     };
     static __device__ __forceinline__ void run(const Args &a) {
         const BatchDesc *__restrict__ desc = a.desc;
@@ -203,17 +242,27 @@ struct WindowFetchOp {
             st->wstart = b0;
         }
         if (blockIdx.x == 0 && threadIdx.x <= w) ustart[threadIdx.x] = (uint32_t)off[threadIdx.x];
-        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        const uint32_t copiers = a.spl ? gridDim.x - 1 : gridDim.x;
+        if (blockIdx.x == copiers) {   // block-uniform: the sampling block
+            __shared__ uint64_t lds[4096];
+            if (a.B < 2) return;
+            if (total == 0) {
+                for (uint32_t j = threadIdx.x; j + 1 < a.B; j += blockDim.x) a.spl[j] = ~0ull;
+                return;
+            }
+            if (a.S == 1024) window_splitters<1>(src, off, w, total, transpose, V, sb, a.B, a.spl, lds);
+            else if (a.S == 2048) window_splitters<2>(src, off, w, total, transpose, V, sb, a.B, a.spl, lds);
+            else window_splitters<4>(src, off, w, total, transpose, V, sb, a.B, a.spl, lds);
+            return;
+        }
+        const uint64_t stride = (uint64_t)copiers * blockDim.x;
         for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
             uint32_t j = 0;
             while (j + 1 < w && off[j + 1] <= t) j++;
-            uint64_t k = src[j][t - off[j]];
-            if (transpose) k = (k << 32) | (k >> 32);
-            if (key_src(k) >= V || key_dst(k) >= V) {
-                errs[j] = gen;
-                k = 0;
-            }
-            staging[t] = k | ((uint64_t)j << (32 + sb));
+            bool bad;
+            const uint64_t k = window_key(src, off, j, t, transpose, V, sb, bad);
+            if (bad) errs[j] = gen;
+            staging[t] = k;
         }
     }
 };
@@ -222,7 +271,8 @@ __global__ void __launch_bounds__(256)
 k_window_fetch(const BatchDesc *__restrict__ desc, FusedState *__restrict__ st, const uint32_t *__restrict__ stop,
                uint32_t w, uint64_t n_max, uint32_t V, uint32_t sb, int transpose, uint64_t *__restrict__ staging,
                uint32_t *__restrict__ wcount, uint32_t *__restrict__ errs, uint32_t *__restrict__ ustart) {
-    WindowFetchOp::run(WindowFetchOp::Args{desc, st, stop, w, n_max, V, sb, transpose, staging, wcount, errs, ustart});
+    WindowFetchOp::run(WindowFetchOp::Args{desc, st, stop, w, n_max, V, sb, transpose, staging, wcount, errs, ustart,
+                                           nullptr, 0, 0});
 }
 
 struct WindowStartsOp {
@@ -323,11 +373,15 @@ void launch_window_starts(const uint64_t *ukeys, const uint32_t *nuniq, uint32_t
 void launch_window_fetch2(const BatchDesc *desc, FusedState *const st[2], const uint32_t *const stop[2], uint32_t w,
                           uint64_t n_max, uint32_t V, uint32_t sb, uint64_t *const staging[2],
                           uint32_t *const wcount[2], uint32_t *const errs[2], uint32_t *const ustart[2],
-                          hipStream_t s) {
+                          uint64_t *const spl[2], uint32_t B, uint32_t S, hipStream_t s) {
     WindowFetchOp::Args a[2];
     for (int k = 0; k < 2; k++)
-        a[k] = {desc, st[k], stop[k], w, n_max, V, sb, k, staging[k], wcount[k], errs[k], ustart[k]};
-    launch_pair<WindowFetchOp, 256>(copy_blocks(n_max), a[0], a[1], s);
+        a[k] = {desc, st[k], stop[k], w, n_max, V, sb, k, staging[k], wcount[k], errs[k], ustart[k], spl[k], B, S};
+    // 1024-thread blocks: the copying ones, then the sampling one
+    uint64_t copiers = (n_max + 1023) / 1024;
+    if (copiers < 1) copiers = 1;
+    if (copiers > 256) copiers = 256;
+    launch_pair<WindowFetchOp, 1024>((uint32_t)copiers + 1, a[0], a[1], s);
 }
 
 void launch_finish_leaf2(FusedState *const st[2], uint32_t *const stop[2], Ctl *const ctl[2],

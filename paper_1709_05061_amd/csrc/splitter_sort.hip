@@ -24,6 +24,7 @@
 // class.
 #include "common.h"
 #include "pair.h"
+#include "bitonic.h"
 
 using namespace gpma_dev;
 
@@ -47,64 +48,6 @@ __device__ __forceinline__ uint64_t dyn_n(const uint32_t *n_dev, uint64_t n_max)
     if (!n_dev) return n_max;
     const uint64_t n = *n_dev;
     return n < n_max ? n : n_max;
-}
-
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, uint32_t m) {
-    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, (int)m, kWave);
-    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), (int)m, kWave);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Bitonic sort, ascending, of the first P keys (P a power of two, 64 <= P <=
-// 1024*R) a 1024-thread workgroup holds: k[r] of thread t is the key at index
-// r*1024 + t.  Partners closer than a wave trade through lane shuffles,
-// partners in other waves through lds (1024*R words), partners 1024 or more
-// apart sit in the same thread.  The sort is bound by vector ALU issue (some
-// 20 instructions per key and stage), so waves wholly past P skip the
-// arithmetic and only keep to the barriers.
-template <int R>
-__device__ void block_bitonic(uint64_t (&k)[R], uint64_t *lds, uint32_t P) {
-    const uint32_t t = threadIdx.x;
-    const bool live = (t & ~(uint32_t)(kWave - 1)) < P;   // wave-uniform
-    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
-        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= 1024) {
-                const uint32_t rj = j >> 10;
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    if (r & rj) continue;
-                    const uint32_t idx = (uint32_t)r * 1024u + t;
-                    const bool asc = (idx & kk) == 0;
-                    const uint64_t a = k[r], b = k[r | rj];
-                    const bool sw = asc ? (a > b) : (a < b);
-                    k[r] = sw ? b : a;
-                    k[r | rj] = sw ? a : b;
-                }
-            } else if (j >= (uint32_t)kWave) {
-                if (live)
-#pragma unroll
-                    for (int r = 0; r < R; r++) lds[(uint32_t)r * 1024u + t] = k[r];
-                __syncthreads();
-                if (live)
-#pragma unroll
-                    for (int r = 0; r < R; r++) {
-                        const uint32_t idx = (uint32_t)r * 1024u + t;
-                        const uint64_t o = lds[idx ^ j];
-                        const bool want_min = ((idx & j) == 0) == ((idx & kk) == 0);
-                        k[r] = want_min ? (o < k[r] ? o : k[r]) : (o > k[r] ? o : k[r]);
-                    }
-                __syncthreads();
-            } else if (live) {
-#pragma unroll
-                for (int r = 0; r < R; r++) {
-                    const uint32_t idx = (uint32_t)r * 1024u + t;
-                    const uint64_t o = shfl_xor_u64(k[r], j);
-                    const bool want_min = ((idx & j) == 0) == ((idx & kk) == 0);
-                    k[r] = want_min ? (o < k[r] ? o : k[r]) : (o > k[r] ? o : k[r]);
-                }
-            }
-        }
-    }
 }
 
 // the m <= 1024*R keys src[0..m) sorted into dst[0..m) (src may equal dst)
@@ -143,8 +86,6 @@ struct SsSplitArgs {
     const uint32_t *n_dev;
     uint32_t B;
     uint64_t *spl;
-    uint32_t *bump;    // optional: a counter advanced by one once the keys are in place
-    uint32_t *clear;   // optional (with bump): a word set to zero at the same time
 };
 
 template <int R>
@@ -157,10 +98,6 @@ struct SsSplittersOp {
         const uint32_t B = a.B;
         uint64_t *__restrict__ spl = a.spl;
         __shared__ uint64_t lds[1024 * R];
-        if (a.bump && threadIdx.x == 0) {
-            *a.bump += 1;
-            *a.clear = 0;
-        }
         const uint64_t n = dyn_n(n_dev, n_max);
         if (B < 2) return;
         if (n == 0) {
@@ -185,8 +122,8 @@ struct SsSplittersOp {
 template <int R>
 __global__ void __launch_bounds__(kSsThreads)
 k_ss_splitters(const uint64_t *__restrict__ keys, uint64_t n_max, const uint32_t *__restrict__ n_dev, uint32_t B,
-               uint64_t *__restrict__ spl, uint32_t *bump, uint32_t *clear) {
-    SsSplittersOp<R>::run(SsSplitArgs{keys, n_max, n_dev, B, spl, bump, clear});
+               uint64_t *__restrict__ spl) {
+    SsSplittersOp<R>::run(SsSplitArgs{keys, n_max, n_dev, B, spl});
 }
 
 // 2. per-tile bucket counts, bucket-major: cnt[b * ntiles + tile]
@@ -199,8 +136,14 @@ struct SsCountOp {
         uint32_t B;
         uint32_t ntiles;
         uint32_t *cnt;
+        uint32_t *bump;    // optional: a counter advanced by one once the keys are in place
+        uint32_t *clear;   // optional (with bump): a word set to zero at the same time
     };
     static __device__ __forceinline__ void run(const Args &a) {
+        if (a.bump && blockIdx.x == 0 && threadIdx.x == 0) {
+            *a.bump += 1;
+            *a.clear = 0;
+        }
         const uint64_t *__restrict__ keys = a.keys;
         uint64_t n_max = a.n_max;
         const uint32_t *__restrict__ n_dev = a.n_dev;
@@ -229,8 +172,9 @@ struct SsCountOp {
 
 __global__ void __launch_bounds__(kSsTileThreads)
 k_ss_count(const uint64_t *__restrict__ keys, uint64_t n_max, const uint32_t *__restrict__ n_dev,
-           const uint64_t *__restrict__ spl, uint32_t B, uint32_t ntiles, uint32_t *__restrict__ cnt) {
-    SsCountOp::run(SsCountOp::Args{keys, n_max, n_dev, spl, B, ntiles, cnt});
+           const uint64_t *__restrict__ spl, uint32_t B, uint32_t ntiles, uint32_t *__restrict__ cnt,
+           uint32_t *bump, uint32_t *clear) {
+    SsCountOp::run(SsCountOp::Args{keys, n_max, n_dev, spl, B, ntiles, cnt, bump, clear});
 }
 
 // 3. scatter each tile's keys to their buckets (order within a bucket is
@@ -458,6 +402,15 @@ uint32_t ss_buckets(uint64_t n_max) {
 
 namespace gpma_host {
 
+uint32_t splitter_buckets(uint64_t n_max) { return ss_buckets(n_max); }
+
+uint64_t *splitter_spl(uint32_t *tmp) { return reinterpret_cast<uint64_t *>(tmp); }
+
+uint32_t splitter_sample_size(uint64_t n_max) {
+    const uint32_t S = ss_buckets(n_max) * kSsOversample;
+    return S <= 1024 ? 1024 : (S <= 2048 ? 2048 : 4096);
+}
+
 bool splitter_sort_fits(uint64_t n_max) { return n_max >= 1 && n_max <= kSsMaxKeys; }
 
 size_t splitter_tmp_words(uint64_t n_max) {
@@ -485,16 +438,13 @@ const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uin
     uint32_t *stmp = cnt + cw;
     const uint32_t S = B * kSsOversample;
     if (S <= 1024)
-        hipLaunchKernelGGL(k_ss_splitters<1>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl, bump,
-                           clear);
+        hipLaunchKernelGGL(k_ss_splitters<1>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl);
     else if (S <= 2048)
-        hipLaunchKernelGGL(k_ss_splitters<2>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl, bump,
-                           clear);
+        hipLaunchKernelGGL(k_ss_splitters<2>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl);
     else
-        hipLaunchKernelGGL(k_ss_splitters<4>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl, bump,
-                           clear);
+        hipLaunchKernelGGL(k_ss_splitters<4>, dim3(1), dim3(kSsThreads), 0, s, in, n_max, n_dev, B, spl);
     hipLaunchKernelGGL(k_ss_count, dim3((uint32_t)ntiles), dim3(kSsTileThreads), 0, s, in, n_max, n_dev, spl, B,
-                       (uint32_t)ntiles, cnt);
+                       (uint32_t)ntiles, cnt, bump, clear);
     const bool fused = cw <= kSsFuseCounts;
     if (!fused) scan_u32(cnt, cnt, cw, nullptr, stmp, s);
     hipLaunchKernelGGL(k_ss_scatter, dim3((uint32_t)ntiles), dim3(kSsTileThreads), 0, s, in, n_max, n_dev, spl, B,
@@ -513,7 +463,7 @@ bool splitter_sort_pairable(uint64_t n_max) {
 // as 0 (buf_a) or 1 (buf_b).
 int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint32_t *const n_dev[2], uint32_t sbits,
                         uint32_t dbits, uint64_t *const buf_a[2], uint64_t *const buf_b[2], uint32_t *const tmp[2],
-                        hipStream_t s, uint32_t *const bump[2], uint32_t *const clear[2]) {
+                        hipStream_t s, uint32_t *const bump[2], uint32_t *const clear[2], bool spl_ready) {
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
     const uint32_t passes = (total + 7) / 8;
@@ -531,15 +481,22 @@ int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint3
         uint64_t *spl = reinterpret_cast<uint64_t *>(tmp[k]);
         uint32_t *bst = tmp[k] + 2 * kSsMaxBuckets;
         uint32_t *cnt = bst + kSsMaxBuckets + 4;
-        sp[k] = {in[k], n_max, n_dev[k], B, spl, bump ? bump[k] : nullptr, bump ? clear[k] : nullptr};
-        ca[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt};
+        sp[k] = {in[k], n_max, n_dev[k], B, spl};
+        ca[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt, bump ? bump[k] : nullptr,
+                 bump ? clear[k] : nullptr};
         sa[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt, 1, bst, mid};
         ba[k] = {mid, fin, n_max, n_dev[k], bst, 1u, B, dbits, bits, passes};
     }
     const uint32_t S = B * kSsOversample;
-    if (S <= 1024) launch_pair<SsSplittersOp<1>, kSsThreads>(1, sp[0], sp[1], s);
-    else if (S <= 2048) launch_pair<SsSplittersOp<2>, kSsThreads>(1, sp[0], sp[1], s);
-    else launch_pair<SsSplittersOp<4>, kSsThreads>(1, sp[0], sp[1], s);
+    if (spl_ready) {
+        // the caller's launch wrote them
+    } else if (S <= 1024) {
+        launch_pair<SsSplittersOp<1>, kSsThreads>(1, sp[0], sp[1], s);
+    } else if (S <= 2048) {
+        launch_pair<SsSplittersOp<2>, kSsThreads>(1, sp[0], sp[1], s);
+    } else {
+        launch_pair<SsSplittersOp<4>, kSsThreads>(1, sp[0], sp[1], s);
+    }
     launch_pair<SsCountOp, kSsTileThreads>((uint32_t)ntiles, ca[0], ca[1], s);
     launch_pair<SsScatterOp, kSsTileThreads>((uint32_t)ntiles, sa[0], sa[1], s);
     launch_pair<SsBucketOp, kSsThreads>(B, ba[0], ba[1], s);
