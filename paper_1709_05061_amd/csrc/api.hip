@@ -1215,7 +1215,7 @@ void enqueue_window_prefix2(gpma *g, gpma *m, uint32_t w, uint64_t n_max, const 
     const uint32_t *nd[2] = {g->wcount, m->wcount};
     uint64_t *ba[2] = {g->kA, m->kA}, *bb[2] = {g->kB, m->kB};
     uint32_t *tmp[2] = {g->tmp, m->tmp};
-    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s, gen, misses, true);
+    const int which = splitter_sort_keys2(in, n_max, nd, sb + tb, sb, ba, bb, tmp, s, gen, misses);
     for (int k = 0; k < 2; k++) h[k]->wukeys = which ? h[k]->kB : h[k]->kA;
 }
 

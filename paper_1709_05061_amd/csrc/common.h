@@ -222,7 +222,7 @@ const uint64_t *radix_sort_keys(const uint64_t *in, uint64_t n, uint32_t sbits, 
 // input is in place, adds one to *bump and zeroes *clear.
 bool splitter_sort_fits(uint64_t n_max);
 size_t splitter_tmp_words(uint64_t n_max);
-// For a caller that samples the splitters itself (spl_ready below): the
+// For a caller that samples the splitters itself (the paired sort below): the
 // bucket count, the sample size (a regular sample of that many keys, sorted,
 // gives splitter j = sample[(j+1)*S/B], j < B-1) and where they go in tmp.
 uint32_t splitter_buckets(uint64_t n_max);
@@ -232,13 +232,14 @@ const uint64_t *splitter_sort_keys(const uint64_t *in, uint64_t n_max, const uin
                                    uint32_t dbits, uint32_t V, uint64_t *buf_a, uint64_t *buf_b, uint32_t *tmp,
                                    hipStream_t s, uint32_t *bump = nullptr, uint32_t *clear = nullptr);
 // two sorts of n_max-key inputs in one set of launches (the array's and its
-// mirror's window), while the bucket counts need no separate scan; returns
-// 0 when the results are in buf_a, 1 for buf_b
+// mirror's window), while the bucket counts need no separate scan; the
+// caller has written each side's splitters (splitter_spl(tmp[k]), from a
+// regular sample of splitter_sample_size keys); returns 0 when the results
+// are in buf_a, 1 for buf_b
 bool splitter_sort_pairable(uint64_t n_max);
 int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint32_t *const n_dev[2], uint32_t sbits,
                         uint32_t dbits, uint64_t *const buf_a[2], uint64_t *const buf_b[2], uint32_t *const tmp[2],
-                        hipStream_t s, uint32_t *const bump[2] = nullptr, uint32_t *const clear[2] = nullptr,
-                        bool spl_ready = false);
+                        hipStream_t s, uint32_t *const bump[2] = nullptr, uint32_t *const clear[2] = nullptr);
 
 // unique of a sorted array: out receives the distinct keys, *count_dev their
 // number.  flags/tmp scratch: n+1 words / scan_tmp_words(n).

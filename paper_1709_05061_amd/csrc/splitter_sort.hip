@@ -7,7 +7,8 @@
 //
 //   1. one workgroup sorts a regular sample of the keys (bitonic, in
 //      registers and LDS) and picks B - 1 splitters (B buckets of about
-//      kSsTarget keys);
+//      kSsTarget keys); the paired form takes them from its caller, whose
+//      copying launch samples them on the side;
 //   2. each 2048-key tile counts its keys per bucket (binary search over the
 //      splitters in LDS);
 //   3. each tile scatters its keys to their buckets; it derives its offsets
@@ -463,7 +464,7 @@ bool splitter_sort_pairable(uint64_t n_max) {
 // as 0 (buf_a) or 1 (buf_b).
 int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint32_t *const n_dev[2], uint32_t sbits,
                         uint32_t dbits, uint64_t *const buf_a[2], uint64_t *const buf_b[2], uint32_t *const tmp[2],
-                        hipStream_t s, uint32_t *const bump[2], uint32_t *const clear[2], bool spl_ready) {
+                        hipStream_t s, uint32_t *const bump[2], uint32_t *const clear[2]) {
     uint32_t total = sbits + dbits;
     if (total == 0) total = 1;
     const uint32_t passes = (total + 7) / 8;
@@ -471,7 +472,6 @@ int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint3
     const int which = (passes & 1) ? 0 : 1;
     const uint32_t B = ss_buckets(n_max);
     const uint64_t ntiles = div_up(n_max, kSsTile);
-    SsSplitArgs sp[2];
     SsCountOp::Args ca[2];
     SsScatterOp::Args sa[2];
     SsBucketOp::Args ba[2];
@@ -481,21 +481,10 @@ int splitter_sort_keys2(const uint64_t *const in[2], uint64_t n_max, const uint3
         uint64_t *spl = reinterpret_cast<uint64_t *>(tmp[k]);
         uint32_t *bst = tmp[k] + 2 * kSsMaxBuckets;
         uint32_t *cnt = bst + kSsMaxBuckets + 4;
-        sp[k] = {in[k], n_max, n_dev[k], B, spl};
         ca[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt, bump ? bump[k] : nullptr,
                  bump ? clear[k] : nullptr};
         sa[k] = {in[k], n_max, n_dev[k], spl, B, (uint32_t)ntiles, cnt, 1, bst, mid};
         ba[k] = {mid, fin, n_max, n_dev[k], bst, 1u, B, dbits, bits, passes};
-    }
-    const uint32_t S = B * kSsOversample;
-    if (spl_ready) {
-        // the caller's launch wrote them
-    } else if (S <= 1024) {
-        launch_pair<SsSplittersOp<1>, kSsThreads>(1, sp[0], sp[1], s);
-    } else if (S <= 2048) {
-        launch_pair<SsSplittersOp<2>, kSsThreads>(1, sp[0], sp[1], s);
-    } else {
-        launch_pair<SsSplittersOp<4>, kSsThreads>(1, sp[0], sp[1], s);
     }
     launch_pair<SsCountOp, kSsTileThreads>((uint32_t)ntiles, ca[0], ca[1], s);
     launch_pair<SsScatterOp, kSsTileThreads>((uint32_t)ntiles, sa[0], sa[1], s);
