@@ -548,6 +548,15 @@ def main():
         e.record(stream)
         return e
 
+    def byte_rates(h):
+        # per handle, looked up once (outside the timed calls after the first):
+        # bytes per rewritten slot, and the handles (array, mirror)
+        r = getattr(h, "_bench_rates", None)
+        if r is None:
+            r = (16.0 + 10.0 / h.leaf_size, 2 if h.mirror() is not None else 1)
+            h._bench_rates = r
+        return r
+
     def update(h, t, fused, bsz=None, t0=0):
         """One slide; returns (applied, resizes, algorithmic bytes): per
         handle 8 B per batch key plus, per merged segment, 16 B per slot and
@@ -555,8 +564,7 @@ def main():
         and its mirror."""
         d, i = st.slide(t, b) if bsz is None else (st.order[t0:t0 + bsz],
                                                   st.order[st.window + t0: st.window + t0 + bsz])
-        per_slot = 16.0 + 10.0 / h.leaf_size
-        nh = 2 if h.mirror() is not None else 1
+        per_slot, nh = byte_rates(h)
         if fused:
             s = h.apply_batches([1, 0], [d, i])
             by = nh * 8.0 * (d.numel() + i.numel()) + per_slot * (s.slots_rewritten + s.mirror_slots_rewritten)
