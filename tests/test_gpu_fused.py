@@ -325,9 +325,15 @@ def test_paired_windows_equal_plain(learned, lazy):
     for c in range(len(cuts) - 1):
         lo, hi = cuts[c], cuts[c + 1]
         say("paired call", lo, hi, "learned", learned, "lazy", lazy)
+        applied = noops = 0
         for i in range(lo, hi):
-            (plain.delete if ops[i] else plain.insert)(dev(bs[i]))
+            sp = (plain.delete if ops[i] else plain.insert)(dev(bs[i]), stats=True)
+            applied += sp.applied
+            noops += sp.noops
         st = fused.apply_batches(ops[lo:hi], [dev(b) for b in bs[lo:hi]])
+        # the call's statistics (written by the device into the pinned results
+        # for paired windows) agree with the plain batches'
+        assert (st.applied, st.noops) == (applied, noops), (lo, hi, st, applied, noops)
         assert np.array_equal(npu64(fused.slots()), npu64(plain.slots())), (lo, hi)
         assert np.array_equal(npu64(fused.mirror().slots()), npu64(plain.mirror().slots())), (lo, hi)
         check_pivots(fused)
