@@ -1178,19 +1178,19 @@ void enqueue_device_batch(gpma *g, bool del, uint64_t cls, const BatchDesc *desc
 // window in one launch (the grid's y index picks the side), so a window takes
 // half the launches.  Used when both sides take the same kernels: the
 // splitter sort without a count scan, the leaf level as the last device
-// level, no lazy-deletion marks, the same locate.
+// level (merges, or marks for a lazy-deletion delete batch), the same
+// locate.
 
-bool pairable_window(const gpma *g, const gpma *m, uint64_t wcls, const uint8_t *ops, uint32_t from, uint32_t to) {
+bool pairable_window(const gpma *g, const gpma *m, uint64_t wcls) {
     for (const gpma *h : {g, m})
         if (h->fused_direct || h->window_radix || h->lib_streams || !window_tag_bits(h) || h->bcap != g->bcap)
             return false;
     if (g->lf != m->lf || g->V != m->V || (g->learned && g->loc) != (m->learned && m->loc)) return false;
+    if ((g->dead != nullptr) != (m->dead != nullptr)) return false;   // lazy deletion on both sides or neither
     if (!splitter_sort_pairable(wcls)) return false;
     for (const gpma *h : {g, m}) {
         const bool upper = h->fused_levels >= 1 && h->H > 1 && seg_merge_lds_bytes(h->lf, 1) <= (size_t)h->dev.max_lds;
         if (upper) return false;
-        for (uint32_t i = from; i < to; i++)
-            if (ops[i] && h->dead) return false;
     }
     return true;
 }
@@ -1272,12 +1272,18 @@ void enqueue_device_batch2(gpma *g, gpma *m, bool del, uint64_t cls, uint32_t po
                                s);
     else
         launch_locate2(cls, piv_c, L, ctl_c, leaf, status, ws, s);
-    launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, piv, cnt, row_ptr, deg, dead, g->lf, lo, hi, ctl,
-                       part, s);
+    // a lazy-deletion delete batch marks its keys in place; anything else
+    // merges into the leaves
+    const bool mark = del && g->dead;
+    if (mark)
+        launch_leaf_mark2(keys_c, leaf_c, status, nd, cls, slots, cnt, dead, deg, g->lf, ctl_c, part, s);
+    else
+        launch_leaf_merge2(del, keys_c, leaf_c, status, nd, cls, slots, piv, cnt, row_ptr, deg, dead, g->lf, lo, hi,
+                           ctl, part, s);
     // each finished batch also lands in the handle's pinned block
     void *host[2] = {g->fblk_hd, m->fblk_hd};
-    launch_finish_leaf2(st, stop, ctl, part_c, leaf_merge_blocks(g->lf, cls), del, g->lf, outs, host,
-                        (uint32_t)kFbOuts, s);
+    const uint64_t nparts = mark ? leaf_mark_blocks(cls) : leaf_merge_blocks(g->lf, cls);
+    launch_finish_leaf2(st, stop, ctl, part_c, nparts, del, g->lf, outs, host, (uint32_t)kFbOuts, s);
 }
 
 constexpr size_t kPairGraphs = 32;   // window shapes kept per handle
@@ -1519,7 +1525,7 @@ int apply_chunk(gpma *g, uint32_t count, const uint8_t *ops, const uint64_t *con
                 e2++;
             }
             const uint64_t wcls = std::min<uint64_t>(batch_class(keys_in), g->bcap);
-            if (pairable_window(g, m, wcls, ops, P[0].next, e2)) {
+            if (pairable_window(g, m, wcls)) {
                 hipGraphExec_t pw = get_pair_graph(g, m, wcls, ops, sizes, P[0].next, e2, g->desc);
                 if (!pw || hipGraphLaunch(pw, s) != hipSuccess) return GPMA_EDEVICE;
                 end[0] = end[1] = e2;

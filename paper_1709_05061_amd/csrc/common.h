@@ -328,7 +328,14 @@ void launch_lock_try(uint32_t h, uint32_t H, const uint64_t *keys, uint32_t *lea
                      uint64_t *slots, uint64_t *piv, uint16_t *cnt, uint32_t *dead, uint32_t *row_ptr, uint32_t *deg,
                      uint64_t *scratch, uint32_t *locks, uint32_t epoch, uint64_t L, uint32_t lf_log2, uint64_t maxh,
                      gpma_dev::Ctl *ctl, hipStream_t s);
-// lazy deletion: mark the located unique keys in place (status kDone/kNoop)
+// lazy deletion: mark the located keys in place (status kDone/kNoop); the
+// paired form writes per-block figures to part (4 words a block,
+// leaf_mark_blocks(n_max) blocks) for the finishing kernel
+void launch_leaf_mark2(const uint64_t *const keys[2], const uint32_t *const leaf[2], uint8_t *const status[2],
+                       const uint32_t *const n_dev[2], uint64_t n_max, uint64_t *const slots[2],
+                       const uint16_t *const cnt[2], uint32_t *const dead[2], uint32_t *const deg[2], uint32_t lf,
+                       const gpma_dev::Ctl *const ctl[2], uint32_t *const part[2], hipStream_t s);
+uint64_t leaf_mark_blocks(uint64_t n_max);
 void launch_leaf_mark(const uint64_t *keys, const uint32_t *leaf, uint8_t *status, const uint32_t *n_dev,
                       uint64_t n_max, uint64_t *slots, const uint16_t *cnt, uint32_t *dead, uint32_t *deg,
                       uint32_t lf, const gpma_dev::Ctl *ctl, hipStream_t s);

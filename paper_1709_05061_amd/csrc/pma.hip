@@ -708,36 +708,80 @@ __global__ void k_dispatch(const uint64_t *__restrict__ M, uint64_t N, uint64_t 
     if (o < cj && is_guard(v)) row_ptr[key_src(v) + 1] = (uint32_t)(pos + 1);
 }
 
-// Lazy deletion: mark each (unique) key of the batch in its leaf.  A key is
-// deleted when its leaf holds it live; the mark keeps the entry's place and
-// the leaf's dead count grows by one.  Absent and already marked keys are
-// no-ops.  Keys are distinct, so no two threads touch one slot.
-__global__ void k_leaf_mark(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf,
-                            uint8_t *__restrict__ status, const uint32_t *__restrict__ n_dev, uint64_t n_max,
-                            uint64_t *__restrict__ slots, const uint16_t *__restrict__ cnt,
-                            uint32_t *__restrict__ dead, uint32_t *__restrict__ deg, uint32_t lf_log2,
-                            const Ctl *__restrict__ ctl) {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_max || i >= *n_dev || ctl->err) return;
-    const uint64_t k = keys[i];
-    if (i > 0 && keys[i - 1] == k) {   // a repeat (sorted keys): its first copy marks
-        status[i] = kNoop;
-        return;
+// Lazy deletion: mark each key of the batch in its leaf.  A key is deleted
+// when its leaf holds it live; the mark keeps the entry's place and the
+// leaf's dead count grows by one.  Absent and already marked keys, and
+// repeats of a key (the batch is sorted; its first copy marks), are no-ops,
+// so no two threads touch one slot.  part (optional): each block writes its
+// marked and no-op counts to part[4*block], 0 and 0 after them (no leaf is
+// rewritten and nothing is left pending), the leaf merge's figures for a
+// finishing kernel to sum.
+struct MarkOp {
+    struct Args {
+        const uint64_t *keys;
+        const uint32_t *leaf;
+        uint8_t *status;
+        const uint32_t *n_dev;
+        uint64_t n_max;
+        uint64_t *slots;
+        const uint16_t *cnt;
+        uint32_t *dead;
+        uint32_t *deg;
+        uint32_t lf_log2;
+        const Ctl *ctl;
+        uint32_t *part;
+    };
+    static __device__ __forceinline__ void run(const Args &a) {
+        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        bool marked = false, noop = false;
+        if (i < a.n_max && i < *a.n_dev && !a.ctl->err) {
+            const uint64_t k = a.keys[i];
+            if (i > 0 && a.keys[i - 1] == k) {
+                noop = true;
+            } else {
+                const uint32_t j = a.leaf[i];
+                const uint64_t base = (uint64_t)j << a.lf_log2;
+                const uint32_t c = a.cnt[j];
+                uint32_t lo = 0, hi = c;   // occupied prefix: first masked key >= k
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if ((a.slots[base + mid] & ~kTomb) < k) lo = mid + 1; else hi = mid;
+                }
+                marked = lo < c && a.slots[base + lo] == k;   // a marked copy differs in bit 63
+                noop = !marked;
+                if (marked) {
+                    a.slots[base + lo] = k | kTomb;
+                    atomicAdd(&a.dead[j], 1u);
+                    atomicAdd(&a.deg[key_src(k)], 0xFFFFFFFFu);
+                }
+            }
+            a.status[i] = marked ? kDone : kNoop;
+        }
+        if (!a.part) return;   // grid-uniform
+        __shared__ uint32_t s_red[2][1024 / kWave];
+        const uint32_t w = threadIdx.x / kWave;
+        const uint32_t nm = (uint32_t)__popcll(__ballot(marked));
+        const uint32_t nn = (uint32_t)__popcll(__ballot(noop));
+        if (__lane_id() == 0) {
+            s_red[0][w] = nm;
+            s_red[1][w] = nn;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            uint32_t t = 0;
+            if (threadIdx.x < 2)
+                for (uint32_t x = 0; x < blockDim.x / kWave; x++) t += s_red[threadIdx.x][x];
+            a.part[4 * (uint64_t)blockIdx.x + threadIdx.x] = t;
+        }
     }
-    const uint32_t j = leaf[i];
-    const uint64_t base = (uint64_t)j << lf_log2;
-    uint32_t lo = 0, hi = cnt[j];   // occupied prefix: first masked key >= k
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if ((slots[base + mid] & ~kTomb) < k) lo = mid + 1; else hi = mid;
-    }
-    const bool hit = lo < cnt[j] && slots[base + lo] == k;   // a marked copy differs in bit 63
-    if (hit) {
-        slots[base + lo] = k | kTomb;
-        atomicAdd(&dead[j], 1u);
-        atomicAdd(&deg[key_src(k)], 0xFFFFFFFFu);
-    }
-    status[i] = hit ? kDone : kNoop;
+};
+
+__global__ void __launch_bounds__(256)
+k_leaf_mark(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ leaf, uint8_t *__restrict__ status,
+            const uint32_t *__restrict__ n_dev, uint64_t n_max, uint64_t *__restrict__ slots,
+            const uint16_t *__restrict__ cnt, uint32_t *__restrict__ dead, uint32_t *__restrict__ deg,
+            uint32_t lf_log2, const Ctl *__restrict__ ctl) {
+    MarkOp::run(MarkOp::Args{keys, leaf, status, n_dev, n_max, slots, cnt, dead, deg, lf_log2, ctl, nullptr});
 }
 
 __global__ void k_mark_done(bool del, const uint64_t *__restrict__ keys, uint8_t *__restrict__ status,
@@ -966,6 +1010,20 @@ void launch_dispatch(const uint64_t *M, uint64_t N, uint64_t *slots, uint64_t *p
     hipLaunchKernelGGL(k_dispatch, dim3((uint32_t)div_up(total, 256)), dim3(256), 0, s, M, N, slots, piv,
                        cnt, dead, row_ptr, first_leaf, P, log2_u32(lf));
 }
+
+void launch_leaf_mark2(const uint64_t *const keys[2], const uint32_t *const leaf[2], uint8_t *const status[2],
+                       const uint32_t *const n_dev[2], uint64_t n_max, uint64_t *const slots[2],
+                       const uint16_t *const cnt[2], uint32_t *const dead[2], uint32_t *const deg[2], uint32_t lf,
+                       const Ctl *const ctl[2], uint32_t *const part[2], hipStream_t s) {
+    if (!n_max) return;
+    MarkOp::Args a[2];
+    for (int k = 0; k < 2; k++)
+        a[k] = {keys[k], leaf[k], status[k], n_dev[k], n_max, slots[k], cnt[k], dead[k], deg[k], log2_u32(lf), ctl[k],
+                part[k]};
+    launch_pair<MarkOp, 256>((uint32_t)div_up(n_max, 256), a[0], a[1], s);
+}
+
+uint64_t leaf_mark_blocks(uint64_t n_max) { return div_up(n_max, 256); }
 
 void launch_leaf_mark(const uint64_t *keys, const uint32_t *leaf, uint8_t *status, const uint32_t *n_dev,
                       uint64_t n_max, uint64_t *slots, const uint16_t *cnt, uint32_t *dead, uint32_t *deg,
