@@ -220,24 +220,29 @@ int gpma_delete_batch(gpma_t *h, const uint64_t *keys_dev, uint64_t b,
 /* Fused batching: apply `count` batches in order (ops[i] = 0 insert, 1
  * delete; keys_dev[i] device pointers with sizes[i] keys; the three arrays
  * are host arrays).  The result is the one of the same sequence of
- * gpma_insert_batch / gpma_delete_batch calls, slot for slot.  Each batch
- * replays a HIP graph captured once per (size class, operation) that runs
- * the whole batch with device-side control up to the highest level the
- * workgroup tier covers; the host synchronises once per call, plus once for
- * each batch that climbs above those levels (its remaining levels and the
- * root are then completed on the host-driven path).  Not in the paper; the
- * answer to its observation that GPMA+ pays for many kernel calls on small
- * batches.  On an invalid key in batch i, batches before i stay applied,
- * batch i and later are not, and GPMA_EINVAL is returned; *completed (if
- * non-NULL) receives the number of batches applied.  Memory for the whole
- * sequence (its insertions and deletions summed) is reserved before the
- * first batch runs: GPMA_ENOMEM applies nothing.  `total` (if non-NULL)
- * receives summed statistics (per-level counts are not filled).  With a
- * mirror the mirror's batches run on a stream of the handle, forked from and
- * joined to `stream` by events; the first call on a given `stream`
- * synchronises it once more to pick that stream (a ~0.4 ms probe: the
- * handle's stream must run beside `stream`, not behind it on one hardware
- * queue). */
+ * gpma_insert_batch / gpma_delete_batch calls, slot for slot.  Batches run
+ * in windows of up to 64 whose keys are sorted together; each batch then
+ * runs with device-side control up to the highest level the workgroup tier
+ * covers (fused_levels).  The host synchronises once per window, plus once
+ * for each batch that climbs above those levels (its remaining levels and
+ * the root are then completed on the host-driven path).  Not in the paper;
+ * the answer to its observation that GPMA+ pays for many kernel calls on
+ * small batches.  On an invalid key in batch i, batches before i stay
+ * applied, batch i and later are not, and GPMA_EINVAL is returned;
+ * *completed (if non-NULL) receives the number of batches applied.  Memory
+ * for the whole sequence (its insertions and deletions summed) is reserved
+ * before the first batch runs: GPMA_ENOMEM applies nothing.  `total` (if
+ * non-NULL) receives summed statistics (per-level counts are not filled).
+ * With a mirror, while the array and the mirror stand at the same batch and
+ * take the same kernels (no level above the leaves on the device), every
+ * step of a window runs for both in one launch and the whole window is one
+ * captured HIP graph on `stream`.  Otherwise each window's sort and each
+ * batch replay graphs captured once per shape (or are enqueued directly,
+ * GPMA_FLAG_FUSED_DIRECT), and the mirror's batches run on a stream of the
+ * handle, forked from and joined to `stream` by events; the first such call
+ * on a given `stream` synchronises it once more to pick that stream (a
+ * ~0.4 ms probe: the handle's stream must run beside `stream`, not behind
+ * it on one hardware queue). */
 int gpma_apply_batches(gpma_t *h, uint32_t count, const uint8_t *ops, const uint64_t *const *keys_dev,
                        const uint64_t *sizes, hipStream_t stream, gpma_stats *total,
                        uint32_t *completed);
