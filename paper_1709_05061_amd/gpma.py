@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import threading
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -62,6 +63,10 @@ class TorchAllocator:
         self.held_bytes = 0
         self.peak_bytes = 0
         self._sizes = {}
+        # handles used from several host threads (the service's query
+        # workers) allocate concurrently: the budget check, the allocation and
+        # the count are one step
+        self._lock = threading.Lock()
         self._alloc_cb = ALLOC_FN(self._alloc)
         self._free_cb = FREE_FN(self._free)
         self.struct = gpma_allocator(self._alloc_cb, self._free_cb, None)
@@ -72,23 +77,25 @@ class TorchAllocator:
         return True
 
     def _alloc(self, nbytes, stream, ctx):
-        try:
-            if not self.allow(int(nbytes)):
+        with self._lock:
+            try:
+                if not self.allow(int(nbytes)):
+                    return None
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
+            except Exception:
                 return None
-            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0))
-        except Exception:
-            return None
-        self._sizes[ptr] = int(nbytes)
-        self.held_bytes += int(nbytes)
-        self.peak_bytes = max(self.peak_bytes, self.held_bytes)
-        return ptr
+            self._sizes[ptr] = int(nbytes)
+            self.held_bytes += int(nbytes)
+            self.peak_bytes = max(self.peak_bytes, self.held_bytes)
+            return ptr
 
     def _free(self, ptr, nbytes, stream, ctx):
-        try:
-            self.held_bytes -= self._sizes.pop(ptr, int(nbytes))
-            torch.cuda.caching_allocator_delete(ptr)
-        except Exception:
-            pass
+        with self._lock:
+            try:
+                self.held_bytes -= self._sizes.pop(ptr, int(nbytes))
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:
+                pass
 
 
 class gpma_stats(C.Structure):
