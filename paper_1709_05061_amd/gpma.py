@@ -338,9 +338,10 @@ class BatchStats:
 
     @classmethod
     def of(cls, st: gpma_stats) -> "BatchStats":
-        segs = list(st.segments_merged)
-        while segs and segs[-1] == 0:
-            segs.pop()
+        # the levels up to the last with a merge (trailing zero words cut in C)
+        w = C.sizeof(st.segments_merged._type_)
+        n = (len(bytes(st.segments_merged).rstrip(b"\0")) + w - 1) // w
+        segs = st.segments_merged[:n]
         return cls(st.requested, st.applied, st.noops, st.top_level, bool(st.resized), segs,
                    st.slots_rewritten, st.mirror_slots_rewritten)
 

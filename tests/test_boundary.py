@@ -52,3 +52,22 @@ def test_thresholds_agree_with_oracle_via_params_validation():
         pytest.skip("libgpma.so not built")
     p = gpma.gpma_default_params()
     assert (p.leaf_size, p.tau_leaf_pm, p.tau_root_pm, p.rho_leaf_pm, p.rho_root_pm) == (0, 920, 800, 80, 400)
+
+
+def test_batch_stats_keep_levels_up_to_the_last_merge():
+    # host logic of the binding: the per-level merge counts of gpma_stats are
+    # cut after the last nonzero level, whatever the values' byte patterns
+    import random
+    from paper_1709_05061_amd import gpma
+    rng = random.Random(5)
+    values = [0, 0, 1, 255, 256, 1 << 24, 1 << 32, (1 << 63) + 1, (1 << 64) - 1]
+    for _ in range(500):
+        st = gpma.gpma_stats()
+        L = len(st.segments_merged)
+        want = [rng.choice(values) for _ in range(rng.randrange(0, L + 1))]
+        for j, v in enumerate(want):
+            st.segments_merged[j] = v
+        while want and want[-1] == 0:
+            want.pop()
+        assert gpma.BatchStats.of(st).segments_merged == want
+    assert gpma.BatchStats.of(gpma.gpma_stats()).segments_merged == []
