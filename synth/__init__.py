@@ -97,9 +97,13 @@ def shuffle(keys: torch.Tensor, seed: int) -> torch.Tensor:
 
 
 def uniform_below(counter: torch.Tensor, seed: int, n: int) -> torch.Tensor:
-    """Integers in [0, n): the high 32 bits of a draw, scaled (n < 2^32)."""
+    """Integers in [0, n): the high 32 bits r of a draw, scaled to
+    floor(r * n / 2^32) (0 <= n < 2^32).  The product is formed in two
+    16-bit halves of n, so it stays inside int64 for every n."""
+    if not 0 <= n < (1 << 32):
+        raise ValueError("uniform_below needs 0 <= n < 2^32")
     r = _srl(splitmix64(counter, seed), 32)
-    return (r * n) >> 32
+    return (r * (n >> 16) + ((r * (n & 0xFFFF)) >> 16)) >> 16
 
 
 # --------------------------------------------------------------------------
