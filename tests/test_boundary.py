@@ -71,3 +71,25 @@ def test_batch_stats_keep_levels_up_to_the_last_merge():
             want.pop()
         assert gpma.BatchStats.of(st).segments_merged == want
     assert gpma.BatchStats.of(gpma.gpma_stats()).segments_merged == []
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    # no fallback path: without the built library every entry point raises
+    from paper_1709_05061_amd import gpma
+    monkeypatch.setattr(gpma, "_lib", None)
+    monkeypatch.setattr(gpma, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libgpma.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        gpma.load_library()
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "8"], {}), ([], {"WORLD_SIZE": "2"})])
+def test_bench_refuses_more_than_one_gpu(argv, env):
+    # one GPU only: the bench exits with a message before it touches a device
+    import subprocess
+    import sys
+    e = dict(os.environ, **env)
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), *argv], capture_output=True, text=True,
+                       env=e, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
